@@ -1,0 +1,183 @@
+"""Benchmark of the WENO-TT hot path on one MI355X.
+
+A step is one SSP-RK3 step of WENO-TT (per stage: exact alpha, one fused LF + WENO5 cross
+per direction, flux difference, stage sum, one rounding; dynamic eps_TT) on the 2D
+four-quadrant Riemann problem, 512 x 512, transmissive, FP64, eps_TT(0) = 1e-8.
+dt = 0.5 h / alpha is taken from the state at the start of every step (inside the timed
+region). The state evolves through warmup and timed steps from t = 0.
+
+Printed: one JSON line with the dense-equivalent throughput (cells x steps / s), the
+roofline of the fiber kernel measured with HIP events on the library's stream, the dense
+GPU WENO5 comparator on the same workload, and the oracle timed on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "dense-equiv cell-updates/s, WENO-TT vs dense WENO5 on GPU, at fixed L1 error"
+
+# Algorithmic FP64 operations of one flux value (one face, all conserved variables) in the
+# fiber kernel, counted from the formulas (division and square root count as one):
+# 2D: 6 stencil cells x 39 (primitives, flux, LF split of 4 variables) + 8 WENO5 x 72 + 4 = 814
+# 3D: 6 x 48 + 10 x 72 + 5 = 1013
+FLOP_PER_POINT = {2: 814.0, 3: 1013.0}
+PEAK_FP64_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-dense", action="store_true")
+    return ap.parse_args()
+
+
+def cpu_baseline(flow, seconds):
+    """The oracle as it stands, on the host cores, over a bounded number of steps."""
+    import numpy as np
+
+    import oracle
+    from oracle import tt_ref
+    oracle.build(force=False)
+    u = np.stack([tt_ref.tt_full(c) for c in flow.cores])
+    bcs = tuple(oracle.BC_PERIODIC if b == 0 else oracle.BC_TRANSMISSIVE for b in flow.bc)
+    P = oracle.Problem(flow.n, flow.lo, flow.hi, bcs, gamma=flow.gamma)
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        a = P.alpha(u)
+        P.ssprk3(u, 0.5 * min(P.h) / a)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= seconds or steps >= 1000:
+            break
+    cells = 1
+    for m in flow.n:
+        cells *= m
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": cells * steps / el, "unit": "cell-updates/s", "cores": cores, "kind": "oracle",
+            "sample": f"{steps} SSP-RK3 steps of the dense FP64 oracle from t=0 on the same {flow.n[0]}x{flow.n[1]} "
+                      f"initial state ({el:.1f} s)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+
+    import workloads
+    from paper_2405_12301_amd import wenott as W
+
+    W.load()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    flow = workloads.config2_quadrants_2d(args.n, seed=args.seed)
+    cells = args.n * args.n
+    h = min(flow.h)
+    opts = W.default_opts(eps_mode=1, eps0=flow.eps0)
+    solver = W.Solver(flow, opts)
+    W.wenott_set_profiling(solver.ctx, True)
+
+    def tt_step():
+        a = solver.max_wavespeed()
+        solver.step(flow.cfl * h / a)
+
+    t_sim = 0.0
+    for _ in range(args.warmup):
+        a = solver.max_wavespeed()
+        solver.step(flow.cfl * h / a)
+        t_sim += flow.cfl * h / a
+    torch.cuda.synchronize()
+    fiber_ms = 0.0
+    fiber_pts = 0
+    fiber_launch = 0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        a = solver.max_wavespeed()
+        dt = flow.cfl * h / a
+        solver.step(dt)
+        t_sim += dt
+        inf = solver.info()
+        fiber_ms += inf.fiber_ms
+        fiber_pts += inf.fiber_points
+        fiber_launch += inf.fiber_launches
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    info = solver.info()
+    ranks = list(info.ranks)[:3]
+    eps_now = info.eps
+    solver.close()
+
+    # fiber kernel roofline (FP64 ALU bound): algorithmic flops / device time of its launches
+    flop = FLOP_PER_POINT[2] * fiber_pts
+    achieved = flop / (fiber_ms * 1e-3) / 1e12 if fiber_ms > 0 else 0.0
+    roofline = {"bound": "alu", "kernel": "k_weno (fused LF + WENO5-JS fiber kernel)",
+                "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                "flop_per_point": FLOP_PER_POINT[2], "points": fiber_pts, "launches": fiber_launch,
+                "avg_launch_us": fiber_ms * 1e3 / max(fiber_launch, 1)}
+
+    dense = None
+    if not args.no_dense:
+        import numpy as np
+        # dense GPU WENO5 comparator on the same initial state and the same number of steps
+        u0 = None
+        s2 = W.Solver(flow, opts)
+        u0 = s2.dense(device=True)
+        s2.close()
+        ctx = W.wenott_dense_init(flow.n, flow.lo, flow.hi, flow.gamma, flow.bc)
+        for _ in range(args.warmup):
+            a = W.wenott_dense_max_wavespeed(ctx, u0)
+            W.wenott_dense_rk3_step(ctx, u0, flow.cfl * h / a)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            a = W.wenott_dense_max_wavespeed(ctx, u0)
+            W.wenott_dense_rk3_step(ctx, u0, flow.cfl * h / a)
+        torch.cuda.synchronize()
+        el2 = time.perf_counter() - t1
+        W.wenott_dense_destroy(ctx)
+        dense = {"value": cells * args.steps / el2, "unit": "cell-updates/s", "ms_per_step": el2 * 1e3 / args.steps,
+                 "note": "hand-written dense FP64 WENO5-JS + LF + SSP-RK3 on the same GPU, same steps"}
+
+    out = {
+        "metric": METRIC,
+        "value": cells * args.steps / el,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": el * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"four-quadrant Riemann problem 2D {args.n}x{args.n}, transmissive, seed {args.seed}, "
+                               f"dynamic eps_TT from 1e-8, CFL 0.5",
+                   "t_sim_end": t_sim, "ranks": ranks, "eps_tt": eps_now},
+        "roofline": roofline,
+        "dense_gpu_weno5": dense,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(flow, args.cpu_seconds)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,204 @@
+/*
+ * wenott.h - C ABI of the WENO-TT hot path for AMD Instinct MI355X (gfx950).
+ *
+ * The library advances a compressible-flow state stored as tensor trains (one TT per
+ * conserved variable, Sec. 4.1 after eq. euler-system-TT) by the WENO-TT scheme:
+ * cross-interpolated Lax-Friedrichs + WENO5-JS numerical fluxes (Sec. 4.2-4.3,
+ * Algorithms lf-cross and weno-cross, fused into one cross per direction), the
+ * shift-operator flux difference (eqs. shifted-fluxes and euler-system-TT), SSP-RK3
+ * stages rounded once each (Sec. 4.4, eq. tt-ssprk3) with the dynamic truncation
+ * tolerance of Sec. 4.6 (eq. eps-tt-formula).
+ *
+ * Conventions that hold for every call:
+ *  - Every call returns a wenott_status; nothing throws across the ABI.
+ *  - Pointers are plain host or device pointers as stated per argument. "device" means
+ *    memory of the HIP device that was current when wenott_init ran.
+ *  - All GPU work is enqueued on the hip stream given to wenott_init (NULL = the null
+ *    stream). Calls that return host values synchronise that stream before returning.
+ *  - A context is used by one host thread at a time.
+ *  - Tensor-train cores are (R_{k-1}, N_k, R_k) arrays in C order (R_k fastest),
+ *    R_0 = R_d = 1, FP64. Grids are cell-centred: x_i = lo + (i + 1/2) h, h = (hi-lo)/N.
+ */
+#ifndef WENOTT_H
+#define WENOTT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct wenott_ctx wenott_ctx; /* opaque */
+
+typedef enum {
+    WENOTT_OK = 0,
+    WENOTT_EINVAL = -1,   /* bad argument: shapes, ranks, sizes, NULL pointers */
+    WENOTT_ENOMEM = -2,   /* device or host allocation failed */
+    WENOTT_EHIP = -3,     /* a HIP runtime call failed */
+    WENOTT_ENOCONV = -4,  /* a cross did not reach its tolerance within max_sweeps / rank_cap */
+    WENOTT_ENONPHYS = -5, /* rho <= 0 or p <= 0 met at an evaluated point */
+    WENOTT_ENAN = -6,     /* NaN or Inf met */
+    WENOTT_ENOTBUILT = -7 /* feature not available in this build */
+} wenott_status;
+
+/* Boundary treatment per grid side (Sec. 4.5). PERIODIC copies core slices (Sec. 4.5.1);
+ * TRANSMISSIVE is zero-order extrapolation (the paper does not describe it). Both are
+ * realised as index maps of the ghost cells, never as stored ghost slices. */
+typedef enum { WENOTT_BC_PERIODIC = 0, WENOTT_BC_TRANSMISSIVE = 1 } wenott_bc;
+
+/* Uniform cell-centred grid: ndim in {2, 3}; n[d] interior cells; box [lo, hi]. */
+typedef struct {
+    int32_t ndim;
+    int32_t pad_;
+    int64_t n[3];
+    double lo[3];
+    double hi[3];
+} wenott_grid;
+
+/* A list of ncomp tensor trains (one per conserved variable, ncomp = ndim + 2).
+ * ranks:  host array [ncomp][ndim + 1]; ranks[c][0] = ranks[c][ndim] = 1.
+ * cores:  host array of ncomp * ndim pointers; cores[c * ndim + k] points to the
+ *         (ranks[c][k], N_k, ranks[c][k+1]) FP64 core, on the host (on_device = 0) or
+ *         the device (on_device = 1).
+ * In views returned by the library, ranks and cores point into library-owned memory
+ * that stays valid until the next call that changes the state; the cores are then
+ * device pointers and every component carries the same (padded) ranks. */
+typedef struct {
+    int32_t ndim;
+    int32_t ncomp;
+    const int64_t *ranks;
+    const void *const *cores;
+    int32_t dtype;     /* 0 = FP64 (the only accepted value) */
+    int32_t on_device; /* 0 host, 1 device */
+} wenott_tt;
+
+/* Options. wenott_default_opts fills the defaults listed in brackets. */
+typedef struct {
+    double c_eps;       /* C_eps of eq. eps-tt-formula, used when eps_mode = 1 and eps0 <= 0 [0] */
+    double eps0;        /* eps_mode 0: the fixed eps_TT; eps_mode 1: eps at t = 0 fixes C_eps [1e-10] */
+    int32_t eps_mode;   /* 0 fixed eps_TT, 1 dynamic eps_TT (Sec. 4.6) [0] */
+    int32_t precision;  /* 0 FP64 fiber evaluation; 1 FP32 gather + reconstruction [0] */
+    int32_t max_sweeps; /* maximum left-to-right cross sweeps per cross [4] */
+    int32_t kick_rank;  /* random enrichment indices added to each sampled index set [4] */
+    int32_t rank_cap;   /* maximum rank of any bond, cross and rounding [256] */
+    int32_t probe_points; /* random points of the sampled cross residual [4096] */
+    uint64_t seed;      /* seed of the library's own counter-based generator [12345] */
+    int32_t alpha_mode; /* 0 exact max(|u|+a) over the grid, 2 use alpha_given [0] */
+    int32_t use_proposal; /* reserved, must be 0 [0] */
+    double alpha_given; /* the Lax-Friedrichs alpha when alpha_mode = 2 */
+    int32_t rounds_per_stage; /* 1 = one rounding per SSP-RK3 stage [1] */
+    int32_t graph_mode; /* reserved, must be 0 [0] */
+} wenott_opts;
+
+/* Per-call diagnostics, filled by wenott_get_info. */
+typedef struct {
+    int32_t ndim, ncomp;
+    int64_t ranks[4];        /* bond ranks of the state (padded, common to all components) */
+    double alpha[3];         /* alpha used by each stage of the last step (or of the last rhs in [0]) */
+    double eps;              /* eps_TT used by the last step */
+    double c_eps;            /* C_eps in force (dynamic mode) */
+    double max_norm;         /* max over components of the Frobenius norm after the last rounding */
+    int32_t sweeps[3][3];    /* [stage][direction] left-to-right sweeps of each cross */
+    double residual[3][3];   /* [stage][direction] sampled relative residual of the accepted cross */
+    int64_t flux_rank[3][3]; /* [stage][direction] largest bond rank of each flux TT */
+    int64_t sum_rank[3];     /* largest bond rank of each stage's sum before rounding */
+    int64_t fiber_points;    /* flux values evaluated by fiber kernels in the last call */
+    double fiber_ms;         /* device time of the fiber kernels in the last call */
+    int64_t fiber_launches;  /* number of fiber-kernel launches in the last call */
+    double step_ms;          /* host wall time of the last call */
+} wenott_info;
+
+/* Fill *o with the defaults. */
+void wenott_default_opts(wenott_opts *o);
+
+/*
+ * Create a context holding a copy of the state (the caller keeps ownership of its buffers).
+ *   out:    receives the context.
+ *   state:  the initial TT list (Sec. 4.1: U_TT = {rho_TT, (rho u)_TT, ..., (rho E)_TT}).
+ *   grid:   the cell-centred grid; state mode sizes must equal grid.n.
+ *   gamma:  ratio of specific heats (Sec. 2.1), > 1.
+ *   bc:     6 entries, bc[2*d + side] (side 0 = low, 1 = high); both sides of a dimension
+ *           must agree in this build.
+ *   opts:   NULL for defaults.
+ *   hip_stream: a hipStream_t (NULL = null stream).
+ * Errors: EINVAL on inconsistent shapes/ranks/options, ENOMEM, EHIP.
+ */
+wenott_status wenott_init(wenott_ctx **out, const wenott_tt *state, const wenott_grid *grid, double gamma,
+                          const int32_t *bc, const wenott_opts *opts, void *hip_stream);
+
+/*
+ * The TT of the semi-discrete right-hand side L(U) = -sum_d (T^d - 1) Fhat_d / h_d
+ * (eq. euler-system-TT): one cross of the fused LF + WENO5 flux per direction (Algorithms
+ * lf-cross and weno-cross), the shift difference on that direction's core, the sum over
+ * directions and one rounding at the context's eps. The state is not changed.
+ * alpha: the Lax-Friedrichs alpha to use, or <= 0 for the alpha_mode rule.
+ * view:  receives a library-owned view of L(U) (device cores), valid until the next call.
+ */
+wenott_status wenott_rhs(wenott_ctx *ctx, double alpha, wenott_tt *view);
+
+/*
+ * One SSP-RK3 step of size dt (eq. tt-ssprk3, Shu-Osher form) with one rounding per
+ * stage. eps <= 0 selects the eps_mode rule (fixed eps0, or eq. eps-tt-formula).
+ * alphas: NULL, or 3 host doubles giving the alpha of each stage (used when
+ *         alpha_mode = 2 semantics are wanted per stage); the alphas used are reported by
+ *         wenott_get_info either way.
+ * On error the state is left unchanged.
+ */
+wenott_status wenott_rk3_step(wenott_ctx *ctx, double dt, double eps, const double *alphas);
+
+/* TT-rounding of the state (Sec. 3.2): right-to-left orthogonalisation, then left-to-right
+ * truncated SVDs, so that ||X - Y||_F <= eps ||X||_F per component. eps > 0. */
+wenott_status wenott_round(wenott_ctx *ctx, double eps);
+
+/* Dense values of the state into a caller buffer out[ncomp][N_1][N_2][N_3] (C order, FP64).
+ * on_device = 1: out is device memory (written on the stream); 0: host memory (synchronises). */
+wenott_status wenott_to_dense(wenott_ctx *ctx, double *out, int32_t on_device);
+
+/* Library-owned view of the current state (device cores, padded common ranks). */
+wenott_status wenott_get_state(wenott_ctx *ctx, wenott_tt *view);
+
+/* Diagnostics of the last rhs / rk3_step call and the current ranks. Synchronises. */
+wenott_status wenott_get_info(wenott_ctx *ctx, wenott_info *info);
+
+/* max over the grid of |u| + a for the current state (the alpha of eq. lax-friedrichs as
+ * defined for the Euler system in Sec. 4.2), for the caller's dt = lambda h / alpha
+ * (eq. cfl-other). Synchronises. ENONPHYS if rho <= 0 or p <= 0 anywhere. */
+wenott_status wenott_max_wavespeed(wenott_ctx *ctx, double *alpha);
+
+/* Current eps_TT of the dynamic rule (eq. eps-tt-formula) or the fixed one. */
+wenott_status wenott_current_eps(wenott_ctx *ctx, double *eps);
+
+/* Record device time of the fiber kernels (reported as fiber_ms by wenott_get_info). */
+wenott_status wenott_set_profiling(wenott_ctx *ctx, int32_t on);
+
+/* Text of the last error met by this context ("" if none); with ctx = NULL, the last error
+ * met by any call on this host thread (e.g. a failed wenott_init). */
+const char *wenott_last_error(wenott_ctx *ctx);
+
+void wenott_destroy(wenott_ctx *ctx);
+const char *wenott_strerror(wenott_status s);
+
+/* ------------------------------------------------------------------------------------
+ * Dense comparator: the same FP64 scheme on the full grid (the paper's "full-tensor"
+ * solver of Sec. 2, eq. euler-system-no-for-loop), run on the GPU. It is what WENO-TT's
+ * dense-equivalent throughput is compared with; it is not used by the TT path.
+ * U and L are device arrays [ncomp][N_1][N_2][N_3] (C order, FP64) owned by the caller.
+ * ---------------------------------------------------------------------------------- */
+typedef struct wenott_dense wenott_dense;
+
+wenott_status wenott_dense_init(wenott_dense **out, const wenott_grid *grid, double gamma, const int32_t *bc,
+                                void *hip_stream);
+/* exact max over the grid of |u| + a; ENONPHYS if rho <= 0 or p <= 0 anywhere. Synchronises. */
+wenott_status wenott_dense_max_wavespeed(wenott_dense *ctx, const double *U, double *alpha);
+/* L(U) with the given Lax-Friedrichs alpha (> 0). */
+wenott_status wenott_dense_rhs(wenott_dense *ctx, const double *U, double alpha, double *L);
+/* One SSP-RK3 step in place. alphas: NULL (exact alpha of each stage input, synchronises per
+ * stage) or 3 host doubles; alphas_used: NULL or 3 host doubles receiving the alphas. */
+wenott_status wenott_dense_rk3_step(wenott_dense *ctx, double *U, double dt, const double *alphas,
+                                    double *alphas_used);
+void wenott_dense_destroy(wenott_dense *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* WENOTT_H */

@@ -1,0 +1,141 @@
+// Internal declarations shared by the HIP kernels and the host driver of libwenott.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+
+#include "wenott.h"
+
+namespace wtt {
+
+struct HipError : std::runtime_error {
+    hipError_t code;
+    HipError(hipError_t c, const char *file, int line)
+        : std::runtime_error(std::string(hipGetErrorString(c)) + " at " + file + ":" + std::to_string(line)), code(c) {}
+};
+struct StatusError : std::runtime_error {
+    wenott_status status;
+    StatusError(wenott_status s, const std::string &m) : std::runtime_error(m), status(s) {}
+};
+
+#define WTT_HIP(x)                                                     \
+    do {                                                               \
+        hipError_t e_ = (x);                                           \
+        if (e_ != hipSuccess) throw ::wtt::HipError(e_, __FILE__, __LINE__); \
+    } while (0)
+#define WTT_REQUIRE(cond, status, msg)                                 \
+    do {                                                               \
+        if (!(cond)) throw ::wtt::StatusError(status, msg);            \
+    } while (0)
+
+constexpr int kMaxDim = 3;
+constexpr int kMaxComp = 5;
+constexpr int kMaxRankLds = 128;  // largest cross rank whose pivot block fits in LDS
+
+// Device flag bits raised by evaluation kernels.
+constexpr int kFlagNonPhys = 1;
+constexpr int kFlagNaN = 2;
+
+// Ghost-cell map: periodic wraps, transmissive clamps (both sides alike).
+__host__ __device__ inline int ghost_map(int i, int n, int bc) {
+    if (bc == WENOTT_BC_PERIODIC) {
+        int r = i % n;
+        return r < 0 ? r + n : r;
+    }
+    return i < 0 ? 0 : (i >= n ? n - 1 : i);
+}
+
+// ------------------------------------------------------------------ linalg.hip
+// Batched C = alpha * op(A) * op(B) + beta * C, row-major FP64. Batch index z = zc * nb2 + zs.
+struct GemmBatch {
+    int nb1 = 1, nb2 = 1;
+    long long sA1 = 0, sA2 = 0, sB1 = 0, sB2 = 0, sC1 = 0, sC2 = 0;
+};
+void gemm_f64(hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha, const double *A, int lda,
+              const double *B, int ldb, double beta, double *C, int ldc, const GemmBatch &bt = GemmBatch());
+
+// R factor of a batch of tall matrices by Householder TSQR. Element (i, j) of matrix z is
+// A[z * sz + i * rs + j * cs]. Writes the n x n upper-triangular R of each into
+// R[z * n * n] (row-major, zeros below the diagonal). Needs scratch of tsqr_scratch_doubles.
+size_t tsqr_scratch_doubles(int m, int n, int batch);
+void tsqr_r(hipStream_t s, int m, int n, int batch, const double *A, long long sz, long long rs, long long cs,
+            double *R, double *scratch);
+
+// One-sided Jacobi SVD of a batch of n x n matrices (row-major at A[z * n * n]).
+// Outputs sigma[z * n + j] sorted descending and V[z * n * n] row-major with column j the
+// right singular vector of sigma_j. scratch: 2 * batch * n * n doubles.
+void jacobi_svd(hipStream_t s, int n, int batch, const double *A, double *sigma, double *V, double *scratch);
+
+// Full-pivot rank-revealing LU of one m x n row-major matrix (overwritten by its residual).
+// Stops when the residual's squared Frobenius norm <= rel_tol2 * (initial squared norm), after
+// rmax pivots, or at a zero residual. Writes rank (>= 1), row/col pivots, L columns (m x rmax, row-major) and the final
+// residual norm^2 into info[0..1] = {rank, resid2} (as doubles).
+void prrlu(hipStream_t s, int m, int n, double *A, int rmax, double rel_tol2, int *rowpiv, int *colpiv, double *L,
+           double *info, double *rowbuf);
+
+// X (m x r, row-major) = L (m x ldl) * inv(L[rowpiv, :r]), the interpolative basis.
+void interp_solve(hipStream_t s, int m, int r, const double *L, int ldl, const int *rowpiv, double *X);
+
+// ------------------------------------------------------------------ fiber.hip
+struct FiberGeom {
+    int d, ncomp, dir, k;       // dimension, components, flux direction, free core
+    int n[kMaxDim];             // cells per dimension
+    int bc[kMaxDim];            // boundary code per dimension
+    double gamma, alpha, eps_w; // EOS, LF alpha, WENO epsilon (h_dir^2)
+};
+
+// Interface matrices of the state cores. Left (side 0): P[c][s][a][R_k] for the p left
+// multi-indices idx[a * k + j], j < k. Right (side 1): Q[c][s][R_{k+1}][b] for the q right
+// multi-indices idx[b * (d-1-k) + j] (modes k+1..d-1). When the flux direction's mode is among
+// the multi-index modes, its entry is a face index m and S = 6 shifted copies hold the cells
+// m-3 .. m+2 (ghost-mapped); otherwise S = 1.
+void iface(hipStream_t s, const FiberGeom &g, int side, const double *const *cores, const int *ranks, int count,
+           const int *idx, int S, double *out);
+
+// Fused LF + WENO5-JS flux evaluation of a block from the gathered stencil values.
+// Wv layout: same_dir (k == dir): W[c][a][cell][b] over N_k cells, the block's middle mode is
+// the N_k + 1 faces; otherwise W[c][s][a][i][b] (6 shifts, N_k cells). Output element
+// (a, i, b, c) goes to out[a * sa + i * si + b * sb + c * sc]. flags: device int (OR-ed bits).
+template <typename T>
+void weno_block(hipStream_t s, const FiberGeom &g, int p, int q, const T *W, double *out, long long sa, long long si,
+                long long sb, long long sc, int *flags);
+
+// Dense evaluation of a TT list from the left part Lm[c] ((prod of N_0..N_{d-2}) x R) and the
+// last cores G[c] (R x N_{d-1}): mode 0 writes out[c][cell]; mode 1 reduces max(|u|+a) into
+// partial[block] and raises flags on non-physical cells.
+void dense_eval(hipStream_t s, int mode, int d, int ncomp, long long nrows, int R, int nlast, const double *Lm,
+                long long lm_stride, const double *G, long long g_stride, double gamma, double *out, double *partial,
+                int nblocks, int *flags);
+double reduce_max_host(hipStream_t s, const double *partial, int n, double *dscratch);
+
+// Sampled residual of a flux TT at random points (face index on mode dir).
+void sample_residual(hipStream_t s, const FiberGeom &g, const double *const *ucores, const int *ranks, int npts,
+                     const int *pts, const double *const *fcores, const int *franks, double *ustencil, double *acc,
+                     int *flags);
+
+// ------------------------------------------------------------------ tt.hip
+void fill(hipStream_t s, double *p, long long n, double v);
+// out[c][o_r + a][i][o_c + b] = w * G[c][a][i][b] (per-component strides given).
+void place_block(hipStream_t s, int ncomp, int ra, int n, int rb, const double *G, long long gstride, double w,
+                 double *out, int Ra, int Rb, long long ostride, int o_r, int o_c);
+// out[c][a][i][b] = scale * (G[c][a][i+1][b] - G[c][a][i][b]), i < n (G has n + 1 faces).
+void face_diff(hipStream_t s, int ncomp, int ra, int n, int rb, const double *G, long long gstride, double scale,
+               double *out, long long ostride);
+// Transposed copy: out[t][i][b] = X[(i * q + b) * r + t] (R->L interpolative core).
+void transpose_rows(hipStream_t s, int M, int q, int r, const double *X, double *out);
+// Copy the last core's component slices into per-component cores: out[c][a][i][0] = G[a][i][c].
+void split_last(hipStream_t s, int ra, int n, int ncomp, const double *G, double *out, long long ostride);
+// Broadcast a shared core to every component slot.
+void broadcast_core(hipStream_t s, int ncomp, long long len, const double *G, double *out, long long ostride);
+// Rounding helpers: per component c, rank r_c from sigma tail vs delta_c, then
+// W1[c] = V[:, :r_c] diag(1/sigma) (n x R), W2[c] = diag(sigma) V[:, :r_c]^T (R x n), padded to R.
+void trunc_ranks(hipStream_t s, int n, int batch, const double *sigma, const double *delta_abs, double rel, int rcap,
+                 int *ranks);
+void build_projectors(hipStream_t s, int n, int batch, int R, const double *sigma, const double *V, const int *ranks,
+                      double *W1, double *W2);
+void frob_norms(hipStream_t s, int batch, long long len, const double *X, long long stride, double *out);
+
+}  // namespace wtt

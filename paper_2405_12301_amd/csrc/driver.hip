@@ -1,0 +1,1024 @@
+// Host driver and C ABI of libwenott (see include/wenott.h).
+//
+// One SSP-RK3 step of WENO-TT (Sec. 4): for each stage, the Lax-Friedrichs alpha of the
+// stage input; for each direction, one rank-adaptive cross of the fused LF + WENO5-JS flux
+// (the LF-cross and WENO-cross of Algorithms lf-cross / weno-cross fused into a single
+// function of the state, with one slice per conserved variable on the last core as in
+// Sec. 4.2); the shift difference (T - 1)/h on that direction's core; the stage's linear
+// combination as a TT sum; one TT-rounding (Sec. 3.2) at eps_TT, which follows eq.
+// eps-tt-formula in dynamic mode.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <new>
+#include <vector>
+
+#include "common.h"
+
+using namespace wtt;
+
+namespace {
+
+// splitmix64: the library's own counter-based generator (pivot enrichment and probe points).
+struct Rng {
+    uint64_t s;
+    explicit Rng(uint64_t seed) : s(seed) {}
+    uint64_t next() {
+        uint64_t z = (s += 0x9E3779B97F4A7C15ULL);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+        return z ^ (z >> 31);
+    }
+    int below(int n) { return (int)(next() % (uint64_t)n); }
+};
+
+// Stream-ordered device allocation.
+template <typename T>
+T *dalloc(hipStream_t s, size_t count) {
+    void *p = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMallocAsync(&p, count * sizeof(T), s);
+    if (e == hipErrorOutOfMemory) throw StatusError(WENOTT_ENOMEM, "device allocation failed");
+    WTT_HIP(e);
+    return (T *)p;
+}
+inline void dfree(hipStream_t s, void *p) {
+    if (p) WTT_HIP(hipFreeAsync(p, s));
+}
+
+enum Slot {
+    S_P, S_Q, S_T, S_W, S_BLOCK, S_L, S_X, S_PIV, S_INFO, S_ROWBUF, S_TSQR, S_R, S_SIG, S_V, S_JAC, S_W1, S_W2,
+    S_RANKS, S_PART, S_DSCAL, S_UST, S_ACC, S_LM, S_NORMS, S_DELTA, S_TMP, S_DENSE, S_NSLOTS
+};
+
+struct Scratch {
+    hipStream_t s = nullptr;
+    void *p[S_NSLOTS] = {};
+    size_t cap[S_NSLOTS] = {};
+    template <typename T>
+    T *get(int slot, size_t count) {
+        size_t bytes = std::max<size_t>(count * sizeof(T), 256);
+        if (cap[slot] < bytes) {
+            dfree(s, p[slot]);
+            p[slot] = nullptr;
+            size_t nb = std::max(bytes, cap[slot] + cap[slot] / 2);
+            p[slot] = dalloc<char>(s, nb);
+            cap[slot] = nb;
+        }
+        return (T *)p[slot];
+    }
+    void release() {
+        for (int i = 0; i < S_NSLOTS; ++i) {
+            if (p[i]) hipFreeAsync(p[i], s);
+            p[i] = nullptr;
+            cap[i] = 0;
+        }
+    }
+};
+
+// Upload ring: pinned host staging + device mirror, reused in stream order.
+struct Ring {
+    hipStream_t s = nullptr;
+    char *h = nullptr, *dv = nullptr;
+    size_t cap = 0, off = 0;
+    void init(hipStream_t st, size_t bytes) {
+        s = st;
+        cap = bytes;
+        WTT_HIP(hipHostMalloc((void **)&h, cap, hipHostMallocDefault));
+        WTT_HIP(hipMalloc((void **)&dv, cap));
+    }
+    void destroy() {
+        if (h) hipHostFree(h);
+        if (dv) hipFree(dv);
+        h = dv = nullptr;
+    }
+    template <typename T>
+    T *put(const T *src, size_t count) {
+        size_t bytes = std::max<size_t>(count * sizeof(T), 8);
+        bytes = (bytes + 255) / 256 * 256;
+        WTT_REQUIRE(bytes <= cap, WENOTT_EINVAL, "upload larger than the staging ring");
+        if (off + bytes > cap) {
+            WTT_HIP(hipStreamSynchronize(s));
+            off = 0;
+        }
+        std::memcpy(h + off, src, count * sizeof(T));
+        WTT_HIP(hipMemcpyAsync(dv + off, h + off, count * sizeof(T), hipMemcpyHostToDevice, s));
+        T *r = (T *)(dv + off);
+        off += bytes;
+        return r;
+    }
+};
+
+// A list of ncomp TTs with common (padded) bond ranks; core k is [c][R_k][N_k][R_{k+1}].
+struct TT {
+    int d = 0, nc = 0;
+    int N[kMaxDim] = {};
+    int R[kMaxDim + 1] = {};
+    double *core[kMaxDim] = {};
+    long long cstride(int k) const { return (long long)R[k] * N[k] * R[k + 1]; }
+    int maxrank() const {
+        int r = 1;
+        for (int k = 1; k < d; ++k) r = std::max(r, R[k]);
+        return r;
+    }
+    void alloc(hipStream_t s) {
+        for (int k = 0; k < d; ++k) core[k] = dalloc<double>(s, (size_t)cstride(k) * nc);
+    }
+    void release(hipStream_t s) {
+        for (int k = 0; k < d; ++k) {
+            dfree(s, core[k]);
+            core[k] = nullptr;
+        }
+    }
+};
+
+// Output of one cross: shared cores [R_k][M_k][R_{k+1}] for k < d-1 and the last core
+// [R_{d-1}][M_{d-1}][ncomp] carrying one slice per conserved variable.
+struct FluxTT {
+    int d = 0, nc = 0;
+    int M[kMaxDim] = {};
+    int R[kMaxDim + 1] = {};
+    double *core[kMaxDim] = {};
+    void release(hipStream_t s) {
+        for (int k = 0; k < d; ++k) {
+            dfree(s, core[k]);
+            core[k] = nullptr;
+        }
+    }
+};
+
+struct ISet {  // a set of multi-indices of a fixed length
+    int len = 0, count = 0;
+    std::vector<int> v;
+};
+
+}  // namespace
+
+struct wenott_ctx {
+    int d = 0, nc = 0;
+    int N[kMaxDim] = {};
+    double lo[kMaxDim] = {}, hi[kMaxDim] = {}, h[kMaxDim] = {};
+    double gamma = 1.4;
+    int bc[kMaxDim] = {};
+    wenott_opts o{};
+    hipStream_t s = nullptr;
+    TT U;
+    TT rhs;
+    bool have_rhs = false;
+    std::vector<int64_t> view_ranks;
+    std::vector<const void *> view_ptrs;
+    Scratch sc;
+    Ring ring;
+    int *d_flags = nullptr;
+    int *h_pinned_int = nullptr;
+    double *h_pinned_dbl = nullptr;
+    std::vector<ISet> warm[kMaxDim];
+    bool warm_valid[kMaxDim] = {};
+    uint64_t counter = 0;
+    double c_eps = 0.0, max_norm = 0.0;
+    bool profiling = false;
+    std::vector<hipEvent_t> ev;
+    int ev_used = 0;
+    wenott_info info{};
+    std::string last_error;
+};
+
+namespace {
+
+inline double seconds_now() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// ------------------------------------------------------------------------ helpers
+void check_flags(wenott_ctx *c) {
+    WTT_HIP(hipMemcpyAsync(c->h_pinned_int, c->d_flags, sizeof(int), hipMemcpyDeviceToHost, c->s));
+    WTT_HIP(hipStreamSynchronize(c->s));
+    int f = c->h_pinned_int[0];
+    if (f) {
+        WTT_HIP(hipMemsetAsync(c->d_flags, 0, sizeof(int), c->s));
+        if (f & kFlagNaN) throw StatusError(WENOTT_ENAN, "NaN or Inf in a flux evaluation");
+        throw StatusError(WENOTT_ENONPHYS, "rho <= 0 or p <= 0 at an evaluated point");
+    }
+}
+
+void ev_record(wenott_ctx *c) {
+    if (!c->profiling) return;
+    if (c->ev_used == (int)c->ev.size()) {
+        hipEvent_t e;
+        WTT_HIP(hipEventCreate(&e));
+        c->ev.push_back(e);
+    }
+    WTT_HIP(hipEventRecord(c->ev[c->ev_used++], c->s));
+}
+
+TT copy_tt(wenott_ctx *c, const TT &a) {
+    TT b = a;
+    b.alloc(c->s);
+    for (int k = 0; k < a.d; ++k)
+        WTT_HIP(hipMemcpyAsync(b.core[k], a.core[k], sizeof(double) * a.cstride(k) * a.nc, hipMemcpyDeviceToDevice,
+                               c->s));
+    return b;
+}
+
+// ------------------------------------------------------------------- exact alpha
+// Left part of every cell's chain product: (N_0 ... N_{d-2}) x R_{d-1} per component.
+const double *left_part(wenott_ctx *c, const TT &U, long long *stride) {
+    if (U.d == 2) {
+        *stride = U.cstride(0);
+        return U.core[0];
+    }
+    long long rows = (long long)U.N[0] * U.N[1];
+    double *Lm = c->sc.get<double>(S_LM, (size_t)rows * U.R[2] * U.nc);
+    GemmBatch bt;
+    bt.nb1 = U.nc;
+    bt.sA1 = U.cstride(0);
+    bt.sB1 = U.cstride(1);
+    bt.sC1 = rows * U.R[2];
+    gemm_f64(c->s, false, false, U.N[0], U.N[1] * U.R[2], U.R[1], 1.0, U.core[0], U.R[1], U.core[1],
+             U.N[1] * U.R[2], 0.0, Lm, U.N[1] * U.R[2], bt);
+    *stride = rows * U.R[2];
+    return Lm;
+}
+
+double exact_alpha(wenott_ctx *c, const TT &U) {
+    long long lms = 0;
+    const double *Lm = left_part(c, U, &lms);
+    long long nrows = 1;
+    for (int k = 0; k < U.d - 1; ++k) nrows *= U.N[k];
+    int nlast = U.N[U.d - 1];
+    long long ncell = nrows * nlast;
+    int nblocks = (int)((ncell + 255) / 256);
+    double *part = c->sc.get<double>(S_PART, nblocks);
+    dense_eval(c->s, 1, U.d, U.nc, nrows, U.R[U.d - 1], nlast, Lm, lms, U.core[U.d - 1], U.cstride(U.d - 1),
+               c->gamma, nullptr, part, nblocks, c->d_flags);
+    double a = reduce_max_host(c->s, part, nblocks, c->sc.get<double>(S_DSCAL, 4));
+    check_flags(c);
+    return a;
+}
+
+void to_dense_dev(wenott_ctx *c, const TT &U, double *out) {
+    long long lms = 0;
+    const double *Lm = left_part(c, U, &lms);
+    long long nrows = 1;
+    for (int k = 0; k < U.d - 1; ++k) nrows *= U.N[k];
+    int nlast = U.N[U.d - 1];
+    long long ncell = nrows * nlast;
+    int nblocks = (int)((ncell + 255) / 256);
+    dense_eval(c->s, 0, U.d, U.nc, nrows, U.R[U.d - 1], nlast, Lm, lms, U.core[U.d - 1], U.cstride(U.d - 1),
+               c->gamma, out, nullptr, nblocks, c->d_flags);
+}
+
+// ---------------------------------------------------------------- block evaluation
+// Flux block Fhat_dir(I_<k[a], i, J_>k[b], c) written with strides (L->R or R->L unfolding).
+void eval_block(wenott_ctx *c, const TT &U, int dir, int k, const ISet &L, const ISet &Rs, double alpha, bool lr,
+                double *out) {
+    const int d = U.d, nc = U.nc;
+    FiberGeom g{};
+    g.d = d; g.ncomp = nc; g.dir = dir; g.k = k;
+    for (int j = 0; j < d; ++j) { g.n[j] = U.N[j]; g.bc[j] = c->bc[j]; }
+    g.gamma = c->gamma; g.alpha = alpha; g.eps_w = c->h[dir] * c->h[dir];
+    const int p = L.count, q = Rs.count;
+    const int SL = dir < k ? 6 : 1, SR = dir > k ? 6 : 1, S = std::max(SL, SR);
+    const int Rk = U.R[k], Rk1 = U.R[k + 1], Nk = U.N[k];
+    int ranks[kMaxDim + 1];
+    for (int j = 0; j <= d; ++j) ranks[j] = U.R[j];
+    const double *cores[kMaxDim];
+    for (int j = 0; j < d; ++j) cores[j] = U.core[j];
+
+    double *P = c->sc.get<double>(S_P, (size_t)nc * SL * p * Rk);
+    if (k == 0) fill(c->s, P, (long long)nc * SL * p * Rk, 1.0);
+    else iface(c->s, g, 0, cores, ranks, p, c->ring.put(L.v.data(), L.v.size()), SL, P);
+    double *Q = c->sc.get<double>(S_Q, (size_t)nc * SR * Rk1 * q);
+    if (k == d - 1) fill(c->s, Q, (long long)nc * SR * Rk1 * q, 1.0);
+    else iface(c->s, g, 1, cores, ranks, q, c->ring.put(Rs.v.data(), Rs.v.size()), SR, Q);
+
+    const long long tsz = (long long)p * Nk * Rk1;
+    double *T = c->sc.get<double>(S_T, (size_t)nc * SL * tsz);
+    GemmBatch b1;
+    b1.nb1 = nc; b1.nb2 = SL;
+    b1.sA1 = (long long)SL * p * Rk; b1.sA2 = (long long)p * Rk;
+    b1.sB1 = U.cstride(k); b1.sB2 = 0;
+    b1.sC1 = SL * tsz; b1.sC2 = tsz;
+    gemm_f64(c->s, false, false, p, Nk * Rk1, Rk, 1.0, P, Rk, U.core[k], Nk * Rk1, 0.0, T, Nk * Rk1, b1);
+    const long long wsz = (long long)p * Nk * q;
+    double *W = c->sc.get<double>(S_W, (size_t)nc * S * wsz);
+    GemmBatch b2;
+    b2.nb1 = nc; b2.nb2 = S;
+    b2.sA1 = SL * tsz; b2.sA2 = SL == 6 ? tsz : 0;
+    b2.sB1 = (long long)SR * Rk1 * q; b2.sB2 = SR == 6 ? (long long)Rk1 * q : 0;
+    b2.sC1 = S * wsz; b2.sC2 = wsz;
+    gemm_f64(c->s, false, false, p * Nk, q, Rk1, 1.0, T, Rk1, Q, q, 0.0, W, q, b2);
+
+    const int M = k == dir ? Nk + 1 : Nk;
+    long long sa, si, sb, sc;
+    if (lr) { sa = (long long)M * q * nc; si = (long long)q * nc; sb = nc; sc = 1; }
+    else { sa = nc; si = (long long)q * p * nc; sb = (long long)p * nc; sc = 1; }
+    ev_record(c);
+    weno_block<double>(c->s, g, p, q, W, out, sa, si, sb, sc, c->d_flags);
+    ev_record(c);
+    c->info.fiber_points += (long long)p * M * q;
+    c->info.fiber_launches += 1;
+}
+
+ISet random_set(Rng &rng, int count, int first_mode, int len, const int *M) {
+    ISet s;
+    s.len = len;
+    s.count = count;
+    s.v.resize((size_t)count * len);
+    for (int a = 0; a < count; ++a)
+        for (int j = 0; j < len; ++j) s.v[(size_t)a * len + j] = rng.below(M[first_mode + j]);
+    return s;
+}
+
+ISet with_kick(const ISet &base, Rng &rng, int kick, int first_mode, const int *M) {
+    ISet s = base;
+    if (base.len == 0 || kick <= 0) return s;
+    ISet extra = random_set(rng, kick, first_mode, base.len, M);
+    s.v.insert(s.v.end(), extra.v.begin(), extra.v.end());
+    s.count += kick;
+    return s;
+}
+
+struct PivotResult {
+    int rank;
+    std::vector<int> rows;
+};
+
+PivotResult pivots(wenott_ctx *c, double *B, int m, int n, double rel_tol2, double **Lout) {
+    int rmax = std::min(std::min(c->o.rank_cap, kMaxRankLds), std::min(m, n));
+    int *piv = c->sc.get<int>(S_PIV, 2 * (size_t)rmax + 2);
+    double *L = c->sc.get<double>(S_L, (size_t)m * rmax);
+    double *info = c->sc.get<double>(S_INFO, 2);
+    double *rowbuf = c->sc.get<double>(S_ROWBUF, n);
+    prrlu(c->s, m, n, B, rmax, rel_tol2, piv, piv + rmax, L, info, rowbuf);
+    WTT_HIP(hipMemcpyAsync(c->h_pinned_dbl, info, 2 * sizeof(double), hipMemcpyDeviceToHost, c->s));
+    WTT_HIP(hipMemcpyAsync(c->h_pinned_int, piv, rmax * sizeof(int), hipMemcpyDeviceToHost, c->s));
+    WTT_HIP(hipStreamSynchronize(c->s));
+    PivotResult r;
+    r.rank = (int)c->h_pinned_dbl[0];
+    r.rows.assign(c->h_pinned_int, c->h_pinned_int + r.rank);
+    *Lout = L;
+    (void)rmax;
+    return r;
+}
+
+double sampled_residual(wenott_ctx *c, const TT &U, const FluxTT &F, int dir, double alpha, Rng &rng) {
+    const int d = U.d, npts = std::max(c->o.probe_points, 16);
+    FiberGeom g{};
+    g.d = d; g.ncomp = U.nc; g.dir = dir; g.k = 0;
+    for (int j = 0; j < d; ++j) { g.n[j] = U.N[j]; g.bc[j] = c->bc[j]; }
+    g.gamma = c->gamma; g.alpha = alpha; g.eps_w = c->h[dir] * c->h[dir];
+    std::vector<int> pts((size_t)npts * d);
+    for (int i = 0; i < npts; ++i)
+        for (int j = 0; j < d; ++j) pts[(size_t)i * d + j] = rng.below(F.M[j]);
+    const int *dp = c->ring.put(pts.data(), pts.size());
+    double *ust = c->sc.get<double>(S_UST, (size_t)npts * 6 * U.nc);
+    int nb = (npts + 255) / 256;
+    double *acc = c->sc.get<double>(S_ACC, 2 * (size_t)nb);
+    int ranks[kMaxDim + 1], franks[kMaxDim + 1];
+    for (int j = 0; j <= d; ++j) { ranks[j] = U.R[j]; franks[j] = F.R[j]; }
+    const double *uc[kMaxDim], *fc[kMaxDim];
+    for (int j = 0; j < d; ++j) { uc[j] = U.core[j]; fc[j] = F.core[j]; }
+    sample_residual(c->s, g, uc, ranks, npts, dp, fc, franks, ust, acc, c->d_flags);
+    std::vector<double> h(2 * (size_t)nb);
+    WTT_HIP(hipMemcpyAsync(h.data(), acc, h.size() * sizeof(double), hipMemcpyDeviceToHost, c->s));
+    WTT_HIP(hipStreamSynchronize(c->s));
+    double d2 = 0.0, n2 = 0.0;
+    for (int b = 0; b < nb; ++b) { d2 += h[2 * b]; n2 += h[2 * b + 1]; }
+    return n2 > 0.0 ? std::sqrt(d2 / n2) : std::sqrt(d2);
+}
+
+// ---------------------------------------------------------------------- the cross
+struct CrossStat {
+    int sweeps = 0;
+    double residual = 0.0;
+    int maxrank = 0;
+};
+
+FluxTT cross_flux(wenott_ctx *c, const TT &U, int dir, double alpha, double eps, CrossStat &st) {
+    const int d = U.d, nc = U.nc;
+    int M[kMaxDim];
+    for (int j = 0; j < d; ++j) M[j] = U.N[j] + (j == dir ? 1 : 0);
+    Rng rng(c->o.seed ^ (0x5851F42D4C957F2DULL * (++c->counter)));
+    std::vector<ISet> Rset(d);
+    Rset[d - 1].len = 0;
+    Rset[d - 1].count = 1;
+    if (c->warm_valid[dir]) {
+        Rset = c->warm[dir];
+    } else {
+        int q0 = std::max(2, U.maxrank());
+        for (int k = 0; k < d - 1; ++k) Rset[k] = random_set(rng, q0, k + 1, d - 1 - k, M);
+    }
+    std::vector<ISet> Lset(d);
+    FluxTT F;
+    F.d = d; F.nc = nc;
+    for (int j = 0; j < d; ++j) F.M[j] = M[j];
+    double rel2 = eps * eps / (4.0 * d);
+    const int kick = c->o.kick_rank;
+    double resid = 1e300;
+    int sweep = 0;
+    for (; sweep < c->o.max_sweeps; ++sweep) {
+        F.release(c->s);
+        Lset[0].len = 0;
+        Lset[0].count = 1;
+        Lset[0].v.clear();
+        F.R[0] = 1;
+        F.R[d] = 1;
+        for (int k = 0; k < d; ++k) {
+            ISet Rk = k < d - 1 ? with_kick(Rset[k], rng, kick, k + 1, M) : Rset[k];
+            const int p = Lset[k].count, q = Rk.count;
+            const long long rows = (long long)p * M[k], cols = (long long)q * nc;
+            double *B = c->sc.get<double>(S_BLOCK, (size_t)(rows * cols));
+            eval_block(c, U, dir, k, Lset[k], Rk, alpha, true, B);
+            if (k < d - 1) {
+                double *L = nullptr;
+                PivotResult pr = pivots(c, B, (int)rows, (int)cols, rel2, &L);
+                const int r = pr.rank;
+                int rmax = std::min(std::min(c->o.rank_cap, kMaxRankLds), (int)std::min(rows, cols));
+                F.core[k] = dalloc<double>(c->s, (size_t)rows * r);
+                interp_solve(c->s, (int)rows, r, L, rmax, c->sc.get<int>(S_PIV, 1), F.core[k]);
+                F.R[k + 1] = r;
+                ISet nl;
+                nl.len = k + 1;
+                nl.count = r;
+                nl.v.resize((size_t)r * (k + 1));
+                for (int t = 0; t < r; ++t) {
+                    int row = pr.rows[t], a = row / M[k], i = row % M[k];
+                    for (int j = 0; j < k; ++j) nl.v[(size_t)t * (k + 1) + j] = Lset[k].v[(size_t)a * k + j];
+                    nl.v[(size_t)t * (k + 1) + k] = i;
+                }
+                Lset[k + 1] = std::move(nl);
+                st.maxrank = std::max(st.maxrank, r);
+            } else {
+                F.core[k] = dalloc<double>(c->s, (size_t)(rows * cols));
+                WTT_HIP(hipMemcpyAsync(F.core[k], B, sizeof(double) * rows * cols, hipMemcpyDeviceToDevice, c->s));
+            }
+        }
+        resid = sampled_residual(c, U, F, dir, alpha, rng);
+        if (resid <= eps || sweep + 1 == c->o.max_sweeps) { ++sweep; break; }
+        // right-to-left sweep: refresh the right index sets from the new left ones
+        for (int k = d - 1; k >= 1; --k) {
+            ISet Lk = with_kick(Lset[k], rng, kick, 0, M);
+            const ISet &Rk = Rset[k];
+            const int p = Lk.count, q = Rk.count;
+            const long long rows = (long long)M[k] * q, cols = (long long)p * nc;
+            double *B = c->sc.get<double>(S_BLOCK, (size_t)(rows * cols));
+            eval_block(c, U, dir, k, Lk, Rk, alpha, false, B);
+            double *L = nullptr;
+            PivotResult pr = pivots(c, B, (int)rows, (int)cols, rel2, &L);
+            ISet nr;
+            nr.len = d - k;
+            nr.count = pr.rank;
+            nr.v.resize((size_t)pr.rank * nr.len);
+            for (int t = 0; t < pr.rank; ++t) {
+                int row = pr.rows[t], i = row / q, b = row % q;
+                nr.v[(size_t)t * nr.len] = i;
+                for (int j = 0; j < Rk.len; ++j) nr.v[(size_t)t * nr.len + 1 + j] = Rk.v[(size_t)b * Rk.len + j];
+            }
+            Rset[k - 1] = std::move(nr);
+        }
+        rel2 *= 0.25;
+    }
+    check_flags(c);
+    c->warm[dir] = Rset;
+    c->warm_valid[dir] = true;
+    st.sweeps = sweep;
+    st.residual = resid;
+    if (!(resid <= 1e3 * eps) && !(resid <= 1e-12))
+        throw StatusError(WENOTT_ENOCONV, "cross did not converge");
+    return F;
+}
+
+// L_dir = -(T^dir - 1) Fhat_dir / h_dir as a per-component TT.
+TT flux_to_rhs_term(wenott_ctx *c, const FluxTT &F, int dir) {
+    const int d = F.d, nc = F.nc;
+    TT L;
+    L.d = d; L.nc = nc;
+    for (int j = 0; j < d; ++j) L.N[j] = c->N[j];
+    for (int j = 0; j <= d; ++j) L.R[j] = F.R[j];
+    L.alloc(c->s);
+    const double scale = -1.0 / c->h[dir];
+    for (int k = 0; k < d - 1; ++k) {
+        long long len = L.cstride(k);
+        if (k == dir) {
+            double *tmp = c->sc.get<double>(S_TMP, (size_t)len);
+            face_diff(c->s, 1, F.R[k], L.N[k], F.R[k + 1], F.core[k], 0, scale, tmp, 0);
+            broadcast_core(c->s, nc, len, tmp, L.core[k], len);
+        } else {
+            broadcast_core(c->s, nc, len, F.core[k], L.core[k], len);
+        }
+    }
+    const int k = d - 1;
+    if (k == dir) {
+        long long per = (long long)F.R[k] * F.M[k];
+        double *tmp = c->sc.get<double>(S_TMP, (size_t)per * nc);
+        split_last(c->s, F.R[k], F.M[k], nc, F.core[k], tmp, per);
+        face_diff(c->s, nc, F.R[k], L.N[k], 1, tmp, per, scale, L.core[k], L.cstride(k));
+    } else {
+        split_last(c->s, F.R[k], F.M[k], nc, F.core[k], L.core[k], L.cstride(k));
+    }
+    return L;
+}
+
+// sum_t w_t X_t by core concatenation (first cores side by side, middle block-diagonal,
+// last stacked); the weights go on the first cores.
+TT tt_sum(wenott_ctx *c, const std::vector<std::pair<double, const TT *>> &terms) {
+    const TT &a = *terms[0].second;
+    TT S;
+    S.d = a.d; S.nc = a.nc;
+    for (int j = 0; j < a.d; ++j) S.N[j] = a.N[j];
+    S.R[0] = S.R[a.d] = 1;
+    for (int k = 1; k < a.d; ++k) {
+        S.R[k] = 0;
+        for (auto &t : terms) S.R[k] += t.second->R[k];
+    }
+    S.alloc(c->s);
+    for (int k = 0; k < S.d; ++k) fill(c->s, S.core[k], S.cstride(k) * S.nc, 0.0);
+    std::vector<int> off(S.d + 1, 0);
+    for (auto &t : terms) {
+        const TT &X = *t.second;
+        for (int k = 0; k < S.d; ++k) {
+            int orow = (k == 0) ? 0 : off[k];
+            int ocol = (k == S.d - 1) ? 0 : off[k + 1];
+            place_block(c->s, S.nc, X.R[k], S.N[k], X.R[k + 1], X.core[k], X.cstride(k), k == 0 ? t.first : 1.0,
+                        S.core[k], S.R[k], S.R[k + 1], S.cstride(k), orow, ocol);
+        }
+        for (int k = 1; k < S.d; ++k) off[k] += X.R[k];
+    }
+    return S;
+}
+
+// SVD pieces of a batch of tall matrices: sigma (sorted) and V, then per-component ranks.
+int svd_ranks(wenott_ctx *c, int m, int n, const double *A, long long sz, long long rs, long long cs,
+              const double *delta_abs, double rel, int rcap, double **sig, double **V, int **rk) {
+    const int nc = c->U.nc;
+    double *scr = c->sc.get<double>(S_TSQR, tsqr_scratch_doubles(m, n, nc));
+    double *R = c->sc.get<double>(S_R, (size_t)nc * n * n);
+    tsqr_r(c->s, m, n, nc, A, sz, rs, cs, R, scr);
+    *sig = c->sc.get<double>(S_SIG, (size_t)nc * n);
+    *V = c->sc.get<double>(S_V, (size_t)nc * n * n);
+    double *jac = c->sc.get<double>(S_JAC, (size_t)nc * (2 * (size_t)n * n + n));
+    jacobi_svd(c->s, n, nc, R, *sig, *V, jac);
+    *rk = c->sc.get<int>(S_RANKS, nc);
+    trunc_ranks(c->s, n, nc, *sig, delta_abs, rel, rcap, *rk);
+    WTT_HIP(hipMemcpyAsync(c->h_pinned_int, *rk, nc * sizeof(int), hipMemcpyDeviceToHost, c->s));
+    WTT_HIP(hipStreamSynchronize(c->s));
+    int r = 1;
+    for (int z = 0; z < nc; ++z) r = std::max(r, c->h_pinned_int[z]);
+    return r;
+}
+
+// TT-rounding (Sec. 3.2). Returns the Frobenius norms of the components in norms.
+void round_tt(wenott_ctx *c, TT &X, double eps, bool truncate, std::vector<double> &norms) {
+    const int d = X.d, nc = X.nc;
+    hipStream_t s = c->s;
+    // right-to-left orthogonalisation: core_k = (Sigma^-1 V^T) B, core_{k-1} <- core_{k-1} V Sigma
+    for (int k = d - 1; k >= 1; --k) {
+        const int n = X.R[k];
+        const int m = X.N[k] * X.R[k + 1];
+        double *sig, *V;
+        int *rk;
+        int r = svd_ranks(c, m, n, X.core[k], X.cstride(k), 1, m, nullptr, 1e-15, n, &sig, &V, &rk);
+        double *W1 = c->sc.get<double>(S_W1, (size_t)nc * n * r);
+        double *W2 = c->sc.get<double>(S_W2, (size_t)nc * n * r);
+        build_projectors(s, n, nc, r, sig, V, rk, W1, W2);
+        double *nk = dalloc<double>(s, (size_t)nc * r * m);
+        GemmBatch b1;
+        b1.nb1 = nc; b1.sA1 = (long long)n * r; b1.sB1 = X.cstride(k); b1.sC1 = (long long)r * m;
+        gemm_f64(s, true, false, r, m, n, 1.0, W1, r, X.core[k], m, 0.0, nk, m, b1);
+        const int mp = X.R[k - 1] * X.N[k - 1];
+        double *nkm = dalloc<double>(s, (size_t)nc * mp * r);
+        GemmBatch b2;
+        b2.nb1 = nc; b2.sA1 = X.cstride(k - 1); b2.sB1 = (long long)r * n; b2.sC1 = (long long)mp * r;
+        gemm_f64(s, false, true, mp, r, n, 1.0, X.core[k - 1], n, W2, n, 0.0, nkm, r, b2);
+        dfree(s, X.core[k]);
+        dfree(s, X.core[k - 1]);
+        X.core[k] = nk;
+        X.core[k - 1] = nkm;
+        X.R[k] = r;
+    }
+    double *dn = c->sc.get<double>(S_NORMS, nc);
+    frob_norms(s, nc, X.cstride(0), X.core[0], X.cstride(0), dn);
+    norms.resize(nc);
+    WTT_HIP(hipMemcpyAsync(c->h_pinned_dbl, dn, nc * sizeof(double), hipMemcpyDeviceToHost, s));
+    WTT_HIP(hipStreamSynchronize(s));
+    for (int z = 0; z < nc; ++z) norms[z] = c->h_pinned_dbl[z];
+    if (!truncate) return;
+    std::vector<double> delta(nc);
+    for (int z = 0; z < nc; ++z) delta[z] = eps * norms[z] / std::sqrt((double)std::max(d - 1, 1));
+    const double *ddelta = c->ring.put(delta.data(), delta.size());
+    // left-to-right truncation: core_k = A V_r Sigma_r^-1, core_{k+1} <- Sigma_r V_r^T core_{k+1}
+    for (int k = 0; k < d - 1; ++k) {
+        const int m = X.R[k] * X.N[k];
+        const int n = X.R[k + 1];
+        double *sig, *V;
+        int *rk;
+        int r = svd_ranks(c, m, n, X.core[k], X.cstride(k), n, 1, ddelta, 0.0, c->o.rank_cap, &sig, &V, &rk);
+        double *W1 = c->sc.get<double>(S_W1, (size_t)nc * n * r);
+        double *W2 = c->sc.get<double>(S_W2, (size_t)nc * n * r);
+        build_projectors(s, n, nc, r, sig, V, rk, W1, W2);
+        double *nk = dalloc<double>(s, (size_t)nc * m * r);
+        GemmBatch b1;
+        b1.nb1 = nc; b1.sA1 = X.cstride(k); b1.sB1 = (long long)n * r; b1.sC1 = (long long)m * r;
+        gemm_f64(s, false, false, m, r, n, 1.0, X.core[k], n, W1, r, 0.0, nk, r, b1);
+        const int mn = X.N[k + 1] * X.R[k + 2];
+        double *nk1 = dalloc<double>(s, (size_t)nc * r * mn);
+        GemmBatch b2;
+        b2.nb1 = nc; b2.sA1 = (long long)r * n; b2.sB1 = X.cstride(k + 1); b2.sC1 = (long long)r * mn;
+        gemm_f64(s, false, false, r, mn, n, 1.0, W2, n, X.core[k + 1], mn, 0.0, nk1, mn, b2);
+        dfree(s, X.core[k]);
+        dfree(s, X.core[k + 1]);
+        X.core[k] = nk;
+        X.core[k + 1] = nk1;
+        X.R[k + 1] = r;
+    }
+}
+
+double geometric_h(const wenott_ctx *c) {
+    double p = 1.0;
+    for (int k = 0; k < c->d; ++k) p *= c->h[k];
+    return std::pow(p, 1.0 / c->d);
+}
+double volume(const wenott_ctx *c) {
+    double v = 1.0;
+    for (int k = 0; k < c->d; ++k) v *= c->hi[k] - c->lo[k];
+    return v;
+}
+// eq. eps-tt-formula generalised to d dimensions: eps = C_eps V^{1/2} h^{5 - d/2} / max_q ||q||_F
+double dynamic_eps(const wenott_ctx *c, double max_norm) {
+    return c->c_eps * std::sqrt(volume(c)) * std::pow(geometric_h(c), 5.0 - 0.5 * c->d) / max_norm;
+}
+double current_eps(const wenott_ctx *c) {
+    if (c->o.eps_mode == 0) return c->o.eps0;
+    return dynamic_eps(c, c->max_norm);
+}
+
+// L(U) as a TT: cross per direction, shift difference, sum over directions.
+std::vector<TT> rhs_terms(wenott_ctx *c, const TT &U, double alpha, double eps, int stage) {
+    std::vector<TT> terms;
+    for (int dir = 0; dir < U.d; ++dir) {
+        CrossStat st;
+        FluxTT F = cross_flux(c, U, dir, alpha, eps, st);
+        if (stage >= 0 && stage < 3) {
+            c->info.sweeps[stage][dir] = st.sweeps;
+            c->info.residual[stage][dir] = st.residual;
+            c->info.flux_rank[stage][dir] = st.maxrank;
+        }
+        terms.push_back(flux_to_rhs_term(c, F, dir));
+        F.release(c->s);
+    }
+    return terms;
+}
+
+void reset_call_info(wenott_ctx *c) {
+    c->info.fiber_points = 0;
+    c->info.fiber_launches = 0;
+    c->info.fiber_ms = 0.0;
+    c->ev_used = 0;
+}
+
+void finish_call_info(wenott_ctx *c, double t0) {
+    if (c->profiling && c->ev_used >= 2) {
+        WTT_HIP(hipStreamSynchronize(c->s));
+        double ms = 0.0;
+        for (int i = 0; i + 1 < c->ev_used; i += 2) {
+            float e = 0.f;
+            WTT_HIP(hipEventElapsedTime(&e, c->ev[i], c->ev[i + 1]));
+            ms += e;
+        }
+        c->info.fiber_ms = ms;
+    }
+    c->info.step_ms = (seconds_now() - t0) * 1e3;
+}
+
+wenott_status run_guarded(wenott_ctx *c, const std::function<void()> &f);
+
+}  // namespace
+
+// ================================================================== C ABI
+
+namespace {
+thread_local std::string g_last_error;
+
+void note_error(wenott_ctx *c, const char *what) {
+    g_last_error = what;
+    if (c) c->last_error = what;
+}
+
+wenott_status run_guarded(wenott_ctx *c, const std::function<void()> &f) {
+    try {
+        f();
+        return WENOTT_OK;
+    } catch (const StatusError &e) {
+        note_error(c, e.what());
+        return e.status;
+    } catch (const HipError &e) {
+        note_error(c, e.what());
+        return e.code == hipErrorOutOfMemory ? WENOTT_ENOMEM : WENOTT_EHIP;
+    } catch (const std::bad_alloc &) {
+        note_error(c, "host allocation failed");
+        return WENOTT_ENOMEM;
+    } catch (const std::exception &e) {
+        note_error(c, e.what());
+        return WENOTT_EINVAL;
+    }
+}
+}  // namespace
+
+extern "C" {
+
+void wenott_default_opts(wenott_opts *o) {
+    std::memset(o, 0, sizeof(*o));
+    o->c_eps = 0.0;
+    o->eps0 = 1e-10;
+    o->eps_mode = 0;
+    o->precision = 0;
+    o->max_sweeps = 4;
+    o->kick_rank = 4;
+    o->rank_cap = 256;
+    o->probe_points = 4096;
+    o->seed = 12345;
+    o->alpha_mode = 0;
+    o->use_proposal = 0;
+    o->alpha_given = 0.0;
+    o->rounds_per_stage = 1;
+    o->graph_mode = 0;
+}
+
+const char *wenott_strerror(wenott_status s) {
+    switch (s) {
+    case WENOTT_OK: return "ok";
+    case WENOTT_EINVAL: return "invalid argument";
+    case WENOTT_ENOMEM: return "out of memory";
+    case WENOTT_EHIP: return "HIP runtime error";
+    case WENOTT_ENOCONV: return "cross did not converge";
+    case WENOTT_ENONPHYS: return "non-physical state (rho <= 0 or p <= 0)";
+    case WENOTT_ENAN: return "NaN or Inf";
+    case WENOTT_ENOTBUILT: return "not available in this build";
+    }
+    return "unknown status";
+}
+
+wenott_status wenott_init(wenott_ctx **out, const wenott_tt *state, const wenott_grid *grid, double gamma,
+                          const int32_t *bc, const wenott_opts *opts, void *hip_stream) {
+    if (!out || !state || !grid || !bc) return WENOTT_EINVAL;
+    *out = nullptr;
+    wenott_ctx *c = new (std::nothrow) wenott_ctx();
+    if (!c) return WENOTT_ENOMEM;
+    wenott_status st = run_guarded(c, [&] {
+        const int d = grid->ndim;
+        WTT_REQUIRE(d == 2 || d == 3, WENOTT_EINVAL, "ndim must be 2 or 3");
+        WTT_REQUIRE(state->ndim == d && state->ncomp == d + 2, WENOTT_EINVAL, "state must hold ndim + 2 TTs");
+        WTT_REQUIRE(state->dtype == 0, WENOTT_EINVAL, "only FP64 cores are accepted");
+        WTT_REQUIRE(state->ranks && state->cores, WENOTT_EINVAL, "null ranks or cores");
+        WTT_REQUIRE(gamma > 1.0, WENOTT_EINVAL, "gamma must exceed 1");
+        c->d = d;
+        c->nc = d + 2;
+        c->gamma = gamma;
+        if (opts) c->o = *opts; else wenott_default_opts(&c->o);
+        WTT_REQUIRE(c->o.use_proposal == 0 && c->o.graph_mode == 0, WENOTT_ENOTBUILT, "option not available");
+        WTT_REQUIRE(c->o.precision == 0 || c->o.precision == 1, WENOTT_EINVAL, "precision must be 0 or 1");
+        WTT_REQUIRE(c->o.max_sweeps >= 1 && c->o.rank_cap >= 1 && c->o.kick_rank >= 0, WENOTT_EINVAL, "bad options");
+        WTT_REQUIRE(c->o.eps_mode == 0 || c->o.eps_mode == 1, WENOTT_EINVAL, "eps_mode must be 0 or 1");
+        for (int k = 0; k < d; ++k) {
+            WTT_REQUIRE(grid->n[k] >= 3 && grid->n[k] <= (1 << 20), WENOTT_EINVAL, "grid size out of range");
+            WTT_REQUIRE(grid->hi[k] > grid->lo[k], WENOTT_EINVAL, "empty box");
+            WTT_REQUIRE(bc[2 * k] == bc[2 * k + 1], WENOTT_EINVAL, "both sides of a dimension must agree");
+            WTT_REQUIRE(bc[2 * k] == WENOTT_BC_PERIODIC || bc[2 * k] == WENOTT_BC_TRANSMISSIVE, WENOTT_EINVAL,
+                        "unknown boundary type");
+            c->N[k] = (int)grid->n[k];
+            c->lo[k] = grid->lo[k];
+            c->hi[k] = grid->hi[k];
+            c->h[k] = (grid->hi[k] - grid->lo[k]) / grid->n[k];
+            c->bc[k] = bc[2 * k];
+        }
+        c->s = (hipStream_t)hip_stream;
+        c->sc.s = c->s;
+        c->ring.init(c->s, 8u << 20);
+        WTT_HIP(hipMalloc((void **)&c->d_flags, sizeof(int)));
+        WTT_HIP(hipMemsetAsync(c->d_flags, 0, sizeof(int), c->s));
+        WTT_HIP(hipHostMalloc((void **)&c->h_pinned_int, 4096 * sizeof(int), hipHostMallocDefault));
+        WTT_HIP(hipHostMalloc((void **)&c->h_pinned_dbl, 4096 * sizeof(double), hipHostMallocDefault));
+        // common padded ranks
+        const int nc = c->nc;
+        TT U;
+        U.d = d; U.nc = nc;
+        for (int k = 0; k < d; ++k) U.N[k] = c->N[k];
+        U.R[0] = U.R[d] = 1;
+        for (int k = 1; k < d; ++k) {
+            int r = 1;
+            for (int q = 0; q < nc; ++q) {
+                int64_t v = state->ranks[q * (d + 1) + k];
+                WTT_REQUIRE(v >= 1 && v <= 4096, WENOTT_EINVAL, "rank out of range");
+                r = std::max<int>(r, (int)v);
+            }
+            U.R[k] = r;
+        }
+        for (int q = 0; q < nc; ++q)
+            WTT_REQUIRE(state->ranks[q * (d + 1)] == 1 && state->ranks[q * (d + 1) + d] == 1, WENOTT_EINVAL,
+                        "boundary ranks must be 1");
+        U.alloc(c->s);
+        const hipMemcpyKind kind = state->on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+        for (int k = 0; k < d; ++k) {
+            fill(c->s, U.core[k], U.cstride(k) * nc, 0.0);
+            for (int q = 0; q < nc; ++q) {
+                const double *src = (const double *)state->cores[q * d + k];
+                WTT_REQUIRE(src != nullptr, WENOTT_EINVAL, "null core pointer");
+                const int ra = (int)state->ranks[q * (d + 1) + k], rb = (int)state->ranks[q * (d + 1) + k + 1];
+                // place the (ra, N, rb) core in the padded (R_k, N, R_{k+1}) slot
+                WTT_HIP(hipMemcpy2DAsync(U.core[k] + q * U.cstride(k), sizeof(double) * U.R[k + 1], src,
+                                         sizeof(double) * rb, sizeof(double) * rb, (size_t)ra * U.N[k], kind, c->s));
+            }
+        }
+        WTT_HIP(hipStreamSynchronize(c->s));
+        c->U = U;
+        // norms for the dynamic eps
+        TT tmp = copy_tt(c, c->U);
+        std::vector<double> norms;
+        round_tt(c, tmp, 0.0, false, norms);
+        tmp.release(c->s);
+        c->max_norm = *std::max_element(norms.begin(), norms.end());
+        if (c->o.eps_mode == 1) {
+            if (c->o.eps0 > 0.0) {
+                c->c_eps = 1.0;
+                c->c_eps = c->o.eps0 / dynamic_eps(c, c->max_norm);
+            } else {
+                c->c_eps = c->o.c_eps;
+            }
+            WTT_REQUIRE(c->c_eps > 0.0, WENOTT_EINVAL, "dynamic eps needs eps0 > 0 or c_eps > 0");
+        }
+        c->info.ndim = d;
+        c->info.ncomp = nc;
+    });
+    if (st != WENOTT_OK) {
+        wenott_destroy(c);
+        return st;
+    }
+    *out = c;
+    return WENOTT_OK;
+}
+
+void wenott_destroy(wenott_ctx *c) {
+    if (!c) return;
+    {
+        hipStreamSynchronize(c->s);
+        c->U.release(c->s);
+        if (c->have_rhs) c->rhs.release(c->s);
+        c->sc.release();
+        hipStreamSynchronize(c->s);
+        c->ring.destroy();
+        if (c->d_flags) hipFree(c->d_flags);
+        if (c->h_pinned_int) hipHostFree(c->h_pinned_int);
+        if (c->h_pinned_dbl) hipHostFree(c->h_pinned_dbl);
+        for (auto e : c->ev) hipEventDestroy(e);
+    }
+    delete c;
+}
+
+static void fill_view(wenott_ctx *c, const TT &X, wenott_tt *view) {
+    c->view_ranks.assign((size_t)X.nc * (X.d + 1), 0);
+    c->view_ptrs.assign((size_t)X.nc * X.d, nullptr);
+    for (int q = 0; q < X.nc; ++q) {
+        for (int k = 0; k <= X.d; ++k) c->view_ranks[q * (X.d + 1) + k] = X.R[k];
+        for (int k = 0; k < X.d; ++k) c->view_ptrs[q * X.d + k] = X.core[k] + q * X.cstride(k);
+    }
+    view->ndim = X.d;
+    view->ncomp = X.nc;
+    view->ranks = c->view_ranks.data();
+    view->cores = c->view_ptrs.data();
+    view->dtype = 0;
+    view->on_device = 1;
+}
+
+wenott_status wenott_rhs(wenott_ctx *c, double alpha, wenott_tt *view) {
+    if (!c || !view) return WENOTT_EINVAL;
+    return run_guarded(c, [&] {
+        double t0 = seconds_now();
+        reset_call_info(c);
+        double a = alpha > 0.0 ? alpha : (c->o.alpha_mode == 2 ? c->o.alpha_given : exact_alpha(c, c->U));
+        WTT_REQUIRE(a > 0.0, WENOTT_EINVAL, "alpha must be positive");
+        c->info.alpha[0] = a;
+        double eps = current_eps(c);
+        std::vector<TT> terms = rhs_terms(c, c->U, a, eps, 0);
+        std::vector<std::pair<double, const TT *>> w;
+        for (auto &t : terms) w.push_back({1.0, &t});
+        TT S = tt_sum(c, w);
+        for (auto &t : terms) t.release(c->s);
+        std::vector<double> norms;
+        round_tt(c, S, eps, true, norms);
+        if (c->have_rhs) c->rhs.release(c->s);
+        c->rhs = S;
+        c->have_rhs = true;
+        fill_view(c, c->rhs, view);
+        c->info.eps = eps;
+        finish_call_info(c, t0);
+    });
+}
+
+wenott_status wenott_rk3_step(wenott_ctx *c, double dt, double eps_in, const double *alphas) {
+    if (!c || !(dt > 0.0)) return WENOTT_EINVAL;
+    return run_guarded(c, [&] {
+        double t0 = seconds_now();
+        reset_call_info(c);
+        const double eps = eps_in > 0.0 ? eps_in : current_eps(c);
+        // Shu-Osher SSP-RK3 (eq. tt-ssprk3): stage s input X_s, output
+        // a_s U^n + b_s (X_s + dt L(X_s)), rounded once.
+        const double aw[3] = {0.0, 0.75, 1.0 / 3.0}, bw[3] = {1.0, 0.25, 2.0 / 3.0};
+        TT X = c->U;  // stage input (aliases U for stage 0)
+        bool x_owned = false;
+        std::vector<double> norms;
+        try {
+            for (int st = 0; st < 3; ++st) {
+                double a;
+                if (alphas) a = alphas[st];
+                else if (c->o.alpha_mode == 2) a = c->o.alpha_given;
+                else a = exact_alpha(c, X);
+                WTT_REQUIRE(a > 0.0, WENOTT_EINVAL, "alpha must be positive");
+                c->info.alpha[st] = a;
+                std::vector<TT> terms = rhs_terms(c, X, a, eps, st);
+                std::vector<std::pair<double, const TT *>> w;
+                if (aw[st] != 0.0) w.push_back({aw[st], &c->U});
+                w.push_back({bw[st], &X});
+                for (auto &t : terms) w.push_back({bw[st] * dt, &t});
+                TT S = tt_sum(c, w);
+                for (auto &t : terms) t.release(c->s);
+                c->info.sum_rank[st] = S.maxrank();
+                round_tt(c, S, eps, true, norms);
+                if (x_owned) X.release(c->s);
+                X = S;
+                x_owned = true;
+            }
+        } catch (...) {
+            if (x_owned) X.release(c->s);
+            throw;
+        }
+        c->U.release(c->s);
+        c->U = X;
+        c->max_norm = *std::max_element(norms.begin(), norms.end());
+        c->info.max_norm = c->max_norm;
+        c->info.eps = eps;
+        c->info.c_eps = c->c_eps;
+        finish_call_info(c, t0);
+    });
+}
+
+wenott_status wenott_round(wenott_ctx *c, double eps) {
+    if (!c || !(eps > 0.0)) return WENOTT_EINVAL;
+    return run_guarded(c, [&] {
+        std::vector<double> norms;
+        round_tt(c, c->U, eps, true, norms);
+        c->max_norm = *std::max_element(norms.begin(), norms.end());
+    });
+}
+
+wenott_status wenott_to_dense(wenott_ctx *c, double *out, int32_t on_device) {
+    if (!c || !out) return WENOTT_EINVAL;
+    return run_guarded(c, [&] {
+        if (on_device) {
+            to_dense_dev(c, c->U, out);
+        } else {
+            long long n = (long long)c->nc;
+            for (int k = 0; k < c->d; ++k) n *= c->N[k];
+            double *tmp = c->sc.get<double>(S_DENSE, (size_t)n);
+            to_dense_dev(c, c->U, tmp);
+            WTT_HIP(hipMemcpyAsync(out, tmp, sizeof(double) * n, hipMemcpyDeviceToHost, c->s));
+            WTT_HIP(hipStreamSynchronize(c->s));
+        }
+    });
+}
+
+wenott_status wenott_get_state(wenott_ctx *c, wenott_tt *view) {
+    if (!c || !view) return WENOTT_EINVAL;
+    return run_guarded(c, [&] { fill_view(c, c->U, view); });
+}
+
+wenott_status wenott_get_info(wenott_ctx *c, wenott_info *info) {
+    if (!c || !info) return WENOTT_EINVAL;
+    return run_guarded(c, [&] {
+        WTT_HIP(hipStreamSynchronize(c->s));
+        for (int k = 0; k < 4; ++k) c->info.ranks[k] = k <= c->d ? c->U.R[k] : 0;
+        *info = c->info;
+    });
+}
+
+wenott_status wenott_max_wavespeed(wenott_ctx *c, double *alpha) {
+    if (!c || !alpha) return WENOTT_EINVAL;
+    return run_guarded(c, [&] { *alpha = exact_alpha(c, c->U); });
+}
+
+wenott_status wenott_current_eps(wenott_ctx *c, double *eps) {
+    if (!c || !eps) return WENOTT_EINVAL;
+    return run_guarded(c, [&] { *eps = current_eps(c); });
+}
+
+wenott_status wenott_set_profiling(wenott_ctx *c, int32_t on) {
+    if (!c) return WENOTT_EINVAL;
+    c->profiling = on != 0;
+    return WENOTT_OK;
+}
+
+const char *wenott_last_error(wenott_ctx *c) { return c ? c->last_error.c_str() : g_last_error.c_str(); }
+
+}  // extern "C"

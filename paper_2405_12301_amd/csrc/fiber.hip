@@ -1,0 +1,431 @@
+// Fiber evaluation of the fused LF + WENO5-JS flux on TT cores (gfx950).
+//
+// A cross over the flux tensor Fhat_dir(i_1..i_d, c) needs the flux on blocks
+// (I_<k, i_k, J_>k). The state value at one point is the chain product of its cores
+// (Sec. 3.1, eq. TT_def_2), so a block of state values is P . G_k . Q with P, Q the left
+// and right interface matrices at the pivots. The flux needs the state at the six cells
+// m-3 .. m+2 around face m along dir (Sec. 2.2 stencils S_0..S_2 for f^+ and their mirror
+// for f^-), realised as six shifted interface matrices or, when the free mode is dir
+// itself, as six neighbouring cells of the same block.
+#include <cmath>
+
+#include "common.h"
+
+namespace wtt {
+
+namespace {
+
+constexpr int kWave = 64;
+
+struct CoreSet {
+    const double *c[kMaxDim];
+    long long cstride[kMaxDim];
+    int R[kMaxDim + 1];
+    int N[kMaxDim];
+};
+
+inline CoreSet make_coreset(const FiberGeom &g, const double *const *cores, const int *ranks, const int *modes) {
+    CoreSet cs{};
+    for (int k = 0; k <= g.d; ++k) cs.R[k] = ranks[k];
+    for (int k = 0; k < g.d; ++k) {
+        cs.c[k] = cores[k];
+        cs.N[k] = modes[k];
+        cs.cstride[k] = (long long)ranks[k] * modes[k] * ranks[k + 1];
+    }
+    return cs;
+}
+
+__device__ inline int mode_index(const FiberGeom &g, int mode, int v, int s, int S) {
+    // entry v of mode `mode`: a face index on the flux direction (shifted to cell m - 3 + s)
+    if (S == 6 && mode == g.dir) return ghost_map(v - 3 + s, g.n[mode], g.bc[mode]);
+    return v;
+}
+
+__global__ void k_iface(FiberGeom g, CoreSet cs, int side, int count, const int *__restrict__ idx, int S,
+                        double *__restrict__ out) {
+    const int k = g.k;
+    const int Rout = side == 0 ? cs.R[k] : cs.R[k + 1];
+    const long long tot = (long long)g.ncomp * S * count * Rout;
+    long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (e >= tot) return;
+    const int beta = (int)(e % Rout);
+    long long r = e / Rout;
+    const int a = (int)(r % count);
+    r /= count;
+    const int s = (int)(r % S);
+    const int c = (int)(r / S);
+    double val;
+    if (side == 0) {
+        const int *mi = idx + (long long)a * k;
+        const int i0 = mode_index(g, 0, mi[0], s, S);
+        const double *G0 = cs.c[0] + c * cs.cstride[0];
+        if (k == 1) {
+            val = G0[(long long)i0 * cs.R[1] + beta];
+        } else {  // k == 2
+            const int i1 = mode_index(g, 1, mi[1], s, S);
+            const double *G1 = cs.c[1] + c * cs.cstride[1];
+            double acc = 0.0;
+            for (int al = 0; al < cs.R[1]; ++al)
+                acc += G0[(long long)i0 * cs.R[1] + al] * G1[((long long)al * cs.N[1] + i1) * cs.R[2] + beta];
+            val = acc;
+        }
+        out[(((long long)c * S + s) * count + a) * Rout + beta] = val;
+    } else {
+        const int len = g.d - 1 - k;
+        const int *mi = idx + (long long)a * len;
+        const int last = g.d - 1;
+        if (len == 1) {
+            const int j = mode_index(g, last, mi[0], s, S);
+            const double *G = cs.c[last] + c * cs.cstride[last];
+            val = G[(long long)beta * cs.N[last] + j];
+        } else {  // k == 0, d == 3
+            const int j1 = mode_index(g, 1, mi[0], s, S), j2 = mode_index(g, 2, mi[1], s, S);
+            const double *G1 = cs.c[1] + c * cs.cstride[1];
+            const double *G2 = cs.c[2] + c * cs.cstride[2];
+            double acc = 0.0;
+            for (int b2 = 0; b2 < cs.R[2]; ++b2)
+                acc += G1[((long long)beta * cs.N[1] + j1) * cs.R[2] + b2] * G2[(long long)b2 * cs.N[2] + j2];
+            val = acc;
+        }
+        out[(((long long)c * S + s) * Rout + beta) * count + a] = val;
+    }
+}
+
+// Left-biased WENO5-JS value at x_{i+1/2} from v_{i-2..i+2} (Sec. 2.2): candidate values,
+// smoothness indicators beta_r, weights d_r / (beta_r + eps)^2 normalised, written with one
+// reciprocal: w_r = d_r prod_{s != r} t_s / sum_s d_s prod_{u != s} t_u, t_r = (beta_r + eps)^2.
+template <typename T>
+__device__ inline T weno5(T vm2, T vm1, T v0, T vp1, T vp2, T eps) {
+    const T c13 = T(13.0 / 12.0), c14 = T(0.25), c16 = T(1.0 / 6.0);
+    T q0 = (T(2) * v0 + T(5) * vp1 - vp2) * c16;
+    T q1 = (-vm1 + T(5) * v0 + T(2) * vp1) * c16;
+    T q2 = (T(2) * vm2 - T(7) * vm1 + T(11) * v0) * c16;
+    T a = v0 - T(2) * vp1 + vp2, b = T(3) * v0 - T(4) * vp1 + vp2;
+    T b0 = c13 * a * a + c14 * b * b;
+    a = vm1 - T(2) * v0 + vp1;
+    b = vm1 - vp1;
+    T b1 = c13 * a * a + c14 * b * b;
+    a = vm2 - T(2) * vm1 + v0;
+    b = vm2 - T(4) * vm1 + T(3) * v0;
+    T b2 = c13 * a * a + c14 * b * b;
+    T t0 = (b0 + eps) * (b0 + eps), t1 = (b1 + eps) * (b1 + eps), t2 = (b2 + eps) * (b2 + eps);
+    T a0 = T(0.3) * t1 * t2, a1 = T(0.6) * t0 * t2, a2 = T(0.1) * t0 * t1;
+    return (a0 * q0 + a1 * q1 + a2 * q2) / (a0 + a1 + a2);
+}
+
+// f^{+-} = (f_dir(q) +- alpha q) / 2 for one stencil cell (Sec. 2.1 fluxes, eq. lax-friedrichs).
+template <int ND, typename T>
+__device__ inline bool split_flux(const T *q, int dir, T gm1, T alpha, T *fp, T *fm) {
+    constexpr int NC = ND + 2;
+    T rho = q[0];
+    T inv = T(1) / rho;
+    T ke = T(0);
+#pragma unroll
+    for (int j = 0; j < ND; ++j) ke += q[1 + j] * q[1 + j];
+    ke *= T(0.5) * inv;
+    T p = gm1 * (q[NC - 1] - ke);
+    T un = q[1 + dir] * inv;
+    T f[NC];
+    f[0] = q[1 + dir];
+#pragma unroll
+    for (int j = 0; j < ND; ++j) f[1 + j] = q[1 + j] * un + (j == dir ? p : T(0));
+    f[NC - 1] = un * (q[NC - 1] + p);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        fp[c] = T(0.5) * (f[c] + alpha * q[c]);
+        fm[c] = T(0.5) * (f[c] - alpha * q[c]);
+    }
+    return rho > T(0) && p > T(0);
+}
+
+template <int ND, typename T>
+__global__ __launch_bounds__(256) void k_weno(FiberGeom g, int p, int M, int q, const T *__restrict__ W,
+                                              double *__restrict__ out, long long sa, long long si, long long sb,
+                                              long long sc, int *__restrict__ flags) {
+    constexpr int NC = ND + 2;
+    const long long tot = (long long)p * M * q;
+    long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (e >= tot) return;
+    const int b = (int)(e % q);
+    const long long r = e / q;
+    const int i = (int)(r % M);
+    const int a = (int)(r / M);
+    const int Nk = g.n[g.k];
+    const bool same = g.k == g.dir;
+    T fp[NC][6], fm[NC][6];
+    bool ok = true;
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+        T qv[NC];
+        if (same) {
+            const int cell = ghost_map(i - 3 + s, Nk, g.bc[g.k]);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) qv[c] = W[(((long long)c * p + a) * Nk + cell) * q + b];
+        } else {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) qv[c] = W[((((long long)c * 6 + s) * p + a) * Nk + i) * q + b];
+        }
+        T fpt[NC], fmt[NC];
+        ok &= split_flux<ND, T>(qv, g.dir, T(g.gamma - 1.0), T(g.alpha), fpt, fmt);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) { fp[c][s] = fpt[c]; fm[c][s] = fmt[c]; }
+    }
+    const T eps = T(g.eps_w);
+    bool finite = true;
+    double *o = out + a * sa + i * si + b * sb;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        // face m sits between cells m-1 and m: f^+ from cells m-3..m+1 (slots 0..4),
+        // f^- mirrored from cells m+2..m-2 (slots 5..1)
+        T hp = weno5<T>(fp[c][0], fp[c][1], fp[c][2], fp[c][3], fp[c][4], eps);
+        T hm = weno5<T>(fm[c][5], fm[c][4], fm[c][3], fm[c][2], fm[c][1], eps);
+        double v = (double)hp + (double)hm;
+        finite &= (v == v) && fabs(v) < 1e300;
+        o[c * sc] = v;
+    }
+    if (!ok) atomicOr(flags, kFlagNonPhys);
+    if (!finite) atomicOr(flags, kFlagNaN);
+}
+
+template <int ND>
+__global__ __launch_bounds__(256) void k_dense_eval(int mode, int ncomp, long long nrows, int R, int nlast,
+                                                    const double *__restrict__ Lm, long long lm_stride,
+                                                    const double *__restrict__ G, long long g_stride, double gamma,
+                                                    double *__restrict__ out, double *__restrict__ partial,
+                                                    int *__restrict__ flags) {
+    constexpr int NC = ND + 2;
+    __shared__ double red[4];
+    const long long ncell = nrows * nlast;
+    long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    double speed = 0.0;
+    bool ok = true;
+    if (e < ncell) {
+        const long long row = e / nlast;
+        const int j = (int)(e % nlast);
+        double qv[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const double *l = Lm + c * lm_stride + row * R;
+            const double *gg = G + c * g_stride + j;
+            double acc = 0.0;
+            for (int al = 0; al < R; ++al) acc += l[al] * gg[(long long)al * nlast];
+            qv[c] = acc;
+        }
+        if (mode == 0) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) out[c * ncell + e] = qv[c];
+        } else {
+            double inv = 1.0 / qv[0], u2 = 0.0;
+#pragma unroll
+            for (int d = 0; d < ND; ++d) u2 += qv[1 + d] * qv[1 + d];
+            u2 *= inv * inv;
+            double pr = (gamma - 1.0) * (qv[NC - 1] - 0.5 * qv[0] * u2);
+            ok = qv[0] > 0.0 && pr > 0.0;
+            speed = ok ? sqrt(u2) + sqrt(gamma * pr * inv) : 0.0;
+        }
+    }
+    if (mode == 1) {
+        for (int off = kWave / 2; off > 0; off >>= 1) speed = fmax(speed, __shfl_xor(speed, off, kWave));
+        if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = speed;
+        __syncthreads();
+        if (threadIdx.x == 0) partial[blockIdx.x] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+        if (!ok) atomicOr(flags, kFlagNonPhys);
+    }
+}
+
+__global__ void k_reduce_max(const double *__restrict__ partial, int n, double *__restrict__ out) {
+    __shared__ double red[16];
+    double v = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) v = fmax(v, partial[i]);
+    for (int off = kWave / 2; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, kWave));
+    if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = 0.0;
+        for (int i = 0; i < (int)(blockDim.x / kWave); ++i) m = fmax(m, red[i]);
+        out[0] = m;
+    }
+}
+
+// State value of component c at a cell multi-index (chain product over the cores).
+template <int ND>
+__device__ inline double tt_point(const CoreSet &cs, int c, const int *cell) {
+    const double *G0 = cs.c[0] + c * cs.cstride[0];
+    const double *G1 = cs.c[1] + c * cs.cstride[1];
+    if (ND == 2) {
+        double acc = 0.0;
+        for (int al = 0; al < cs.R[1]; ++al) acc += G0[(long long)cell[0] * cs.R[1] + al] * G1[(long long)al * cs.N[1] + cell[1]];
+        return acc;
+    } else {
+        const double *G2 = cs.c[2] + c * cs.cstride[2];
+        double acc = 0.0;
+        for (int be = 0; be < cs.R[2]; ++be) {
+            double v = 0.0;
+            for (int al = 0; al < cs.R[1]; ++al)
+                v += G0[(long long)cell[0] * cs.R[1] + al] * G1[((long long)al * cs.N[1] + cell[1]) * cs.R[2] + be];
+            acc += v * G2[(long long)be * cs.N[2] + cell[2]];
+        }
+        return acc;
+    }
+}
+
+template <int ND>
+__global__ void k_sample_state(FiberGeom g, CoreSet cs, int npts, const int *__restrict__ pts,
+                               double *__restrict__ ust) {
+    constexpr int NC = ND + 2;
+    long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (e >= (long long)npts * 6 * NC) return;
+    const int c = (int)(e % NC);
+    const int s = (int)((e / NC) % 6);
+    const int pt = (int)(e / (NC * 6));
+    int cell[ND];
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+        int v = pts[pt * ND + d];
+        cell[d] = d == g.dir ? ghost_map(v - 3 + s, g.n[d], g.bc[d]) : v;
+    }
+    ust[e] = tt_point<ND>(cs, c, cell);
+}
+
+template <int ND>
+__global__ __launch_bounds__(256) void k_sample_flux(FiberGeom g, CoreSet fs, int npts, const int *__restrict__ pts,
+                                                     const double *__restrict__ ust, double *__restrict__ acc,
+                                                     int *__restrict__ flags) {
+    constexpr int NC = ND + 2;
+    __shared__ double red[2][4];
+    const int pt = blockIdx.x * blockDim.x + threadIdx.x;
+    double d2 = 0.0, n2 = 0.0;
+    bool ok = true;
+    if (pt < npts) {
+        double fp[NC][6], fm[NC][6];
+        for (int s = 0; s < 6; ++s) {
+            double qv[NC], a[NC], b[NC];
+            for (int c = 0; c < NC; ++c) qv[c] = ust[((long long)pt * 6 + s) * NC + c];
+            ok &= split_flux<ND, double>(qv, g.dir, g.gamma - 1.0, g.alpha, a, b);
+            for (int c = 0; c < NC; ++c) { fp[c][s] = a[c]; fm[c][s] = b[c]; }
+        }
+        // approximation: shared cores 0..d-2, last core (R, M, NC)
+        const int *m = pts + pt * ND;
+        double approx[NC];
+        for (int c = 0; c < NC; ++c) approx[c] = 0.0;
+        if (ND == 2) {
+            for (int al = 0; al < fs.R[1]; ++al) {
+                double l = fs.c[0][(long long)m[0] * fs.R[1] + al];
+                const double *last = fs.c[1] + ((long long)al * fs.N[1] + m[1]) * NC;
+                for (int c = 0; c < NC; ++c) approx[c] += l * last[c];
+            }
+        } else {
+            for (int be = 0; be < fs.R[2]; ++be) {
+                double v = 0.0;
+                for (int al = 0; al < fs.R[1]; ++al)
+                    v += fs.c[0][(long long)m[0] * fs.R[1] + al] * fs.c[1][((long long)al * fs.N[1] + m[1]) * fs.R[2] + be];
+                const double *last = fs.c[2] + ((long long)be * fs.N[2] + m[2]) * NC;
+                for (int c = 0; c < NC; ++c) approx[c] += v * last[c];
+            }
+        }
+        const double eps = g.eps_w;
+        for (int c = 0; c < NC; ++c) {
+            double ex = weno5<double>(fp[c][0], fp[c][1], fp[c][2], fp[c][3], fp[c][4], eps) +
+                        weno5<double>(fm[c][5], fm[c][4], fm[c][3], fm[c][2], fm[c][1], eps);
+            d2 += (ex - approx[c]) * (ex - approx[c]);
+            n2 += ex * ex;
+        }
+    }
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        d2 += __shfl_xor(d2, off, kWave);
+        n2 += __shfl_xor(n2, off, kWave);
+    }
+    if (threadIdx.x % kWave == 0) { red[0][threadIdx.x / kWave] = d2; red[1][threadIdx.x / kWave] = n2; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        acc[2 * blockIdx.x] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+        acc[2 * blockIdx.x + 1] = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+    }
+    if (!ok) atomicOr(flags, kFlagNonPhys);
+}
+
+inline unsigned cdiv(long long a, long long b) { return (unsigned)((a + b - 1) / b); }
+
+}  // namespace
+
+void iface(hipStream_t s, const FiberGeom &g, int side, const double *const *cores, const int *ranks, int count,
+           const int *idx, int S, double *out) {
+    int modes[kMaxDim];
+    for (int k = 0; k < g.d; ++k) modes[k] = g.n[k];
+    CoreSet cs = make_coreset(g, cores, ranks, modes);
+    int Rout = side == 0 ? ranks[g.k] : ranks[g.k + 1];
+    long long tot = (long long)g.ncomp * S * count * Rout;
+    if (tot == 0) return;
+    k_iface<<<cdiv(tot, 256), 256, 0, s>>>(g, cs, side, count, idx, S, out);
+    WTT_HIP(hipGetLastError());
+}
+
+template <typename T>
+void weno_block(hipStream_t s, const FiberGeom &g, int p, int q, const T *W, double *out, long long sa, long long si,
+                long long sb, long long sc, int *flags) {
+    const int M = g.k == g.dir ? g.n[g.k] + 1 : g.n[g.k];
+    long long tot = (long long)p * M * q;
+    if (tot == 0) return;
+    if (g.d == 2)
+        k_weno<2, T><<<cdiv(tot, 256), 256, 0, s>>>(g, p, M, q, W, out, sa, si, sb, sc, flags);
+    else
+        k_weno<3, T><<<cdiv(tot, 256), 256, 0, s>>>(g, p, M, q, W, out, sa, si, sb, sc, flags);
+    WTT_HIP(hipGetLastError());
+}
+template void weno_block<double>(hipStream_t, const FiberGeom &, int, int, const double *, double *, long long,
+                                 long long, long long, long long, int *);
+template void weno_block<float>(hipStream_t, const FiberGeom &, int, int, const float *, double *, long long,
+                                long long, long long, long long, int *);
+
+void dense_eval(hipStream_t s, int mode, int d, int ncomp, long long nrows, int R, int nlast, const double *Lm,
+                long long lm_stride, const double *G, long long g_stride, double gamma, double *out, double *partial,
+                int nblocks, int *flags) {
+    (void)ncomp;
+    long long ncell = nrows * nlast;
+    WTT_REQUIRE(cdiv(ncell, 256) == (unsigned)nblocks, WENOTT_EINVAL, "dense_eval block count");
+    if (d == 2)
+        k_dense_eval<2><<<nblocks, 256, 0, s>>>(mode, 4, nrows, R, nlast, Lm, lm_stride, G, g_stride, gamma, out,
+                                                partial, flags);
+    else
+        k_dense_eval<3><<<nblocks, 256, 0, s>>>(mode, 5, nrows, R, nlast, Lm, lm_stride, G, g_stride, gamma, out,
+                                                partial, flags);
+    WTT_HIP(hipGetLastError());
+}
+
+double reduce_max_host(hipStream_t s, const double *partial, int n, double *dscratch) {
+    k_reduce_max<<<1, 1024, 0, s>>>(partial, n, dscratch);
+    WTT_HIP(hipGetLastError());
+    double v = 0.0;
+    WTT_HIP(hipMemcpyAsync(&v, dscratch, sizeof(double), hipMemcpyDeviceToHost, s));
+    WTT_HIP(hipStreamSynchronize(s));
+    return v;
+}
+
+void sample_residual(hipStream_t s, const FiberGeom &g, const double *const *ucores, const int *ranks, int npts,
+                     const int *pts, const double *const *fcores, const int *franks, double *ustencil, double *acc,
+                     int *flags) {
+    int modes[kMaxDim], fmodes[kMaxDim];
+    for (int k = 0; k < g.d; ++k) {
+        modes[k] = g.n[k];
+        fmodes[k] = g.n[k] + (k == g.dir ? 1 : 0);
+    }
+    CoreSet us = make_coreset(g, ucores, ranks, modes);
+    CoreSet fs{};
+    for (int k = 0; k <= g.d; ++k) fs.R[k] = franks[k];
+    for (int k = 0; k < g.d; ++k) {
+        fs.c[k] = fcores[k];
+        fs.N[k] = fmodes[k];
+        fs.cstride[k] = 0;
+    }
+    long long n1 = (long long)npts * 6 * g.ncomp;
+    if (g.d == 2) {
+        k_sample_state<2><<<cdiv(n1, 256), 256, 0, s>>>(g, us, npts, pts, ustencil);
+        k_sample_flux<2><<<cdiv(npts, 256), 256, 0, s>>>(g, fs, npts, pts, ustencil, acc, flags);
+    } else {
+        k_sample_state<3><<<cdiv(n1, 256), 256, 0, s>>>(g, us, npts, pts, ustencil);
+        k_sample_flux<3><<<cdiv(npts, 256), 256, 0, s>>>(g, fs, npts, pts, ustencil, acc, flags);
+    }
+    WTT_HIP(hipGetLastError());
+}
+
+}  // namespace wtt

@@ -1,0 +1,352 @@
+"""ctypes binding of libwenott (the C ABI in include/wenott.h).
+
+Argument marshalling only: every step of the WENO-TT path runs in the HIP library.
+Importing this module does not touch the GPU; the first call that needs the library
+loads it and raises if it has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libwenott.so")
+
+OK, EINVAL, ENOMEM, EHIP, ENOCONV, ENONPHYS, ENAN, ENOTBUILT = 0, -1, -2, -3, -4, -5, -6, -7
+BC_PERIODIC, BC_TRANSMISSIVE = 0, 1
+
+EXPORTED = ["wenott_default_opts", "wenott_init", "wenott_rhs", "wenott_rk3_step", "wenott_round",
+            "wenott_to_dense", "wenott_get_state", "wenott_get_info", "wenott_max_wavespeed",
+            "wenott_current_eps", "wenott_set_profiling", "wenott_last_error", "wenott_destroy",
+            "wenott_strerror", "wenott_dense_init", "wenott_dense_max_wavespeed", "wenott_dense_rhs",
+            "wenott_dense_rk3_step", "wenott_dense_destroy"]
+
+
+class wenott_grid(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int32), ("pad_", ctypes.c_int32), ("n", ctypes.c_int64 * 3),
+                ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3)]
+
+
+class wenott_tt(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int32), ("ncomp", ctypes.c_int32), ("ranks", ctypes.POINTER(ctypes.c_int64)),
+                ("cores", ctypes.POINTER(ctypes.c_void_p)), ("dtype", ctypes.c_int32), ("on_device", ctypes.c_int32)]
+
+
+class wenott_opts(ctypes.Structure):
+    _fields_ = [("c_eps", ctypes.c_double), ("eps0", ctypes.c_double), ("eps_mode", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("max_sweeps", ctypes.c_int32), ("kick_rank", ctypes.c_int32),
+                ("rank_cap", ctypes.c_int32), ("probe_points", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("alpha_mode", ctypes.c_int32), ("use_proposal", ctypes.c_int32), ("alpha_given", ctypes.c_double),
+                ("rounds_per_stage", ctypes.c_int32), ("graph_mode", ctypes.c_int32)]
+
+
+class wenott_info(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int32), ("ncomp", ctypes.c_int32), ("ranks", ctypes.c_int64 * 4),
+                ("alpha", ctypes.c_double * 3), ("eps", ctypes.c_double), ("c_eps", ctypes.c_double),
+                ("max_norm", ctypes.c_double), ("sweeps", (ctypes.c_int32 * 3) * 3),
+                ("residual", (ctypes.c_double * 3) * 3), ("flux_rank", (ctypes.c_int64 * 3) * 3),
+                ("sum_rank", ctypes.c_int64 * 3), ("fiber_points", ctypes.c_int64), ("fiber_ms", ctypes.c_double),
+                ("fiber_launches", ctypes.c_int64), ("step_ms", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libwenott.so; raises RuntimeError when it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libwenott.so is not built ({path}); run paper_2405_12301_amd/build.py")
+    # torch ships its own HIP runtime with the same SONAME as the system one; importing it
+    # first makes the library bind to that already-loaded runtime (one runtime per process).
+    import torch  # noqa: F401
+    lib = ctypes.CDLL(path)
+    P = ctypes.POINTER
+    vp = ctypes.c_void_p
+    lib.wenott_default_opts.argtypes = [P(wenott_opts)]
+    lib.wenott_default_opts.restype = None
+    lib.wenott_init.argtypes = [P(vp), P(wenott_tt), P(wenott_grid), ctypes.c_double, P(ctypes.c_int32),
+                                P(wenott_opts), vp]
+    lib.wenott_rhs.argtypes = [vp, ctypes.c_double, P(wenott_tt)]
+    lib.wenott_rk3_step.argtypes = [vp, ctypes.c_double, ctypes.c_double, P(ctypes.c_double)]
+    lib.wenott_round.argtypes = [vp, ctypes.c_double]
+    lib.wenott_to_dense.argtypes = [vp, vp, ctypes.c_int32]
+    lib.wenott_get_state.argtypes = [vp, P(wenott_tt)]
+    lib.wenott_get_info.argtypes = [vp, P(wenott_info)]
+    lib.wenott_max_wavespeed.argtypes = [vp, P(ctypes.c_double)]
+    lib.wenott_current_eps.argtypes = [vp, P(ctypes.c_double)]
+    lib.wenott_set_profiling.argtypes = [vp, ctypes.c_int32]
+    lib.wenott_last_error.argtypes = [vp]
+    lib.wenott_last_error.restype = ctypes.c_char_p
+    lib.wenott_destroy.argtypes = [vp]
+    lib.wenott_destroy.restype = None
+    lib.wenott_strerror.argtypes = [ctypes.c_int]
+    lib.wenott_strerror.restype = ctypes.c_char_p
+    lib.wenott_dense_init.argtypes = [P(vp), P(wenott_grid), ctypes.c_double, P(ctypes.c_int32), vp]
+    lib.wenott_dense_max_wavespeed.argtypes = [vp, vp, P(ctypes.c_double)]
+    lib.wenott_dense_rhs.argtypes = [vp, vp, ctypes.c_double, vp]
+    lib.wenott_dense_rk3_step.argtypes = [vp, vp, ctypes.c_double, P(ctypes.c_double), P(ctypes.c_double)]
+    lib.wenott_dense_destroy.argtypes = [vp]
+    lib.wenott_dense_destroy.restype = None
+    for name in ("wenott_init", "wenott_rhs", "wenott_rk3_step", "wenott_round", "wenott_to_dense",
+                 "wenott_get_state", "wenott_get_info", "wenott_max_wavespeed", "wenott_current_eps",
+                 "wenott_set_profiling", "wenott_dense_init", "wenott_dense_max_wavespeed", "wenott_dense_rhs",
+                 "wenott_dense_rk3_step"):
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+class WenottError(RuntimeError):
+    def __init__(self, status: int, msg: str = ""):
+        super().__init__(f"{load().wenott_strerror(status).decode()} ({status}) {msg}".strip())
+        self.status = status
+
+
+def _check(status: int, ctx=None):
+    if status != OK:
+        msg = load().wenott_last_error(ctx).decode()
+        raise WenottError(status, msg)
+
+
+def default_opts(**kw) -> wenott_opts:
+    o = wenott_opts()
+    load().wenott_default_opts(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def _stream_handle():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+# ---- thin wrappers with the C names ---------------------------------------------------
+def wenott_init(cores, n, lo, hi, gamma, bc, opts=None, stream=None):
+    """cores: [ncomp][ndim] arrays (numpy host arrays or torch CUDA tensors), FP64,
+    each of shape (R_{k-1}, N_k, R_k). bc: one code per dimension. Returns a ctypes handle."""
+    lib = load()
+    ndim = len(n)
+    ncomp = len(cores)
+    g = wenott_grid()
+    g.ndim = ndim
+    for d in range(ndim):
+        g.n[d], g.lo[d], g.hi[d] = int(n[d]), float(lo[d]), float(hi[d])
+    ranks = (ctypes.c_int64 * (ncomp * (ndim + 1)))()
+    ptrs = (ctypes.c_void_p * (ncomp * ndim))()
+    keep = []
+    on_device = 0
+    for c in range(ncomp):
+        for k in range(ndim):
+            a = cores[c][k]
+            if hasattr(a, "is_cuda") and a.is_cuda:
+                import torch
+                a = a.contiguous().to(torch.float64)
+                on_device = 1
+                ptrs[c * ndim + k] = a.data_ptr()
+            else:
+                a = np.ascontiguousarray(a, dtype=np.float64)
+                ptrs[c * ndim + k] = a.ctypes.data
+            keep.append(a)
+            ranks[c * (ndim + 1) + k] = a.shape[0]
+            if k == ndim - 1:
+                ranks[c * (ndim + 1) + ndim] = a.shape[2]
+    t = wenott_tt(ndim, ncomp, ranks, ptrs, 0, on_device)
+    bcs = (ctypes.c_int32 * 6)()
+    for d in range(ndim):
+        bcs[2 * d] = bcs[2 * d + 1] = int(bc[d])
+    o = opts if opts is not None else default_opts()
+    h = ctypes.c_void_p()
+    st = _stream_handle() if stream is None else stream
+    _check(lib.wenott_init(ctypes.byref(h), ctypes.byref(t), ctypes.byref(g), float(gamma), bcs, ctypes.byref(o), st))
+    return h
+
+
+def wenott_rhs(ctx, alpha=0.0):
+    v = wenott_tt()
+    _check(load().wenott_rhs(ctx, float(alpha), ctypes.byref(v)), ctx)
+    return v
+
+
+def wenott_rk3_step(ctx, dt, eps=0.0, alphas=None):
+    a = None if alphas is None else (ctypes.c_double * 3)(*[float(x) for x in alphas])
+    _check(load().wenott_rk3_step(ctx, float(dt), float(eps), a), ctx)
+
+
+def wenott_round(ctx, eps):
+    _check(load().wenott_round(ctx, float(eps)), ctx)
+
+
+def wenott_to_dense(ctx, out, on_device: bool):
+    ptr = out.data_ptr() if on_device else out.ctypes.data
+    _check(load().wenott_to_dense(ctx, ctypes.c_void_p(ptr), 1 if on_device else 0), ctx)
+
+
+def wenott_get_state(ctx):
+    v = wenott_tt()
+    _check(load().wenott_get_state(ctx, ctypes.byref(v)), ctx)
+    return v
+
+
+def wenott_get_info(ctx) -> wenott_info:
+    i = wenott_info()
+    _check(load().wenott_get_info(ctx, ctypes.byref(i)), ctx)
+    return i
+
+
+def wenott_max_wavespeed(ctx) -> float:
+    a = ctypes.c_double()
+    _check(load().wenott_max_wavespeed(ctx, ctypes.byref(a)), ctx)
+    return a.value
+
+
+def wenott_current_eps(ctx) -> float:
+    a = ctypes.c_double()
+    _check(load().wenott_current_eps(ctx, ctypes.byref(a)), ctx)
+    return a.value
+
+
+def wenott_set_profiling(ctx, on: bool):
+    _check(load().wenott_set_profiling(ctx, 1 if on else 0), ctx)
+
+
+def _grid(n, lo, hi):
+    g = wenott_grid()
+    g.ndim = len(n)
+    for d in range(len(n)):
+        g.n[d], g.lo[d], g.hi[d] = int(n[d]), float(lo[d]), float(hi[d])
+    return g
+
+
+def _bcs(bc):
+    b = (ctypes.c_int32 * 6)()
+    for d in range(len(bc)):
+        b[2 * d] = b[2 * d + 1] = int(bc[d])
+    return b
+
+
+def wenott_dense_init(n, lo, hi, gamma, bc, stream=None):
+    h = ctypes.c_void_p()
+    st = _stream_handle() if stream is None else stream
+    _check(load().wenott_dense_init(ctypes.byref(h), ctypes.byref(_grid(n, lo, hi)), float(gamma), _bcs(bc), st))
+    return h
+
+
+def wenott_dense_max_wavespeed(ctx, U) -> float:
+    a = ctypes.c_double()
+    _check(load().wenott_dense_max_wavespeed(ctx, ctypes.c_void_p(U.data_ptr()), ctypes.byref(a)))
+    return a.value
+
+
+def wenott_dense_rhs(ctx, U, alpha, L):
+    _check(load().wenott_dense_rhs(ctx, ctypes.c_void_p(U.data_ptr()), float(alpha), ctypes.c_void_p(L.data_ptr())))
+
+
+def wenott_dense_rk3_step(ctx, U, dt, alphas=None):
+    a = None if alphas is None else (ctypes.c_double * 3)(*[float(x) for x in alphas])
+    used = (ctypes.c_double * 3)()
+    _check(load().wenott_dense_rk3_step(ctx, ctypes.c_void_p(U.data_ptr()), float(dt), a, used))
+    return [used[0], used[1], used[2]]
+
+
+def wenott_dense_destroy(ctx):
+    if ctx:
+        load().wenott_dense_destroy(ctx)
+
+
+def wenott_destroy(ctx):
+    if ctx:
+        load().wenott_destroy(ctx)
+
+
+class Solver:
+    """Convenience owner of one context (state on the device)."""
+
+    def __init__(self, flow, opts=None, stream=None):
+        self.flow = flow
+        self.n = tuple(flow.n)
+        self.ncomp = flow.ncomp
+        self.ctx = wenott_init(flow.cores, flow.n, flow.lo, flow.hi, flow.gamma, flow.bc, opts, stream)
+
+    def close(self):
+        if self.ctx:
+            wenott_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def dense(self, device: bool = False):
+        if device:
+            import torch
+            out = torch.empty((self.ncomp,) + self.n, dtype=torch.float64, device="cuda")
+            wenott_to_dense(self.ctx, out, True)
+            return out
+        out = np.empty((self.ncomp,) + self.n)
+        wenott_to_dense(self.ctx, out, False)
+        return out
+
+    def step(self, dt, eps=0.0, alphas=None):
+        wenott_rk3_step(self.ctx, dt, eps, alphas)
+
+    def info(self):
+        return wenott_get_info(self.ctx)
+
+    def max_wavespeed(self):
+        return wenott_max_wavespeed(self.ctx)
+
+    def eps(self):
+        return wenott_current_eps(self.ctx)
+
+    def round(self, eps):
+        wenott_round(self.ctx, eps)
+
+    def rhs_cores(self, alpha=0.0):
+        """Host copies of the cores of the TT of L(U) computed by the library."""
+        return _view_cores(wenott_rhs(self.ctx, alpha), self.n)
+
+    def state_cores(self):
+        return _view_cores(wenott_get_state(self.ctx), self.n)
+
+
+def _view_cores(view: wenott_tt, n):
+    """Host copies of the cores of a library view: [ncomp][ndim] numpy arrays."""
+    import torch
+    ndim, ncomp = view.ndim, view.ncomp
+    torch.cuda.synchronize()
+    cores = []
+    for c in range(ncomp):
+        comp = []
+        for k in range(ndim):
+            r0 = int(view.ranks[c * (ndim + 1) + k])
+            r1 = int(view.ranks[c * (ndim + 1) + k + 1])
+            arr = np.empty((r0, int(n[k]), r1))
+            nbytes = arr.nbytes
+            _memcpy_d2h(arr.ctypes.data, view.cores[c * ndim + k], nbytes)
+            comp.append(arr)
+        cores.append(comp)
+    return cores
+
+
+_hip = None
+
+
+def _memcpy_d2h(dst, src, nbytes):
+    global _hip
+    if _hip is None:
+        _hip = ctypes.CDLL("libamdhip64.so")
+        _hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+        _hip.hipMemcpy.restype = ctypes.c_int
+    r = _hip.hipMemcpy(ctypes.c_void_p(dst), ctypes.c_void_p(src), ctypes.c_size_t(nbytes), 2)
+    if r != 0:
+        raise RuntimeError(f"hipMemcpy failed ({r})")

@@ -1,0 +1,210 @@
+"""Parity of the HIP WENO-TT path against the oracle, through the C ABI (needs a GPU)."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from oracle import tt_ref
+from tests.gpu_util import dense_of_cores, oracle_problem, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def W():
+    from paper_2405_12301_amd import wenott
+    wenott.load()
+    oracle.build(force=False)
+    return wenott
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def assert_rhs_parity(got, Lref, u, P, alpha, eps):
+    """Each flux cross is accurate to eps relative to the flux tensor (the cross bound of
+    Sec. 3.3), the shift difference (T - 1)/h has norm <= 2/h, and the sum is rounded at eps:
+    max_c ||L_TT - L||_F <= 10 eps (sum_d 2 max_c ||Fhat_d,c||_F / h_d + max_c ||L_c||_F)."""
+    scale = sum(2.0 * max(np.linalg.norm(F[c]) for c in range(F.shape[0])) / P.h[d]
+                for d, F in enumerate(P.interface_flux(u, alpha, d) for d in range(P.ndim)))
+    scale += max(np.linalg.norm(Lref[c]) for c in range(Lref.shape[0]))
+    err = max(np.linalg.norm(got[c] - Lref[c]) for c in range(got.shape[0]))
+    assert err <= 10 * eps * scale, (err, eps * scale)
+
+
+def test_to_dense_and_alpha_config1(W):
+    _say("case: to_dense / alpha, smooth wave 2D 64^2")
+    f = workloads.config1_smooth_wave_2d(64)
+    s = W.Solver(f)
+    try:
+        got = s.dense()
+        ref = dense_of_cores(f.cores)
+        assert np.max(np.abs(got - ref)) < 1e-13
+        a = s.max_wavespeed()
+        assert abs(a - oracle_problem(f).alpha(ref)) < 1e-12
+    finally:
+        s.close()
+
+
+@pytest.mark.parametrize("shape,rank", [((40, 33), 7), ((12, 10, 9), 5)])
+def test_round_error_bound_and_ranks(W, shape, rank):
+    _say("case: round", shape, rank)
+    f = workloads.random_positive_tt(shape, rank, seed=3)
+    ref = dense_of_cores(f.cores)
+    s = W.Solver(f)
+    try:
+        eps = 1e-3
+        s.round(eps)
+        cores = s.state_cores()
+        got = dense_of_cores(cores)
+        for c in range(ref.shape[0]):
+            err = np.linalg.norm(got[c] - ref[c])
+            assert err <= eps * np.linalg.norm(ref[c]) * (1 + 1e-9) + 1e-14, (c, err)
+            want = tt_ref.tt_ranks(tt_ref.tt_svd(ref[c], eps))
+            # common padded ranks: the largest component rank at each bond
+        want_max = np.max([tt_ref.tt_ranks(tt_ref.tt_svd(ref[c], eps)) for c in range(ref.shape[0])], axis=0)
+        got_r = tt_ref.tt_ranks(cores[0])
+        assert all(g <= w for g, w in zip(got_r, want_max)), (got_r, want_max)
+    finally:
+        s.close()
+
+
+def test_rhs_matches_oracle_config1(W):
+    _say("case: rhs, smooth wave 2D 64^2")
+    f = workloads.config1_smooth_wave_2d(64)
+    eps = 1e-10
+    s = W.Solver(f, W.default_opts(eps0=eps))
+    try:
+        ref_u = dense_of_cores(f.cores)
+        P = oracle_problem(f)
+        a = P.alpha(ref_u)
+        Lref = P.rhs(ref_u, a)
+        got = dense_of_cores(s.rhs_cores(a))
+        info = s.info()
+        _say("rhs rel err", rel_err(got, Lref), "flux residuals", info.residual[0][0], info.residual[0][1])
+        assert_rhs_parity(got, Lref, ref_u, P, a, eps)
+    finally:
+        s.close()
+
+
+def test_rk3_step_matches_oracle_config1(W):
+    _say("case: rk3 step, smooth wave 2D 64^2")
+    f = workloads.config1_smooth_wave_2d(64)
+    eps = 1e-10
+    s = W.Solver(f, W.default_opts(eps0=eps))
+    try:
+        u = dense_of_cores(f.cores)
+        P = oracle_problem(f)
+        dt = 0.5 * min(P.h) / P.alpha(u)
+        s.step(dt)
+        info = s.info()
+        al = [info.alpha[i] for i in range(3)]
+        P.ssprk3(u, dt, alphas=al)
+        got = s.dense()
+        e = rel_err(got, u)
+        _say("step rel err", e, "ranks", list(info.ranks), "alphas", al)
+        assert e <= 10 * eps
+    finally:
+        s.close()
+
+
+@pytest.mark.parametrize("which", ["wave", "quadrants"])
+def test_dense_comparator_matches_oracle(W, which):
+    import torch
+    _say("case: dense comparator", which)
+    f = workloads.config1_smooth_wave_2d(64) if which == "wave" else workloads.config2_quadrants_2d(64, seed=1)
+    u = dense_of_cores(f.cores)
+    P = oracle_problem(f)
+    ctx = W.wenott_dense_init(f.n, f.lo, f.hi, f.gamma, f.bc)
+    try:
+        U = torch.from_numpy(u.copy()).cuda()
+        a = W.wenott_dense_max_wavespeed(ctx, U)
+        assert abs(a - P.alpha(u)) <= 1e-14 * a
+        dt = 0.5 * min(P.h) / a
+        for _ in range(3):
+            al = W.wenott_dense_rk3_step(ctx, U, dt)
+            P.ssprk3(u, dt, alphas=al)
+        got = U.cpu().numpy()
+        assert rel_err(got, u) < 1e-13
+    finally:
+        W.wenott_dense_destroy(ctx)
+
+
+def _step_parity(W, f, eps, nsteps=1, opts=None, tol_factor=10.0):
+    """Advance the TT path and the oracle from the same densified state with the same dt and
+    the alphas the TT path used; per-step error in the max_c ||.||_F / max_c ||.||_F norm."""
+    o = opts if opts is not None else W.default_opts(eps0=eps)
+    s = W.Solver(f, o)
+    try:
+        P = oracle_problem(f)
+        errs = []
+        for _ in range(nsteps):
+            u = s.dense()
+            dt = 0.5 * min(P.h) / P.alpha(u)
+            s.step(dt)
+            info = s.info()
+            al = [info.alpha[i] for i in range(3)]
+            P.ssprk3(u, dt, alphas=al)
+            e = rel_err(s.dense(), u)
+            errs.append(e)
+            _say("  step err", e, "eps", info.eps, "ranks", list(info.ranks), "sweeps",
+                 [list(r) for r in info.sweeps], "sum ranks", list(info.sum_rank))
+            assert e <= tol_factor * info.eps, (e, info.eps)
+        return errs
+    finally:
+        s.close()
+
+
+def test_step_parity_3d_smooth(W):
+    _say("case: rk3 step, 3D smooth wave 24^3 with 2 Fourier modes")
+    f = workloads.config3_wave_3d(24, seed=0, modes=2)
+    _step_parity(W, f, 1e-9, nsteps=2)
+
+
+@pytest.mark.parametrize("n", [(64, 64), (37, 29)])
+def test_step_parity_quadrants_shocks(W, n):
+    _say("case: rk3 steps, four-quadrant Riemann problem", n)
+    f = workloads.config2_quadrants_2d(64, seed=2)
+    if n != (64, 64):
+        import dataclasses
+        g = workloads.config2_quadrants_2d(max(n), seed=2)
+        # ragged grid: resample the quadrant cores on an n0 x n1 grid
+        cores = []
+        for comp in g.cores:
+            c0 = np.zeros((1, n[0], 2)); c0[0, :, 0] = np.arange(n[0]) < n[0] // 2; c0[0, :, 1] = 1 - c0[0, :, 0]
+            vals = comp[1][:, [0, -1], 0]  # (2 quadrants in x) x (low/high y)
+            c1 = np.zeros((2, n[1], 1))
+            for a in range(2):
+                c1[a, :, 0] = np.where(np.arange(n[1]) < n[1] // 2, vals[a, 0], vals[a, 1])
+            cores.append([c0, c1])
+        f = dataclasses.replace(g, n=n, cores=cores)
+    _step_parity(W, f, 1e-8, nsteps=3)
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_full_rank_exactness_8d(W, ndim):
+    _say("case: full-rank exactness on 8^d, random smooth state, d =", ndim)
+    f = workloads.random_positive_tt((8,) * ndim, rank=8, seed=7, amp=0.3)
+    _step_parity(W, f, 1e-13, nsteps=1, tol_factor=1e2)
+
+
+def test_sod_stays_rank_one_and_matches(W):
+    _say("case: axis-aligned Sod in 3D stays rank 1")
+    f = workloads.sod_1d_like(3, 32)
+    s = W.Solver(f, W.default_opts(eps_mode=0, eps0=1e-8))
+    try:
+        P = oracle_problem(f)
+        u = s.dense()
+        for _ in range(3):
+            dt = 0.5 * min(P.h) / P.alpha(u)
+            s.step(dt)
+            info = s.info()
+            P.ssprk3(u, dt, alphas=[info.alpha[i] for i in range(3)])
+        assert list(info.ranks)[:4] == [1, 1, 1, 1]
+        assert rel_err(s.dense(), u) <= 1e-7
+    finally:
+        s.close()
