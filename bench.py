@@ -1,14 +1,16 @@
 """Benchmark of the WENO-TT hot path on one MI355X.
 
-A step is one SSP-RK3 step of WENO-TT (per stage: exact alpha, one fused LF + WENO5 cross
-per direction, flux difference, stage sum, one rounding; dynamic eps_TT) on the 2D
+A step is one SSP-RK3 step of WENO-TT (per stage: exact alpha, one rank-adaptive cross of the
+stage value whose fiber kernel gathers the star stencil from the TT cores and applies
+Lax-Friedrichs splitting and WENO5-JS, one TT-rounding; dynamic eps_TT) on the 2D
 four-quadrant Riemann problem, 512 x 512, transmissive, FP64, eps_TT(0) = 1e-8.
 dt = 0.5 h / alpha is taken from the state at the start of every step (inside the timed
 region). The state evolves through warmup and timed steps from t = 0.
 
 Printed: one JSON line with the dense-equivalent throughput (cells x steps / s), the
-roofline of the fiber kernel measured with HIP events on the library's stream, the dense
-GPU WENO5 comparator on the same workload, and the oracle timed on the host cores.
+roofline of the dominant kernel class measured with HIP events on the library's stream
+(with the other classes as a breakdown), the dense GPU WENO5 comparator on the same
+workload, and the oracle timed on the host cores.
 """
 from __future__ import annotations
 
@@ -23,11 +25,6 @@ sys.path.insert(0, ROOT)
 
 METRIC = "dense-equiv cell-updates/s, WENO-TT vs dense WENO5 on GPU, at fixed L1 error"
 
-# Algorithmic FP64 operations of one flux value (one face, all conserved variables) in the
-# fiber kernel, counted from the formulas (division and square root count as one):
-# 2D: 6 stencil cells x 39 (primitives, flux, LF split of 4 variables) + 8 WENO5 x 72 + 4 = 814
-# 3D: 6 x 48 + 10 x 72 + 5 = 1013
-FLOP_PER_POINT = {2: 814.0, 3: 1013.0}
 PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 
@@ -93,19 +90,17 @@ def main():
     solver = W.Solver(flow, opts)
     W.wenott_set_profiling(solver.ctx, True)
 
-    def tt_step():
-        a = solver.max_wavespeed()
-        solver.step(flow.cfl * h / a)
-
     t_sim = 0.0
     for _ in range(args.warmup):
         a = solver.max_wavespeed()
         solver.step(flow.cfl * h / a)
         t_sim += flow.cfl * h / a
     torch.cuda.synchronize()
-    fiber_ms = 0.0
-    fiber_pts = 0
-    fiber_launch = 0
+    ncls = 4
+    cls_ms = [0.0] * ncls
+    cls_fl = [0.0] * ncls
+    cls_by = [0.0] * ncls
+    cls_n = [0] * ncls
     t0 = time.perf_counter()
     for _ in range(args.steps):
         a = solver.max_wavespeed()
@@ -113,9 +108,11 @@ def main():
         solver.step(dt)
         t_sim += dt
         inf = solver.info()
-        fiber_ms += inf.fiber_ms
-        fiber_pts += inf.fiber_points
-        fiber_launch += inf.fiber_launches
+        for i in range(ncls):
+            cls_ms[i] += inf.class_ms[i]
+            cls_fl[i] += inf.class_flops[i]
+            cls_by[i] += inf.class_bytes[i]
+            cls_n[i] += inf.class_launches[i]
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     info = solver.info()
@@ -123,14 +120,27 @@ def main():
     eps_now = info.eps
     solver.close()
 
-    # fiber kernel roofline (FP64 ALU bound): algorithmic flops / device time of its launches
-    flop = FLOP_PER_POINT[2] * fiber_pts
-    achieved = flop / (fiber_ms * 1e-3) / 1e12 if fiber_ms > 0 else 0.0
-    roofline = {"bound": "alu", "kernel": "k_weno (fused LF + WENO5-JS fiber kernel)",
-                "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
-                "flop_per_point": FLOP_PER_POINT[2], "points": fiber_pts, "launches": fiber_launch,
-                "avg_launch_us": fiber_ms * 1e3 / max(fiber_launch, 1)}
+    names = ["k_stage (fused star-stencil LF + WENO5-JS stage-value fiber kernel)",
+             "k_prrlu_reg (full-pivot rank-revealing LU, cross pivots)",
+             "k_hhqr (Householder TSQR, rounding)", "k_jacobi_lds (one-sided Jacobi SVD, rounding)"]
+    breakdown = {}
+    for i in range(ncls):
+        entry = {"ms_per_step": cls_ms[i] / args.steps, "launches_per_step": cls_n[i] / args.steps,
+                 "avg_launch_us": cls_ms[i] * 1e3 / max(cls_n[i], 1)}
+        if cls_fl[i] > 0 and cls_ms[i] > 0:
+            entry["tflops"] = cls_fl[i] / (cls_ms[i] * 1e-3) / 1e12
+            entry["gbs_algorithmic"] = cls_by[i] / (cls_ms[i] * 1e-3) / 1e9
+        breakdown[names[i].split()[0]] = entry
+    # dominant kernel: the class with the most device time among those with an algorithmic count
+    dom = max((i for i in range(ncls) if cls_fl[i] > 0), key=lambda i: cls_ms[i])
+    achieved = cls_fl[dom] / (cls_ms[dom] * 1e-3) / 1e12 if cls_ms[dom] > 0 else 0.0
+    roofline = {"bound": "alu", "kernel": names[dom], "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                "algorithmic_flops_per_launch": cls_fl[dom] / max(cls_n[dom], 1),
+                "algorithmic_bytes_per_launch": cls_by[dom] / max(cls_n[dom], 1),
+                "avg_launch_us": cls_ms[dom] * 1e3 / max(cls_n[dom], 1),
+                "hbm_frac_algorithmic": cls_by[dom] / (cls_ms[dom] * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                "breakdown": breakdown}
 
     dense = None
     if not args.no_dense:

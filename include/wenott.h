@@ -88,6 +88,10 @@ typedef struct {
     double alpha_given; /* the Lax-Friedrichs alpha when alpha_mode = 2 */
     int32_t rounds_per_stage; /* 1 = one rounding per SSP-RK3 stage [1] */
     int32_t graph_mode; /* reserved, must be 0 [0] */
+    int32_t scheme;     /* 0: one cross per stage of the stage value a U^n + b (X + dt L(X)) itself;
+                           1: one cross of the flux Fhat_d per direction (Algorithms lf-cross and
+                              weno-cross fused), shift difference on core d, TT sum of the stage
+                              terms. Both round once per stage. [0] */
 } wenott_opts;
 
 /* Per-call diagnostics, filled by wenott_get_info. */
@@ -106,6 +110,14 @@ typedef struct {
     double fiber_ms;         /* device time of the fiber kernels in the last call */
     int64_t fiber_launches;  /* number of fiber-kernel launches in the last call */
     double step_ms;          /* host wall time of the last call */
+    /* With profiling on: per kernel class of the last call, [0] fiber (fused flux / stage
+     * kernel), [1] pivot selection (rank-revealing LU), [2] Householder TSQR, [3] Jacobi SVD:
+     * device time from HIP events on the context's stream, launches, and the algorithmic
+     * flops and bytes of those launches (counted from the formulas, not measured). */
+    double class_ms[4];
+    int64_t class_launches[4];
+    double class_flops[4];
+    double class_bytes[4];
 } wenott_info;
 
 /* Fill *o with the defaults. */

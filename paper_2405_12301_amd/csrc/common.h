@@ -53,9 +53,17 @@ __host__ __device__ inline int ghost_map(int i, int n, int bc) {
 struct GemmBatch {
     int nb1 = 1, nb2 = 1;
     long long sA1 = 0, sA2 = 0, sB1 = 0, sB2 = 0, sC1 = 0, sC2 = 0;
+    int ktot = 0;  // > 0: split-K, batch index z2 is the K-chunk of length K, valid up to ktot
 };
 void gemm_f64(hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha, const double *A, int lda,
               const double *B, int ldb, double beta, double *C, int ldc, const GemmBatch &bt = GemmBatch());
+
+// C[z] = A[z]^T B[z] (A: K x M, B: K x N) with the long reduction split into chunks summed
+// by a second pass; part needs gemm_tn_splitk_part(M, N, K, batch) doubles (falls back to
+// one pass when part_cap is smaller).
+void gemm_tn_splitk(hipStream_t s, int M, int N, int K, const double *A, int lda, const double *B, int ldb, double *C,
+                    int ldc, int batch, long long sA, long long sB, long long sC, double *part, size_t part_cap);
+size_t gemm_tn_splitk_part(int M, int N, int K, int batch);
 
 // R factor of a batch of tall matrices by Householder TSQR. Element (i, j) of matrix z is
 // A[z * sz + i * rs + j * cs]. Writes the n x n upper-triangular R of each into
@@ -65,9 +73,11 @@ void tsqr_r(hipStream_t s, int m, int n, int batch, const double *A, long long s
             double *R, double *scratch);
 
 // One-sided Jacobi SVD of a batch of n x n matrices (row-major at A[z * n * n]).
-// Outputs sigma[z * n + j] sorted descending and V[z * n * n] row-major with column j the
-// right singular vector of sigma_j. scratch: 2 * batch * n * n doubles.
-void jacobi_svd(hipStream_t s, int n, int batch, const double *A, double *sigma, double *V, double *scratch);
+// Outputs sigma[z * n + j] sorted descending, V[z * n * n] row-major with column j the
+// right singular vector of sigma_j and, if US != null, A V (= U Sigma). The matrices live in
+// LDS when 2 n^2 doubles fit; otherwise scratch must hold batch * (2 n^2 + n) doubles.
+void jacobi_svd(hipStream_t s, int n, int batch, const double *A, double *sigma, double *V, double *scratch,
+                double *US = nullptr);
 
 // Full-pivot rank-revealing LU of one m x n row-major matrix (overwritten by its residual).
 // Stops when the residual's squared Frobenius norm <= rel_tol2 * (initial squared norm), after
@@ -75,6 +85,10 @@ void jacobi_svd(hipStream_t s, int n, int batch, const double *A, double *sigma,
 // residual norm^2 into info[0..1] = {rank, resid2} (as doubles).
 void prrlu(hipStream_t s, int m, int n, double *A, int rmax, double rel_tol2, int *rowpiv, int *colpiv, double *L,
            double *info, double *rowbuf);
+
+// X = R^{-1} for the upper Cholesky factor R of each r x r Gram matrix G (batch); ws holds
+// batch * r * r doubles. Zero (padding) columns keep a unit diagonal.
+void chol_upper_inv(hipStream_t s, int r, int batch, const double *G, double *X, double *ws);
 
 // X (m x r, row-major) = L (m x ldl) * inv(L[rowpiv, :r]), the interpolative basis.
 void interp_solve(hipStream_t s, int m, int r, const double *L, int ldl, const int *rowpiv, double *X);
@@ -89,11 +103,33 @@ struct FiberGeom {
 
 // Interface matrices of the state cores. Left (side 0): P[c][s][a][R_k] for the p left
 // multi-indices idx[a * k + j], j < k. Right (side 1): Q[c][s][R_{k+1}][b] for the q right
-// multi-indices idx[b * (d-1-k) + j] (modes k+1..d-1). When the flux direction's mode is among
-// the multi-index modes, its entry is a face index m and S = 6 shifted copies hold the cells
-// m-3 .. m+2 (ghost-mapped); otherwise S = 1.
+// multi-indices idx[b * (d-1-k) + j] (modes k+1..d-1). The entry on mode shift_mode (if it is
+// one of the multi-index modes) is shifted: shift slot s = 0..S-1 takes cell v - 3 + s
+// (ghost-mapped): S = 6 for a face index (cells m-3..m+2), S = 7 for a cell (i-3..i+3).
 void iface(hipStream_t s, const FiberGeom &g, int side, const double *const *cores, const int *ranks, int count,
-           const int *idx, int S, double *out);
+           const int *idx, int S, int shift_mode, double *out);
+
+// Fused stage kernel: Y = wn Un + wx X + wl L(X) at the block points (a, i, b) of core k,
+// L(X) = -sum_d (Fhat_d(+1/2) - Fhat_d(-1/2)) / h_d from the seven cells around each point in
+// every direction. X stencil values: W0[c][a][cell][b] over the N_k cells of mode k (the
+// neighbours along mode k) and, for every direction d != k, Wd[d][c][s][a][i][b] (s = 0..6 for
+// cells -3..+3). Un values WN[c][a][i][b] (read only when wn != 0). Output as weno_block.
+struct StageArgs {
+    const double *W0;
+    const double *Wd[kMaxDim];
+    const double *WN;
+    double wn, wx, wl;
+    double inv_h[kMaxDim], eps_w[kMaxDim];
+};
+void stage_block(hipStream_t s, const FiberGeom &g, int p, int q, const StageArgs &a, double *out, long long sa,
+                 long long si, long long sb, long long sc, int *flags);
+// Exact stage value at random cells and the sampled residual of a TT of it: X at the 7 d
+// star cells (slot d*7 + s), Un at the point, TT approximation (shared cores + last core with
+// one slice per component).
+void sample_stage(hipStream_t s, const FiberGeom &g, const double *const *xcores, const int *xranks,
+                  const double *const *ncores, const int *nranks, int npts, const int *pts,
+                  const double *const *fcores, const int *franks, double wn, double wx, double wl,
+                  const double *inv_h, const double *eps_w, double *ust, double *acc, int *flags);
 
 // Fused LF + WENO5-JS flux evaluation of a block from the gathered stencil values.
 // Wv layout: same_dir (k == dir): W[c][a][cell][b] over N_k cells, the block's middle mode is
@@ -109,7 +145,7 @@ void weno_block(hipStream_t s, const FiberGeom &g, int p, int q, const T *W, dou
 void dense_eval(hipStream_t s, int mode, int d, int ncomp, long long nrows, int R, int nlast, const double *Lm,
                 long long lm_stride, const double *G, long long g_stride, double gamma, double *out, double *partial,
                 int nblocks, int *flags);
-double reduce_max_host(hipStream_t s, const double *partial, int n, double *dscratch);
+void reduce_max_dev(hipStream_t s, const double *partial, int n, double *dst);
 
 // Sampled residual of a flux TT at random points (face index on mode dir).
 void sample_residual(hipStream_t s, const FiberGeom &g, const double *const *ucores, const int *ranks, int npts,

@@ -50,7 +50,8 @@ inline void dfree(hipStream_t s, void *p) {
 
 enum Slot {
     S_P, S_Q, S_T, S_W, S_BLOCK, S_L, S_X, S_PIV, S_INFO, S_ROWBUF, S_TSQR, S_R, S_SIG, S_V, S_JAC, S_W1, S_W2,
-    S_RANKS, S_PART, S_DSCAL, S_UST, S_ACC, S_LM, S_NORMS, S_DELTA, S_TMP, S_DENSE, S_NSLOTS
+    S_RANKS, S_PART, S_DSCAL, S_UST, S_ACC, S_LM, S_NORMS, S_DELTA, S_TMP, S_DENSE,
+    S_PD0, S_PD1, S_QD0, S_QD1, S_TD0, S_TD1, S_WD0, S_WD1, S_PN, S_QN, S_TN, S_WN, S_SPLIT, S_NSLOTS
 };
 
 struct Scratch {
@@ -174,12 +175,13 @@ struct wenott_ctx {
     int *d_flags = nullptr;
     int *h_pinned_int = nullptr;
     double *h_pinned_dbl = nullptr;
-    std::vector<ISet> warm[kMaxDim];
-    bool warm_valid[kMaxDim] = {};
+    std::vector<ISet> warm[kMaxDim + 1];  // per flux direction, and [kMaxDim] for the stage value
+    bool warm_valid[kMaxDim + 1] = {};
     uint64_t counter = 0;
     double c_eps = 0.0, max_norm = 0.0;
     bool profiling = false;
     std::vector<hipEvent_t> ev;
+    std::vector<int> ev_class;
     int ev_used = 0;
     wenott_info info{};
     std::string last_error;
@@ -192,6 +194,15 @@ inline double seconds_now() {
 }
 
 // ------------------------------------------------------------------------ helpers
+// Raise the status recorded in a flag word already copied to the host.
+void raise_flags(wenott_ctx *c, int f) {
+    if (f) {
+        WTT_HIP(hipMemsetAsync(c->d_flags, 0, sizeof(int), c->s));
+        if (f & kFlagNaN) throw StatusError(WENOTT_ENAN, "NaN or Inf in a flux evaluation");
+        throw StatusError(WENOTT_ENONPHYS, "rho <= 0 or p <= 0 at an evaluated point");
+    }
+}
+
 void check_flags(wenott_ctx *c) {
     WTT_HIP(hipMemcpyAsync(c->h_pinned_int, c->d_flags, sizeof(int), hipMemcpyDeviceToHost, c->s));
     WTT_HIP(hipStreamSynchronize(c->s));
@@ -203,14 +214,25 @@ void check_flags(wenott_ctx *c) {
     }
 }
 
-void ev_record(wenott_ctx *c) {
+// Kernel classes timed with HIP events when profiling is on (wenott_info.class_*).
+enum KClass { KC_FIBER = 0, KC_PIVOT = 1, KC_TSQR = 2, KC_SVD = 3 };
+
+void ev_record(wenott_ctx *c, int cls = KC_FIBER) {
     if (!c->profiling) return;
     if (c->ev_used == (int)c->ev.size()) {
         hipEvent_t e;
         WTT_HIP(hipEventCreate(&e));
         c->ev.push_back(e);
+        c->ev_class.push_back(0);
     }
+    c->ev_class[c->ev_used] = cls;
     WTT_HIP(hipEventRecord(c->ev[c->ev_used++], c->s));
+}
+
+void add_work(wenott_ctx *c, int cls, double flops, double bytes) {
+    c->info.class_flops[cls] += flops;
+    c->info.class_bytes[cls] += bytes;
+    c->info.class_launches[cls] += 1;
 }
 
 TT copy_tt(wenott_ctx *c, const TT &a) {
@@ -253,9 +275,13 @@ double exact_alpha(wenott_ctx *c, const TT &U) {
     double *part = c->sc.get<double>(S_PART, nblocks);
     dense_eval(c->s, 1, U.d, U.nc, nrows, U.R[U.d - 1], nlast, Lm, lms, U.core[U.d - 1], U.cstride(U.d - 1),
                c->gamma, nullptr, part, nblocks, c->d_flags);
-    double a = reduce_max_host(c->s, part, nblocks, c->sc.get<double>(S_DSCAL, 4));
-    check_flags(c);
-    return a;
+    double *dsc = c->sc.get<double>(S_DSCAL, 4);
+    reduce_max_dev(c->s, part, nblocks, dsc);
+    WTT_HIP(hipMemcpyAsync(c->h_pinned_dbl + 64, dsc, sizeof(double), hipMemcpyDeviceToHost, c->s));
+    WTT_HIP(hipMemcpyAsync(c->h_pinned_int + 64, c->d_flags, sizeof(int), hipMemcpyDeviceToHost, c->s));
+    WTT_HIP(hipStreamSynchronize(c->s));
+    raise_flags(c, c->h_pinned_int[64]);
+    return c->h_pinned_dbl[64];
 }
 
 void to_dense_dev(wenott_ctx *c, const TT &U, double *out) {
@@ -289,10 +315,10 @@ void eval_block(wenott_ctx *c, const TT &U, int dir, int k, const ISet &L, const
 
     double *P = c->sc.get<double>(S_P, (size_t)nc * SL * p * Rk);
     if (k == 0) fill(c->s, P, (long long)nc * SL * p * Rk, 1.0);
-    else iface(c->s, g, 0, cores, ranks, p, c->ring.put(L.v.data(), L.v.size()), SL, P);
+    else iface(c->s, g, 0, cores, ranks, p, c->ring.put(L.v.data(), L.v.size()), SL, SL == 6 ? dir : -1, P);
     double *Q = c->sc.get<double>(S_Q, (size_t)nc * SR * Rk1 * q);
     if (k == d - 1) fill(c->s, Q, (long long)nc * SR * Rk1 * q, 1.0);
-    else iface(c->s, g, 1, cores, ranks, q, c->ring.put(Rs.v.data(), Rs.v.size()), SR, Q);
+    else iface(c->s, g, 1, cores, ranks, q, c->ring.put(Rs.v.data(), Rs.v.size()), SR, SR == 6 ? dir : -1, Q);
 
     const long long tsz = (long long)p * Nk * Rk1;
     double *T = c->sc.get<double>(S_T, (size_t)nc * SL * tsz);
@@ -315,11 +341,17 @@ void eval_block(wenott_ctx *c, const TT &U, int dir, int k, const ISet &L, const
     long long sa, si, sb, sc;
     if (lr) { sa = (long long)M * q * nc; si = (long long)q * nc; sb = nc; sc = 1; }
     else { sa = nc; si = (long long)q * p * nc; sb = (long long)p * nc; sc = 1; }
-    ev_record(c);
+    ev_record(c, KC_FIBER);
     weno_block<double>(c->s, g, p, q, W, out, sa, si, sb, sc, c->d_flags);
-    ev_record(c);
+    ev_record(c, KC_FIBER);
     c->info.fiber_points += (long long)p * M * q;
     c->info.fiber_launches += 1;
+    {  // one face flux per point: 6 cells x (primitives, flux, split) + 2 nc WENO5 + nc adds
+        const double pts = (double)p * M * q;
+        const double per = d == 2 ? 814.0 : 1013.0;
+        const double reads = (k == dir ? 1.0 : 6.0) * nc * 8.0;  // distinct gathered values per point
+        add_work(c, KC_FIBER, pts * per, pts * (reads + nc * 8.0));
+    }
 }
 
 ISet random_set(Rng &rng, int count, int first_mode, int len, const int *M) {
@@ -352,12 +384,19 @@ PivotResult pivots(wenott_ctx *c, double *B, int m, int n, double rel_tol2, doub
     double *L = c->sc.get<double>(S_L, (size_t)m * rmax);
     double *info = c->sc.get<double>(S_INFO, 2);
     double *rowbuf = c->sc.get<double>(S_ROWBUF, n);
+    ev_record(c, KC_PIVOT);
     prrlu(c->s, m, n, B, rmax, rel_tol2, piv, piv + rmax, L, info, rowbuf);
+    ev_record(c, KC_PIVOT);
     WTT_HIP(hipMemcpyAsync(c->h_pinned_dbl, info, 2 * sizeof(double), hipMemcpyDeviceToHost, c->s));
     WTT_HIP(hipMemcpyAsync(c->h_pinned_int, piv, rmax * sizeof(int), hipMemcpyDeviceToHost, c->s));
     WTT_HIP(hipStreamSynchronize(c->s));
     PivotResult r;
     r.rank = (int)c->h_pinned_dbl[0];
+    {  // full-pivot elimination to rank r: sum_t 2 (m - t)(n - t) flops; the block is read once, L written
+        double fl = 0.0;
+        for (int t = 0; t < r.rank; ++t) fl += 2.0 * (double)(m - t) * (double)(n - t);
+        add_work(c, KC_PIVOT, fl, 8.0 * ((double)m * n + (double)m * r.rank));
+    }
     r.rows.assign(c->h_pinned_int, c->h_pinned_int + r.rank);
     *Lout = L;
     (void)rmax;
@@ -382,9 +421,12 @@ double sampled_residual(wenott_ctx *c, const TT &U, const FluxTT &F, int dir, do
     const double *uc[kMaxDim], *fc[kMaxDim];
     for (int j = 0; j < d; ++j) { uc[j] = U.core[j]; fc[j] = F.core[j]; }
     sample_residual(c->s, g, uc, ranks, npts, dp, fc, franks, ust, acc, c->d_flags);
-    std::vector<double> h(2 * (size_t)nb);
-    WTT_HIP(hipMemcpyAsync(h.data(), acc, h.size() * sizeof(double), hipMemcpyDeviceToHost, c->s));
+    WTT_REQUIRE(2 * (size_t)nb <= 3000, WENOTT_EINVAL, "too many probe points");
+    WTT_HIP(hipMemcpyAsync(c->h_pinned_dbl + 128, acc, 2 * nb * sizeof(double), hipMemcpyDeviceToHost, c->s));
+    WTT_HIP(hipMemcpyAsync(c->h_pinned_int + 128, c->d_flags, sizeof(int), hipMemcpyDeviceToHost, c->s));
     WTT_HIP(hipStreamSynchronize(c->s));
+    raise_flags(c, c->h_pinned_int[128]);
+    const double *h = c->h_pinned_dbl + 128;
     double d2 = 0.0, n2 = 0.0;
     for (int b = 0; b < nb; ++b) { d2 += h[2 * b]; n2 += h[2 * b + 1]; }
     return n2 > 0.0 ? std::sqrt(d2 / n2) : std::sqrt(d2);
@@ -397,19 +439,32 @@ struct CrossStat {
     int maxrank = 0;
 };
 
-FluxTT cross_flux(wenott_ctx *c, const TT &U, int dir, double alpha, double eps, CrossStat &st) {
-    const int d = U.d, nc = U.nc;
-    int M[kMaxDim];
-    for (int j = 0; j < d; ++j) M[j] = U.N[j] + (j == dir ? 1 : 0);
+// A cross target: mode sizes, a block evaluator and the sampled residual of a candidate TT.
+struct CrossTarget {
+    int d = 0, nc = 0, q0 = 2;
+    int M[kMaxDim] = {};
+    std::function<void(int k, const ISet &L, const ISet &R, bool lr, double *out)> eval;
+    std::function<double(const FluxTT &F, Rng &rng)> residual;
+    int warm_slot = 0;
+};
+
+// Rank-adaptive cross (Sec. 3.3): left-to-right sweeps build interpolative cores
+// B(:, J) B(I, J)^{-1} from full-pivot rank-revealing LU pivots on the unfolding
+// (rows: left index x mode, columns: right index x component); a sweep is accepted when the
+// relative residual at random points is <= eps, otherwise a right-to-left sweep refreshes the
+// right index sets and the next sweep starts with a tighter pivot tolerance. Every sampled
+// index set is enriched by kick_rank random indices.
+FluxTT cross_generic(wenott_ctx *c, const CrossTarget &t, double eps, CrossStat &st) {
+    const int d = t.d, nc = t.nc;
+    const int *M = t.M;
     Rng rng(c->o.seed ^ (0x5851F42D4C957F2DULL * (++c->counter)));
     std::vector<ISet> Rset(d);
     Rset[d - 1].len = 0;
     Rset[d - 1].count = 1;
-    if (c->warm_valid[dir]) {
-        Rset = c->warm[dir];
+    if (c->warm_valid[t.warm_slot]) {
+        Rset = c->warm[t.warm_slot];
     } else {
-        int q0 = std::max(2, U.maxrank());
-        for (int k = 0; k < d - 1; ++k) Rset[k] = random_set(rng, q0, k + 1, d - 1 - k, M);
+        for (int k = 0; k < d - 1; ++k) Rset[k] = random_set(rng, t.q0, k + 1, d - 1 - k, M);
     }
     std::vector<ISet> Lset(d);
     FluxTT F;
@@ -431,7 +486,7 @@ FluxTT cross_flux(wenott_ctx *c, const TT &U, int dir, double alpha, double eps,
             const int p = Lset[k].count, q = Rk.count;
             const long long rows = (long long)p * M[k], cols = (long long)q * nc;
             double *B = c->sc.get<double>(S_BLOCK, (size_t)(rows * cols));
-            eval_block(c, U, dir, k, Lset[k], Rk, alpha, true, B);
+            t.eval(k, Lset[k], Rk, true, B);
             if (k < d - 1) {
                 double *L = nullptr;
                 PivotResult pr = pivots(c, B, (int)rows, (int)cols, rel2, &L);
@@ -444,10 +499,10 @@ FluxTT cross_flux(wenott_ctx *c, const TT &U, int dir, double alpha, double eps,
                 nl.len = k + 1;
                 nl.count = r;
                 nl.v.resize((size_t)r * (k + 1));
-                for (int t = 0; t < r; ++t) {
-                    int row = pr.rows[t], a = row / M[k], i = row % M[k];
-                    for (int j = 0; j < k; ++j) nl.v[(size_t)t * (k + 1) + j] = Lset[k].v[(size_t)a * k + j];
-                    nl.v[(size_t)t * (k + 1) + k] = i;
+                for (int tt = 0; tt < r; ++tt) {
+                    int row = pr.rows[tt], a = row / M[k], i = row % M[k];
+                    for (int j = 0; j < k; ++j) nl.v[(size_t)tt * (k + 1) + j] = Lset[k].v[(size_t)a * k + j];
+                    nl.v[(size_t)tt * (k + 1) + k] = i;
                 }
                 Lset[k + 1] = std::move(nl);
                 st.maxrank = std::max(st.maxrank, r);
@@ -456,7 +511,7 @@ FluxTT cross_flux(wenott_ctx *c, const TT &U, int dir, double alpha, double eps,
                 WTT_HIP(hipMemcpyAsync(F.core[k], B, sizeof(double) * rows * cols, hipMemcpyDeviceToDevice, c->s));
             }
         }
-        resid = sampled_residual(c, U, F, dir, alpha, rng);
+        resid = t.residual(F, rng);
         if (resid <= eps || sweep + 1 == c->o.max_sweeps) { ++sweep; break; }
         // right-to-left sweep: refresh the right index sets from the new left ones
         for (int k = d - 1; k >= 1; --k) {
@@ -465,25 +520,24 @@ FluxTT cross_flux(wenott_ctx *c, const TT &U, int dir, double alpha, double eps,
             const int p = Lk.count, q = Rk.count;
             const long long rows = (long long)M[k] * q, cols = (long long)p * nc;
             double *B = c->sc.get<double>(S_BLOCK, (size_t)(rows * cols));
-            eval_block(c, U, dir, k, Lk, Rk, alpha, false, B);
+            t.eval(k, Lk, Rk, false, B);
             double *L = nullptr;
             PivotResult pr = pivots(c, B, (int)rows, (int)cols, rel2, &L);
             ISet nr;
             nr.len = d - k;
             nr.count = pr.rank;
             nr.v.resize((size_t)pr.rank * nr.len);
-            for (int t = 0; t < pr.rank; ++t) {
-                int row = pr.rows[t], i = row / q, b = row % q;
-                nr.v[(size_t)t * nr.len] = i;
-                for (int j = 0; j < Rk.len; ++j) nr.v[(size_t)t * nr.len + 1 + j] = Rk.v[(size_t)b * Rk.len + j];
+            for (int tt = 0; tt < pr.rank; ++tt) {
+                int row = pr.rows[tt], i = row / q, b = row % q;
+                nr.v[(size_t)tt * nr.len] = i;
+                for (int j = 0; j < Rk.len; ++j) nr.v[(size_t)tt * nr.len + 1 + j] = Rk.v[(size_t)b * Rk.len + j];
             }
             Rset[k - 1] = std::move(nr);
         }
         rel2 *= 0.25;
     }
-    check_flags(c);
-    c->warm[dir] = Rset;
-    c->warm_valid[dir] = true;
+    c->warm[t.warm_slot] = Rset;
+    c->warm_valid[t.warm_slot] = true;
     st.sweeps = sweep;
     st.residual = resid;
     if (!(resid <= 1e3 * eps) && !(resid <= 1e-12))
@@ -491,15 +545,163 @@ FluxTT cross_flux(wenott_ctx *c, const TT &U, int dir, double alpha, double eps,
     return F;
 }
 
-// L_dir = -(T^dir - 1) Fhat_dir / h_dir as a per-component TT.
-TT flux_to_rhs_term(wenott_ctx *c, const FluxTT &F, int dir) {
+FluxTT cross_flux(wenott_ctx *c, const TT &U, int dir, double alpha, double eps, CrossStat &st) {
+    CrossTarget t;
+    t.d = U.d;
+    t.nc = U.nc;
+    t.q0 = std::max(2, U.maxrank());
+    for (int j = 0; j < U.d; ++j) t.M[j] = U.N[j] + (j == dir ? 1 : 0);
+    t.eval = [&](int k, const ISet &L, const ISet &R, bool lr, double *out) {
+        eval_block(c, U, dir, k, L, R, alpha, lr, out);
+    };
+    t.residual = [&](const FluxTT &F, Rng &rng) { return sampled_residual(c, U, F, dir, alpha, rng); };
+    t.warm_slot = dir;
+    return cross_generic(c, t, eps, st);
+}
+
+// ------------------------------------------------------------------- stage value
+struct StageWeights {
+    double wn, wx, wl;  // Y = wn Un + wx X + wl L(X)
+};
+
+// Interface matrices + gathered stencil blocks of X (and Un) for core k, then the fused stage kernel.
+void eval_stage_block(wenott_ctx *c, const TT &X, const TT *Un, StageWeights w, double alpha, int k, const ISet &L,
+                      const ISet &Rs, bool lr, double *out) {
+    const int d = X.d, nc = X.nc;
+    hipStream_t s = c->s;
+    FiberGeom g{};
+    g.d = d; g.ncomp = nc; g.dir = 0; g.k = k;
+    for (int j = 0; j < d; ++j) { g.n[j] = X.N[j]; g.bc[j] = c->bc[j]; }
+    g.gamma = c->gamma; g.alpha = alpha; g.eps_w = 0.0;
+    const int p = L.count, q = Rs.count, Nk = X.N[k];
+    const int *didxL = k > 0 ? c->ring.put(L.v.data(), L.v.size()) : nullptr;
+    const int *didxR = k < d - 1 ? c->ring.put(Rs.v.data(), Rs.v.size()) : nullptr;
+
+    // W = P G_k Q for a TT (X or Un); S shifts on P (left) or Q (right) of mode `shift`.
+    auto gather = [&](const TT &Y, int shift, int slotP, int slotQ, int slotT, int slotW) -> double * {
+        const int Rk = Y.R[k], Rk1 = Y.R[k + 1];
+        int ranks[kMaxDim + 1];
+        for (int j = 0; j <= d; ++j) ranks[j] = Y.R[j];
+        const double *cores[kMaxDim];
+        for (int j = 0; j < d; ++j) cores[j] = Y.core[j];
+        const int SL = (shift >= 0 && shift < k) ? 7 : 1, SR = (shift > k) ? 7 : 1, S = std::max(SL, SR);
+        double *P = c->sc.get<double>(slotP, (size_t)nc * SL * p * Rk);
+        if (k == 0) fill(s, P, (long long)nc * SL * p * Rk, 1.0);
+        else iface(s, g, 0, cores, ranks, p, didxL, SL, SL == 7 ? shift : -1, P);
+        double *Q = c->sc.get<double>(slotQ, (size_t)nc * SR * Rk1 * q);
+        if (k == d - 1) fill(s, Q, (long long)nc * SR * Rk1 * q, 1.0);
+        else iface(s, g, 1, cores, ranks, q, didxR, SR, SR == 7 ? shift : -1, Q);
+        const long long tsz = (long long)p * Nk * Rk1;
+        double *T = c->sc.get<double>(slotT, (size_t)nc * SL * tsz);
+        GemmBatch b1;
+        b1.nb1 = nc; b1.nb2 = SL;
+        b1.sA1 = (long long)SL * p * Rk; b1.sA2 = (long long)p * Rk;
+        b1.sB1 = Y.cstride(k); b1.sB2 = 0;
+        b1.sC1 = SL * tsz; b1.sC2 = tsz;
+        gemm_f64(s, false, false, p, Nk * Rk1, Rk, 1.0, P, Rk, Y.core[k], Nk * Rk1, 0.0, T, Nk * Rk1, b1);
+        const long long wsz = (long long)p * Nk * q;
+        double *W = c->sc.get<double>(slotW, (size_t)nc * S * wsz);
+        GemmBatch b2;
+        b2.nb1 = nc; b2.nb2 = S;
+        b2.sA1 = SL * tsz; b2.sA2 = SL == 7 ? tsz : 0;
+        b2.sB1 = (long long)SR * Rk1 * q; b2.sB2 = SR == 7 ? (long long)Rk1 * q : 0;
+        b2.sC1 = S * wsz; b2.sC2 = wsz;
+        gemm_f64(s, false, false, p * Nk, q, Rk1, 1.0, T, Rk1, Q, q, 0.0, W, q, b2);
+        return W;
+    };
+    StageArgs a{};
+    a.W0 = gather(X, -1, S_P, S_Q, S_T, S_W);
+    int od = 0;
+    for (int dd = 0; dd < d; ++dd) {
+        a.inv_h[dd] = 1.0 / c->h[dd];
+        a.eps_w[dd] = c->h[dd] * c->h[dd];
+        if (dd == k) continue;
+        a.Wd[dd] = gather(X, dd, od == 0 ? S_PD0 : S_PD1, od == 0 ? S_QD0 : S_QD1, od == 0 ? S_TD0 : S_TD1,
+                          od == 0 ? S_WD0 : S_WD1);
+        ++od;
+    }
+    a.WN = nullptr;
+    if (Un && w.wn != 0.0) a.WN = gather(*Un, -1, S_PN, S_QN, S_TN, S_WN);
+    a.wn = w.wn; a.wx = w.wx; a.wl = w.wl;
+    long long sa, si, sb, sc;
+    if (lr) { sa = (long long)Nk * q * nc; si = (long long)q * nc; sb = nc; sc = 1; }
+    else { sa = nc; si = (long long)q * p * nc; sb = (long long)p * nc; sc = 1; }
+    ev_record(c, KC_FIBER);
+    stage_block(s, g, p, q, a, out, sa, si, sb, sc, c->d_flags);
+    ev_record(c, KC_FIBER);
+    c->info.fiber_points += (long long)p * Nk * q;
+    c->info.fiber_launches += 1;
+    {  // per point and direction: 7 cells x (primitives, flux, split) + 4 nc WENO5 + difference;
+       // distinct gathered values: the point itself, 6 shifted cells per other direction, Un
+        const double pts = (double)p * Nk * q;
+        const double per = d == 2 ? 2894.0 : 5398.0;
+        const double reads = (1.0 + 6.0 * (d - 1) + (a.WN ? 1.0 : 0.0)) * nc * 8.0;
+        add_work(c, KC_FIBER, pts * per, pts * (reads + nc * 8.0));
+    }
+}
+
+double sampled_stage_residual(wenott_ctx *c, const TT &X, const TT *Un, StageWeights w, double alpha,
+                              const FluxTT &F, Rng &rng) {
+    const int d = X.d, npts = std::max(c->o.probe_points, 16);
+    FiberGeom g{};
+    g.d = d; g.ncomp = X.nc; g.dir = 0; g.k = 0;
+    for (int j = 0; j < d; ++j) { g.n[j] = X.N[j]; g.bc[j] = c->bc[j]; }
+    g.gamma = c->gamma; g.alpha = alpha;
+    std::vector<int> pts((size_t)npts * d);
+    for (int i = 0; i < npts; ++i)
+        for (int j = 0; j < d; ++j) pts[(size_t)i * d + j] = rng.below(X.N[j]);
+    const int *dp = c->ring.put(pts.data(), pts.size());
+    const int SL = 7 * d + 1;
+    double *ust = c->sc.get<double>(S_UST, (size_t)npts * SL * X.nc);
+    int nb = (npts + 255) / 256;
+    double *acc = c->sc.get<double>(S_ACC, 2 * (size_t)nb);
+    int xr[kMaxDim + 1], nr[kMaxDim + 1], fr[kMaxDim + 1];
+    const double *xc[kMaxDim], *ncs[kMaxDim], *fc[kMaxDim];
+    for (int j = 0; j <= d; ++j) { xr[j] = X.R[j]; fr[j] = F.R[j]; nr[j] = Un ? Un->R[j] : 1; }
+    for (int j = 0; j < d; ++j) { xc[j] = X.core[j]; fc[j] = F.core[j]; ncs[j] = Un ? Un->core[j] : nullptr; }
+    double inv_h[kMaxDim], eps_w[kMaxDim];
+    for (int j = 0; j < d; ++j) { inv_h[j] = 1.0 / c->h[j]; eps_w[j] = c->h[j] * c->h[j]; }
+    const bool use_un = Un && w.wn != 0.0;
+    sample_stage(c->s, g, xc, xr, use_un ? ncs : nullptr, nr, npts, dp, fc, fr, use_un ? w.wn : 0.0, w.wx, w.wl,
+                 inv_h, eps_w, ust, acc, c->d_flags);
+    WTT_REQUIRE(2 * (size_t)nb <= 3000, WENOTT_EINVAL, "too many probe points");
+    WTT_HIP(hipMemcpyAsync(c->h_pinned_dbl + 128, acc, 2 * nb * sizeof(double), hipMemcpyDeviceToHost, c->s));
+    WTT_HIP(hipMemcpyAsync(c->h_pinned_int + 128, c->d_flags, sizeof(int), hipMemcpyDeviceToHost, c->s));
+    WTT_HIP(hipStreamSynchronize(c->s));
+    raise_flags(c, c->h_pinned_int[128]);
+    const double *h = c->h_pinned_dbl + 128;
+    double d2 = 0.0, n2 = 0.0;
+    for (int b = 0; b < nb; ++b) { d2 += h[2 * b]; n2 += h[2 * b + 1]; }
+    return n2 > 0.0 ? std::sqrt(d2 / n2) : std::sqrt(d2);
+}
+
+FluxTT cross_stage(wenott_ctx *c, const TT &X, const TT *Un, StageWeights w, double alpha, double eps,
+                   CrossStat &st) {
+    CrossTarget t;
+    t.d = X.d;
+    t.nc = X.nc;
+    t.q0 = std::max(2, X.maxrank());
+    for (int j = 0; j < X.d; ++j) t.M[j] = X.N[j];
+    t.eval = [&](int k, const ISet &L, const ISet &R, bool lr, double *out) {
+        eval_stage_block(c, X, Un, w, alpha, k, L, R, lr, out);
+    };
+    t.residual = [&](const FluxTT &F, Rng &rng) { return sampled_stage_residual(c, X, Un, w, alpha, F, rng); };
+    t.warm_slot = kMaxDim;
+    return cross_generic(c, t, eps, st);
+}
+
+// Per-component TT of a cross result: shared cores copied to every component, the last
+// core split into its component slices. With dir >= 0 the result is the flux term
+// L_dir = -(T^dir - 1) Fhat_dir / h_dir: the shift difference acts on core dir only
+// (eqs. shifted-fluxes and euler-system-TT) and maps its N + 1 faces to N cells.
+TT cross_to_tt(wenott_ctx *c, const FluxTT &F, int dir) {
     const int d = F.d, nc = F.nc;
     TT L;
     L.d = d; L.nc = nc;
     for (int j = 0; j < d; ++j) L.N[j] = c->N[j];
     for (int j = 0; j <= d; ++j) L.R[j] = F.R[j];
     L.alloc(c->s);
-    const double scale = -1.0 / c->h[dir];
+    const double scale = dir >= 0 ? -1.0 / c->h[dir] : 1.0;
     for (int k = 0; k < d - 1; ++k) {
         long long len = L.cstride(k);
         if (k == dir) {
@@ -556,11 +758,17 @@ int svd_ranks(wenott_ctx *c, int m, int n, const double *A, long long sz, long l
     const int nc = c->U.nc;
     double *scr = c->sc.get<double>(S_TSQR, tsqr_scratch_doubles(m, n, nc));
     double *R = c->sc.get<double>(S_R, (size_t)nc * n * n);
+    ev_record(c, KC_TSQR);
     tsqr_r(c->s, m, n, nc, A, sz, rs, cs, R, scr);
+    ev_record(c, KC_TSQR);
+    add_work(c, KC_TSQR, nc * (2.0 * m * (double)n * n - 2.0 / 3.0 * (double)n * n * n), 8.0 * nc * (double)m * n);
     *sig = c->sc.get<double>(S_SIG, (size_t)nc * n);
     *V = c->sc.get<double>(S_V, (size_t)nc * n * n);
     double *jac = c->sc.get<double>(S_JAC, (size_t)nc * (2 * (size_t)n * n + n));
+    ev_record(c, KC_SVD);
     jacobi_svd(c->s, n, nc, R, *sig, *V, jac);
+    ev_record(c, KC_SVD);
+    add_work(c, KC_SVD, 0.0, 8.0 * nc * 3.0 * (double)n * n);
     *rk = c->sc.get<int>(S_RANKS, nc);
     trunc_ranks(c->s, n, nc, *sig, delta_abs, rel, rcap, *rk);
     WTT_HIP(hipMemcpyAsync(c->h_pinned_int, *rk, nc * sizeof(int), hipMemcpyDeviceToHost, c->s));
@@ -570,70 +778,118 @@ int svd_ranks(wenott_ctx *c, int m, int n, const double *A, long long sz, long l
     return r;
 }
 
-// TT-rounding (Sec. 3.2). Returns the Frobenius norms of the components in norms.
+// TT-rounding (Sec. 3.2) with one SVD per bond. Right-to-left, only R factors are formed:
+// with T_k the R factor of (G_k x_3 T_{k+1}^T) unfolded as R_{k-1} x (N_k r_k) and transposed,
+// the right part X_{>=k} equals T_k^T times a matrix with orthonormal rows. Left-to-right,
+// C_k = G'_k x_3 T_{k+1}^T has the singular values of the k-th unfolding; its truncated SVD
+// gives the new left-orthonormal core U_r = G'_k (T_{k+1}^T V_r Sigma_r^{-1}), and the next
+// core becomes (U_r^T G'_k) G_{k+1}. Each truncation keeps the smallest rank whose discarded
+// tail is at most eps ||X_c||_F / sqrt(d-1), so ||X - Y||_F <= eps ||X||_F per component.
+// Returns the Frobenius norms of the components in norms.
 void round_tt(wenott_ctx *c, TT &X, double eps, bool truncate, std::vector<double> &norms) {
     const int d = X.d, nc = X.nc;
     hipStream_t s = c->s;
-    // right-to-left orthogonalisation: core_k = (Sigma^-1 V^T) B, core_{k-1} <- core_{k-1} V Sigma
+    std::vector<double *> T(d + 1, nullptr);
+    // right-to-left: R factors only
     for (int k = d - 1; k >= 1; --k) {
-        const int n = X.R[k];
-        const int m = X.N[k] * X.R[k + 1];
-        double *sig, *V;
-        int *rk;
-        int r = svd_ranks(c, m, n, X.core[k], X.cstride(k), 1, m, nullptr, 1e-15, n, &sig, &V, &rk);
-        double *W1 = c->sc.get<double>(S_W1, (size_t)nc * n * r);
-        double *W2 = c->sc.get<double>(S_W2, (size_t)nc * n * r);
-        build_projectors(s, n, nc, r, sig, V, rk, W1, W2);
-        double *nk = dalloc<double>(s, (size_t)nc * r * m);
-        GemmBatch b1;
-        b1.nb1 = nc; b1.sA1 = (long long)n * r; b1.sB1 = X.cstride(k); b1.sC1 = (long long)r * m;
-        gemm_f64(s, true, false, r, m, n, 1.0, W1, r, X.core[k], m, 0.0, nk, m, b1);
-        const int mp = X.R[k - 1] * X.N[k - 1];
-        double *nkm = dalloc<double>(s, (size_t)nc * mp * r);
-        GemmBatch b2;
-        b2.nb1 = nc; b2.sA1 = X.cstride(k - 1); b2.sB1 = (long long)r * n; b2.sC1 = (long long)mp * r;
-        gemm_f64(s, false, true, mp, r, n, 1.0, X.core[k - 1], n, W2, n, 0.0, nkm, r, b2);
-        dfree(s, X.core[k]);
-        dfree(s, X.core[k - 1]);
-        X.core[k] = nk;
-        X.core[k - 1] = nkm;
-        X.R[k] = r;
+        const int Rk = X.R[k], Nk = X.N[k], Rk1 = X.R[k + 1];
+        const long long m = (long long)Nk * Rk1;
+        const double *C = X.core[k];
+        if (k < d - 1) {
+            double *Cb = c->sc.get<double>(S_TMP, (size_t)nc * Rk * m);
+            GemmBatch b;
+            b.nb1 = nc; b.sA1 = X.cstride(k); b.sB1 = (long long)Rk1 * Rk1; b.sC1 = (long long)Rk * m;
+            gemm_f64(s, false, true, Rk * Nk, Rk1, Rk1, 1.0, X.core[k], Rk1, T[k + 1], Rk1, 0.0, Cb, Rk1, b);
+            C = Cb;
+        }
+        double *scr = c->sc.get<double>(S_TSQR, tsqr_scratch_doubles((int)m, Rk, nc));
+        T[k] = dalloc<double>(s, (size_t)nc * Rk * Rk);
+        ev_record(c, KC_TSQR);
+        tsqr_r(s, (int)m, Rk, nc, C, (long long)Rk * m, 1, m, T[k], scr);
+        ev_record(c, KC_TSQR);
+        add_work(c, KC_TSQR, nc * (2.0 * m * (double)Rk * Rk - 2.0 / 3.0 * (double)Rk * Rk * Rk),
+                 8.0 * nc * (double)m * Rk);
     }
-    double *dn = c->sc.get<double>(S_NORMS, nc);
-    frob_norms(s, nc, X.cstride(0), X.core[0], X.cstride(0), dn);
-    norms.resize(nc);
-    WTT_HIP(hipMemcpyAsync(c->h_pinned_dbl, dn, nc * sizeof(double), hipMemcpyDeviceToHost, s));
-    WTT_HIP(hipStreamSynchronize(s));
-    for (int z = 0; z < nc; ++z) norms[z] = c->h_pinned_dbl[z];
-    if (!truncate) return;
+    // norms: ||X_c|| = ||G_0 T_1^T||_F
+    {
+        const int N0 = X.N[0], R1 = X.R[1];
+        double *C0 = c->sc.get<double>(S_TMP, (size_t)nc * N0 * R1);
+        GemmBatch b;
+        b.nb1 = nc; b.sA1 = X.cstride(0); b.sB1 = (long long)R1 * R1; b.sC1 = (long long)N0 * R1;
+        gemm_f64(s, false, true, N0, R1, R1, 1.0, X.core[0], R1, T[1], R1, 0.0, C0, R1, b);
+        double *dn = c->sc.get<double>(S_NORMS, nc);
+        frob_norms(s, nc, (long long)N0 * R1, C0, (long long)N0 * R1, dn);
+        norms.resize(nc);
+        WTT_HIP(hipMemcpyAsync(c->h_pinned_dbl, dn, nc * sizeof(double), hipMemcpyDeviceToHost, s));
+        WTT_HIP(hipStreamSynchronize(s));
+        for (int z = 0; z < nc; ++z) norms[z] = c->h_pinned_dbl[z];
+    }
+    if (!truncate) {
+        for (int k = 1; k < d; ++k) dfree(s, T[k]);
+        return;
+    }
     std::vector<double> delta(nc);
     for (int z = 0; z < nc; ++z) delta[z] = eps * norms[z] / std::sqrt((double)std::max(d - 1, 1));
     const double *ddelta = c->ring.put(delta.data(), delta.size());
-    // left-to-right truncation: core_k = A V_r Sigma_r^-1, core_{k+1} <- Sigma_r V_r^T core_{k+1}
     for (int k = 0; k < d - 1; ++k) {
-        const int m = X.R[k] * X.N[k];
-        const int n = X.R[k + 1];
+        const int Rk = X.R[k], Nk = X.N[k], n = X.R[k + 1];
+        const int m = Rk * Nk;
+        double *C = c->sc.get<double>(S_TMP, (size_t)nc * m * n);
+        GemmBatch b0;
+        b0.nb1 = nc; b0.sA1 = X.cstride(k); b0.sB1 = (long long)n * n; b0.sC1 = (long long)m * n;
+        gemm_f64(s, false, true, m, n, n, 1.0, X.core[k], n, T[k + 1], n, 0.0, C, n, b0);
         double *sig, *V;
         int *rk;
-        int r = svd_ranks(c, m, n, X.core[k], X.cstride(k), n, 1, ddelta, 0.0, c->o.rank_cap, &sig, &V, &rk);
+        int r = svd_ranks(c, m, n, C, (long long)m * n, n, 1, ddelta, 0.0, c->o.rank_cap, &sig, &V, &rk);
         double *W1 = c->sc.get<double>(S_W1, (size_t)nc * n * r);
         double *W2 = c->sc.get<double>(S_W2, (size_t)nc * n * r);
         build_projectors(s, n, nc, r, sig, V, rk, W1, W2);
-        double *nk = dalloc<double>(s, (size_t)nc * m * r);
+        // P = T_{k+1}^T W1 (n x r)
+        double *P = c->sc.get<double>(S_P, (size_t)nc * n * r);
         GemmBatch b1;
-        b1.nb1 = nc; b1.sA1 = X.cstride(k); b1.sB1 = (long long)n * r; b1.sC1 = (long long)m * r;
-        gemm_f64(s, false, false, m, r, n, 1.0, X.core[k], n, W1, r, 0.0, nk, r, b1);
+        b1.nb1 = nc; b1.sA1 = (long long)n * n; b1.sB1 = (long long)n * r; b1.sC1 = (long long)n * r;
+        gemm_f64(s, true, false, n, r, n, 1.0, T[k + 1], n, W1, r, 0.0, P, r, b1);
+        // new core k = G'_k P (m x r)
+        double *nk = dalloc<double>(s, (size_t)nc * m * r);
+        GemmBatch b2;
+        b2.nb1 = nc; b2.sA1 = X.cstride(k); b2.sB1 = (long long)n * r; b2.sC1 = (long long)m * r;
+        gemm_f64(s, false, false, m, r, n, 1.0, X.core[k], n, P, r, 0.0, nk, r, b2);
+        // Columns of G'_k P belonging to small kept singular values carry rounding noise along
+        // the dominant directions (relative size u ||G'_k|| ||T|| / sigma_j); re-orthonormalise
+        // them in descending sigma order (two CholeskyQR passes) before projecting.
+        for (int pass = 0; pass < 2; ++pass) {
+            double *Gm = c->sc.get<double>(S_PD0, (size_t)nc * r * r);
+            double *Xi = c->sc.get<double>(S_PD1, (size_t)nc * r * r);
+            double *ws = c->sc.get<double>(S_TD0, (size_t)nc * r * r);
+            size_t pc = gemm_tn_splitk_part(r, r, m, nc);
+            gemm_tn_splitk(s, r, r, m, nk, r, nk, r, Gm, r, nc, (long long)m * r, (long long)m * r, (long long)r * r,
+                           c->sc.get<double>(S_SPLIT, pc), pc);
+            chol_upper_inv(s, r, nc, Gm, Xi, ws);
+            double *nk2 = c->sc.get<double>(S_TD1, (size_t)nc * m * r);
+            GemmBatch bx;
+            bx.nb1 = nc; bx.sA1 = (long long)m * r; bx.sB1 = (long long)r * r; bx.sC1 = (long long)m * r;
+            gemm_f64(s, false, false, m, r, r, 1.0, nk, r, Xi, r, 0.0, nk2, r, bx);
+            WTT_HIP(hipMemcpyAsync(nk, nk2, sizeof(double) * nc * m * r, hipMemcpyDeviceToDevice, s));
+        }
+        // S = new^T G'_k (r x n); next core = S G_{k+1}
+        double *Sm = c->sc.get<double>(S_Q, (size_t)nc * r * n);
+        {
+            size_t pc = gemm_tn_splitk_part(r, n, m, nc);
+            gemm_tn_splitk(s, r, n, m, nk, r, X.core[k], n, Sm, n, nc, (long long)m * r, X.cstride(k), (long long)r * n,
+                           c->sc.get<double>(S_SPLIT, pc), pc);
+        }
         const int mn = X.N[k + 1] * X.R[k + 2];
         double *nk1 = dalloc<double>(s, (size_t)nc * r * mn);
-        GemmBatch b2;
-        b2.nb1 = nc; b2.sA1 = (long long)r * n; b2.sB1 = X.cstride(k + 1); b2.sC1 = (long long)r * mn;
-        gemm_f64(s, false, false, r, mn, n, 1.0, W2, n, X.core[k + 1], mn, 0.0, nk1, mn, b2);
+        GemmBatch b4;
+        b4.nb1 = nc; b4.sA1 = (long long)r * n; b4.sB1 = X.cstride(k + 1); b4.sC1 = (long long)r * mn;
+        gemm_f64(s, false, false, r, mn, n, 1.0, Sm, n, X.core[k + 1], mn, 0.0, nk1, mn, b4);
         dfree(s, X.core[k]);
         dfree(s, X.core[k + 1]);
         X.core[k] = nk;
         X.core[k + 1] = nk1;
         X.R[k + 1] = r;
     }
+    for (int k = 1; k < d; ++k) dfree(s, T[k]);
 }
 
 double geometric_h(const wenott_ctx *c) {
@@ -666,7 +922,7 @@ std::vector<TT> rhs_terms(wenott_ctx *c, const TT &U, double alpha, double eps, 
             c->info.residual[stage][dir] = st.residual;
             c->info.flux_rank[stage][dir] = st.maxrank;
         }
-        terms.push_back(flux_to_rhs_term(c, F, dir));
+        terms.push_back(cross_to_tt(c, F, dir));
         F.release(c->s);
     }
     return terms;
@@ -676,19 +932,24 @@ void reset_call_info(wenott_ctx *c) {
     c->info.fiber_points = 0;
     c->info.fiber_launches = 0;
     c->info.fiber_ms = 0.0;
+    for (int i = 0; i < 4; ++i) {
+        c->info.class_ms[i] = 0.0;
+        c->info.class_flops[i] = 0.0;
+        c->info.class_bytes[i] = 0.0;
+        c->info.class_launches[i] = 0;
+    }
     c->ev_used = 0;
 }
 
 void finish_call_info(wenott_ctx *c, double t0) {
     if (c->profiling && c->ev_used >= 2) {
         WTT_HIP(hipStreamSynchronize(c->s));
-        double ms = 0.0;
         for (int i = 0; i + 1 < c->ev_used; i += 2) {
             float e = 0.f;
             WTT_HIP(hipEventElapsedTime(&e, c->ev[i], c->ev[i + 1]));
-            ms += e;
+            c->info.class_ms[c->ev_class[i]] += e;
         }
-        c->info.fiber_ms = ms;
+        c->info.fiber_ms = c->info.class_ms[KC_FIBER];
     }
     c->info.step_ms = (seconds_now() - t0) * 1e3;
 }
@@ -745,6 +1006,7 @@ void wenott_default_opts(wenott_opts *o) {
     o->alpha_given = 0.0;
     o->rounds_per_stage = 1;
     o->graph_mode = 0;
+    o->scheme = 0;
 }
 
 const char *wenott_strerror(wenott_status s) {
@@ -782,6 +1044,7 @@ wenott_status wenott_init(wenott_ctx **out, const wenott_tt *state, const wenott
         WTT_REQUIRE(c->o.precision == 0 || c->o.precision == 1, WENOTT_EINVAL, "precision must be 0 or 1");
         WTT_REQUIRE(c->o.max_sweeps >= 1 && c->o.rank_cap >= 1 && c->o.kick_rank >= 0, WENOTT_EINVAL, "bad options");
         WTT_REQUIRE(c->o.eps_mode == 0 || c->o.eps_mode == 1, WENOTT_EINVAL, "eps_mode must be 0 or 1");
+        WTT_REQUIRE(c->o.scheme == 0 || c->o.scheme == 1, WENOTT_EINVAL, "scheme must be 0 or 1");
         for (int k = 0; k < d; ++k) {
             WTT_REQUIRE(grid->n[k] >= 3 && grid->n[k] <= (1 << 20), WENOTT_EINVAL, "grid size out of range");
             WTT_REQUIRE(grid->hi[k] > grid->lo[k], WENOTT_EINVAL, "empty box");
@@ -901,11 +1164,23 @@ wenott_status wenott_rhs(wenott_ctx *c, double alpha, wenott_tt *view) {
         WTT_REQUIRE(a > 0.0, WENOTT_EINVAL, "alpha must be positive");
         c->info.alpha[0] = a;
         double eps = current_eps(c);
-        std::vector<TT> terms = rhs_terms(c, c->U, a, eps, 0);
-        std::vector<std::pair<double, const TT *>> w;
-        for (auto &t : terms) w.push_back({1.0, &t});
-        TT S = tt_sum(c, w);
-        for (auto &t : terms) t.release(c->s);
+        TT S;
+        if (c->o.scheme == 0) {
+            // one cross of L(U) itself (stage value with weights 0, 0, 1)
+            CrossStat st;
+            FluxTT F = cross_stage(c, c->U, nullptr, StageWeights{0.0, 0.0, 1.0}, a, eps, st);
+            c->info.sweeps[0][0] = st.sweeps;
+            c->info.residual[0][0] = st.residual;
+            c->info.flux_rank[0][0] = st.maxrank;
+            S = cross_to_tt(c, F, -1);
+            F.release(c->s);
+        } else {
+            std::vector<TT> terms = rhs_terms(c, c->U, a, eps, 0);
+            std::vector<std::pair<double, const TT *>> w;
+            for (auto &t : terms) w.push_back({1.0, &t});
+            S = tt_sum(c, w);
+            for (auto &t : terms) t.release(c->s);
+        }
         std::vector<double> norms;
         round_tt(c, S, eps, true, norms);
         if (c->have_rhs) c->rhs.release(c->s);
@@ -937,13 +1212,25 @@ wenott_status wenott_rk3_step(wenott_ctx *c, double dt, double eps_in, const dou
                 else a = exact_alpha(c, X);
                 WTT_REQUIRE(a > 0.0, WENOTT_EINVAL, "alpha must be positive");
                 c->info.alpha[st] = a;
-                std::vector<TT> terms = rhs_terms(c, X, a, eps, st);
-                std::vector<std::pair<double, const TT *>> w;
-                if (aw[st] != 0.0) w.push_back({aw[st], &c->U});
-                w.push_back({bw[st], &X});
-                for (auto &t : terms) w.push_back({bw[st] * dt, &t});
-                TT S = tt_sum(c, w);
-                for (auto &t : terms) t.release(c->s);
+                TT S;
+                if (c->o.scheme == 0) {
+                    // stage-cross: one cross of a_s U^n + b_s (X + dt L(X)) itself
+                    CrossStat cs;
+                    FluxTT F = cross_stage(c, X, &c->U, StageWeights{aw[st], bw[st], bw[st] * dt}, a, eps, cs);
+                    c->info.sweeps[st][0] = cs.sweeps;
+                    c->info.residual[st][0] = cs.residual;
+                    c->info.flux_rank[st][0] = cs.maxrank;
+                    S = cross_to_tt(c, F, -1);
+                    F.release(c->s);
+                } else {
+                    std::vector<TT> terms = rhs_terms(c, X, a, eps, st);
+                    std::vector<std::pair<double, const TT *>> w;
+                    if (aw[st] != 0.0) w.push_back({aw[st], &c->U});
+                    w.push_back({bw[st], &X});
+                    for (auto &t : terms) w.push_back({bw[st] * dt, &t});
+                    S = tt_sum(c, w);
+                    for (auto &t : terms) t.release(c->s);
+                }
                 c->info.sum_rank[st] = S.maxrank();
                 round_tt(c, S, eps, true, norms);
                 if (x_owned) X.release(c->s);

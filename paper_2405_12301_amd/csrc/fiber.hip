@@ -35,14 +35,15 @@ inline CoreSet make_coreset(const FiberGeom &g, const double *const *cores, cons
     return cs;
 }
 
-__device__ inline int mode_index(const FiberGeom &g, int mode, int v, int s, int S) {
-    // entry v of mode `mode`: a face index on the flux direction (shifted to cell m - 3 + s)
-    if (S == 6 && mode == g.dir) return ghost_map(v - 3 + s, g.n[mode], g.bc[mode]);
+// Entry v of mode `mode` of a multi-index. On the shifted mode it is a face index m (S = 6,
+// cells m-3 .. m+2) or a cell index i (S = 7, cells i-3 .. i+3); shift slot s gives cell v - 3 + s.
+__device__ inline int mode_index(const FiberGeom &g, int mode, int v, int s, int shift_mode) {
+    if (mode == shift_mode) return ghost_map(v - 3 + s, g.n[mode], g.bc[mode]);
     return v;
 }
 
 __global__ void k_iface(FiberGeom g, CoreSet cs, int side, int count, const int *__restrict__ idx, int S,
-                        double *__restrict__ out) {
+                        int shift_mode, double *__restrict__ out) {
     const int k = g.k;
     const int Rout = side == 0 ? cs.R[k] : cs.R[k + 1];
     const long long tot = (long long)g.ncomp * S * count * Rout;
@@ -57,12 +58,12 @@ __global__ void k_iface(FiberGeom g, CoreSet cs, int side, int count, const int 
     double val;
     if (side == 0) {
         const int *mi = idx + (long long)a * k;
-        const int i0 = mode_index(g, 0, mi[0], s, S);
+        const int i0 = mode_index(g, 0, mi[0], s, shift_mode);
         const double *G0 = cs.c[0] + c * cs.cstride[0];
         if (k == 1) {
             val = G0[(long long)i0 * cs.R[1] + beta];
         } else {  // k == 2
-            const int i1 = mode_index(g, 1, mi[1], s, S);
+            const int i1 = mode_index(g, 1, mi[1], s, shift_mode);
             const double *G1 = cs.c[1] + c * cs.cstride[1];
             double acc = 0.0;
             for (int al = 0; al < cs.R[1]; ++al)
@@ -75,11 +76,11 @@ __global__ void k_iface(FiberGeom g, CoreSet cs, int side, int count, const int 
         const int *mi = idx + (long long)a * len;
         const int last = g.d - 1;
         if (len == 1) {
-            const int j = mode_index(g, last, mi[0], s, S);
+            const int j = mode_index(g, last, mi[0], s, shift_mode);
             const double *G = cs.c[last] + c * cs.cstride[last];
             val = G[(long long)beta * cs.N[last] + j];
         } else {  // k == 0, d == 3
-            const int j1 = mode_index(g, 1, mi[0], s, S), j2 = mode_index(g, 2, mi[1], s, S);
+            const int j1 = mode_index(g, 1, mi[0], s, shift_mode), j2 = mode_index(g, 2, mi[1], s, shift_mode);
             const double *G1 = cs.c[1] + c * cs.cstride[1];
             const double *G2 = cs.c[2] + c * cs.cstride[2];
             double acc = 0.0;
@@ -344,19 +345,179 @@ __global__ __launch_bounds__(256) void k_sample_flux(FiberGeom g, CoreSet fs, in
     if (!ok) atomicOr(flags, kFlagNonPhys);
 }
 
+// ---------------------------------------------------------------------------- stage
+// -(Fhat(+1/2) - Fhat(-1/2)) / h along one direction from the state at cells -3..+3
+// (slots 0..6) of every component. Face +1/2: f^+ from slots 1..5, f^- mirrored from 6..2;
+// face -1/2: f^+ from slots 0..4, f^- mirrored from 5..1.
+template <int ND, typename T>
+__device__ inline bool stage_dir(const T (&v)[ND + 2][7], int dir, T gm1, T alpha, T eps, T inv_h, T *acc) {
+    constexpr int NC = ND + 2;
+    T fp[NC][7], fm[NC][7];
+    bool ok = true;
+#pragma unroll
+    for (int s = 0; s < 7; ++s) {
+        T qv[NC], a[NC], b[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) qv[c] = v[c][s];
+        ok &= split_flux<ND, T>(qv, dir, gm1, alpha, a, b);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) { fp[c][s] = a[c]; fm[c][s] = b[c]; }
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        T fr = weno5<T>(fp[c][1], fp[c][2], fp[c][3], fp[c][4], fp[c][5], eps) +
+               weno5<T>(fm[c][6], fm[c][5], fm[c][4], fm[c][3], fm[c][2], eps);
+        T fl = weno5<T>(fp[c][0], fp[c][1], fp[c][2], fp[c][3], fp[c][4], eps) +
+               weno5<T>(fm[c][5], fm[c][4], fm[c][3], fm[c][2], fm[c][1], eps);
+        acc[c] -= (fr - fl) * inv_h;
+    }
+    return ok;
+}
+
+template <int ND>
+__global__ __launch_bounds__(256) void k_stage(FiberGeom g, int p, int q, StageArgs sa_, double *__restrict__ out,
+                                               long long sa, long long si, long long sb, long long sc,
+                                               int *__restrict__ flags) {
+    constexpr int NC = ND + 2;
+    const int Nk = g.n[g.k];
+    const long long tot = (long long)p * Nk * q;
+    long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (e >= tot) return;
+    const int b = (int)(e % q);
+    const long long r = e / q;
+    const int i = (int)(r % Nk);
+    const int a = (int)(r / Nk);
+    const double gm1 = g.gamma - 1.0;
+    double acc[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc[c] = 0.0;
+    bool ok = true;
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+        double v[NC][7];
+        if (d == g.k) {
+#pragma unroll
+            for (int s = 0; s < 7; ++s) {
+                const int cell = ghost_map(i - 3 + s, Nk, g.bc[g.k]);
+#pragma unroll
+                for (int c = 0; c < NC; ++c) v[c][s] = sa_.W0[(((long long)c * p + a) * Nk + cell) * q + b];
+            }
+        } else {
+            const double *W = sa_.Wd[d];
+#pragma unroll
+            for (int s = 0; s < 7; ++s)
+#pragma unroll
+                for (int c = 0; c < NC; ++c) v[c][s] = W[((((long long)c * 7 + s) * p + a) * Nk + i) * q + b];
+        }
+        ok &= stage_dir<ND, double>(v, d, gm1, g.alpha, sa_.eps_w[d], sa_.inv_h[d], acc);
+    }
+    bool finite = true;
+    double *o = out + a * sa + i * si + b * sb;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        const long long idx = (((long long)c * p + a) * Nk + i) * q + b;
+        double y = sa_.wx * sa_.W0[idx] + sa_.wl * acc[c];
+        if (sa_.wn != 0.0) y += sa_.wn * sa_.WN[idx];
+        finite &= (y == y) && fabs(y) < 1e300;
+        o[c * sc] = y;
+    }
+    if (!ok) atomicOr(flags, kFlagNonPhys);
+    if (!finite) atomicOr(flags, kFlagNaN);
+}
+
+// X at the 7 d star cells (slot d * 7 + s) of every point; cs2 (Un) at slot 7 d when given.
+template <int ND>
+__global__ void k_sample_star(FiberGeom g, CoreSet cs, CoreSet un, int use_un, int npts, const int *__restrict__ pts,
+                              double *__restrict__ ust) {
+    constexpr int NC = ND + 2;
+    constexpr int SL = 7 * ND + 1;
+    long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (e >= (long long)npts * SL * NC) return;
+    const int c = (int)(e % NC);
+    const int slot = (int)((e / NC) % SL);
+    const int pt = (int)(e / ((long long)NC * SL));
+    int cell[ND];
+#pragma unroll
+    for (int d = 0; d < ND; ++d) cell[d] = pts[pt * ND + d];
+    if (slot == 7 * ND) {
+        ust[e] = use_un ? tt_point<ND>(un, c, cell) : 0.0;
+        return;
+    }
+    const int d = slot / 7, s = slot % 7;
+    cell[d] = ghost_map(cell[d] - 3 + s, g.n[d], g.bc[d]);
+    ust[e] = tt_point<ND>(cs, c, cell);
+}
+
+template <int ND>
+__global__ __launch_bounds__(256) void k_sample_stage(FiberGeom g, CoreSet fs, int npts, const int *__restrict__ pts,
+                                                      const double *__restrict__ ust, double wn, double wx, double wl,
+                                                      StageArgs hs, double *__restrict__ acc, int *__restrict__ flags) {
+    constexpr int NC = ND + 2;
+    constexpr int SL = 7 * ND + 1;
+    __shared__ double red[2][4];
+    const int pt = blockIdx.x * blockDim.x + threadIdx.x;
+    double d2 = 0.0, n2 = 0.0;
+    bool ok = true;
+    if (pt < npts) {
+        const double *u = ust + (long long)pt * SL * NC;
+        double L[NC];
+        for (int c = 0; c < NC; ++c) L[c] = 0.0;
+        for (int d = 0; d < ND; ++d) {
+            double v[NC][7];
+            for (int s = 0; s < 7; ++s)
+                for (int c = 0; c < NC; ++c) v[c][s] = u[(d * 7 + s) * NC + c];
+            ok &= stage_dir<ND, double>(v, d, g.gamma - 1.0, g.alpha, hs.eps_w[d], hs.inv_h[d], L);
+        }
+        const int *m = pts + pt * ND;
+        double approx[NC];
+        for (int c = 0; c < NC; ++c) approx[c] = 0.0;
+        if (ND == 2) {
+            for (int al = 0; al < fs.R[1]; ++al) {
+                double l = fs.c[0][(long long)m[0] * fs.R[1] + al];
+                const double *last = fs.c[1] + ((long long)al * fs.N[1] + m[1]) * NC;
+                for (int c = 0; c < NC; ++c) approx[c] += l * last[c];
+            }
+        } else {
+            for (int be = 0; be < fs.R[2]; ++be) {
+                double v = 0.0;
+                for (int al = 0; al < fs.R[1]; ++al)
+                    v += fs.c[0][(long long)m[0] * fs.R[1] + al] * fs.c[1][((long long)al * fs.N[1] + m[1]) * fs.R[2] + be];
+                const double *last = fs.c[2] + ((long long)be * fs.N[2] + m[2]) * NC;
+                for (int c = 0; c < NC; ++c) approx[c] += v * last[c];
+            }
+        }
+        for (int c = 0; c < NC; ++c) {
+            double ex = wx * u[(0 * 7 + 3) * NC + c] + wl * L[c] + (wn != 0.0 ? wn * u[7 * ND * NC + c] : 0.0);
+            d2 += (ex - approx[c]) * (ex - approx[c]);
+            n2 += ex * ex;
+        }
+    }
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        d2 += __shfl_xor(d2, off, kWave);
+        n2 += __shfl_xor(n2, off, kWave);
+    }
+    if (threadIdx.x % kWave == 0) { red[0][threadIdx.x / kWave] = d2; red[1][threadIdx.x / kWave] = n2; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        acc[2 * blockIdx.x] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+        acc[2 * blockIdx.x + 1] = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+    }
+    if (!ok) atomicOr(flags, kFlagNonPhys);
+}
+
 inline unsigned cdiv(long long a, long long b) { return (unsigned)((a + b - 1) / b); }
 
 }  // namespace
 
 void iface(hipStream_t s, const FiberGeom &g, int side, const double *const *cores, const int *ranks, int count,
-           const int *idx, int S, double *out) {
+           const int *idx, int S, int shift_mode, double *out) {
     int modes[kMaxDim];
     for (int k = 0; k < g.d; ++k) modes[k] = g.n[k];
     CoreSet cs = make_coreset(g, cores, ranks, modes);
     int Rout = side == 0 ? ranks[g.k] : ranks[g.k + 1];
     long long tot = (long long)g.ncomp * S * count * Rout;
     if (tot == 0) return;
-    k_iface<<<cdiv(tot, 256), 256, 0, s>>>(g, cs, side, count, idx, S, out);
+    k_iface<<<cdiv(tot, 256), 256, 0, s>>>(g, cs, side, count, idx, S, shift_mode, out);
     WTT_HIP(hipGetLastError());
 }
 
@@ -392,13 +553,9 @@ void dense_eval(hipStream_t s, int mode, int d, int ncomp, long long nrows, int 
     WTT_HIP(hipGetLastError());
 }
 
-double reduce_max_host(hipStream_t s, const double *partial, int n, double *dscratch) {
-    k_reduce_max<<<1, 1024, 0, s>>>(partial, n, dscratch);
+void reduce_max_dev(hipStream_t s, const double *partial, int n, double *dst) {
+    k_reduce_max<<<1, 1024, 0, s>>>(partial, n, dst);
     WTT_HIP(hipGetLastError());
-    double v = 0.0;
-    WTT_HIP(hipMemcpyAsync(&v, dscratch, sizeof(double), hipMemcpyDeviceToHost, s));
-    WTT_HIP(hipStreamSynchronize(s));
-    return v;
 }
 
 void sample_residual(hipStream_t s, const FiberGeom &g, const double *const *ucores, const int *ranks, int npts,
@@ -424,6 +581,47 @@ void sample_residual(hipStream_t s, const FiberGeom &g, const double *const *uco
     } else {
         k_sample_state<3><<<cdiv(n1, 256), 256, 0, s>>>(g, us, npts, pts, ustencil);
         k_sample_flux<3><<<cdiv(npts, 256), 256, 0, s>>>(g, fs, npts, pts, ustencil, acc, flags);
+    }
+    WTT_HIP(hipGetLastError());
+}
+
+
+void stage_block(hipStream_t s, const FiberGeom &g, int p, int q, const StageArgs &a, double *out, long long sa,
+                 long long si, long long sb, long long sc, int *flags) {
+    long long tot = (long long)p * g.n[g.k] * q;
+    if (tot == 0) return;
+    if (g.d == 2)
+        k_stage<2><<<cdiv(tot, 256), 256, 0, s>>>(g, p, q, a, out, sa, si, sb, sc, flags);
+    else
+        k_stage<3><<<cdiv(tot, 256), 256, 0, s>>>(g, p, q, a, out, sa, si, sb, sc, flags);
+    WTT_HIP(hipGetLastError());
+}
+
+void sample_stage(hipStream_t s, const FiberGeom &g, const double *const *xcores, const int *xranks,
+                  const double *const *ncores, const int *nranks, int npts, const int *pts,
+                  const double *const *fcores, const int *franks, double wn, double wx, double wl,
+                  const double *inv_h, const double *eps_w, double *ust, double *acc, int *flags) {
+    int modes[kMaxDim];
+    for (int k = 0; k < g.d; ++k) modes[k] = g.n[k];
+    CoreSet xs = make_coreset(g, xcores, xranks, modes);
+    CoreSet us = ncores ? make_coreset(g, ncores, nranks, modes) : xs;
+    CoreSet fs{};
+    for (int k = 0; k <= g.d; ++k) fs.R[k] = franks[k];
+    for (int k = 0; k < g.d; ++k) {
+        fs.c[k] = fcores[k];
+        fs.N[k] = modes[k];
+        fs.cstride[k] = 0;
+    }
+    StageArgs hs{};
+    for (int k = 0; k < g.d; ++k) { hs.inv_h[k] = inv_h[k]; hs.eps_w[k] = eps_w[k]; }
+    const int SL = 7 * g.d + 1;
+    long long n1 = (long long)npts * SL * g.ncomp;
+    if (g.d == 2) {
+        k_sample_star<2><<<cdiv(n1, 256), 256, 0, s>>>(g, xs, us, ncores != nullptr, npts, pts, ust);
+        k_sample_stage<2><<<cdiv(npts, 256), 256, 0, s>>>(g, fs, npts, pts, ust, wn, wx, wl, hs, acc, flags);
+    } else {
+        k_sample_star<3><<<cdiv(n1, 256), 256, 0, s>>>(g, xs, us, ncores != nullptr, npts, pts, ust);
+        k_sample_stage<3><<<cdiv(npts, 256), 256, 0, s>>>(g, fs, npts, pts, ust, wn, wx, wl, hs, acc, flags);
     }
     WTT_HIP(hipGetLastError());
 }

@@ -45,6 +45,7 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, double alpha,
     A += z1 * bt.sA1 + z2 * bt.sA2;
     B += z1 * bt.sB1 + z2 * bt.sB2;
     C += z1 * bt.sC1 + z2 * bt.sC2;
+    if (bt.ktot > 0) K = min(K, bt.ktot - z2 * K);  // split-K: chunk z2 of the reduction
     __shared__ double As[BK][BM + 1];
     __shared__ double Bs[BK][BN + 1];
     const int t = threadIdx.x, tx = t % 16, ty = t / 16;
@@ -104,14 +105,15 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, double alpha,
 // Householder QR of one row block [r0, r0 + nr) of matrix z, in a column-major scratch copy.
 __global__ __launch_bounds__(256) void k_hhqr(int m, int n, int bm, int nblk, const double *__restrict__ A,
                                               long long sz, long long rs, long long cs, double *__restrict__ Rout,
-                                              double *__restrict__ scratch) {
+                                              double *__restrict__ scratch, int use_lds) {
+    extern __shared__ double wlds[];
     __shared__ double red[8];
     __shared__ double sh[3];
     const int blk = blockIdx.x, z = blockIdx.y, tid = threadIdx.x;
     const int lane = tid % kWave, w = tid / kWave, nw = blockDim.x / kWave;
     const int r0 = blk * bm;
     const int nr = min(bm, m - r0);
-    double *W = scratch + ((long long)z * nblk + blk) * (long long)bm * n;
+    double *W = use_lds ? wlds : scratch + ((long long)z * nblk + blk) * (long long)bm * n;
     const double *Az = A + (long long)z * sz;
     const long long tot = (long long)nr * n;
     if (cs <= rs) {
@@ -171,6 +173,19 @@ __global__ __launch_bounds__(256) void k_hhqr(int m, int n, int bm, int nblk, co
     }
 }
 
+__global__ void k_sum_chunks(long long per, int nchunk, int batch, const double *__restrict__ part, double *__restrict__ C,
+                             int M, int N, int ldc, long long sC) {
+    long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (e >= per * batch) return;
+    const int z = (int)(e / per);
+    const long long r = e % per;
+    const int i = (int)(r / N), j = (int)(r % N);
+    double acc = 0.0;
+    for (int k = 0; k < nchunk; ++k) acc += part[((long long)z * nchunk + k) * per + r];
+    C[z * sC + (long long)i * ldc + j] = acc;
+    (void)M;
+}
+
 __global__ void k_copy(long long n, const double *__restrict__ src, double *__restrict__ dst) {
     long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (i < n) dst[i] = src[i];
@@ -191,32 +206,31 @@ int leaf_rows(int n) {
 }
 
 // ---------------------------------------------------------------------- Jacobi SVD
-__global__ __launch_bounds__(1024) void k_jacobi(int n, const double *__restrict__ Ain, double *__restrict__ sigma,
-                                                 double *__restrict__ Vout, double *__restrict__ scratch) {
-    extern __shared__ int smem[];
-    const int z = blockIdx.x, tid = threadIdx.x, lane = tid % kWave, w = tid / kWave, nw = blockDim.x / kWave;
-    const int np = n + (n & 1);  // padded to even; the pad column is zero
-    int *top = smem, *bot = smem + np / 2, *tmp = smem + np;
-    __shared__ int nrot;
-    double *A = scratch + (long long)z * 2 * n * n;  // column-major A[j*n + i]
-    double *V = A + (long long)n * n;
-    const double *Az = Ain + (long long)z * n * n;
-    for (long long e = tid; e < (long long)n * n; e += blockDim.x) {
-        int i = (int)(e / n), j = (int)(e % n);
-        A[(long long)j * n + i] = Az[e];
-        V[(long long)j * n + i] = (i == j) ? 1.0 : 0.0;
-    }
-    for (int k = tid; k < np / 2; k += blockDim.x) { top[k] = 2 * k; bot[k] = 2 * k + 1; }
-    __syncthreads();
+// One-sided (Hestenes) Jacobi on the columns of an n x n matrix. Column pairs follow the
+// round-robin "circle" schedule: with np = n rounded up to even, round r pairs player np-1
+// with r and (r + k) mod (np-1) with (r - k) mod (np-1) for k = 1 .. np/2 - 1; np - 1 rounds
+// meet every pair once. A padded column (odd n) is never rotated.
+__device__ inline void circle_pair(int r, int k, int np, int *p, int *q) {
+    int a, b;
+    if (k == 0) { a = np - 1; b = r; }
+    else { a = (r + k) % (np - 1); b = (r - k + (np - 1)) % (np - 1); }
+    *p = a < b ? a : b;
+    *q = a < b ? b : a;
+}
+
+// A and V are column-major (column j at j * n); they live in LDS (fast path) or global memory.
+__device__ void jacobi_sweeps(int n, double *A, double *V, int *nrot) {
+    const int tid = threadIdx.x, lane = tid % kWave, w = tid / kWave, nw = blockDim.x / kWave;
+    const int np = n + (n & 1);
     const double tol = 1e-15;
-    for (int sweep = 0; sweep < 40; ++sweep) {
-        if (tid == 0) nrot = 0;
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        if (tid == 0) *nrot = 0;
         __syncthreads();
-        for (int round = 0; round < np - 1; ++round) {
+        for (int r = 0; r < np - 1; ++r) {
             for (int k = w; k < np / 2; k += nw) {
-                int p = top[k], q = bot[k];
-                if (p > q) { int t = p; p = q; q = t; }
-                if (q >= n) continue;  // pad column
+                int p, q;
+                circle_pair(r, k, np, &p, &q);
+                if (q >= n) continue;
                 double *ap = A + (long long)p * n, *aq = A + (long long)q * n;
                 double a = 0.0, b = 0.0, c = 0.0;
                 for (int i = lane; i < n; i += kWave) {
@@ -239,53 +253,76 @@ __global__ __launch_bounds__(1024) void k_jacobi(int n, const double *__restrict
                     vp[i] = cs * x - sn * y;
                     vq[i] = sn * x + cs * y;
                 }
-                if (lane == 0) atomicAdd(&nrot, 1);
-            }
-            __syncthreads();
-            // round-robin rotation of the tournament (all pairs met in np - 1 rounds)
-            if (tid == 0) {
-                int h = np / 2;
-                for (int k = 0; k < h; ++k) tmp[k] = top[k];
-                for (int k = 0; k < h; ++k) tmp[h + k] = bot[k];
-                top[0] = tmp[0];
-                if (h > 1) top[1] = tmp[h];
-                for (int k = 2; k < h; ++k) top[k] = tmp[k - 1];
-                for (int k = 0; k < h - 1; ++k) bot[k] = tmp[h + k + 1];
-                bot[h - 1] = tmp[h - 1];
-                if (h == 1) { top[0] = tmp[0]; bot[0] = tmp[1]; }
+                if (lane == 0) atomicAdd(nrot, 1);
             }
             __syncthreads();
         }
+        const int done = *nrot == 0;
         __syncthreads();
-        if (nrot == 0) break;
-        __syncthreads();
+        if (done) break;
     }
 }
 
-// Norms after convergence, written into the pad-free arrays (separate kernel keeps it simple).
-__global__ void k_colnorm(int n, int batch, const double *__restrict__ scratch, double *__restrict__ sig) {
-    int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n * batch) return;
-    int z = e / n, j = e % n;
-    const double *A = scratch + (long long)z * 2 * n * n + (long long)j * n;
-    double s = 0.0;
-    for (int i = 0; i < n; ++i) s += A[i] * A[i];
-    sig[e] = sqrt(s);
+// Singular values (column norms), descending order by rank counting; writes sigma, V (row-major,
+// column = singular vector) and, if US != null, A V = U Sigma (row-major).
+__device__ void jacobi_finish(int n, const double *A, const double *V, double *sig_tmp, double *sigma,
+                              double *Vout, double *US) {
+    const int tid = threadIdx.x, lane = tid % kWave, w = tid / kWave, nw = blockDim.x / kWave;
+    for (int j = w; j < n; j += nw) {
+        double s = 0.0;
+        for (int i = lane; i < n; i += kWave) s += A[(long long)j * n + i] * A[(long long)j * n + i];
+        s = wave_sum(s);
+        if (lane == 0) sig_tmp[j] = sqrt(s);
+    }
+    __syncthreads();
+    for (int j = tid; j < n; j += blockDim.x) {
+        double sj = sig_tmp[j];
+        int pos = 0;
+        for (int i = 0; i < n; ++i) pos += (sig_tmp[i] > sj) || (sig_tmp[i] == sj && i < j);
+        sigma[pos] = sj;
+        for (int i = 0; i < n; ++i) Vout[(long long)i * n + pos] = V[(long long)j * n + i];
+        if (US)
+            for (int i = 0; i < n; ++i) US[(long long)i * n + pos] = A[(long long)j * n + i];
+    }
 }
 
-__global__ void k_sort_sv(int n, int batch, const double *__restrict__ sig_unsorted, const double *__restrict__ scratch,
-                          double *__restrict__ sigma, double *__restrict__ Vout) {
-    int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n * batch) return;
-    int z = e / n, j = e % n;
-    const double *s = sig_unsorted + (long long)z * n;
-    double sj = s[j];
-    int pos = 0;
-    for (int i = 0; i < n; ++i) pos += (s[i] > sj) || (s[i] == sj && i < j);
-    sigma[(long long)z * n + pos] = sj;
-    const double *V = scratch + (long long)z * 2 * n * n + (long long)n * n + (long long)j * n;
-    double *Vz = Vout + (long long)z * n * n;
-    for (int i = 0; i < n; ++i) Vz[(long long)i * n + pos] = V[i];
+__global__ __launch_bounds__(1024) void k_jacobi_lds(int n, const double *__restrict__ Ain, double *__restrict__ sigma,
+                                                     double *__restrict__ Vout, double *__restrict__ US) {
+    extern __shared__ double sm[];
+    __shared__ int nrot;
+    __shared__ double sig_tmp[512];
+    const int z = blockIdx.x, tid = threadIdx.x;
+    double *A = sm, *V = sm + (long long)n * n;
+    const double *Az = Ain + (long long)z * n * n;
+    for (int e = tid; e < n * n; e += blockDim.x) {
+        int i = e / n, j = e % n;
+        A[j * n + i] = Az[e];
+        V[j * n + i] = (i == j) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    jacobi_sweeps(n, A, V, &nrot);
+    jacobi_finish(n, A, V, sig_tmp, sigma + (long long)z * n, Vout + (long long)z * n * n,
+                  US ? US + (long long)z * n * n : nullptr);
+}
+
+__global__ __launch_bounds__(1024) void k_jacobi_global(int n, const double *__restrict__ Ain,
+                                                        double *__restrict__ sigma, double *__restrict__ Vout,
+                                                        double *__restrict__ US, double *__restrict__ scratch) {
+    __shared__ int nrot;
+    const int z = blockIdx.x, tid = threadIdx.x;
+    double *A = scratch + (long long)z * (2 * (long long)n * n + n);
+    double *V = A + (long long)n * n;
+    double *sig_tmp = V + (long long)n * n;
+    const double *Az = Ain + (long long)z * n * n;
+    for (long long e = tid; e < (long long)n * n; e += blockDim.x) {
+        int i = (int)(e / n), j = (int)(e % n);
+        A[(long long)j * n + i] = Az[e];
+        V[(long long)j * n + i] = (i == j) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    jacobi_sweeps(n, A, V, &nrot);
+    jacobi_finish(n, A, V, sig_tmp, sigma + (long long)z * n, Vout + (long long)z * n * n,
+                  US ? US + (long long)z * n * n : nullptr);
 }
 
 // ------------------------------------------------------------------- prrLU (pivots)
@@ -380,6 +417,108 @@ __global__ __launch_bounds__(1024) void k_prrlu(int m, int n, double *__restrict
         for (int i = tid; i < m; i += blockDim.x) L[(long long)i * rmax] = (i == 0) ? 1.0 : 0.0;
 }
 
+// Register-resident variant for blocks of at most 1024 * E entries: every thread keeps its
+// entries (linear index tid + 1024 l) in registers and walks their (row, column) pairs
+// incrementally; per pivot only the pivot row and column go through LDS. Two barriers per
+// pivot: after the wave partials (every thread then reduces the 16 partials itself) and after
+// the pivot row/column are published.
+template <int E>
+__global__ __launch_bounds__(1024) void k_prrlu_reg(int m, int n, const double *__restrict__ A, int rmax,
+                                                    double rel_tol2, int *__restrict__ rowpiv, int *__restrict__ colpiv,
+                                                    double *__restrict__ L, double *__restrict__ info) {
+    extern __shared__ double sm[];
+    double *colv = sm, *rowv = sm + m;
+    __shared__ double wmax[16], wsum[16];
+    __shared__ int widx[16];
+    __shared__ int s_zero;
+    const int tid = threadIdx.x, lane = tid % kWave, w = tid / kWave, nw = blockDim.x / kWave;
+    const int tot = m * n;
+    const int di = 1024 / n, dj = 1024 % n;
+    if (tid == 0) s_zero = 0;
+    double a[E];
+#pragma unroll
+    for (int l = 0; l < E; ++l) {
+        const int e = tid + 1024 * l;
+        a[l] = e < tot ? A[e] : 0.0;
+    }
+    __syncthreads();  // s_zero is visible to every thread from here on
+    double tol2 = 0.0, bs = 0.0;
+    int t = 0, stop = 0;
+    for (;; ++t) {
+        double lmax = -1.0, lsum = 0.0;
+        int lidx = 0x7fffffff;
+        const int base0 = tid + s_zero;
+#pragma unroll
+        for (int l = 0; l < E; ++l) {
+            const int e = base0 + 1024 * l;
+            const double av = fabs(a[l]);
+            lsum += a[l] * a[l];
+            if (e < tot && av > lmax) { lmax = av; lidx = e; }
+        }
+        for (int off = kWave / 2; off > 0; off >>= 1) {
+            double om = __shfl_xor(lmax, off, kWave);
+            int oi = __shfl_xor(lidx, off, kWave);
+            double os = __shfl_xor(lsum, off, kWave);
+            if (om > lmax || (om == lmax && oi < lidx)) { lmax = om; lidx = oi; }
+            lsum += os;
+        }
+        if (lane == 0) { wmax[w] = lmax; widx[w] = lidx; wsum[w] = lsum; }
+        __syncthreads();  // barrier A
+        double bm = wmax[0];
+        int bi = widx[0];
+        bs = 0.0;
+        for (int k = 0; k < nw; ++k) {
+            bs += wsum[k];
+            if (wmax[k] > bm || (wmax[k] == bm && widx[k] < bi)) { bm = wmax[k]; bi = widx[k]; }
+        }
+        if (t == 0) tol2 = rel_tol2 * bs;
+        stop = (t >= rmax) || (bm <= 0.0) || (bs <= tol2);
+        if (t == 0 && bm <= 0.0) stop = 2;
+        if (t == 0 && stop == 1) stop = 0;
+        if (stop) break;
+        const int pi = bi / n, pj = bi % n;
+        {  // owners publish the pivot row and column
+            const int base = tid + s_zero;
+            int ri = base / n, cj = base % n;
+#pragma unroll
+            for (int l = 0; l < E; ++l) {
+                if (base + 1024 * l < tot) {
+                    if (ri == pi) rowv[cj] = a[l];
+                    if (cj == pj) colv[ri] = a[l];
+                }
+                ri += di; cj += dj;
+                if (cj >= n) { cj -= n; ++ri; }
+            }
+        }
+        __syncthreads();  // barrier B
+        const double inv = 1.0 / rowv[pj];
+        if (tid == 0) { rowpiv[t] = pi; colpiv[t] = pj; }
+        {
+            const int base = tid + s_zero;
+            int ri = base / n, cj = base % n;
+#pragma unroll
+            for (int l = 0; l < E; ++l) {
+                if (base + 1024 * l < tot)
+                    a[l] = (ri == pi || cj == pj) ? 0.0 : a[l] - colv[ri] * inv * rowv[cj];
+                ri += di; cj += dj;
+                if (cj >= n) { cj -= n; ++ri; }
+            }
+        }
+        for (int i = tid; i < m; i += blockDim.x) L[(long long)i * rmax + t] = (i == pi) ? 1.0 : colv[i] * inv;
+    }
+    if (tid == 0) {
+        int rank = t;
+        if (stop == 2) {
+            rank = 1;
+            rowpiv[0] = 0; colpiv[0] = 0;
+        }
+        info[0] = (double)rank;
+        info[1] = bs;
+    }
+    if (stop == 2)
+        for (int i = tid; i < m; i += blockDim.x) L[(long long)i * rmax] = (i == 0) ? 1.0 : 0.0;
+}
+
 // Row i of X solves x L_I = L[i, :r] with L_I = L[rowpiv, :r] unit lower triangular in pivot
 // order (entry (s, t) is zero for t > s and one for t = s: the pivot rows were eliminated).
 __global__ void k_interp(int m, int r, const double *__restrict__ L, int ldl, const int *__restrict__ rowpiv,
@@ -400,6 +539,51 @@ __global__ void k_interp_exact_rows(int r, const int *__restrict__ rowpiv, doubl
     if (e >= r * r) return;
     int s = e / r, t = e % r;
     X[(long long)rowpiv[s] * r + t] = (s == t) ? 1.0 : 0.0;
+}
+
+// ---------------------------------------------------------------- CholeskyQR helper
+// X = R^{-1} with G = R^T R (upper Cholesky factor) of a nearly orthonormal basis's Gram
+// matrix, one workgroup per matrix. A column whose squared norm is below 1/2 is a padding
+// zero column: it keeps a unit diagonal and no coupling, so it stays zero after U X.
+__global__ __launch_bounds__(256) void k_chol_inv(int r, const double *__restrict__ Gin, double *__restrict__ Xout,
+                                                  double *__restrict__ Rws) {
+    const int z = blockIdx.x, tid = threadIdx.x;
+    const double *G = Gin + (long long)z * r * r;
+    double *R = Rws + (long long)z * r * r;
+    double *X = Xout + (long long)z * r * r;
+    __shared__ double diag;
+    __shared__ int zero_col;
+    for (int e = tid; e < r * r; e += blockDim.x) R[e] = 0.0;
+    __syncthreads();
+    for (int j = 0; j < r; ++j) {
+        if (tid == 0) {
+            double dd = G[(long long)j * r + j];
+            for (int k = 0; k < j; ++k) dd -= R[(long long)k * r + j] * R[(long long)k * r + j];
+            zero_col = !(dd > 0.5);
+            diag = zero_col ? 1.0 : sqrt(dd);
+            R[(long long)j * r + j] = diag;
+        }
+        __syncthreads();
+        for (int i = j + 1 + tid; i < r; i += blockDim.x) {
+            double v = 0.0;
+            if (!zero_col) {
+                v = G[(long long)j * r + i];
+                for (int k = 0; k < j; ++k) v -= R[(long long)k * r + j] * R[(long long)k * r + i];
+                v /= diag;
+            }
+            R[(long long)j * r + i] = v;
+        }
+        __syncthreads();
+    }
+    // inverse of the upper-triangular R, one column per thread (back substitution)
+    for (int i = tid; i < r; i += blockDim.x) {
+        for (int j = r - 1; j >= 0; --j) X[(long long)j * r + i] = 0.0;
+        for (int j = i; j >= 0; --j) {
+            double v = (j == i) ? 1.0 : 0.0;
+            for (int k = j + 1; k <= i; ++k) v -= R[(long long)j * r + k] * X[(long long)k * r + i];
+            X[(long long)j * r + i] = v / R[(long long)j * r + j];
+        }
+    }
 }
 
 inline unsigned cdiv(long long a, long long b) { return (unsigned)((a + b - 1) / b); }
@@ -446,7 +630,10 @@ void tsqr_r(hipStream_t s, int m, int n, int batch, const double *A, long long s
     }
     double *R0 = W + (long long)batch * wsize;
     double *R1 = R0 + (long long)batch * nblk * n * n;
-    k_hhqr<<<dim3(nblk, batch), 256, 0, s>>>(m, n, bm, nblk, A, sz, rs, cs, R0, W);
+    const size_t lds_budget = 64 * 1024;
+    size_t lb = sizeof(double) * (size_t)bm * n;
+    k_hhqr<<<dim3(nblk, batch), 256, lb <= lds_budget ? lb : 0, s>>>(m, n, bm, nblk, A, sz, rs, cs, R0, W,
+                                                                       lb <= lds_budget);
     WTT_HIP(hipGetLastError());
     double *cur = R0, *nxt = R1;
     while (nblk > 1) {
@@ -454,7 +641,9 @@ void tsqr_r(hipStream_t s, int m, int n, int batch, const double *A, long long s
         int group = std::max(2, bm / n);
         int nb2 = (nblk + group - 1) / group;
         int bm2 = group * n;
-        k_hhqr<<<dim3(nb2, batch), 256, 0, s>>>(mm, n, bm2, nb2, cur, (long long)nblk * n * n, n, 1, nxt, W);
+        size_t lb2 = sizeof(double) * (size_t)bm2 * n;
+        k_hhqr<<<dim3(nb2, batch), 256, lb2 <= lds_budget ? lb2 : 0, s>>>(mm, n, bm2, nb2, cur, (long long)nblk * n * n,
+                                                                          n, 1, nxt, W, lb2 <= lds_budget);
         WTT_HIP(hipGetLastError());
         std::swap(cur, nxt);
         nblk = nb2;
@@ -464,20 +653,38 @@ void tsqr_r(hipStream_t s, int m, int n, int batch, const double *A, long long s
     WTT_HIP(hipGetLastError());
 }
 
-void jacobi_svd(hipStream_t s, int n, int batch, const double *A, double *sigma, double *V, double *scratch) {
-    int np = n + (n & 1);
-    size_t lds = sizeof(int) * (size_t)(2 * np);
-    k_jacobi<<<batch, 1024, lds, s>>>(n, A, sigma, V, scratch);
-    WTT_HIP(hipGetLastError());
-    // sigma unsorted into the V output area's first row? use a dedicated temp at the end of scratch
-    double *sig_tmp = scratch + (long long)batch * 2 * n * n;  // caller provides 2*b*n*n + b*n
-    k_colnorm<<<cdiv((long long)n * batch, 256), 256, 0, s>>>(n, batch, scratch, sig_tmp);
-    k_sort_sv<<<cdiv((long long)n * batch, 256), 256, 0, s>>>(n, batch, sig_tmp, scratch, sigma, V);
+int lds_limit_bytes() {
+    static int lim = -1;
+    if (lim < 0) {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+            v = 65536;
+        lim = v;
+    }
+    return lim;
+}
+
+void jacobi_svd(hipStream_t s, int n, int batch, const double *A, double *sigma, double *V, double *scratch,
+                double *US) {
+    // static LDS of the kernel: the column-norm buffer (512 doubles) and a counter
+    size_t lds = sizeof(double) * 2 * (size_t)n * n;
+    if (n <= 512 && lds + 512 * sizeof(double) + 64 <= (size_t)lds_limit_bytes())
+        k_jacobi_lds<<<batch, 1024, lds, s>>>(n, A, sigma, V, US);
+    else
+        k_jacobi_global<<<batch, 1024, 0, s>>>(n, A, sigma, V, US, scratch);
     WTT_HIP(hipGetLastError());
 }
 
 void prrlu(hipStream_t s, int m, int n, double *A, int rmax, double rel_tol2, int *rowpiv, int *colpiv, double *L,
            double *info, double *rowbuf) {
+    const long long tot = (long long)m * n;
+    const size_t lds_rc = sizeof(double) * (size_t)(m + n);
+    if (m < 32768 && n < 32768 && lds_rc <= 48 * 1024) {
+        if (tot <= 1024 * 8) { k_prrlu_reg<8><<<1, 1024, lds_rc, s>>>(m, n, A, rmax, rel_tol2, rowpiv, colpiv, L, info); WTT_HIP(hipGetLastError()); return; }
+        if (tot <= 1024 * 16) { k_prrlu_reg<16><<<1, 1024, lds_rc, s>>>(m, n, A, rmax, rel_tol2, rowpiv, colpiv, L, info); WTT_HIP(hipGetLastError()); return; }
+        if (tot <= 1024 * 32) { k_prrlu_reg<32><<<1, 1024, lds_rc, s>>>(m, n, A, rmax, rel_tol2, rowpiv, colpiv, L, info); WTT_HIP(hipGetLastError()); return; }
+    }
     int use_lds = n <= 4096;
     size_t lds = use_lds ? sizeof(double) * (size_t)n : 0;
     k_prrlu<<<1, 1024, lds, s>>>(m, n, A, rmax, rel_tol2, rowpiv, colpiv, L, info, rowbuf, use_lds);
@@ -488,6 +695,37 @@ void interp_solve(hipStream_t s, int m, int r, const double *L, int ldl, const i
     k_interp<<<cdiv(m, 256), 256, 0, s>>>(m, r, L, ldl, rowpiv, X);
     k_interp_exact_rows<<<cdiv((long long)r * r, 256), 256, 0, s>>>(r, rowpiv, X);
     WTT_HIP(hipGetLastError());
+}
+
+void chol_upper_inv(hipStream_t s, int r, int batch, const double *G, double *X, double *ws) {
+    k_chol_inv<<<batch, 256, 0, s>>>(r, G, X, ws);
+    WTT_HIP(hipGetLastError());
+}
+
+void gemm_tn_splitk(hipStream_t s, int M, int N, int K, const double *A, int lda, const double *B, int ldb, double *C,
+                    int ldc, int batch, long long sA, long long sB, long long sC, double *part, size_t part_cap) {
+    const int chunk = 64;
+    const int nchunk = (K + chunk - 1) / chunk;
+    const long long per = (long long)M * N;
+    if (nchunk <= 1 || (size_t)per * nchunk * batch > part_cap) {
+        GemmBatch bt;
+        bt.nb1 = batch; bt.sA1 = sA; bt.sB1 = sB; bt.sC1 = sC;
+        gemm_f64(s, true, false, M, N, K, 1.0, A, lda, B, ldb, 0.0, C, ldc, bt);
+        return;
+    }
+    GemmBatch bt;
+    bt.nb1 = batch; bt.nb2 = nchunk;
+    bt.sA1 = sA; bt.sA2 = (long long)chunk * lda;
+    bt.sB1 = sB; bt.sB2 = (long long)chunk * ldb;
+    bt.sC1 = per * nchunk; bt.sC2 = per;
+    bt.ktot = K;
+    gemm_f64(s, true, false, M, N, chunk, 1.0, A, lda, B, ldb, 0.0, part, N, bt);
+    k_sum_chunks<<<cdiv(per * batch, 256), 256, 0, s>>>(per, nchunk, batch, part, C, M, N, ldc, sC);
+    WTT_HIP(hipGetLastError());
+}
+
+size_t gemm_tn_splitk_part(int M, int N, int K, int batch) {
+    return (size_t)M * N * ((K + 63) / 64) * batch;
 }
 
 }  // namespace wtt

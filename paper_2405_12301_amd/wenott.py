@@ -39,7 +39,7 @@ class wenott_opts(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("max_sweeps", ctypes.c_int32), ("kick_rank", ctypes.c_int32),
                 ("rank_cap", ctypes.c_int32), ("probe_points", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("alpha_mode", ctypes.c_int32), ("use_proposal", ctypes.c_int32), ("alpha_given", ctypes.c_double),
-                ("rounds_per_stage", ctypes.c_int32), ("graph_mode", ctypes.c_int32)]
+                ("rounds_per_stage", ctypes.c_int32), ("graph_mode", ctypes.c_int32), ("scheme", ctypes.c_int32)]
 
 
 class wenott_info(ctypes.Structure):
@@ -48,7 +48,9 @@ class wenott_info(ctypes.Structure):
                 ("max_norm", ctypes.c_double), ("sweeps", (ctypes.c_int32 * 3) * 3),
                 ("residual", (ctypes.c_double * 3) * 3), ("flux_rank", (ctypes.c_int64 * 3) * 3),
                 ("sum_rank", ctypes.c_int64 * 3), ("fiber_points", ctypes.c_int64), ("fiber_ms", ctypes.c_double),
-                ("fiber_launches", ctypes.c_int64), ("step_ms", ctypes.c_double)]
+                ("fiber_launches", ctypes.c_int64), ("step_ms", ctypes.c_double),
+                ("class_ms", ctypes.c_double * 4), ("class_launches", ctypes.c_int64 * 4),
+                ("class_flops", ctypes.c_double * 4), ("class_bytes", ctypes.c_double * 4)]
 
 
 _lib = None
