@@ -39,6 +39,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-dense", action="store_true")
+    ap.add_argument("--workload", default="quadrants2d", choices=["quadrants2d", "wave3d", "sod3d"],
+                    help="quadrants2d is the contract workload; the others are side measurements")
+    ap.add_argument("--precision", type=int, default=0, help="0 FP64 fiber path, 1 FP32 fiber path")
     return ap.parse_args()
 
 
@@ -83,10 +86,23 @@ def main():
     W.load()
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    flow = workloads.config2_quadrants_2d(args.n, seed=args.seed)
-    cells = args.n * args.n
+    if args.workload == "quadrants2d":
+        flow = workloads.config2_quadrants_2d(args.n, seed=args.seed)
+        opts = W.default_opts(eps_mode=1, eps0=flow.eps0, precision=args.precision)
+        wl = (f"four-quadrant Riemann problem 2D {args.n}x{args.n}, transmissive, seed {args.seed}, "
+              f"dynamic eps_TT from 1e-8, CFL 0.5")
+    elif args.workload == "wave3d":
+        flow = workloads.config3_wave_3d(args.n, seed=args.seed)
+        opts = W.default_opts(eps_mode=0, eps0=flow.eps0, precision=args.precision)
+        wl = f"3D smooth density wave {args.n}^3 with 8 Fourier modes, periodic, eps_TT 1e-6 fixed, CFL 0.5"
+    else:
+        flow = workloads.sod_1d_like(3, args.n)
+        opts = W.default_opts(eps_mode=0, eps0=1e-6, precision=args.precision)
+        wl = f"3D Sod shock tube {args.n}^3 (axis-aligned, rank 1), transmissive, eps_TT 1e-6, CFL 0.5"
+    cells = 1
+    for m in flow.n:
+        cells *= m
     h = min(flow.h)
-    opts = W.default_opts(eps_mode=1, eps0=flow.eps0)
     solver = W.Solver(flow, opts)
     W.wenott_set_profiling(solver.ctx, True)
 
@@ -176,15 +192,14 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.precision == 0 else "f32 fiber / f64 rounding",
         "data": "synthetic",
-        "config": {"workload": f"four-quadrant Riemann problem 2D {args.n}x{args.n}, transmissive, seed {args.seed}, "
-                               f"dynamic eps_TT from 1e-8, CFL 0.5",
+        "config": {"workload": wl,
                    "t_sim_end": t_sim, "ranks": ranks, "eps_tt": eps_now},
         "roofline": roofline,
         "dense_gpu_weno5": dense,
     }
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.workload == "quadrants2d":
         out["cpu_baseline"] = cpu_baseline(flow, args.cpu_seconds)
     print(json.dumps(out))
 

@@ -111,18 +111,28 @@ void iface(hipStream_t s, const FiberGeom &g, int side, const double *const *cor
 
 // Fused stage kernel: Y = wn Un + wx X + wl L(X) at the block points (a, i, b) of core k,
 // L(X) = -sum_d (Fhat_d(+1/2) - Fhat_d(-1/2)) / h_d from the seven cells around each point in
-// every direction. X stencil values: W0[c][a][cell][b] over the N_k cells of mode k (the
-// neighbours along mode k) and, for every direction d != k, Wd[d][c][s][a][i][b] (s = 0..6 for
-// cells -3..+3). Un values WN[c][a][i][b] (read only when wn != 0). Output as weno_block.
-struct StageArgs {
-    const double *W0;
-    const double *Wd[kMaxDim];
+// every direction, computed in T (FP64, or FP32 for the reduced-precision path). X stencil
+// values: W0[c][a][cell][b] over the N_k cells of mode k (the neighbours along mode k) and,
+// for every direction d != k, Wd[d][c][s][a][i][b] (s = 0..6 for cells -3..+3). The pass-through
+// terms use FP64 values: X0[c][a][i][b] (X itself) and WN (Un, read only when wn != 0).
+template <typename T>
+struct StageArgsT {
+    const T *W0;
+    const T *Wd[kMaxDim];
+    const double *X0;
     const double *WN;
     double wn, wx, wl;
     double inv_h[kMaxDim], eps_w[kMaxDim];
 };
-void stage_block(hipStream_t s, const FiberGeom &g, int p, int q, const StageArgs &a, double *out, long long sa,
+template <typename T>
+void stage_block(hipStream_t s, const FiberGeom &g, int p, int q, const StageArgsT<T> &a, double *out, long long sa,
                  long long si, long long sb, long long sc, int *flags);
+
+// FP32 batched GEMM C = A B (row-major) on the matrix cores (v_mfma_f32_16x16x4f32).
+void gemm_f32(hipStream_t s, int M, int N, int K, const float *A, int lda, const float *B, int ldb, float *C, int ldc,
+              const GemmBatch &bt = GemmBatch());
+void to_f32(hipStream_t s, long long n, const double *x, float *y);
+
 // Exact stage value at random cells and the sampled residual of a TT of it: X at the 7 d
 // star cells (slot d*7 + s), Un at the point, TT approximation (shared cores + last core with
 // one slice per component).

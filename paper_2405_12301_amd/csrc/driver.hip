@@ -51,7 +51,8 @@ inline void dfree(hipStream_t s, void *p) {
 enum Slot {
     S_P, S_Q, S_T, S_W, S_BLOCK, S_L, S_X, S_PIV, S_INFO, S_ROWBUF, S_TSQR, S_R, S_SIG, S_V, S_JAC, S_W1, S_W2,
     S_RANKS, S_PART, S_DSCAL, S_UST, S_ACC, S_LM, S_NORMS, S_DELTA, S_TMP, S_DENSE,
-    S_PD0, S_PD1, S_QD0, S_QD1, S_TD0, S_TD1, S_WD0, S_WD1, S_PN, S_QN, S_TN, S_WN, S_SPLIT, S_NSLOTS
+    S_PD0, S_PD1, S_QD0, S_QD1, S_TD0, S_TD1, S_WD0, S_WD1, S_PN, S_QN, S_TN, S_WN, S_SPLIT,
+    S_F_G, S_F_P, S_F_Q, S_F_T, S_F_W0, S_F_WD0, S_F_WD1, S_NSLOTS
 };
 
 struct Scratch {
@@ -609,25 +610,76 @@ void eval_stage_block(wenott_ctx *c, const TT &X, const TT *Un, StageWeights w, 
         gemm_f64(s, false, false, p * Nk, q, Rk1, 1.0, T, Rk1, Q, q, 0.0, W, q, b2);
         return W;
     };
-    StageArgs a{};
+    // FP32 gather: interface matrices formed in FP64 and rounded, the block contractions
+    // P G_k Q in FP32 on the matrix cores.
+    auto gather32 = [&](const TT &Y, int shift, int slotW) -> float * {
+        const int Rk = Y.R[k], Rk1 = Y.R[k + 1];
+        int ranks[kMaxDim + 1];
+        for (int j = 0; j <= d; ++j) ranks[j] = Y.R[j];
+        const double *cores[kMaxDim];
+        for (int j = 0; j < d; ++j) cores[j] = Y.core[j];
+        const int SL = (shift >= 0 && shift < k) ? 7 : 1, SR = (shift > k) ? 7 : 1, S = std::max(SL, SR);
+        double *P = c->sc.get<double>(S_P, (size_t)nc * SL * p * Rk);
+        if (k == 0) fill(s, P, (long long)nc * SL * p * Rk, 1.0);
+        else iface(s, g, 0, cores, ranks, p, didxL, SL, SL == 7 ? shift : -1, P);
+        double *Q = c->sc.get<double>(S_Q, (size_t)nc * SR * Rk1 * q);
+        if (k == d - 1) fill(s, Q, (long long)nc * SR * Rk1 * q, 1.0);
+        else iface(s, g, 1, cores, ranks, q, didxR, SR, SR == 7 ? shift : -1, Q);
+        float *P32 = c->sc.get<float>(S_F_P, (size_t)nc * SL * p * Rk);
+        float *Q32 = c->sc.get<float>(S_F_Q, (size_t)nc * SR * Rk1 * q);
+        float *G32 = c->sc.get<float>(S_F_G, (size_t)Y.cstride(k) * nc);
+        to_f32(s, (long long)nc * SL * p * Rk, P, P32);
+        to_f32(s, (long long)nc * SR * Rk1 * q, Q, Q32);
+        to_f32(s, Y.cstride(k) * nc, Y.core[k], G32);
+        const long long tsz = (long long)p * Nk * Rk1;
+        float *T = c->sc.get<float>(S_F_T, (size_t)nc * SL * tsz);
+        GemmBatch b1;
+        b1.nb1 = nc; b1.nb2 = SL;
+        b1.sA1 = (long long)SL * p * Rk; b1.sA2 = (long long)p * Rk;
+        b1.sB1 = Y.cstride(k); b1.sB2 = 0;
+        b1.sC1 = SL * tsz; b1.sC2 = tsz;
+        gemm_f32(s, p, Nk * Rk1, Rk, P32, Rk, G32, Nk * Rk1, T, Nk * Rk1, b1);
+        const long long wsz = (long long)p * Nk * q;
+        float *W = c->sc.get<float>(slotW, (size_t)nc * S * wsz);
+        GemmBatch b2;
+        b2.nb1 = nc; b2.nb2 = S;
+        b2.sA1 = SL * tsz; b2.sA2 = SL == 7 ? tsz : 0;
+        b2.sB1 = (long long)SR * Rk1 * q; b2.sB2 = SR == 7 ? (long long)Rk1 * q : 0;
+        b2.sC1 = S * wsz; b2.sC2 = wsz;
+        gemm_f32(s, p * Nk, q, Rk1, T, Rk1, Q32, q, W, q, b2);
+        return W;
+    };
+    StageArgsT<double> a{};
+    StageArgsT<float> a32{};
+    const bool fp32 = c->o.precision == 1;
     a.W0 = gather(X, -1, S_P, S_Q, S_T, S_W);
+    a.X0 = a.W0;
+    if (fp32) {
+        a32.W0 = gather32(X, -1, S_F_W0);
+        a32.X0 = a.W0;
+    }
     int od = 0;
     for (int dd = 0; dd < d; ++dd) {
-        a.inv_h[dd] = 1.0 / c->h[dd];
-        a.eps_w[dd] = c->h[dd] * c->h[dd];
+        a.inv_h[dd] = a32.inv_h[dd] = 1.0 / c->h[dd];
+        a.eps_w[dd] = a32.eps_w[dd] = c->h[dd] * c->h[dd];
         if (dd == k) continue;
-        a.Wd[dd] = gather(X, dd, od == 0 ? S_PD0 : S_PD1, od == 0 ? S_QD0 : S_QD1, od == 0 ? S_TD0 : S_TD1,
-                          od == 0 ? S_WD0 : S_WD1);
+        if (fp32)
+            a32.Wd[dd] = gather32(X, dd, od == 0 ? S_F_WD0 : S_F_WD1);
+        else
+            a.Wd[dd] = gather(X, dd, od == 0 ? S_PD0 : S_PD1, od == 0 ? S_QD0 : S_QD1, od == 0 ? S_TD0 : S_TD1,
+                              od == 0 ? S_WD0 : S_WD1);
         ++od;
     }
     a.WN = nullptr;
     if (Un && w.wn != 0.0) a.WN = gather(*Un, -1, S_PN, S_QN, S_TN, S_WN);
-    a.wn = w.wn; a.wx = w.wx; a.wl = w.wl;
+    a.wn = a32.wn = w.wn; a.wx = a32.wx = w.wx; a.wl = a32.wl = w.wl;
+    a32.WN = a.WN;
     long long sa, si, sb, sc;
     if (lr) { sa = (long long)Nk * q * nc; si = (long long)q * nc; sb = nc; sc = 1; }
     else { sa = nc; si = (long long)q * p * nc; sb = (long long)p * nc; sc = 1; }
     ev_record(c, KC_FIBER);
-    stage_block(s, g, p, q, a, out, sa, si, sb, sc, c->d_flags);
+    if (fp32) stage_block<float>(s, g, p, q, a32, out, sa, si, sb, sc, c->d_flags);
+    else stage_block<double>(s, g, p, q, a, out, sa, si, sb, sc, c->d_flags);
     ev_record(c, KC_FIBER);
     c->info.fiber_points += (long long)p * Nk * q;
     c->info.fiber_launches += 1;
@@ -677,6 +729,10 @@ double sampled_stage_residual(wenott_ctx *c, const TT &X, const TT *Un, StageWei
 
 FluxTT cross_stage(wenott_ctx *c, const TT &X, const TT *Un, StageWeights w, double alpha, double eps,
                    CrossStat &st) {
+    // FP32 flux evaluation: the face-flux differences (Fhat(+1/2) - Fhat(-1/2)) / h cancel, so
+    // the dt L part of the stage value carries relative noise up to ~1e-6 of the stage value;
+    // the cross tolerance is floored there (pivots chasing FP32 noise would run to the cap).
+    if (c->o.precision == 1) eps = std::max(eps, 1e-6);
     CrossTarget t;
     t.d = X.d;
     t.nc = X.nc;
@@ -1045,6 +1101,7 @@ wenott_status wenott_init(wenott_ctx **out, const wenott_tt *state, const wenott
         WTT_REQUIRE(c->o.max_sweeps >= 1 && c->o.rank_cap >= 1 && c->o.kick_rank >= 0, WENOTT_EINVAL, "bad options");
         WTT_REQUIRE(c->o.eps_mode == 0 || c->o.eps_mode == 1, WENOTT_EINVAL, "eps_mode must be 0 or 1");
         WTT_REQUIRE(c->o.scheme == 0 || c->o.scheme == 1, WENOTT_EINVAL, "scheme must be 0 or 1");
+        WTT_REQUIRE(c->o.precision == 0 || c->o.scheme == 0, WENOTT_EINVAL, "the FP32 path runs in scheme 0");
         for (int k = 0; k < d; ++k) {
             WTT_REQUIRE(grid->n[k] >= 3 && grid->n[k] <= (1 << 20), WENOTT_EINVAL, "grid size out of range");
             WTT_REQUIRE(grid->hi[k] > grid->lo[k], WENOTT_EINVAL, "empty box");

@@ -374,8 +374,8 @@ __device__ inline bool stage_dir(const T (&v)[ND + 2][7], int dir, T gm1, T alph
     return ok;
 }
 
-template <int ND>
-__global__ __launch_bounds__(256) void k_stage(FiberGeom g, int p, int q, StageArgs sa_, double *__restrict__ out,
+template <int ND, typename T>
+__global__ __launch_bounds__(256) void k_stage(FiberGeom g, int p, int q, StageArgsT<T> sa_, double *__restrict__ out,
                                                long long sa, long long si, long long sb, long long sc,
                                                int *__restrict__ flags) {
     constexpr int NC = ND + 2;
@@ -387,14 +387,14 @@ __global__ __launch_bounds__(256) void k_stage(FiberGeom g, int p, int q, StageA
     const long long r = e / q;
     const int i = (int)(r % Nk);
     const int a = (int)(r / Nk);
-    const double gm1 = g.gamma - 1.0;
-    double acc[NC];
+    const T gm1 = T(g.gamma - 1.0), alpha = T(g.alpha);
+    T acc[NC];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) acc[c] = 0.0;
+    for (int c = 0; c < NC; ++c) acc[c] = T(0);
     bool ok = true;
 #pragma unroll
     for (int d = 0; d < ND; ++d) {
-        double v[NC][7];
+        T v[NC][7];
         if (d == g.k) {
 #pragma unroll
             for (int s = 0; s < 7; ++s) {
@@ -403,20 +403,20 @@ __global__ __launch_bounds__(256) void k_stage(FiberGeom g, int p, int q, StageA
                 for (int c = 0; c < NC; ++c) v[c][s] = sa_.W0[(((long long)c * p + a) * Nk + cell) * q + b];
             }
         } else {
-            const double *W = sa_.Wd[d];
+            const T *W = sa_.Wd[d];
 #pragma unroll
             for (int s = 0; s < 7; ++s)
 #pragma unroll
                 for (int c = 0; c < NC; ++c) v[c][s] = W[((((long long)c * 7 + s) * p + a) * Nk + i) * q + b];
         }
-        ok &= stage_dir<ND, double>(v, d, gm1, g.alpha, sa_.eps_w[d], sa_.inv_h[d], acc);
+        ok &= stage_dir<ND, T>(v, d, gm1, alpha, T(sa_.eps_w[d]), T(sa_.inv_h[d]), acc);
     }
     bool finite = true;
     double *o = out + a * sa + i * si + b * sb;
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
         const long long idx = (((long long)c * p + a) * Nk + i) * q + b;
-        double y = sa_.wx * sa_.W0[idx] + sa_.wl * acc[c];
+        double y = sa_.wx * sa_.X0[idx] + sa_.wl * (double)acc[c];
         if (sa_.wn != 0.0) y += sa_.wn * sa_.WN[idx];
         finite &= (y == y) && fabs(y) < 1e300;
         o[c * sc] = y;
@@ -451,7 +451,7 @@ __global__ void k_sample_star(FiberGeom g, CoreSet cs, CoreSet un, int use_un, i
 template <int ND>
 __global__ __launch_bounds__(256) void k_sample_stage(FiberGeom g, CoreSet fs, int npts, const int *__restrict__ pts,
                                                       const double *__restrict__ ust, double wn, double wx, double wl,
-                                                      StageArgs hs, double *__restrict__ acc, int *__restrict__ flags) {
+                                                      StageArgsT<double> hs, double *__restrict__ acc, int *__restrict__ flags) {
     constexpr int NC = ND + 2;
     constexpr int SL = 7 * ND + 1;
     __shared__ double red[2][4];
@@ -586,16 +586,21 @@ void sample_residual(hipStream_t s, const FiberGeom &g, const double *const *uco
 }
 
 
-void stage_block(hipStream_t s, const FiberGeom &g, int p, int q, const StageArgs &a, double *out, long long sa,
+template <typename T>
+void stage_block(hipStream_t s, const FiberGeom &g, int p, int q, const StageArgsT<T> &a, double *out, long long sa,
                  long long si, long long sb, long long sc, int *flags) {
     long long tot = (long long)p * g.n[g.k] * q;
     if (tot == 0) return;
     if (g.d == 2)
-        k_stage<2><<<cdiv(tot, 256), 256, 0, s>>>(g, p, q, a, out, sa, si, sb, sc, flags);
+        k_stage<2, T><<<cdiv(tot, 256), 256, 0, s>>>(g, p, q, a, out, sa, si, sb, sc, flags);
     else
-        k_stage<3><<<cdiv(tot, 256), 256, 0, s>>>(g, p, q, a, out, sa, si, sb, sc, flags);
+        k_stage<3, T><<<cdiv(tot, 256), 256, 0, s>>>(g, p, q, a, out, sa, si, sb, sc, flags);
     WTT_HIP(hipGetLastError());
 }
+template void stage_block<double>(hipStream_t, const FiberGeom &, int, int, const StageArgsT<double> &, double *,
+                                  long long, long long, long long, long long, int *);
+template void stage_block<float>(hipStream_t, const FiberGeom &, int, int, const StageArgsT<float> &, double *,
+                                 long long, long long, long long, long long, int *);
 
 void sample_stage(hipStream_t s, const FiberGeom &g, const double *const *xcores, const int *xranks,
                   const double *const *ncores, const int *nranks, int npts, const int *pts,
@@ -612,7 +617,7 @@ void sample_stage(hipStream_t s, const FiberGeom &g, const double *const *xcores
         fs.N[k] = modes[k];
         fs.cstride[k] = 0;
     }
-    StageArgs hs{};
+    StageArgsT<double> hs{};
     for (int k = 0; k < g.d; ++k) { hs.inv_h[k] = inv_h[k]; hs.eps_w[k] = eps_w[k]; }
     const int SL = 7 * g.d + 1;
     long long n1 = (long long)npts * SL * g.ncomp;

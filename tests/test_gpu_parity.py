@@ -221,3 +221,35 @@ def test_sod_stays_rank_one_and_matches(W, scheme):
         assert rel_err(s.dense(), u) <= 1e-7
     finally:
         s.close()
+
+
+@pytest.mark.parametrize("case", ["wave3d", "quadrants"])
+def test_fp32_fiber_path_error(W, case):
+    """Reduced-precision path: gathers on the FP32 matrix cores and FP32 LF + WENO5 in the
+    fiber kernel; pivots, rounding and the error estimator in FP64. The error against the FP64
+    oracle is reported and bounded by 10 eps_cross + 1e-7 per step."""
+    _say("case: FP32 fiber path,", case)
+    if case == "wave3d":
+        f = workloads.config3_wave_3d(24, seed=0, modes=8)
+        eps = 1e-6
+    else:
+        f = workloads.config2_quadrants_2d(64, seed=2)
+        eps = 1e-8
+    res = {}
+    for prec in (0, 1):
+        s = W.Solver(f, W.default_opts(eps0=eps, precision=prec))
+        try:
+            P = oracle_problem(f)
+            u = s.dense()
+            dt = 0.5 * min(P.h) / P.alpha(u)
+            s.step(dt)
+            info = s.info()
+            P.ssprk3(u, dt, alphas=[info.alpha[i] for i in range(3)])
+            got = s.dense()
+            res[prec] = (rel_err(got, u), got, list(info.ranks))
+        finally:
+            s.close()
+    e64, e32 = res[0][0], res[1][0]
+    d = rel_err(res[1][1], res[0][1])
+    _say(f"  FP64 path err {e64:.3e}  FP32 path err {e32:.3e}  FP32 vs FP64 path {d:.3e}  ranks {res[0][2]} {res[1][2]}")
+    assert e32 <= 10 * max(eps, 1e-6)
