@@ -84,7 +84,7 @@ typedef struct {
     int32_t probe_points; /* random points of the sampled cross residual [4096] */
     uint64_t seed;      /* seed of the library's own counter-based generator [12345] */
     int32_t alpha_mode; /* 0 exact max(|u|+a) over the grid, 2 use alpha_given [0] */
-    int32_t use_proposal; /* reserved, must be 0 [0] */
+    int32_t use_proposal; /* 1: seed stage crosses from the learned proposal (wenott_set_proposal) [0] */
     double alpha_given; /* the Lax-Friedrichs alpha when alpha_mode = 2 */
     int32_t rounds_per_stage; /* 1 = one rounding per SSP-RK3 stage [1] */
     int32_t graph_mode; /* reserved, must be 0 [0] */
@@ -118,6 +118,9 @@ typedef struct {
     int64_t class_launches[4];
     double class_flops[4];
     double class_bytes[4];
+    /* learned proposal: stage crosses seeded by it and those whose first sweep was accepted */
+    int64_t proposals_tried, proposals_accepted;
+    int64_t pivots_total;    /* rank-revealing LU pivots taken in the last call */
 } wenott_info;
 
 /* Fill *o with the defaults. */
@@ -189,6 +192,48 @@ const char *wenott_last_error(wenott_ctx *ctx);
 
 void wenott_destroy(wenott_ctx *ctx);
 const char *wenott_strerror(wenott_status s);
+
+/* ------------------------------------------------------------------------------------
+ * Learned cross proposal (an addition to the paper's method). A 3-layer MLP
+ * IN -> HID -> HID -> OUT (ReLU) maps per-bond features of the previous stage cross (the
+ * histogram of the right indices its pivots used, the normalised singular-value tail of the
+ * last rounding, ranks, sweeps, residual, eps, CFL, stage) to logits of the rank change
+ * (RANK_CLASSES, change -8..+8) and of where the next right index set should sample
+ * (BINS bins along the bond's first right mode). A proposal seeds the first sweep of the
+ * stage cross; it is accepted only if that sweep's sampled residual is <= eps, otherwise the
+ * plain cross continues from it. Parameters are one FP32 device array (W1[IN][HID], b1, W2,
+ * b2, W3[HID][OUT], b3). Inference inside the library rounds weights and activations to
+ * BF16 and accumulates in FP32. Training: loss = cross-entropy of the rank class +
+ * cross-entropy of the bin distribution against the target histogram, batch mean.
+ * ---------------------------------------------------------------------------------- */
+#define WENOTT_MLP_IN 96
+#define WENOTT_MLP_HID 128
+#define WENOTT_MLP_OUT 81
+#define WENOTT_MLP_RANK_CLASSES 17
+#define WENOTT_MLP_BINS 64
+
+int64_t wenott_mlp_nparams(void);
+/* floats of device workspace for a batch (forward and loss_grad) */
+int64_t wenott_mlp_workspace(int32_t batch);
+/* He-normal weights, zero biases, from a counter-based generator. params: device. */
+wenott_status wenott_mlp_init_params(float *params, uint64_t seed, void *hip_stream);
+/* y[batch][OUT] = MLP(x[batch][IN]); all device; bf16 != 0 rounds operands to BF16. */
+wenott_status wenott_mlp_forward(const float *params, const float *x, int32_t batch, float *y, int32_t bf16,
+                                 float *work, void *hip_stream);
+/* grad[nparams] and loss (device scalar) of a batch; rank_class[batch] in 0..16, hist[batch][BINS]. */
+wenott_status wenott_mlp_loss_grad(const float *params, const float *x, const int32_t *rank_class, const float *hist,
+                                   int32_t batch, float *grad, float *loss, float *work, void *hip_stream);
+/* one Adam step (beta 0.9 / 0.999, eps 1e-8) at step t >= 1 with learning rate lr; m, v: device state. */
+wenott_status wenott_mlp_adam_step(float *params, const float *grad, float *m, float *v, int32_t t, float lr,
+                                   void *hip_stream);
+/* Use (params != NULL, device, kept by the caller) or stop using the learned proposal. */
+wenott_status wenott_set_proposal(wenott_ctx *ctx, const float *params);
+/* Record one (features, rank class, bin histogram) sample per bond of every stage cross. */
+wenott_status wenott_set_cross_logging(wenott_ctx *ctx, int32_t on);
+/* Copy up to max logged samples to host arrays x[max][IN], rank_class[max], hist[max][BINS];
+ * *n receives the count; the log is cleared. */
+wenott_status wenott_get_cross_log(wenott_ctx *ctx, float *x, int32_t *rank_class, float *hist, int32_t max,
+                                   int32_t *n);
 
 /* ------------------------------------------------------------------------------------
  * Dense comparator: the same FP64 scheme on the full grid (the paper's "full-tensor"

@@ -52,7 +52,7 @@ enum Slot {
     S_P, S_Q, S_T, S_W, S_BLOCK, S_L, S_X, S_PIV, S_INFO, S_ROWBUF, S_TSQR, S_R, S_SIG, S_V, S_JAC, S_W1, S_W2,
     S_RANKS, S_PART, S_DSCAL, S_UST, S_ACC, S_LM, S_NORMS, S_DELTA, S_TMP, S_DENSE,
     S_PD0, S_PD1, S_QD0, S_QD1, S_TD0, S_TD1, S_WD0, S_WD1, S_PN, S_QN, S_TN, S_WN, S_SPLIT,
-    S_F_G, S_F_P, S_F_Q, S_F_T, S_F_W0, S_F_WD0, S_F_WD1, S_NSLOTS
+    S_F_G, S_F_P, S_F_Q, S_F_T, S_F_W0, S_F_WD0, S_F_WD1, S_MLPY, S_MLPW, S_NSLOTS
 };
 
 struct Scratch {
@@ -186,6 +186,22 @@ struct wenott_ctx {
     int ev_used = 0;
     wenott_info info{};
     std::string last_error;
+    // learned proposal and pivot logs of stage crosses (one history per TT bond)
+    struct BondHist {
+        bool valid = false;
+        int rank = 0;
+        float hist[WENOTT_MLP_BINS] = {};
+        float sig[16] = {};
+        std::vector<int> useful;  // right multi-indices whose columns were pivots (len d-1-k each)
+    };
+    BondHist bond[kMaxDim];
+    float last_sig[16] = {};
+    int prev_sweeps = 1;
+    double prev_resid = 0.0;
+    const float *proposal = nullptr;
+    bool logging = false;
+    std::vector<float> log_x, log_hist;
+    std::vector<int> log_cls;
 };
 
 namespace {
@@ -376,7 +392,7 @@ ISet with_kick(const ISet &base, Rng &rng, int kick, int first_mode, const int *
 
 struct PivotResult {
     int rank;
-    std::vector<int> rows;
+    std::vector<int> rows, cols;
 };
 
 PivotResult pivots(wenott_ctx *c, double *B, int m, int n, double rel_tol2, double **Lout) {
@@ -389,10 +405,12 @@ PivotResult pivots(wenott_ctx *c, double *B, int m, int n, double rel_tol2, doub
     prrlu(c->s, m, n, B, rmax, rel_tol2, piv, piv + rmax, L, info, rowbuf);
     ev_record(c, KC_PIVOT);
     WTT_HIP(hipMemcpyAsync(c->h_pinned_dbl, info, 2 * sizeof(double), hipMemcpyDeviceToHost, c->s));
-    WTT_HIP(hipMemcpyAsync(c->h_pinned_int, piv, rmax * sizeof(int), hipMemcpyDeviceToHost, c->s));
+    WTT_HIP(hipMemcpyAsync(c->h_pinned_int, piv, 2 * rmax * sizeof(int), hipMemcpyDeviceToHost, c->s));
     WTT_HIP(hipStreamSynchronize(c->s));
     PivotResult r;
     r.rank = (int)c->h_pinned_dbl[0];
+    r.cols.assign(c->h_pinned_int + rmax, c->h_pinned_int + rmax + r.rank);
+    c->info.pivots_total += r.rank;
     {  // full-pivot elimination to rank r: sum_t 2 (m - t)(n - t) flops; the block is read once, L written
         double fl = 0.0;
         for (int t = 0; t < r.rank; ++t) fl += 2.0 * (double)(m - t) * (double)(n - t);
@@ -440,6 +458,123 @@ struct CrossStat {
     int maxrank = 0;
 };
 
+// ------------------------------------------------------------- learned proposal hooks
+// Per-bond features of the proposal (see include/wenott.h): the previous cross's useful-right-
+// index histogram, the last rounding's singular-value tail, log rank, eps, CFL, sweeps,
+// residual, stage and dimension.
+std::vector<float> proposal_features(wenott_ctx *c, int d, double eps, double lambda, int stage) {
+    const int IN = WENOTT_MLP_IN, NB = WENOTT_MLP_BINS;
+    std::vector<float> x((size_t)(d - 1) * IN, 0.f);
+    for (int k = 0; k < d - 1; ++k) {
+        float *f = x.data() + (size_t)k * IN;
+        const auto &b = c->bond[k];
+        for (int j = 0; j < NB; ++j) f[j] = b.hist[j];
+        for (int j = 0; j < 16; ++j) f[NB + j] = b.sig[j];
+        f[80] = (float)(std::log2((double)b.rank + 1.0) / 8.0);
+        f[81] = (float)(std::log10(eps) / 16.0 + 1.0);
+        f[82] = (float)lambda;
+        f[83] = (float)(c->prev_sweeps / 4.0);
+        f[84] = (float)(std::min(4.0, std::max(-4.0, std::log10(std::max(c->prev_resid, 1e-300) / eps))) / 4.0);
+        if (stage >= 0 && stage < 3) f[85 + stage] = 1.f;
+        f[88] = (float)(d - 2);
+    }
+    return x;
+}
+
+// Right index sets from the proposal: the previous useful multi-indices, then new ones whose
+// first mode is drawn from the predicted bin distribution, up to the predicted rank + 2.
+void apply_proposal(wenott_ctx *c, int d, const int *M, const std::vector<float> &x, std::vector<ISet> &Rset,
+                    Rng &rng) {
+    const int IN = WENOTT_MLP_IN, OUT = WENOTT_MLP_OUT, NR = WENOTT_MLP_RANK_CLASSES, NB = WENOTT_MLP_BINS;
+    const int nb = d - 1;
+    const float *dx = c->ring.put(x.data(), x.size());
+    float *y = c->sc.get<float>(S_MLPY, (size_t)nb * OUT);
+    float *work = c->sc.get<float>(S_MLPW, (size_t)wenott_mlp_workspace(nb));
+    WTT_REQUIRE(wenott_mlp_forward(c->proposal, dx, nb, y, 1, work, c->s) == WENOTT_OK, WENOTT_EHIP,
+                "proposal forward failed");
+    std::vector<float> hy((size_t)nb * OUT);
+    WTT_HIP(hipMemcpyAsync(hy.data(), y, hy.size() * sizeof(float), hipMemcpyDeviceToHost, c->s));
+    WTT_HIP(hipStreamSynchronize(c->s));
+    for (int k = 0; k < nb; ++k) {
+        const float *yk = hy.data() + (size_t)k * OUT;
+        int cls = 0;
+        for (int j = 1; j < NR; ++j)
+            if (yk[j] > yk[cls]) cls = j;
+        const auto &b = c->bond[k];
+        const int rhat = std::max(1, b.rank + cls - NR / 2);
+        const int want = rhat + 2;
+        const int len = d - 1 - k;
+        ISet s;
+        s.len = len;
+        const int nuse = std::min<int>((int)b.useful.size() / len, want);
+        s.v.assign(b.useful.begin(), b.useful.begin() + (size_t)nuse * len);
+        s.count = nuse;
+        // bin distribution
+        float mx = yk[NR];
+        for (int j = 1; j < NB; ++j) mx = std::max(mx, yk[NR + j]);
+        std::vector<double> p(NB);
+        double tot = 0.0;
+        for (int j = 0; j < NB; ++j) tot += (p[j] = std::exp((double)yk[NR + j] - mx));
+        while (s.count < want) {
+            double u = (rng.next() >> 11) * (1.0 / 9007199254740992.0) * tot, acc = 0.0;
+            int bin = NB - 1;
+            for (int j = 0; j < NB; ++j) {
+                acc += p[j];
+                if (u < acc) { bin = j; break; }
+            }
+            const int m = M[k + 1];
+            const int lo = (int)((long long)bin * m / NB), hi = std::max(lo + 1, (int)((long long)(bin + 1) * m / NB));
+            s.v.push_back(std::min(m - 1, lo + rng.below(hi - lo)));
+            for (int j = 1; j < len; ++j) {
+                if (nuse > 0) s.v.push_back(b.useful[(size_t)rng.below(nuse) * len + j]);
+                else s.v.push_back(rng.below(M[k + 1 + j]));
+            }
+            ++s.count;
+        }
+        Rset[k] = std::move(s);
+    }
+}
+
+// After a stage cross: log (features, rank class, useful-index histogram) and update the bond
+// histories. usedR[k] is the right set of core k in the accepted sweep, usedC[k] its pivot columns.
+void learn_update(wenott_ctx *c, int d, int nc, const int *M, const FluxTT &F, const std::vector<ISet> &usedR,
+                  const std::vector<std::vector<int>> &usedC, const std::vector<float> &feats, bool have_feats,
+                  int sweeps, double resid) {
+    const int IN = WENOTT_MLP_IN, NB = WENOTT_MLP_BINS, NR = WENOTT_MLP_RANK_CLASSES;
+    for (int k = 0; k < d - 1; ++k) {
+        auto &b = c->bond[k];
+        const ISet &R = usedR[k];
+        float hist[WENOTT_MLP_BINS] = {};
+        std::vector<int> useful;
+        std::vector<char> seen(R.count, 0);
+        for (int col : usedC[k]) {
+            const int bi = col / nc;
+            if (bi < 0 || bi >= R.count || seen[bi]) continue;
+            seen[bi] = 1;
+            const int pos = R.v[(size_t)bi * R.len];
+            hist[std::min(NB - 1, (int)((long long)pos * NB / M[k + 1]))] += 1.f;
+            useful.insert(useful.end(), R.v.begin() + (size_t)bi * R.len, R.v.begin() + (size_t)(bi + 1) * R.len);
+        }
+        float tot = 0.f;
+        for (float h : hist) tot += h;
+        if (tot > 0.f)
+            for (float &h : hist) h /= tot;
+        const int rnew = F.R[k + 1];
+        if (c->logging && have_feats && b.valid) {
+            const int cls = std::min(NR - 1, std::max(0, rnew - b.rank + NR / 2));
+            c->log_x.insert(c->log_x.end(), feats.begin() + (size_t)k * IN, feats.begin() + (size_t)(k + 1) * IN);
+            c->log_cls.push_back(cls);
+            c->log_hist.insert(c->log_hist.end(), hist, hist + NB);
+        }
+        b.valid = true;
+        b.rank = rnew;
+        std::memcpy(b.hist, hist, sizeof(hist));
+        b.useful = std::move(useful);
+    }
+    c->prev_sweeps = sweeps;
+    c->prev_resid = resid;
+}
+
 // A cross target: mode sizes, a block evaluator and the sampled residual of a candidate TT.
 struct CrossTarget {
     int d = 0, nc = 0, q0 = 2;
@@ -447,6 +582,9 @@ struct CrossTarget {
     std::function<void(int k, const ISet &L, const ISet &R, bool lr, double *out)> eval;
     std::function<double(const FluxTT &F, Rng &rng)> residual;
     int warm_slot = 0;
+    bool learn = false;  // stage cross: keep bond histories, log samples, use the proposal
+    double lambda = 0.0;
+    int stage = -1;
 };
 
 // Rank-adaptive cross (Sec. 3.3): left-to-right sweeps build interpolative cores
@@ -475,6 +613,18 @@ FluxTT cross_generic(wenott_ctx *c, const CrossTarget &t, double eps, CrossStat 
     const int kick = c->o.kick_rank;
     double resid = 1e300;
     int sweep = 0;
+    bool have_feats = t.learn;
+    for (int k = 0; k < d - 1; ++k) have_feats = have_feats && c->bond[k].valid;
+    std::vector<float> feats;
+    if (have_feats) feats = proposal_features(c, d, eps, t.lambda, t.stage);
+    bool proposed = false;
+    if (have_feats && c->proposal && c->o.use_proposal) {
+        apply_proposal(c, d, M, feats, Rset, rng);
+        proposed = true;
+        c->info.proposals_tried += 1;
+    }
+    std::vector<ISet> usedR(d);
+    std::vector<std::vector<int>> usedC(d);
     for (; sweep < c->o.max_sweeps; ++sweep) {
         F.release(c->s);
         Lset[0].len = 0;
@@ -483,7 +633,8 @@ FluxTT cross_generic(wenott_ctx *c, const CrossTarget &t, double eps, CrossStat 
         F.R[0] = 1;
         F.R[d] = 1;
         for (int k = 0; k < d; ++k) {
-            ISet Rk = k < d - 1 ? with_kick(Rset[k], rng, kick, k + 1, M) : Rset[k];
+            const int kick_now = (proposed && sweep == 0) ? 0 : kick;  // the proposal replaces the random kick
+            ISet Rk = k < d - 1 ? with_kick(Rset[k], rng, kick_now, k + 1, M) : Rset[k];
             const int p = Lset[k].count, q = Rk.count;
             const long long rows = (long long)p * M[k], cols = (long long)q * nc;
             double *B = c->sc.get<double>(S_BLOCK, (size_t)(rows * cols));
@@ -491,6 +642,10 @@ FluxTT cross_generic(wenott_ctx *c, const CrossTarget &t, double eps, CrossStat 
             if (k < d - 1) {
                 double *L = nullptr;
                 PivotResult pr = pivots(c, B, (int)rows, (int)cols, rel2, &L);
+                if (t.learn) {
+                    usedR[k] = Rk;
+                    usedC[k] = pr.cols;
+                }
                 const int r = pr.rank;
                 int rmax = std::min(std::min(c->o.rank_cap, kMaxRankLds), (int)std::min(rows, cols));
                 F.core[k] = dalloc<double>(c->s, (size_t)rows * r);
@@ -541,6 +696,8 @@ FluxTT cross_generic(wenott_ctx *c, const CrossTarget &t, double eps, CrossStat 
     c->warm_valid[t.warm_slot] = true;
     st.sweeps = sweep;
     st.residual = resid;
+    if (proposed && sweep == 1 && resid <= eps) c->info.proposals_accepted += 1;
+    if (t.learn) learn_update(c, d, nc, M, F, usedR, usedC, feats, have_feats, sweep, resid);
     if (!(resid <= 1e3 * eps) && !(resid <= 1e-12))
         throw StatusError(WENOTT_ENOCONV, "cross did not converge");
     return F;
@@ -743,6 +900,11 @@ FluxTT cross_stage(wenott_ctx *c, const TT &X, const TT *Un, StageWeights w, dou
     };
     t.residual = [&](const FluxTT &F, Rng &rng) { return sampled_stage_residual(c, X, Un, w, alpha, F, rng); };
     t.warm_slot = kMaxDim;
+    t.learn = w.wx != 0.0;  // stage crosses of rk3_step
+    double hmin = c->h[0];
+    for (int j = 1; j < X.d; ++j) hmin = std::min(hmin, c->h[j]);
+    t.lambda = w.wx != 0.0 ? w.wl / w.wx * alpha / hmin : 0.0;
+    t.stage = w.wx == 0.0 ? -1 : (w.wn == 0.0 ? 0 : (w.wn > 0.5 ? 1 : 2));
     return cross_generic(c, t, eps, st);
 }
 
@@ -828,9 +990,21 @@ int svd_ranks(wenott_ctx *c, int m, int n, const double *A, long long sz, long l
     *rk = c->sc.get<int>(S_RANKS, nc);
     trunc_ranks(c->s, n, nc, *sig, delta_abs, rel, rcap, *rk);
     WTT_HIP(hipMemcpyAsync(c->h_pinned_int, *rk, nc * sizeof(int), hipMemcpyDeviceToHost, c->s));
+    const bool tail = (size_t)nc * n <= 3000;
+    if (tail) WTT_HIP(hipMemcpyAsync(c->h_pinned_dbl + 1024, *sig, (size_t)nc * n * sizeof(double), hipMemcpyDeviceToHost, c->s));
     WTT_HIP(hipStreamSynchronize(c->s));
     int r = 1;
     for (int z = 0; z < nc; ++z) r = std::max(r, c->h_pinned_int[z]);
+    // normalised log singular-value tail (largest over components), a feature of the proposal
+    for (int j = 0; j < 16; ++j) {
+        double v = 0.0;
+        if (tail && j < n)
+            for (int z = 0; z < nc; ++z) {
+                const double *sg = c->h_pinned_dbl + 1024 + (size_t)z * n;
+                if (sg[0] > 0.0) v = std::max(v, 1.0 + std::log10(std::max(sg[j] / sg[0], 1e-16)) / 16.0);
+            }
+        c->last_sig[j] = (float)v;
+    }
     return r;
 }
 
@@ -897,6 +1071,7 @@ void round_tt(wenott_ctx *c, TT &X, double eps, bool truncate, std::vector<doubl
         double *sig, *V;
         int *rk;
         int r = svd_ranks(c, m, n, C, (long long)m * n, n, 1, ddelta, 0.0, c->o.rank_cap, &sig, &V, &rk);
+        std::memcpy(c->bond[k].sig, c->last_sig, sizeof(c->last_sig));
         double *W1 = c->sc.get<double>(S_W1, (size_t)nc * n * r);
         double *W2 = c->sc.get<double>(S_W2, (size_t)nc * n * r);
         build_projectors(s, n, nc, r, sig, V, rk, W1, W2);
@@ -985,6 +1160,9 @@ std::vector<TT> rhs_terms(wenott_ctx *c, const TT &U, double alpha, double eps, 
 }
 
 void reset_call_info(wenott_ctx *c) {
+    c->info.proposals_tried = 0;
+    c->info.proposals_accepted = 0;
+    c->info.pivots_total = 0;
     c->info.fiber_points = 0;
     c->info.fiber_launches = 0;
     c->info.fiber_ms = 0.0;
@@ -1096,7 +1274,8 @@ wenott_status wenott_init(wenott_ctx **out, const wenott_tt *state, const wenott
         c->nc = d + 2;
         c->gamma = gamma;
         if (opts) c->o = *opts; else wenott_default_opts(&c->o);
-        WTT_REQUIRE(c->o.use_proposal == 0 && c->o.graph_mode == 0, WENOTT_ENOTBUILT, "option not available");
+        WTT_REQUIRE(c->o.graph_mode == 0, WENOTT_ENOTBUILT, "option not available");
+        WTT_REQUIRE(c->o.use_proposal == 0 || c->o.use_proposal == 1, WENOTT_EINVAL, "use_proposal must be 0 or 1");
         WTT_REQUIRE(c->o.precision == 0 || c->o.precision == 1, WENOTT_EINVAL, "precision must be 0 or 1");
         WTT_REQUIRE(c->o.max_sweeps >= 1 && c->o.rank_cap >= 1 && c->o.kick_rank >= 0, WENOTT_EINVAL, "bad options");
         WTT_REQUIRE(c->o.eps_mode == 0 || c->o.eps_mode == 1, WENOTT_EINVAL, "eps_mode must be 0 or 1");
@@ -1360,6 +1539,31 @@ wenott_status wenott_current_eps(wenott_ctx *c, double *eps) {
 wenott_status wenott_set_profiling(wenott_ctx *c, int32_t on) {
     if (!c) return WENOTT_EINVAL;
     c->profiling = on != 0;
+    return WENOTT_OK;
+}
+
+wenott_status wenott_set_proposal(wenott_ctx *c, const float *params) {
+    if (!c) return WENOTT_EINVAL;
+    c->proposal = params;
+    return WENOTT_OK;
+}
+
+wenott_status wenott_set_cross_logging(wenott_ctx *c, int32_t on) {
+    if (!c) return WENOTT_EINVAL;
+    c->logging = on != 0;
+    return WENOTT_OK;
+}
+
+wenott_status wenott_get_cross_log(wenott_ctx *c, float *x, int32_t *rank_class, float *hist, int32_t max, int32_t *n) {
+    if (!c || !n || max < 0 || (max > 0 && (!x || !rank_class || !hist))) return WENOTT_EINVAL;
+    const int cnt = std::min<int>(max, (int)c->log_cls.size());
+    std::memcpy(x, c->log_x.data(), sizeof(float) * (size_t)cnt * WENOTT_MLP_IN);
+    std::memcpy(rank_class, c->log_cls.data(), sizeof(int32_t) * (size_t)cnt);
+    std::memcpy(hist, c->log_hist.data(), sizeof(float) * (size_t)cnt * WENOTT_MLP_BINS);
+    *n = cnt;
+    c->log_x.clear();
+    c->log_cls.clear();
+    c->log_hist.clear();
     return WENOTT_OK;
 }
 

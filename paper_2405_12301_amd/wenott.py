@@ -21,7 +21,11 @@ EXPORTED = ["wenott_default_opts", "wenott_init", "wenott_rhs", "wenott_rk3_step
             "wenott_to_dense", "wenott_get_state", "wenott_get_info", "wenott_max_wavespeed",
             "wenott_current_eps", "wenott_set_profiling", "wenott_last_error", "wenott_destroy",
             "wenott_strerror", "wenott_dense_init", "wenott_dense_max_wavespeed", "wenott_dense_rhs",
-            "wenott_dense_rk3_step", "wenott_dense_destroy"]
+            "wenott_dense_rk3_step", "wenott_dense_destroy", "wenott_mlp_nparams", "wenott_mlp_workspace",
+            "wenott_mlp_init_params", "wenott_mlp_forward", "wenott_mlp_loss_grad", "wenott_mlp_adam_step",
+            "wenott_set_proposal", "wenott_set_cross_logging", "wenott_get_cross_log"]
+
+MLP_IN, MLP_HID, MLP_OUT, MLP_RANK_CLASSES, MLP_BINS = 96, 128, 81, 17, 64
 
 
 class wenott_grid(ctypes.Structure):
@@ -50,7 +54,9 @@ class wenott_info(ctypes.Structure):
                 ("sum_rank", ctypes.c_int64 * 3), ("fiber_points", ctypes.c_int64), ("fiber_ms", ctypes.c_double),
                 ("fiber_launches", ctypes.c_int64), ("step_ms", ctypes.c_double),
                 ("class_ms", ctypes.c_double * 4), ("class_launches", ctypes.c_int64 * 4),
-                ("class_flops", ctypes.c_double * 4), ("class_bytes", ctypes.c_double * 4)]
+                ("class_flops", ctypes.c_double * 4), ("class_bytes", ctypes.c_double * 4),
+                ("proposals_tried", ctypes.c_int64), ("proposals_accepted", ctypes.c_int64),
+                ("pivots_total", ctypes.c_int64)]
 
 
 _lib = None
@@ -94,10 +100,22 @@ def load(path: str = LIB_PATH):
     lib.wenott_dense_rk3_step.argtypes = [vp, vp, ctypes.c_double, P(ctypes.c_double), P(ctypes.c_double)]
     lib.wenott_dense_destroy.argtypes = [vp]
     lib.wenott_dense_destroy.restype = None
+    lib.wenott_mlp_nparams.argtypes = []
+    lib.wenott_mlp_nparams.restype = ctypes.c_int64
+    lib.wenott_mlp_workspace.argtypes = [ctypes.c_int32]
+    lib.wenott_mlp_workspace.restype = ctypes.c_int64
+    lib.wenott_mlp_init_params.argtypes = [vp, ctypes.c_uint64, vp]
+    lib.wenott_mlp_forward.argtypes = [vp, vp, ctypes.c_int32, vp, ctypes.c_int32, vp, vp]
+    lib.wenott_mlp_loss_grad.argtypes = [vp, vp, vp, vp, ctypes.c_int32, vp, vp, vp, vp]
+    lib.wenott_mlp_adam_step.argtypes = [vp, vp, vp, vp, ctypes.c_int32, ctypes.c_float, vp]
+    lib.wenott_set_proposal.argtypes = [vp, vp]
+    lib.wenott_set_cross_logging.argtypes = [vp, ctypes.c_int32]
+    lib.wenott_get_cross_log.argtypes = [vp, vp, vp, vp, ctypes.c_int32, P(ctypes.c_int32)]
     for name in ("wenott_init", "wenott_rhs", "wenott_rk3_step", "wenott_round", "wenott_to_dense",
                  "wenott_get_state", "wenott_get_info", "wenott_max_wavespeed", "wenott_current_eps",
                  "wenott_set_profiling", "wenott_dense_init", "wenott_dense_max_wavespeed", "wenott_dense_rhs",
-                 "wenott_dense_rk3_step"):
+                 "wenott_dense_rk3_step", "wenott_mlp_init_params", "wenott_mlp_forward", "wenott_mlp_loss_grad",
+                 "wenott_mlp_adam_step", "wenott_set_proposal", "wenott_set_cross_logging", "wenott_get_cross_log"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -261,6 +279,56 @@ def wenott_dense_rk3_step(ctx, U, dt, alphas=None):
 def wenott_dense_destroy(ctx):
     if ctx:
         load().wenott_dense_destroy(ctx)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def wenott_mlp_nparams() -> int:
+    return int(load().wenott_mlp_nparams())
+
+
+def wenott_mlp_workspace(batch: int) -> int:
+    return int(load().wenott_mlp_workspace(int(batch)))
+
+
+def wenott_mlp_init_params(params, seed: int):
+    _check(load().wenott_mlp_init_params(_ptr(params), int(seed), _stream_handle()))
+
+
+def wenott_mlp_forward(params, x, y, work, bf16: bool):
+    _check(load().wenott_mlp_forward(_ptr(params), _ptr(x), int(x.shape[0]), _ptr(y), 1 if bf16 else 0, _ptr(work),
+                                     _stream_handle()))
+
+
+def wenott_mlp_loss_grad(params, x, cls, hist, grad, loss, work):
+    _check(load().wenott_mlp_loss_grad(_ptr(params), _ptr(x), _ptr(cls), _ptr(hist), int(x.shape[0]), _ptr(grad),
+                                       _ptr(loss), _ptr(work), _stream_handle()))
+
+
+def wenott_mlp_adam_step(params, grad, m, v, t: int, lr: float):
+    _check(load().wenott_mlp_adam_step(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), int(t), float(lr),
+                                       _stream_handle()))
+
+
+def wenott_set_proposal(ctx, params):
+    _check(load().wenott_set_proposal(ctx, None if params is None else _ptr(params)), ctx)
+
+
+def wenott_set_cross_logging(ctx, on: bool):
+    _check(load().wenott_set_cross_logging(ctx, 1 if on else 0), ctx)
+
+
+def wenott_get_cross_log(ctx, max_samples: int = 100000):
+    x = np.zeros((max_samples, MLP_IN), dtype=np.float32)
+    cls = np.zeros(max_samples, dtype=np.int32)
+    hist = np.zeros((max_samples, MLP_BINS), dtype=np.float32)
+    n = ctypes.c_int32()
+    _check(load().wenott_get_cross_log(ctx, x.ctypes.data, cls.ctypes.data, hist.ctypes.data, max_samples,
+                                       ctypes.byref(n)), ctx)
+    k = n.value
+    return x[:k].copy(), cls[:k].copy(), hist[:k].copy()
 
 
 def wenott_destroy(ctx):

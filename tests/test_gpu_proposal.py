@@ -1,0 +1,119 @@
+"""The learned cross proposal: MLP kernels against the FP64 reference, training on the
+library's own pivot logs, and a proposal-seeded run against the oracle (needs a GPU)."""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from oracle import mlp_ref
+from tests.gpu_util import oracle_problem, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def W():
+    from paper_2405_12301_amd import wenott
+    wenott.load()
+    oracle.build(force=False)
+    return wenott
+
+
+def _batch(rng, B):
+    x = rng.normal(size=(B, mlp_ref.IN)).astype(np.float32)
+    cls = rng.integers(0, mlp_ref.NR, size=B).astype(np.int32)
+    hist = rng.random(size=(B, mlp_ref.NB)).astype(np.float32)
+    hist /= hist.sum(axis=1, keepdims=True)
+    return x, cls, hist
+
+
+def test_mlp_gradients_match_fp64_reference(W):
+    import torch
+    _say("case: MLP FP32 gradient vs FP64 reference")
+    rng = np.random.default_rng(0)
+    P = torch.empty(W.wenott_mlp_nparams(), dtype=torch.float32, device="cuda")
+    W.wenott_mlp_init_params(P, 7)
+    x, cls, hist = _batch(rng, 32)
+    g = torch.zeros_like(P)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    work = torch.empty(W.wenott_mlp_workspace(32), dtype=torch.float32, device="cuda")
+    W.wenott_mlp_loss_grad(P, torch.from_numpy(x).cuda(), torch.from_numpy(cls).cuda(),
+                           torch.from_numpy(hist).cuda(), g, loss, work)
+    p64 = P.cpu().numpy().astype(np.float64)
+    l_ref, g_ref = mlp_ref.loss_and_grad(p64, x.astype(np.float64), cls, hist.astype(np.float64))
+    gg = g.cpu().numpy().astype(np.float64)
+    e = np.linalg.norm(gg - g_ref) / np.linalg.norm(g_ref)
+    _say(f"  loss {loss.item():.6f} vs {l_ref:.6f}; gradient rel err {e:.2e}")
+    assert abs(loss.item() - l_ref) <= 1e-5 * abs(l_ref)
+    assert e <= 1e-4
+    # inference: FP32 and BF16 (weights and activations rounded, FP32 accumulation)
+    y = torch.empty((32, mlp_ref.OUT), dtype=torch.float32, device="cuda")
+    xt = torch.from_numpy(x).cuda()
+    W.wenott_mlp_forward(P, xt, y, work, False)
+    y_ref = mlp_ref.forward(p64, x.astype(np.float64))[2]
+    e32 = np.abs(y.cpu().numpy() - y_ref).max() / np.abs(y_ref).max()
+    W.wenott_mlp_forward(P, xt, y, work, True)
+    e16 = np.abs(y.cpu().numpy() - y_ref).max() / np.abs(y_ref).max()
+    _say(f"  forward max rel err FP32 {e32:.2e}, BF16 {e16:.2e}")
+    assert e32 <= 1e-5 and e16 <= 3e-2
+
+
+def _quadrant_flows(seeds, n):
+    return [workloads.config2_quadrants_2d(n, seed=s) for s in seeds]
+
+
+def test_proposal_trained_on_pivot_logs(W):
+    import torch
+    from paper_2405_12301_amd import proposal
+    _say("case: learned proposal, logs from plain runs, held-out run vs oracle")
+    t0 = time.time()
+    x, cls, hist = proposal.collect_logs(_quadrant_flows(range(100, 112), 64), steps=12)
+    _say(f"  logged {x.shape[0]} samples in {time.time() - t0:.1f} s; rank classes {np.bincount(cls, minlength=17)}")
+    assert x.shape[0] > 100
+    P, losses = proposal.train(x, cls, hist, iters=300)
+    _say(f"  training loss {losses[0]:.3f} -> {losses[-1]:.3f}")
+    assert losses[-1] < losses[0]
+    # held-out seed: plain vs proposal-seeded, both checked step by step against the oracle
+    f = workloads.config2_quadrants_2d(96, seed=7)
+    eps = 1e-8
+    stats = {}
+    for use in (0, 1):
+        s = W.Solver(f, W.default_opts(eps_mode=0, eps0=eps, use_proposal=use))
+        try:
+            if use:
+                W.wenott_set_proposal(s.ctx, P)
+            Pb = oracle_problem(f)
+            piv = tried = acc = 0
+            sweeps = 0
+            wall = 0.0
+            worst = 0.0
+            for _ in range(10):
+                u = s.dense()
+                dt = 0.5 * min(Pb.h) / Pb.alpha(u)
+                t1 = time.perf_counter()
+                s.step(dt)
+                wall += time.perf_counter() - t1
+                info = s.info()
+                Pb.ssprk3(u, dt, alphas=[info.alpha[i] for i in range(3)])
+                worst = max(worst, rel_err(s.dense(), u) / info.eps)
+                piv += info.pivots_total
+                tried += info.proposals_tried
+                acc += info.proposals_accepted
+                sweeps += sum(info.sweeps[i][0] for i in range(3))
+            stats[use] = (piv, sweeps, tried, acc, wall, worst)
+        finally:
+            s.close()
+    for use in (0, 1):
+        piv, sw, tr, ac, wall, worst = stats[use]
+        _say(f"  {'proposal' if use else 'plain   '}: pivots {piv}, sweeps {sw}, proposals {ac}/{tr} accepted, "
+             f"{wall * 1e3 / 10:.2f} ms/step, worst step err / eps {worst:.2f}")
+    assert stats[1][2] > 0
+    assert stats[0][5] <= 10 and stats[1][5] <= 10
