@@ -39,8 +39,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-dense", action="store_true")
-    ap.add_argument("--workload", default="quadrants2d", choices=["quadrants2d", "wave3d", "sod3d"],
+    ap.add_argument("--workload", default="quadrants2d", choices=["quadrants2d", "wave3d", "sod3d", "blast_batch"],
                     help="quadrants2d is the contract workload; the others are side measurements")
+    ap.add_argument("--batch", type=int, default=32, help="states of the blast_batch workload")
     ap.add_argument("--precision", type=int, default=0, help="0 FP64 fiber path, 1 FP32 fiber path")
     return ap.parse_args()
 
@@ -73,11 +74,97 @@ def cpu_baseline(flow, seconds):
                       f"initial state ({el:.1f} s)"}
 
 
+CLASS_NAMES = ["k_stage (fused star-stencil LF + WENO5-JS stage-value fiber kernel)",
+               "k_prrlu_reg (full-pivot rank-revealing LU, cross pivots)",
+               "k_hhqr (Householder TSQR, rounding)", "k_jacobi_lds (one-sided Jacobi SVD, rounding)"]
+
+
+def roofline_of(cls_ms, cls_fl, cls_by, cls_n, steps):
+    ncls = len(cls_ms)
+    breakdown = {}
+    for i in range(ncls):
+        entry = {"ms_per_step": cls_ms[i] / steps, "launches_per_step": cls_n[i] / steps,
+                 "avg_launch_us": cls_ms[i] * 1e3 / max(cls_n[i], 1)}
+        if cls_fl[i] > 0 and cls_ms[i] > 0:
+            entry["tflops"] = cls_fl[i] / (cls_ms[i] * 1e-3) / 1e12
+            entry["gbs_algorithmic"] = cls_by[i] / (cls_ms[i] * 1e-3) / 1e9
+        breakdown[CLASS_NAMES[i].split()[0]] = entry
+    # dominant kernel: the class with the most device time among those with an algorithmic count
+    dom = max((i for i in range(ncls) if cls_fl[i] > 0), key=lambda i: cls_ms[i])
+    achieved = cls_fl[dom] / (cls_ms[dom] * 1e-3) / 1e12 if cls_ms[dom] > 0 else 0.0
+    return {"bound": "alu", "kernel": CLASS_NAMES[dom], "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
+            "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+            "algorithmic_flops_per_launch": cls_fl[dom] / max(cls_n[dom], 1),
+            "algorithmic_bytes_per_launch": cls_by[dom] / max(cls_n[dom], 1),
+            "avg_launch_us": cls_ms[dom] * 1e3 / max(cls_n[dom], 1),
+            "hbm_frac_algorithmic": cls_by[dom] / (cls_ms[dom] * 1e-3) / 1e9 / PEAK_HBM_GBS,
+            "breakdown": breakdown}
+
+
+def blast_batch(args):
+    """Side measurement: a batch of independent 3D spherical blasts with seeded grid sizes
+    from {64,96,128,192,256}^3, stepped in lock-step by wenott_batch_rk3_step."""
+    import torch
+
+    import workloads
+    from paper_2405_12301_amd import wenott as W
+
+    W.load()
+    torch.cuda.set_device(0)
+    t_gen = time.perf_counter()
+    flows = [workloads.config4_blast_3d(seed=args.seed + i) for i in range(args.batch)]
+    print(f"# generated {len(flows)} blast states in {time.perf_counter() - t_gen:.1f} s", file=sys.stderr, flush=True)
+    solvers = [W.Solver(f, W.default_opts(eps_mode=1, eps0=f.eps0)) for f in flows]
+    for s in solvers:
+        W.wenott_set_profiling(s.ctx, True)
+    cells = sum(int(f.n[0]) * int(f.n[1]) * int(f.n[2]) for f in flows)
+    hs = [min(f.h) for f in flows]
+
+    def one_step():
+        dts = [f.cfl * h / s.max_wavespeed() for f, h, s in zip(flows, hs, solvers)]
+        W.wenott_batch_rk3_step([s.ctx for s in solvers], dts)
+
+    for _ in range(args.warmup):
+        one_step()
+    torch.cuda.synchronize()
+    ncls = 4
+    cls_ms, cls_fl, cls_by, cls_n = [0.0] * ncls, [0.0] * ncls, [0.0] * ncls, [0] * ncls
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        one_step()
+        for s in solvers:
+            inf = s.info()
+            for i in range(ncls):
+                cls_ms[i] += inf.class_ms[i]
+                cls_fl[i] += inf.class_flops[i]
+                cls_by[i] += inf.class_bytes[i]
+                cls_n[i] += inf.class_launches[i]
+        print(f"# step {k} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ranks = [max(list(s.info().ranks)[:4]) for s in solvers]
+    for s in solvers:
+        s.close()
+    out = {"metric": METRIC, "value": cells * args.steps / el, "unit": "cell-updates/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": el * 1e3 / args.steps,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": f"batch of {args.batch} 3D spherical blasts, grids from {{64..256}}^3 "
+                                  f"(seeds {args.seed}..{args.seed + args.batch - 1}), transmissive, dynamic eps_TT "
+                                  f"from 1e-6, CFL 0.5, lock-step batched stepping",
+                      "cells_total": cells, "max_ranks": ranks},
+           "roofline": roofline_of(cls_ms, cls_fl, cls_by, cls_n, args.steps)}
+    print(json.dumps(out))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    if args.workload == "blast_batch":
+        blast_batch(args)
+        return
     import torch
 
     import workloads
@@ -136,27 +223,7 @@ def main():
     eps_now = info.eps
     solver.close()
 
-    names = ["k_stage (fused star-stencil LF + WENO5-JS stage-value fiber kernel)",
-             "k_prrlu_reg (full-pivot rank-revealing LU, cross pivots)",
-             "k_hhqr (Householder TSQR, rounding)", "k_jacobi_lds (one-sided Jacobi SVD, rounding)"]
-    breakdown = {}
-    for i in range(ncls):
-        entry = {"ms_per_step": cls_ms[i] / args.steps, "launches_per_step": cls_n[i] / args.steps,
-                 "avg_launch_us": cls_ms[i] * 1e3 / max(cls_n[i], 1)}
-        if cls_fl[i] > 0 and cls_ms[i] > 0:
-            entry["tflops"] = cls_fl[i] / (cls_ms[i] * 1e-3) / 1e12
-            entry["gbs_algorithmic"] = cls_by[i] / (cls_ms[i] * 1e-3) / 1e9
-        breakdown[names[i].split()[0]] = entry
-    # dominant kernel: the class with the most device time among those with an algorithmic count
-    dom = max((i for i in range(ncls) if cls_fl[i] > 0), key=lambda i: cls_ms[i])
-    achieved = cls_fl[dom] / (cls_ms[dom] * 1e-3) / 1e12 if cls_ms[dom] > 0 else 0.0
-    roofline = {"bound": "alu", "kernel": names[dom], "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
-                "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
-                "algorithmic_flops_per_launch": cls_fl[dom] / max(cls_n[dom], 1),
-                "algorithmic_bytes_per_launch": cls_by[dom] / max(cls_n[dom], 1),
-                "avg_launch_us": cls_ms[dom] * 1e3 / max(cls_n[dom], 1),
-                "hbm_frac_algorithmic": cls_by[dom] / (cls_ms[dom] * 1e-3) / 1e9 / PEAK_HBM_GBS,
-                "breakdown": breakdown}
+    roofline = roofline_of(cls_ms, cls_fl, cls_by, cls_n, args.steps)
 
     dense = None
     if not args.no_dense:

@@ -161,6 +161,17 @@ wenott_status wenott_rhs(wenott_ctx *ctx, double alpha, wenott_tt *view);
  */
 wenott_status wenott_rk3_step(wenott_ctx *ctx, double dt, double eps, const double *alphas);
 
+/*
+ * n independent states (each its own context, all created on the same stream, ndim equal,
+ * scheme 0, no proposal) advanced by one SSP-RK3 step each, in lock-step: every phase of a
+ * stage (alpha, the pivot searches of each cross sweep, the sampled residuals, the rounding's
+ * norms, Jacobi SVDs and truncation ranks) is one batched launch and one host
+ * synchronisation for the whole batch. dt[n] per state; eps: NULL or eps[n] (<= 0 selects the
+ * state's rule). Results equal n separate wenott_rk3_step calls up to the random enrichment
+ * indices. On error no state is changed.
+ */
+wenott_status wenott_batch_rk3_step(wenott_ctx **ctxs, int32_t n, const double *dt, const double *eps);
+
 /* TT-rounding of the state (Sec. 3.2): right-to-left orthogonalisation, then left-to-right
  * truncated SVDs, so that ||X - Y||_F <= eps ||X||_F per component. eps > 0. */
 wenott_status wenott_round(wenott_ctx *ctx, double eps);

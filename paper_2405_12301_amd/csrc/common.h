@@ -90,6 +90,30 @@ void prrlu(hipStream_t s, int m, int n, double *A, int rmax, double rel_tol2, in
 // batch * r * r doubles. Zero (padding) columns keep a unit diagonal.
 void chol_upper_inv(hipStream_t s, int r, int batch, const double *G, double *X, double *ws);
 
+// Batched forms: one workgroup per job (and per component for the SVD / Cholesky), the jobs
+// read from a device array; used to step many independent states in lock-step.
+struct PrrluJob {
+    double *A;
+    int m, n, rmax;
+    double rel_tol2;
+    int *rowpiv, *colpiv;
+    double *L, *info, *rowbuf;
+};
+struct SvdJob {
+    const double *A;
+    double *sigma, *V;
+    int n, batch;
+};
+struct CholJob {
+    const double *G;
+    double *X, *R;
+    int r, batch;
+};
+void prrlu_batch(hipStream_t s, int njobs, const PrrluJob *host_jobs, PrrluJob *dev_jobs);
+bool jacobi_batch_fits(int nmax);
+void jacobi_svd_batch(hipStream_t s, int njobs, int ncomp, int nmax, const SvdJob *dev_jobs);
+void chol_upper_inv_batch(hipStream_t s, int njobs, int ncomp, const CholJob *dev_jobs);
+
 // X (m x r, row-major) = L (m x ldl) * inv(L[rowpiv, :r]), the interpolative basis.
 void interp_solve(hipStream_t s, int m, int r, const double *L, int ldl, const int *rowpiv, double *X);
 

@@ -281,7 +281,8 @@ const double *left_part(wenott_ctx *c, const TT &U, long long *stride) {
     return Lm;
 }
 
-double exact_alpha(wenott_ctx *c, const TT &U) {
+// Enqueue the exact alpha of U into dst (device) and the flag word into the pinned slot [64].
+void exact_alpha_launch(wenott_ctx *c, const TT &U, double *dst) {
     long long lms = 0;
     const double *Lm = left_part(c, U, &lms);
     long long nrows = 1;
@@ -292,10 +293,13 @@ double exact_alpha(wenott_ctx *c, const TT &U) {
     double *part = c->sc.get<double>(S_PART, nblocks);
     dense_eval(c->s, 1, U.d, U.nc, nrows, U.R[U.d - 1], nlast, Lm, lms, U.core[U.d - 1], U.cstride(U.d - 1),
                c->gamma, nullptr, part, nblocks, c->d_flags);
-    double *dsc = c->sc.get<double>(S_DSCAL, 4);
-    reduce_max_dev(c->s, part, nblocks, dsc);
-    WTT_HIP(hipMemcpyAsync(c->h_pinned_dbl + 64, dsc, sizeof(double), hipMemcpyDeviceToHost, c->s));
+    reduce_max_dev(c->s, part, nblocks, dst);
+    WTT_HIP(hipMemcpyAsync(c->h_pinned_dbl + 64, dst, sizeof(double), hipMemcpyDeviceToHost, c->s));
     WTT_HIP(hipMemcpyAsync(c->h_pinned_int + 64, c->d_flags, sizeof(int), hipMemcpyDeviceToHost, c->s));
+}
+
+double exact_alpha(wenott_ctx *c, const TT &U) {
+    exact_alpha_launch(c, U, c->sc.get<double>(S_DSCAL, 4));
     WTT_HIP(hipStreamSynchronize(c->s));
     raise_flags(c, c->h_pinned_int[64]);
     return c->h_pinned_dbl[64];
@@ -849,8 +853,8 @@ void eval_stage_block(wenott_ctx *c, const TT &X, const TT *Un, StageWeights w, 
     }
 }
 
-double sampled_stage_residual(wenott_ctx *c, const TT &X, const TT *Un, StageWeights w, double alpha,
-                              const FluxTT &F, Rng &rng) {
+int sampled_stage_residual_launch(wenott_ctx *c, const TT &X, const TT *Un, StageWeights w, double alpha,
+                                  const FluxTT &F, Rng &rng) {
     const int d = X.d, npts = std::max(c->o.probe_points, 16);
     FiberGeom g{};
     g.d = d; g.ncomp = X.nc; g.dir = 0; g.k = 0;
@@ -876,12 +880,23 @@ double sampled_stage_residual(wenott_ctx *c, const TT &X, const TT *Un, StageWei
     WTT_REQUIRE(2 * (size_t)nb <= 3000, WENOTT_EINVAL, "too many probe points");
     WTT_HIP(hipMemcpyAsync(c->h_pinned_dbl + 128, acc, 2 * nb * sizeof(double), hipMemcpyDeviceToHost, c->s));
     WTT_HIP(hipMemcpyAsync(c->h_pinned_int + 128, c->d_flags, sizeof(int), hipMemcpyDeviceToHost, c->s));
-    WTT_HIP(hipStreamSynchronize(c->s));
+    return nb;
+}
+
+// Residual from the pinned copies of a launched sampled residual (after a synchronisation).
+double sampled_residual_finish(wenott_ctx *c, int nb) {
     raise_flags(c, c->h_pinned_int[128]);
     const double *h = c->h_pinned_dbl + 128;
     double d2 = 0.0, n2 = 0.0;
     for (int b = 0; b < nb; ++b) { d2 += h[2 * b]; n2 += h[2 * b + 1]; }
     return n2 > 0.0 ? std::sqrt(d2 / n2) : std::sqrt(d2);
+}
+
+double sampled_stage_residual(wenott_ctx *c, const TT &X, const TT *Un, StageWeights w, double alpha,
+                              const FluxTT &F, Rng &rng) {
+    const int nb = sampled_stage_residual_launch(c, X, Un, w, alpha, F, rng);
+    WTT_HIP(hipStreamSynchronize(c->s));
+    return sampled_residual_finish(c, nb);
 }
 
 FluxTT cross_stage(wenott_ctx *c, const TT &X, const TT *Un, StageWeights w, double alpha, double eps,
@@ -1121,6 +1136,359 @@ void round_tt(wenott_ctx *c, TT &X, double eps, bool truncate, std::vector<doubl
         X.R[k + 1] = r;
     }
     for (int k = 1; k < d; ++k) dfree(s, T[k]);
+}
+
+// ===================================================================== batched stepping
+// Many independent states advance in lock-step through the phases of a stage: every state's
+// block evaluations are enqueued, then one batched pivot launch (one workgroup per state) and
+// one host synchronisation serve the whole batch; likewise the sampled residuals, the norms,
+// the Jacobi SVDs and the truncation ranks of the rounding. Per-state kernels (gathers, stage
+// kernel, GEMMs, TSQR) are enqueued back to back on the shared stream.
+struct BState {
+    wenott_ctx *c = nullptr;
+    TT X;
+    bool x_owned = false;
+    double alpha = 0.0, eps = 0.0, ceps = 0.0, dt = 0.0;
+    int M[kMaxDim] = {};
+    std::vector<ISet> Rset, Lset;
+    FluxTT F;
+    Rng rng{0};
+    double rel2 = 0.0, resid = 1e300;
+    int sweep = 0;
+    bool active = true;
+    // per-core pivots of the batched pivot phase
+    double *B = nullptr, *L = nullptr;
+    int *piv = nullptr;
+    double *info = nullptr;
+    int m = 0, n = 0, rmax = 0;
+    std::vector<double> norms;
+    int nb_acc = 0;
+};
+
+// One batched pivot phase over the states with a non-null block: prrLU of each block.
+void batch_pivots(std::vector<BState *> &act) {
+    if (act.empty()) return;
+    wenott_ctx *c0 = act[0]->c;
+    std::vector<PrrluJob> jobs;
+    for (BState *b : act) {
+        wenott_ctx *c = b->c;
+        b->rmax = std::min(std::min(c->o.rank_cap, kMaxRankLds), std::min(b->m, b->n));
+        b->piv = c->sc.get<int>(S_PIV, 2 * (size_t)b->rmax + 2);
+        b->L = c->sc.get<double>(S_L, (size_t)b->m * b->rmax);
+        b->info = c->sc.get<double>(S_INFO, 2);
+        PrrluJob j;
+        j.A = b->B; j.m = b->m; j.n = b->n; j.rmax = b->rmax; j.rel_tol2 = b->rel2;
+        j.rowpiv = b->piv; j.colpiv = b->piv + b->rmax; j.L = b->L; j.info = b->info;
+        j.rowbuf = c->sc.get<double>(S_ROWBUF, b->n);
+        jobs.push_back(j);
+    }
+    PrrluJob *dj = c0->ring.put(jobs.data(), jobs.size());
+    ev_record(c0, KC_PIVOT);
+    prrlu_batch(c0->s, (int)jobs.size(), jobs.data(), dj);
+    ev_record(c0, KC_PIVOT);
+    for (BState *b : act) {
+        WTT_HIP(hipMemcpyAsync(b->c->h_pinned_dbl, b->info, 2 * sizeof(double), hipMemcpyDeviceToHost, b->c->s));
+        WTT_HIP(hipMemcpyAsync(b->c->h_pinned_int, b->piv, 2 * b->rmax * sizeof(int), hipMemcpyDeviceToHost, b->c->s));
+    }
+    WTT_HIP(hipStreamSynchronize(c0->s));
+    for (BState *b : act) {
+        const int r = (int)b->c->h_pinned_dbl[0];
+        double fl = 0.0;
+        for (int t = 0; t < r; ++t) fl += 2.0 * (double)(b->m - t) * (double)(b->n - t);
+        add_work(b->c, KC_PIVOT, fl, 8.0 * ((double)b->m * b->n + (double)b->m * r));
+        b->c->info.pivots_total += r;
+    }
+}
+
+void batch_cross(std::vector<BState> &bs, const double *aw, const double *bw, int st) {
+    const int d = bs[0].X.d, nc = bs[0].X.nc;
+    for (auto &b : bs) {
+        wenott_ctx *c = b.c;
+        for (int j = 0; j < d; ++j) b.M[j] = b.X.N[j];
+        b.rng = Rng(c->o.seed ^ (0x5851F42D4C957F2DULL * (++c->counter)));
+        b.Rset.assign(d, ISet());
+        b.Rset[d - 1].len = 0;
+        b.Rset[d - 1].count = 1;
+        if (c->warm_valid[kMaxDim]) b.Rset = c->warm[kMaxDim];
+        else
+            for (int k = 0; k < d - 1; ++k) b.Rset[k] = random_set(b.rng, std::max(2, b.X.maxrank()), k + 1, d - 1 - k, b.M);
+        b.Lset.assign(d, ISet());
+        b.F = FluxTT();
+        b.F.d = d; b.F.nc = nc;
+        for (int j = 0; j < d; ++j) b.F.M[j] = b.M[j];
+        // the FP32 fiber path floors the cross tolerance as in the single-state cross
+        b.ceps = c->o.precision == 1 ? std::max(b.eps, 1e-6) : b.eps;
+        b.rel2 = b.ceps * b.ceps / (4.0 * d);
+        b.resid = 1e300;
+        b.sweep = 0;
+        b.active = true;
+    }
+    const int max_sweeps = bs[0].c->o.max_sweeps;
+    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+        std::vector<BState *> act;
+        for (auto &b : bs)
+            if (b.active) act.push_back(&b);
+        if (act.empty()) break;
+        for (BState *b : act) {
+            b->F.release(b->c->s);
+            b->Lset[0].len = 0; b->Lset[0].count = 1; b->Lset[0].v.clear();
+            b->F.R[0] = 1; b->F.R[d] = 1;
+        }
+        std::vector<ISet> Rk(bs.size());
+        for (int k = 0; k < d; ++k) {
+            for (BState *b : act) {
+                const size_t z = b - bs.data();
+                Rk[z] = k < d - 1 ? with_kick(b->Rset[k], b->rng, b->c->o.kick_rank, k + 1, b->M) : b->Rset[k];
+                const int p = b->Lset[k].count, q = Rk[z].count;
+                b->m = p * b->M[k];
+                b->n = q * nc;
+                const StageWeights w{aw[st], bw[st], bw[st] * b->dt};
+                if (k < d - 1) {
+                    b->B = b->c->sc.get<double>(S_BLOCK, (size_t)b->m * b->n);
+                    eval_stage_block(b->c, b->X, &b->c->U, w, b->alpha, k, b->Lset[k], Rk[z], true, b->B);
+                } else {
+                    b->F.core[k] = dalloc<double>(b->c->s, (size_t)b->m * b->n);
+                    eval_stage_block(b->c, b->X, &b->c->U, w, b->alpha, k, b->Lset[k], Rk[z], true, b->F.core[k]);
+                }
+            }
+            if (k == d - 1) break;
+            batch_pivots(act);
+            for (BState *b : act) {
+                const int r = (int)b->c->h_pinned_dbl[0];
+                std::vector<int> rows(b->c->h_pinned_int, b->c->h_pinned_int + r);
+                b->F.core[k] = dalloc<double>(b->c->s, (size_t)b->m * r);
+                interp_solve(b->c->s, b->m, r, b->L, b->rmax, b->piv, b->F.core[k]);
+                b->F.R[k + 1] = r;
+                ISet nl;
+                nl.len = k + 1;
+                nl.count = r;
+                nl.v.resize((size_t)r * (k + 1));
+                for (int tt = 0; tt < r; ++tt) {
+                    const int row = rows[tt], a = row / b->M[k], i = row % b->M[k];
+                    for (int j = 0; j < k; ++j) nl.v[(size_t)tt * (k + 1) + j] = b->Lset[k].v[(size_t)a * k + j];
+                    nl.v[(size_t)tt * (k + 1) + k] = i;
+                }
+                b->Lset[k + 1] = std::move(nl);
+            }
+        }
+        // sampled residuals of every active state, one synchronisation
+        for (BState *b : act) {
+            const StageWeights w{aw[st], bw[st], bw[st] * b->dt};
+            b->nb_acc = sampled_stage_residual_launch(b->c, b->X, &b->c->U, w, b->alpha, b->F, b->rng);
+        }
+        WTT_HIP(hipStreamSynchronize(act[0]->c->s));
+        std::vector<BState *> refresh;
+        for (BState *b : act) {
+            b->resid = sampled_residual_finish(b->c, b->nb_acc);
+            b->sweep = sweep + 1;
+            if (b->resid <= b->ceps || sweep + 1 == max_sweeps) b->active = false;
+            else refresh.push_back(b);
+        }
+        // right-to-left refresh of the states that missed eps
+        for (int k = d - 1; k >= 1 && !refresh.empty(); --k) {
+            std::vector<ISet> Lk(bs.size());
+            for (BState *b : refresh) {
+                const size_t z = b - bs.data();
+                Lk[z] = with_kick(b->Lset[k], b->rng, b->c->o.kick_rank, 0, b->M);
+                const ISet &R = b->Rset[k];
+                b->m = b->M[k] * R.count;
+                b->n = Lk[z].count * nc;
+                b->B = b->c->sc.get<double>(S_BLOCK, (size_t)b->m * b->n);
+                const StageWeights w{aw[st], bw[st], bw[st] * b->dt};
+                eval_stage_block(b->c, b->X, &b->c->U, w, b->alpha, k, Lk[z], R, false, b->B);
+            }
+            batch_pivots(refresh);
+            for (BState *b : refresh) {
+                const ISet &R = b->Rset[k];
+                const int r = (int)b->c->h_pinned_dbl[0], q = R.count;
+                ISet nr;
+                nr.len = d - k;
+                nr.count = r;
+                nr.v.resize((size_t)r * nr.len);
+                for (int tt = 0; tt < r; ++tt) {
+                    const int row = b->c->h_pinned_int[tt], i = row / q, bb = row % q;
+                    nr.v[(size_t)tt * nr.len] = i;
+                    for (int j = 0; j < R.len; ++j) nr.v[(size_t)tt * nr.len + 1 + j] = R.v[(size_t)bb * R.len + j];
+                }
+                b->Rset[k - 1] = std::move(nr);
+            }
+        }
+        for (BState *b : refresh) b->rel2 *= 0.25;
+    }
+    for (auto &b : bs) {
+        b.c->warm[kMaxDim] = b.Rset;
+        b.c->warm_valid[kMaxDim] = true;
+        b.c->info.sweeps[st][0] = b.sweep;
+        b.c->info.residual[st][0] = b.resid;
+        int fr = 1;
+        for (int k = 1; k < d; ++k) fr = std::max(fr, b.F.R[k]);
+        b.c->info.flux_rank[st][0] = fr;
+        if (!(b.resid <= 1e3 * b.ceps) && !(b.resid <= 1e-12))
+            throw StatusError(WENOTT_ENOCONV, "cross did not converge");
+    }
+}
+
+// Lock-step TT-rounding of every state's stage TT (same algorithm as round_tt).
+void batch_round(std::vector<BState> &bs, std::vector<TT> &Xs) {
+    const int d = Xs[0].d, nc = Xs[0].nc;
+    const size_t ns = bs.size();
+    std::vector<std::vector<double *>> T(ns, std::vector<double *>(d + 1, nullptr));
+    for (size_t z = 0; z < ns; ++z) {
+        wenott_ctx *c = bs[z].c;
+        TT &X = Xs[z];
+        for (int k = d - 1; k >= 1; --k) {
+            const int Rk = X.R[k], Nk = X.N[k], Rk1 = X.R[k + 1];
+            const long long m = (long long)Nk * Rk1;
+            const double *C = X.core[k];
+            if (k < d - 1) {
+                double *Cb = c->sc.get<double>(S_TMP, (size_t)nc * Rk * m);
+                GemmBatch b;
+                b.nb1 = nc; b.sA1 = X.cstride(k); b.sB1 = (long long)Rk1 * Rk1; b.sC1 = (long long)Rk * m;
+                gemm_f64(c->s, false, true, Rk * Nk, Rk1, Rk1, 1.0, X.core[k], Rk1, T[z][k + 1], Rk1, 0.0, Cb, Rk1, b);
+                C = Cb;
+            }
+            double *scr = c->sc.get<double>(S_TSQR, tsqr_scratch_doubles((int)m, Rk, nc));
+            T[z][k] = dalloc<double>(c->s, (size_t)nc * Rk * Rk);
+            ev_record(c, KC_TSQR);
+            tsqr_r(c->s, (int)m, Rk, nc, C, (long long)Rk * m, 1, m, T[z][k], scr);
+            ev_record(c, KC_TSQR);
+            add_work(c, KC_TSQR, nc * (2.0 * m * (double)Rk * Rk - 2.0 / 3.0 * (double)Rk * Rk * Rk),
+                     8.0 * nc * (double)m * Rk);
+
+        }
+        const int N0 = X.N[0], R1 = X.R[1];
+        double *C0 = c->sc.get<double>(S_TMP, (size_t)nc * N0 * R1);
+        GemmBatch b;
+        b.nb1 = nc; b.sA1 = X.cstride(0); b.sB1 = (long long)R1 * R1; b.sC1 = (long long)N0 * R1;
+        gemm_f64(c->s, false, true, N0, R1, R1, 1.0, X.core[0], R1, T[z][1], R1, 0.0, C0, R1, b);
+        double *dn = c->sc.get<double>(S_NORMS, nc);
+        frob_norms(c->s, nc, (long long)N0 * R1, C0, (long long)N0 * R1, dn);
+        WTT_HIP(hipMemcpyAsync(c->h_pinned_dbl + 64, dn, nc * sizeof(double), hipMemcpyDeviceToHost, c->s));
+    }
+    WTT_HIP(hipStreamSynchronize(bs[0].c->s));
+    std::vector<const double *> ddelta(ns);
+    for (size_t z = 0; z < ns; ++z) {
+        wenott_ctx *c = bs[z].c;
+        bs[z].norms.assign(c->h_pinned_dbl + 64, c->h_pinned_dbl + 64 + nc);
+        std::vector<double> delta(nc);
+        for (int q = 0; q < nc; ++q) delta[q] = bs[z].eps * bs[z].norms[q] / std::sqrt((double)std::max(d - 1, 1));
+        ddelta[z] = c->ring.put(delta.data(), delta.size());
+    }
+    for (int k = 0; k < d - 1; ++k) {
+        std::vector<SvdJob> jobs(ns);
+        std::vector<double *> sig(ns), V(ns);
+        std::vector<int *> rk(ns);
+        int nmax = 1;
+        for (size_t z = 0; z < ns; ++z) nmax = std::max(nmax, Xs[z].R[k + 1]);
+        const bool fits = jacobi_batch_fits(nmax);
+        for (size_t z = 0; z < ns; ++z) {
+            wenott_ctx *c = bs[z].c;
+            TT &X = Xs[z];
+            const int m = X.R[k] * X.N[k], n = X.R[k + 1];
+            double *C = c->sc.get<double>(S_TMP, (size_t)nc * m * n);
+            GemmBatch b0;
+            b0.nb1 = nc; b0.sA1 = X.cstride(k); b0.sB1 = (long long)n * n; b0.sC1 = (long long)m * n;
+            gemm_f64(c->s, false, true, m, n, n, 1.0, X.core[k], n, T[z][k + 1], n, 0.0, C, n, b0);
+            double *scr = c->sc.get<double>(S_TSQR, tsqr_scratch_doubles(m, n, nc));
+            double *R = c->sc.get<double>(S_R, (size_t)nc * n * n);
+            ev_record(c, KC_TSQR);
+            tsqr_r(c->s, m, n, nc, C, (long long)m * n, n, 1, R, scr);
+            ev_record(c, KC_TSQR);
+            add_work(c, KC_TSQR, nc * (2.0 * m * (double)n * n - 2.0 / 3.0 * (double)n * n * n), 8.0 * nc * (double)m * n);
+            add_work(c, KC_SVD, 0.0, 8.0 * nc * 3.0 * (double)n * n);
+            sig[z] = c->sc.get<double>(S_SIG, (size_t)nc * n);
+            V[z] = c->sc.get<double>(S_V, (size_t)nc * n * n);
+            jobs[z] = SvdJob{R, sig[z], V[z], n, nc};
+            if (!fits) {
+                double *jac = c->sc.get<double>(S_JAC, (size_t)nc * (2 * (size_t)n * n + n));
+                ev_record(c, KC_SVD);
+                jacobi_svd(c->s, n, nc, R, sig[z], V[z], jac);
+                ev_record(c, KC_SVD);
+            }
+        }
+        if (fits) {
+            SvdJob *dj = bs[0].c->ring.put(jobs.data(), jobs.size());
+            ev_record(bs[0].c, KC_SVD);
+            jacobi_svd_batch(bs[0].c->s, (int)ns, nc, nmax, dj);
+            ev_record(bs[0].c, KC_SVD);
+        }
+        for (size_t z = 0; z < ns; ++z) {
+            wenott_ctx *c = bs[z].c;
+            const int n = Xs[z].R[k + 1];
+            rk[z] = c->sc.get<int>(S_RANKS, nc);
+            trunc_ranks(c->s, n, nc, sig[z], ddelta[z], 0.0, c->o.rank_cap, rk[z]);
+            WTT_HIP(hipMemcpyAsync(c->h_pinned_int, rk[z], nc * sizeof(int), hipMemcpyDeviceToHost, c->s));
+        }
+        WTT_HIP(hipStreamSynchronize(bs[0].c->s));
+        std::vector<CholJob> cj(ns);
+        std::vector<double *> nk(ns), nk2(ns);
+        std::vector<int> rr(ns);
+        int pass_ok = 1;
+        for (size_t z = 0; z < ns; ++z) {
+            wenott_ctx *c = bs[z].c;
+            TT &X = Xs[z];
+            const int m = X.R[k] * X.N[k], n = X.R[k + 1];
+            int r = 1;
+            for (int q = 0; q < nc; ++q) r = std::max(r, c->h_pinned_int[q]);
+            rr[z] = r;
+            double *W1 = c->sc.get<double>(S_W1, (size_t)nc * n * r);
+            double *W2 = c->sc.get<double>(S_W2, (size_t)nc * n * r);
+            build_projectors(c->s, n, nc, r, sig[z], V[z], rk[z], W1, W2);
+            double *P = c->sc.get<double>(S_P, (size_t)nc * n * r);
+            GemmBatch b1;
+            b1.nb1 = nc; b1.sA1 = (long long)n * n; b1.sB1 = (long long)n * r; b1.sC1 = (long long)n * r;
+            gemm_f64(c->s, true, false, n, r, n, 1.0, T[z][k + 1], n, W1, r, 0.0, P, r, b1);
+            nk[z] = dalloc<double>(c->s, (size_t)nc * m * r);
+            GemmBatch b2;
+            b2.nb1 = nc; b2.sA1 = X.cstride(k); b2.sB1 = (long long)n * r; b2.sC1 = (long long)m * r;
+            gemm_f64(c->s, false, false, m, r, n, 1.0, X.core[k], n, P, r, 0.0, nk[z], r, b2);
+        }
+        for (int pass = 0; pass < 2 && pass_ok; ++pass) {
+            for (size_t z = 0; z < ns; ++z) {
+                wenott_ctx *c = bs[z].c;
+                const int m = Xs[z].R[k] * Xs[z].N[k], r = rr[z];
+                double *Gm = c->sc.get<double>(S_PD0, (size_t)nc * r * r);
+                double *Xi = c->sc.get<double>(S_PD1, (size_t)nc * r * r);
+                double *ws = c->sc.get<double>(S_TD0, (size_t)nc * r * r);
+                size_t pc = gemm_tn_splitk_part(r, r, m, nc);
+                gemm_tn_splitk(c->s, r, r, m, nk[z], r, nk[z], r, Gm, r, nc, (long long)m * r, (long long)m * r,
+                               (long long)r * r, c->sc.get<double>(S_SPLIT, pc), pc);
+                cj[z] = CholJob{Gm, Xi, ws, r, nc};
+            }
+            CholJob *dc = bs[0].c->ring.put(cj.data(), cj.size());
+            chol_upper_inv_batch(bs[0].c->s, (int)ns, nc, dc);
+            for (size_t z = 0; z < ns; ++z) {
+                wenott_ctx *c = bs[z].c;
+                const int m = Xs[z].R[k] * Xs[z].N[k], r = rr[z];
+                nk2[z] = c->sc.get<double>(S_TD1, (size_t)nc * m * r);
+                GemmBatch bx;
+                bx.nb1 = nc; bx.sA1 = (long long)m * r; bx.sB1 = (long long)r * r; bx.sC1 = (long long)m * r;
+                gemm_f64(c->s, false, false, m, r, r, 1.0, nk[z], r, cj[z].X, r, 0.0, nk2[z], r, bx);
+                WTT_HIP(hipMemcpyAsync(nk[z], nk2[z], sizeof(double) * nc * m * r, hipMemcpyDeviceToDevice, c->s));
+            }
+        }
+        for (size_t z = 0; z < ns; ++z) {
+            wenott_ctx *c = bs[z].c;
+            TT &X = Xs[z];
+            const int m = X.R[k] * X.N[k], n = X.R[k + 1], r = rr[z];
+            double *Sm = c->sc.get<double>(S_Q, (size_t)nc * r * n);
+            size_t pc = gemm_tn_splitk_part(r, n, m, nc);
+            gemm_tn_splitk(c->s, r, n, m, nk[z], r, X.core[k], n, Sm, n, nc, (long long)m * r, X.cstride(k),
+                           (long long)r * n, c->sc.get<double>(S_SPLIT, pc), pc);
+            const int mn = X.N[k + 1] * X.R[k + 2];
+            double *nk1 = dalloc<double>(c->s, (size_t)nc * r * mn);
+            GemmBatch b4;
+            b4.nb1 = nc; b4.sA1 = (long long)r * n; b4.sB1 = X.cstride(k + 1); b4.sC1 = (long long)r * mn;
+            gemm_f64(c->s, false, false, r, mn, n, 1.0, Sm, n, X.core[k + 1], mn, 0.0, nk1, mn, b4);
+            dfree(c->s, X.core[k]);
+            dfree(c->s, X.core[k + 1]);
+            X.core[k] = nk[z];
+            X.core[k + 1] = nk1;
+            X.R[k + 1] = r;
+        }
+    }
+    for (size_t z = 0; z < ns; ++z)
+        for (int k = 1; k < d; ++k) dfree(bs[z].c->s, T[z][k]);
 }
 
 double geometric_h(const wenott_ctx *c) {
@@ -1484,6 +1852,86 @@ wenott_status wenott_rk3_step(wenott_ctx *c, double dt, double eps_in, const dou
         c->info.eps = eps;
         c->info.c_eps = c->c_eps;
         finish_call_info(c, t0);
+    });
+}
+
+wenott_status wenott_batch_rk3_step(wenott_ctx **ctxs, int32_t n, const double *dt, const double *eps_in) {
+    if (!ctxs || n <= 0 || !dt) return WENOTT_EINVAL;
+    for (int i = 0; i < n; ++i)
+        if (!ctxs[i] || !(dt[i] > 0.0)) return WENOTT_EINVAL;
+    return run_guarded(ctxs[0], [&] {
+        const int d = ctxs[0]->d;
+        for (int i = 0; i < n; ++i) {
+            wenott_ctx *c = ctxs[i];
+            WTT_REQUIRE(c->d == d && c->s == ctxs[0]->s, WENOTT_EINVAL,
+                        "batched states need the same dimension and the same stream");
+            WTT_REQUIRE(c->o.scheme == 0 && c->o.use_proposal == 0 && !c->logging, WENOTT_EINVAL,
+                        "batched stepping runs the stage-cross scheme without the proposal or cross logging");
+            for (int j = 0; j < i; ++j) WTT_REQUIRE(ctxs[j] != c, WENOTT_EINVAL, "a context appears twice");
+        }
+        double t0 = seconds_now();
+        std::vector<BState> bs(n);
+        for (int i = 0; i < n; ++i) {
+            reset_call_info(ctxs[i]);
+            bs[i].c = ctxs[i];
+            bs[i].X = ctxs[i]->U;
+            bs[i].dt = dt[i];
+            bs[i].eps = (eps_in && eps_in[i] > 0.0) ? eps_in[i] : current_eps(ctxs[i]);
+        }
+        const double aw[3] = {0.0, 0.75, 1.0 / 3.0}, bw[3] = {1.0, 0.25, 2.0 / 3.0};
+        std::vector<TT> Ys;
+        try {
+            for (int st = 0; st < 3; ++st) {
+                bool any = false;
+                for (auto &b : bs)
+                    if (b.c->o.alpha_mode != 2) {
+                        exact_alpha_launch(b.c, b.X, b.c->sc.get<double>(S_DSCAL, 4));
+                        any = true;
+                    }
+                if (any) WTT_HIP(hipStreamSynchronize(ctxs[0]->s));
+                for (auto &b : bs) {
+                    if (b.c->o.alpha_mode == 2) {
+                        b.alpha = b.c->o.alpha_given;
+                    } else {
+                        raise_flags(b.c, b.c->h_pinned_int[64]);
+                        b.alpha = b.c->h_pinned_dbl[64];
+                    }
+                    WTT_REQUIRE(b.alpha > 0.0, WENOTT_EINVAL, "alpha must be positive");
+                    b.c->info.alpha[st] = b.alpha;
+                }
+                batch_cross(bs, aw, bw, st);
+                Ys.assign(n, TT());
+                for (int i = 0; i < n; ++i) {
+                    Ys[i] = cross_to_tt(bs[i].c, bs[i].F, -1);
+                    bs[i].F.release(bs[i].c->s);
+                    bs[i].c->info.sum_rank[st] = Ys[i].maxrank();
+                }
+                batch_round(bs, Ys);
+                for (int i = 0; i < n; ++i) {
+                    if (bs[i].x_owned) bs[i].X.release(bs[i].c->s);
+                    bs[i].X = Ys[i];
+                    bs[i].x_owned = true;
+                }
+                Ys.clear();
+            }
+        } catch (...) {
+            for (auto &y : Ys) y.release(ctxs[0]->s);
+            for (auto &b : bs) {
+                if (b.x_owned) b.X.release(b.c->s);
+                b.F.release(b.c->s);
+            }
+            throw;
+        }
+        for (auto &b : bs) {
+            wenott_ctx *c = b.c;
+            c->U.release(c->s);
+            c->U = b.X;
+            c->max_norm = *std::max_element(b.norms.begin(), b.norms.end());
+            c->info.max_norm = c->max_norm;
+            c->info.eps = b.eps;
+            c->info.c_eps = c->c_eps;
+        }
+        for (int i = 0; i < n; ++i) finish_call_info(ctxs[i], t0);
     });
 }
 

@@ -326,7 +326,7 @@ __global__ __launch_bounds__(1024) void k_jacobi_global(int n, const double *__r
 }
 
 // ------------------------------------------------------------------- prrLU (pivots)
-__global__ __launch_bounds__(1024) void k_prrlu(int m, int n, double *__restrict__ A, int rmax, double rel_tol2,
+__device__ __forceinline__ void prrlu_glob_body(int m, int n, double *__restrict__ A, int rmax, double rel_tol2,
                                                 int *__restrict__ rowpiv, int *__restrict__ colpiv,
                                                 double *__restrict__ L, double *__restrict__ info,
                                                 double *__restrict__ rowbuf_g, int use_lds) {
@@ -417,15 +417,27 @@ __global__ __launch_bounds__(1024) void k_prrlu(int m, int n, double *__restrict
         for (int i = tid; i < m; i += blockDim.x) L[(long long)i * rmax] = (i == 0) ? 1.0 : 0.0;
 }
 
+__global__ __launch_bounds__(1024) void k_prrlu(int m, int n, double *__restrict__ A, int rmax, double rel_tol2,
+                                                int *__restrict__ rowpiv, int *__restrict__ colpiv,
+                                                double *__restrict__ L, double *__restrict__ info,
+                                                double *__restrict__ rowbuf_g, int use_lds) {
+    prrlu_glob_body(m, n, A, rmax, rel_tol2, rowpiv, colpiv, L, info, rowbuf_g, use_lds);
+}
+
+__global__ __launch_bounds__(1024) void k_prrlu_batch(const PrrluJob *__restrict__ jobs) {
+    const PrrluJob j = jobs[blockIdx.x];
+    prrlu_glob_body(j.m, j.n, j.A, j.rmax, j.rel_tol2, j.rowpiv, j.colpiv, j.L, j.info, j.rowbuf, 0);
+}
+
 // Register-resident variant for blocks of at most 1024 * E entries: every thread keeps its
 // entries (linear index tid + 1024 l) in registers and walks their (row, column) pairs
 // incrementally; per pivot only the pivot row and column go through LDS. Two barriers per
 // pivot: after the wave partials (every thread then reduces the 16 partials itself) and after
 // the pivot row/column are published.
 template <int E>
-__global__ __launch_bounds__(1024) void k_prrlu_reg(int m, int n, const double *__restrict__ A, int rmax,
-                                                    double rel_tol2, int *__restrict__ rowpiv, int *__restrict__ colpiv,
-                                                    double *__restrict__ L, double *__restrict__ info) {
+__device__ __forceinline__ void prrlu_reg_body(int m, int n, const double *__restrict__ A, int rmax,
+                                               double rel_tol2, int *__restrict__ rowpiv, int *__restrict__ colpiv,
+                                               double *__restrict__ L, double *__restrict__ info) {
     extern __shared__ double sm[];
     double *colv = sm, *rowv = sm + m;
     __shared__ double wmax[16], wsum[16];
@@ -519,6 +531,20 @@ __global__ __launch_bounds__(1024) void k_prrlu_reg(int m, int n, const double *
         for (int i = tid; i < m; i += blockDim.x) L[(long long)i * rmax] = (i == 0) ? 1.0 : 0.0;
 }
 
+template <int E>
+__global__ __launch_bounds__(1024) void k_prrlu_reg(int m, int n, const double *__restrict__ A, int rmax,
+                                                    double rel_tol2, int *__restrict__ rowpiv, int *__restrict__ colpiv,
+                                                    double *__restrict__ L, double *__restrict__ info) {
+    prrlu_reg_body<E>(m, n, A, rmax, rel_tol2, rowpiv, colpiv, L, info);
+}
+
+// One workgroup per job: the pivot searches of a batch of independent cross blocks.
+template <int E>
+__global__ __launch_bounds__(1024) void k_prrlu_reg_batch(const PrrluJob *__restrict__ jobs) {
+    const PrrluJob j = jobs[blockIdx.x];
+    prrlu_reg_body<E>(j.m, j.n, j.A, j.rmax, j.rel_tol2, j.rowpiv, j.colpiv, j.L, j.info);
+}
+
 // Row i of X solves x L_I = L[i, :r] with L_I = L[rowpiv, :r] unit lower triangular in pivot
 // order (entry (s, t) is zero for t > s and one for t = s: the pivot rows were eliminated).
 __global__ void k_interp(int m, int r, const double *__restrict__ L, int ldl, const int *__restrict__ rowpiv,
@@ -545,12 +571,9 @@ __global__ void k_interp_exact_rows(int r, const int *__restrict__ rowpiv, doubl
 // X = R^{-1} with G = R^T R (upper Cholesky factor) of a nearly orthonormal basis's Gram
 // matrix, one workgroup per matrix. A column whose squared norm is below 1/2 is a padding
 // zero column: it keeps a unit diagonal and no coupling, so it stays zero after U X.
-__global__ __launch_bounds__(256) void k_chol_inv(int r, const double *__restrict__ Gin, double *__restrict__ Xout,
-                                                  double *__restrict__ Rws) {
-    const int z = blockIdx.x, tid = threadIdx.x;
-    const double *G = Gin + (long long)z * r * r;
-    double *R = Rws + (long long)z * r * r;
-    double *X = Xout + (long long)z * r * r;
+__device__ __forceinline__ void chol_inv_body(int r, const double *__restrict__ G, double *__restrict__ X,
+                                              double *__restrict__ R) {
+    const int tid = threadIdx.x;
     __shared__ double diag;
     __shared__ int zero_col;
     for (int e = tid; e < r * r; e += blockDim.x) R[e] = 0.0;
@@ -584,6 +607,40 @@ __global__ __launch_bounds__(256) void k_chol_inv(int r, const double *__restric
             X[(long long)j * r + i] = v / R[(long long)j * r + j];
         }
     }
+}
+
+__global__ __launch_bounds__(256) void k_chol_inv(int r, const double *__restrict__ Gin, double *__restrict__ Xout,
+                                                  double *__restrict__ Rws) {
+    const long long off = (long long)blockIdx.x * r * r;
+    chol_inv_body(r, Gin + off, Xout + off, Rws + off);
+}
+
+// grid (jobs, components): job j holds ncomp matrices of size r_j x r_j
+__global__ __launch_bounds__(256) void k_chol_inv_batch(const CholJob *__restrict__ jobs) {
+    const CholJob j = jobs[blockIdx.x];
+    if ((int)blockIdx.y >= j.batch) return;
+    const long long off = (long long)blockIdx.y * j.r * j.r;
+    chol_inv_body(j.r, j.G + off, j.X + off, j.R + off);
+}
+
+// grid (jobs, components): one-sided Jacobi of the n_j x n_j matrices of a batch of jobs in LDS
+__global__ __launch_bounds__(1024) void k_jacobi_lds_batch(const SvdJob *__restrict__ jobs) {
+    extern __shared__ double sm[];
+    __shared__ int nrot;
+    __shared__ double sig_tmp[512];
+    const SvdJob j = jobs[blockIdx.x];
+    if ((int)blockIdx.y >= j.batch) return;
+    const int n = j.n, z = blockIdx.y, tid = threadIdx.x;
+    double *A = sm, *V = sm + (long long)n * n;
+    const double *Az = j.A + (long long)z * n * n;
+    for (int e = tid; e < n * n; e += blockDim.x) {
+        int i = e / n, jj = e % n;
+        A[jj * n + i] = Az[e];
+        V[jj * n + i] = (i == jj) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    jacobi_sweeps(n, A, V, &nrot);
+    jacobi_finish(n, A, V, sig_tmp, j.sigma + (long long)z * n, j.V + (long long)z * n * n, nullptr);
 }
 
 inline unsigned cdiv(long long a, long long b) { return (unsigned)((a + b - 1) / b); }
@@ -726,6 +783,44 @@ void gemm_tn_splitk(hipStream_t s, int M, int N, int K, const double *A, int lda
 
 size_t gemm_tn_splitk_part(int M, int N, int K, int batch) {
     return (size_t)M * N * ((K + 63) / 64) * batch;
+}
+
+void prrlu_batch(hipStream_t s, int njobs, const PrrluJob *host_jobs, PrrluJob *dev_jobs) {
+    if (njobs <= 0) return;
+    long long maxtot = 0;
+    int maxm = 0, maxn = 0;
+    for (int i = 0; i < njobs; ++i) {
+        maxtot = std::max(maxtot, (long long)host_jobs[i].m * host_jobs[i].n);
+        maxm = std::max(maxm, host_jobs[i].m);
+        maxn = std::max(maxn, host_jobs[i].n);
+    }
+    const size_t lds_rc = sizeof(double) * (size_t)(maxm + maxn);
+    if (lds_rc <= 48 * 1024 && maxtot <= 1024 * 32) {
+        if (maxtot <= 1024 * 8) k_prrlu_reg_batch<8><<<njobs, 1024, lds_rc, s>>>(dev_jobs);
+        else if (maxtot <= 1024 * 16) k_prrlu_reg_batch<16><<<njobs, 1024, lds_rc, s>>>(dev_jobs);
+        else k_prrlu_reg_batch<32><<<njobs, 1024, lds_rc, s>>>(dev_jobs);
+    } else {
+        k_prrlu_batch<<<njobs, 1024, 0, s>>>(dev_jobs);
+    }
+    WTT_HIP(hipGetLastError());
+}
+
+bool jacobi_batch_fits(int nmax) {
+    const size_t lds = sizeof(double) * 2 * (size_t)nmax * nmax;
+    return nmax <= 512 && lds + 512 * sizeof(double) + 64 <= (size_t)lds_limit_bytes();
+}
+
+void jacobi_svd_batch(hipStream_t s, int njobs, int ncomp, int nmax, const SvdJob *dev_jobs) {
+    if (njobs <= 0) return;
+    const size_t lds = sizeof(double) * 2 * (size_t)nmax * nmax;
+    k_jacobi_lds_batch<<<dim3(njobs, ncomp), 1024, lds, s>>>(dev_jobs);
+    WTT_HIP(hipGetLastError());
+}
+
+void chol_upper_inv_batch(hipStream_t s, int njobs, int ncomp, const CholJob *dev_jobs) {
+    if (njobs <= 0) return;
+    k_chol_inv_batch<<<dim3(njobs, ncomp), 256, 0, s>>>(dev_jobs);
+    WTT_HIP(hipGetLastError());
 }
 
 }  // namespace wtt

@@ -23,7 +23,7 @@ EXPORTED = ["wenott_default_opts", "wenott_init", "wenott_rhs", "wenott_rk3_step
             "wenott_strerror", "wenott_dense_init", "wenott_dense_max_wavespeed", "wenott_dense_rhs",
             "wenott_dense_rk3_step", "wenott_dense_destroy", "wenott_mlp_nparams", "wenott_mlp_workspace",
             "wenott_mlp_init_params", "wenott_mlp_forward", "wenott_mlp_loss_grad", "wenott_mlp_adam_step",
-            "wenott_set_proposal", "wenott_set_cross_logging", "wenott_get_cross_log"]
+            "wenott_set_proposal", "wenott_set_cross_logging", "wenott_get_cross_log", "wenott_batch_rk3_step"]
 
 MLP_IN, MLP_HID, MLP_OUT, MLP_RANK_CLASSES, MLP_BINS = 96, 128, 81, 17, 64
 
@@ -81,6 +81,7 @@ def load(path: str = LIB_PATH):
                                 P(wenott_opts), vp]
     lib.wenott_rhs.argtypes = [vp, ctypes.c_double, P(wenott_tt)]
     lib.wenott_rk3_step.argtypes = [vp, ctypes.c_double, ctypes.c_double, P(ctypes.c_double)]
+    lib.wenott_batch_rk3_step.argtypes = [P(vp), ctypes.c_int32, P(ctypes.c_double), P(ctypes.c_double)]
     lib.wenott_round.argtypes = [vp, ctypes.c_double]
     lib.wenott_to_dense.argtypes = [vp, vp, ctypes.c_int32]
     lib.wenott_get_state.argtypes = [vp, P(wenott_tt)]
@@ -111,7 +112,7 @@ def load(path: str = LIB_PATH):
     lib.wenott_set_proposal.argtypes = [vp, vp]
     lib.wenott_set_cross_logging.argtypes = [vp, ctypes.c_int32]
     lib.wenott_get_cross_log.argtypes = [vp, vp, vp, vp, ctypes.c_int32, P(ctypes.c_int32)]
-    for name in ("wenott_init", "wenott_rhs", "wenott_rk3_step", "wenott_round", "wenott_to_dense",
+    for name in ("wenott_init", "wenott_rhs", "wenott_rk3_step", "wenott_batch_rk3_step", "wenott_round", "wenott_to_dense",
                  "wenott_get_state", "wenott_get_info", "wenott_max_wavespeed", "wenott_current_eps",
                  "wenott_set_profiling", "wenott_dense_init", "wenott_dense_max_wavespeed", "wenott_dense_rhs",
                  "wenott_dense_rk3_step", "wenott_mlp_init_params", "wenott_mlp_forward", "wenott_mlp_loss_grad",
@@ -198,6 +199,17 @@ def wenott_rhs(ctx, alpha=0.0):
 def wenott_rk3_step(ctx, dt, eps=0.0, alphas=None):
     a = None if alphas is None else (ctypes.c_double * 3)(*[float(x) for x in alphas])
     _check(load().wenott_rk3_step(ctx, float(dt), float(eps), a), ctx)
+
+
+def wenott_batch_rk3_step(ctxs, dts, eps=None):
+    """One SSP-RK3 step of each of len(ctxs) states in lock-step (one stream, same ndim)."""
+    n = len(ctxs)
+    if n == 0 or len(dts) != n or (eps is not None and len(eps) != n):
+        raise ValueError("ctxs, dts and eps must have the same non-zero length")
+    arr = (ctypes.c_void_p * n)(*ctxs)
+    d = (ctypes.c_double * n)(*[float(x) for x in dts])
+    e = None if eps is None else (ctypes.c_double * n)(*[float(x) for x in eps])
+    _check(load().wenott_batch_rk3_step(arr, n, d, e), ctxs[0])
 
 
 def wenott_round(ctx, eps):

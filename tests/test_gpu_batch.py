@@ -1,0 +1,132 @@
+"""Lock-step batched stepping of many independent states (needs a GPU).
+
+The batched call advances every state by one SSP-RK3 step with the same algorithm as the
+single-state step; it only regroups the launches and host synchronisations. Each state is
+checked against the oracle step for step (the per-step bound of the single-state tests) and
+against the same state stepped on its own.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from tests.gpu_util import oracle_problem, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def W():
+    from paper_2405_12301_amd import wenott
+    wenott.load()
+    oracle.build(force=False)
+    return wenott
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _flows(ndim):
+    if ndim == 2:
+        return [workloads.config2_quadrants_2d(64, seed=2), workloads.config2_quadrants_2d(48, seed=5),
+                workloads.config1_smooth_wave_2d(40), workloads.config2_quadrants_2d(96, seed=9)]
+    return [workloads.config3_wave_3d(24, seed=0, modes=8), workloads.sod_1d_like(3, 32)]
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_batch_matches_oracle_and_single_steps(W, ndim):
+    _say("case: batched rk3 steps, ndim", ndim)
+    flows = _flows(ndim)
+    eps = 1e-8
+    opts = W.default_opts(eps_mode=0, eps0=eps)
+    batch = [W.Solver(f, opts) for f in flows]
+    single = [W.Solver(f, opts) for f in flows]
+    try:
+        probs = [oracle_problem(f) for f in flows]
+        for step in range(2):
+            us = [s.dense() for s in batch]
+            dts = [0.5 * min(P.h) / P.alpha(u) for P, u in zip(probs, us)]
+            W.wenott_batch_rk3_step([s.ctx for s in batch], dts)
+            for i, (s, s1, P, u, dt) in enumerate(zip(batch, single, probs, us, dts)):
+                info = s.info()
+                P.ssprk3(u, dt, alphas=[info.alpha[j] for j in range(3)])
+                got = s.dense()
+                err = rel_err(got, u)
+                s1.step(dt)
+                d1 = rel_err(got, s1.dense())
+                _say(f"  step {step} state {i} n={flows[i].n} ranks={list(info.ranks)[:ndim + 1]} "
+                     f"sweeps={[info.sweeps[j][0] for j in range(3)]} err={err:.3e} vs-single={d1:.3e}")
+                assert info.sweeps[0][0] >= 1 and info.fiber_points > 0
+                assert err <= 10 * eps, (i, err)
+                assert d1 <= 10 * eps, (i, d1)
+    finally:
+        for s in batch + single:
+            s.close()
+
+
+def test_batch_of_one_equals_single_step(W):
+    _say("case: batch of one state")
+    f = workloads.config2_quadrants_2d(64, seed=3)
+    opts = W.default_opts(eps_mode=0, eps0=1e-8)
+    a, b = W.Solver(f, opts), W.Solver(f, opts)
+    try:
+        dt = 0.5 * min(f.h) / a.max_wavespeed()
+        W.wenott_batch_rk3_step([a.ctx], [dt])
+        b.step(dt)
+        assert np.array_equal(a.dense(), b.dense())
+    finally:
+        a.close()
+        b.close()
+
+
+def test_batch_rejects_mixed_inputs_and_leaves_states(W):
+    _say("case: batched step argument checks")
+    f2 = workloads.config2_quadrants_2d(32, seed=1)
+    f3 = workloads.sod_1d_like(3, 16)
+    s2 = W.Solver(f2, W.default_opts(eps_mode=0, eps0=1e-8))
+    s3 = W.Solver(f3, W.default_opts(eps_mode=0, eps0=1e-8))
+    s1 = W.Solver(f2, W.default_opts(eps_mode=0, eps0=1e-8, scheme=1))
+    try:
+        before = s2.dense()
+        with pytest.raises(W.WenottError):
+            W.wenott_batch_rk3_step([s2.ctx, s3.ctx], [1e-3, 1e-3])
+        with pytest.raises(W.WenottError):
+            W.wenott_batch_rk3_step([s2.ctx, s1.ctx], [1e-3, 1e-3])
+        with pytest.raises(W.WenottError):
+            W.wenott_batch_rk3_step([s2.ctx, s2.ctx], [1e-3, 1e-3])
+        with pytest.raises(W.WenottError):
+            W.wenott_batch_rk3_step([s2.ctx], [-1.0])
+        assert np.array_equal(before, s2.dense())
+    finally:
+        for s in (s1, s2, s3):
+            s.close()
+
+
+def test_batch_of_blasts_small_grids(W):
+    """Spherical blasts of the batched workload's kind on grids the oracle steps in seconds
+    (uneven sizes from {16, 24, 32}^3), two steps in lock-step, each state against the oracle."""
+    _say("case: batch of 6 small blasts")
+    rng = np.random.default_rng(11)
+    flows = [workloads.config4_blast_3d(seed=20 + i, n=tuple(int(x) for x in rng.choice([16, 24, 32], size=3)),
+                                        width=0.04) for i in range(6)]
+    eps = 1e-8
+    solvers = [W.Solver(f, W.default_opts(eps_mode=0, eps0=eps)) for f in flows]
+    try:
+        probs = [oracle_problem(f) for f in flows]
+        for step in range(2):
+            us = [s.dense() for s in solvers]
+            dts = [0.5 * min(P.h) / P.alpha(u) for P, u in zip(probs, us)]
+            W.wenott_batch_rk3_step([s.ctx for s in solvers], dts)
+            for i, (s, P, u, dt) in enumerate(zip(solvers, probs, us, dts)):
+                info = s.info()
+                P.ssprk3(u, dt, alphas=[info.alpha[j] for j in range(3)])
+                err = rel_err(s.dense(), u)
+                _say(f"  step {step} blast {i} n={flows[i].n} ranks={list(info.ranks)[:4]} err={err:.3e}")
+                assert err <= 10 * eps, (i, err)
+    finally:
+        for s in solvers:
+            s.close()
