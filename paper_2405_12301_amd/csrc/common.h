@@ -83,8 +83,14 @@ void jacobi_svd(hipStream_t s, int n, int batch, const double *A, double *sigma,
 // Stops when the residual's squared Frobenius norm <= rel_tol2 * (initial squared norm), after
 // rmax pivots, or at a zero residual. Writes rank (>= 1), row/col pivots, L columns (m x rmax, row-major) and the final
 // residual norm^2 into info[0..1] = {rank, resid2} (as doubles).
-void prrlu(hipStream_t s, int m, int n, double *A, int rmax, double rel_tol2, int *rowpiv, int *colpiv, double *L,
-           double *info, double *rowbuf);
+// ws: prrlu_ws_doubles(m, n) doubles (pivot row, per-workgroup partials and control of the
+// multi-workgroup form used when the block does not fit one workgroup's registers). That form
+// runs one launch per pivot step: this call launches steps t_begin..min(t_end, rmax) and returns
+// the next step; info[0] stays negative until the factorisation has stopped, and the caller
+// continues from the returned step. The register form finishes in one call (t_begin = 0).
+int prrlu(hipStream_t s, int m, int n, double *A, int rmax, double rel_tol2, int *rowpiv, int *colpiv, double *L,
+          double *info, double *ws, int t_begin, int t_end);
+size_t prrlu_ws_doubles(int m, int n);
 
 // X = R^{-1} for the upper Cholesky factor R of each r x r Gram matrix G (batch); ws holds
 // batch * r * r doubles. Zero (padding) columns keep a unit diagonal.
@@ -97,8 +103,10 @@ struct PrrluJob {
     int m, n, rmax;
     double rel_tol2;
     int *rowpiv, *colpiv;
-    double *L, *info, *rowbuf;
+    double *L, *info, *ws;  // ws: prrlu_ws_doubles(m, n) doubles
+    int rows, nblk, mode;   // set by prrlu_prepare: rows per workgroup, workgroups, 0 register / 1 multi-workgroup
 };
+void prrlu_prepare(PrrluJob &j);
 struct SvdJob {
     const double *A;
     double *sigma, *V;
@@ -109,7 +117,9 @@ struct CholJob {
     double *X, *R;
     int r, batch;
 };
-void prrlu_batch(hipStream_t s, int njobs, const PrrluJob *host_jobs, PrrluJob *dev_jobs);
+// Launches the register jobs (t_begin = 0) and steps t_begin..t_end of the multi-workgroup jobs.
+void prrlu_batch(hipStream_t s, int njobs, const PrrluJob *host_jobs, const PrrluJob *dev_jobs, int t_begin,
+                 int t_end);
 bool jacobi_batch_fits(int nmax);
 void jacobi_svd_batch(hipStream_t s, int njobs, int ncomp, int nmax, const SvdJob *dev_jobs);
 void chol_upper_inv_batch(hipStream_t s, int njobs, int ncomp, const CholJob *dev_jobs);

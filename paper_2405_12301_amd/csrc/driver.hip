@@ -195,6 +195,7 @@ struct wenott_ctx {
         std::vector<int> useful;  // right multi-indices whose columns were pivots (len d-1-k each)
     };
     BondHist bond[kMaxDim];
+    int piv_hist[(kMaxDim + 1) * 2 * kMaxDim];  // last pivot rank per (cross slot, sweep direction, core)
     float last_sig[16] = {};
     int prev_sweeps = 1;
     double prev_resid = 0.0;
@@ -399,20 +400,38 @@ struct PivotResult {
     std::vector<int> rows, cols;
 };
 
-PivotResult pivots(wenott_ctx *c, double *B, int m, int n, double rel_tol2, double **Lout) {
+inline int hist_index(int slot, int dir, int k) { return (slot * 2 + dir) * kMaxDim + k; }
+
+// First number of pivot steps to launch for a block: the rank this bond had the last time,
+// with a margin, else the number of index tuples on the block's column side.
+int pivot_guess(const wenott_ctx *c, int hist_slot, int n, int rmax) {
+    const int h = hist_slot >= 0 ? c->piv_hist[hist_slot] : -1;
+    const int g = h > 0 ? h + std::max(2, h / 4) : n / std::max(c->U.nc, 1);
+    return std::max(1, std::min(g, rmax));
+}
+
+PivotResult pivots(wenott_ctx *c, double *B, int m, int n, double rel_tol2, double **Lout, int hist_slot) {
     int rmax = std::min(std::min(c->o.rank_cap, kMaxRankLds), std::min(m, n));
     int *piv = c->sc.get<int>(S_PIV, 2 * (size_t)rmax + 2);
     double *L = c->sc.get<double>(S_L, (size_t)m * rmax);
     double *info = c->sc.get<double>(S_INFO, 2);
-    double *rowbuf = c->sc.get<double>(S_ROWBUF, n);
+    double *ws = c->sc.get<double>(S_ROWBUF, prrlu_ws_doubles(m, n));
     ev_record(c, KC_PIVOT);
-    prrlu(c->s, m, n, B, rmax, rel_tol2, piv, piv + rmax, L, info, rowbuf);
+    int next = prrlu(c->s, m, n, B, rmax, rel_tol2, piv, piv + rmax, L, info, ws, 0, pivot_guess(c, hist_slot, n, rmax));
     ev_record(c, KC_PIVOT);
-    WTT_HIP(hipMemcpyAsync(c->h_pinned_dbl, info, 2 * sizeof(double), hipMemcpyDeviceToHost, c->s));
-    WTT_HIP(hipMemcpyAsync(c->h_pinned_int, piv, 2 * rmax * sizeof(int), hipMemcpyDeviceToHost, c->s));
-    WTT_HIP(hipStreamSynchronize(c->s));
+    for (;;) {
+        WTT_HIP(hipMemcpyAsync(c->h_pinned_dbl, info, 2 * sizeof(double), hipMemcpyDeviceToHost, c->s));
+        WTT_HIP(hipMemcpyAsync(c->h_pinned_int, piv, 2 * rmax * sizeof(int), hipMemcpyDeviceToHost, c->s));
+        WTT_HIP(hipStreamSynchronize(c->s));
+        if (c->h_pinned_dbl[0] >= 0.0) break;
+        WTT_REQUIRE(next <= rmax, WENOTT_EHIP, "pivot search did not stop");
+        ev_record(c, KC_PIVOT);
+        next = prrlu(c->s, m, n, B, rmax, rel_tol2, piv, piv + rmax, L, info, ws, next, next + std::max(8, next / 2));
+        ev_record(c, KC_PIVOT);
+    }
     PivotResult r;
     r.rank = (int)c->h_pinned_dbl[0];
+    if (hist_slot >= 0) c->piv_hist[hist_slot] = r.rank;
     r.cols.assign(c->h_pinned_int + rmax, c->h_pinned_int + rmax + r.rank);
     c->info.pivots_total += r.rank;
     {  // full-pivot elimination to rank r: sum_t 2 (m - t)(n - t) flops; the block is read once, L written
@@ -422,7 +441,6 @@ PivotResult pivots(wenott_ctx *c, double *B, int m, int n, double rel_tol2, doub
     }
     r.rows.assign(c->h_pinned_int, c->h_pinned_int + r.rank);
     *Lout = L;
-    (void)rmax;
     return r;
 }
 
@@ -645,7 +663,7 @@ FluxTT cross_generic(wenott_ctx *c, const CrossTarget &t, double eps, CrossStat 
             t.eval(k, Lset[k], Rk, true, B);
             if (k < d - 1) {
                 double *L = nullptr;
-                PivotResult pr = pivots(c, B, (int)rows, (int)cols, rel2, &L);
+                PivotResult pr = pivots(c, B, (int)rows, (int)cols, rel2, &L, hist_index(t.warm_slot, 0, k));
                 if (t.learn) {
                     usedR[k] = Rk;
                     usedC[k] = pr.cols;
@@ -682,7 +700,7 @@ FluxTT cross_generic(wenott_ctx *c, const CrossTarget &t, double eps, CrossStat 
             double *B = c->sc.get<double>(S_BLOCK, (size_t)(rows * cols));
             t.eval(k, Lk, Rk, false, B);
             double *L = nullptr;
-            PivotResult pr = pivots(c, B, (int)rows, (int)cols, rel2, &L);
+            PivotResult pr = pivots(c, B, (int)rows, (int)cols, rel2, &L, hist_index(t.warm_slot, 1, k));
             ISet nr;
             nr.len = d - k;
             nr.count = pr.rank;
@@ -1165,34 +1183,61 @@ struct BState {
     int nb_acc = 0;
 };
 
-// One batched pivot phase over the states with a non-null block: prrLU of each block.
-void batch_pivots(std::vector<BState *> &act) {
+// One batched pivot phase over the given states: prrLU of each state's block. The register
+// jobs finish in the first launch; the multi-workgroup jobs run in chunks of pivot steps, each
+// chunk followed by one synchronisation, until every job has stopped.
+void batch_pivots(std::vector<BState *> &act, int dir, int k) {
     if (act.empty()) return;
     wenott_ctx *c0 = act[0]->c;
     std::vector<PrrluJob> jobs;
+    int t_end = 0;
     for (BState *b : act) {
         wenott_ctx *c = b->c;
         b->rmax = std::min(std::min(c->o.rank_cap, kMaxRankLds), std::min(b->m, b->n));
         b->piv = c->sc.get<int>(S_PIV, 2 * (size_t)b->rmax + 2);
         b->L = c->sc.get<double>(S_L, (size_t)b->m * b->rmax);
         b->info = c->sc.get<double>(S_INFO, 2);
-        PrrluJob j;
+        PrrluJob j{};
         j.A = b->B; j.m = b->m; j.n = b->n; j.rmax = b->rmax; j.rel_tol2 = b->rel2;
         j.rowpiv = b->piv; j.colpiv = b->piv + b->rmax; j.L = b->L; j.info = b->info;
-        j.rowbuf = c->sc.get<double>(S_ROWBUF, b->n);
+        j.ws = c->sc.get<double>(S_ROWBUF, prrlu_ws_doubles(b->m, b->n));
+        prrlu_prepare(j);
+        if (j.mode == 1) t_end = std::max(t_end, pivot_guess(c, hist_index(kMaxDim, dir, k), b->n, b->rmax));
         jobs.push_back(j);
     }
-    PrrluJob *dj = c0->ring.put(jobs.data(), jobs.size());
-    ev_record(c0, KC_PIVOT);
-    prrlu_batch(c0->s, (int)jobs.size(), jobs.data(), dj);
-    ev_record(c0, KC_PIVOT);
-    for (BState *b : act) {
-        WTT_HIP(hipMemcpyAsync(b->c->h_pinned_dbl, b->info, 2 * sizeof(double), hipMemcpyDeviceToHost, b->c->s));
-        WTT_HIP(hipMemcpyAsync(b->c->h_pinned_int, b->piv, 2 * b->rmax * sizeof(int), hipMemcpyDeviceToHost, b->c->s));
+    int t_begin = 0;
+    std::vector<size_t> open(act.size());
+    for (size_t z = 0; z < act.size(); ++z) open[z] = z;
+    for (;;) {
+        std::vector<PrrluJob> hj;
+        for (size_t z : open) hj.push_back(jobs[z]);
+        const PrrluJob *dj = c0->ring.put(hj.data(), hj.size());
+        ev_record(c0, KC_PIVOT);
+        prrlu_batch(c0->s, (int)hj.size(), hj.data(), dj, t_begin, t_end);
+        ev_record(c0, KC_PIVOT);
+        for (size_t z : open) {
+            BState *b = act[z];
+            WTT_HIP(hipMemcpyAsync(b->c->h_pinned_dbl, b->info, 2 * sizeof(double), hipMemcpyDeviceToHost, b->c->s));
+            WTT_HIP(hipMemcpyAsync(b->c->h_pinned_int, b->piv, 2 * b->rmax * sizeof(int), hipMemcpyDeviceToHost,
+                                   b->c->s));
+        }
+        WTT_HIP(hipStreamSynchronize(c0->s));
+        std::vector<size_t> still;
+        int rmax_open = 0;
+        for (size_t z : open)
+            if (act[z]->c->h_pinned_dbl[0] < 0.0) {
+                still.push_back(z);
+                rmax_open = std::max(rmax_open, act[z]->rmax);
+            }
+        if (still.empty()) break;
+        t_begin = t_end + 1;
+        WTT_REQUIRE(t_begin <= rmax_open, WENOTT_EHIP, "pivot search did not stop");
+        t_end = std::min(rmax_open, t_begin + std::max(8, t_begin / 2));
+        open = std::move(still);
     }
-    WTT_HIP(hipStreamSynchronize(c0->s));
     for (BState *b : act) {
         const int r = (int)b->c->h_pinned_dbl[0];
+        b->c->piv_hist[hist_index(kMaxDim, dir, k)] = r;
         double fl = 0.0;
         for (int t = 0; t < r; ++t) fl += 2.0 * (double)(b->m - t) * (double)(b->n - t);
         add_work(b->c, KC_PIVOT, fl, 8.0 * ((double)b->m * b->n + (double)b->m * r));
@@ -1252,7 +1297,7 @@ void batch_cross(std::vector<BState> &bs, const double *aw, const double *bw, in
                 }
             }
             if (k == d - 1) break;
-            batch_pivots(act);
+            batch_pivots(act, 0, k);
             for (BState *b : act) {
                 const int r = (int)b->c->h_pinned_dbl[0];
                 std::vector<int> rows(b->c->h_pinned_int, b->c->h_pinned_int + r);
@@ -1297,7 +1342,7 @@ void batch_cross(std::vector<BState> &bs, const double *aw, const double *bw, in
                 const StageWeights w{aw[st], bw[st], bw[st] * b->dt};
                 eval_stage_block(b->c, b->X, &b->c->U, w, b->alpha, k, Lk[z], R, false, b->B);
             }
-            batch_pivots(refresh);
+            batch_pivots(refresh, 1, k);
             for (BState *b : refresh) {
                 const ISet &R = b->Rset[k];
                 const int r = (int)b->c->h_pinned_dbl[0], q = R.count;
@@ -1641,6 +1686,7 @@ wenott_status wenott_init(wenott_ctx **out, const wenott_tt *state, const wenott
         c->d = d;
         c->nc = d + 2;
         c->gamma = gamma;
+        std::fill(std::begin(c->piv_hist), std::end(c->piv_hist), -1);
         if (opts) c->o = *opts; else wenott_default_opts(&c->o);
         WTT_REQUIRE(c->o.graph_mode == 0, WENOTT_ENOTBUILT, "option not available");
         WTT_REQUIRE(c->o.use_proposal == 0 || c->o.use_proposal == 1, WENOTT_EINVAL, "use_proposal must be 0 or 1");

@@ -326,107 +326,188 @@ __global__ __launch_bounds__(1024) void k_jacobi_global(int n, const double *__r
 }
 
 // ------------------------------------------------------------------- prrLU (pivots)
-__device__ __forceinline__ void prrlu_glob_body(int m, int n, double *__restrict__ A, int rmax, double rel_tol2,
-                                                int *__restrict__ rowpiv, int *__restrict__ colpiv,
-                                                double *__restrict__ L, double *__restrict__ info,
-                                                double *__restrict__ rowbuf_g, int use_lds) {
-    extern __shared__ double rowbuf_s[];
-    __shared__ double wmax[16], wsum[16];
-    __shared__ long long widx[16];
-    __shared__ int s_stop, s_rank;
-    __shared__ long long s_idx;
-    __shared__ double s_piv, s_sum, s_tol2;
-    const int tid = threadIdx.x, lane = tid % kWave, w = tid / kWave, nw = blockDim.x / kWave;
-    double *rowbuf = use_lds ? rowbuf_s : rowbuf_g;
-    const long long tot = (long long)m * n;
-    const int step_i = blockDim.x / n, step_j = blockDim.x % n;
-    // local reduction of the current residual
+// Multi-workgroup variant for blocks too large for one workgroup's registers: one launch per
+// pivot step t. Each workgroup owns a run of whole rows; at step t it first applies the
+// elimination of pivot t-1 to its rows (writing column t-1 of L for them), then reduces its
+// rows' largest magnitude (ties to the lower linear index) and squared sum. The last workgroup
+// of a job to finish (ticket counter) combines the partials in workgroup order, takes the stop
+// decision of the single-workgroup forms and publishes pivot t and its row for the next launch.
+// Workspace (doubles): pivot row [n], partial max [nblk], partial sum [nblk], partial index
+// [nblk], control block, ticket.
+struct PrrluCtl {
+    long long idx;
+    double piv, tol2;
+    int stop, pad;
+};
+
+struct PrrluWs {
+    double *rowbuf, *pmax, *psum;
+    long long *pidx;
+    PrrluCtl *ctl;
+    unsigned *ticket;
+};
+
+__host__ __device__ inline PrrluWs prrlu_ws_split(double *ws, int n, int nblk) {
+    PrrluWs w;
+    w.rowbuf = ws;
+    w.pmax = ws + n;
+    w.psum = w.pmax + nblk;
+    w.pidx = (long long *)(w.psum + nblk);
+    w.ctl = (PrrluCtl *)(w.pidx + nblk);
+    w.ticket = (unsigned *)(w.ctl + 1);
+    return w;
+}
+
+constexpr int kMwThreads = 256, kMwElems = 8192, kMwMaxRows = 2048;
+
+__device__ __forceinline__ void prrlu_mw_init_body(const PrrluJob &J) {
+    const PrrluWs w = prrlu_ws_split(J.ws, J.n, J.nblk);
+    w.ctl->stop = 0;
+    w.ctl->idx = 0;
+    w.ctl->piv = 0.0;
+    w.ctl->tol2 = 0.0;
+    *w.ticket = 0u;
+    J.info[0] = -1.0;  // not finished: the host launches further steps
+}
+
+__device__ __forceinline__ void prrlu_mw_step_body(const PrrluJob &J, int t) {
+    __shared__ double lc[kMwMaxRows];
+    __shared__ double wmax[kMwThreads / kWave], wsum[kMwThreads / kWave];
+    __shared__ long long widx[kMwThreads / kWave];
+    __shared__ int s_last;
+    const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave;
+    const int m = J.m, n = J.n, rmax = J.rmax;
+    const PrrluWs w = prrlu_ws_split(J.ws, n, J.nblk);
+    double *__restrict__ A = J.A;
+    if (w.ctl->stop) return;
+    const int r0 = blockIdx.x * J.rows, nr = min(J.rows, m - r0);
+    int pi = -1, pj = -1;
+    if (t > 0) {
+        const long long pidx = w.ctl->idx;
+        pi = (int)(pidx / n);
+        pj = (int)(pidx % n);
+        const double piv = w.ctl->piv;
+        for (int ri = tid; ri < nr; ri += kMwThreads) {
+            const int i = r0 + ri;
+            const double l = (i == pi) ? 1.0 : A[(long long)i * n + pj] / piv;
+            lc[ri] = l;
+            J.L[(long long)i * rmax + (t - 1)] = l;
+        }
+        __syncthreads();
+    }
     double lmax = -1.0, lsum = 0.0;
-    long long lidx = 0;
-    {
-        int i = tid / n, j = tid % n;
-        for (long long e = tid; e < tot; e += blockDim.x) {
-            double v = A[e], av = fabs(v);
-            lsum += v * v;
-            if (av > lmax) { lmax = av; lidx = e; }
-            i += step_i; j += step_j;
-            if (j >= n) { j -= n; ++i; }
+    long long lidx = 0x7fffffffffffffffLL;
+    const long long base = (long long)r0 * n, cnt = (long long)nr * n;
+    const int step_i = kMwThreads / n, step_j = kMwThreads % n;
+    int ri = tid / n, j = tid % n;
+    for (long long e = tid; e < cnt; e += kMwThreads) {
+        double v = A[base + e];
+        if (t > 0) {
+            v = (r0 + ri == pi || j == pj) ? 0.0 : v - lc[ri] * w.rowbuf[j];
+            A[base + e] = v;
         }
+        const double av = fabs(v);
+        lsum += v * v;
+        if (av > lmax) { lmax = av; lidx = base + e; }
+        ri += step_i; j += step_j;
+        if (j >= n) { j -= n; ++ri; }
     }
-    int t = 0;
-    for (;; ++t) {
-        // wave then block argmax (ties to the lower linear index) and sum
-        for (int off = kWave / 2; off > 0; off >>= 1) {
-            double om = __shfl_xor(lmax, off, kWave);
-            long long oi = __shfl_xor(lidx, off, kWave);
-            double os = __shfl_xor(lsum, off, kWave);
-            if (om > lmax || (om == lmax && oi < lidx)) { lmax = om; lidx = oi; }
-            lsum += os;
-        }
-        if (lane == 0) { wmax[w] = lmax; widx[w] = lidx; wsum[w] = lsum; }
-        __syncthreads();
-        if (tid == 0) {
-            double bm = wmax[0], bs = 0.0;
-            long long bi = widx[0];
-            for (int k = 0; k < nw; ++k) {
-                bs += wsum[k];
-                if (wmax[k] > bm || (wmax[k] == bm && widx[k] < bi)) { bm = wmax[k]; bi = widx[k]; }
-            }
-            s_sum = bs;
-            if (t == 0) s_tol2 = rel_tol2 * bs;
-            int stop = (t >= rmax) || (bm <= 0.0) || (bs <= s_tol2);
-            if (t == 0 && bm <= 0.0) stop = 2;  // all-zero block
-            if (t == 0 && stop == 1) stop = 0;  // always take at least one pivot of a nonzero block
-            s_stop = stop;
-            s_idx = bi;
-            s_piv = stop ? 0.0 : A[bi];
-            s_rank = t;
-        }
-        __syncthreads();
-        if (s_stop) break;
-        const long long pidx = s_idx;
-        const int pi = (int)(pidx / n), pj = (int)(pidx % n);
-        const double piv = s_piv;
-        if (tid == 0) { rowpiv[t] = pi; colpiv[t] = pj; }
-        for (int j = tid; j < n; j += blockDim.x) rowbuf[j] = A[(long long)pi * n + j];
-        for (int i = tid; i < m; i += blockDim.x) L[(long long)i * rmax + t] = (i == pi) ? 1.0 : A[(long long)i * n + pj] / piv;
-        __syncthreads();
-        lmax = -1.0; lsum = 0.0; lidx = 0;
-        int i = tid / n, j = tid % n;
-        for (long long e = tid; e < tot; e += blockDim.x) {
-            double v = (i == pi || j == pj) ? 0.0 : A[e] - L[(long long)i * rmax + t] * rowbuf[j];
-            A[e] = v;
-            double av = fabs(v);
-            lsum += v * v;
-            if (av > lmax) { lmax = av; lidx = e; }
-            i += step_i; j += step_j;
-            if (j >= n) { j -= n; ++i; }
-        }
-        __syncthreads();
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        const double om = __shfl_xor(lmax, off, kWave);
+        const long long oi = __shfl_xor(lidx, off, kWave);
+        lsum += __shfl_xor(lsum, off, kWave);
+        if (om > lmax || (om == lmax && oi < lidx)) { lmax = om; lidx = oi; }
     }
+    if (lane == 0) { wmax[wv] = lmax; widx[wv] = lidx; wsum[wv] = lsum; }
+    __syncthreads();
     if (tid == 0) {
-        int rank = s_rank;
-        if (s_stop == 2) {  // zero block: rank-1 zero approximation with a unit basis vector
-            rank = 1;
-            rowpiv[0] = 0; colpiv[0] = 0;
+        double bm = wmax[0], bs = 0.0;
+        long long bi = widx[0];
+        for (int k = 0; k < kMwThreads / kWave; ++k) {
+            bs += wsum[k];
+            if (wmax[k] > bm || (wmax[k] == bm && widx[k] < bi)) { bm = wmax[k]; bi = widx[k]; }
         }
-        info[0] = (double)rank;
-        info[1] = s_sum;
+        w.pmax[blockIdx.x] = bm;
+        w.psum[blockIdx.x] = bs;
+        w.pidx[blockIdx.x] = bi;
+        __threadfence();  // release: this workgroup's rows and partials before its ticket
+        const unsigned prev = atomicAdd(w.ticket, 1u);
+        s_last = (prev == (unsigned)J.nblk - 1u);
     }
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();  // acquire: every workgroup's rows and partials
+    // combine the partials in workgroup order (the result does not depend on arrival order)
+    double bm = -1.0, bs = 0.0;
+    long long bi = 0x7fffffffffffffffLL;
+    for (int b = tid; b < J.nblk; b += kMwThreads) {
+        const double vm = w.pmax[b];
+        const long long vi = w.pidx[b];
+        bs += w.psum[b];
+        if (vm > bm || (vm == bm && vi < bi)) { bm = vm; bi = vi; }
+    }
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        const double om = __shfl_xor(bm, off, kWave);
+        const long long oi = __shfl_xor(bi, off, kWave);
+        bs += __shfl_xor(bs, off, kWave);
+        if (om > bm || (om == bm && oi < bi)) { bm = om; bi = oi; }
+    }
+    if (lane == 0) { wmax[wv] = bm; widx[wv] = bi; wsum[wv] = bs; }
+    __syncthreads();
+    __shared__ int s_stop;
+    __shared__ long long s_idx;
+    if (tid == 0) {
+        double gm = wmax[0], gs = 0.0;
+        long long gi = widx[0];
+        for (int k = 0; k < kMwThreads / kWave; ++k) {
+            gs += wsum[k];
+            if (wmax[k] > gm || (wmax[k] == gm && widx[k] < gi)) { gm = wmax[k]; gi = widx[k]; }
+        }
+        if (t == 0) w.ctl->tol2 = J.rel_tol2 * gs;
+        int stop = (t >= rmax) || (gm <= 0.0) || (gs <= w.ctl->tol2);
+        if (t == 0 && gm <= 0.0) stop = 2;  // all-zero block
+        if (t == 0 && stop == 1) stop = 0;  // always take at least one pivot of a nonzero block
+        if (stop) {
+            int rank = t;
+            if (stop == 2) {
+                rank = 1;
+                J.rowpiv[0] = 0; J.colpiv[0] = 0;
+            }
+            J.info[0] = (double)rank;
+            J.info[1] = gs;
+        } else {
+            J.rowpiv[t] = (int)(gi / n);
+            J.colpiv[t] = (int)(gi % n);
+            w.ctl->idx = gi;
+            w.ctl->piv = A[gi];
+        }
+        w.ctl->stop = stop;
+        *w.ticket = 0u;
+        s_stop = stop;
+        s_idx = gi;
+    }
+    __syncthreads();
     if (s_stop == 2)
-        for (int i = tid; i < m; i += blockDim.x) L[(long long)i * rmax] = (i == 0) ? 1.0 : 0.0;
+        for (int i = tid; i < m; i += kMwThreads) J.L[(long long)i * rmax] = (i == 0) ? 1.0 : 0.0;
+    if (!s_stop) {
+        const long long prow = (s_idx / n) * (long long)n;
+        for (int jj = tid; jj < n; jj += kMwThreads) w.rowbuf[jj] = A[prow + jj];
+    }
 }
 
-__global__ __launch_bounds__(1024) void k_prrlu(int m, int n, double *__restrict__ A, int rmax, double rel_tol2,
-                                                int *__restrict__ rowpiv, int *__restrict__ colpiv,
-                                                double *__restrict__ L, double *__restrict__ info,
-                                                double *__restrict__ rowbuf_g, int use_lds) {
-    prrlu_glob_body(m, n, A, rmax, rel_tol2, rowpiv, colpiv, L, info, rowbuf_g, use_lds);
+__global__ void k_prrlu_mw_init(PrrluJob J) { prrlu_mw_init_body(J); }
+
+__global__ __launch_bounds__(kMwThreads) void k_prrlu_mw_step(PrrluJob J, int t) { prrlu_mw_step_body(J, t); }
+
+__global__ void k_prrlu_mw_init_batch(const PrrluJob *__restrict__ jobs, int njobs) {
+    const int z = blockIdx.x * blockDim.x + threadIdx.x;
+    if (z < njobs && jobs[z].mode == 1) prrlu_mw_init_body(jobs[z]);
 }
 
-__global__ __launch_bounds__(1024) void k_prrlu_batch(const PrrluJob *__restrict__ jobs) {
-    const PrrluJob j = jobs[blockIdx.x];
-    prrlu_glob_body(j.m, j.n, j.A, j.rmax, j.rel_tol2, j.rowpiv, j.colpiv, j.L, j.info, j.rowbuf, 0);
+__global__ __launch_bounds__(kMwThreads) void k_prrlu_mw_step_batch(const PrrluJob *__restrict__ jobs, int t) {
+    const PrrluJob J = jobs[blockIdx.y];
+    if (J.mode != 1 || (int)blockIdx.x >= J.nblk) return;
+    prrlu_mw_step_body(J, t);
 }
 
 // Register-resident variant for blocks of at most 1024 * E entries: every thread keeps its
@@ -542,6 +623,7 @@ __global__ __launch_bounds__(1024) void k_prrlu_reg(int m, int n, const double *
 template <int E>
 __global__ __launch_bounds__(1024) void k_prrlu_reg_batch(const PrrluJob *__restrict__ jobs) {
     const PrrluJob j = jobs[blockIdx.x];
+    if (j.mode != 0) return;
     prrlu_reg_body<E>(j.m, j.n, j.A, j.rmax, j.rel_tol2, j.rowpiv, j.colpiv, j.L, j.info);
 }
 
@@ -733,19 +815,44 @@ void jacobi_svd(hipStream_t s, int n, int batch, const double *A, double *sigma,
     WTT_HIP(hipGetLastError());
 }
 
-void prrlu(hipStream_t s, int m, int n, double *A, int rmax, double rel_tol2, int *rowpiv, int *colpiv, double *L,
-           double *info, double *rowbuf) {
+bool prrlu_reg_fits(int m, int n) {
+    return (long long)m * n <= 1024 * 32 && sizeof(double) * (size_t)(m + n) <= 48 * 1024;
+}
+
+void prrlu_prepare(PrrluJob &j) {
+    j.rows = std::max(1, std::min(j.m, std::min(kMwMaxRows, kMwElems / std::max(j.n, 1))));
+    j.nblk = (j.m + j.rows - 1) / j.rows;
+    j.mode = prrlu_reg_fits(j.m, j.n) ? 0 : 1;
+}
+
+size_t prrlu_ws_doubles(int m, int n) {
+    PrrluJob j{};
+    j.m = m; j.n = n;
+    prrlu_prepare(j);
+    return (size_t)n + 3 * (size_t)j.nblk + 8;
+}
+
+int prrlu(hipStream_t s, int m, int n, double *A, int rmax, double rel_tol2, int *rowpiv, int *colpiv, double *L,
+          double *info, double *ws, int t_begin, int t_end) {
     const long long tot = (long long)m * n;
     const size_t lds_rc = sizeof(double) * (size_t)(m + n);
-    if (m < 32768 && n < 32768 && lds_rc <= 48 * 1024) {
-        if (tot <= 1024 * 8) { k_prrlu_reg<8><<<1, 1024, lds_rc, s>>>(m, n, A, rmax, rel_tol2, rowpiv, colpiv, L, info); WTT_HIP(hipGetLastError()); return; }
-        if (tot <= 1024 * 16) { k_prrlu_reg<16><<<1, 1024, lds_rc, s>>>(m, n, A, rmax, rel_tol2, rowpiv, colpiv, L, info); WTT_HIP(hipGetLastError()); return; }
-        if (tot <= 1024 * 32) { k_prrlu_reg<32><<<1, 1024, lds_rc, s>>>(m, n, A, rmax, rel_tol2, rowpiv, colpiv, L, info); WTT_HIP(hipGetLastError()); return; }
+    if (prrlu_reg_fits(m, n)) {
+        if (t_begin > 0) return rmax + 1;
+        if (tot <= 1024 * 8) k_prrlu_reg<8><<<1, 1024, lds_rc, s>>>(m, n, A, rmax, rel_tol2, rowpiv, colpiv, L, info);
+        else if (tot <= 1024 * 16) k_prrlu_reg<16><<<1, 1024, lds_rc, s>>>(m, n, A, rmax, rel_tol2, rowpiv, colpiv, L, info);
+        else k_prrlu_reg<32><<<1, 1024, lds_rc, s>>>(m, n, A, rmax, rel_tol2, rowpiv, colpiv, L, info);
+        WTT_HIP(hipGetLastError());
+        return rmax + 1;
     }
-    int use_lds = n <= 4096;
-    size_t lds = use_lds ? sizeof(double) * (size_t)n : 0;
-    k_prrlu<<<1, 1024, lds, s>>>(m, n, A, rmax, rel_tol2, rowpiv, colpiv, L, info, rowbuf, use_lds);
+    PrrluJob j{};
+    j.A = A; j.m = m; j.n = n; j.rmax = rmax; j.rel_tol2 = rel_tol2;
+    j.rowpiv = rowpiv; j.colpiv = colpiv; j.L = L; j.info = info; j.ws = ws;
+    prrlu_prepare(j);
+    if (t_begin == 0) k_prrlu_mw_init<<<1, 1, 0, s>>>(j);
+    const int last = std::min(t_end, rmax);
+    for (int t = t_begin; t <= last; ++t) k_prrlu_mw_step<<<j.nblk, kMwThreads, 0, s>>>(j, t);
     WTT_HIP(hipGetLastError());
+    return last + 1;
 }
 
 void interp_solve(hipStream_t s, int m, int r, const double *L, int ldl, const int *rowpiv, double *X) {
@@ -785,22 +892,33 @@ size_t gemm_tn_splitk_part(int M, int N, int K, int batch) {
     return (size_t)M * N * ((K + 63) / 64) * batch;
 }
 
-void prrlu_batch(hipStream_t s, int njobs, const PrrluJob *host_jobs, PrrluJob *dev_jobs) {
+void prrlu_batch(hipStream_t s, int njobs, const PrrluJob *host_jobs, const PrrluJob *dev_jobs, int t_begin,
+                 int t_end) {
     if (njobs <= 0) return;
     long long maxtot = 0;
-    int maxm = 0, maxn = 0;
+    int maxm = 0, maxn = 0, maxblk = 0, nreg = 0, nmw = 0;
     for (int i = 0; i < njobs; ++i) {
-        maxtot = std::max(maxtot, (long long)host_jobs[i].m * host_jobs[i].n);
-        maxm = std::max(maxm, host_jobs[i].m);
-        maxn = std::max(maxn, host_jobs[i].n);
+        const PrrluJob &j = host_jobs[i];
+        if (j.mode == 0) {
+            maxtot = std::max(maxtot, (long long)j.m * j.n);
+            maxm = std::max(maxm, j.m);
+            maxn = std::max(maxn, j.n);
+            ++nreg;
+        } else {
+            maxblk = std::max(maxblk, j.nblk);
+            ++nmw;
+        }
     }
-    const size_t lds_rc = sizeof(double) * (size_t)(maxm + maxn);
-    if (lds_rc <= 48 * 1024 && maxtot <= 1024 * 32) {
+    if (nreg && t_begin == 0) {
+        const size_t lds_rc = sizeof(double) * (size_t)(maxm + maxn);
         if (maxtot <= 1024 * 8) k_prrlu_reg_batch<8><<<njobs, 1024, lds_rc, s>>>(dev_jobs);
         else if (maxtot <= 1024 * 16) k_prrlu_reg_batch<16><<<njobs, 1024, lds_rc, s>>>(dev_jobs);
         else k_prrlu_reg_batch<32><<<njobs, 1024, lds_rc, s>>>(dev_jobs);
-    } else {
-        k_prrlu_batch<<<njobs, 1024, 0, s>>>(dev_jobs);
+    }
+    if (nmw) {
+        if (t_begin == 0) k_prrlu_mw_init_batch<<<cdiv(njobs, 64), 64, 0, s>>>(dev_jobs, njobs);
+        for (int t = t_begin; t <= t_end; ++t)
+            k_prrlu_mw_step_batch<<<dim3(maxblk, njobs), kMwThreads, 0, s>>>(dev_jobs, t);
     }
     WTT_HIP(hipGetLastError());
 }
