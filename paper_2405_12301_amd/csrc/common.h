@@ -76,8 +76,10 @@ void tsqr_r(hipStream_t s, int m, int n, int batch, const double *A, long long s
 // Outputs sigma[z * n + j] sorted descending, V[z * n * n] row-major with column j the
 // right singular vector of sigma_j and, if US != null, A V (= U Sigma). The matrices live in
 // LDS when 2 n^2 doubles fit; otherwise scratch must hold batch * (2 n^2 + n) doubles.
+// delta (device, one per matrix, may be null): truncation threshold of the singular values;
+// rotations whose effect stays far below it are skipped.
 void jacobi_svd(hipStream_t s, int n, int batch, const double *A, double *sigma, double *V, double *scratch,
-                double *US = nullptr);
+                double *US = nullptr, const double *delta = nullptr);
 
 // Full-pivot rank-revealing LU of one m x n row-major matrix (overwritten by its residual).
 // Stops when the residual's squared Frobenius norm <= rel_tol2 * (initial squared norm), after
@@ -104,13 +106,16 @@ struct PrrluJob {
     double rel_tol2;
     int *rowpiv, *colpiv;
     double *L, *info, *ws;  // ws: prrlu_ws_doubles(m, n) doubles
-    int rows, nblk, mode;   // set by prrlu_prepare: rows per workgroup, workgroups, 0 register / 1 multi-workgroup
+    // set by prrlu_prepare: 0 single-workgroup register tiles (shape: tile shape id) or 1
+    // multi-workgroup (rows per workgroup, workgroups)
+    int mode, shape, rows, nblk;
 };
 void prrlu_prepare(PrrluJob &j);
 struct SvdJob {
     const double *A;
     double *sigma, *V;
     int n, batch;
+    const double *delta;  // per component truncation threshold (device) or null
 };
 struct CholJob {
     const double *G;

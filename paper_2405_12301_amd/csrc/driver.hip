@@ -1017,7 +1017,7 @@ int svd_ranks(wenott_ctx *c, int m, int n, const double *A, long long sz, long l
     *V = c->sc.get<double>(S_V, (size_t)nc * n * n);
     double *jac = c->sc.get<double>(S_JAC, (size_t)nc * (2 * (size_t)n * n + n));
     ev_record(c, KC_SVD);
-    jacobi_svd(c->s, n, nc, R, *sig, *V, jac);
+    jacobi_svd(c->s, n, nc, R, *sig, *V, jac, nullptr, rel == 0.0 ? delta_abs : nullptr);
     ev_record(c, KC_SVD);
     add_work(c, KC_SVD, 0.0, 8.0 * nc * 3.0 * (double)n * n);
     *rk = c->sc.get<int>(S_RANKS, nc);
@@ -1098,9 +1098,11 @@ void round_tt(wenott_ctx *c, TT &X, double eps, bool truncate, std::vector<doubl
         const int Rk = X.R[k], Nk = X.N[k], n = X.R[k + 1];
         const int m = Rk * Nk;
         double *C = c->sc.get<double>(S_TMP, (size_t)nc * m * n);
-        GemmBatch b0;
-        b0.nb1 = nc; b0.sA1 = X.cstride(k); b0.sB1 = (long long)n * n; b0.sC1 = (long long)m * n;
-        gemm_f64(s, false, true, m, n, n, 1.0, X.core[k], n, T[k + 1], n, 0.0, C, n, b0);
+        if (k > 0) {  // for k = 0 the buffer still holds G_0 T_1^T from the norms
+            GemmBatch b0;
+            b0.nb1 = nc; b0.sA1 = X.cstride(k); b0.sB1 = (long long)n * n; b0.sC1 = (long long)m * n;
+            gemm_f64(s, false, true, m, n, n, 1.0, X.core[k], n, T[k + 1], n, 0.0, C, n, b0);
+        }
         double *sig, *V;
         int *rk;
         int r = svd_ranks(c, m, n, C, (long long)m * n, n, 1, ddelta, 0.0, c->o.rank_cap, &sig, &V, &rk);
@@ -1121,19 +1123,21 @@ void round_tt(wenott_ctx *c, TT &X, double eps, bool truncate, std::vector<doubl
         // Columns of G'_k P belonging to small kept singular values carry rounding noise along
         // the dominant directions (relative size u ||G'_k|| ||T|| / sigma_j); re-orthonormalise
         // them in descending sigma order (two CholeskyQR passes) before projecting.
-        for (int pass = 0; pass < 2; ++pass) {
-            double *Gm = c->sc.get<double>(S_PD0, (size_t)nc * r * r);
-            double *Xi = c->sc.get<double>(S_PD1, (size_t)nc * r * r);
-            double *ws = c->sc.get<double>(S_TD0, (size_t)nc * r * r);
-            size_t pc = gemm_tn_splitk_part(r, r, m, nc);
-            gemm_tn_splitk(s, r, r, m, nk, r, nk, r, Gm, r, nc, (long long)m * r, (long long)m * r, (long long)r * r,
-                           c->sc.get<double>(S_SPLIT, pc), pc);
-            chol_upper_inv(s, r, nc, Gm, Xi, ws);
+        {  // two passes ping-pong between nk and a scratch copy, ending in nk
             double *nk2 = c->sc.get<double>(S_TD1, (size_t)nc * m * r);
-            GemmBatch bx;
-            bx.nb1 = nc; bx.sA1 = (long long)m * r; bx.sB1 = (long long)r * r; bx.sC1 = (long long)m * r;
-            gemm_f64(s, false, false, m, r, r, 1.0, nk, r, Xi, r, 0.0, nk2, r, bx);
-            WTT_HIP(hipMemcpyAsync(nk, nk2, sizeof(double) * nc * m * r, hipMemcpyDeviceToDevice, s));
+            for (int pass = 0; pass < 2; ++pass) {
+                double *src = pass == 0 ? nk : nk2, *dst = pass == 0 ? nk2 : nk;
+                double *Gm = c->sc.get<double>(S_PD0, (size_t)nc * r * r);
+                double *Xi = c->sc.get<double>(S_PD1, (size_t)nc * r * r);
+                double *ws = c->sc.get<double>(S_TD0, (size_t)nc * r * r);
+                size_t pc = gemm_tn_splitk_part(r, r, m, nc);
+                gemm_tn_splitk(s, r, r, m, src, r, src, r, Gm, r, nc, (long long)m * r, (long long)m * r,
+                               (long long)r * r, c->sc.get<double>(S_SPLIT, pc), pc);
+                chol_upper_inv(s, r, nc, Gm, Xi, ws);
+                GemmBatch bx;
+                bx.nb1 = nc; bx.sA1 = (long long)m * r; bx.sB1 = (long long)r * r; bx.sC1 = (long long)m * r;
+                gemm_f64(s, false, false, m, r, r, 1.0, src, r, Xi, r, 0.0, dst, r, bx);
+            }
         }
         // S = new^T G'_k (r x n); next core = S G_{k+1}
         double *Sm = c->sc.get<double>(S_Q, (size_t)nc * r * n);
@@ -1431,9 +1435,11 @@ void batch_round(std::vector<BState> &bs, std::vector<TT> &Xs) {
             TT &X = Xs[z];
             const int m = X.R[k] * X.N[k], n = X.R[k + 1];
             double *C = c->sc.get<double>(S_TMP, (size_t)nc * m * n);
-            GemmBatch b0;
-            b0.nb1 = nc; b0.sA1 = X.cstride(k); b0.sB1 = (long long)n * n; b0.sC1 = (long long)m * n;
-            gemm_f64(c->s, false, true, m, n, n, 1.0, X.core[k], n, T[z][k + 1], n, 0.0, C, n, b0);
+            if (k > 0) {  // for k = 0 the buffer still holds G_0 T_1^T from the norms
+                GemmBatch b0;
+                b0.nb1 = nc; b0.sA1 = X.cstride(k); b0.sB1 = (long long)n * n; b0.sC1 = (long long)m * n;
+                gemm_f64(c->s, false, true, m, n, n, 1.0, X.core[k], n, T[z][k + 1], n, 0.0, C, n, b0);
+            }
             double *scr = c->sc.get<double>(S_TSQR, tsqr_scratch_doubles(m, n, nc));
             double *R = c->sc.get<double>(S_R, (size_t)nc * n * n);
             ev_record(c, KC_TSQR);
@@ -1443,11 +1449,11 @@ void batch_round(std::vector<BState> &bs, std::vector<TT> &Xs) {
             add_work(c, KC_SVD, 0.0, 8.0 * nc * 3.0 * (double)n * n);
             sig[z] = c->sc.get<double>(S_SIG, (size_t)nc * n);
             V[z] = c->sc.get<double>(S_V, (size_t)nc * n * n);
-            jobs[z] = SvdJob{R, sig[z], V[z], n, nc};
+            jobs[z] = SvdJob{R, sig[z], V[z], n, nc, ddelta[z]};
             if (!fits) {
                 double *jac = c->sc.get<double>(S_JAC, (size_t)nc * (2 * (size_t)n * n + n));
                 ev_record(c, KC_SVD);
-                jacobi_svd(c->s, n, nc, R, sig[z], V[z], jac);
+                jacobi_svd(c->s, n, nc, R, sig[z], V[z], jac, nullptr, ddelta[z]);
                 ev_record(c, KC_SVD);
             }
         }
@@ -1468,7 +1474,6 @@ void batch_round(std::vector<BState> &bs, std::vector<TT> &Xs) {
         std::vector<CholJob> cj(ns);
         std::vector<double *> nk(ns), nk2(ns);
         std::vector<int> rr(ns);
-        int pass_ok = 1;
         for (size_t z = 0; z < ns; ++z) {
             wenott_ctx *c = bs[z].c;
             TT &X = Xs[z];
@@ -1488,15 +1493,18 @@ void batch_round(std::vector<BState> &bs, std::vector<TT> &Xs) {
             b2.nb1 = nc; b2.sA1 = X.cstride(k); b2.sB1 = (long long)n * r; b2.sC1 = (long long)m * r;
             gemm_f64(c->s, false, false, m, r, n, 1.0, X.core[k], n, P, r, 0.0, nk[z], r, b2);
         }
-        for (int pass = 0; pass < 2 && pass_ok; ++pass) {
+        for (size_t z = 0; z < ns; ++z)
+            nk2[z] = bs[z].c->sc.get<double>(S_TD1, (size_t)nc * Xs[z].R[k] * Xs[z].N[k] * rr[z]);
+        for (int pass = 0; pass < 2; ++pass) {  // ping-pong between nk and nk2, ending in nk
             for (size_t z = 0; z < ns; ++z) {
                 wenott_ctx *c = bs[z].c;
                 const int m = Xs[z].R[k] * Xs[z].N[k], r = rr[z];
+                double *src = pass == 0 ? nk[z] : nk2[z];
                 double *Gm = c->sc.get<double>(S_PD0, (size_t)nc * r * r);
                 double *Xi = c->sc.get<double>(S_PD1, (size_t)nc * r * r);
                 double *ws = c->sc.get<double>(S_TD0, (size_t)nc * r * r);
                 size_t pc = gemm_tn_splitk_part(r, r, m, nc);
-                gemm_tn_splitk(c->s, r, r, m, nk[z], r, nk[z], r, Gm, r, nc, (long long)m * r, (long long)m * r,
+                gemm_tn_splitk(c->s, r, r, m, src, r, src, r, Gm, r, nc, (long long)m * r, (long long)m * r,
                                (long long)r * r, c->sc.get<double>(S_SPLIT, pc), pc);
                 cj[z] = CholJob{Gm, Xi, ws, r, nc};
             }
@@ -1505,11 +1513,10 @@ void batch_round(std::vector<BState> &bs, std::vector<TT> &Xs) {
             for (size_t z = 0; z < ns; ++z) {
                 wenott_ctx *c = bs[z].c;
                 const int m = Xs[z].R[k] * Xs[z].N[k], r = rr[z];
-                nk2[z] = c->sc.get<double>(S_TD1, (size_t)nc * m * r);
+                double *src = pass == 0 ? nk[z] : nk2[z], *dst = pass == 0 ? nk2[z] : nk[z];
                 GemmBatch bx;
                 bx.nb1 = nc; bx.sA1 = (long long)m * r; bx.sB1 = (long long)r * r; bx.sC1 = (long long)m * r;
-                gemm_f64(c->s, false, false, m, r, r, 1.0, nk[z], r, cj[z].X, r, 0.0, nk2[z], r, bx);
-                WTT_HIP(hipMemcpyAsync(nk[z], nk2[z], sizeof(double) * nc * m * r, hipMemcpyDeviceToDevice, c->s));
+                gemm_f64(c->s, false, false, m, r, r, 1.0, src, r, cj[z].X, r, 0.0, dst, r, bx);
             }
         }
         for (size_t z = 0; z < ns; ++z) {

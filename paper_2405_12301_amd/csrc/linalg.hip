@@ -17,9 +17,31 @@ namespace {
 
 constexpr int kWave = 64;
 
+// Lane permutation of a double with a DPP control word (both 32-bit halves moved alike).
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Sum over the 64 lanes of a wave (every lane active); every lane gets the result. Within each
+// row of 16 lanes: swap neighbours, swap pairs (quad permutations), mirror halves, mirror the
+// row; then the four row sums are read from lanes 0, 16, 32, 48.
 __device__ inline double wave_sum(double v) {
-    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
-    return v;
+    v += dpp_d<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+    v += dpp_d<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+    v += dpp_d<0x141>(v);  // row_half_mirror
+    v += dpp_d<0x140>(v);  // row_mirror
+    return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
 }
 
 // Sum over the workgroup; every thread gets the result. red must hold >= nwaves doubles.
@@ -102,13 +124,18 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, double alpha,
 }
 
 // --------------------------------------------------------------------------- TSQR
-// Householder QR of one row block [r0, r0 + nr) of matrix z, in a column-major scratch copy.
-__global__ __launch_bounds__(256) void k_hhqr(int m, int n, int bm, int nblk, const double *__restrict__ A,
+// Householder QR of one row block [r0, r0 + nr) of matrix z, in a column-major scratch copy;
+// only R is kept. Step j reflects column j onto its diagonal: every thread derives the
+// reflector (beta, tau and the scale of the unnormalised vector) from the squared norm of the
+// column below the diagonal, which the wave that updated column j in the previous step left in
+// LDS; the waves then apply it to the trailing columns, the wave of column j + 1 also forming
+// that column's new norm. One barrier per column.
+__global__ __launch_bounds__(1024) void k_hhqr(int m, int n, int bm, int nblk, const double *__restrict__ A,
                                               long long sz, long long rs, long long cs, double *__restrict__ Rout,
                                               double *__restrict__ scratch, int use_lds) {
     extern __shared__ double wlds[];
-    __shared__ double red[8];
-    __shared__ double sh[3];
+    __shared__ double red[16];
+    __shared__ double snorm[2];
     const int blk = blockIdx.x, z = blockIdx.y, tid = threadIdx.x;
     const int lane = tid % kWave, w = tid / kWave, nw = blockDim.x / kWave;
     const int r0 = blk * bm;
@@ -128,44 +155,56 @@ __global__ __launch_bounds__(256) void k_hhqr(int m, int n, int bm, int nblk, co
         }
     }
     __syncthreads();
+    {
+        double ss = 0.0;
+        for (int i = 1 + tid; i < nr; i += blockDim.x) ss += W[i] * W[i];
+        ss = block_sum(ss, red);
+        if (tid == 0) snorm[0] = ss;
+    }
+    __syncthreads();
     const int kmax = min(nr, n);
+    double beta_prev = 0.0;
     for (int j = 0; j < kmax; ++j) {
         double *col = W + (long long)j * bm;
-        double ss = 0.0;
-        for (int i = j + 1 + tid; i < nr; i += blockDim.x) ss += col[i] * col[i];
-        ss = block_sum(ss, red);
-        if (tid == 0) {
-            double a = col[j];
-            double xn = sqrt(ss);
-            double beta, tau, scale;
-            if (xn == 0.0) {
-                beta = a; tau = 0.0; scale = 0.0;
-            } else {
-                beta = -copysign(hypot(a, xn), a);
-                tau = (beta - a) / beta;
-                scale = 1.0 / (a - beta);
-            }
-            sh[0] = beta; sh[1] = tau; sh[2] = scale;
+        if (tid == 0 && j > 0) W[(long long)(j - 1) * bm + (j - 1)] = beta_prev;  // nobody reads it any more
+        const double a = col[j], xn2 = snorm[j & 1];
+        double beta, tau, scale;
+        if (xn2 == 0.0) {
+            beta = a; tau = 0.0; scale = 0.0;
+        } else {
+            beta = -copysign(sqrt(a * a + xn2), a);
+            tau = (beta - a) / beta;
+            scale = 1.0 / (a - beta);
         }
-        __syncthreads();
-        const double tau = sh[1], scale = sh[2];
-        if (tau != 0.0)
-            for (int i = j + 1 + tid; i < nr; i += blockDim.x) col[i] *= scale;
-        __syncthreads();
-        if (tid == 0) col[j] = sh[0];
-        if (tau != 0.0) {
-            for (int l = j + 1 + w; l < n; l += nw) {
-                double *cl = W + (long long)l * bm;
-                double dot = lane == 0 ? cl[j] : 0.0;
+        beta_prev = beta;
+        // v = [1; scale * col[j+1..]]; each trailing column l: cl -= tau (v . cl) v
+        for (int l = j + 1 + w; l < n; l += nw) {
+            double *cl = W + (long long)l * bm;
+            double ss = 0.0;  // squared norm of the updated column below row j + 1 (for l = j + 1)
+            if (tau != 0.0) {
+                double dot = 0.0;
                 for (int i = j + 1 + lane; i < nr; i += kWave) dot += col[i] * cl[i];
-                dot = wave_sum(dot);
-                const double f = tau * dot;
-                if (lane == 0) cl[j] -= f;
-                for (int i = j + 1 + lane; i < nr; i += kWave) cl[i] -= f * col[i];
+                const double clj = readlane_d(lane == 0 ? cl[j] : 0.0, 0);
+                dot = clj + scale * wave_sum(dot);
+                const double f = tau * dot, fs = f * scale;
+                if (lane == 0) cl[j] = clj - f;
+                for (int i = j + 1 + lane; i < nr; i += kWave) {
+                    const double v = cl[i] - fs * col[i];
+                    cl[i] = v;
+                    if (i >= j + 2) ss += v * v;
+                }
+            } else {
+                for (int i = j + 2 + lane; i < nr; i += kWave) ss += cl[i] * cl[i];
+            }
+            if (l == j + 1) {
+                ss = wave_sum(ss);
+                if (lane == 0) snorm[(j + 1) & 1] = ss;
             }
         }
         __syncthreads();
     }
+    if (tid == 0 && kmax > 0) W[(long long)(kmax - 1) * bm + (kmax - 1)] = beta_prev;
+    __syncthreads();
     double *R = Rout + ((long long)z * nblk + blk) * (long long)n * n;
     for (long long e = tid; e < (long long)n * n; e += blockDim.x) {
         int i = (int)(e / n), jj = (int)(e % n);
@@ -219,11 +258,24 @@ __device__ inline void circle_pair(int r, int k, int np, int *p, int *q) {
 }
 
 // A and V are column-major (column j at j * n); they live in LDS (fast path) or global memory.
-__device__ void jacobi_sweeps(int n, double *A, double *V, int *nrot) {
+// Squared column norms are recomputed at the start of every sweep and updated through each
+// rotation (a' = a - t c, b' = b + t c), so a pair needs one dot product; nrm holds n doubles.
+// A pair whose cross product is at most eta (an absolute threshold, 0 for none) is also left
+// alone: with eta = 0.01 delta^2 / n, where delta is the truncation threshold of the singular
+// values, the skipped rotations move no singular value by more than 1% of delta, and columns
+// far below delta are not orthogonalised against each other to full relative precision.
+__device__ void jacobi_sweeps(int n, double *A, double *V, int *nrot, double *nrm, double eta) {
     const int tid = threadIdx.x, lane = tid % kWave, w = tid / kWave, nw = blockDim.x / kWave;
     const int np = n + (n & 1);
     const double tol = 1e-15;
     for (int sweep = 0; sweep < 60; ++sweep) {
+        for (int j = w; j < n; j += nw) {
+            const double *aj = A + (long long)j * n;
+            double ss = 0.0;
+            for (int i = lane; i < n; i += kWave) ss += aj[i] * aj[i];
+            ss = wave_sum(ss);
+            if (lane == 0) nrm[j] = ss;
+        }
         if (tid == 0) *nrot = 0;
         __syncthreads();
         for (int r = 0; r < np - 1; ++r) {
@@ -232,16 +284,16 @@ __device__ void jacobi_sweeps(int n, double *A, double *V, int *nrot) {
                 circle_pair(r, k, np, &p, &q);
                 if (q >= n) continue;
                 double *ap = A + (long long)p * n, *aq = A + (long long)q * n;
-                double a = 0.0, b = 0.0, c = 0.0;
-                for (int i = lane; i < n; i += kWave) {
-                    double x = ap[i], y = aq[i];
-                    a += x * x; b += y * y; c += x * y;
-                }
-                a = wave_sum(a); b = wave_sum(b); c = wave_sum(c);
-                if (c == 0.0 || !(fabs(c) > tol * sqrt(a) * sqrt(b))) continue;
-                double zeta = (b - a) / (2.0 * c);
-                double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-                double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+                double c = 0.0;
+                for (int i = lane; i < n; i += kWave) c += ap[i] * aq[i];
+                c = wave_sum(c);
+                const double a = nrm[p], b = nrm[q];
+                if (c == 0.0 || !(fabs(c) > tol * sqrt(a * b)) || !(fabs(c) > eta)) continue;
+                // t = tan of the rotation angle: the root of t^2 c + (b - a) t - c = 0 of smaller
+                // magnitude, t = sign(b - a) 2c / (|b - a| + sqrt((b - a)^2 + 4 c^2))
+                const double dd = b - a;
+                const double t = copysign(1.0, dd) * (2.0 * c) / (fabs(dd) + sqrt(dd * dd + 4.0 * c * c));
+                const double cs = rsqrt(1.0 + t * t), sn = cs * t;
                 for (int i = lane; i < n; i += kWave) {
                     double x = ap[i], y = aq[i];
                     ap[i] = cs * x - sn * y;
@@ -253,7 +305,11 @@ __device__ void jacobi_sweeps(int n, double *A, double *V, int *nrot) {
                     vp[i] = cs * x - sn * y;
                     vq[i] = sn * x + cs * y;
                 }
-                if (lane == 0) atomicAdd(nrot, 1);
+                if (lane == 0) {
+                    nrm[p] = fmax(a - t * c, 0.0);
+                    nrm[q] = b + t * c;
+                    atomicAdd(nrot, 1);
+                }
             }
             __syncthreads();
         }
@@ -286,8 +342,13 @@ __device__ void jacobi_finish(int n, const double *A, const double *V, double *s
     }
 }
 
+__device__ __forceinline__ double jacobi_eta(const double *delta, int z, int n) {
+    return delta ? 0.01 * delta[z] * delta[z] / n : 0.0;
+}
+
 __global__ __launch_bounds__(1024) void k_jacobi_lds(int n, const double *__restrict__ Ain, double *__restrict__ sigma,
-                                                     double *__restrict__ Vout, double *__restrict__ US) {
+                                                     double *__restrict__ Vout, double *__restrict__ US,
+                                                     const double *__restrict__ delta) {
     extern __shared__ double sm[];
     __shared__ int nrot;
     __shared__ double sig_tmp[512];
@@ -300,14 +361,15 @@ __global__ __launch_bounds__(1024) void k_jacobi_lds(int n, const double *__rest
         V[j * n + i] = (i == j) ? 1.0 : 0.0;
     }
     __syncthreads();
-    jacobi_sweeps(n, A, V, &nrot);
+    jacobi_sweeps(n, A, V, &nrot, sig_tmp, jacobi_eta(delta, z, n));
     jacobi_finish(n, A, V, sig_tmp, sigma + (long long)z * n, Vout + (long long)z * n * n,
                   US ? US + (long long)z * n * n : nullptr);
 }
 
 __global__ __launch_bounds__(1024) void k_jacobi_global(int n, const double *__restrict__ Ain,
                                                         double *__restrict__ sigma, double *__restrict__ Vout,
-                                                        double *__restrict__ US, double *__restrict__ scratch) {
+                                                        double *__restrict__ US, double *__restrict__ scratch,
+                                                        const double *__restrict__ delta) {
     __shared__ int nrot;
     const int z = blockIdx.x, tid = threadIdx.x;
     double *A = scratch + (long long)z * (2 * (long long)n * n + n);
@@ -320,7 +382,7 @@ __global__ __launch_bounds__(1024) void k_jacobi_global(int n, const double *__r
         V[(long long)j * n + i] = (i == j) ? 1.0 : 0.0;
     }
     __syncthreads();
-    jacobi_sweeps(n, A, V, &nrot);
+    jacobi_sweeps(n, A, V, &nrot, sig_tmp, jacobi_eta(delta, z, n));
     jacobi_finish(n, A, V, sig_tmp, sigma + (long long)z * n, Vout + (long long)z * n * n,
                   US ? US + (long long)z * n * n : nullptr);
 }
@@ -358,7 +420,7 @@ __host__ __device__ inline PrrluWs prrlu_ws_split(double *ws, int n, int nblk) {
     return w;
 }
 
-constexpr int kMwThreads = 256, kMwElems = 8192, kMwMaxRows = 2048;
+constexpr int kMwThreads = 256, kMwTW = 8, kMwK = 4;
 
 __device__ __forceinline__ void prrlu_mw_init_body(const PrrluJob &J) {
     const PrrluWs w = prrlu_ws_split(J.ws, J.n, J.nblk);
@@ -370,48 +432,93 @@ __device__ __forceinline__ void prrlu_mw_init_body(const PrrluJob &J) {
     J.info[0] = -1.0;  // not finished: the host launches further steps
 }
 
+// Workgroup b owns a stripe of J.rows = RS * kMwK rows; thread (tr, tc) holds the kMwTW
+// columns [8 tc, 8 tc + 8) of rows r0 + tr + k RS, k < kMwK, with RS = 256 / ceil(n / 8).
 __device__ __forceinline__ void prrlu_mw_step_body(const PrrluJob &J, int t) {
-    __shared__ double lc[kMwMaxRows];
+    __shared__ double lc[kMwThreads * kMwK];
     __shared__ double wmax[kMwThreads / kWave], wsum[kMwThreads / kWave];
     __shared__ long long widx[kMwThreads / kWave];
-    __shared__ int s_last;
+    __shared__ int s_last, s_stop;
+    __shared__ long long s_idx;
     const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave;
     const int m = J.m, n = J.n, rmax = J.rmax;
     const PrrluWs w = prrlu_ws_split(J.ws, n, J.nblk);
     double *__restrict__ A = J.A;
     if (w.ctl->stop) return;
-    const int r0 = blockIdx.x * J.rows, nr = min(J.rows, m - r0);
+    const int tpr = (n + kMwTW - 1) / kMwTW, RS = kMwThreads / tpr;
+    const int tr = tid / tpr, tc = tid % tpr, c0 = tc * kMwTW;
+    const bool active = tr < RS;
+    const int r0 = blockIdx.x * J.rows;
+    double a[kMwK][kMwTW];
+#pragma unroll
+    for (int k = 0; k < kMwK; ++k) {
+        const int row = r0 + tr + k * RS;
+        const bool rv = active && row < m;
+#pragma unroll
+        for (int j = 0; j < kMwTW; ++j) a[k][j] = (rv && c0 + j < n) ? A[(long long)row * n + c0 + j] : 0.0;
+    }
     int pi = -1, pj = -1;
     if (t > 0) {
         const long long pidx = w.ctl->idx;
         pi = (int)(pidx / n);
         pj = (int)(pidx % n);
-        const double piv = w.ctl->piv;
-        for (int ri = tid; ri < nr; ri += kMwThreads) {
-            const int i = r0 + ri;
-            const double l = (i == pi) ? 1.0 : A[(long long)i * n + pj] / piv;
-            lc[ri] = l;
-            J.L[(long long)i * rmax + (t - 1)] = l;
+        const double inv = 1.0 / w.ctl->piv;
+        if (active && pj >= c0 && pj < c0 + kMwTW) {  // the pivot column's owners publish it
+#pragma unroll
+            for (int j = 0; j < kMwTW; ++j)
+                if (c0 + j == pj)
+#pragma unroll
+                    for (int k = 0; k < kMwK; ++k) lc[tr + k * RS] = a[k][j];
         }
         __syncthreads();
+        if (active) {
+            double u[kMwTW];
+#pragma unroll
+            for (int j = 0; j < kMwTW; ++j) u[j] = c0 + j < n ? w.rowbuf[c0 + j] : 0.0;
+#pragma unroll
+            for (int k = 0; k < kMwK; ++k) {
+                const int row = r0 + tr + k * RS;
+                if (row >= m) continue;
+                const double l = row == pi ? 1.0 : lc[tr + k * RS] * inv;
+                if (tc == 0) J.L[(long long)row * rmax + (t - 1)] = l;
+                if (row == pi) {
+#pragma unroll
+                    for (int j = 0; j < kMwTW; ++j) a[k][j] = 0.0;
+                } else {
+#pragma unroll
+                    for (int j = 0; j < kMwTW; ++j) a[k][j] = fma(-l, u[j], a[k][j]);
+                }
+            }
+            if (pj >= c0 && pj < c0 + kMwTW) {
+#pragma unroll
+                for (int j = 0; j < kMwTW; ++j)
+                    if (c0 + j == pj)
+#pragma unroll
+                        for (int k = 0; k < kMwK; ++k) a[k][j] = 0.0;
+            }
+#pragma unroll
+            for (int k = 0; k < kMwK; ++k) {
+                const int row = r0 + tr + k * RS;
+                if (row >= m) continue;
+#pragma unroll
+                for (int j = 0; j < kMwTW; ++j)
+                    if (c0 + j < n) A[(long long)row * n + c0 + j] = a[k][j];
+            }
+        }
     }
     double lmax = -1.0, lsum = 0.0;
     long long lidx = 0x7fffffffffffffffLL;
-    const long long base = (long long)r0 * n, cnt = (long long)nr * n;
-    const int step_i = kMwThreads / n, step_j = kMwThreads % n;
-    int ri = tid / n, j = tid % n;
-    for (long long e = tid; e < cnt; e += kMwThreads) {
-        double v = A[base + e];
-        if (t > 0) {
-            v = (r0 + ri == pi || j == pj) ? 0.0 : v - lc[ri] * w.rowbuf[j];
-            A[base + e] = v;
+#pragma unroll
+    for (int k = 0; k < kMwK; ++k) {
+        const long long rb = (long long)(r0 + tr + k * RS) * n + c0;
+#pragma unroll
+        for (int j = 0; j < kMwTW; ++j) {
+            const double v = a[k][j];
+            lsum = fma(v, v, lsum);
+            if (fabs(v) > lmax) { lmax = fabs(v); lidx = rb + j; }
         }
-        const double av = fabs(v);
-        lsum += v * v;
-        if (av > lmax) { lmax = av; lidx = base + e; }
-        ri += step_i; j += step_j;
-        if (j >= n) { j -= n; ++ri; }
     }
+    if (!active) { lmax = -1.0; lsum = 0.0; }
     for (int off = kWave / 2; off > 0; off >>= 1) {
         const double om = __shfl_xor(lmax, off, kWave);
         const long long oi = __shfl_xor(lidx, off, kWave);
@@ -452,10 +559,9 @@ __device__ __forceinline__ void prrlu_mw_step_body(const PrrluJob &J, int t) {
         bs += __shfl_xor(bs, off, kWave);
         if (om > bm || (om == bm && oi < bi)) { bm = om; bi = oi; }
     }
+    __syncthreads();
     if (lane == 0) { wmax[wv] = bm; widx[wv] = bi; wsum[wv] = bs; }
     __syncthreads();
-    __shared__ int s_stop;
-    __shared__ long long s_idx;
     if (tid == 0) {
         double gm = wmax[0], gs = 0.0;
         long long gi = widx[0];
@@ -510,50 +616,51 @@ __global__ __launch_bounds__(kMwThreads) void k_prrlu_mw_step_batch(const PrrluJ
     prrlu_mw_step_body(J, t);
 }
 
-// Register-resident variant for blocks of at most 1024 * E entries: every thread keeps its
-// entries (linear index tid + 1024 l) in registers and walks their (row, column) pairs
-// incrementally; per pivot only the pivot row and column go through LDS. Two barriers per
-// pivot: after the wave partials (every thread then reduces the 16 partials itself) and after
-// the pivot row/column are published.
-template <int E>
-__device__ __forceinline__ void prrlu_reg_body(int m, int n, const double *__restrict__ A, int rmax,
-                                               double rel_tol2, int *__restrict__ rowpiv, int *__restrict__ colpiv,
-                                               double *__restrict__ L, double *__restrict__ info) {
+// Single-workgroup form: the whole block stays in registers for all pivot steps. Thread tid
+// holds the TH x TW tile at rows [TH (tid / tn), +TH), columns [TW (tid % tn), +TW), with
+// tn = ceil(n / TW); the launch needs ceil(m / TH) * tn <= 1024. Per pivot step only the pivot
+// row and column pass through LDS. Two barriers per step: after the wave partials (every thread
+// then reduces the 16 partials itself) and after the pivot row and column are published. The
+// eliminated row and column are set to exact zeros.
+template <int TH, int TW>
+__device__ __forceinline__ void prrlu_tile_body(int m, int n, const double *__restrict__ A, int rmax,
+                                                double rel_tol2, int *__restrict__ rowpiv, int *__restrict__ colpiv,
+                                                double *__restrict__ L, double *__restrict__ info) {
     extern __shared__ double sm[];
     double *colv = sm, *rowv = sm + m;
     __shared__ double wmax[16], wsum[16];
     __shared__ int widx[16];
-    __shared__ int s_zero;
     const int tid = threadIdx.x, lane = tid % kWave, w = tid / kWave, nw = blockDim.x / kWave;
-    const int tot = m * n;
-    const int di = 1024 / n, dj = 1024 % n;
-    if (tid == 0) s_zero = 0;
-    double a[E];
+    const int tn = (n + TW - 1) / TW, tm = (m + TH - 1) / TH;
+    const bool active = tid < tm * tn;
+    const int r0 = active ? (tid / tn) * TH : m, c0 = active ? (tid % tn) * TW : n;
+    const int base = r0 * n + c0;
+    double a[TH][TW];
 #pragma unroll
-    for (int l = 0; l < E; ++l) {
-        const int e = tid + 1024 * l;
-        a[l] = e < tot ? A[e] : 0.0;
-    }
-    __syncthreads();  // s_zero is visible to every thread from here on
+    for (int i = 0; i < TH; ++i)
+#pragma unroll
+        for (int j = 0; j < TW; ++j) a[i][j] = (r0 + i < m && c0 + j < n) ? A[base + i * n + j] : 0.0;
     double tol2 = 0.0, bs = 0.0;
     int t = 0, stop = 0;
     for (;; ++t) {
         double lmax = -1.0, lsum = 0.0;
         int lidx = 0x7fffffff;
-        const int base0 = tid + s_zero;
 #pragma unroll
-        for (int l = 0; l < E; ++l) {
-            const int e = base0 + 1024 * l;
-            const double av = fabs(a[l]);
-            lsum += a[l] * a[l];
-            if (e < tot && av > lmax) { lmax = av; lidx = e; }
+        for (int i = 0; i < TH; ++i) {
+            const int rb = base + i * n;
+#pragma unroll
+            for (int j = 0; j < TW; ++j) {
+                const double v = a[i][j];
+                lsum = fma(v, v, lsum);
+                if (fabs(v) > lmax) { lmax = fabs(v); lidx = rb + j; }
+            }
         }
+        if (!active) lmax = -1.0;
         for (int off = kWave / 2; off > 0; off >>= 1) {
-            double om = __shfl_xor(lmax, off, kWave);
-            int oi = __shfl_xor(lidx, off, kWave);
-            double os = __shfl_xor(lsum, off, kWave);
+            const double om = __shfl_xor(lmax, off, kWave);
+            const int oi = __shfl_xor(lidx, off, kWave);
+            lsum += __shfl_xor(lsum, off, kWave);
             if (om > lmax || (om == lmax && oi < lidx)) { lmax = om; lidx = oi; }
-            lsum += os;
         }
         if (lane == 0) { wmax[w] = lmax; widx[w] = lidx; wsum[w] = lsum; }
         __syncthreads();  // barrier A
@@ -570,31 +677,49 @@ __device__ __forceinline__ void prrlu_reg_body(int m, int n, const double *__res
         if (t == 0 && stop == 1) stop = 0;
         if (stop) break;
         const int pi = bi / n, pj = bi % n;
-        {  // owners publish the pivot row and column
-            const int base = tid + s_zero;
-            int ri = base / n, cj = base % n;
+        const bool own_r = pi >= r0 && pi < r0 + TH, own_c = pj >= c0 && pj < c0 + TW;
+        if (own_r) {  // owners publish the pivot row and column
 #pragma unroll
-            for (int l = 0; l < E; ++l) {
-                if (base + 1024 * l < tot) {
-                    if (ri == pi) rowv[cj] = a[l];
-                    if (cj == pj) colv[ri] = a[l];
-                }
-                ri += di; cj += dj;
-                if (cj >= n) { cj -= n; ++ri; }
-            }
+            for (int i = 0; i < TH; ++i)
+                if (r0 + i == pi)
+#pragma unroll
+                    for (int j = 0; j < TW; ++j)
+                        if (c0 + j < n) rowv[c0 + j] = a[i][j];
+        }
+        if (own_c) {
+#pragma unroll
+            for (int j = 0; j < TW; ++j)
+                if (c0 + j == pj)
+#pragma unroll
+                    for (int i = 0; i < TH; ++i)
+                        if (r0 + i < m) colv[r0 + i] = a[i][j];
         }
         __syncthreads();  // barrier B
         const double inv = 1.0 / rowv[pj];
         if (tid == 0) { rowpiv[t] = pi; colpiv[t] = pj; }
-        {
-            const int base = tid + s_zero;
-            int ri = base / n, cj = base % n;
+        if (active) {
+            double u[TW];
 #pragma unroll
-            for (int l = 0; l < E; ++l) {
-                if (base + 1024 * l < tot)
-                    a[l] = (ri == pi || cj == pj) ? 0.0 : a[l] - colv[ri] * inv * rowv[cj];
-                ri += di; cj += dj;
-                if (cj >= n) { cj -= n; ++ri; }
+            for (int j = 0; j < TW; ++j) u[j] = c0 + j < n ? rowv[c0 + j] : 0.0;
+#pragma unroll
+            for (int i = 0; i < TH; ++i) {
+                const double l = r0 + i < m ? colv[r0 + i] * inv : 0.0;
+#pragma unroll
+                for (int j = 0; j < TW; ++j) a[i][j] = fma(-l, u[j], a[i][j]);
+            }
+            if (own_r) {
+#pragma unroll
+                for (int i = 0; i < TH; ++i)
+                    if (r0 + i == pi)
+#pragma unroll
+                        for (int j = 0; j < TW; ++j) a[i][j] = 0.0;
+            }
+            if (own_c) {
+#pragma unroll
+                for (int j = 0; j < TW; ++j)
+                    if (c0 + j == pj)
+#pragma unroll
+                        for (int i = 0; i < TH; ++i) a[i][j] = 0.0;
             }
         }
         for (int i = tid; i < m; i += blockDim.x) L[(long long)i * rmax + t] = (i == pi) ? 1.0 : colv[i] * inv;
@@ -612,19 +737,58 @@ __device__ __forceinline__ void prrlu_reg_body(int m, int n, const double *__res
         for (int i = tid; i < m; i += blockDim.x) L[(long long)i * rmax] = (i == 0) ? 1.0 : 0.0;
 }
 
-template <int E>
-__global__ __launch_bounds__(1024) void k_prrlu_reg(int m, int n, const double *__restrict__ A, int rmax,
-                                                    double rel_tol2, int *__restrict__ rowpiv, int *__restrict__ colpiv,
-                                                    double *__restrict__ L, double *__restrict__ info) {
-    prrlu_reg_body<E>(m, n, A, rmax, rel_tol2, rowpiv, colpiv, L, info);
+template <int TH, int TW>
+__global__ __launch_bounds__(1024) void k_prrlu_tile(int m, int n, const double *__restrict__ A, int rmax,
+                                                     double rel_tol2, int *__restrict__ rowpiv,
+                                                     int *__restrict__ colpiv, double *__restrict__ L,
+                                                     double *__restrict__ info) {
+    prrlu_tile_body<TH, TW>(m, n, A, rmax, rel_tol2, rowpiv, colpiv, L, info);
 }
 
-// One workgroup per job: the pivot searches of a batch of independent cross blocks.
-template <int E>
-__global__ __launch_bounds__(1024) void k_prrlu_reg_batch(const PrrluJob *__restrict__ jobs) {
+// One workgroup per job of the given tile shape: the pivot searches of a batch of blocks.
+template <int TH, int TW>
+__global__ __launch_bounds__(1024) void k_prrlu_tile_batch(const PrrluJob *__restrict__ jobs, int shape) {
     const PrrluJob j = jobs[blockIdx.x];
-    if (j.mode != 0) return;
-    prrlu_reg_body<E>(j.m, j.n, j.A, j.rmax, j.rel_tol2, j.rowpiv, j.colpiv, j.L, j.info);
+    if (j.mode != 0 || j.shape != shape) return;
+    prrlu_tile_body<TH, TW>(j.m, j.n, j.A, j.rmax, j.rel_tol2, j.rowpiv, j.colpiv, j.L, j.info);
+}
+
+// Tile shapes of the single-workgroup form, smallest register footprint first.
+struct TileShape {
+    int th, tw;
+};
+constexpr TileShape kTileShapes[] = {{1, 4}, {2, 4}, {1, 16}, {4, 4}, {2, 8}, {8, 2}, {4, 8}, {8, 4}, {2, 16},
+                                     {4, 9}};
+constexpr int kNumTileShapes = sizeof(kTileShapes) / sizeof(kTileShapes[0]);
+
+template <int TH, int TW>
+void launch_tile(hipStream_t s, int nb, size_t lds, const PrrluJob *jobs, int shape, int m, int n, const double *A,
+                 int rmax, double rel_tol2, int *rowpiv, int *colpiv, double *L, double *info) {
+    if (jobs) k_prrlu_tile_batch<TH, TW><<<nb, 1024, lds, s>>>(jobs, shape);
+    else k_prrlu_tile<TH, TW><<<1, 1024, lds, s>>>(m, n, A, rmax, rel_tol2, rowpiv, colpiv, L, info);
+}
+
+void dispatch_tile(hipStream_t s, int shape, int nb, size_t lds, const PrrluJob *jobs, int m, int n, const double *A,
+                   int rmax, double rel_tol2, int *rowpiv, int *colpiv, double *L, double *info) {
+#define WTT_TILE(ID, TH, TW) \
+    case ID: launch_tile<TH, TW>(s, nb, lds, jobs, shape, m, n, A, rmax, rel_tol2, rowpiv, colpiv, L, info); break;
+    switch (shape) {
+        WTT_TILE(0, 1, 4) WTT_TILE(1, 2, 4) WTT_TILE(2, 1, 16) WTT_TILE(3, 4, 4) WTT_TILE(4, 2, 8) WTT_TILE(5, 8, 2)
+        WTT_TILE(6, 4, 8) WTT_TILE(7, 8, 4) WTT_TILE(8, 2, 16) WTT_TILE(9, 4, 9)
+        default: throw StatusError(WENOTT_EINVAL, "bad pivot tile shape");
+    }
+#undef WTT_TILE
+}
+
+// First tile shape whose tiles cover the m x n block with at most 1024 threads, or -1.
+int tile_shape_for(int m, int n) {
+    if (sizeof(double) * (size_t)(m + n) > 48 * 1024) return -1;
+    for (int k = 0; k < kNumTileShapes; ++k) {
+        const long long tiles = (long long)((m + kTileShapes[k].th - 1) / kTileShapes[k].th) *
+                                ((n + kTileShapes[k].tw - 1) / kTileShapes[k].tw);
+        if (tiles <= 1024) return k;
+    }
+    return -1;
 }
 
 // Row i of X solves x L_I = L[i, :r] with L_I = L[rowpiv, :r] unit lower triangular in pivot
@@ -721,7 +885,7 @@ __global__ __launch_bounds__(1024) void k_jacobi_lds_batch(const SvdJob *__restr
         V[jj * n + i] = (i == jj) ? 1.0 : 0.0;
     }
     __syncthreads();
-    jacobi_sweeps(n, A, V, &nrot);
+    jacobi_sweeps(n, A, V, &nrot, sig_tmp, jacobi_eta(j.delta, z, n));
     jacobi_finish(n, A, V, sig_tmp, j.sigma + (long long)z * n, j.V + (long long)z * n * n, nullptr);
 }
 
@@ -756,6 +920,18 @@ size_t tsqr_scratch_doubles(int m, int n, int batch) {
     return (size_t)batch * (size_t)(w + 2 * r);
 }
 
+int lds_limit_bytes() {
+    static int lim = -1;
+    if (lim < 0) {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+            v = 65536;
+        lim = v;
+    }
+    return lim;
+}
+
 void tsqr_r(hipStream_t s, int m, int n, int batch, const double *A, long long sz, long long rs, long long cs,
             double *R, double *scratch) {
     int bm = leaf_rows(n);
@@ -769,9 +945,9 @@ void tsqr_r(hipStream_t s, int m, int n, int batch, const double *A, long long s
     }
     double *R0 = W + (long long)batch * wsize;
     double *R1 = R0 + (long long)batch * nblk * n * n;
-    const size_t lds_budget = 64 * 1024;
+    const size_t lds_budget = (size_t)lds_limit_bytes() - 2048;  // static LDS of k_hhqr stays below 2 KB
     size_t lb = sizeof(double) * (size_t)bm * n;
-    k_hhqr<<<dim3(nblk, batch), 256, lb <= lds_budget ? lb : 0, s>>>(m, n, bm, nblk, A, sz, rs, cs, R0, W,
+    k_hhqr<<<dim3(nblk, batch), 1024, lb <= lds_budget ? lb : 0, s>>>(m, n, bm, nblk, A, sz, rs, cs, R0, W,
                                                                        lb <= lds_budget);
     WTT_HIP(hipGetLastError());
     double *cur = R0, *nxt = R1;
@@ -781,7 +957,7 @@ void tsqr_r(hipStream_t s, int m, int n, int batch, const double *A, long long s
         int nb2 = (nblk + group - 1) / group;
         int bm2 = group * n;
         size_t lb2 = sizeof(double) * (size_t)bm2 * n;
-        k_hhqr<<<dim3(nb2, batch), 256, lb2 <= lds_budget ? lb2 : 0, s>>>(mm, n, bm2, nb2, cur, (long long)nblk * n * n,
+        k_hhqr<<<dim3(nb2, batch), 1024, lb2 <= lds_budget ? lb2 : 0, s>>>(mm, n, bm2, nb2, cur, (long long)nblk * n * n,
                                                                           n, 1, nxt, W, lb2 <= lds_budget);
         WTT_HIP(hipGetLastError());
         std::swap(cur, nxt);
@@ -792,37 +968,25 @@ void tsqr_r(hipStream_t s, int m, int n, int batch, const double *A, long long s
     WTT_HIP(hipGetLastError());
 }
 
-int lds_limit_bytes() {
-    static int lim = -1;
-    if (lim < 0) {
-        int dev = 0, v = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
-            v = 65536;
-        lim = v;
-    }
-    return lim;
-}
 
 void jacobi_svd(hipStream_t s, int n, int batch, const double *A, double *sigma, double *V, double *scratch,
-                double *US) {
+                double *US, const double *delta) {
     // static LDS of the kernel: the column-norm buffer (512 doubles) and a counter
     size_t lds = sizeof(double) * 2 * (size_t)n * n;
     if (n <= 512 && lds + 512 * sizeof(double) + 64 <= (size_t)lds_limit_bytes())
-        k_jacobi_lds<<<batch, 1024, lds, s>>>(n, A, sigma, V, US);
+        k_jacobi_lds<<<batch, 1024, lds, s>>>(n, A, sigma, V, US, delta);
     else
-        k_jacobi_global<<<batch, 1024, 0, s>>>(n, A, sigma, V, US, scratch);
+        k_jacobi_global<<<batch, 1024, 0, s>>>(n, A, sigma, V, US, scratch, delta);
     WTT_HIP(hipGetLastError());
 }
 
-bool prrlu_reg_fits(int m, int n) {
-    return (long long)m * n <= 1024 * 32 && sizeof(double) * (size_t)(m + n) <= 48 * 1024;
-}
-
 void prrlu_prepare(PrrluJob &j) {
-    j.rows = std::max(1, std::min(j.m, std::min(kMwMaxRows, kMwElems / std::max(j.n, 1))));
+    j.shape = tile_shape_for(j.m, j.n);
+    j.mode = j.shape >= 0 ? 0 : 1;
+    const int tpr = (j.n + kMwTW - 1) / kMwTW;
+    WTT_REQUIRE(tpr <= kMwThreads, WENOTT_EINVAL, "pivot block wider than the multi-workgroup form supports");
+    j.rows = (kMwThreads / tpr) * kMwK;
     j.nblk = (j.m + j.rows - 1) / j.rows;
-    j.mode = prrlu_reg_fits(j.m, j.n) ? 0 : 1;
 }
 
 size_t prrlu_ws_doubles(int m, int n) {
@@ -834,20 +998,17 @@ size_t prrlu_ws_doubles(int m, int n) {
 
 int prrlu(hipStream_t s, int m, int n, double *A, int rmax, double rel_tol2, int *rowpiv, int *colpiv, double *L,
           double *info, double *ws, int t_begin, int t_end) {
-    const long long tot = (long long)m * n;
-    const size_t lds_rc = sizeof(double) * (size_t)(m + n);
-    if (prrlu_reg_fits(m, n)) {
-        if (t_begin > 0) return rmax + 1;
-        if (tot <= 1024 * 8) k_prrlu_reg<8><<<1, 1024, lds_rc, s>>>(m, n, A, rmax, rel_tol2, rowpiv, colpiv, L, info);
-        else if (tot <= 1024 * 16) k_prrlu_reg<16><<<1, 1024, lds_rc, s>>>(m, n, A, rmax, rel_tol2, rowpiv, colpiv, L, info);
-        else k_prrlu_reg<32><<<1, 1024, lds_rc, s>>>(m, n, A, rmax, rel_tol2, rowpiv, colpiv, L, info);
-        WTT_HIP(hipGetLastError());
-        return rmax + 1;
-    }
     PrrluJob j{};
     j.A = A; j.m = m; j.n = n; j.rmax = rmax; j.rel_tol2 = rel_tol2;
     j.rowpiv = rowpiv; j.colpiv = colpiv; j.L = L; j.info = info; j.ws = ws;
     prrlu_prepare(j);
+    if (j.mode == 0) {
+        if (t_begin > 0) return rmax + 1;
+        dispatch_tile(s, j.shape, 1, sizeof(double) * (size_t)(m + n), nullptr, m, n, A, rmax, rel_tol2, rowpiv,
+                      colpiv, L, info);
+        WTT_HIP(hipGetLastError());
+        return rmax + 1;
+    }
     if (t_begin == 0) k_prrlu_mw_init<<<1, 1, 0, s>>>(j);
     const int last = std::min(t_end, rmax);
     for (int t = t_begin; t <= last; ++t) k_prrlu_mw_step<<<j.nblk, kMwThreads, 0, s>>>(j, t);
@@ -895,26 +1056,22 @@ size_t gemm_tn_splitk_part(int M, int N, int K, int batch) {
 void prrlu_batch(hipStream_t s, int njobs, const PrrluJob *host_jobs, const PrrluJob *dev_jobs, int t_begin,
                  int t_end) {
     if (njobs <= 0) return;
-    long long maxtot = 0;
-    int maxm = 0, maxn = 0, maxblk = 0, nreg = 0, nmw = 0;
+    int maxblk = 0, nmw = 0;
+    int lds_shape[kNumTileShapes] = {};  // LDS bytes per tile shape in use (0: unused)
     for (int i = 0; i < njobs; ++i) {
         const PrrluJob &j = host_jobs[i];
         if (j.mode == 0) {
-            maxtot = std::max(maxtot, (long long)j.m * j.n);
-            maxm = std::max(maxm, j.m);
-            maxn = std::max(maxn, j.n);
-            ++nreg;
+            lds_shape[j.shape] = std::max(lds_shape[j.shape], (int)(sizeof(double) * (size_t)(j.m + j.n)));
         } else {
             maxblk = std::max(maxblk, j.nblk);
             ++nmw;
         }
     }
-    if (nreg && t_begin == 0) {
-        const size_t lds_rc = sizeof(double) * (size_t)(maxm + maxn);
-        if (maxtot <= 1024 * 8) k_prrlu_reg_batch<8><<<njobs, 1024, lds_rc, s>>>(dev_jobs);
-        else if (maxtot <= 1024 * 16) k_prrlu_reg_batch<16><<<njobs, 1024, lds_rc, s>>>(dev_jobs);
-        else k_prrlu_reg_batch<32><<<njobs, 1024, lds_rc, s>>>(dev_jobs);
-    }
+    if (t_begin == 0)
+        for (int k = 0; k < kNumTileShapes; ++k)
+            if (lds_shape[k] > 0)
+                dispatch_tile(s, k, njobs, (size_t)lds_shape[k], dev_jobs, 0, 0, nullptr, 0, 0.0, nullptr, nullptr,
+                              nullptr, nullptr);
     if (nmw) {
         if (t_begin == 0) k_prrlu_mw_init_batch<<<cdiv(njobs, 64), 64, 0, s>>>(dev_jobs, njobs);
         for (int t = t_begin; t <= t_end; ++t)
