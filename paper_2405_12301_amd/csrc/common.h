@@ -138,7 +138,10 @@ struct FiberGeom {
     int n[kMaxDim];             // cells per dimension
     int bc[kMaxDim];            // boundary code per dimension
     double gamma, alpha, eps_w; // EOS, LF alpha, WENO epsilon (h_dir^2)
+    const double *alpha_dev;    // if set, alpha is read from this device scalar instead
 };
+
+__device__ inline double geom_alpha(const FiberGeom &g) { return g.alpha_dev ? *g.alpha_dev : g.alpha; }
 
 // Interface matrices of the state cores. Left (side 0): P[c][s][a][R_k] for the p left
 // multi-indices idx[a * k + j], j < k. Right (side 1): Q[c][s][R_{k+1}][b] for the q right
@@ -221,6 +224,8 @@ void trunc_ranks(hipStream_t s, int n, int batch, const double *sigma, const dou
                  int *ranks);
 void build_projectors(hipStream_t s, int n, int batch, int R, const double *sigma, const double *V, const int *ranks,
                       double *W1, double *W2);
-void frob_norms(hipStream_t s, int batch, long long len, const double *X, long long stride, double *out);
+// out[z] = ||X[z]||_F; if scaled is given, scaled[z] = scale * out[z] as well.
+void frob_norms(hipStream_t s, int batch, long long len, const double *X, long long stride, double *out,
+                double *scaled = nullptr, double scale = 0.0);
 
 }  // namespace wtt

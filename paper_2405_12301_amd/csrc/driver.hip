@@ -196,6 +196,9 @@ struct wenott_ctx {
     };
     BondHist bond[kMaxDim];
     int piv_hist[(kMaxDim + 1) * 2 * kMaxDim];  // last pivot rank per (cross slot, sweep direction, core)
+    const double *alpha_dev = nullptr;  // stage alpha on the device (read by the fiber kernels) when set
+    double alpha_cache = 0.0;           // exact alpha of the current state, if alpha_cache_valid
+    bool alpha_cache_valid = false;
     float last_sig[16] = {};
     int prev_sweeps = 1;
     double prev_resid = 0.0;
@@ -282,8 +285,13 @@ const double *left_part(wenott_ctx *c, const TT &U, long long *stride) {
     return Lm;
 }
 
-// Enqueue the exact alpha of U into dst (device) and the flag word into the pinned slot [64].
-void exact_alpha_launch(wenott_ctx *c, const TT &U, double *dst) {
+// Pinned host slots read after a later synchronisation: stage alphas and their flag words,
+// and the component norms of the last rounding.
+constexpr int kPinAlpha = 4064, kPinNorms = 4080;
+
+// Enqueue the exact alpha of U into dst (device), and copies of it and of the flag word into
+// the pinned slots kPinAlpha + slot.
+void exact_alpha_launch(wenott_ctx *c, const TT &U, double *dst, int slot = 0) {
     long long lms = 0;
     const double *Lm = left_part(c, U, &lms);
     long long nrows = 1;
@@ -295,15 +303,15 @@ void exact_alpha_launch(wenott_ctx *c, const TT &U, double *dst) {
     dense_eval(c->s, 1, U.d, U.nc, nrows, U.R[U.d - 1], nlast, Lm, lms, U.core[U.d - 1], U.cstride(U.d - 1),
                c->gamma, nullptr, part, nblocks, c->d_flags);
     reduce_max_dev(c->s, part, nblocks, dst);
-    WTT_HIP(hipMemcpyAsync(c->h_pinned_dbl + 64, dst, sizeof(double), hipMemcpyDeviceToHost, c->s));
-    WTT_HIP(hipMemcpyAsync(c->h_pinned_int + 64, c->d_flags, sizeof(int), hipMemcpyDeviceToHost, c->s));
+    WTT_HIP(hipMemcpyAsync(c->h_pinned_dbl + kPinAlpha + slot, dst, sizeof(double), hipMemcpyDeviceToHost, c->s));
+    WTT_HIP(hipMemcpyAsync(c->h_pinned_int + kPinAlpha + slot, c->d_flags, sizeof(int), hipMemcpyDeviceToHost, c->s));
 }
 
 double exact_alpha(wenott_ctx *c, const TT &U) {
     exact_alpha_launch(c, U, c->sc.get<double>(S_DSCAL, 4));
     WTT_HIP(hipStreamSynchronize(c->s));
-    raise_flags(c, c->h_pinned_int[64]);
-    return c->h_pinned_dbl[64];
+    raise_flags(c, c->h_pinned_int[kPinAlpha]);
+    return c->h_pinned_dbl[kPinAlpha];
 }
 
 void to_dense_dev(wenott_ctx *c, const TT &U, double *out) {
@@ -752,7 +760,7 @@ void eval_stage_block(wenott_ctx *c, const TT &X, const TT *Un, StageWeights w, 
     FiberGeom g{};
     g.d = d; g.ncomp = nc; g.dir = 0; g.k = k;
     for (int j = 0; j < d; ++j) { g.n[j] = X.N[j]; g.bc[j] = c->bc[j]; }
-    g.gamma = c->gamma; g.alpha = alpha; g.eps_w = 0.0;
+    g.gamma = c->gamma; g.alpha = alpha; g.eps_w = 0.0; g.alpha_dev = c->alpha_dev;
     const int p = L.count, q = Rs.count, Nk = X.N[k];
     const int *didxL = k > 0 ? c->ring.put(L.v.data(), L.v.size()) : nullptr;
     const int *didxR = k < d - 1 ? c->ring.put(Rs.v.data(), Rs.v.size()) : nullptr;
@@ -877,7 +885,7 @@ int sampled_stage_residual_launch(wenott_ctx *c, const TT &X, const TT *Un, Stag
     FiberGeom g{};
     g.d = d; g.ncomp = X.nc; g.dir = 0; g.k = 0;
     for (int j = 0; j < d; ++j) { g.n[j] = X.N[j]; g.bc[j] = c->bc[j]; }
-    g.gamma = c->gamma; g.alpha = alpha;
+    g.gamma = c->gamma; g.alpha = alpha; g.alpha_dev = c->alpha_dev;
     std::vector<int> pts((size_t)npts * d);
     for (int i = 0; i < npts; ++i)
         for (int j = 0; j < d; ++j) pts[(size_t)i * d + j] = rng.below(X.N[j]);
@@ -1080,20 +1088,21 @@ void round_tt(wenott_ctx *c, TT &X, double eps, bool truncate, std::vector<doubl
         GemmBatch b;
         b.nb1 = nc; b.sA1 = X.cstride(0); b.sB1 = (long long)R1 * R1; b.sC1 = (long long)N0 * R1;
         gemm_f64(s, false, true, N0, R1, R1, 1.0, X.core[0], R1, T[1], R1, 0.0, C0, R1, b);
-        double *dn = c->sc.get<double>(S_NORMS, nc);
-        frob_norms(s, nc, (long long)N0 * R1, C0, (long long)N0 * R1, dn);
-        norms.resize(nc);
-        WTT_HIP(hipMemcpyAsync(c->h_pinned_dbl, dn, nc * sizeof(double), hipMemcpyDeviceToHost, s));
-        WTT_HIP(hipStreamSynchronize(s));
-        for (int z = 0; z < nc; ++z) norms[z] = c->h_pinned_dbl[z];
+        // the truncation thresholds delta_c = eps ||X_c|| / sqrt(d - 1) stay on the device; the
+        // norms reach the host through a pinned copy read after the next synchronisation
+        double *dn = c->sc.get<double>(S_NORMS, 2 * (size_t)nc);
+        frob_norms(s, nc, (long long)N0 * R1, C0, (long long)N0 * R1, dn, dn + nc,
+                   eps / std::sqrt((double)std::max(d - 1, 1)));
+        WTT_HIP(hipMemcpyAsync(c->h_pinned_dbl + kPinNorms, dn, nc * sizeof(double), hipMemcpyDeviceToHost, s));
+        norms.assign(nc, 0.0);
     }
-    if (!truncate) {
+    const double *ddelta = c->sc.get<double>(S_NORMS, 2 * (size_t)nc) + nc;
+    if (!truncate || d < 2) {
+        WTT_HIP(hipStreamSynchronize(s));
+        norms.assign(c->h_pinned_dbl + kPinNorms, c->h_pinned_dbl + kPinNorms + nc);
         for (int k = 1; k < d; ++k) dfree(s, T[k]);
         return;
     }
-    std::vector<double> delta(nc);
-    for (int z = 0; z < nc; ++z) delta[z] = eps * norms[z] / std::sqrt((double)std::max(d - 1, 1));
-    const double *ddelta = c->ring.put(delta.data(), delta.size());
     for (int k = 0; k < d - 1; ++k) {
         const int Rk = X.R[k], Nk = X.N[k], n = X.R[k + 1];
         const int m = Rk * Nk;
@@ -1158,6 +1167,8 @@ void round_tt(wenott_ctx *c, TT &X, double eps, bool truncate, std::vector<doubl
         X.R[k + 1] = r;
     }
     for (int k = 1; k < d; ++k) dfree(s, T[k]);
+    // the truncation ranks were read after the norms were copied
+    norms.assign(c->h_pinned_dbl + kPinNorms, c->h_pinned_dbl + kPinNorms + nc);
 }
 
 // ===================================================================== batched stepping
@@ -1863,12 +1874,25 @@ wenott_status wenott_rk3_step(wenott_ctx *c, double dt, double eps_in, const dou
         std::vector<double> norms;
         try {
             for (int st = 0; st < 3; ++st) {
-                double a;
+                double a = 0.0;
+                // Deferred alpha: the exact alpha stays on the device for the fiber kernels and is
+                // read back after the stage's next synchronisation (the proposal's features and
+                // the per-direction scheme need it on the host at once).
+                const bool deferred = !alphas && c->o.alpha_mode != 2 && !(st == 0 && c->alpha_cache_valid) &&
+                                      c->o.scheme == 0 && !c->o.use_proposal && !c->logging;
                 if (alphas) a = alphas[st];
                 else if (c->o.alpha_mode == 2) a = c->o.alpha_given;
-                else a = exact_alpha(c, X);
-                WTT_REQUIRE(a > 0.0, WENOTT_EINVAL, "alpha must be positive");
-                c->info.alpha[st] = a;
+                else if (st == 0 && c->alpha_cache_valid) a = c->alpha_cache;
+                else if (deferred) {
+                    double *dal = c->sc.get<double>(S_DSCAL, 8) + 4;
+                    exact_alpha_launch(c, X, dal + st, st);
+                    c->alpha_dev = dal + st;
+                    a = 1.0;  // not used by the kernels while alpha_dev is set
+                } else a = exact_alpha(c, X);
+                if (!deferred) {
+                    WTT_REQUIRE(a > 0.0, WENOTT_EINVAL, "alpha must be positive");
+                    c->info.alpha[st] = a;
+                }
                 TT S;
                 if (c->o.scheme == 0) {
                     // stage-cross: one cross of a_s U^n + b_s (X + dt L(X)) itself
@@ -1889,17 +1913,26 @@ wenott_status wenott_rk3_step(wenott_ctx *c, double dt, double eps_in, const dou
                     for (auto &t : terms) t.release(c->s);
                 }
                 c->info.sum_rank[st] = S.maxrank();
-                round_tt(c, S, eps, true, norms);
+                round_tt(c, S, eps, true, norms);  // synchronises: the deferred alpha has arrived
                 if (x_owned) X.release(c->s);
                 X = S;
                 x_owned = true;
+                if (deferred) {
+                    c->alpha_dev = nullptr;
+                    raise_flags(c, c->h_pinned_int[kPinAlpha + st]);
+                    a = c->h_pinned_dbl[kPinAlpha + st];
+                    WTT_REQUIRE(a > 0.0, WENOTT_EINVAL, "alpha must be positive");
+                    c->info.alpha[st] = a;
+                }
             }
         } catch (...) {
+            c->alpha_dev = nullptr;
             if (x_owned) X.release(c->s);
             throw;
         }
         c->U.release(c->s);
         c->U = X;
+        c->alpha_cache_valid = false;
         c->max_norm = *std::max_element(norms.begin(), norms.end());
         c->info.max_norm = c->max_norm;
         c->info.eps = eps;
@@ -1946,8 +1979,8 @@ wenott_status wenott_batch_rk3_step(wenott_ctx **ctxs, int32_t n, const double *
                     if (b.c->o.alpha_mode == 2) {
                         b.alpha = b.c->o.alpha_given;
                     } else {
-                        raise_flags(b.c, b.c->h_pinned_int[64]);
-                        b.alpha = b.c->h_pinned_dbl[64];
+                        raise_flags(b.c, b.c->h_pinned_int[kPinAlpha]);
+                        b.alpha = b.c->h_pinned_dbl[kPinAlpha];
                     }
                     WTT_REQUIRE(b.alpha > 0.0, WENOTT_EINVAL, "alpha must be positive");
                     b.c->info.alpha[st] = b.alpha;
@@ -1979,6 +2012,7 @@ wenott_status wenott_batch_rk3_step(wenott_ctx **ctxs, int32_t n, const double *
             wenott_ctx *c = b.c;
             c->U.release(c->s);
             c->U = b.X;
+            c->alpha_cache_valid = false;
             c->max_norm = *std::max_element(b.norms.begin(), b.norms.end());
             c->info.max_norm = c->max_norm;
             c->info.eps = b.eps;
@@ -1993,6 +2027,7 @@ wenott_status wenott_round(wenott_ctx *c, double eps) {
     return run_guarded(c, [&] {
         std::vector<double> norms;
         round_tt(c, c->U, eps, true, norms);
+        c->alpha_cache_valid = false;
         c->max_norm = *std::max_element(norms.begin(), norms.end());
     });
 }
@@ -2029,7 +2064,11 @@ wenott_status wenott_get_info(wenott_ctx *c, wenott_info *info) {
 
 wenott_status wenott_max_wavespeed(wenott_ctx *c, double *alpha) {
     if (!c || !alpha) return WENOTT_EINVAL;
-    return run_guarded(c, [&] { *alpha = exact_alpha(c, c->U); });
+    return run_guarded(c, [&] {
+        *alpha = exact_alpha(c, c->U);
+        c->alpha_cache = *alpha;  // the first stage of the next step reuses it
+        c->alpha_cache_valid = *alpha > 0.0;
+    });
 }
 
 wenott_status wenott_current_eps(wenott_ctx *c, double *eps) {

@@ -167,7 +167,7 @@ __global__ __launch_bounds__(256) void k_weno(FiberGeom g, int p, int M, int q, 
             for (int c = 0; c < NC; ++c) qv[c] = W[((((long long)c * 6 + s) * p + a) * Nk + i) * q + b];
         }
         T fpt[NC], fmt[NC];
-        ok &= split_flux<ND, T>(qv, g.dir, T(g.gamma - 1.0), T(g.alpha), fpt, fmt);
+        ok &= split_flux<ND, T>(qv, g.dir, T(g.gamma - 1.0), T(geom_alpha(g)), fpt, fmt);
 #pragma unroll
         for (int c = 0; c < NC; ++c) { fp[c][s] = fpt[c]; fm[c][s] = fmt[c]; }
     }
@@ -302,7 +302,7 @@ __global__ __launch_bounds__(256) void k_sample_flux(FiberGeom g, CoreSet fs, in
         for (int s = 0; s < 6; ++s) {
             double qv[NC], a[NC], b[NC];
             for (int c = 0; c < NC; ++c) qv[c] = ust[((long long)pt * 6 + s) * NC + c];
-            ok &= split_flux<ND, double>(qv, g.dir, g.gamma - 1.0, g.alpha, a, b);
+            ok &= split_flux<ND, double>(qv, g.dir, g.gamma - 1.0, geom_alpha(g), a, b);
             for (int c = 0; c < NC; ++c) { fp[c][s] = a[c]; fm[c][s] = b[c]; }
         }
         // approximation: shared cores 0..d-2, last core (R, M, NC)
@@ -387,7 +387,7 @@ __global__ __launch_bounds__(256) void k_stage(FiberGeom g, int p, int q, StageA
     const long long r = e / q;
     const int i = (int)(r % Nk);
     const int a = (int)(r / Nk);
-    const T gm1 = T(g.gamma - 1.0), alpha = T(g.alpha);
+    const T gm1 = T(g.gamma - 1.0), alpha = T(geom_alpha(g));
     T acc[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) acc[c] = T(0);
@@ -466,7 +466,7 @@ __global__ __launch_bounds__(256) void k_sample_stage(FiberGeom g, CoreSet fs, i
             double v[NC][7];
             for (int s = 0; s < 7; ++s)
                 for (int c = 0; c < NC; ++c) v[c][s] = u[(d * 7 + s) * NC + c];
-            ok &= stage_dir<ND, double>(v, d, g.gamma - 1.0, g.alpha, hs.eps_w[d], hs.inv_h[d], L);
+            ok &= stage_dir<ND, double>(v, d, g.gamma - 1.0, geom_alpha(g), hs.eps_w[d], hs.inv_h[d], L);
         }
         const int *m = pts + pt * ND;
         double approx[NC];

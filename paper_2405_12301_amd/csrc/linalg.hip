@@ -33,6 +33,64 @@ __device__ __forceinline__ double readlane_d(double v, int lane) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+
+template <int CTRL>
+__device__ __forceinline__ long long dpp_ll(long long v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(v >> 32), CTRL, 0xF, 0xF, false);
+    return ((long long)hi << 32) | (unsigned)lo;
+}
+
+__device__ __forceinline__ long long readlane_ll(long long v, int lane) {
+    const int lo = __builtin_amdgcn_readlane((int)v, lane);
+    const int hi = __builtin_amdgcn_readlane((int)(v >> 32), lane);
+    return ((long long)hi << 32) | (unsigned)lo;
+}
+
+// (largest magnitude, its linear index) with ties to the lower index, and a running sum.
+template <typename I>
+__device__ __forceinline__ void amax_merge(double &m, I &i, double om, I oi) {
+    const bool take = om > m || (om == m && oi < i);
+    m = take ? om : m;
+    i = take ? oi : i;
+}
+
+template <int CTRL, typename I>
+__device__ __forceinline__ void amax_sum_step(double &m, I &i, double &s) {
+    const double om = dpp_d<CTRL>(m), os = dpp_d<CTRL>(s);
+    I oi;
+    if constexpr (sizeof(I) == 8) oi = dpp_ll<CTRL>(i);
+    else oi = dpp_i<CTRL>(i);
+    amax_merge(m, i, om, oi);
+    s += os;
+}
+
+// Wave-wide argmax and sum (every lane active); every lane gets the results.
+template <typename I>
+__device__ __forceinline__ void wave_amax_sum(double &m, I &i, double &s) {
+    amax_sum_step<0xB1>(m, i, s);
+    amax_sum_step<0x4E>(m, i, s);
+    amax_sum_step<0x141>(m, i, s);
+    amax_sum_step<0x140>(m, i, s);
+    double rm[4], rs[4];
+    I ri[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        rm[r] = readlane_d(m, 16 * r);
+        rs[r] = readlane_d(s, 16 * r);
+        if constexpr (sizeof(I) == 8) ri[r] = readlane_ll(i, 16 * r);
+        else ri[r] = __builtin_amdgcn_readlane(i, 16 * r);
+    }
+    m = rm[0]; i = ri[0];
+#pragma unroll
+    for (int r = 1; r < 4; ++r) amax_merge(m, i, rm[r], ri[r]);
+    s = (rs[0] + rs[1]) + (rs[2] + rs[3]);
+}
+
 // Sum over the 64 lanes of a wave (every lane active); every lane gets the result. Within each
 // row of 16 lanes: swap neighbours, swap pairs (quad permutations), mirror halves, mirror the
 // row; then the four row sums are read from lanes 0, 16, 32, 48.
@@ -130,43 +188,49 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, double alpha,
 // column below the diagonal, which the wave that updated column j in the previous step left in
 // LDS; the waves then apply it to the trailing columns, the wave of column j + 1 also forming
 // that column's new norm. One barrier per column.
-__global__ __launch_bounds__(1024) void k_hhqr(int m, int n, int bm, int nblk, const double *__restrict__ A,
-                                              long long sz, long long rs, long long cs, double *__restrict__ Rout,
-                                              double *__restrict__ scratch, int use_lds) {
+template <int RPL, int NT>
+__global__ __launch_bounds__(NT) void k_hhqr(int m, int n, int bm, int nblk, const double *__restrict__ A,
+                                            long long sz, long long rs, long long cs, double *__restrict__ Rout,
+                                            double *__restrict__ scratch, int use_lds) {
     extern __shared__ double wlds[];
-    __shared__ double red[16];
+    __shared__ double red[NT / kWave];
     __shared__ double snorm[2];
     const int blk = blockIdx.x, z = blockIdx.y, tid = threadIdx.x;
-    const int lane = tid % kWave, w = tid / kWave, nw = blockDim.x / kWave;
+    const int lane = tid % kWave, w = tid / kWave, nw = NT / kWave;
     const int r0 = blk * bm;
     const int nr = min(bm, m - r0);
+    // LDS copies use a padded leading dimension so that a row of consecutive columns does not
+    // fall into one bank
+    const int ldw = use_lds ? bm + 1 : bm;
     double *W = use_lds ? wlds : scratch + ((long long)z * nblk + blk) * (long long)bm * n;
     const double *Az = A + (long long)z * sz;
     const long long tot = (long long)nr * n;
     if (cs <= rs) {
-        for (long long e = tid; e < tot; e += blockDim.x) {
+        for (long long e = tid; e < tot; e += NT) {
             int i = (int)(e / n), j = (int)(e % n);
-            W[(long long)j * bm + i] = Az[(long long)(r0 + i) * rs + (long long)j * cs];
+            W[(long long)j * ldw + i] = Az[(long long)(r0 + i) * rs + (long long)j * cs];
         }
     } else {
-        for (long long e = tid; e < tot; e += blockDim.x) {
+        for (long long e = tid; e < tot; e += NT) {
             int j = (int)(e / nr), i = (int)(e % nr);
-            W[(long long)j * bm + i] = Az[(long long)(r0 + i) * rs + (long long)j * cs];
+            W[(long long)j * ldw + i] = Az[(long long)(r0 + i) * rs + (long long)j * cs];
         }
     }
     __syncthreads();
     {
         double ss = 0.0;
-        for (int i = 1 + tid; i < nr; i += blockDim.x) ss += W[i] * W[i];
+        for (int i = 1 + tid; i < nr; i += NT) ss += W[i] * W[i];
         ss = block_sum(ss, red);
         if (tid == 0) snorm[0] = ss;
     }
     __syncthreads();
+    // lane L owns rows L + 64 q, q < RPL (RPL * 64 >= bm); a column's entries at those rows are
+    // loaded into registers together, so one LDS latency covers the whole column
     const int kmax = min(nr, n);
     double beta_prev = 0.0;
     for (int j = 0; j < kmax; ++j) {
-        double *col = W + (long long)j * bm;
-        if (tid == 0 && j > 0) W[(long long)(j - 1) * bm + (j - 1)] = beta_prev;  // nobody reads it any more
+        const double *col = W + (long long)j * ldw;
+        if (tid == 0 && j > 0) W[(long long)(j - 1) * ldw + (j - 1)] = beta_prev;  // nobody reads it any more
         const double a = col[j], xn2 = snorm[j & 1];
         double beta, tau, scale;
         if (xn2 == 0.0) {
@@ -177,38 +241,59 @@ __global__ __launch_bounds__(1024) void k_hhqr(int m, int n, int bm, int nblk, c
             scale = 1.0 / (a - beta);
         }
         beta_prev = beta;
+        if (j + 1 + w < n) {  // this wave has trailing columns
+        double cv[RPL];
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) {
+            const int i = lane + kWave * q;
+            cv[q] = (i > j && i < nr) ? col[i] : 0.0;
+        }
         // v = [1; scale * col[j+1..]]; each trailing column l: cl -= tau (v . cl) v
         for (int l = j + 1 + w; l < n; l += nw) {
-            double *cl = W + (long long)l * bm;
+            double *cl = W + (long long)l * ldw;
+            double x[RPL];
+#pragma unroll
+            for (int q = 0; q < RPL; ++q) {
+                const int i = lane + kWave * q;
+                x[q] = (i > j && i < nr) ? cl[i] : 0.0;
+            }
             double ss = 0.0;  // squared norm of the updated column below row j + 1 (for l = j + 1)
             if (tau != 0.0) {
                 double dot = 0.0;
-                for (int i = j + 1 + lane; i < nr; i += kWave) dot += col[i] * cl[i];
+#pragma unroll
+                for (int q = 0; q < RPL; ++q) dot = fma(cv[q], x[q], dot);
                 const double clj = readlane_d(lane == 0 ? cl[j] : 0.0, 0);
                 dot = clj + scale * wave_sum(dot);
                 const double f = tau * dot, fs = f * scale;
                 if (lane == 0) cl[j] = clj - f;
-                for (int i = j + 1 + lane; i < nr; i += kWave) {
-                    const double v = cl[i] - fs * col[i];
-                    cl[i] = v;
-                    if (i >= j + 2) ss += v * v;
+#pragma unroll
+                for (int q = 0; q < RPL; ++q) {
+                    const int i = lane + kWave * q;
+                    const double v = x[q] - fs * cv[q];
+                    if (i > j && i < nr) cl[i] = v;
+                    if (i >= j + 2 && i < nr) ss = fma(v, v, ss);
                 }
             } else {
-                for (int i = j + 2 + lane; i < nr; i += kWave) ss += cl[i] * cl[i];
+#pragma unroll
+                for (int q = 0; q < RPL; ++q) {
+                    const int i = lane + kWave * q;
+                    if (i >= j + 2) ss = fma(x[q], x[q], ss);
+                }
             }
             if (l == j + 1) {
                 ss = wave_sum(ss);
                 if (lane == 0) snorm[(j + 1) & 1] = ss;
             }
         }
+        }
         __syncthreads();
     }
-    if (tid == 0 && kmax > 0) W[(long long)(kmax - 1) * bm + (kmax - 1)] = beta_prev;
+    if (tid == 0 && kmax > 0) W[(long long)(kmax - 1) * ldw + (kmax - 1)] = beta_prev;
     __syncthreads();
     double *R = Rout + ((long long)z * nblk + blk) * (long long)n * n;
-    for (long long e = tid; e < (long long)n * n; e += blockDim.x) {
+    for (long long e = tid; e < (long long)n * n; e += NT) {
         int i = (int)(e / n), jj = (int)(e % n);
-        R[e] = (i <= jj && i < nr) ? W[(long long)jj * bm + i] : 0.0;
+        R[e] = (i <= jj && i < nr) ? W[(long long)jj * ldw + i] : 0.0;
     }
 }
 
@@ -513,18 +598,15 @@ __device__ __forceinline__ void prrlu_mw_step_body(const PrrluJob &J, int t) {
         const long long rb = (long long)(r0 + tr + k * RS) * n + c0;
 #pragma unroll
         for (int j = 0; j < kMwTW; ++j) {
-            const double v = a[k][j];
+            const double v = a[k][j], av = fabs(v);
             lsum = fma(v, v, lsum);
-            if (fabs(v) > lmax) { lmax = fabs(v); lidx = rb + j; }
+            const bool gt = av > lmax;
+            lmax = gt ? av : lmax;
+            lidx = gt ? rb + j : lidx;
         }
     }
     if (!active) { lmax = -1.0; lsum = 0.0; }
-    for (int off = kWave / 2; off > 0; off >>= 1) {
-        const double om = __shfl_xor(lmax, off, kWave);
-        const long long oi = __shfl_xor(lidx, off, kWave);
-        lsum += __shfl_xor(lsum, off, kWave);
-        if (om > lmax || (om == lmax && oi < lidx)) { lmax = om; lidx = oi; }
-    }
+    wave_amax_sum(lmax, lidx, lsum);
     if (lane == 0) { wmax[wv] = lmax; widx[wv] = lidx; wsum[wv] = lsum; }
     __syncthreads();
     if (tid == 0) {
@@ -548,17 +630,10 @@ __device__ __forceinline__ void prrlu_mw_step_body(const PrrluJob &J, int t) {
     double bm = -1.0, bs = 0.0;
     long long bi = 0x7fffffffffffffffLL;
     for (int b = tid; b < J.nblk; b += kMwThreads) {
-        const double vm = w.pmax[b];
-        const long long vi = w.pidx[b];
+        amax_merge(bm, bi, w.pmax[b], w.pidx[b]);
         bs += w.psum[b];
-        if (vm > bm || (vm == bm && vi < bi)) { bm = vm; bi = vi; }
     }
-    for (int off = kWave / 2; off > 0; off >>= 1) {
-        const double om = __shfl_xor(bm, off, kWave);
-        const long long oi = __shfl_xor(bi, off, kWave);
-        bs += __shfl_xor(bs, off, kWave);
-        if (om > bm || (om == bm && oi < bi)) { bm = om; bi = oi; }
-    }
+    wave_amax_sum(bm, bi, bs);
     __syncthreads();
     if (lane == 0) { wmax[wv] = bm; widx[wv] = bi; wsum[wv] = bs; }
     __syncthreads();
@@ -650,18 +725,15 @@ __device__ __forceinline__ void prrlu_tile_body(int m, int n, const double *__re
             const int rb = base + i * n;
 #pragma unroll
             for (int j = 0; j < TW; ++j) {
-                const double v = a[i][j];
+                const double v = a[i][j], av = fabs(v);
                 lsum = fma(v, v, lsum);
-                if (fabs(v) > lmax) { lmax = fabs(v); lidx = rb + j; }
+                const bool gt = av > lmax;
+                lmax = gt ? av : lmax;
+                lidx = gt ? rb + j : lidx;
             }
         }
         if (!active) lmax = -1.0;
-        for (int off = kWave / 2; off > 0; off >>= 1) {
-            const double om = __shfl_xor(lmax, off, kWave);
-            const int oi = __shfl_xor(lidx, off, kWave);
-            lsum += __shfl_xor(lsum, off, kWave);
-            if (om > lmax || (om == lmax && oi < lidx)) { lmax = om; lidx = oi; }
-        }
+        wave_amax_sum(lmax, lidx, lsum);
         if (lane == 0) { wmax[w] = lmax; widx[w] = lidx; wsum[w] = lsum; }
         __syncthreads();  // barrier A
         double bm = wmax[0];
@@ -904,17 +976,38 @@ void gemm_f64(hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha
     WTT_HIP(hipGetLastError());
 }
 
+// Row blocks of the TSQR: a leaf holds bm rows (all of them when they fit in LDS), a tree node
+// stacks `group` R factors.
+struct TsqrPlan {
+    int bm, nblk, group;
+    bool leaf_lds;
+};
+
+int lds_limit_bytes();
+
+size_t tsqr_lds_bytes(int rows, int n) { return sizeof(double) * (size_t)(rows + 1) * n; }
+
+TsqrPlan tsqr_plan(int m, int n) {
+    const long long budget = (long long)lds_limit_bytes() - 2048;  // static LDS of k_hhqr stays below 2 KB
+    const long long fit = budget / (8LL * n) - 1;                 // rows with the padded leading dimension
+    TsqrPlan p;
+    const int want = leaf_rows(n);  // max(256, 2n) rows: two leaves of 256 beat one of 512
+    if (m <= want && m <= fit) p.bm = m;
+    else p.bm = want;
+    p.nblk = (m + p.bm - 1) / p.bm;
+    p.leaf_lds = (long long)tsqr_lds_bytes(p.bm, n) <= budget;
+    p.group = (int)std::max<long long>(2, std::min<long long>(std::max<long long>(fit, p.bm), 2048) / n);
+    return p;
+}
+
 size_t tsqr_scratch_doubles(int m, int n, int batch) {
-    // the Householder work area is reused by every level of the tree: size it for the largest
-    int bm = leaf_rows(n);
-    long long nblk = (m + bm - 1) / bm;
-    long long w = nblk * (long long)bm * n;
-    long long r = nblk * (long long)n * n;
-    long long nb = nblk;
-    while (nb > 1) {
-        long long group = std::max(2, bm / n);
-        long long nb2 = (nb + group - 1) / group;
-        w = std::max(w, nb2 * group * (long long)n * n);
+    // the global-memory Householder work area is reused by every level: size it for the largest
+    const TsqrPlan p = tsqr_plan(m, n);
+    long long w = (long long)p.nblk * p.bm * n;
+    const long long r = (long long)p.nblk * n * n;
+    for (long long nb = p.nblk; nb > 1;) {
+        const long long nb2 = (nb + p.group - 1) / p.group;
+        w = std::max(w, nb2 * p.group * (long long)n * n);
         nb = nb2;
     }
     return (size_t)batch * (size_t)(w + 2 * r);
@@ -932,42 +1025,45 @@ int lds_limit_bytes() {
     return lim;
 }
 
+void launch_hhqr(hipStream_t s, int nblk, int batch, bool lds, int m, int n, int bm, const double *A, long long sz,
+                 long long rs, long long cs, double *Rout, double *W) {
+    const size_t lb = lds ? tsqr_lds_bytes(bm, n) : 0;
+    const dim3 grid(nblk, batch);
+    if (bm <= 4 * kWave) k_hhqr<4, 1024><<<grid, 1024, lb, s>>>(m, n, bm, nblk, A, sz, rs, cs, Rout, W, lds);
+    else if (bm <= 8 * kWave) k_hhqr<8, 1024><<<grid, 1024, lb, s>>>(m, n, bm, nblk, A, sz, rs, cs, Rout, W, lds);
+    else if (bm <= 16 * kWave) k_hhqr<16, 1024><<<grid, 1024, lb, s>>>(m, n, bm, nblk, A, sz, rs, cs, Rout, W, lds);
+    else if (bm <= 32 * kWave) k_hhqr<32, 512><<<grid, 512, lb, s>>>(m, n, bm, nblk, A, sz, rs, cs, Rout, W, lds);
+    else throw StatusError(WENOTT_EINVAL, "TSQR row block too tall");
+    WTT_HIP(hipGetLastError());
+}
+
 void tsqr_r(hipStream_t s, int m, int n, int batch, const double *A, long long sz, long long rs, long long cs,
             double *R, double *scratch) {
-    int bm = leaf_rows(n);
-    int nblk = (m + bm - 1) / bm;
+    const TsqrPlan p = tsqr_plan(m, n);
+    int nblk = p.nblk;
     double *W = scratch;
-    long long wsize = (long long)nblk * bm * n;
+    long long wsize = (long long)nblk * p.bm * n;
     for (long long nb = nblk; nb > 1;) {
-        long long group = std::max(2, bm / n), nb2 = (nb + group - 1) / group;
-        wsize = std::max(wsize, nb2 * group * (long long)n * n);
+        const long long nb2 = (nb + p.group - 1) / p.group;
+        wsize = std::max(wsize, nb2 * p.group * (long long)n * n);
         nb = nb2;
     }
     double *R0 = W + (long long)batch * wsize;
     double *R1 = R0 + (long long)batch * nblk * n * n;
-    const size_t lds_budget = (size_t)lds_limit_bytes() - 2048;  // static LDS of k_hhqr stays below 2 KB
-    size_t lb = sizeof(double) * (size_t)bm * n;
-    k_hhqr<<<dim3(nblk, batch), 1024, lb <= lds_budget ? lb : 0, s>>>(m, n, bm, nblk, A, sz, rs, cs, R0, W,
-                                                                       lb <= lds_budget);
-    WTT_HIP(hipGetLastError());
+    const size_t lds_budget = (size_t)lds_limit_bytes() - 2048;
+    launch_hhqr(s, nblk, batch, p.leaf_lds, m, n, p.bm, A, sz, rs, cs, nblk == 1 ? R : R0, W);
     double *cur = R0, *nxt = R1;
     while (nblk > 1) {
-        int mm = nblk * n;  // stacked R factors
-        int group = std::max(2, bm / n);
-        int nb2 = (nblk + group - 1) / group;
-        int bm2 = group * n;
-        size_t lb2 = sizeof(double) * (size_t)bm2 * n;
-        k_hhqr<<<dim3(nb2, batch), 1024, lb2 <= lds_budget ? lb2 : 0, s>>>(mm, n, bm2, nb2, cur, (long long)nblk * n * n,
-                                                                          n, 1, nxt, W, lb2 <= lds_budget);
-        WTT_HIP(hipGetLastError());
+        const int mm = nblk * n;  // stacked R factors
+        const int nb2 = (nblk + p.group - 1) / p.group;
+        const int bm2 = std::min(p.group, nblk) * n;  // rows of a node
+        const bool lds2 = tsqr_lds_bytes(bm2, n) <= lds_budget;
+        double *out = nb2 == 1 ? R : nxt;
+        launch_hhqr(s, nb2, batch, lds2, mm, n, bm2, cur, (long long)nblk * n * n, n, 1, out, W);
         std::swap(cur, nxt);
         nblk = nb2;
     }
-    long long tot = (long long)batch * n * n;
-    k_copy<<<cdiv(tot, 256), 256, 0, s>>>(tot, cur, R);
-    WTT_HIP(hipGetLastError());
 }
-
 
 void jacobi_svd(hipStream_t s, int n, int batch, const double *A, double *sigma, double *V, double *scratch,
                 double *US, const double *delta) {

@@ -111,7 +111,8 @@ __global__ void k_projectors(int n, int batch, int R, const double *__restrict__
     W2[(long long)z * per + (long long)t * n + i] = keep ? v * sg : 0.0;        // R x n
 }
 
-__global__ void k_frob(long long len, const double *__restrict__ X, long long stride, double *__restrict__ out) {
+__global__ void k_frob(long long len, const double *__restrict__ X, long long stride, double *__restrict__ out,
+                       double *__restrict__ scaled, double scale) {
     __shared__ double red[16];
     const double *x = X + blockIdx.x * stride;
     double s = 0.0;
@@ -123,6 +124,7 @@ __global__ void k_frob(long long len, const double *__restrict__ X, long long st
         double t = 0.0;
         for (int i = 0; i < (int)(blockDim.x / kWave); ++i) t += red[i];
         out[blockIdx.x] = sqrt(t);
+        if (scaled) scaled[blockIdx.x] = scale * sqrt(t);
     }
 }
 
@@ -185,8 +187,9 @@ void build_projectors(hipStream_t s, int n, int batch, int R, const double *sigm
     WTT_HIP(hipGetLastError());
 }
 
-void frob_norms(hipStream_t s, int batch, long long len, const double *X, long long stride, double *out) {
-    k_frob<<<batch, 1024, 0, s>>>(len, X, stride, out);
+void frob_norms(hipStream_t s, int batch, long long len, const double *X, long long stride, double *out,
+                double *scaled, double scale) {
+    k_frob<<<batch, 1024, 0, s>>>(len, X, stride, out, scaled, scale);
     WTT_HIP(hipGetLastError());
 }
 
