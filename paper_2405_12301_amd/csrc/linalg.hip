@@ -91,6 +91,20 @@ __device__ __forceinline__ void wave_amax_sum(double &m, I &i, double &s) {
     s = (rs[0] + rs[1]) + (rs[2] + rs[3]);
 }
 
+// Argmax and sum over lanes 0..15 (every lane active); the result of row 0 is returned to all
+// lanes. Used to combine up to 16 per-wave partials read from LDS.
+template <typename I>
+__device__ __forceinline__ void row0_amax_sum(double &m, I &i, double &s) {
+    amax_sum_step<0xB1>(m, i, s);
+    amax_sum_step<0x4E>(m, i, s);
+    amax_sum_step<0x141>(m, i, s);
+    amax_sum_step<0x140>(m, i, s);
+    m = readlane_d(m, 0);
+    s = readlane_d(s, 0);
+    if constexpr (sizeof(I) == 8) i = readlane_ll(i, 0);
+    else i = __builtin_amdgcn_readlane(i, 0);
+}
+
 // Sum over the 64 lanes of a wave (every lane active); every lane gets the result. Within each
 // row of 16 lanes: swap neighbours, swap pairs (quad permutations), mirror halves, mirror the
 // row; then the four row sums are read from lanes 0, 16, 32, 48.
@@ -736,13 +750,10 @@ __device__ __forceinline__ void prrlu_tile_body(int m, int n, const double *__re
         wave_amax_sum(lmax, lidx, lsum);
         if (lane == 0) { wmax[w] = lmax; widx[w] = lidx; wsum[w] = lsum; }
         __syncthreads();  // barrier A
-        double bm = wmax[0];
-        int bi = widx[0];
-        bs = 0.0;
-        for (int k = 0; k < nw; ++k) {
-            bs += wsum[k];
-            if (wmax[k] > bm || (wmax[k] == bm && widx[k] < bi)) { bm = wmax[k]; bi = widx[k]; }
-        }
+        double bm = lane < nw ? wmax[lane] : -1.0;
+        int bi = lane < nw ? widx[lane] : 0x7fffffff;
+        bs = lane < nw ? wsum[lane] : 0.0;
+        row0_amax_sum(bm, bi, bs);
         if (t == 0) tol2 = rel_tol2 * bs;
         stop = (t >= rmax) || (bm <= 0.0) || (bs <= tol2);
         if (t == 0 && bm <= 0.0) stop = 2;
