@@ -172,6 +172,18 @@ wenott_status wenott_rk3_step(wenott_ctx *ctx, double dt, double eps, const doub
  */
 wenott_status wenott_batch_rk3_step(wenott_ctx **ctxs, int32_t n, const double *dt, const double *eps);
 
+/*
+ * Tile autotuner of the FP64 contractions (process-wide). Each problem bucket (transposes and
+ * the binary orders of magnitude of M, N, K and the batch) is tuned on its first live calls:
+ * the candidate tile shapes are timed with events collected without synchronising, and the
+ * fastest is kept. Every shape sums in the same order, so results do not depend on the table.
+ * on = 0: the default shape everywhere. The table call copies up to max rows of
+ * {ta, tb, log2 M, log2 N, log2 K, log2 batch, shape (-1 while tuning)} into out (may be NULL)
+ * and stores the number of rows in *count.
+ */
+wenott_status wenott_gemm_autotune(int32_t on);
+wenott_status wenott_gemm_autotune_table(int32_t *out, int32_t max, int32_t *count);
+
 /* TT-rounding of the state (Sec. 3.2): right-to-left orthogonalisation, then left-to-right
  * truncated SVDs, so that ||X - Y||_F <= eps ||X||_F per component. eps > 0. */
 wenott_status wenott_round(wenott_ctx *ctx, double eps);

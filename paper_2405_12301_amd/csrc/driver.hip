@@ -2022,6 +2022,17 @@ wenott_status wenott_batch_rk3_step(wenott_ctx **ctxs, int32_t n, const double *
     });
 }
 
+wenott_status wenott_gemm_autotune(int32_t on) {
+    gemm_tune_enable(on != 0);
+    return WENOTT_OK;
+}
+
+wenott_status wenott_gemm_autotune_table(int32_t *out, int32_t max, int32_t *count) {
+    if (!count || max < 0) return WENOTT_EINVAL;
+    *count = gemm_tune_table(out, out ? max : 0);
+    return WENOTT_OK;
+}
+
 wenott_status wenott_round(wenott_ctx *c, double eps) {
     if (!c || !(eps > 0.0)) return WENOTT_EINVAL;
     return run_guarded(c, [&] {

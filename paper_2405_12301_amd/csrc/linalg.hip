@@ -7,6 +7,10 @@
 //    each step takes the largest residual entry, found by wavefront reductions);
 //  - the interpolative basis L * inv(L[I, :]) of a cross (Sec. 3.3, CUR / skeleton form).
 #include <algorithm>
+#include <array>
+#include <map>
+#include <mutex>
+#include <vector>
 #include <cmath>
 
 #include "common.h"
@@ -129,65 +133,77 @@ __device__ inline double block_sum(double v, double *red) {
 }
 
 // ------------------------------------------------------------------------------ GEMM
-constexpr int BM = 64, BN = 64, BK = 16;
+constexpr int BK = 16;
 
-template <bool TA, bool TB>
+// C tile TBM x TBN per 256-thread workgroup; thread (ty, tx) = (t / 16, t % 16) owns rows
+// ty * (TBM / 16) + i and columns tx + 16 j. Every output sums over k in the same order for
+// every tile shape, so the shape changes the speed, never the result.
+template <bool TA, bool TB, int TBM, int TBN>
 __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, double alpha, const double *__restrict__ A,
                                               int lda, const double *__restrict__ B, int ldb, double beta,
                                               double *__restrict__ C, int ldc, GemmBatch bt) {
+    constexpr int RI = TBM / 16, RJ = TBN / 16;
     const int z = blockIdx.z, z1 = z / bt.nb2, z2 = z % bt.nb2;
     A += z1 * bt.sA1 + z2 * bt.sA2;
     B += z1 * bt.sB1 + z2 * bt.sB2;
     C += z1 * bt.sC1 + z2 * bt.sC2;
     if (bt.ktot > 0) K = min(K, bt.ktot - z2 * K);  // split-K: chunk z2 of the reduction
-    __shared__ double As[BK][BM + 1];
-    __shared__ double Bs[BK][BN + 1];
+    __shared__ double As[BK][TBM + 1];
+    __shared__ double Bs[BK][TBN + 1];
     const int t = threadIdx.x, tx = t % 16, ty = t / 16;
-    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
-    double acc[4][4];
+    const int m0 = blockIdx.y * TBM, n0 = blockIdx.x * TBN;
+    double acc[RI][RJ];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < RI; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+        for (int j = 0; j < RJ; ++j) acc[i][j] = 0.0;
     for (int k0 = 0; k0 < K; k0 += BK) {
 #pragma unroll
-        for (int l = 0; l < 4; ++l) {
-            int e = t + 256 * l, r, kk;
-            if (!TA) { r = e / BK; kk = e % BK; } else { kk = e / BM; r = e % BM; }
-            int gm = m0 + r, gk = k0 + kk;
-            double v = 0.0;
-            if (gm < M && gk < K) v = TA ? A[(long long)gk * lda + gm] : A[(long long)gm * lda + gk];
-            As[kk][r] = v;
-            int c;
-            if (!TB) { kk = e / BN; c = e % BN; } else { c = e / BK; kk = e % BK; }
-            int gn = n0 + c;
-            gk = k0 + kk;
-            v = 0.0;
-            if (gn < N && gk < K) v = TB ? B[(long long)gn * ldb + gk] : B[(long long)gk * ldb + gn];
-            Bs[kk][c] = v;
+        for (int l = 0; l < (TBM * BK + 255) / 256; ++l) {
+            const int e = t + 256 * l;
+            if (e < TBM * BK) {
+                int r, kk;
+                if (!TA) { r = e / BK; kk = e % BK; } else { kk = e / TBM; r = e % TBM; }
+                const int gm = m0 + r, gk = k0 + kk;
+                double v = 0.0;
+                if (gm < M && gk < K) v = TA ? A[(long long)gk * lda + gm] : A[(long long)gm * lda + gk];
+                As[kk][r] = v;
+            }
+        }
+#pragma unroll
+        for (int l = 0; l < (TBN * BK + 255) / 256; ++l) {
+            const int e = t + 256 * l;
+            if (e < TBN * BK) {
+                int c, kk;
+                if (!TB) { kk = e / TBN; c = e % TBN; } else { c = e / BK; kk = e % BK; }
+                const int gn = n0 + c, gk = k0 + kk;
+                double v = 0.0;
+                if (gn < N && gk < K) v = TB ? B[(long long)gn * ldb + gk] : B[(long long)gk * ldb + gn];
+                Bs[kk][c] = v;
+            }
         }
         __syncthreads();
 #pragma unroll
         for (int kk = 0; kk < BK; ++kk) {
-            double a[4], b[4];
+            double a[RI], b[RJ];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) a[i] = As[kk][ty * 4 + i];
+            for (int i = 0; i < RI; ++i) a[i] = As[kk][ty * RI + i];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tx + 16 * j];
+            for (int j = 0; j < RJ; ++j) b[j] = Bs[kk][tx + 16 * j];
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < RI; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+                for (int j = 0; j < RJ; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
         }
         __syncthreads();
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        int gm = m0 + ty * 4 + i;
+    for (int i = 0; i < RI; ++i) {
+        const int gm = m0 + ty * RI + i;
         if (gm >= M) continue;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            int gn = n0 + tx + 16 * j;
+        for (int j = 0; j < RJ; ++j) {
+            const int gn = n0 + tx + 16 * j;
             if (gn >= N) continue;
             double *c = C + (long long)gm * ldc + gn;
             *c = beta == 0.0 ? alpha * acc[i][j] : alpha * acc[i][j] + beta * *c;
@@ -976,15 +992,168 @@ inline unsigned cdiv(long long a, long long b) { return (unsigned)((a + b - 1) /
 
 }  // namespace
 
+namespace {
+
+// ------------------------------------------------------------------ GEMM autotuner
+// Tile shapes (TBM x TBN) of k_gemm. The table maps a bucket of the problem (transposes and the
+// binary orders of magnitude of M, N, K and the batch) to the shape chosen for it. A bucket seen
+// for the first time is tuned on the live calls: each call launches the next candidate between
+// two events; the timings are collected when the events have completed (no synchronisation),
+// and after kTuneSamples timings of every candidate the fastest shape is kept.
+constexpr int kGemmShapes[][2] = {{64, 64}, {32, 64}, {64, 32}, {32, 32}};
+constexpr int kNumGemmShapes = 4, kTuneSamples = 3;
+
+struct TuneEntry {
+    int choice = -1;  // chosen shape, -1 while tuning
+    int next = 0;     // next candidate to time
+    int count[kNumGemmShapes] = {};
+    float total[kNumGemmShapes] = {};
+    struct Pending {
+        int cand;
+        hipEvent_t e0, e1;
+    };
+    std::vector<Pending> pending;
+};
+
+struct GemmTuner {
+    std::mutex mu;
+    std::map<std::array<int, 6>, TuneEntry> table;
+    std::vector<hipEvent_t> free_events;
+    int enabled = 1;
+    hipEvent_t get_event() {
+        if (!free_events.empty()) {
+            hipEvent_t e = free_events.back();
+            free_events.pop_back();
+            return e;
+        }
+        hipEvent_t e;
+        WTT_HIP(hipEventCreate(&e));
+        return e;
+    }
+};
+
+GemmTuner &tuner() {
+    static GemmTuner *t = new GemmTuner();  // lives until the process ends (events may be in flight)
+    return *t;
+}
+
+int log2_bucket(long long x) {
+    int b = 0;
+    while ((1LL << b) < x && b < 40) ++b;
+    return b;
+}
+
+template <bool TA, bool TB>
+void launch_gemm_shape(int shape, hipStream_t s, int M, int N, int K, double alpha, const double *A, int lda,
+                       const double *B, int ldb, double beta, double *C, int ldc, const GemmBatch &bt) {
+    const int tbm = kGemmShapes[shape][0], tbn = kGemmShapes[shape][1];
+    dim3 grid(cdiv(N, tbn), cdiv(M, tbm), bt.nb1 * bt.nb2), block(256);
+    switch (shape) {
+        case 0: k_gemm<TA, TB, 64, 64><<<grid, block, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, bt); break;
+        case 1: k_gemm<TA, TB, 32, 64><<<grid, block, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, bt); break;
+        case 2: k_gemm<TA, TB, 64, 32><<<grid, block, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, bt); break;
+        default: k_gemm<TA, TB, 32, 32><<<grid, block, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, bt); break;
+    }
+}
+
+void launch_gemm(int shape, hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha, const double *A,
+                 int lda, const double *B, int ldb, double beta, double *C, int ldc, const GemmBatch &bt) {
+    if (!ta && !tb) launch_gemm_shape<false, false>(shape, s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, bt);
+    else if (ta && !tb) launch_gemm_shape<true, false>(shape, s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, bt);
+    else if (!ta && tb) launch_gemm_shape<false, true>(shape, s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, bt);
+    else launch_gemm_shape<true, true>(shape, s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, bt);
+}
+
+}  // namespace
+
+void gemm_tune_enable(int on) {
+    GemmTuner &t = tuner();
+    std::lock_guard<std::mutex> lk(t.mu);
+    t.enabled = on;
+}
+
+int gemm_tune_table(int32_t *out, int max_entries) {
+    GemmTuner &t = tuner();
+    std::lock_guard<std::mutex> lk(t.mu);
+    int n = 0;
+    for (auto &kv : t.table) {
+        if (out && n < max_entries) {
+            for (int q = 0; q < 6; ++q) out[n * 7 + q] = kv.first[q];
+            out[n * 7 + 6] = kv.second.choice;
+        }
+        ++n;
+    }
+    return n;
+}
+
+namespace {
+
+void gemm_f64_tuned(hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha, const double *A, int lda,
+                    const double *B, int ldb, double beta, double *C, int ldc, const GemmBatch &bt) {
+    GemmTuner &t = tuner();
+    int shape = 0;
+    TuneEntry::Pending timed{-1, nullptr, nullptr};
+    {
+        std::lock_guard<std::mutex> lk(t.mu);
+        if (t.enabled) {
+            const std::array<int, 6> key{(int)ta, (int)tb, log2_bucket(M), log2_bucket(N), log2_bucket(K),
+                                         log2_bucket((long long)bt.nb1 * bt.nb2)};
+            TuneEntry &e = t.table[key];
+            if (e.choice >= 0) {
+                shape = e.choice;
+            } else {
+                // collect the timings that have arrived
+                for (size_t q = 0; q < e.pending.size();) {
+                    auto &pd = e.pending[q];
+                    if (hipEventQuery(pd.e1) == hipSuccess) {
+                        float ms = 0.f;
+                        if (hipEventElapsedTime(&ms, pd.e0, pd.e1) == hipSuccess) {
+                            e.total[pd.cand] += ms;
+                            e.count[pd.cand] += 1;
+                        }
+                        t.free_events.push_back(pd.e0);
+                        t.free_events.push_back(pd.e1);
+                        e.pending.erase(e.pending.begin() + q);
+                    } else {
+                        ++q;
+                    }
+                }
+                bool done = true;
+                for (int c = 0; c < kNumGemmShapes; ++c) done = done && e.count[c] >= kTuneSamples;
+                if (done) {
+                    int best = 0;
+                    for (int c = 1; c < kNumGemmShapes; ++c)
+                        if (e.total[c] / e.count[c] < e.total[best] / e.count[best]) best = c;
+                    e.choice = best;
+                    shape = best;
+                } else {
+                    shape = e.next;
+                    e.next = (e.next + 1) % kNumGemmShapes;
+                    timed.cand = shape;
+                    timed.e0 = t.get_event();
+                    timed.e1 = t.get_event();
+                }
+            }
+        }
+    }
+    if (timed.cand >= 0) WTT_HIP(hipEventRecord(timed.e0, s));
+    launch_gemm(shape, s, ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, bt);
+    WTT_HIP(hipGetLastError());
+    if (timed.cand >= 0) {
+        WTT_HIP(hipEventRecord(timed.e1, s));
+        std::lock_guard<std::mutex> lk(t.mu);
+        const std::array<int, 6> key{(int)ta, (int)tb, log2_bucket(M), log2_bucket(N), log2_bucket(K),
+                                     log2_bucket((long long)bt.nb1 * bt.nb2)};
+        t.table[key].pending.push_back(timed);
+    }
+}
+
+}  // namespace
+
 void gemm_f64(hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha, const double *A, int lda,
               const double *B, int ldb, double beta, double *C, int ldc, const GemmBatch &bt) {
     if (M <= 0 || N <= 0) return;
-    dim3 grid(cdiv(N, BN), cdiv(M, BM), bt.nb1 * bt.nb2), block(256);
-    if (!ta && !tb) k_gemm<false, false><<<grid, block, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, bt);
-    else if (ta && !tb) k_gemm<true, false><<<grid, block, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, bt);
-    else if (!ta && tb) k_gemm<false, true><<<grid, block, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, bt);
-    else k_gemm<true, true><<<grid, block, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, bt);
-    WTT_HIP(hipGetLastError());
+    gemm_f64_tuned(s, ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, bt);
 }
 
 // Row blocks of the TSQR: a leaf holds bm rows (all of them when they fit in LDS), a tree node

@@ -23,7 +23,8 @@ EXPORTED = ["wenott_default_opts", "wenott_init", "wenott_rhs", "wenott_rk3_step
             "wenott_strerror", "wenott_dense_init", "wenott_dense_max_wavespeed", "wenott_dense_rhs",
             "wenott_dense_rk3_step", "wenott_dense_destroy", "wenott_mlp_nparams", "wenott_mlp_workspace",
             "wenott_mlp_init_params", "wenott_mlp_forward", "wenott_mlp_loss_grad", "wenott_mlp_adam_step",
-            "wenott_set_proposal", "wenott_set_cross_logging", "wenott_get_cross_log", "wenott_batch_rk3_step"]
+            "wenott_set_proposal", "wenott_set_cross_logging", "wenott_get_cross_log", "wenott_batch_rk3_step",
+            "wenott_gemm_autotune", "wenott_gemm_autotune_table"]
 
 MLP_IN, MLP_HID, MLP_OUT, MLP_RANK_CLASSES, MLP_BINS = 96, 128, 81, 17, 64
 
@@ -83,6 +84,8 @@ def load(path: str = LIB_PATH):
     lib.wenott_rk3_step.argtypes = [vp, ctypes.c_double, ctypes.c_double, P(ctypes.c_double)]
     lib.wenott_batch_rk3_step.argtypes = [P(vp), ctypes.c_int32, P(ctypes.c_double), P(ctypes.c_double)]
     lib.wenott_round.argtypes = [vp, ctypes.c_double]
+    lib.wenott_gemm_autotune.argtypes = [ctypes.c_int32]
+    lib.wenott_gemm_autotune_table.argtypes = [P(ctypes.c_int32), ctypes.c_int32, P(ctypes.c_int32)]
     lib.wenott_to_dense.argtypes = [vp, vp, ctypes.c_int32]
     lib.wenott_get_state.argtypes = [vp, P(wenott_tt)]
     lib.wenott_get_info.argtypes = [vp, P(wenott_info)]
@@ -112,7 +115,8 @@ def load(path: str = LIB_PATH):
     lib.wenott_set_proposal.argtypes = [vp, vp]
     lib.wenott_set_cross_logging.argtypes = [vp, ctypes.c_int32]
     lib.wenott_get_cross_log.argtypes = [vp, vp, vp, vp, ctypes.c_int32, P(ctypes.c_int32)]
-    for name in ("wenott_init", "wenott_rhs", "wenott_rk3_step", "wenott_batch_rk3_step", "wenott_round", "wenott_to_dense",
+    for name in ("wenott_init", "wenott_rhs", "wenott_rk3_step", "wenott_batch_rk3_step", "wenott_round",
+                 "wenott_gemm_autotune", "wenott_gemm_autotune_table", "wenott_to_dense",
                  "wenott_get_state", "wenott_get_info", "wenott_max_wavespeed", "wenott_current_eps",
                  "wenott_set_profiling", "wenott_dense_init", "wenott_dense_max_wavespeed", "wenott_dense_rhs",
                  "wenott_dense_rk3_step", "wenott_mlp_init_params", "wenott_mlp_forward", "wenott_mlp_loss_grad",
@@ -210,6 +214,20 @@ def wenott_batch_rk3_step(ctxs, dts, eps=None):
     d = (ctypes.c_double * n)(*[float(x) for x in dts])
     e = None if eps is None else (ctypes.c_double * n)(*[float(x) for x in eps])
     _check(load().wenott_batch_rk3_step(arr, n, d, e), ctxs[0])
+
+
+def wenott_gemm_autotune(on):
+    _check(load().wenott_gemm_autotune(int(bool(on))), None)
+
+
+def wenott_gemm_autotune_table():
+    """Rows (ta, tb, log2 M, log2 N, log2 K, log2 batch, shape or -1 while tuning)."""
+    lib = load()
+    n = ctypes.c_int32(0)
+    _check(lib.wenott_gemm_autotune_table(None, 0, ctypes.byref(n)), None)
+    buf = (ctypes.c_int32 * (7 * max(n.value, 1)))()
+    _check(lib.wenott_gemm_autotune_table(buf, n.value, ctypes.byref(n)), None)
+    return [tuple(buf[7 * i:7 * i + 7]) for i in range(n.value)]
 
 
 def wenott_round(ctx, eps):

@@ -130,3 +130,29 @@ def test_batch_of_blasts_small_grids(W):
     finally:
         for s in solvers:
             s.close()
+
+
+def test_gemm_autotuner_changes_speed_not_results(W):
+    """The tile table is tuned on live calls; every tile shape sums in the same order, so a
+    step with the tuner on equals the step with the fixed shape bit for bit."""
+    _say("case: GEMM tile autotuner on vs off")
+    f = workloads.config2_quadrants_2d(64, seed=4)
+    opts = W.default_opts(eps_mode=0, eps0=1e-8)
+    outs = []
+    try:
+        for on in (0, 1):
+            W.wenott_gemm_autotune(on)
+            s = W.Solver(f, opts)
+            try:
+                dt = 0.5 * min(f.h) / s.max_wavespeed()
+                for _ in range(4):  # enough calls for several buckets to finish tuning
+                    s.step(dt)
+                outs.append(s.dense())
+            finally:
+                s.close()
+        table = W.wenott_gemm_autotune_table()
+        _say(f"  buckets {len(table)}, decided {sum(1 for r in table if r[6] >= 0)}")
+        assert len(table) > 0 and any(r[6] >= 0 for r in table)
+        assert np.array_equal(outs[0], outs[1])
+    finally:
+        W.wenott_gemm_autotune(1)
