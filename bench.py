@@ -42,6 +42,9 @@ def parse():
     ap.add_argument("--workload", default="quadrants2d", choices=["quadrants2d", "wave3d", "sod3d", "blast_batch"],
                     help="quadrants2d is the contract workload; the others are side measurements")
     ap.add_argument("--batch", type=int, default=32, help="states of the blast_batch workload")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 256 MiB device-to-device copy three times (the reference for "
+                         "the FETCH_SIZE / WRITE_SIZE counters)")
     ap.add_argument("--precision", type=int, default=0, help="0 FP64 fiber path, 1 FP32 fiber path")
     return ap.parse_args()
 
@@ -75,11 +78,38 @@ def cpu_baseline(flow, seconds):
 
 
 CLASS_NAMES = ["k_stage (fused star-stencil LF + WENO5-JS stage-value fiber kernel)",
-               "k_prrlu_reg (full-pivot rank-revealing LU, cross pivots)",
+               "k_prrlu (full-pivot rank-revealing LU, cross pivots: k_prrlu_tile / k_prrlu_mw_step)",
                "k_hhqr (Householder TSQR, rounding)", "k_jacobi_lds (one-sided Jacobi SVD, rounding)"]
+CLASS_KEYS = ["k_stage", "k_prrlu", "k_hhqr", "k_jacobi_lds"]
 
 
-def roofline_of(cls_ms, cls_fl, cls_by, cls_n, steps):
+def kernel_source_digest():
+    """sha256 over the HIP sources: traffic taken from counters is valid only for these."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2405_12301_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(os.path.basename(f).encode())
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload, cls_key):
+    """HBM bytes per class launch from the committed counter summary of this workload, or None
+    when there is none or the kernels changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    if t.get("source_sha256") != kernel_source_digest():
+        return None
+    c = t.get("classes", {}).get(cls_key)
+    return None if c is None else c.get("bytes_per_launch")
+
+
+def roofline_of(cls_ms, cls_fl, cls_by, cls_n, steps, workload=None):
     ncls = len(cls_ms)
     breakdown = {}
     for i in range(ncls):
@@ -88,12 +118,13 @@ def roofline_of(cls_ms, cls_fl, cls_by, cls_n, steps):
         if cls_fl[i] > 0 and cls_ms[i] > 0:
             entry["tflops"] = cls_fl[i] / (cls_ms[i] * 1e-3) / 1e12
             entry["gbs_algorithmic"] = cls_by[i] / (cls_ms[i] * 1e-3) / 1e9
-        breakdown[CLASS_NAMES[i].split()[0]] = entry
+        breakdown[CLASS_KEYS[i]] = entry
     # dominant kernel: the class with the most device time among those with an algorithmic count
     dom = max((i for i in range(ncls) if cls_fl[i] > 0), key=lambda i: cls_ms[i])
     achieved = cls_fl[dom] / (cls_ms[dom] * 1e-3) / 1e12 if cls_ms[dom] > 0 else 0.0
+    traffic = measured_traffic(workload, CLASS_KEYS[dom]) if workload else None
     return {"bound": "alu", "kernel": CLASS_NAMES[dom], "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
-            "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+            "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,
             "algorithmic_flops_per_launch": cls_fl[dom] / max(cls_n[dom], 1),
             "algorithmic_bytes_per_launch": cls_by[dom] / max(cls_n[dom], 1),
             "avg_launch_us": cls_ms[dom] * 1e3 / max(cls_n[dom], 1),
@@ -162,6 +193,16 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    if args.calibrate_copy:
+        import torch
+        n = 256 * 1024 * 1024 // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": n * 8, "copies": 3}))
+        return
     if args.workload == "blast_batch":
         blast_batch(args)
         return
@@ -223,7 +264,8 @@ def main():
     eps_now = info.eps
     solver.close()
 
-    roofline = roofline_of(cls_ms, cls_fl, cls_by, cls_n, args.steps)
+    roofline = roofline_of(cls_ms, cls_fl, cls_by, cls_n, args.steps,
+                           f"{args.workload}_{args.n}" if args.precision == 0 else None)
 
     dense = None
     if not args.no_dense:

@@ -218,7 +218,9 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, double alpha,
 // column below the diagonal, which the wave that updated column j in the previous step left in
 // LDS; the waves then apply it to the trailing columns, the wave of column j + 1 also forming
 // that column's new norm. One barrier per column.
-template <int RPL, int NT>
+// LEAF: leaf level (true, one launch per TSQR call) or tree level (false); the two levels get
+// distinct kernel names so that profiles can count TSQR calls.
+template <int RPL, int NT, bool LEAF>
 __global__ __launch_bounds__(NT) void k_hhqr(int m, int n, int bm, int nblk, const double *__restrict__ A,
                                             long long sz, long long rs, long long cs, double *__restrict__ Rout,
                                             double *__restrict__ scratch, int use_lds) {
@@ -1205,14 +1207,15 @@ int lds_limit_bytes() {
     return lim;
 }
 
+template <bool LEAF>
 void launch_hhqr(hipStream_t s, int nblk, int batch, bool lds, int m, int n, int bm, const double *A, long long sz,
                  long long rs, long long cs, double *Rout, double *W) {
     const size_t lb = lds ? tsqr_lds_bytes(bm, n) : 0;
     const dim3 grid(nblk, batch);
-    if (bm <= 4 * kWave) k_hhqr<4, 1024><<<grid, 1024, lb, s>>>(m, n, bm, nblk, A, sz, rs, cs, Rout, W, lds);
-    else if (bm <= 8 * kWave) k_hhqr<8, 1024><<<grid, 1024, lb, s>>>(m, n, bm, nblk, A, sz, rs, cs, Rout, W, lds);
-    else if (bm <= 16 * kWave) k_hhqr<16, 1024><<<grid, 1024, lb, s>>>(m, n, bm, nblk, A, sz, rs, cs, Rout, W, lds);
-    else if (bm <= 32 * kWave) k_hhqr<32, 512><<<grid, 512, lb, s>>>(m, n, bm, nblk, A, sz, rs, cs, Rout, W, lds);
+    if (bm <= 4 * kWave) k_hhqr<4, 1024, LEAF><<<grid, 1024, lb, s>>>(m, n, bm, nblk, A, sz, rs, cs, Rout, W, lds);
+    else if (bm <= 8 * kWave) k_hhqr<8, 1024, LEAF><<<grid, 1024, lb, s>>>(m, n, bm, nblk, A, sz, rs, cs, Rout, W, lds);
+    else if (bm <= 16 * kWave) k_hhqr<16, 1024, LEAF><<<grid, 1024, lb, s>>>(m, n, bm, nblk, A, sz, rs, cs, Rout, W, lds);
+    else if (bm <= 32 * kWave) k_hhqr<32, 512, LEAF><<<grid, 512, lb, s>>>(m, n, bm, nblk, A, sz, rs, cs, Rout, W, lds);
     else throw StatusError(WENOTT_EINVAL, "TSQR row block too tall");
     WTT_HIP(hipGetLastError());
 }
@@ -1231,7 +1234,7 @@ void tsqr_r(hipStream_t s, int m, int n, int batch, const double *A, long long s
     double *R0 = W + (long long)batch * wsize;
     double *R1 = R0 + (long long)batch * nblk * n * n;
     const size_t lds_budget = (size_t)lds_limit_bytes() - 2048;
-    launch_hhqr(s, nblk, batch, p.leaf_lds, m, n, p.bm, A, sz, rs, cs, nblk == 1 ? R : R0, W);
+    launch_hhqr<true>(s, nblk, batch, p.leaf_lds, m, n, p.bm, A, sz, rs, cs, nblk == 1 ? R : R0, W);
     double *cur = R0, *nxt = R1;
     while (nblk > 1) {
         const int mm = nblk * n;  // stacked R factors
@@ -1239,7 +1242,7 @@ void tsqr_r(hipStream_t s, int m, int n, int batch, const double *A, long long s
         const int bm2 = std::min(p.group, nblk) * n;  // rows of a node
         const bool lds2 = tsqr_lds_bytes(bm2, n) <= lds_budget;
         double *out = nb2 == 1 ? R : nxt;
-        launch_hhqr(s, nb2, batch, lds2, mm, n, bm2, cur, (long long)nblk * n * n, n, 1, out, W);
+        launch_hhqr<false>(s, nb2, batch, lds2, mm, n, bm2, cur, (long long)nblk * n * n, n, 1, out, W);
         std::swap(cur, nxt);
         nblk = nb2;
     }
