@@ -505,14 +505,13 @@ __global__ __launch_bounds__(1024) void k_jacobi_global(int n, const double *__r
 }
 
 // ------------------------------------------------------------------- prrLU (pivots)
-// Multi-workgroup variant for blocks too large for one workgroup's registers: one launch per
-// pivot step t. Each workgroup owns a run of whole rows; at step t it first applies the
-// elimination of pivot t-1 to its rows (writing column t-1 of L for them), then reduces its
-// rows' largest magnitude (ties to the lower linear index) and squared sum. The last workgroup
-// of a job to finish (ticket counter) combines the partials in workgroup order, takes the stop
-// decision of the single-workgroup forms and publishes pivot t and its row for the next launch.
-// Workspace (doubles): pivot row [n], partial max [nblk], partial sum [nblk], partial index
-// [nblk], control block, ticket.
+// Multi-workgroup variant for blocks too large for one workgroup's registers: two launches per
+// pivot step t. In the first, each workgroup owns a run of whole rows, applies the elimination
+// of pivot t-1 to them (writing column t-1 of L) and reduces their largest magnitude (ties to
+// the lower linear index) and squared sum. In the second, one workgroup per job combines the
+// partials in workgroup order, takes the stop decision of the single-workgroup form and
+// publishes pivot t and its row for the next step. Workspace (doubles): pivot row [n], partial
+// max [nblk], partial sum [nblk], partial index [nblk], control block.
 struct PrrluCtl {
     long long idx;
     double piv, tol2;
@@ -523,7 +522,6 @@ struct PrrluWs {
     double *rowbuf, *pmax, *psum;
     long long *pidx;
     PrrluCtl *ctl;
-    unsigned *ticket;
 };
 
 __host__ __device__ inline PrrluWs prrlu_ws_split(double *ws, int n, int nblk) {
@@ -533,11 +531,10 @@ __host__ __device__ inline PrrluWs prrlu_ws_split(double *ws, int n, int nblk) {
     w.psum = w.pmax + nblk;
     w.pidx = (long long *)(w.psum + nblk);
     w.ctl = (PrrluCtl *)(w.pidx + nblk);
-    w.ticket = (unsigned *)(w.ctl + 1);
     return w;
 }
 
-constexpr int kMwThreads = 256, kMwTW = 8, kMwK = 4;
+constexpr int kMwThreads = 256, kMwTW = 8, kMwK = 2;
 
 __device__ __forceinline__ void prrlu_mw_init_body(const PrrluJob &J) {
     const PrrluWs w = prrlu_ws_split(J.ws, J.n, J.nblk);
@@ -545,18 +542,19 @@ __device__ __forceinline__ void prrlu_mw_init_body(const PrrluJob &J) {
     w.ctl->idx = 0;
     w.ctl->piv = 0.0;
     w.ctl->tol2 = 0.0;
-    *w.ticket = 0u;
     J.info[0] = -1.0;  // not finished: the host launches further steps
 }
 
-// Workgroup b owns a stripe of J.rows = RS * kMwK rows; thread (tr, tc) holds the kMwTW
-// columns [8 tc, 8 tc + 8) of rows r0 + tr + k RS, k < kMwK, with RS = 256 / ceil(n / 8).
-__device__ __forceinline__ void prrlu_mw_step_body(const PrrluJob &J, int t) {
+// Step t, part 1 (all workgroups of the job): workgroup b owns a stripe of J.rows = RS * kMwK
+// rows; thread (tr, tc) holds the kMwTW columns [8 tc, 8 tc + 8) of rows r0 + tr + k RS, k < kMwK,
+// with RS = 256 / ceil(n / 8). It eliminates pivot t - 1 (chosen by part 2 of the previous step)
+// from its rows, writes column t - 1 of L for them, and stores the stripe's largest magnitude,
+// its index and the squared sum as the workgroup's partial. The kernel boundary orders the
+// parts, so no fence or atomic is needed.
+__device__ __forceinline__ void prrlu_mw_update_body(const PrrluJob &J, int t) {
     __shared__ double lc[kMwThreads * kMwK];
     __shared__ double wmax[kMwThreads / kWave], wsum[kMwThreads / kWave];
     __shared__ long long widx[kMwThreads / kWave];
-    __shared__ int s_last, s_stop;
-    __shared__ long long s_idx;
     const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave;
     const int m = J.m, n = J.n, rmax = J.rmax;
     const PrrluWs w = prrlu_ws_split(J.ws, n, J.nblk);
@@ -574,11 +572,9 @@ __device__ __forceinline__ void prrlu_mw_step_body(const PrrluJob &J, int t) {
 #pragma unroll
         for (int j = 0; j < kMwTW; ++j) a[k][j] = (rv && c0 + j < n) ? A[(long long)row * n + c0 + j] : 0.0;
     }
-    int pi = -1, pj = -1;
     if (t > 0) {
         const long long pidx = w.ctl->idx;
-        pi = (int)(pidx / n);
-        pj = (int)(pidx % n);
+        const int pi = (int)(pidx / n), pj = (int)(pidx % n);
         const double inv = 1.0 / w.ctl->piv;
         if (active && pj >= c0 && pj < c0 + kMwTW) {  // the pivot column's owners publish it
 #pragma unroll
@@ -646,19 +642,25 @@ __device__ __forceinline__ void prrlu_mw_step_body(const PrrluJob &J, int t) {
         long long bi = widx[0];
         for (int k = 0; k < kMwThreads / kWave; ++k) {
             bs += wsum[k];
-            if (wmax[k] > bm || (wmax[k] == bm && widx[k] < bi)) { bm = wmax[k]; bi = widx[k]; }
+            amax_merge(bm, bi, wmax[k], widx[k]);
         }
         w.pmax[blockIdx.x] = bm;
         w.psum[blockIdx.x] = bs;
         w.pidx[blockIdx.x] = bi;
-        __threadfence();  // release: this workgroup's rows and partials before its ticket
-        const unsigned prev = atomicAdd(w.ticket, 1u);
-        s_last = (prev == (unsigned)J.nblk - 1u);
     }
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();  // acquire: every workgroup's rows and partials
-    // combine the partials in workgroup order (the result does not depend on arrival order)
+}
+
+// Step t, part 2 (one workgroup per job): combine the partials in workgroup order, take the
+// stop decision of the single-workgroup form and publish pivot t and its row.
+__device__ __forceinline__ void prrlu_mw_select_body(const PrrluJob &J, int t) {
+    __shared__ double wmax[kMwThreads / kWave], wsum[kMwThreads / kWave];
+    __shared__ long long widx[kMwThreads / kWave];
+    __shared__ int s_stop;
+    __shared__ long long s_idx;
+    const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave;
+    const int m = J.m, n = J.n, rmax = J.rmax;
+    const PrrluWs w = prrlu_ws_split(J.ws, n, J.nblk);
+    if (w.ctl->stop) return;
     double bm = -1.0, bs = 0.0;
     long long bi = 0x7fffffffffffffffLL;
     for (int b = tid; b < J.nblk; b += kMwThreads) {
@@ -666,7 +668,6 @@ __device__ __forceinline__ void prrlu_mw_step_body(const PrrluJob &J, int t) {
         bs += w.psum[b];
     }
     wave_amax_sum(bm, bi, bs);
-    __syncthreads();
     if (lane == 0) { wmax[wv] = bm; widx[wv] = bi; wsum[wv] = bs; }
     __syncthreads();
     if (tid == 0) {
@@ -674,7 +675,7 @@ __device__ __forceinline__ void prrlu_mw_step_body(const PrrluJob &J, int t) {
         long long gi = widx[0];
         for (int k = 0; k < kMwThreads / kWave; ++k) {
             gs += wsum[k];
-            if (wmax[k] > gm || (wmax[k] == gm && widx[k] < gi)) { gm = wmax[k]; gi = widx[k]; }
+            amax_merge(gm, gi, wmax[k], widx[k]);
         }
         if (t == 0) w.ctl->tol2 = J.rel_tol2 * gs;
         int stop = (t >= rmax) || (gm <= 0.0) || (gs <= w.ctl->tol2);
@@ -692,10 +693,9 @@ __device__ __forceinline__ void prrlu_mw_step_body(const PrrluJob &J, int t) {
             J.rowpiv[t] = (int)(gi / n);
             J.colpiv[t] = (int)(gi % n);
             w.ctl->idx = gi;
-            w.ctl->piv = A[gi];
+            w.ctl->piv = J.A[gi];
         }
         w.ctl->stop = stop;
-        *w.ticket = 0u;
         s_stop = stop;
         s_idx = gi;
     }
@@ -704,23 +704,31 @@ __device__ __forceinline__ void prrlu_mw_step_body(const PrrluJob &J, int t) {
         for (int i = tid; i < m; i += kMwThreads) J.L[(long long)i * rmax] = (i == 0) ? 1.0 : 0.0;
     if (!s_stop) {
         const long long prow = (s_idx / n) * (long long)n;
-        for (int jj = tid; jj < n; jj += kMwThreads) w.rowbuf[jj] = A[prow + jj];
+        for (int jj = tid; jj < n; jj += kMwThreads) w.rowbuf[jj] = J.A[prow + jj];
     }
 }
 
 __global__ void k_prrlu_mw_init(PrrluJob J) { prrlu_mw_init_body(J); }
 
-__global__ __launch_bounds__(kMwThreads) void k_prrlu_mw_step(PrrluJob J, int t) { prrlu_mw_step_body(J, t); }
+__global__ __launch_bounds__(kMwThreads) void k_prrlu_mw_update(PrrluJob J, int t) { prrlu_mw_update_body(J, t); }
+
+__global__ __launch_bounds__(kMwThreads) void k_prrlu_mw_select(PrrluJob J, int t) { prrlu_mw_select_body(J, t); }
 
 __global__ void k_prrlu_mw_init_batch(const PrrluJob *__restrict__ jobs, int njobs) {
     const int z = blockIdx.x * blockDim.x + threadIdx.x;
     if (z < njobs && jobs[z].mode == 1) prrlu_mw_init_body(jobs[z]);
 }
 
-__global__ __launch_bounds__(kMwThreads) void k_prrlu_mw_step_batch(const PrrluJob *__restrict__ jobs, int t) {
+__global__ __launch_bounds__(kMwThreads) void k_prrlu_mw_update_batch(const PrrluJob *__restrict__ jobs, int t) {
     const PrrluJob J = jobs[blockIdx.y];
     if (J.mode != 1 || (int)blockIdx.x >= J.nblk) return;
-    prrlu_mw_step_body(J, t);
+    prrlu_mw_update_body(J, t);
+}
+
+__global__ __launch_bounds__(kMwThreads) void k_prrlu_mw_select_batch(const PrrluJob *__restrict__ jobs, int t) {
+    const PrrluJob J = jobs[blockIdx.x];
+    if (J.mode != 1) return;
+    prrlu_mw_select_body(J, t);
 }
 
 // Single-workgroup form: the whole block stays in registers for all pivot steps. Thread tid
@@ -1290,7 +1298,10 @@ int prrlu(hipStream_t s, int m, int n, double *A, int rmax, double rel_tol2, int
     }
     if (t_begin == 0) k_prrlu_mw_init<<<1, 1, 0, s>>>(j);
     const int last = std::min(t_end, rmax);
-    for (int t = t_begin; t <= last; ++t) k_prrlu_mw_step<<<j.nblk, kMwThreads, 0, s>>>(j, t);
+    for (int t = t_begin; t <= last; ++t) {
+        k_prrlu_mw_update<<<j.nblk, kMwThreads, 0, s>>>(j, t);
+        k_prrlu_mw_select<<<1, kMwThreads, 0, s>>>(j, t);
+    }
     WTT_HIP(hipGetLastError());
     return last + 1;
 }
@@ -1353,8 +1364,10 @@ void prrlu_batch(hipStream_t s, int njobs, const PrrluJob *host_jobs, const Prrl
                               nullptr, nullptr);
     if (nmw) {
         if (t_begin == 0) k_prrlu_mw_init_batch<<<cdiv(njobs, 64), 64, 0, s>>>(dev_jobs, njobs);
-        for (int t = t_begin; t <= t_end; ++t)
-            k_prrlu_mw_step_batch<<<dim3(maxblk, njobs), kMwThreads, 0, s>>>(dev_jobs, t);
+        for (int t = t_begin; t <= t_end; ++t) {
+            k_prrlu_mw_update_batch<<<dim3(maxblk, njobs), kMwThreads, 0, s>>>(dev_jobs, t);
+            k_prrlu_mw_select_batch<<<njobs, kMwThreads, 0, s>>>(dev_jobs, t);
+        }
     }
     WTT_HIP(hipGetLastError());
 }
