@@ -448,6 +448,111 @@ __global__ void k_sample_star(FiberGeom g, CoreSet cs, CoreSet un, int use_un, i
     ust[e] = tt_point<ND>(cs, c, cell);
 }
 
+// 3D star samples with one 256-thread workgroup per probe point. For point (i0, i1, i2) and a
+// component with cores G0 (N0 x R1), G1 (R1 x N1 x R2), G2 (R2 x N2): the line along mode 0 needs
+// the vector w = G1(:, i1, :) G2(:, i2) once and a dot product per cell; the line along mode 2
+// needs v = G0(i0, :) G1(:, i1, :) once and a dot product per cell; the cells along mode 1 each
+// need one such matrix-vector product. 9 R1 R2 multiply-adds per point and component instead
+// of 22; G1 rows are read contiguously by consecutive threads.
+__device__ inline double block_sum256(double v, double *red) {
+    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    __syncthreads();
+    if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = v;
+    __syncthreads();
+    return (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+__device__ inline double wave_sum_f(double v) {
+    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+__global__ __launch_bounds__(256) void k_sample_star3(FiberGeom g, CoreSet cs, CoreSet un, int use_un, int npts,
+                                                      const int *__restrict__ pts, double *__restrict__ ust) {
+    constexpr int NC = 5, SL = 22;
+    extern __shared__ double sm[];
+    __shared__ double red[4];
+    __shared__ double vals[SL];
+    const int pt = blockIdx.x, tid = threadIdx.x, lane = tid % kWave, w = tid / kWave;
+    if (pt >= npts) return;
+    const int i0 = pts[pt * 3], i1 = pts[pt * 3 + 1], i2 = pts[pt * 3 + 2];
+    const int N0 = g.n[0], N1 = g.n[1], N2 = g.n[2];
+    for (int c = 0; c < NC; ++c) {
+        const int R1 = cs.R[1], R2 = cs.R[2];
+        double *g0row = sm, *w1 = sm + R1, *v = sm + 2 * R1, *g2col = sm + 2 * R1 + R2;
+        const double *G0 = cs.c[0] + c * cs.cstride[0];
+        const double *G1 = cs.c[1] + c * cs.cstride[1];
+        const double *G2 = cs.c[2] + c * cs.cstride[2];
+        for (int al = tid; al < R1; al += 256) g0row[al] = G0[(long long)i0 * R1 + al];
+        for (int be = tid; be < R2; be += 256) g2col[be] = G2[(long long)be * N2 + i2];
+        __syncthreads();
+        // v = G0(i0, :) G1(:, i1, :)
+        for (int be = tid; be < R2; be += 256) {
+            double acc = 0.0;
+            for (int al = 0; al < R1; ++al) acc = fma(g0row[al], G1[((long long)al * N1 + i1) * R2 + be], acc);
+            v[be] = acc;
+        }
+        // w = G1(:, i1, :) G2(:, i2)
+        for (int al = w; al < R1; al += 4) {
+            const double *row = G1 + ((long long)al * N1 + i1) * R2;
+            double p = 0.0;
+            for (int be = lane; be < R2; be += kWave) p = fma(row[be], g2col[be], p);
+            p = wave_sum_f(p);
+            if (lane == 0) w1[al] = p;
+        }
+        __syncthreads();
+        // lines along modes 0 and 2: 14 dot products over the four waves
+        for (int q = w; q < 14; q += 4) {
+            const int sft = q % 7 - 3;
+            double p = 0.0;
+            if (q < 7) {
+                const double *row = G0 + (long long)ghost_map(i0 + sft, N0, g.bc[0]) * R1;
+                for (int al = lane; al < R1; al += kWave) p = fma(row[al], w1[al], p);
+            } else {
+                const int j2 = ghost_map(i2 + sft, N2, g.bc[2]);
+                for (int be = lane; be < R2; be += kWave) p = fma(v[be], G2[(long long)be * N2 + j2], p);
+            }
+            p = wave_sum_f(p);
+            if (lane == 0) vals[q < 7 ? q : 14 + (q - 7)] = p;
+        }
+        // line along mode 1
+        for (int sft = -3; sft <= 3; ++sft) {
+            double part = 0.0;
+            if (sft == 0) {
+                for (int be = tid; be < R2; be += 256) part = fma(v[be], g2col[be], part);
+            } else {
+                const int j1 = ghost_map(i1 + sft, N1, g.bc[1]);
+                for (int be = tid; be < R2; be += 256) {
+                    double acc = 0.0;
+                    for (int al = 0; al < R1; ++al) acc = fma(g0row[al], G1[((long long)al * N1 + j1) * R2 + be], acc);
+                    part = fma(acc, g2col[be], part);
+                }
+            }
+            part = block_sum256(part, red);
+            if (tid == 0) vals[7 + sft + 3] = part;
+        }
+        // U^n at the point itself
+        double un_part = 0.0;
+        if (use_un) {
+            const int S1 = un.R[1], S2 = un.R[2];
+            const double *H0 = un.c[0] + c * un.cstride[0];
+            const double *H1 = un.c[1] + c * un.cstride[1];
+            const double *H2 = un.c[2] + c * un.cstride[2];
+            for (int be = tid; be < S2; be += 256) {
+                double acc = 0.0;
+                for (int al = 0; al < S1; ++al)
+                    acc = fma(H0[(long long)i0 * S1 + al], H1[((long long)al * N1 + i1) * S2 + be], acc);
+                un_part = fma(acc, H2[(long long)be * N2 + i2], un_part);
+            }
+        }
+        un_part = block_sum256(un_part, red);
+        if (tid == 0) vals[21] = use_un ? un_part : 0.0;
+        __syncthreads();
+        for (int q = tid; q < SL; q += 256) ust[((long long)pt * SL + q) * NC + c] = vals[q];
+        __syncthreads();
+    }
+}
+
 template <int ND>
 __global__ __launch_bounds__(256) void k_sample_stage(FiberGeom g, CoreSet fs, int npts, const int *__restrict__ pts,
                                                       const double *__restrict__ ust, double wn, double wx, double wl,
@@ -625,7 +730,11 @@ void sample_stage(hipStream_t s, const FiberGeom &g, const double *const *xcores
         k_sample_star<2><<<cdiv(n1, 256), 256, 0, s>>>(g, xs, us, ncores != nullptr, npts, pts, ust);
         k_sample_stage<2><<<cdiv(npts, 256), 256, 0, s>>>(g, fs, npts, pts, ust, wn, wx, wl, hs, acc, flags);
     } else {
-        k_sample_star<3><<<cdiv(n1, 256), 256, 0, s>>>(g, xs, us, ncores != nullptr, npts, pts, ust);
+        const size_t lds = sizeof(double) * 2 * ((size_t)xs.R[1] + xs.R[2]);
+        if (lds <= 48 * 1024)
+            k_sample_star3<<<npts, 256, lds, s>>>(g, xs, us, ncores != nullptr, npts, pts, ust);
+        else
+            k_sample_star<3><<<cdiv(n1, 256), 256, 0, s>>>(g, xs, us, ncores != nullptr, npts, pts, ust);
         k_sample_stage<3><<<cdiv(npts, 256), 256, 0, s>>>(g, fs, npts, pts, ust, wn, wx, wl, hs, acc, flags);
     }
     WTT_HIP(hipGetLastError());

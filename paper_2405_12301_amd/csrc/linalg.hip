@@ -504,6 +504,28 @@ __global__ __launch_bounds__(1024) void k_jacobi_global(int n, const double *__r
                   US ? US + (long long)z * n * n : nullptr);
 }
 
+// A in LDS, V and the norms in global scratch: for n whose A and V together exceed LDS.
+__global__ __launch_bounds__(1024) void k_jacobi_hybrid(int n, const double *__restrict__ Ain,
+                                                        double *__restrict__ sigma, double *__restrict__ Vout,
+                                                        double *__restrict__ US, double *__restrict__ scratch,
+                                                        const double *__restrict__ delta) {
+    extern __shared__ double A[];
+    __shared__ int nrot;
+    const int z = blockIdx.x, tid = threadIdx.x;
+    double *V = scratch + (long long)z * (2 * (long long)n * n + n) + (long long)n * n;
+    double *sig_tmp = V + (long long)n * n;
+    const double *Az = Ain + (long long)z * n * n;
+    for (long long e = tid; e < (long long)n * n; e += blockDim.x) {
+        int i = (int)(e / n), j = (int)(e % n);
+        A[(long long)j * n + i] = Az[e];
+        V[(long long)j * n + i] = (i == j) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    jacobi_sweeps(n, A, V, &nrot, sig_tmp, jacobi_eta(delta, z, n));
+    jacobi_finish(n, A, V, sig_tmp, sigma + (long long)z * n, Vout + (long long)z * n * n,
+                  US ? US + (long long)z * n * n : nullptr);
+}
+
 // ------------------------------------------------------------------- prrLU (pivots)
 // Multi-workgroup variant for blocks too large for one workgroup's registers: two launches per
 // pivot step t. In the first, each workgroup owns a run of whole rows, applies the elimination
@@ -915,6 +937,26 @@ __global__ void k_interp(int m, int r, const double *__restrict__ L, int ldl, co
     }
 }
 
+// The same with L_I = L[rowpiv, :r] staged in LDS by every workgroup (LI[s * r + t]).
+__global__ __launch_bounds__(256) void k_interp_lds(int m, int r, const double *__restrict__ L, int ldl,
+                                                    const int *__restrict__ rowpiv, double *__restrict__ X) {
+    extern __shared__ double LI[];
+    for (int e = threadIdx.x; e < r * r; e += blockDim.x) {
+        const int sr = e / r, t = e % r;
+        LI[e] = L[(long long)rowpiv[sr] * ldl + t];
+    }
+    __syncthreads();
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    double *x = X + (long long)i * r;
+    const double *l = L + (long long)i * ldl;
+    for (int t = r - 1; t >= 0; --t) {
+        double acc = l[t];
+        for (int sr = t + 1; sr < r; ++sr) acc -= x[sr] * LI[sr * r + t];
+        x[t] = acc;
+    }
+}
+
 __global__ void k_interp_exact_rows(int r, const int *__restrict__ rowpiv, double *__restrict__ X) {
     int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= r * r) return;
@@ -1260,8 +1302,11 @@ void jacobi_svd(hipStream_t s, int n, int batch, const double *A, double *sigma,
                 double *US, const double *delta) {
     // static LDS of the kernel: the column-norm buffer (512 doubles) and a counter
     size_t lds = sizeof(double) * 2 * (size_t)n * n;
+    const size_t lds_a = sizeof(double) * (size_t)n * n;
     if (n <= 512 && lds + 512 * sizeof(double) + 64 <= (size_t)lds_limit_bytes())
         k_jacobi_lds<<<batch, 1024, lds, s>>>(n, A, sigma, V, US, delta);
+    else if (lds_a + 64 <= (size_t)lds_limit_bytes())
+        k_jacobi_hybrid<<<batch, 1024, lds_a, s>>>(n, A, sigma, V, US, scratch, delta);
     else
         k_jacobi_global<<<batch, 1024, 0, s>>>(n, A, sigma, V, US, scratch, delta);
     WTT_HIP(hipGetLastError());
@@ -1307,7 +1352,11 @@ int prrlu(hipStream_t s, int m, int n, double *A, int rmax, double rel_tol2, int
 }
 
 void interp_solve(hipStream_t s, int m, int r, const double *L, int ldl, const int *rowpiv, double *X) {
-    k_interp<<<cdiv(m, 256), 256, 0, s>>>(m, r, L, ldl, rowpiv, X);
+    const size_t lds = sizeof(double) * (size_t)r * r;
+    if (r > 0 && lds <= (size_t)lds_limit_bytes() - 1024)
+        k_interp_lds<<<cdiv(m, 256), 256, lds, s>>>(m, r, L, ldl, rowpiv, X);
+    else
+        k_interp<<<cdiv(m, 256), 256, 0, s>>>(m, r, L, ldl, rowpiv, X);
     k_interp_exact_rows<<<cdiv((long long)r * r, 256), 256, 0, s>>>(r, rowpiv, X);
     WTT_HIP(hipGetLastError());
 }
