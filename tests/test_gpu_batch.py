@@ -156,3 +156,32 @@ def test_gemm_autotuner_changes_speed_not_results(W):
         assert np.array_equal(outs[0], outs[1])
     finally:
         W.wenott_gemm_autotune(1)
+
+
+def test_blast_batch_full_size_two_states_vs_oracle(W):
+    """The batched workload at its full size and launch configuration (32 blasts, grids from
+    {64..256}^3, dynamic eps from 1e-6, one lock-step batched step); the oracle steps two of the
+    states (the smallest and the largest grid) on their full grids with the alphas the batch
+    used, and the per-step error is within 10 eps_TT."""
+    _say("case: blast batch, 32 states at full size, one batched step")
+    flows = [workloads.config4_blast_3d(seed=i) for i in range(32)]
+    solvers = [W.Solver(f, W.default_opts(eps_mode=1, eps0=f.eps0)) for f in flows]
+    try:
+        cells = [int(np.prod(f.n)) for f in flows]
+        pick = [int(np.argmin(cells)), int(np.argmax(cells))]
+        u0 = {i: solvers[i].dense() for i in pick}
+        dts = [f.cfl * min(f.h) / s.max_wavespeed() for f, s in zip(flows, solvers)]
+        W.wenott_batch_rk3_step([s.ctx for s in solvers], dts)
+        for i in pick:
+            info = solvers[i].info()
+            P = oracle_problem(flows[i])
+            u = u0[i]
+            P.ssprk3(u, dts[i], alphas=[info.alpha[j] for j in range(3)])
+            err = rel_err(solvers[i].dense(), u)
+            _say(f"  state {i} n={flows[i].n} ranks={list(info.ranks)[:4]} eps={info.eps:.2e} err={err:.3e}")
+            assert err <= 10 * info.eps, (i, err, info.eps)
+        for s in solvers:
+            assert all(np.isfinite(list(s.info().ranks)[:4]))
+    finally:
+        for s in solvers:
+            s.close()
