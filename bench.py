@@ -221,8 +221,10 @@ def main():
               f"dynamic eps_TT from 1e-8, CFL 0.5")
     elif args.workload == "wave3d":
         flow = workloads.config3_wave_3d(args.n, seed=args.seed)
-        opts = W.default_opts(eps_mode=0, eps0=flow.eps0, precision=args.precision)
-        wl = f"3D smooth density wave {args.n}^3 with 8 Fourier modes, periodic, eps_TT 1e-6 fixed, CFL 0.5"
+        eps_w = 1e-10 if args.precision == 0 else 1e-6
+        opts = W.default_opts(eps_mode=0, eps0=eps_w, precision=args.precision)
+        wl = (f"3D smooth density wave {args.n}^3 with 8 Fourier modes, periodic, eps_TT {eps_w:g} fixed, CFL 0.5; "
+              f"L1 error of rho against the exact (translated) solution reported for TT and dense")
     else:
         flow = workloads.sod_1d_like(3, args.n)
         opts = W.default_opts(eps_mode=0, eps0=1e-6, precision=args.precision)
@@ -260,8 +262,14 @@ def main():
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     info = solver.info()
-    ranks = list(info.ranks)[:3]
+    ranks = list(info.ranks)[:flow.ndim + 1]
     eps_now = info.eps
+    l1 = None
+    if flow.exact_rho is not None:
+        import numpy as np
+        rho_tt = solver.dense(device=True)[0].cpu().numpy()
+        l1 = {"tt": float(np.mean(np.abs(rho_tt - flow.exact_rho(t_sim)))), "t_tt": t_sim}
+        del rho_tt
     solver.close()
 
     roofline = roofline_of(cls_ms, cls_fl, cls_by, cls_n, args.steps,
@@ -276,17 +284,23 @@ def main():
         u0 = s2.dense(device=True)
         s2.close()
         ctx = W.wenott_dense_init(flow.n, flow.lo, flow.hi, flow.gamma, flow.bc)
+        t_dense = 0.0
         for _ in range(args.warmup):
             a = W.wenott_dense_max_wavespeed(ctx, u0)
             W.wenott_dense_rk3_step(ctx, u0, flow.cfl * h / a)
+            t_dense += flow.cfl * h / a
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         for _ in range(args.steps):
             a = W.wenott_dense_max_wavespeed(ctx, u0)
             W.wenott_dense_rk3_step(ctx, u0, flow.cfl * h / a)
+            t_dense += flow.cfl * h / a
         torch.cuda.synchronize()
         el2 = time.perf_counter() - t1
         W.wenott_dense_destroy(ctx)
+        if l1 is not None:
+            l1["dense"] = float(np.mean(np.abs(u0[0].cpu().numpy() - flow.exact_rho(t_dense))))
+            l1["t_dense"] = t_dense
         dense = {"value": cells * args.steps / el2, "unit": "cell-updates/s", "ms_per_step": el2 * 1e3 / args.steps,
                  "note": "hand-written dense FP64 WENO5-JS + LF + SSP-RK3 on the same GPU, same steps"}
 
@@ -308,6 +322,8 @@ def main():
         "roofline": roofline,
         "dense_gpu_weno5": dense,
     }
+    if l1 is not None:
+        out["l1_error_vs_exact"] = l1
     if not args.no_cpu_baseline and args.workload == "quadrants2d":
         out["cpu_baseline"] = cpu_baseline(flow, args.cpu_seconds)
     print(json.dumps(out))

@@ -33,6 +33,8 @@ class Flow:
     eps_mode: int = 0  # 0 fixed eps, 1 dynamic
     eps0: float = 1e-10
     note: str = ""
+    # density of the exact solution on the grid at time t, where one is known in closed form
+    exact_rho: object = None
 
     @property
     def ncomp(self):
@@ -179,19 +181,31 @@ def config3_wave_3d(n: int = 256, seed: int = 0, modes: int = 8, amp: float = 1e
     h = 2.0 / n
     xs = [(np.arange(n) + 0.5) * h for _ in range(3)]
     terms = [_const_term(xs, 1.0), _sin_plane_term(xs, (math.pi,) * 3, 0.0, 0.2)]
+    waves = [((math.pi,) * 3, 0.0, 0.2)]
     for _ in range(modes):
         while True:
             k = rng.integers(-3, 4, size=3)
             if np.any(k != 0):
                 break
         phi = rng.uniform(0.0, 2.0 * math.pi)
-        terms.append(_sin_plane_term(xs, tuple(math.pi * float(kk) for kk in k), phi, amp))
+        kv = tuple(math.pi * float(kk) for kk in k)
+        terms.append(_sin_plane_term(xs, kv, phi, amp))
+        waves.append((kv, phi, amp))
+
+    def exact_rho(t):
+        # u = v = w = 1 and p = 1 everywhere: every conserved variable is carried along (1, 1, 1)
+        r = np.ones((n, n, n))
+        for kv, phi, a in waves:
+            ph = [kv[d] * (xs[d] - t) for d in range(3)]
+            r += a * np.sin(ph[0][:, None, None] + ph[1][None, :, None] + ph[2][None, None, :] + phi)
+        return r
     rho = _concat_terms(terms)
     e_terms = [_const_term(xs, 1.0 / (g - 1.0) + 1.5)] + [_scale(t, 1.5) for t in terms[1:]]
     ene = _concat_terms(e_terms)
     return Flow("wave_3d", 3, (n, n, n), (0.0,) * 3, (2.0,) * 3, (PERIODIC,) * 3, g,
                 [rho, [c.copy() for c in rho], [c.copy() for c in rho], [c.copy() for c in rho], ene],
-                t_end=0.1, cfl=0.5, eps_mode=0, eps0=1e-6, note=f"seed {seed}, {modes} modes")
+                t_end=0.1, cfl=0.5, eps_mode=0, eps0=1e-6, note=f"seed {seed}, {modes} modes",
+                exact_rho=exact_rho)
 
 
 def tt_svd_input(x: np.ndarray, eps: float, rank_cap: int | None = None):
