@@ -201,8 +201,16 @@ __global__ __launch_bounds__(256) void k_dense_eval(int mode, int ncomp, long lo
     double speed = 0.0;
     bool ok = true;
     if (e < ncell) {
-        const long long row = e / nlast;
-        const int j = (int)(e % nlast);
+        // (row, j) of this cell without a 64-bit division per thread: the block's first cell is
+        // split once (uniform values), the thread's offset by at most one 32-bit division
+        const long long e0 = (long long)blockIdx.x * blockDim.x;
+        long long row = e0 / nlast;
+        int j = (int)(e0 - row * nlast) + (int)threadIdx.x;
+        if (j >= nlast) {
+            const int q = (int)((unsigned)j / (unsigned)nlast);
+            row += q;
+            j -= q * nlast;
+        }
         double qv[NC];
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
@@ -730,8 +738,10 @@ void sample_stage(hipStream_t s, const FiberGeom &g, const double *const *xcores
         k_sample_star<2><<<cdiv(n1, 256), 256, 0, s>>>(g, xs, us, ncores != nullptr, npts, pts, ust);
         k_sample_stage<2><<<cdiv(npts, 256), 256, 0, s>>>(g, fs, npts, pts, ust, wn, wx, wl, hs, acc, flags);
     } else {
+        // the point-per-workgroup form pays off once a cell costs more than a few hundred
+        // multiply-adds (R1 R2); below that one thread per sample is faster
         const size_t lds = sizeof(double) * 2 * ((size_t)xs.R[1] + xs.R[2]);
-        if (lds <= 48 * 1024)
+        if (lds <= 48 * 1024 && (long long)xs.R[1] * xs.R[2] > 512)
             k_sample_star3<<<npts, 256, lds, s>>>(g, xs, us, ncores != nullptr, npts, pts, ust);
         else
             k_sample_star<3><<<cdiv(n1, 256), 256, 0, s>>>(g, xs, us, ncores != nullptr, npts, pts, ust);
