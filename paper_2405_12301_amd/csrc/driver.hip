@@ -173,7 +173,10 @@ struct wenott_ctx {
     std::vector<const void *> view_ptrs;
     Scratch sc;
     Ring ring;
-    int *d_flags = nullptr;
+    int *d_flags = nullptr;  // first word of d_status
+    // Status block: [0] flag word, [1..4] alpha slots, [8..) residual partials; copied to the
+    // pinned mirror h_status in one transfer per readback.
+    double *d_status = nullptr, *h_status = nullptr;
     int *h_pinned_int = nullptr;
     double *h_pinned_dbl = nullptr;
     std::vector<ISet> warm[kMaxDim + 1];  // per flux direction, and [kMaxDim] for the stage value
@@ -222,6 +225,16 @@ void raise_flags(wenott_ctx *c, int f) {
         if (f & kFlagNaN) throw StatusError(WENOTT_ENAN, "NaN or Inf in a flux evaluation");
         throw StatusError(WENOTT_ENONPHYS, "rho <= 0 or p <= 0 at an evaluated point");
     }
+}
+
+constexpr int kStatusAlpha = 1, kStatusAcc = 8, kMaxResidualBlocks = 64;
+constexpr int kStatusDoubles = kStatusAcc + 2 * kMaxResidualBlocks;
+
+int status_flags(const wenott_ctx *c) { return *(const int *)c->h_status; }
+
+// Copy the first `doubles` entries of the status block to its pinned mirror.
+void status_readback(wenott_ctx *c, int doubles) {
+    WTT_HIP(hipMemcpyAsync(c->h_status, c->d_status, sizeof(double) * doubles, hipMemcpyDeviceToHost, c->s));
 }
 
 void check_flags(wenott_ctx *c) {
@@ -285,13 +298,13 @@ const double *left_part(wenott_ctx *c, const TT &U, long long *stride) {
     return Lm;
 }
 
-// Pinned host slots read after a later synchronisation: stage alphas and their flag words,
-// and the component norms of the last rounding.
-constexpr int kPinAlpha = 4064, kPinNorms = 4080;
+// Pinned host slots read after a later synchronisation: the component norms of the last rounding.
+constexpr int kPinNorms = 4080;
 
-// Enqueue the exact alpha of U into dst (device), and copies of it and of the flag word into
-// the pinned slots kPinAlpha + slot.
-void exact_alpha_launch(wenott_ctx *c, const TT &U, double *dst, int slot = 0) {
+// Enqueue the exact alpha of U into alpha slot `slot` of the status block and a copy of the
+// block head (flag word and alpha slots) to its pinned mirror. Returns the device address.
+double *exact_alpha_launch(wenott_ctx *c, const TT &U, int slot) {
+    double *dst = c->d_status + kStatusAlpha + slot;
     long long lms = 0;
     const double *Lm = left_part(c, U, &lms);
     long long nrows = 1;
@@ -303,15 +316,17 @@ void exact_alpha_launch(wenott_ctx *c, const TT &U, double *dst, int slot = 0) {
     dense_eval(c->s, 1, U.d, U.nc, nrows, U.R[U.d - 1], nlast, Lm, lms, U.core[U.d - 1], U.cstride(U.d - 1),
                c->gamma, nullptr, part, nblocks, c->d_flags);
     reduce_max_dev(c->s, part, nblocks, dst);
-    WTT_HIP(hipMemcpyAsync(c->h_pinned_dbl + kPinAlpha + slot, dst, sizeof(double), hipMemcpyDeviceToHost, c->s));
-    WTT_HIP(hipMemcpyAsync(c->h_pinned_int + kPinAlpha + slot, c->d_flags, sizeof(int), hipMemcpyDeviceToHost, c->s));
+    status_readback(c, kStatusAlpha + 4);
+    return dst;
 }
 
+double status_alpha(const wenott_ctx *c, int slot) { return c->h_status[kStatusAlpha + slot]; }
+
 double exact_alpha(wenott_ctx *c, const TT &U) {
-    exact_alpha_launch(c, U, c->sc.get<double>(S_DSCAL, 4));
+    exact_alpha_launch(c, U, 3);
     WTT_HIP(hipStreamSynchronize(c->s));
-    raise_flags(c, c->h_pinned_int[kPinAlpha]);
-    return c->h_pinned_dbl[kPinAlpha];
+    raise_flags(c, status_flags(c));
+    return status_alpha(c, 3);
 }
 
 void to_dense_dev(wenott_ctx *c, const TT &U, double *out) {
@@ -418,27 +433,42 @@ int pivot_guess(const wenott_ctx *c, int hist_slot, int n, int rmax) {
     return std::max(1, std::min(g, rmax));
 }
 
+// Pivot indices (2 rmax + 2 ints) and the {rank, residual} pair share one device buffer, so
+// that one transfer brings both back: byte offset of the pair.
+size_t pivot_info_offset(int rmax) { return ((2 * (size_t)rmax + 2) * sizeof(int) + 7) / 8 * 8; }
+
+int *pivot_buffer(wenott_ctx *c, int rmax, double **info) {
+    const size_t off = pivot_info_offset(rmax);
+    int *piv = c->sc.get<int>(S_PIV, off / sizeof(int) + 4);
+    *info = (double *)((char *)piv + off);
+    return piv;
+}
+
+double pinned_pivot_info(const wenott_ctx *c, int rmax, int which) {
+    return ((const double *)((const char *)c->h_pinned_int + pivot_info_offset(rmax)))[which];
+}
+
 PivotResult pivots(wenott_ctx *c, double *B, int m, int n, double rel_tol2, double **Lout, int hist_slot) {
     int rmax = std::min(std::min(c->o.rank_cap, kMaxRankLds), std::min(m, n));
-    int *piv = c->sc.get<int>(S_PIV, 2 * (size_t)rmax + 2);
+    double *info = nullptr;
+    int *piv = pivot_buffer(c, rmax, &info);
     double *L = c->sc.get<double>(S_L, (size_t)m * rmax);
-    double *info = c->sc.get<double>(S_INFO, 2);
     double *ws = c->sc.get<double>(S_ROWBUF, prrlu_ws_doubles(m, n));
     ev_record(c, KC_PIVOT);
     int next = prrlu(c->s, m, n, B, rmax, rel_tol2, piv, piv + rmax, L, info, ws, 0, pivot_guess(c, hist_slot, n, rmax));
     ev_record(c, KC_PIVOT);
     for (;;) {
-        WTT_HIP(hipMemcpyAsync(c->h_pinned_dbl, info, 2 * sizeof(double), hipMemcpyDeviceToHost, c->s));
-        WTT_HIP(hipMemcpyAsync(c->h_pinned_int, piv, 2 * rmax * sizeof(int), hipMemcpyDeviceToHost, c->s));
+        WTT_HIP(hipMemcpyAsync(c->h_pinned_int, piv, pivot_info_offset(rmax) + 2 * sizeof(double),
+                               hipMemcpyDeviceToHost, c->s));
         WTT_HIP(hipStreamSynchronize(c->s));
-        if (c->h_pinned_dbl[0] >= 0.0) break;
+        if (pinned_pivot_info(c, rmax, 0) >= 0.0) break;
         WTT_REQUIRE(next <= rmax, WENOTT_EHIP, "pivot search did not stop");
         ev_record(c, KC_PIVOT);
         next = prrlu(c->s, m, n, B, rmax, rel_tol2, piv, piv + rmax, L, info, ws, next, next + std::max(8, next / 2));
         ev_record(c, KC_PIVOT);
     }
     PivotResult r;
-    r.rank = (int)c->h_pinned_dbl[0];
+    r.rank = (int)pinned_pivot_info(c, rmax, 0);
     if (hist_slot >= 0) c->piv_hist[hist_slot] = r.rank;
     r.cols.assign(c->h_pinned_int + rmax, c->h_pinned_int + rmax + r.rank);
     c->info.pivots_total += r.rank;
@@ -464,18 +494,18 @@ double sampled_residual(wenott_ctx *c, const TT &U, const FluxTT &F, int dir, do
     const int *dp = c->ring.put(pts.data(), pts.size());
     double *ust = c->sc.get<double>(S_UST, (size_t)npts * 6 * U.nc);
     int nb = (npts + 255) / 256;
-    double *acc = c->sc.get<double>(S_ACC, 2 * (size_t)nb);
+    WTT_REQUIRE(nb <= kMaxResidualBlocks, WENOTT_EINVAL, "too many probe points");
+    double *acc = c->d_status + kStatusAcc;
     int ranks[kMaxDim + 1], franks[kMaxDim + 1];
     for (int j = 0; j <= d; ++j) { ranks[j] = U.R[j]; franks[j] = F.R[j]; }
     const double *uc[kMaxDim], *fc[kMaxDim];
     for (int j = 0; j < d; ++j) { uc[j] = U.core[j]; fc[j] = F.core[j]; }
     sample_residual(c->s, g, uc, ranks, npts, dp, fc, franks, ust, acc, c->d_flags);
     WTT_REQUIRE(2 * (size_t)nb <= 3000, WENOTT_EINVAL, "too many probe points");
-    WTT_HIP(hipMemcpyAsync(c->h_pinned_dbl + 128, acc, 2 * nb * sizeof(double), hipMemcpyDeviceToHost, c->s));
-    WTT_HIP(hipMemcpyAsync(c->h_pinned_int + 128, c->d_flags, sizeof(int), hipMemcpyDeviceToHost, c->s));
+    status_readback(c, kStatusAcc + 2 * nb);
     WTT_HIP(hipStreamSynchronize(c->s));
-    raise_flags(c, c->h_pinned_int[128]);
-    const double *h = c->h_pinned_dbl + 128;
+    raise_flags(c, status_flags(c));
+    const double *h = c->h_status + kStatusAcc;
     double d2 = 0.0, n2 = 0.0;
     for (int b = 0; b < nb; ++b) { d2 += h[2 * b]; n2 += h[2 * b + 1]; }
     return n2 > 0.0 ? std::sqrt(d2 / n2) : std::sqrt(d2);
@@ -893,7 +923,8 @@ int sampled_stage_residual_launch(wenott_ctx *c, const TT &X, const TT *Un, Stag
     const int SL = 7 * d + 1;
     double *ust = c->sc.get<double>(S_UST, (size_t)npts * SL * X.nc);
     int nb = (npts + 255) / 256;
-    double *acc = c->sc.get<double>(S_ACC, 2 * (size_t)nb);
+    WTT_REQUIRE(nb <= kMaxResidualBlocks, WENOTT_EINVAL, "too many probe points");
+    double *acc = c->d_status + kStatusAcc;
     int xr[kMaxDim + 1], nr[kMaxDim + 1], fr[kMaxDim + 1];
     const double *xc[kMaxDim], *ncs[kMaxDim], *fc[kMaxDim];
     for (int j = 0; j <= d; ++j) { xr[j] = X.R[j]; fr[j] = F.R[j]; nr[j] = Un ? Un->R[j] : 1; }
@@ -903,16 +934,14 @@ int sampled_stage_residual_launch(wenott_ctx *c, const TT &X, const TT *Un, Stag
     const bool use_un = Un && w.wn != 0.0;
     sample_stage(c->s, g, xc, xr, use_un ? ncs : nullptr, nr, npts, dp, fc, fr, use_un ? w.wn : 0.0, w.wx, w.wl,
                  inv_h, eps_w, ust, acc, c->d_flags);
-    WTT_REQUIRE(2 * (size_t)nb <= 3000, WENOTT_EINVAL, "too many probe points");
-    WTT_HIP(hipMemcpyAsync(c->h_pinned_dbl + 128, acc, 2 * nb * sizeof(double), hipMemcpyDeviceToHost, c->s));
-    WTT_HIP(hipMemcpyAsync(c->h_pinned_int + 128, c->d_flags, sizeof(int), hipMemcpyDeviceToHost, c->s));
+    status_readback(c, kStatusAcc + 2 * nb);
     return nb;
 }
 
 // Residual from the pinned copies of a launched sampled residual (after a synchronisation).
 double sampled_residual_finish(wenott_ctx *c, int nb) {
-    raise_flags(c, c->h_pinned_int[128]);
-    const double *h = c->h_pinned_dbl + 128;
+    raise_flags(c, status_flags(c));
+    const double *h = c->h_status + kStatusAcc;
     double d2 = 0.0, n2 = 0.0;
     for (int b = 0; b < nb; ++b) { d2 += h[2 * b]; n2 += h[2 * b + 1]; }
     return n2 > 0.0 ? std::sqrt(d2 / n2) : std::sqrt(d2);
@@ -1031,7 +1060,7 @@ int svd_ranks(wenott_ctx *c, int m, int n, const double *A, long long sz, long l
     *rk = c->sc.get<int>(S_RANKS, nc);
     trunc_ranks(c->s, n, nc, *sig, delta_abs, rel, rcap, *rk);
     WTT_HIP(hipMemcpyAsync(c->h_pinned_int, *rk, nc * sizeof(int), hipMemcpyDeviceToHost, c->s));
-    const bool tail = (size_t)nc * n <= 3000;
+    const bool tail = (size_t)nc * n <= 3000 && (c->o.use_proposal || c->logging);
     if (tail) WTT_HIP(hipMemcpyAsync(c->h_pinned_dbl + 1024, *sig, (size_t)nc * n * sizeof(double), hipMemcpyDeviceToHost, c->s));
     WTT_HIP(hipStreamSynchronize(c->s));
     int r = 1;
@@ -1209,9 +1238,8 @@ void batch_pivots(std::vector<BState *> &act, int dir, int k) {
     for (BState *b : act) {
         wenott_ctx *c = b->c;
         b->rmax = std::min(std::min(c->o.rank_cap, kMaxRankLds), std::min(b->m, b->n));
-        b->piv = c->sc.get<int>(S_PIV, 2 * (size_t)b->rmax + 2);
+        b->piv = pivot_buffer(c, b->rmax, &b->info);
         b->L = c->sc.get<double>(S_L, (size_t)b->m * b->rmax);
-        b->info = c->sc.get<double>(S_INFO, 2);
         PrrluJob j{};
         j.A = b->B; j.m = b->m; j.n = b->n; j.rmax = b->rmax; j.rel_tol2 = b->rel2;
         j.rowpiv = b->piv; j.colpiv = b->piv + b->rmax; j.L = b->L; j.info = b->info;
@@ -1232,15 +1260,14 @@ void batch_pivots(std::vector<BState *> &act, int dir, int k) {
         ev_record(c0, KC_PIVOT);
         for (size_t z : open) {
             BState *b = act[z];
-            WTT_HIP(hipMemcpyAsync(b->c->h_pinned_dbl, b->info, 2 * sizeof(double), hipMemcpyDeviceToHost, b->c->s));
-            WTT_HIP(hipMemcpyAsync(b->c->h_pinned_int, b->piv, 2 * b->rmax * sizeof(int), hipMemcpyDeviceToHost,
-                                   b->c->s));
+            WTT_HIP(hipMemcpyAsync(b->c->h_pinned_int, b->piv, pivot_info_offset(b->rmax) + 2 * sizeof(double),
+                                   hipMemcpyDeviceToHost, b->c->s));
         }
         WTT_HIP(hipStreamSynchronize(c0->s));
         std::vector<size_t> still;
         int rmax_open = 0;
         for (size_t z : open)
-            if (act[z]->c->h_pinned_dbl[0] < 0.0) {
+            if (pinned_pivot_info(act[z]->c, act[z]->rmax, 0) < 0.0) {
                 still.push_back(z);
                 rmax_open = std::max(rmax_open, act[z]->rmax);
             }
@@ -1251,7 +1278,7 @@ void batch_pivots(std::vector<BState *> &act, int dir, int k) {
         open = std::move(still);
     }
     for (BState *b : act) {
-        const int r = (int)b->c->h_pinned_dbl[0];
+        const int r = (int)pinned_pivot_info(b->c, b->rmax, 0);
         b->c->piv_hist[hist_index(kMaxDim, dir, k)] = r;
         double fl = 0.0;
         for (int t = 0; t < r; ++t) fl += 2.0 * (double)(b->m - t) * (double)(b->n - t);
@@ -1314,7 +1341,7 @@ void batch_cross(std::vector<BState> &bs, const double *aw, const double *bw, in
             if (k == d - 1) break;
             batch_pivots(act, 0, k);
             for (BState *b : act) {
-                const int r = (int)b->c->h_pinned_dbl[0];
+                const int r = (int)pinned_pivot_info(b->c, b->rmax, 0);
                 std::vector<int> rows(b->c->h_pinned_int, b->c->h_pinned_int + r);
                 b->F.core[k] = dalloc<double>(b->c->s, (size_t)b->m * r);
                 interp_solve(b->c->s, b->m, r, b->L, b->rmax, b->piv, b->F.core[k]);
@@ -1360,7 +1387,7 @@ void batch_cross(std::vector<BState> &bs, const double *aw, const double *bw, in
             batch_pivots(refresh, 1, k);
             for (BState *b : refresh) {
                 const ISet &R = b->Rset[k];
-                const int r = (int)b->c->h_pinned_dbl[0], q = R.count;
+                const int r = (int)pinned_pivot_info(b->c, b->rmax, 0), q = R.count;
                 ISet nr;
                 nr.len = d - k;
                 nr.count = r;
@@ -1728,8 +1755,10 @@ wenott_status wenott_init(wenott_ctx **out, const wenott_tt *state, const wenott
         c->s = (hipStream_t)hip_stream;
         c->sc.s = c->s;
         c->ring.init(c->s, 8u << 20);
-        WTT_HIP(hipMalloc((void **)&c->d_flags, sizeof(int)));
-        WTT_HIP(hipMemsetAsync(c->d_flags, 0, sizeof(int), c->s));
+        WTT_HIP(hipMalloc((void **)&c->d_status, sizeof(double) * kStatusDoubles));
+        WTT_HIP(hipMemsetAsync(c->d_status, 0, sizeof(double) * kStatusDoubles, c->s));
+        c->d_flags = (int *)c->d_status;
+        WTT_HIP(hipHostMalloc((void **)&c->h_status, sizeof(double) * kStatusDoubles, hipHostMallocDefault));
         WTT_HIP(hipHostMalloc((void **)&c->h_pinned_int, 4096 * sizeof(int), hipHostMallocDefault));
         WTT_HIP(hipHostMalloc((void **)&c->h_pinned_dbl, 4096 * sizeof(double), hipHostMallocDefault));
         // common padded ranks
@@ -1800,7 +1829,8 @@ void wenott_destroy(wenott_ctx *c) {
         c->sc.release();
         hipStreamSynchronize(c->s);
         c->ring.destroy();
-        if (c->d_flags) hipFree(c->d_flags);
+        if (c->d_status) hipFree(c->d_status);
+        if (c->h_status) hipHostFree(c->h_status);
         if (c->h_pinned_int) hipHostFree(c->h_pinned_int);
         if (c->h_pinned_dbl) hipHostFree(c->h_pinned_dbl);
         for (auto e : c->ev) hipEventDestroy(e);
@@ -1884,9 +1914,7 @@ wenott_status wenott_rk3_step(wenott_ctx *c, double dt, double eps_in, const dou
                 else if (c->o.alpha_mode == 2) a = c->o.alpha_given;
                 else if (st == 0 && c->alpha_cache_valid) a = c->alpha_cache;
                 else if (deferred) {
-                    double *dal = c->sc.get<double>(S_DSCAL, 8) + 4;
-                    exact_alpha_launch(c, X, dal + st, st);
-                    c->alpha_dev = dal + st;
+                    c->alpha_dev = exact_alpha_launch(c, X, st);
                     a = 1.0;  // not used by the kernels while alpha_dev is set
                 } else a = exact_alpha(c, X);
                 if (!deferred) {
@@ -1919,8 +1947,8 @@ wenott_status wenott_rk3_step(wenott_ctx *c, double dt, double eps_in, const dou
                 x_owned = true;
                 if (deferred) {
                     c->alpha_dev = nullptr;
-                    raise_flags(c, c->h_pinned_int[kPinAlpha + st]);
-                    a = c->h_pinned_dbl[kPinAlpha + st];
+                    raise_flags(c, status_flags(c));
+                    a = status_alpha(c, st);
                     WTT_REQUIRE(a > 0.0, WENOTT_EINVAL, "alpha must be positive");
                     c->info.alpha[st] = a;
                 }
@@ -1971,7 +1999,7 @@ wenott_status wenott_batch_rk3_step(wenott_ctx **ctxs, int32_t n, const double *
                 bool any = false;
                 for (auto &b : bs)
                     if (b.c->o.alpha_mode != 2) {
-                        exact_alpha_launch(b.c, b.X, b.c->sc.get<double>(S_DSCAL, 4));
+                        exact_alpha_launch(b.c, b.X, 3);
                         any = true;
                     }
                 if (any) WTT_HIP(hipStreamSynchronize(ctxs[0]->s));
@@ -1979,8 +2007,8 @@ wenott_status wenott_batch_rk3_step(wenott_ctx **ctxs, int32_t n, const double *
                     if (b.c->o.alpha_mode == 2) {
                         b.alpha = b.c->o.alpha_given;
                     } else {
-                        raise_flags(b.c, b.c->h_pinned_int[kPinAlpha]);
-                        b.alpha = b.c->h_pinned_dbl[kPinAlpha];
+                        raise_flags(b.c, status_flags(b.c));
+                        b.alpha = status_alpha(b.c, 3);
                     }
                     WTT_REQUIRE(b.alpha > 0.0, WENOTT_EINVAL, "alpha must be positive");
                     b.c->info.alpha[st] = b.alpha;
