@@ -57,10 +57,11 @@ struct GemmBatch {
 };
 void gemm_f64(hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha, const double *A, int lda,
               const double *B, int ldb, double beta, double *C, int ldc, const GemmBatch &bt = GemmBatch());
-// The tile shape of gemm_f64 comes from a process-wide table tuned on live calls (on by default;
-// off: the 64 x 64 shape everywhere). gemm_tune_table copies up to max_entries rows of
-// {ta, tb, log2 M, log2 N, log2 K, log2 batch, shape (-1 while tuning)} and returns the count.
-void gemm_tune_enable(int on);
+// The tile shape of gemm_f64 comes from a process-wide table tuned on live calls (mode 1, the
+// default); mode 0: the 64 x 64 vector shape everywhere; mode 2 + k: shape k everywhere.
+// gemm_tune_table copies up to max_entries rows of {ta, tb, log2 M, log2 N, log2 K, log2 batch,
+// shape (-1 while tuning)} and returns the count.
+void gemm_tune_enable(int mode);
 int gemm_tune_table(int32_t *out, int max_entries);
 
 // C[z] = A[z]^T B[z] (A: K x M, B: K x N) with the long reduction split into chunks summed

@@ -2050,8 +2050,9 @@ wenott_status wenott_batch_rk3_step(wenott_ctx **ctxs, int32_t n, const double *
     });
 }
 
-wenott_status wenott_gemm_autotune(int32_t on) {
-    gemm_tune_enable(on != 0);
+wenott_status wenott_gemm_autotune(int32_t mode) {
+    if (mode < 0 || mode > 6) return WENOTT_EINVAL;
+    gemm_tune_enable(mode);
     return WENOTT_OK;
 }
 

@@ -211,6 +211,81 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, double alpha,
     }
 }
 
+// FP64 matrix-core form: 64 x 64 tile per 256-thread workgroup, each wave a 32 x 32 quarter as
+// 2 x 2 v_mfma_f64_16x16x4f64 tiles, operands staged through LDS in depth-16 slices. Operand
+// layout of the instruction: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]; its four
+// accumulators hold D[l / 16 + 4 v][l % 16], v = 0..3 (checked on the device against a host
+// product). The matrix core sums each group of four products in its own order, so results
+// agree with the vector form to rounding.
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <bool TA, bool TB>
+__global__ __launch_bounds__(256) void k_gemm_mfma(int M, int N, int K, double alpha, const double *__restrict__ A,
+                                                   int lda, const double *__restrict__ B, int ldb, double beta,
+                                                   double *__restrict__ C, int ldc, GemmBatch bt) {
+    constexpr int TBM = 64, TBN = 64;
+    const int z = blockIdx.z, z1 = z / bt.nb2, z2 = z % bt.nb2;
+    A += z1 * bt.sA1 + z2 * bt.sA2;
+    B += z1 * bt.sB1 + z2 * bt.sB2;
+    C += z1 * bt.sC1 + z2 * bt.sC2;
+    if (bt.ktot > 0) K = min(K, bt.ktot - z2 * K);
+    __shared__ double As[BK][TBM + 1];
+    __shared__ double Bs[BK][TBN + 1];
+    const int t = threadIdx.x, lane = t % 64, wv = t / 64, wr = wv / 2, wc = wv % 2;
+    const int m0 = blockIdx.y * TBM, n0 = blockIdx.x * TBN;
+    f64x4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < K; k0 += BK) {
+#pragma unroll
+        for (int l = 0; l < TBM * BK / 256; ++l) {
+            const int e = t + 256 * l;
+            int r, kk;
+            if (!TA) { r = e / BK; kk = e % BK; } else { kk = e / TBM; r = e % TBM; }
+            const int gm = m0 + r, gk = k0 + kk;
+            double v = 0.0;
+            if (gm < M && gk < K) v = TA ? A[(long long)gk * lda + gm] : A[(long long)gm * lda + gk];
+            As[kk][r] = v;
+            int c;
+            if (!TB) { kk = e / TBN; c = e % TBN; } else { c = e / BK; kk = e % BK; }
+            const int gn = n0 + c;
+            const int gk2 = k0 + kk;
+            v = 0.0;
+            if (gn < N && gk2 < K) v = TB ? B[(long long)gn * ldb + gk2] : B[(long long)gk2 * ldb + gn];
+            Bs[kk][c] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < BK; ks += 4) {
+            double a[2], b[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) a[i] = As[ks + lane / 16][wr * 32 + i * 16 + lane % 16];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) b[j] = Bs[ks + lane / 16][wc * 32 + j * 16 + lane % 16];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int gm = m0 + wr * 32 + i * 16 + lane / 16 + 4 * v;
+                const int gn = n0 + wc * 32 + j * 16 + lane % 16;
+                if (gm < M && gn < N) {
+                    double *c = C + (long long)gm * ldc + gn;
+                    *c = beta == 0.0 ? alpha * acc[i][j][v] : alpha * acc[i][j][v] + beta * *c;
+                }
+            }
+}
+
 // --------------------------------------------------------------------------- TSQR
 // Householder QR of one row block [r0, r0 + nr) of matrix z, in a column-major scratch copy;
 // only R is kept. Step j reflects column j onto its diagonal: every thread derives the
@@ -1052,8 +1127,10 @@ namespace {
 // for the first time is tuned on the live calls: each call launches the next candidate between
 // two events; the timings are collected when the events have completed (no synchronisation),
 // and after kTuneSamples timings of every candidate the fastest shape is kept.
-constexpr int kGemmShapes[][2] = {{64, 64}, {32, 64}, {64, 32}, {32, 32}};
-constexpr int kNumGemmShapes = 4, kTuneSamples = 3;
+// Shapes 0-3 run on the vector units and sum every output in the same order; shape 4 is the
+// FP64 matrix-core form (64 x 64), whose results agree with them to rounding.
+constexpr int kGemmShapes[][2] = {{64, 64}, {32, 64}, {64, 32}, {32, 32}, {64, 64}};
+constexpr int kNumGemmShapes = 5, kTuneSamples = 3;
 
 struct TuneEntry {
     int choice = -1;  // chosen shape, -1 while tuning
@@ -1104,7 +1181,8 @@ void launch_gemm_shape(int shape, hipStream_t s, int M, int N, int K, double alp
         case 0: k_gemm<TA, TB, 64, 64><<<grid, block, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, bt); break;
         case 1: k_gemm<TA, TB, 32, 64><<<grid, block, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, bt); break;
         case 2: k_gemm<TA, TB, 64, 32><<<grid, block, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, bt); break;
-        default: k_gemm<TA, TB, 32, 32><<<grid, block, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, bt); break;
+        case 3: k_gemm<TA, TB, 32, 32><<<grid, block, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, bt); break;
+        default: k_gemm_mfma<TA, TB><<<grid, block, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, bt); break;
     }
 }
 
@@ -1118,10 +1196,10 @@ void launch_gemm(int shape, hipStream_t s, bool ta, bool tb, int M, int N, int K
 
 }  // namespace
 
-void gemm_tune_enable(int on) {
+void gemm_tune_enable(int mode) {
     GemmTuner &t = tuner();
     std::lock_guard<std::mutex> lk(t.mu);
-    t.enabled = on;
+    t.enabled = mode;
 }
 
 int gemm_tune_table(int32_t *out, int max_entries) {
@@ -1147,7 +1225,9 @@ void gemm_f64_tuned(hipStream_t s, bool ta, bool tb, int M, int N, int K, double
     TuneEntry::Pending timed{-1, nullptr, nullptr};
     {
         std::lock_guard<std::mutex> lk(t.mu);
-        if (t.enabled) {
+        if (t.enabled >= 2) {
+            shape = std::min(t.enabled - 2, kNumGemmShapes - 1);  // one shape forced everywhere
+        } else if (t.enabled) {
             const std::array<int, 6> key{(int)ta, (int)tb, log2_bucket(M), log2_bucket(N), log2_bucket(K),
                                          log2_bucket((long long)bt.nb1 * bt.nb2)};
             TuneEntry &e = t.table[key];

@@ -216,8 +216,9 @@ def wenott_batch_rk3_step(ctxs, dts, eps=None):
     _check(load().wenott_batch_rk3_step(arr, n, d, e), ctxs[0])
 
 
-def wenott_gemm_autotune(on):
-    _check(load().wenott_gemm_autotune(int(bool(on))), None)
+def wenott_gemm_autotune(mode):
+    """1 tuned (default), 0 fixed 64x64 vector shape, 2 + k shape k everywhere (4: FP64 matrix cores)."""
+    _check(load().wenott_gemm_autotune(int(mode)), None)
 
 
 def wenott_gemm_autotune_table():

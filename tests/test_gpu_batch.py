@@ -133,27 +133,42 @@ def test_batch_of_blasts_small_grids(W):
 
 
 def test_gemm_autotuner_changes_speed_not_results(W):
-    """The tile table is tuned on live calls; every tile shape sums in the same order, so a
-    step with the tuner on equals the step with the fixed shape bit for bit."""
-    _say("case: GEMM tile autotuner on vs off")
+    """The tile table is tuned on live calls. The vector shapes sum every output in the same
+    order and the FP64 matrix-core shape agrees with them to rounding; a rounding difference can
+    still flip a pivot among near-equal candidates, so runs with the tuner on, or with the
+    matrix-core shape forced everywhere, are held to the parity bar against the fixed-shape run
+    (10 eps per step over 4 steps), and the matrix-core run is checked against the oracle."""
+    _say("case: GEMM tile autotuner and FP64 matrix-core GEMM")
     f = workloads.config2_quadrants_2d(64, seed=4)
     opts = W.default_opts(eps_mode=0, eps0=1e-8)
-    outs = []
+    P = oracle_problem(f)
+    outs = {}
     try:
-        for on in (0, 1):
-            W.wenott_gemm_autotune(on)
+        for mode in (0, 1, 6):
+            W.wenott_gemm_autotune(mode)
             s = W.Solver(f, opts)
             try:
+                u = s.dense()
                 dt = 0.5 * min(f.h) / s.max_wavespeed()
                 for _ in range(4):  # enough calls for several buckets to finish tuning
                     s.step(dt)
-                outs.append(s.dense())
+                    info = s.info()
+                    if mode == 6:
+                        P.ssprk3(u, dt, alphas=[info.alpha[j] for j in range(3)])
+                        err = rel_err(s.dense(), u)
+                        assert err <= 10 * 1e-8, err
+                        u = s.dense()
+                outs[mode] = s.dense()
             finally:
                 s.close()
         table = W.wenott_gemm_autotune_table()
-        _say(f"  buckets {len(table)}, decided {sum(1 for r in table if r[6] >= 0)}")
+        _say(f"  buckets {len(table)}, decided {sum(1 for r in table if r[6] >= 0)}, "
+             f"matrix-core chosen {sum(1 for r in table if r[6] == 4)}")
         assert len(table) > 0 and any(r[6] >= 0 for r in table)
-        assert np.array_equal(outs[0], outs[1])
+        for mode in (1, 6):
+            d = rel_err(outs[mode], outs[0])
+            _say(f"  mode {mode} vs fixed shape: {d:.3e}")
+            assert d <= 4 * 10 * 1e-8, (mode, d)
     finally:
         W.wenott_gemm_autotune(1)
 
