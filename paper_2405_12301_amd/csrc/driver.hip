@@ -803,25 +803,36 @@ void eval_stage_block(wenott_ctx *c, const TT &X, const TT *Un, StageWeights w, 
         const double *cores[kMaxDim];
         for (int j = 0; j < d; ++j) cores[j] = Y.core[j];
         const int SL = (shift >= 0 && shift < k) ? 7 : 1, SR = (shift > k) ? 7 : 1, S = std::max(SL, SR);
-        double *P = c->sc.get<double>(slotP, (size_t)nc * SL * p * Rk);
-        if (k == 0) fill(s, P, (long long)nc * SL * p * Rk, 1.0);
-        else iface(s, g, 0, cores, ranks, p, didxL, SL, SL == 7 ? shift : -1, P);
-        double *Q = c->sc.get<double>(slotQ, (size_t)nc * SR * Rk1 * q);
-        if (k == d - 1) fill(s, Q, (long long)nc * SR * Rk1 * q, 1.0);
-        else iface(s, g, 1, cores, ranks, q, didxR, SR, SR == 7 ? shift : -1, Q);
         const long long tsz = (long long)p * Nk * Rk1;
-        double *T = c->sc.get<double>(slotT, (size_t)nc * SL * tsz);
-        GemmBatch b1;
-        b1.nb1 = nc; b1.nb2 = SL;
-        b1.sA1 = (long long)SL * p * Rk; b1.sA2 = (long long)p * Rk;
-        b1.sB1 = Y.cstride(k); b1.sB2 = 0;
-        b1.sC1 = SL * tsz; b1.sC2 = tsz;
-        gemm_f64(s, false, false, p, Nk * Rk1, Rk, 1.0, P, Rk, Y.core[k], Nk * Rk1, 0.0, T, Nk * Rk1, b1);
+        // T = P G_k; at the first core the left part is the scalar 1 (p = 1, R_0 = 1) and T is
+        // the core itself
+        const double *T;
+        long long tA1;
+        if (k == 0) {
+            T = Y.core[k];
+            tA1 = Y.cstride(k);
+        } else {
+            double *P = c->sc.get<double>(slotP, (size_t)nc * SL * p * Rk);
+            iface(s, g, 0, cores, ranks, p, didxL, SL, SL == 7 ? shift : -1, P);
+            double *Tm = c->sc.get<double>(slotT, (size_t)nc * SL * tsz);
+            GemmBatch b1;
+            b1.nb1 = nc; b1.nb2 = SL;
+            b1.sA1 = (long long)SL * p * Rk; b1.sA2 = (long long)p * Rk;
+            b1.sB1 = Y.cstride(k); b1.sB2 = 0;
+            b1.sC1 = SL * tsz; b1.sC2 = tsz;
+            gemm_f64(s, false, false, p, Nk * Rk1, Rk, 1.0, P, Rk, Y.core[k], Nk * Rk1, 0.0, Tm, Nk * Rk1, b1);
+            T = Tm;
+            tA1 = SL * tsz;
+        }
+        // W = T Q; at the last core the right part is the scalar 1 (q = 1, R_d = 1) and W = T
+        if (k == d - 1) return const_cast<double *>(T);
+        double *Q = c->sc.get<double>(slotQ, (size_t)nc * SR * Rk1 * q);
+        iface(s, g, 1, cores, ranks, q, didxR, SR, SR == 7 ? shift : -1, Q);
         const long long wsz = (long long)p * Nk * q;
         double *W = c->sc.get<double>(slotW, (size_t)nc * S * wsz);
         GemmBatch b2;
         b2.nb1 = nc; b2.nb2 = S;
-        b2.sA1 = SL * tsz; b2.sA2 = SL == 7 ? tsz : 0;
+        b2.sA1 = tA1; b2.sA2 = SL == 7 ? tsz : 0;
         b2.sB1 = (long long)SR * Rk1 * q; b2.sB2 = SR == 7 ? (long long)Rk1 * q : 0;
         b2.sC1 = S * wsz; b2.sC2 = wsz;
         gemm_f64(s, false, false, p * Nk, q, Rk1, 1.0, T, Rk1, Q, q, 0.0, W, q, b2);
