@@ -302,15 +302,16 @@ wenott_status wenott_dense_init(wenott_dense **out, const wenott_grid *grid, dou
 
 void wenott_dense_destroy(wenott_dense *c) {
     if (!c) return;
-    hipStreamSynchronize(c->s);
-    hipFree(c->F);
-    hipFree(c->L);
-    hipFree(c->U1);
-    hipFree(c->part);
-    hipFree(c->scal);
-    hipFree(c->flags);
-    if (c->hscal) hipHostFree(c->hscal);
-    if (c->hflag) hipHostFree(c->hflag);
+    // teardown: errors are not reportable here
+    (void)hipStreamSynchronize(c->s);
+    (void)hipFree(c->F);
+    (void)hipFree(c->L);
+    (void)hipFree(c->U1);
+    (void)hipFree(c->part);
+    (void)hipFree(c->scal);
+    (void)hipFree(c->flags);
+    if (c->hscal) (void)hipHostFree(c->hscal);
+    if (c->hflag) (void)hipHostFree(c->hflag);
     delete c;
 }
 

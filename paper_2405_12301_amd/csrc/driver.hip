@@ -49,8 +49,8 @@ inline void dfree(hipStream_t s, void *p) {
 }
 
 enum Slot {
-    S_P, S_Q, S_T, S_W, S_BLOCK, S_L, S_X, S_PIV, S_INFO, S_ROWBUF, S_TSQR, S_R, S_SIG, S_V, S_JAC, S_W1, S_W2,
-    S_RANKS, S_PART, S_DSCAL, S_UST, S_ACC, S_LM, S_NORMS, S_DELTA, S_TMP, S_DENSE,
+    S_P, S_Q, S_T, S_W, S_BLOCK, S_L, S_PIV, S_ROWBUF, S_TSQR, S_R, S_SIG, S_V, S_JAC, S_W1, S_W2,
+    S_RANKS, S_PART, S_UST, S_LM, S_NORMS, S_TMP, S_DENSE,
     S_PD0, S_PD1, S_QD0, S_QD1, S_TD0, S_TD1, S_WD0, S_WD1, S_PN, S_QN, S_TN, S_WN, S_SPLIT,
     S_F_G, S_F_P, S_F_Q, S_F_T, S_F_W0, S_F_WD0, S_F_WD1, S_MLPY, S_MLPW, S_NSLOTS
 };
@@ -73,7 +73,7 @@ struct Scratch {
     }
     void release() {
         for (int i = 0; i < S_NSLOTS; ++i) {
-            if (p[i]) hipFreeAsync(p[i], s);
+            if (p[i]) (void)hipFreeAsync(p[i], s);
             p[i] = nullptr;
             cap[i] = 0;
         }
@@ -92,8 +92,8 @@ struct Ring {
         WTT_HIP(hipMalloc((void **)&dv, cap));
     }
     void destroy() {
-        if (h) hipHostFree(h);
-        if (dv) hipFree(dv);
+        if (h) (void)hipHostFree(h);
+        if (dv) (void)hipFree(dv);
         h = dv = nullptr;
     }
     template <typename T>
@@ -235,17 +235,6 @@ int status_flags(const wenott_ctx *c) { return *(const int *)c->h_status; }
 // Copy the first `doubles` entries of the status block to its pinned mirror.
 void status_readback(wenott_ctx *c, int doubles) {
     WTT_HIP(hipMemcpyAsync(c->h_status, c->d_status, sizeof(double) * doubles, hipMemcpyDeviceToHost, c->s));
-}
-
-void check_flags(wenott_ctx *c) {
-    WTT_HIP(hipMemcpyAsync(c->h_pinned_int, c->d_flags, sizeof(int), hipMemcpyDeviceToHost, c->s));
-    WTT_HIP(hipStreamSynchronize(c->s));
-    int f = c->h_pinned_int[0];
-    if (f) {
-        WTT_HIP(hipMemsetAsync(c->d_flags, 0, sizeof(int), c->s));
-        if (f & kFlagNaN) throw StatusError(WENOTT_ENAN, "NaN or Inf in a flux evaluation");
-        throw StatusError(WENOTT_ENONPHYS, "rho <= 0 or p <= 0 at an evaluated point");
-    }
 }
 
 // Kernel classes timed with HIP events when profiling is on (wenott_info.class_*).
@@ -545,7 +534,7 @@ std::vector<float> proposal_features(wenott_ctx *c, int d, double eps, double la
 // first mode is drawn from the predicted bin distribution, up to the predicted rank + 2.
 void apply_proposal(wenott_ctx *c, int d, const int *M, const std::vector<float> &x, std::vector<ISet> &Rset,
                     Rng &rng) {
-    const int IN = WENOTT_MLP_IN, OUT = WENOTT_MLP_OUT, NR = WENOTT_MLP_RANK_CLASSES, NB = WENOTT_MLP_BINS;
+    const int OUT = WENOTT_MLP_OUT, NR = WENOTT_MLP_RANK_CLASSES, NB = WENOTT_MLP_BINS;
     const int nb = d - 1;
     const float *dx = c->ring.put(x.data(), x.size());
     float *y = c->sc.get<float>(S_MLPY, (size_t)nb * OUT);
@@ -1833,18 +1822,18 @@ wenott_status wenott_init(wenott_ctx **out, const wenott_tt *state, const wenott
 
 void wenott_destroy(wenott_ctx *c) {
     if (!c) return;
-    {
-        hipStreamSynchronize(c->s);
+    {  // teardown: errors are not reportable here, the context goes away regardless
+        (void)hipStreamSynchronize(c->s);
         c->U.release(c->s);
         if (c->have_rhs) c->rhs.release(c->s);
         c->sc.release();
-        hipStreamSynchronize(c->s);
+        (void)hipStreamSynchronize(c->s);
         c->ring.destroy();
-        if (c->d_status) hipFree(c->d_status);
-        if (c->h_status) hipHostFree(c->h_status);
-        if (c->h_pinned_int) hipHostFree(c->h_pinned_int);
-        if (c->h_pinned_dbl) hipHostFree(c->h_pinned_dbl);
-        for (auto e : c->ev) hipEventDestroy(e);
+        if (c->d_status) (void)hipFree(c->d_status);
+        if (c->h_status) (void)hipHostFree(c->h_status);
+        if (c->h_pinned_int) (void)hipHostFree(c->h_pinned_int);
+        if (c->h_pinned_dbl) (void)hipHostFree(c->h_pinned_dbl);
+        for (auto e : c->ev) (void)hipEventDestroy(e);
     }
     delete c;
 }

@@ -417,20 +417,6 @@ __global__ void k_sum_chunks(long long per, int nchunk, int batch, const double 
     (void)M;
 }
 
-__global__ void k_copy(long long n, const double *__restrict__ src, double *__restrict__ dst) {
-    long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    if (i < n) dst[i] = src[i];
-}
-
-__global__ void k_copy_strided(int n, int batch, const double *__restrict__ src, long long sstride,
-                               double *__restrict__ dst) {
-    long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    long long nn = (long long)n * n;
-    if (e >= nn * batch) return;
-    int z = (int)(e / nn);
-    dst[e] = src[z * sstride + e % nn];
-}
-
 int leaf_rows(int n) {
     int bm = std::max(256, 2 * n);
     return (bm + 63) / 64 * 64;
