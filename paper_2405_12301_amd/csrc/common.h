@@ -91,11 +91,12 @@ void jacobi_svd(hipStream_t s, int n, int batch, const double *A, double *sigma,
 // Stops when the residual's squared Frobenius norm <= rel_tol2 * (initial squared norm), after
 // rmax pivots, or at a zero residual. Writes rank (>= 1), row/col pivots, L columns (m x rmax, row-major) and the final
 // residual norm^2 into info[0..1] = {rank, resid2} (as doubles).
-// ws: prrlu_ws_doubles(m, n) doubles (pivot row, per-workgroup partials and control of the
-// multi-workgroup form used when the block does not fit one workgroup's registers). That form
-// runs one launch per pivot step: this call launches steps t_begin..min(t_end, rmax) and returns
-// the next step; info[0] stays negative until the factorisation has stopped, and the caller
-// continues from the returned step. The register form finishes in one call (t_begin = 0).
+// ws: prrlu_ws_doubles(m, n) doubles (double-buffered per-workgroup partials and candidate rows,
+// and control, of the multi-workgroup form used when the block does not fit one workgroup's
+// registers). That form runs one launch per step, launch t deciding pivot t - 1 and eliminating
+// it: this call launches steps t_begin..min(t_end, rmax + 1) and returns the next step; info[0]
+// stays negative until the factorisation has stopped, and the caller continues from the
+// returned step. The register form finishes in one call (t_begin = 0). Needs rmax >= 1.
 int prrlu(hipStream_t s, int m, int n, double *A, int rmax, double rel_tol2, int *rowpiv, int *colpiv, double *L,
           double *info, double *ws, int t_begin, int t_end);
 size_t prrlu_ws_doubles(int m, int n);
@@ -230,6 +231,9 @@ void trunc_ranks(hipStream_t s, int n, int batch, const double *sigma, const dou
                  int *ranks);
 void build_projectors(hipStream_t s, int n, int batch, int R, const double *sigma, const double *V, const int *ranks,
                       double *W1, double *W2);
+// npts random cells of an n[0] x ... x n[d-1] grid (int [npts][d]), drawn on the device from seed.
+void sample_points(hipStream_t s, int npts, int d, const int *n, unsigned long long seed, int *out);
+
 // out[z] = ||X[z]||_F; if scaled is given, scaled[z] = scale * out[z] as well.
 void frob_norms(hipStream_t s, int batch, long long len, const double *X, long long stride, double *out,
                 double *scaled = nullptr, double scale = 0.0);

@@ -49,7 +49,7 @@ inline void dfree(hipStream_t s, void *p) {
 }
 
 enum Slot {
-    S_P, S_Q, S_T, S_W, S_BLOCK, S_L, S_PIV, S_ROWBUF, S_TSQR, S_R, S_SIG, S_V, S_JAC, S_W1, S_W2,
+    S_P, S_Q, S_T, S_W, S_PTS, S_BLOCK, S_L, S_PIV, S_ROWBUF, S_TSQR, S_R, S_SIG, S_V, S_JAC, S_W1, S_W2,
     S_RANKS, S_PART, S_UST, S_LM, S_NORMS, S_TMP, S_DENSE,
     S_PD0, S_PD1, S_QD0, S_QD1, S_TD0, S_TD1, S_WD0, S_WD1, S_PN, S_QN, S_TN, S_WN, S_SPLIT,
     S_F_G, S_F_P, S_F_Q, S_F_T, S_F_W0, S_F_WD0, S_F_WD1, S_MLPY, S_MLPW, S_NSLOTS
@@ -444,14 +444,15 @@ PivotResult pivots(wenott_ctx *c, double *B, int m, int n, double rel_tol2, doub
     double *L = c->sc.get<double>(S_L, (size_t)m * rmax);
     double *ws = c->sc.get<double>(S_ROWBUF, prrlu_ws_doubles(m, n));
     ev_record(c, KC_PIVOT);
-    int next = prrlu(c->s, m, n, B, rmax, rel_tol2, piv, piv + rmax, L, info, ws, 0, pivot_guess(c, hist_slot, n, rmax));
+    int next = prrlu(c->s, m, n, B, rmax, rel_tol2, piv, piv + rmax, L, info, ws, 0,
+                     pivot_guess(c, hist_slot, n, rmax) + 1);
     ev_record(c, KC_PIVOT);
     for (;;) {
         WTT_HIP(hipMemcpyAsync(c->h_pinned_int, piv, pivot_info_offset(rmax) + 2 * sizeof(double),
                                hipMemcpyDeviceToHost, c->s));
         WTT_HIP(hipStreamSynchronize(c->s));
         if (pinned_pivot_info(c, rmax, 0) >= 0.0) break;
-        WTT_REQUIRE(next <= rmax, WENOTT_EHIP, "pivot search did not stop");
+        WTT_REQUIRE(next <= rmax + 1, WENOTT_EHIP, "pivot search did not stop");
         ev_record(c, KC_PIVOT);
         next = prrlu(c->s, m, n, B, rmax, rel_tol2, piv, piv + rmax, L, info, ws, next, next + std::max(8, next / 2));
         ev_record(c, KC_PIVOT);
@@ -477,10 +478,8 @@ double sampled_residual(wenott_ctx *c, const TT &U, const FluxTT &F, int dir, do
     g.d = d; g.ncomp = U.nc; g.dir = dir; g.k = 0;
     for (int j = 0; j < d; ++j) { g.n[j] = U.N[j]; g.bc[j] = c->bc[j]; }
     g.gamma = c->gamma; g.alpha = alpha; g.eps_w = c->h[dir] * c->h[dir];
-    std::vector<int> pts((size_t)npts * d);
-    for (int i = 0; i < npts; ++i)
-        for (int j = 0; j < d; ++j) pts[(size_t)i * d + j] = rng.below(F.M[j]);
-    const int *dp = c->ring.put(pts.data(), pts.size());
+    int *dp = c->sc.get<int>(S_PTS, (size_t)npts * d);
+    sample_points(c->s, npts, d, F.M, rng.next(), dp);
     double *ust = c->sc.get<double>(S_UST, (size_t)npts * 6 * U.nc);
     int nb = (npts + 255) / 256;
     WTT_REQUIRE(nb <= kMaxResidualBlocks, WENOTT_EINVAL, "too many probe points");
@@ -916,10 +915,8 @@ int sampled_stage_residual_launch(wenott_ctx *c, const TT &X, const TT *Un, Stag
     g.d = d; g.ncomp = X.nc; g.dir = 0; g.k = 0;
     for (int j = 0; j < d; ++j) { g.n[j] = X.N[j]; g.bc[j] = c->bc[j]; }
     g.gamma = c->gamma; g.alpha = alpha; g.alpha_dev = c->alpha_dev;
-    std::vector<int> pts((size_t)npts * d);
-    for (int i = 0; i < npts; ++i)
-        for (int j = 0; j < d; ++j) pts[(size_t)i * d + j] = rng.below(X.N[j]);
-    const int *dp = c->ring.put(pts.data(), pts.size());
+    int *dp = c->sc.get<int>(S_PTS, (size_t)npts * d);
+    sample_points(c->s, npts, d, X.N, rng.next(), dp);
     const int SL = 7 * d + 1;
     double *ust = c->sc.get<double>(S_UST, (size_t)npts * SL * X.nc);
     int nb = (npts + 255) / 256;
@@ -1245,7 +1242,7 @@ void batch_pivots(std::vector<BState *> &act, int dir, int k) {
         j.rowpiv = b->piv; j.colpiv = b->piv + b->rmax; j.L = b->L; j.info = b->info;
         j.ws = c->sc.get<double>(S_ROWBUF, prrlu_ws_doubles(b->m, b->n));
         prrlu_prepare(j);
-        if (j.mode == 1) t_end = std::max(t_end, pivot_guess(c, hist_index(kMaxDim, dir, k), b->n, b->rmax));
+        if (j.mode == 1) t_end = std::max(t_end, pivot_guess(c, hist_index(kMaxDim, dir, k), b->n, b->rmax) + 1);
         jobs.push_back(j);
     }
     int t_begin = 0;
@@ -1273,8 +1270,8 @@ void batch_pivots(std::vector<BState *> &act, int dir, int k) {
             }
         if (still.empty()) break;
         t_begin = t_end + 1;
-        WTT_REQUIRE(t_begin <= rmax_open, WENOTT_EHIP, "pivot search did not stop");
-        t_end = std::min(rmax_open, t_begin + std::max(8, t_begin / 2));
+        WTT_REQUIRE(t_begin <= rmax_open + 1, WENOTT_EHIP, "pivot search did not stop");
+        t_end = std::min(rmax_open + 1, t_begin + std::max(8, t_begin / 2));
         open = std::move(still);
     }
     for (BState *b : act) {

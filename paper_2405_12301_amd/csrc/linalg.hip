@@ -588,32 +588,40 @@ __global__ __launch_bounds__(1024) void k_jacobi_hybrid(int n, const double *__r
 }
 
 // ------------------------------------------------------------------- prrLU (pivots)
-// Multi-workgroup variant for blocks too large for one workgroup's registers: two launches per
-// pivot step t. In the first, each workgroup owns a run of whole rows, applies the elimination
-// of pivot t-1 to them (writing column t-1 of L) and reduces their largest magnitude (ties to
-// the lower linear index) and squared sum. In the second, one workgroup per job combines the
-// partials in workgroup order, takes the stop decision of the single-workgroup form and
-// publishes pivot t and its row for the next step. Workspace (doubles): pivot row [n], partial
-// max [nblk], partial sum [nblk], partial index [nblk], control block.
+// Multi-workgroup variant for blocks too large for one workgroup's registers: one launch per
+// pivot step. Launch t (t >= 1) first decides pivot t - 1 from the partials the workgroups of
+// launch t - 1 left (largest magnitude with ties to the lower linear index, its row, and the
+// squared sum, per workgroup): every workgroup combines them in workgroup order, so all take
+// the same decision without a fence or an atomic. Each then eliminates that pivot from its own
+// rows (writing column t - 1 of L), and leaves its partials of the new residual, including the
+// whole row of its largest entry (the next pivot row if it wins). Partials are double-buffered
+// by step parity. Workspace (doubles): 2 x [max nblk | sum nblk | index nblk | rows nblk x n],
+// then a control block.
+// stop_launch is 0 until the launch that decides to stop writes its own index t (>= 1) there;
+// launches after it return at once. A workgroup of that same launch may read 0 or t, and both
+// let it go on and take the same stop decision itself.
 struct PrrluCtl {
-    long long idx;
-    double piv, tol2;
-    int stop, pad;
+    double tol2;
+    int stop_launch, pad;
 };
 
 struct PrrluWs {
-    double *rowbuf, *pmax, *psum;
-    long long *pidx;
+    double *pmax[2], *psum[2], *prow[2];
+    long long *pidx[2];
     PrrluCtl *ctl;
 };
 
 __host__ __device__ inline PrrluWs prrlu_ws_split(double *ws, int n, int nblk) {
     PrrluWs w;
-    w.rowbuf = ws;
-    w.pmax = ws + n;
-    w.psum = w.pmax + nblk;
-    w.pidx = (long long *)(w.psum + nblk);
-    w.ctl = (PrrluCtl *)(w.pidx + nblk);
+    double *p = ws;
+    for (int b = 0; b < 2; ++b) {
+        w.pmax[b] = p;
+        w.psum[b] = p + nblk;
+        w.pidx[b] = (long long *)(p + 2 * nblk);
+        w.prow[b] = p + 3 * nblk;
+        p += 3 * nblk + (size_t)nblk * n;
+    }
+    w.ctl = (PrrluCtl *)p;
     return w;
 }
 
@@ -621,32 +629,90 @@ constexpr int kMwThreads = 256, kMwTW = 8, kMwK = 2;
 
 __device__ __forceinline__ void prrlu_mw_init_body(const PrrluJob &J) {
     const PrrluWs w = prrlu_ws_split(J.ws, J.n, J.nblk);
-    w.ctl->stop = 0;
-    w.ctl->idx = 0;
-    w.ctl->piv = 0.0;
+    w.ctl->stop_launch = 0;
     w.ctl->tol2 = 0.0;
     J.info[0] = -1.0;  // not finished: the host launches further steps
 }
 
-// Step t, part 1 (all workgroups of the job): workgroup b owns a stripe of J.rows = RS * kMwK
-// rows; thread (tr, tc) holds the kMwTW columns [8 tc, 8 tc + 8) of rows r0 + tr + k RS, k < kMwK,
-// with RS = 256 / ceil(n / 8). It eliminates pivot t - 1 (chosen by part 2 of the previous step)
-// from its rows, writes column t - 1 of L for them, and stores the stripe's largest magnitude,
-// its index and the squared sum as the workgroup's partial. The kernel boundary orders the
-// parts, so no fence or atomic is needed.
-__device__ __forceinline__ void prrlu_mw_update_body(const PrrluJob &J, int t) {
+// Workgroup b owns a stripe of J.rows = RS * kMwK rows; thread (tr, tc) holds the kMwTW columns
+// [8 tc, 8 tc + 8) of rows r0 + tr + k RS, k < kMwK, with RS = 256 / ceil(n / 8).
+__device__ __forceinline__ void prrlu_mw_step_body(const PrrluJob &J, int t) {
     __shared__ double lc[kMwThreads * kMwK];
+    __shared__ double u[kMwThreads * kMwTW];  // the pivot row (prrlu_prepare enforces n <= this)
     __shared__ double wmax[kMwThreads / kWave], wsum[kMwThreads / kWave];
     __shared__ long long widx[kMwThreads / kWave];
+    __shared__ int s_stop, s_wk;
+    __shared__ long long s_gi;
+    __shared__ double s_gs;
     const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave;
     const int m = J.m, n = J.n, rmax = J.rmax;
     const PrrluWs w = prrlu_ws_split(J.ws, n, J.nblk);
     double *__restrict__ A = J.A;
-    if (w.ctl->stop) return;
+    const int sl = w.ctl->stop_launch;
+    if (sl != 0 && sl < t) return;
     const int tpr = (n + kMwTW - 1) / kMwTW, RS = kMwThreads / tpr;
     const int tr = tid / tpr, tc = tid % tpr, c0 = tc * kMwTW;
     const bool active = tr < RS;
     const int r0 = blockIdx.x * J.rows;
+    const int cur = t & 1, prev = cur ^ 1;
+    int pi = -1, pj = -1;
+    if (t > 0) {
+        // decide pivot t - 1 from the previous launch's partials (the same in every workgroup)
+        double bm = -1.0, bs = 0.0;
+        long long bi = 0x7fffffffffffffffLL;
+        for (int b = tid; b < J.nblk; b += kMwThreads) {
+            amax_merge(bm, bi, w.pmax[prev][b], w.pidx[prev][b]);
+            bs += w.psum[prev][b];
+        }
+        // the winning workgroup is the owner of the winning index's row stripe
+        wave_amax_sum(bm, bi, bs);
+        if (lane == 0) { wmax[wv] = bm; widx[wv] = bi; wsum[wv] = bs; }
+        __syncthreads();
+        if (tid == 0) {
+            double gm = wmax[0], gs = 0.0;
+            long long gi = widx[0];
+            for (int k = 0; k < kMwThreads / kWave; ++k) {
+                gs += wsum[k];
+                amax_merge(gm, gi, wmax[k], widx[k]);
+            }
+            const int tp = t - 1;  // the pivot being decided
+            const double tol2 = tp == 0 ? J.rel_tol2 * gs : w.ctl->tol2;
+            int stop = (tp >= rmax) || (gm <= 0.0) || (gs <= tol2);
+            if (tp == 0 && gm <= 0.0) stop = 2;  // all-zero block
+            if (tp == 0 && stop == 1) stop = 0;  // always take at least one pivot of a nonzero block
+            s_stop = stop;
+            s_gi = gi;
+            s_gs = gs;
+            s_wk = gm > 0.0 ? (int)((gi / n) / J.rows) : 0;  // the workgroup whose stripe holds the row
+            if (blockIdx.x == 0) {
+                if (tp == 0) w.ctl->tol2 = tol2;
+                if (stop) {
+                    int rank = tp;
+                    if (stop == 2) {
+                        rank = 1;
+                        J.rowpiv[0] = 0; J.colpiv[0] = 0;
+                    }
+                    J.info[0] = (double)rank;
+                    J.info[1] = gs;
+                    w.ctl->stop_launch = t;
+                } else {
+                    J.rowpiv[tp] = (int)(gi / n);
+                    J.colpiv[tp] = (int)(gi % n);
+                }
+            }
+        }
+        __syncthreads();
+        if (s_stop) {
+            if (s_stop == 2)
+                for (int row = r0 + tid; row < min(m, r0 + J.rows); row += kMwThreads)
+                    J.L[(long long)row * rmax] = (row == 0) ? 1.0 : 0.0;
+            return;
+        }
+        pi = (int)(s_gi / n);
+        pj = (int)(s_gi % n);
+        const double *prow = w.prow[prev] + (long long)s_wk * n;
+        for (int j = tid; j < n; j += kMwThreads) u[j] = prow[j];
+    }
     double a[kMwK][kMwTW];
 #pragma unroll
     for (int k = 0; k < kMwK; ++k) {
@@ -656,9 +722,6 @@ __device__ __forceinline__ void prrlu_mw_update_body(const PrrluJob &J, int t) {
         for (int j = 0; j < kMwTW; ++j) a[k][j] = (rv && c0 + j < n) ? A[(long long)row * n + c0 + j] : 0.0;
     }
     if (t > 0) {
-        const long long pidx = w.ctl->idx;
-        const int pi = (int)(pidx / n), pj = (int)(pidx % n);
-        const double inv = 1.0 / w.ctl->piv;
         if (active && pj >= c0 && pj < c0 + kMwTW) {  // the pivot column's owners publish it
 #pragma unroll
             for (int j = 0; j < kMwTW; ++j)
@@ -667,10 +730,11 @@ __device__ __forceinline__ void prrlu_mw_update_body(const PrrluJob &J, int t) {
                     for (int k = 0; k < kMwK; ++k) lc[tr + k * RS] = a[k][j];
         }
         __syncthreads();
+        const double inv = 1.0 / u[pj];
         if (active) {
-            double u[kMwTW];
+            double uu[kMwTW];
 #pragma unroll
-            for (int j = 0; j < kMwTW; ++j) u[j] = c0 + j < n ? w.rowbuf[c0 + j] : 0.0;
+            for (int j = 0; j < kMwTW; ++j) uu[j] = c0 + j < n ? u[c0 + j] : 0.0;
 #pragma unroll
             for (int k = 0; k < kMwK; ++k) {
                 const int row = r0 + tr + k * RS;
@@ -682,7 +746,7 @@ __device__ __forceinline__ void prrlu_mw_update_body(const PrrluJob &J, int t) {
                     for (int j = 0; j < kMwTW; ++j) a[k][j] = 0.0;
                 } else {
 #pragma unroll
-                    for (int j = 0; j < kMwTW; ++j) a[k][j] = fma(-l, u[j], a[k][j]);
+                    for (int j = 0; j < kMwTW; ++j) a[k][j] = fma(-l, uu[j], a[k][j]);
                 }
             }
             if (pj >= c0 && pj < c0 + kMwTW) {
@@ -718,6 +782,7 @@ __device__ __forceinline__ void prrlu_mw_update_body(const PrrluJob &J, int t) {
     }
     if (!active) { lmax = -1.0; lsum = 0.0; }
     wave_amax_sum(lmax, lidx, lsum);
+    __syncthreads();  // every thread is done with lc and u of this step
     if (lane == 0) { wmax[wv] = lmax; widx[wv] = lidx; wsum[wv] = lsum; }
     __syncthreads();
     if (tid == 0) {
@@ -727,91 +792,34 @@ __device__ __forceinline__ void prrlu_mw_update_body(const PrrluJob &J, int t) {
             bs += wsum[k];
             amax_merge(bm, bi, wmax[k], widx[k]);
         }
-        w.pmax[blockIdx.x] = bm;
-        w.psum[blockIdx.x] = bs;
-        w.pidx[blockIdx.x] = bi;
-    }
-}
-
-// Step t, part 2 (one workgroup per job): combine the partials in workgroup order, take the
-// stop decision of the single-workgroup form and publish pivot t and its row.
-__device__ __forceinline__ void prrlu_mw_select_body(const PrrluJob &J, int t) {
-    __shared__ double wmax[kMwThreads / kWave], wsum[kMwThreads / kWave];
-    __shared__ long long widx[kMwThreads / kWave];
-    __shared__ int s_stop;
-    __shared__ long long s_idx;
-    const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave;
-    const int m = J.m, n = J.n, rmax = J.rmax;
-    const PrrluWs w = prrlu_ws_split(J.ws, n, J.nblk);
-    if (w.ctl->stop) return;
-    double bm = -1.0, bs = 0.0;
-    long long bi = 0x7fffffffffffffffLL;
-    for (int b = tid; b < J.nblk; b += kMwThreads) {
-        amax_merge(bm, bi, w.pmax[b], w.pidx[b]);
-        bs += w.psum[b];
-    }
-    wave_amax_sum(bm, bi, bs);
-    if (lane == 0) { wmax[wv] = bm; widx[wv] = bi; wsum[wv] = bs; }
-    __syncthreads();
-    if (tid == 0) {
-        double gm = wmax[0], gs = 0.0;
-        long long gi = widx[0];
-        for (int k = 0; k < kMwThreads / kWave; ++k) {
-            gs += wsum[k];
-            amax_merge(gm, gi, wmax[k], widx[k]);
-        }
-        if (t == 0) w.ctl->tol2 = J.rel_tol2 * gs;
-        int stop = (t >= rmax) || (gm <= 0.0) || (gs <= w.ctl->tol2);
-        if (t == 0 && gm <= 0.0) stop = 2;  // all-zero block
-        if (t == 0 && stop == 1) stop = 0;  // always take at least one pivot of a nonzero block
-        if (stop) {
-            int rank = t;
-            if (stop == 2) {
-                rank = 1;
-                J.rowpiv[0] = 0; J.colpiv[0] = 0;
-            }
-            J.info[0] = (double)rank;
-            J.info[1] = gs;
-        } else {
-            J.rowpiv[t] = (int)(gi / n);
-            J.colpiv[t] = (int)(gi % n);
-            w.ctl->idx = gi;
-            w.ctl->piv = J.A[gi];
-        }
-        w.ctl->stop = stop;
-        s_stop = stop;
-        s_idx = gi;
+        w.pmax[cur][blockIdx.x] = bm;
+        w.psum[cur][blockIdx.x] = bs;
+        w.pidx[cur][blockIdx.x] = bi;
+        s_gi = bi;
     }
     __syncthreads();
-    if (s_stop == 2)
-        for (int i = tid; i < m; i += kMwThreads) J.L[(long long)i * rmax] = (i == 0) ? 1.0 : 0.0;
-    if (!s_stop) {
-        const long long prow = (s_idx / n) * (long long)n;
-        for (int jj = tid; jj < n; jj += kMwThreads) w.rowbuf[jj] = J.A[prow + jj];
+    // the candidate pivot row: the whole row of this stripe's largest entry, as just written
+    // by this workgroup (its own rows, so no other workgroup touches it in this launch)
+    if (s_gi != 0x7fffffffffffffffLL) {
+        const long long rowbase = (s_gi / n) * (long long)n;
+        double *dst = w.prow[cur] + (long long)blockIdx.x * n;
+        for (int j = tid; j < n; j += kMwThreads) dst[j] = A[rowbase + j];
     }
 }
 
 __global__ void k_prrlu_mw_init(PrrluJob J) { prrlu_mw_init_body(J); }
 
-__global__ __launch_bounds__(kMwThreads) void k_prrlu_mw_update(PrrluJob J, int t) { prrlu_mw_update_body(J, t); }
-
-__global__ __launch_bounds__(kMwThreads) void k_prrlu_mw_select(PrrluJob J, int t) { prrlu_mw_select_body(J, t); }
+__global__ __launch_bounds__(kMwThreads) void k_prrlu_mw_step(PrrluJob J, int t) { prrlu_mw_step_body(J, t); }
 
 __global__ void k_prrlu_mw_init_batch(const PrrluJob *__restrict__ jobs, int njobs) {
     const int z = blockIdx.x * blockDim.x + threadIdx.x;
     if (z < njobs && jobs[z].mode == 1) prrlu_mw_init_body(jobs[z]);
 }
 
-__global__ __launch_bounds__(kMwThreads) void k_prrlu_mw_update_batch(const PrrluJob *__restrict__ jobs, int t) {
+__global__ __launch_bounds__(kMwThreads) void k_prrlu_mw_step_batch(const PrrluJob *__restrict__ jobs, int t) {
     const PrrluJob J = jobs[blockIdx.y];
     if (J.mode != 1 || (int)blockIdx.x >= J.nblk) return;
-    prrlu_mw_update_body(J, t);
-}
-
-__global__ __launch_bounds__(kMwThreads) void k_prrlu_mw_select_batch(const PrrluJob *__restrict__ jobs, int t) {
-    const PrrluJob J = jobs[blockIdx.x];
-    if (J.mode != 1) return;
-    prrlu_mw_select_body(J, t);
+    prrlu_mw_step_body(J, t);
 }
 
 // Single-workgroup form: the whole block stays in registers for all pivot steps. Thread tid
@@ -820,15 +828,15 @@ __global__ __launch_bounds__(kMwThreads) void k_prrlu_mw_select_batch(const Prrl
 // row and column pass through LDS. Two barriers per step: after the wave partials (every thread
 // then reduces the 16 partials itself) and after the pivot row and column are published. The
 // eliminated row and column are set to exact zeros.
-template <int TH, int TW>
+template <int TH, int TW, int NT>
 __device__ __forceinline__ void prrlu_tile_body(int m, int n, const double *__restrict__ A, int rmax,
                                                 double rel_tol2, int *__restrict__ rowpiv, int *__restrict__ colpiv,
                                                 double *__restrict__ L, double *__restrict__ info) {
     extern __shared__ double sm[];
     double *colv = sm, *rowv = sm + m;
-    __shared__ double wmax[16], wsum[16];
-    __shared__ int widx[16];
-    const int tid = threadIdx.x, lane = tid % kWave, w = tid / kWave, nw = blockDim.x / kWave;
+    __shared__ double wmax[NT / kWave], wsum[NT / kWave];
+    __shared__ int widx[NT / kWave];
+    const int tid = threadIdx.x, lane = tid % kWave, w = tid / kWave, nw = NT / kWave;
     const int tn = (n + TW - 1) / TW, tm = (m + TH - 1) / TH;
     const bool active = tid < tm * tn;
     const int r0 = active ? (tid / tn) * TH : m, c0 = active ? (tid % tn) * TW : n;
@@ -914,7 +922,7 @@ __device__ __forceinline__ void prrlu_tile_body(int m, int n, const double *__re
                         for (int i = 0; i < TH; ++i) a[i][j] = 0.0;
             }
         }
-        for (int i = tid; i < m; i += blockDim.x) L[(long long)i * rmax + t] = (i == pi) ? 1.0 : colv[i] * inv;
+        for (int i = tid; i < m; i += NT) L[(long long)i * rmax + t] = (i == pi) ? 1.0 : colv[i] * inv;
     }
     if (tid == 0) {
         int rank = t;
@@ -926,59 +934,62 @@ __device__ __forceinline__ void prrlu_tile_body(int m, int n, const double *__re
         info[1] = bs;
     }
     if (stop == 2)
-        for (int i = tid; i < m; i += blockDim.x) L[(long long)i * rmax] = (i == 0) ? 1.0 : 0.0;
+        for (int i = tid; i < m; i += NT) L[(long long)i * rmax] = (i == 0) ? 1.0 : 0.0;
 }
 
-template <int TH, int TW>
-__global__ __launch_bounds__(1024) void k_prrlu_tile(int m, int n, const double *__restrict__ A, int rmax,
-                                                     double rel_tol2, int *__restrict__ rowpiv,
-                                                     int *__restrict__ colpiv, double *__restrict__ L,
-                                                     double *__restrict__ info) {
-    prrlu_tile_body<TH, TW>(m, n, A, rmax, rel_tol2, rowpiv, colpiv, L, info);
+template <int TH, int TW, int NT>
+__global__ __launch_bounds__(NT) void k_prrlu_tile(int m, int n, const double *__restrict__ A, int rmax,
+                                                   double rel_tol2, int *__restrict__ rowpiv,
+                                                   int *__restrict__ colpiv, double *__restrict__ L,
+                                                   double *__restrict__ info) {
+    prrlu_tile_body<TH, TW, NT>(m, n, A, rmax, rel_tol2, rowpiv, colpiv, L, info);
 }
 
 // One workgroup per job of the given tile shape: the pivot searches of a batch of blocks.
-template <int TH, int TW>
-__global__ __launch_bounds__(1024) void k_prrlu_tile_batch(const PrrluJob *__restrict__ jobs, int shape) {
+template <int TH, int TW, int NT>
+__global__ __launch_bounds__(NT) void k_prrlu_tile_batch(const PrrluJob *__restrict__ jobs, int shape) {
     const PrrluJob j = jobs[blockIdx.x];
     if (j.mode != 0 || j.shape != shape) return;
-    prrlu_tile_body<TH, TW>(j.m, j.n, j.A, j.rmax, j.rel_tol2, j.rowpiv, j.colpiv, j.L, j.info);
+    prrlu_tile_body<TH, TW, NT>(j.m, j.n, j.A, j.rmax, j.rel_tol2, j.rowpiv, j.colpiv, j.L, j.info);
 }
 
-// Tile shapes of the single-workgroup form, smallest register footprint first.
+// Tile shapes of the single-workgroup form, smallest register footprint first: 1024 threads
+// with up to 36 entries each, then 512 threads (twice the registers per thread) with up to 80.
 struct TileShape {
-    int th, tw;
+    int th, tw, nt;
 };
-constexpr TileShape kTileShapes[] = {{1, 4}, {2, 4}, {1, 16}, {4, 4}, {2, 8}, {8, 2}, {4, 8}, {8, 4}, {2, 16},
-                                     {4, 9}};
+constexpr TileShape kTileShapes[] = {{1, 4, 1024}, {2, 4, 1024}, {1, 16, 1024}, {4, 4, 1024}, {2, 8, 1024},
+                                     {8, 2, 1024}, {4, 8, 1024}, {8, 4, 1024},  {2, 16, 1024}, {4, 9, 1024},
+                                     {8, 8, 512},  {8, 10, 512}};
 constexpr int kNumTileShapes = sizeof(kTileShapes) / sizeof(kTileShapes[0]);
 
-template <int TH, int TW>
+template <int TH, int TW, int NT>
 void launch_tile(hipStream_t s, int nb, size_t lds, const PrrluJob *jobs, int shape, int m, int n, const double *A,
                  int rmax, double rel_tol2, int *rowpiv, int *colpiv, double *L, double *info) {
-    if (jobs) k_prrlu_tile_batch<TH, TW><<<nb, 1024, lds, s>>>(jobs, shape);
-    else k_prrlu_tile<TH, TW><<<1, 1024, lds, s>>>(m, n, A, rmax, rel_tol2, rowpiv, colpiv, L, info);
+    if (jobs) k_prrlu_tile_batch<TH, TW, NT><<<nb, NT, lds, s>>>(jobs, shape);
+    else k_prrlu_tile<TH, TW, NT><<<1, NT, lds, s>>>(m, n, A, rmax, rel_tol2, rowpiv, colpiv, L, info);
 }
 
 void dispatch_tile(hipStream_t s, int shape, int nb, size_t lds, const PrrluJob *jobs, int m, int n, const double *A,
                    int rmax, double rel_tol2, int *rowpiv, int *colpiv, double *L, double *info) {
-#define WTT_TILE(ID, TH, TW) \
-    case ID: launch_tile<TH, TW>(s, nb, lds, jobs, shape, m, n, A, rmax, rel_tol2, rowpiv, colpiv, L, info); break;
+#define WTT_TILE(ID, TH, TW, NT) \
+    case ID: launch_tile<TH, TW, NT>(s, nb, lds, jobs, shape, m, n, A, rmax, rel_tol2, rowpiv, colpiv, L, info); break;
     switch (shape) {
-        WTT_TILE(0, 1, 4) WTT_TILE(1, 2, 4) WTT_TILE(2, 1, 16) WTT_TILE(3, 4, 4) WTT_TILE(4, 2, 8) WTT_TILE(5, 8, 2)
-        WTT_TILE(6, 4, 8) WTT_TILE(7, 8, 4) WTT_TILE(8, 2, 16) WTT_TILE(9, 4, 9)
+        WTT_TILE(0, 1, 4, 1024) WTT_TILE(1, 2, 4, 1024) WTT_TILE(2, 1, 16, 1024) WTT_TILE(3, 4, 4, 1024)
+        WTT_TILE(4, 2, 8, 1024) WTT_TILE(5, 8, 2, 1024) WTT_TILE(6, 4, 8, 1024) WTT_TILE(7, 8, 4, 1024)
+        WTT_TILE(8, 2, 16, 1024) WTT_TILE(9, 4, 9, 1024) WTT_TILE(10, 8, 8, 512) WTT_TILE(11, 8, 10, 512)
         default: throw StatusError(WENOTT_EINVAL, "bad pivot tile shape");
     }
 #undef WTT_TILE
 }
 
-// First tile shape whose tiles cover the m x n block with at most 1024 threads, or -1.
+// First tile shape whose tiles cover the m x n block within its thread count, or -1.
 int tile_shape_for(int m, int n) {
     if (sizeof(double) * (size_t)(m + n) > 48 * 1024) return -1;
     for (int k = 0; k < kNumTileShapes; ++k) {
         const long long tiles = (long long)((m + kTileShapes[k].th - 1) / kTileShapes[k].th) *
                                 ((n + kTileShapes[k].tw - 1) / kTileShapes[k].tw);
-        if (tiles <= 1024) return k;
+        if (tiles <= kTileShapes[k].nt) return k;
     }
     return -1;
 }
@@ -1391,7 +1402,7 @@ size_t prrlu_ws_doubles(int m, int n) {
     PrrluJob j{};
     j.m = m; j.n = n;
     prrlu_prepare(j);
-    return (size_t)n + 3 * (size_t)j.nblk + 8;
+    return 2 * (3 * (size_t)j.nblk + (size_t)j.nblk * n) + 2;
 }
 
 int prrlu(hipStream_t s, int m, int n, double *A, int rmax, double rel_tol2, int *rowpiv, int *colpiv, double *L,
@@ -1399,6 +1410,7 @@ int prrlu(hipStream_t s, int m, int n, double *A, int rmax, double rel_tol2, int
     PrrluJob j{};
     j.A = A; j.m = m; j.n = n; j.rmax = rmax; j.rel_tol2 = rel_tol2;
     j.rowpiv = rowpiv; j.colpiv = colpiv; j.L = L; j.info = info; j.ws = ws;
+    WTT_REQUIRE(rmax >= 1 && m >= 1 && n >= 1, WENOTT_EINVAL, "pivot search needs a nonempty block and rmax >= 1");
     prrlu_prepare(j);
     if (j.mode == 0) {
         if (t_begin > 0) return rmax + 1;
@@ -1407,12 +1419,10 @@ int prrlu(hipStream_t s, int m, int n, double *A, int rmax, double rel_tol2, int
         WTT_HIP(hipGetLastError());
         return rmax + 1;
     }
+    // launch t decides pivot t - 1, so the last possible decision (stop at rmax) is launch rmax + 1
     if (t_begin == 0) k_prrlu_mw_init<<<1, 1, 0, s>>>(j);
-    const int last = std::min(t_end, rmax);
-    for (int t = t_begin; t <= last; ++t) {
-        k_prrlu_mw_update<<<j.nblk, kMwThreads, 0, s>>>(j, t);
-        k_prrlu_mw_select<<<1, kMwThreads, 0, s>>>(j, t);
-    }
+    const int last = std::min(t_end, rmax + 1);
+    for (int t = t_begin; t <= last; ++t) k_prrlu_mw_step<<<j.nblk, kMwThreads, 0, s>>>(j, t);
     WTT_HIP(hipGetLastError());
     return last + 1;
 }
@@ -1479,10 +1489,8 @@ void prrlu_batch(hipStream_t s, int njobs, const PrrluJob *host_jobs, const Prrl
                               nullptr, nullptr);
     if (nmw) {
         if (t_begin == 0) k_prrlu_mw_init_batch<<<cdiv(njobs, 64), 64, 0, s>>>(dev_jobs, njobs);
-        for (int t = t_begin; t <= t_end; ++t) {
-            k_prrlu_mw_update_batch<<<dim3(maxblk, njobs), kMwThreads, 0, s>>>(dev_jobs, t);
-            k_prrlu_mw_select_batch<<<njobs, kMwThreads, 0, s>>>(dev_jobs, t);
-        }
+        for (int t = t_begin; t <= t_end; ++t)
+            k_prrlu_mw_step_batch<<<dim3(maxblk, njobs), kMwThreads, 0, s>>>(dev_jobs, t);
     }
     WTT_HIP(hipGetLastError());
 }

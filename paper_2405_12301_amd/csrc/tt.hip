@@ -187,6 +187,25 @@ void build_projectors(hipStream_t s, int n, int batch, int R, const double *sigm
     WTT_HIP(hipGetLastError());
 }
 
+// Random probe cells: coordinate j of point i is splitmix64(seed + golden (i d + j + 1)) mod N_j.
+__global__ void k_sample_points(int npts, int d, int n0, int n1, int n2, unsigned long long seed, int *__restrict__ out) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= npts * d) return;
+    const int j = e % d;
+    unsigned long long z = seed + 0x9E3779B97F4A7C15ULL * (unsigned long long)(e + 1);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    z ^= z >> 31;
+    const int nj = j == 0 ? n0 : (j == 1 ? n1 : n2);
+    out[e] = (int)(z % (unsigned long long)nj);
+}
+
+void sample_points(hipStream_t s, int npts, int d, const int *n, unsigned long long seed, int *out) {
+    k_sample_points<<<cdiv((long long)npts * d, 256), 256, 0, s>>>(npts, d, n[0], d > 1 ? n[1] : 1, d > 2 ? n[2] : 1,
+                                                                     seed, out);
+    WTT_HIP(hipGetLastError());
+}
+
 void frob_norms(hipStream_t s, int batch, long long len, const double *X, long long stride, double *out,
                 double *scaled, double scale) {
     k_frob<<<batch, 1024, 0, s>>>(len, X, stride, out, scaled, scale);
