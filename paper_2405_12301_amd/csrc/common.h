@@ -78,14 +78,16 @@ size_t tsqr_scratch_doubles(int m, int n, int batch);
 void tsqr_r(hipStream_t s, int m, int n, int batch, const double *A, long long sz, long long rs, long long cs,
             double *R, double *scratch);
 
-// One-sided Jacobi SVD of a batch of n x n matrices (row-major at A[z * n * n]).
-// Outputs sigma[z * n + j] sorted descending, V[z * n * n] row-major with column j the
-// right singular vector of sigma_j and, if US != null, A V (= U Sigma). The matrices live in
-// LDS when 2 n^2 doubles fit; otherwise scratch must hold batch * (2 n^2 + n) doubles.
+// Singular values and right singular vectors of tall matrices C_z = Q_z R_z from their n x n
+// row-major upper-triangular R factors (R at R[z * n * n]), by one-sided Jacobi on R^T.
+// Outputs sigma[z * n + j] sorted descending and V[z * n * n] row-major with column j the right
+// singular vector of sigma_j (zero for sigma_j = 0). The matrices live in LDS when n^2 doubles
+// fit; otherwise scratch must hold jacobi_scratch_doubles(n, batch) doubles.
 // delta (device, one per matrix, may be null): truncation threshold of the singular values;
 // rotations whose effect stays far below it are skipped.
-void jacobi_svd(hipStream_t s, int n, int batch, const double *A, double *sigma, double *V, double *scratch,
-                double *US = nullptr, const double *delta = nullptr);
+void jacobi_svd(hipStream_t s, int n, int batch, const double *R, double *sigma, double *V, double *scratch,
+                const double *delta = nullptr);
+size_t jacobi_scratch_doubles(int n, int batch);
 
 // Full-pivot rank-revealing LU of one m x n row-major matrix (overwritten by its residual).
 // Stops when the residual's squared Frobenius norm <= rel_tol2 * (initial squared norm), after
@@ -119,7 +121,7 @@ struct PrrluJob {
 };
 void prrlu_prepare(PrrluJob &j);
 struct SvdJob {
-    const double *A;
+    const double *A;  // R factors, as for jacobi_svd
     double *sigma, *V;
     int n, batch;
     const double *delta;  // per component truncation threshold (device) or null

@@ -12,7 +12,10 @@
 #include <cmath>
 #include <cstring>
 #include <functional>
+#include <map>
+#include <mutex>
 #include <new>
+#include <unordered_map>
 #include <vector>
 
 #include "common.h"
@@ -34,18 +37,105 @@ struct Rng {
     int below(int n) { return (int)(next() % (uint64_t)n); }
 };
 
-// Stream-ordered device allocation.
+// Stream-ordered device allocation with a per-stream cache of freed blocks. The work of one
+// stream runs in order, so a block freed on a stream can be handed out again on that stream at
+// once: whatever is enqueued later runs after everything that used the block before. Sizes are
+// rounded up to eight classes per power of two; up to kCacheBytes per stream stay cached, beyond
+// that a freed block goes back to the runtime. The TT cores of every cross and rounding come and
+// go through here, so a step makes no runtime allocation once the ranks have settled.
+constexpr size_t kCacheBytes = size_t(2) << 30;
+
+struct AllocCache {
+    std::mutex mu;
+    std::unordered_map<void *, std::pair<hipStream_t, size_t>> live;  // pointer -> (stream, bytes)
+    std::map<hipStream_t, std::multimap<size_t, void *>> idle;
+    std::map<hipStream_t, size_t> idle_bytes;
+};
+
+AllocCache &alloc_cache() {
+    static AllocCache *ac = new AllocCache;  // never destroyed: blocks outlive static destructors
+    return *ac;
+}
+
+size_t size_class(size_t bytes) {
+    bytes = std::max<size_t>(bytes, 256);
+    const int p = 63 - __builtin_clzll((unsigned long long)bytes);
+    const size_t step = size_t(1) << (p - 3);
+    return (bytes + step - 1) / step * step;
+}
+
+// Returns the idle blocks of stream s to the runtime.
+void release_stream_cache(hipStream_t s) {
+    AllocCache &ac = alloc_cache();
+    std::multimap<size_t, void *> blocks;
+    {
+        std::lock_guard<std::mutex> g(ac.mu);
+        auto it = ac.idle.find(s);
+        if (it == ac.idle.end()) return;
+        blocks.swap(it->second);
+        ac.idle.erase(it);
+        ac.idle_bytes.erase(s);
+    }
+    for (auto &b : blocks) (void)hipFreeAsync(b.second, s);
+}
+
+// Drops p from the bookkeeping (for teardown paths that free it themselves).
+void forget_block(void *p) {
+    AllocCache &ac = alloc_cache();
+    std::lock_guard<std::mutex> g(ac.mu);
+    ac.live.erase(p);
+}
+
 template <typename T>
 T *dalloc(hipStream_t s, size_t count) {
+    const size_t bytes = size_class(std::max<size_t>(count, 1) * sizeof(T));
+    AllocCache &ac = alloc_cache();
+    {
+        std::lock_guard<std::mutex> g(ac.mu);
+        auto it = ac.idle.find(s);
+        if (it != ac.idle.end()) {
+            auto f = it->second.find(bytes);
+            if (f != it->second.end()) {
+                void *p = f->second;
+                it->second.erase(f);
+                ac.idle_bytes[s] -= bytes;
+                ac.live[p] = {s, bytes};
+                return (T *)p;
+            }
+        }
+    }
     void *p = nullptr;
-    if (count == 0) count = 1;
-    hipError_t e = hipMallocAsync(&p, count * sizeof(T), s);
+    hipError_t e = hipMallocAsync(&p, bytes, s);
+    if (e == hipErrorOutOfMemory) {  // give the idle blocks back and try once more
+        (void)hipGetLastError();
+        release_stream_cache(s);
+        e = hipMallocAsync(&p, bytes, s);
+    }
     if (e == hipErrorOutOfMemory) throw StatusError(WENOTT_ENOMEM, "device allocation failed");
     WTT_HIP(e);
+    std::lock_guard<std::mutex> g(ac.mu);
+    ac.live[p] = {s, bytes};
     return (T *)p;
 }
+
 inline void dfree(hipStream_t s, void *p) {
-    if (p) WTT_HIP(hipFreeAsync(p, s));
+    if (!p) return;
+    AllocCache &ac = alloc_cache();
+    {
+        std::lock_guard<std::mutex> g(ac.mu);
+        auto it = ac.live.find(p);
+        if (it != ac.live.end()) {
+            const hipStream_t owner = it->second.first;
+            const size_t bytes = it->second.second;
+            ac.live.erase(it);
+            if (owner == s && ac.idle_bytes[s] + bytes <= kCacheBytes) {
+                ac.idle[s].emplace(bytes, p);
+                ac.idle_bytes[s] += bytes;
+                return;
+            }
+        }
+    }
+    WTT_HIP(hipFreeAsync(p, s));
 }
 
 enum Slot {
@@ -73,7 +163,10 @@ struct Scratch {
     }
     void release() {
         for (int i = 0; i < S_NSLOTS; ++i) {
-            if (p[i]) (void)hipFreeAsync(p[i], s);
+            if (p[i]) {
+                forget_block(p[i]);
+                (void)hipFreeAsync(p[i], s);
+            }
             p[i] = nullptr;
             cap[i] = 0;
         }
@@ -1049,9 +1142,9 @@ int svd_ranks(wenott_ctx *c, int m, int n, const double *A, long long sz, long l
     add_work(c, KC_TSQR, nc * (2.0 * m * (double)n * n - 2.0 / 3.0 * (double)n * n * n), 8.0 * nc * (double)m * n);
     *sig = c->sc.get<double>(S_SIG, (size_t)nc * n);
     *V = c->sc.get<double>(S_V, (size_t)nc * n * n);
-    double *jac = c->sc.get<double>(S_JAC, (size_t)nc * (2 * (size_t)n * n + n));
+    double *jac = c->sc.get<double>(S_JAC, jacobi_scratch_doubles(n, nc));
     ev_record(c, KC_SVD);
-    jacobi_svd(c->s, n, nc, R, *sig, *V, jac, nullptr, rel == 0.0 ? delta_abs : nullptr);
+    jacobi_svd(c->s, n, nc, R, *sig, *V, jac, rel == 0.0 ? delta_abs : nullptr);
     ev_record(c, KC_SVD);
     add_work(c, KC_SVD, 0.0, 8.0 * nc * 3.0 * (double)n * n);
     *rk = c->sc.get<int>(S_RANKS, nc);
@@ -1486,9 +1579,9 @@ void batch_round(std::vector<BState> &bs, std::vector<TT> &Xs) {
             V[z] = c->sc.get<double>(S_V, (size_t)nc * n * n);
             jobs[z] = SvdJob{R, sig[z], V[z], n, nc, ddelta[z]};
             if (!fits) {
-                double *jac = c->sc.get<double>(S_JAC, (size_t)nc * (2 * (size_t)n * n + n));
+                double *jac = c->sc.get<double>(S_JAC, jacobi_scratch_doubles(n, nc));
                 ev_record(c, KC_SVD);
-                jacobi_svd(c->s, n, nc, R, sig[z], V[z], jac, nullptr, ddelta[z]);
+                jacobi_svd(c->s, n, nc, R, sig[z], V[z], jac, ddelta[z]);
                 ev_record(c, KC_SVD);
             }
         }
@@ -1824,6 +1917,7 @@ void wenott_destroy(wenott_ctx *c) {
         c->U.release(c->s);
         if (c->have_rhs) c->rhs.release(c->s);
         c->sc.release();
+        release_stream_cache(c->s);
         (void)hipStreamSynchronize(c->s);
         c->ring.destroy();
         if (c->d_status) (void)hipFree(c->d_status);

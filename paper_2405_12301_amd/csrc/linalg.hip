@@ -404,6 +404,108 @@ __global__ __launch_bounds__(NT) void k_hhqr(int m, int n, int bm, int nblk, con
     }
 }
 
+// Sum over each row of 16 lanes (all 16 active); every lane of the row gets the same bits.
+__device__ __forceinline__ double row_sum16(double v) {
+    v += dpp_d<0xB1>(v);
+    v += dpp_d<0x4E>(v);
+    v += dpp_d<0x141>(v);
+    v += dpp_d<0x140>(v);
+    return v;
+}
+
+// Register-resident Householder QR of a row block with at most 64 columns and 16 RPT rows, one
+// 1024-thread workgroup per block. Lane l of wave w holds column c = 4 w + l / 16 at rows
+// l % 16 + 16 q, q < RPT, for the whole factorisation; per column step only the Householder
+// vector (and tau) passes through LDS, double-buffered by step parity, so one barrier per step.
+// Each row of 16 lanes reduces its dot products with DPP alone. At step j every trailing column
+// is reflected, then its row j (final, an entry of R) moves to the LDS copy of R and is zeroed in
+// the registers, so rows above the current step never enter a sum; the owner of column j + 1
+// then forms the next vector from its registers: alpha = its row j + 1, xn2 = the squared norm
+// below it, beta = -sign(alpha) sqrt(alpha^2 + xn2), tau = (beta - alpha) / beta,
+// v = [1; x / (alpha - beta)]. Rows past the block's end are zeros and stay zeros.
+template <int RPT>
+__device__ __forceinline__ void qr_reg_prep(double (&a)[RPT], int j, int lane, double *__restrict__ vb,
+                                            double *__restrict__ tb, double *__restrict__ Rl) {
+    const int rg = lane & 15, qj = j >> 4, src = __builtin_amdgcn_readfirstlane((lane & 48) | (j & 15));
+    double x = 0.0;
+#pragma unroll
+    for (int q = 0; q < RPT; ++q)
+        if (q == qj) x = a[q];
+    const double alpha = readlane_d(x, src);
+    if (rg == (j & 15)) {
+#pragma unroll
+        for (int q = 0; q < RPT; ++q)
+            if (q == qj) a[q] = 0.0;
+    }
+    double ss = 0.0;
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) ss = fma(a[q], a[q], ss);
+    const double xn2 = row_sum16(ss);
+    double beta, tau, scale;
+    if (xn2 == 0.0) {
+        beta = alpha; tau = 0.0; scale = 0.0;
+    } else {
+        beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+        tau = (beta - alpha) / beta;
+        scale = 1.0 / (alpha - beta);
+    }
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) vb[rg + 16 * q] = a[q] * scale;
+    if (rg == (j & 15)) {
+        vb[j] = 1.0;
+        Rl[j * 64 + j] = beta;
+        *tb = tau;
+    }
+}
+
+template <int RPT>
+__global__ __launch_bounds__(1024) void k_qr_reg(int m, int n, int bm, int nblk, const double *__restrict__ A,
+                                                 long long sz, long long rs, long long cs, double *__restrict__ Rout) {
+    __shared__ double vb[2][16 * RPT];
+    __shared__ double tb[2];
+    __shared__ double Rl[64 * 64];
+    const int blk = blockIdx.x, z = blockIdx.y, tid = threadIdx.x;
+    const int lane = tid % kWave, w = tid / kWave;
+    const int rg = lane & 15, c = 4 * w + (lane >> 4);
+    const int r0 = blk * bm, nr = min(bm, m - r0);
+    const double *Az = A + (long long)z * sz;
+    double a[RPT];
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        const int i = rg + 16 * q;
+        a[q] = (c < n && i < nr) ? Az[(long long)(r0 + i) * rs + (long long)c * cs] : 0.0;
+    }
+    if (c == 0) qr_reg_prep<RPT>(a, 0, lane, vb[0], &tb[0], Rl);
+    __syncthreads();
+    for (int j = 0; j < n; ++j) {
+        if (c > j && c < n) {
+            const double *v = vb[j & 1];
+            double dot = 0.0;
+#pragma unroll
+            for (int q = 0; q < RPT; ++q) dot = fma(v[rg + 16 * q], a[q], dot);
+            const double f = tb[j & 1] * row_sum16(dot);
+#pragma unroll
+            for (int q = 0; q < RPT; ++q) a[q] = fma(-f, v[rg + 16 * q], a[q]);
+            const int qj = j >> 4;
+            if (rg == (j & 15)) {
+#pragma unroll
+                for (int q = 0; q < RPT; ++q)
+                    if (q == qj) {
+                        Rl[j * 64 + c] = a[q];
+                        a[q] = 0.0;
+                    }
+            }
+            if (c == j + 1) qr_reg_prep<RPT>(a, j + 1, lane, vb[(j + 1) & 1], &tb[(j + 1) & 1], Rl);
+        }
+        __syncthreads();
+    }
+    double *R = Rout + ((long long)z * nblk + blk) * (long long)n * n;
+    for (int e = tid; e < n * n; e += 1024) {
+        const int i = e / n, l = e % n;
+        R[e] = i <= l ? Rl[i * 64 + l] : 0.0;
+    }
+}
+
 __global__ void k_sum_chunks(long long per, int nchunk, int batch, const double *__restrict__ part, double *__restrict__ C,
                              int M, int N, int ldc, long long sC) {
     long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
@@ -435,22 +537,28 @@ __device__ inline void circle_pair(int r, int k, int np, int *p, int *q) {
     *q = a < b ? b : a;
 }
 
-// A and V are column-major (column j at j * n); they live in LDS (fast path) or global memory.
-// Squared column norms are recomputed at the start of every sweep and updated through each
-// rotation (a' = a - t c, b' = b + t c), so a pair needs one dot product; nrm holds n doubles.
-// A pair whose cross product is at most eta (an absolute threshold, 0 for none) is also left
-// alone: with eta = 0.01 delta^2 / n, where delta is the truncation threshold of the singular
-// values, the skipped rotations move no singular value by more than 1% of delta, and columns
-// far below delta are not orthogonalised against each other to full relative precision.
-__device__ void jacobi_sweeps(int n, double *A, double *V, int *nrot, double *nrm, double eta) {
+// The SVD of an n x n upper-triangular R (the R factor of a tall matrix C = Q R) is taken by
+// one-sided Jacobi on X = R^T, whose columns are the rows of R: the rotations make the columns
+// of X V_x orthogonal, R^T V_x = U_x Sigma, so C = (Q V_x) Sigma U_x^T and the right singular
+// vectors of C are the normalised final columns of X. The rotations need not be accumulated,
+// and Jacobi on R^T needs about half the sweeps of Jacobi on R (the transposed triangular
+// factor is the classical preconditioning of one-sided Jacobi).
+// X is column-major (column j at j * n), in LDS or global memory. Squared column norms are
+// recomputed at the start of every sweep and updated through each rotation (a' = a - t c,
+// b' = b + t c), so a pair needs one dot product; nrm holds n doubles. A pair whose cross
+// product is at most eta (an absolute threshold, 0 for none) is left alone: with
+// eta = 0.01 delta^2 / n, where delta is the truncation threshold of the singular values, the
+// skipped rotations move no singular value by more than 1% of delta, and columns far below
+// delta are not orthogonalised against each other to full relative precision.
+__device__ void jacobi_sweeps(int n, double *X, int *nrot, double *nrm, double eta) {
     const int tid = threadIdx.x, lane = tid % kWave, w = tid / kWave, nw = blockDim.x / kWave;
     const int np = n + (n & 1);
     const double tol = 1e-15;
     for (int sweep = 0; sweep < 60; ++sweep) {
         for (int j = w; j < n; j += nw) {
-            const double *aj = A + (long long)j * n;
+            const double *xj = X + (long long)j * n;
             double ss = 0.0;
-            for (int i = lane; i < n; i += kWave) ss += aj[i] * aj[i];
+            for (int i = lane; i < n; i += kWave) ss += xj[i] * xj[i];
             ss = wave_sum(ss);
             if (lane == 0) nrm[j] = ss;
         }
@@ -461,9 +569,9 @@ __device__ void jacobi_sweeps(int n, double *A, double *V, int *nrot, double *nr
                 int p, q;
                 circle_pair(r, k, np, &p, &q);
                 if (q >= n) continue;
-                double *ap = A + (long long)p * n, *aq = A + (long long)q * n;
+                double *xp = X + (long long)p * n, *xq = X + (long long)q * n;
                 double c = 0.0;
-                for (int i = lane; i < n; i += kWave) c += ap[i] * aq[i];
+                for (int i = lane; i < n; i += kWave) c += xp[i] * xq[i];
                 c = wave_sum(c);
                 const double a = nrm[p], b = nrm[q];
                 if (c == 0.0 || !(fabs(c) > tol * sqrt(a * b)) || !(fabs(c) > eta)) continue;
@@ -473,20 +581,14 @@ __device__ void jacobi_sweeps(int n, double *A, double *V, int *nrot, double *nr
                 const double t = copysign(1.0, dd) * (2.0 * c) / (fabs(dd) + sqrt(dd * dd + 4.0 * c * c));
                 const double cs = rsqrt(1.0 + t * t), sn = cs * t;
                 for (int i = lane; i < n; i += kWave) {
-                    double x = ap[i], y = aq[i];
-                    ap[i] = cs * x - sn * y;
-                    aq[i] = sn * x + cs * y;
-                }
-                double *vp = V + (long long)p * n, *vq = V + (long long)q * n;
-                for (int i = lane; i < n; i += kWave) {
-                    double x = vp[i], y = vq[i];
-                    vp[i] = cs * x - sn * y;
-                    vq[i] = sn * x + cs * y;
+                    const double x = xp[i], y = xq[i];
+                    xp[i] = cs * x - sn * y;
+                    xq[i] = sn * x + cs * y;
                 }
                 if (lane == 0) {
                     nrm[p] = fmax(a - t * c, 0.0);
                     nrm[q] = b + t * c;
-                    atomicAdd(nrot, 1);
+                    *nrot = 1;  // every writer stores the same value
                 }
             }
             __syncthreads();
@@ -497,26 +599,27 @@ __device__ void jacobi_sweeps(int n, double *A, double *V, int *nrot, double *nr
     }
 }
 
-// Singular values (column norms), descending order by rank counting; writes sigma, V (row-major,
-// column = singular vector) and, if US != null, A V = U Sigma (row-major).
-__device__ void jacobi_finish(int n, const double *A, const double *V, double *sig_tmp, double *sigma,
-                              double *Vout, double *US) {
+// Singular values = final column norms of X, descending by rank counting (ties to the lower
+// column); the right singular vectors of C are the normalised columns (row-major V, column pos
+// = singular vector pos; a zero column gives a zero vector, whose singular value 0 is never
+// kept by the truncation).
+__device__ void jacobi_finish(int n, const double *X, double *sig_tmp, double *sigma, double *Vout) {
     const int tid = threadIdx.x, lane = tid % kWave, w = tid / kWave, nw = blockDim.x / kWave;
     for (int j = w; j < n; j += nw) {
         double s = 0.0;
-        for (int i = lane; i < n; i += kWave) s += A[(long long)j * n + i] * A[(long long)j * n + i];
+        for (int i = lane; i < n; i += kWave) s += X[(long long)j * n + i] * X[(long long)j * n + i];
         s = wave_sum(s);
         if (lane == 0) sig_tmp[j] = sqrt(s);
     }
     __syncthreads();
-    for (int j = tid; j < n; j += blockDim.x) {
-        double sj = sig_tmp[j];
+    for (int j = w; j < n; j += nw) {
+        const double sj = sig_tmp[j];
         int pos = 0;
-        for (int i = 0; i < n; ++i) pos += (sig_tmp[i] > sj) || (sig_tmp[i] == sj && i < j);
-        sigma[pos] = sj;
-        for (int i = 0; i < n; ++i) Vout[(long long)i * n + pos] = V[(long long)j * n + i];
-        if (US)
-            for (int i = 0; i < n; ++i) US[(long long)i * n + pos] = A[(long long)j * n + i];
+        for (int i = lane; i < n; i += kWave) pos += (sig_tmp[i] > sj) || (sig_tmp[i] == sj && i < j);
+        pos = (int)wave_sum((double)pos);
+        const double inv = sj > 0.0 ? 1.0 / sj : 0.0;
+        if (lane == 0) sigma[pos] = sj;
+        for (int i = lane; i < n; i += kWave) Vout[(long long)i * n + pos] = X[(long long)j * n + i] * inv;
     }
 }
 
@@ -524,67 +627,33 @@ __device__ __forceinline__ double jacobi_eta(const double *delta, int z, int n) 
     return delta ? 0.01 * delta[z] * delta[z] / n : 0.0;
 }
 
-__global__ __launch_bounds__(1024) void k_jacobi_lds(int n, const double *__restrict__ Ain, double *__restrict__ sigma,
-                                                     double *__restrict__ Vout, double *__restrict__ US,
-                                                     const double *__restrict__ delta) {
-    extern __shared__ double sm[];
+// One workgroup per matrix; X = R^T is a plain copy of the row-major R (column j = row j).
+__global__ __launch_bounds__(1024) void k_jacobi_lds(int n, const double *__restrict__ Rin, double *__restrict__ sigma,
+                                                     double *__restrict__ Vout, const double *__restrict__ delta) {
+    extern __shared__ double X[];
     __shared__ int nrot;
     __shared__ double sig_tmp[512];
     const int z = blockIdx.x, tid = threadIdx.x;
-    double *A = sm, *V = sm + (long long)n * n;
-    const double *Az = Ain + (long long)z * n * n;
-    for (int e = tid; e < n * n; e += blockDim.x) {
-        int i = e / n, j = e % n;
-        A[j * n + i] = Az[e];
-        V[j * n + i] = (i == j) ? 1.0 : 0.0;
-    }
+    const double *Rz = Rin + (long long)z * n * n;
+    for (int e = tid; e < n * n; e += blockDim.x) X[e] = Rz[e];
     __syncthreads();
-    jacobi_sweeps(n, A, V, &nrot, sig_tmp, jacobi_eta(delta, z, n));
-    jacobi_finish(n, A, V, sig_tmp, sigma + (long long)z * n, Vout + (long long)z * n * n,
-                  US ? US + (long long)z * n * n : nullptr);
+    jacobi_sweeps(n, X, &nrot, sig_tmp, jacobi_eta(delta, z, n));
+    jacobi_finish(n, X, sig_tmp, sigma + (long long)z * n, Vout + (long long)z * n * n);
 }
 
-__global__ __launch_bounds__(1024) void k_jacobi_global(int n, const double *__restrict__ Ain,
+__global__ __launch_bounds__(1024) void k_jacobi_global(int n, const double *__restrict__ Rin,
                                                         double *__restrict__ sigma, double *__restrict__ Vout,
-                                                        double *__restrict__ US, double *__restrict__ scratch,
+                                                        double *__restrict__ scratch,
                                                         const double *__restrict__ delta) {
     __shared__ int nrot;
     const int z = blockIdx.x, tid = threadIdx.x;
-    double *A = scratch + (long long)z * (2 * (long long)n * n + n);
-    double *V = A + (long long)n * n;
-    double *sig_tmp = V + (long long)n * n;
-    const double *Az = Ain + (long long)z * n * n;
-    for (long long e = tid; e < (long long)n * n; e += blockDim.x) {
-        int i = (int)(e / n), j = (int)(e % n);
-        A[(long long)j * n + i] = Az[e];
-        V[(long long)j * n + i] = (i == j) ? 1.0 : 0.0;
-    }
+    double *X = scratch + (long long)z * ((long long)n * n + n);
+    double *sig_tmp = X + (long long)n * n;
+    const double *Rz = Rin + (long long)z * n * n;
+    for (long long e = tid; e < (long long)n * n; e += blockDim.x) X[e] = Rz[e];
     __syncthreads();
-    jacobi_sweeps(n, A, V, &nrot, sig_tmp, jacobi_eta(delta, z, n));
-    jacobi_finish(n, A, V, sig_tmp, sigma + (long long)z * n, Vout + (long long)z * n * n,
-                  US ? US + (long long)z * n * n : nullptr);
-}
-
-// A in LDS, V and the norms in global scratch: for n whose A and V together exceed LDS.
-__global__ __launch_bounds__(1024) void k_jacobi_hybrid(int n, const double *__restrict__ Ain,
-                                                        double *__restrict__ sigma, double *__restrict__ Vout,
-                                                        double *__restrict__ US, double *__restrict__ scratch,
-                                                        const double *__restrict__ delta) {
-    extern __shared__ double A[];
-    __shared__ int nrot;
-    const int z = blockIdx.x, tid = threadIdx.x;
-    double *V = scratch + (long long)z * (2 * (long long)n * n + n) + (long long)n * n;
-    double *sig_tmp = V + (long long)n * n;
-    const double *Az = Ain + (long long)z * n * n;
-    for (long long e = tid; e < (long long)n * n; e += blockDim.x) {
-        int i = (int)(e / n), j = (int)(e % n);
-        A[(long long)j * n + i] = Az[e];
-        V[(long long)j * n + i] = (i == j) ? 1.0 : 0.0;
-    }
-    __syncthreads();
-    jacobi_sweeps(n, A, V, &nrot, sig_tmp, jacobi_eta(delta, z, n));
-    jacobi_finish(n, A, V, sig_tmp, sigma + (long long)z * n, Vout + (long long)z * n * n,
-                  US ? US + (long long)z * n * n : nullptr);
+    jacobi_sweeps(n, X, &nrot, sig_tmp, jacobi_eta(delta, z, n));
+    jacobi_finish(n, X, sig_tmp, sigma + (long long)z * n, Vout + (long long)z * n * n);
 }
 
 // ------------------------------------------------------------------- prrLU (pivots)
@@ -635,15 +704,18 @@ __device__ __forceinline__ void prrlu_mw_init_body(const PrrluJob &J) {
 }
 
 // Workgroup b owns a stripe of J.rows = RS * kMwK rows; thread (tr, tc) holds the kMwTW columns
-// [8 tc, 8 tc + 8) of rows r0 + tr + k RS, k < kMwK, with RS = 256 / ceil(n / 8).
+// [8 tc, 8 tc + 8) of rows r0 + tr + k RS, k < kMwK, with RS = 256 / ceil(n / 8). The stripe is
+// loaded before the decision (it does not depend on it); the candidate row a workgroup leaves
+// for the next launch comes from the registers of the threads that hold it.
+constexpr int kMwCand = 2048;  // doubles: the widest pivot row (n <= 256 * 8)
+
 __device__ __forceinline__ void prrlu_mw_step_body(const PrrluJob &J, int t) {
     __shared__ double lc[kMwThreads * kMwK];
-    __shared__ double u[kMwThreads * kMwTW];  // the pivot row (prrlu_prepare enforces n <= this)
+    __shared__ double u[kMwCand];
     __shared__ double wmax[kMwThreads / kWave], wsum[kMwThreads / kWave];
     __shared__ long long widx[kMwThreads / kWave];
     __shared__ int s_stop, s_wk;
-    __shared__ long long s_gi;
-    __shared__ double s_gs;
+    __shared__ long long s_gi, s_bi;
     const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave;
     const int m = J.m, n = J.n, rmax = J.rmax;
     const PrrluWs w = prrlu_ws_split(J.ws, n, J.nblk);
@@ -655,7 +727,16 @@ __device__ __forceinline__ void prrlu_mw_step_body(const PrrluJob &J, int t) {
     const bool active = tr < RS;
     const int r0 = blockIdx.x * J.rows;
     const int cur = t & 1, prev = cur ^ 1;
+    double a[kMwK][kMwTW];
+#pragma unroll
+    for (int k = 0; k < kMwK; ++k) {
+        const int row = r0 + tr + k * RS;
+        const bool rv = active && row < m;
+#pragma unroll
+        for (int j = 0; j < kMwTW; ++j) a[k][j] = (rv && c0 + j < n) ? A[(long long)row * n + c0 + j] : 0.0;
+    }
     int pi = -1, pj = -1;
+    const double *urow = u;  // the pivot row
     if (t > 0) {
         // decide pivot t - 1 from the previous launch's partials (the same in every workgroup)
         double bm = -1.0, bs = 0.0;
@@ -682,7 +763,6 @@ __device__ __forceinline__ void prrlu_mw_step_body(const PrrluJob &J, int t) {
             if (tp == 0 && stop == 1) stop = 0;  // always take at least one pivot of a nonzero block
             s_stop = stop;
             s_gi = gi;
-            s_gs = gs;
             s_wk = gm > 0.0 ? (int)((gi / n) / J.rows) : 0;  // the workgroup whose stripe holds the row
             if (blockIdx.x == 0) {
                 if (tp == 0) w.ctl->tol2 = tol2;
@@ -710,18 +790,10 @@ __device__ __forceinline__ void prrlu_mw_step_body(const PrrluJob &J, int t) {
         }
         pi = (int)(s_gi / n);
         pj = (int)(s_gi % n);
-        const double *prow = w.prow[prev] + (long long)s_wk * n;
-        for (int j = tid; j < n; j += kMwThreads) u[j] = prow[j];
-    }
-    double a[kMwK][kMwTW];
-#pragma unroll
-    for (int k = 0; k < kMwK; ++k) {
-        const int row = r0 + tr + k * RS;
-        const bool rv = active && row < m;
-#pragma unroll
-        for (int j = 0; j < kMwTW; ++j) a[k][j] = (rv && c0 + j < n) ? A[(long long)row * n + c0 + j] : 0.0;
-    }
-    if (t > 0) {
+        {
+            const double *prow = w.prow[prev] + (long long)s_wk * n;
+            for (int j = tid; j < n; j += kMwThreads) u[j] = prow[j];
+        }
         if (active && pj >= c0 && pj < c0 + kMwTW) {  // the pivot column's owners publish it
 #pragma unroll
             for (int j = 0; j < kMwTW; ++j)
@@ -730,11 +802,11 @@ __device__ __forceinline__ void prrlu_mw_step_body(const PrrluJob &J, int t) {
                     for (int k = 0; k < kMwK; ++k) lc[tr + k * RS] = a[k][j];
         }
         __syncthreads();
-        const double inv = 1.0 / u[pj];
+        const double inv = 1.0 / urow[pj];
         if (active) {
             double uu[kMwTW];
 #pragma unroll
-            for (int j = 0; j < kMwTW; ++j) uu[j] = c0 + j < n ? u[c0 + j] : 0.0;
+            for (int j = 0; j < kMwTW; ++j) uu[j] = c0 + j < n ? urow[c0 + j] : 0.0;
 #pragma unroll
             for (int k = 0; k < kMwK; ++k) {
                 const int row = r0 + tr + k * RS;
@@ -782,7 +854,7 @@ __device__ __forceinline__ void prrlu_mw_step_body(const PrrluJob &J, int t) {
     }
     if (!active) { lmax = -1.0; lsum = 0.0; }
     wave_amax_sum(lmax, lidx, lsum);
-    __syncthreads();  // every thread is done with lc and u of this step
+    // wmax / widx / wsum were last read by thread 0 before the barriers above
     if (lane == 0) { wmax[wv] = lmax; widx[wv] = lidx; wsum[wv] = lsum; }
     __syncthreads();
     if (tid == 0) {
@@ -795,15 +867,23 @@ __device__ __forceinline__ void prrlu_mw_step_body(const PrrluJob &J, int t) {
         w.pmax[cur][blockIdx.x] = bm;
         w.psum[cur][blockIdx.x] = bs;
         w.pidx[cur][blockIdx.x] = bi;
-        s_gi = bi;
+        s_bi = bi;
     }
     __syncthreads();
-    // the candidate pivot row: the whole row of this stripe's largest entry, as just written
-    // by this workgroup (its own rows, so no other workgroup touches it in this launch)
-    if (s_gi != 0x7fffffffffffffffLL) {
-        const long long rowbase = (s_gi / n) * (long long)n;
-        double *dst = w.prow[cur] + (long long)blockIdx.x * n;
-        for (int j = tid; j < n; j += kMwThreads) dst[j] = A[rowbase + j];
+    // the candidate pivot row: the whole row of this stripe's largest entry, from the registers
+    // of the threads that hold it (a real row: ties go to the lowest index, and the stripe's
+    // first entry is real)
+    if (s_bi != 0x7fffffffffffffffLL && active) {
+        const int local = (int)(s_bi / n) - r0;
+        if (local % RS == tr) {
+            double *dst = w.prow[cur] + (long long)blockIdx.x * n;
+#pragma unroll
+            for (int k = 0; k < kMwK; ++k)
+                if (k == local / RS)
+#pragma unroll
+                    for (int j = 0; j < kMwTW; ++j)
+                        if (c0 + j < n) dst[c0 + j] = a[k][j];
+        }
     }
 }
 
@@ -1094,22 +1174,17 @@ __global__ __launch_bounds__(256) void k_chol_inv_batch(const CholJob *__restric
 
 // grid (jobs, components): one-sided Jacobi of the n_j x n_j matrices of a batch of jobs in LDS
 __global__ __launch_bounds__(1024) void k_jacobi_lds_batch(const SvdJob *__restrict__ jobs) {
-    extern __shared__ double sm[];
+    extern __shared__ double X[];
     __shared__ int nrot;
     __shared__ double sig_tmp[512];
     const SvdJob j = jobs[blockIdx.x];
     if ((int)blockIdx.y >= j.batch) return;
     const int n = j.n, z = blockIdx.y, tid = threadIdx.x;
-    double *A = sm, *V = sm + (long long)n * n;
-    const double *Az = j.A + (long long)z * n * n;
-    for (int e = tid; e < n * n; e += blockDim.x) {
-        int i = e / n, jj = e % n;
-        A[jj * n + i] = Az[e];
-        V[jj * n + i] = (i == jj) ? 1.0 : 0.0;
-    }
+    const double *Rz = j.A + (long long)z * n * n;
+    for (int e = tid; e < n * n; e += blockDim.x) X[e] = Rz[e];
     __syncthreads();
-    jacobi_sweeps(n, A, V, &nrot, sig_tmp, jacobi_eta(j.delta, z, n));
-    jacobi_finish(n, A, V, sig_tmp, j.sigma + (long long)z * n, j.V + (long long)z * n * n, nullptr);
+    jacobi_sweeps(n, X, &nrot, sig_tmp, jacobi_eta(j.delta, z, n));
+    jacobi_finish(n, X, sig_tmp, j.sigma + (long long)z * n, j.V + (long long)z * n * n);
 }
 
 inline unsigned cdiv(long long a, long long b) { return (unsigned)((a + b - 1) / b); }
@@ -1347,8 +1422,38 @@ void launch_hhqr(hipStream_t s, int nblk, int batch, bool lds, int m, int n, int
     WTT_HIP(hipGetLastError());
 }
 
+constexpr int kQrRegCols = 64, kQrRegRows = 256;  // 16 rows per lane at most (no spills)
+
+void launch_qr_reg(hipStream_t s, int nblk, int batch, int m, int n, int bm, const double *A, long long sz,
+                   long long rs, long long cs, double *Rout) {
+    const int rows = std::max(bm, n);
+    const dim3 grid(nblk, batch);
+    WTT_REQUIRE(n <= kQrRegCols && rows <= kQrRegRows, WENOTT_EINVAL, "register QR block too large");
+    if (rows <= 64) k_qr_reg<4><<<grid, 1024, 0, s>>>(m, n, bm, nblk, A, sz, rs, cs, Rout);
+    else if (rows <= 128) k_qr_reg<8><<<grid, 1024, 0, s>>>(m, n, bm, nblk, A, sz, rs, cs, Rout);
+    else k_qr_reg<16><<<grid, 1024, 0, s>>>(m, n, bm, nblk, A, sz, rs, cs, Rout);
+    WTT_HIP(hipGetLastError());
+}
+
 void tsqr_r(hipStream_t s, int m, int n, int batch, const double *A, long long sz, long long rs, long long cs,
             double *R, double *scratch) {
+    if (n <= kQrRegCols) {
+        // register-resident leaves of up to 256 rows, then nodes of up to 256 stacked rows; the
+        // two R buffers fit in what tsqr_scratch_doubles reserves for the general plan's R buffers
+        int nblk = (m + kQrRegRows - 1) / kQrRegRows;
+        const int bm = std::min(m, kQrRegRows);
+        double *cur = scratch, *nxt = scratch + (long long)batch * nblk * n * n;
+        launch_qr_reg(s, nblk, batch, m, n, bm, A, sz, rs, cs, nblk == 1 ? R : cur);
+        const int group = std::max(2, kQrRegRows / n);
+        while (nblk > 1) {
+            const int nb2 = (nblk + group - 1) / group;
+            const int bm2 = std::min(group, nblk) * n;
+            launch_qr_reg(s, nb2, batch, nblk * n, n, bm2, cur, (long long)nblk * n * n, n, 1, nb2 == 1 ? R : nxt);
+            std::swap(cur, nxt);
+            nblk = nb2;
+        }
+        return;
+    }
     const TsqrPlan p = tsqr_plan(m, n);
     int nblk = p.nblk;
     double *W = scratch;
@@ -1375,25 +1480,25 @@ void tsqr_r(hipStream_t s, int m, int n, int batch, const double *A, long long s
     }
 }
 
-void jacobi_svd(hipStream_t s, int n, int batch, const double *A, double *sigma, double *V, double *scratch,
-                double *US, const double *delta) {
+void jacobi_svd(hipStream_t s, int n, int batch, const double *R, double *sigma, double *V, double *scratch,
+                const double *delta) {
     // static LDS of the kernel: the column-norm buffer (512 doubles) and a counter
-    size_t lds = sizeof(double) * 2 * (size_t)n * n;
-    const size_t lds_a = sizeof(double) * (size_t)n * n;
+    const size_t lds = sizeof(double) * (size_t)n * n;
     if (n <= 512 && lds + 512 * sizeof(double) + 64 <= (size_t)lds_limit_bytes())
-        k_jacobi_lds<<<batch, 1024, lds, s>>>(n, A, sigma, V, US, delta);
-    else if (lds_a + 64 <= (size_t)lds_limit_bytes())
-        k_jacobi_hybrid<<<batch, 1024, lds_a, s>>>(n, A, sigma, V, US, scratch, delta);
+        k_jacobi_lds<<<batch, 1024, lds, s>>>(n, R, sigma, V, delta);
     else
-        k_jacobi_global<<<batch, 1024, 0, s>>>(n, A, sigma, V, US, scratch, delta);
+        k_jacobi_global<<<batch, 1024, 0, s>>>(n, R, sigma, V, scratch, delta);
     WTT_HIP(hipGetLastError());
 }
+
+size_t jacobi_scratch_doubles(int n, int batch) { return (size_t)batch * ((size_t)n * n + n); }
 
 void prrlu_prepare(PrrluJob &j) {
     j.shape = tile_shape_for(j.m, j.n);
     j.mode = j.shape >= 0 ? 0 : 1;
     const int tpr = (j.n + kMwTW - 1) / kMwTW;
-    WTT_REQUIRE(tpr <= kMwThreads, WENOTT_EINVAL, "pivot block wider than the multi-workgroup form supports");
+    WTT_REQUIRE(tpr <= kMwThreads && j.n <= kMwCand, WENOTT_EINVAL,
+                "pivot block wider than the multi-workgroup form supports");
     j.rows = (kMwThreads / tpr) * kMwK;
     j.nblk = (j.m + j.rows - 1) / j.rows;
 }
@@ -1496,13 +1601,13 @@ void prrlu_batch(hipStream_t s, int njobs, const PrrluJob *host_jobs, const Prrl
 }
 
 bool jacobi_batch_fits(int nmax) {
-    const size_t lds = sizeof(double) * 2 * (size_t)nmax * nmax;
+    const size_t lds = sizeof(double) * (size_t)nmax * nmax;
     return nmax <= 512 && lds + 512 * sizeof(double) + 64 <= (size_t)lds_limit_bytes();
 }
 
 void jacobi_svd_batch(hipStream_t s, int njobs, int ncomp, int nmax, const SvdJob *dev_jobs) {
     if (njobs <= 0) return;
-    const size_t lds = sizeof(double) * 2 * (size_t)nmax * nmax;
+    const size_t lds = sizeof(double) * (size_t)nmax * nmax;
     k_jacobi_lds_batch<<<dim3(njobs, ncomp), 1024, lds, s>>>(dev_jobs);
     WTT_HIP(hipGetLastError());
 }
