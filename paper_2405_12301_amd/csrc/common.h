@@ -98,7 +98,8 @@ size_t jacobi_scratch_doubles(int n, int batch);
 // registers). That form runs one launch per step, launch t deciding pivot t - 1 and eliminating
 // it: this call launches steps t_begin..min(t_end, rmax + 1) and returns the next step; info[0]
 // stays negative until the factorisation has stopped, and the caller continues from the
-// returned step. The register form finishes in one call (t_begin = 0). Needs rmax >= 1.
+// returned step. The register form and the persistent form finish in one call (t_begin = 0);
+// info[0] = -2 reports a persistent launch whose grid barrier wait ran out. Needs rmax >= 1.
 int prrlu(hipStream_t s, int m, int n, double *A, int rmax, double rel_tol2, int *rowpiv, int *colpiv, double *L,
           double *info, double *ws, int t_begin, int t_end);
 size_t prrlu_ws_doubles(int m, int n);
@@ -115,8 +116,9 @@ struct PrrluJob {
     double rel_tol2;
     int *rowpiv, *colpiv;
     double *L, *info, *ws;  // ws: prrlu_ws_doubles(m, n) doubles
-    // set by prrlu_prepare: 0 single-workgroup register tiles (shape: tile shape id) or 1
-    // multi-workgroup (rows per workgroup, workgroups)
+    // set by prrlu_prepare: 0 single-workgroup register tiles (shape: tile shape id), 1
+    // multi-workgroup (rows per workgroup, workgroups) stepped one launch per pivot, 2 the same
+    // layout in one persistent launch (when the workgroups can all be resident)
     int mode, shape, rows, nblk;
 };
 void prrlu_prepare(PrrluJob &j);

@@ -544,7 +544,9 @@ PivotResult pivots(wenott_ctx *c, double *B, int m, int n, double rel_tol2, doub
         WTT_HIP(hipMemcpyAsync(c->h_pinned_int, piv, pivot_info_offset(rmax) + 2 * sizeof(double),
                                hipMemcpyDeviceToHost, c->s));
         WTT_HIP(hipStreamSynchronize(c->s));
-        if (pinned_pivot_info(c, rmax, 0) >= 0.0) break;
+        const double state = pinned_pivot_info(c, rmax, 0);
+        if (state >= 0.0) break;
+        WTT_REQUIRE(state != -2.0, WENOTT_EHIP, "pivot search: grid barrier wait ran out");
         WTT_REQUIRE(next <= rmax + 1, WENOTT_EHIP, "pivot search did not stop");
         ev_record(c, KC_PIVOT);
         next = prrlu(c->s, m, n, B, rmax, rel_tol2, piv, piv + rmax, L, info, ws, next, next + std::max(8, next / 2));
@@ -741,7 +743,12 @@ FluxTT cross_generic(wenott_ctx *c, const CrossTarget &t, double eps, CrossStat 
     std::vector<ISet> Rset(d);
     Rset[d - 1].len = 0;
     Rset[d - 1].count = 1;
-    if (c->warm_valid[t.warm_slot]) {
+    // Without the previous cross's index sets the right sets start random, and a feature that
+    // is localised in every mode (the first update of a discontinuity crossing, say) can fall
+    // between them and between the sampled points alike; such a cold start always takes the
+    // refresh sweep, whose right sets come from the pivot rows of the first sweep.
+    const bool cold = !c->warm_valid[t.warm_slot];
+    if (!cold) {
         Rset = c->warm[t.warm_slot];
     } else {
         for (int k = 0; k < d - 1; ++k) Rset[k] = random_set(rng, t.q0, k + 1, d - 1 - k, M);
@@ -809,7 +816,7 @@ FluxTT cross_generic(wenott_ctx *c, const CrossTarget &t, double eps, CrossStat 
             }
         }
         resid = t.residual(F, rng);
-        if (resid <= eps || sweep + 1 == c->o.max_sweeps) { ++sweep; break; }
+        if ((resid <= eps && !(cold && sweep == 0)) || sweep + 1 == c->o.max_sweeps) { ++sweep; break; }
         // right-to-left sweep: refresh the right index sets from the new left ones
         for (int k = d - 1; k >= 1; --k) {
             ISet Lk = with_kick(Lset[k], rng, kick, 0, M);
@@ -1307,7 +1314,7 @@ struct BState {
     Rng rng{0};
     double rel2 = 0.0, resid = 1e300;
     int sweep = 0;
-    bool active = true;
+    bool active = true, cold = false;
     // per-core pivots of the batched pivot phase
     double *B = nullptr, *L = nullptr;
     int *piv = nullptr;
@@ -1335,7 +1342,7 @@ void batch_pivots(std::vector<BState *> &act, int dir, int k) {
         j.rowpiv = b->piv; j.colpiv = b->piv + b->rmax; j.L = b->L; j.info = b->info;
         j.ws = c->sc.get<double>(S_ROWBUF, prrlu_ws_doubles(b->m, b->n));
         prrlu_prepare(j);
-        if (j.mode == 1) t_end = std::max(t_end, pivot_guess(c, hist_index(kMaxDim, dir, k), b->n, b->rmax) + 1);
+        if (j.mode >= 1) t_end = std::max(t_end, pivot_guess(c, hist_index(kMaxDim, dir, k), b->n, b->rmax) + 1);
         jobs.push_back(j);
     }
     int t_begin = 0;
@@ -1356,11 +1363,14 @@ void batch_pivots(std::vector<BState *> &act, int dir, int k) {
         WTT_HIP(hipStreamSynchronize(c0->s));
         std::vector<size_t> still;
         int rmax_open = 0;
-        for (size_t z : open)
-            if (pinned_pivot_info(act[z]->c, act[z]->rmax, 0) < 0.0) {
+        for (size_t z : open) {
+            const double state = pinned_pivot_info(act[z]->c, act[z]->rmax, 0);
+            WTT_REQUIRE(state != -2.0, WENOTT_EHIP, "pivot search: grid barrier wait ran out");
+            if (state < 0.0) {
                 still.push_back(z);
                 rmax_open = std::max(rmax_open, act[z]->rmax);
             }
+        }
         if (still.empty()) break;
         t_begin = t_end + 1;
         WTT_REQUIRE(t_begin <= rmax_open + 1, WENOTT_EHIP, "pivot search did not stop");
@@ -1386,7 +1396,8 @@ void batch_cross(std::vector<BState> &bs, const double *aw, const double *bw, in
         b.Rset.assign(d, ISet());
         b.Rset[d - 1].len = 0;
         b.Rset[d - 1].count = 1;
-        if (c->warm_valid[kMaxDim]) b.Rset = c->warm[kMaxDim];
+        b.cold = !c->warm_valid[kMaxDim];  // as in the single-state cross: a cold start takes the refresh sweep
+        if (!b.cold) b.Rset = c->warm[kMaxDim];
         else
             for (int k = 0; k < d - 1; ++k) b.Rset[k] = random_set(b.rng, std::max(2, b.X.maxrank()), k + 1, d - 1 - k, b.M);
         b.Lset.assign(d, ISet());
@@ -1458,7 +1469,7 @@ void batch_cross(std::vector<BState> &bs, const double *aw, const double *bw, in
         for (BState *b : act) {
             b->resid = sampled_residual_finish(b->c, b->nb_acc);
             b->sweep = sweep + 1;
-            if (b->resid <= b->ceps || sweep + 1 == max_sweeps) b->active = false;
+            if ((b->resid <= b->ceps && !(b->cold && sweep == 0)) || sweep + 1 == max_sweeps) b->active = false;
             else refresh.push_back(b);
         }
         // right-to-left refresh of the states that missed eps

@@ -671,7 +671,10 @@ __global__ __launch_bounds__(1024) void k_jacobi_global(int n, const double *__r
 // let it go on and take the same stop decision itself.
 struct PrrluCtl {
     double tol2;
-    int stop_launch, pad;
+    int stop_launch;
+    unsigned bar;  // grid barrier arrivals of the persistent form
+    int fail;      // set by a workgroup of the persistent form whose barrier wait ran out
+    int pad;
 };
 
 struct PrrluWs {
@@ -700,6 +703,8 @@ __device__ __forceinline__ void prrlu_mw_init_body(const PrrluJob &J) {
     const PrrluWs w = prrlu_ws_split(J.ws, J.n, J.nblk);
     w.ctl->stop_launch = 0;
     w.ctl->tol2 = 0.0;
+    w.ctl->bar = 0u;
+    w.ctl->fail = 0;
     J.info[0] = -1.0;  // not finished: the host launches further steps
 }
 
@@ -887,18 +892,221 @@ __device__ __forceinline__ void prrlu_mw_step_body(const PrrluJob &J, int t) {
     }
 }
 
+// Persistent form, for blocks of at most kCoopMaxBlk stripes: one launch for the whole
+// factorisation, each stripe held in registers throughout (the same layout as above). It is
+// launched only when the device holds all its workgroups at once (the grid is at most the
+// occupancy times the compute units); a plain launch is used, since the cooperative launch API
+// costs about 0.1 ms of host time per call. Workgroups are dispatched in order, so even a grid
+// that other work keeps partly waiting makes progress as slots free up. Per pivot step every workgroup publishes the
+// partials and candidate row of its residual (double-buffered by step parity), all meet at a
+// grid barrier (a counter with device-scope release / acquire atomics), and each then takes the
+// same decision from the partials, reads the winning row and eliminates it from its stripe. Two
+// buffers and one barrier per step suffice: a buffer is written again two steps later, after
+// the next barrier, which no workgroup passes before every workgroup has read it. The barrier
+// wait is bounded: after kCoopSpin polls a workgroup marks the job failed and leaves (info[0] =
+// -2), and the others leave at their next poll.
+constexpr int kCoopMaxBlk = 64;
+constexpr int kCoopSpin = 1 << 22;
+
+__device__ __forceinline__ bool coop_grid_sync(PrrluCtl *ctl, unsigned target) {
+    __hip_atomic_fetch_add(&ctl->bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    for (int sp = 0; sp < kCoopSpin; ++sp) {
+        if (__hip_atomic_load(&ctl->bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= target) return true;
+        if (__hip_atomic_load(&ctl->fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
+        __builtin_amdgcn_s_sleep(1);
+    }
+    __hip_atomic_store(&ctl->fail, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return false;
+}
+
+__device__ __forceinline__ void prrlu_coop_body(const PrrluJob &J) {
+    __shared__ double lc[kMwThreads * kMwK];
+    __shared__ double u[kMwCand];
+    __shared__ double wmax[kMwThreads / kWave], wsum[kMwThreads / kWave];
+    __shared__ long long widx[kMwThreads / kWave];
+    __shared__ int s_stop, s_wk, s_ok;
+    __shared__ long long s_gi, s_bi;
+    const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave;
+    const int m = J.m, n = J.n, rmax = J.rmax, G = J.nblk;
+    const PrrluWs w = prrlu_ws_split(J.ws, n, J.nblk);
+    const int tpr = (n + kMwTW - 1) / kMwTW, RS = kMwThreads / tpr;
+    const int tr = tid / tpr, tc = tid % tpr, c0 = tc * kMwTW;
+    const bool active = tr < RS;
+    const int r0 = blockIdx.x * J.rows;
+    double a[kMwK][kMwTW];
+#pragma unroll
+    for (int k = 0; k < kMwK; ++k) {
+        const int row = r0 + tr + k * RS;
+        const bool rv = active && row < m;
+#pragma unroll
+        for (int j = 0; j < kMwTW; ++j) a[k][j] = (rv && c0 + j < n) ? J.A[(long long)row * n + c0 + j] : 0.0;
+    }
+    double tol2 = 0.0;  // thread 0: every workgroup forms the same value from the same partials
+    for (int t = 0;; ++t) {
+        const int cur = t & 1;
+        // partials of the residual after t pivots, and this stripe's candidate row
+        double lmax = -1.0, lsum = 0.0;
+        long long lidx = 0x7fffffffffffffffLL;
+#pragma unroll
+        for (int k = 0; k < kMwK; ++k) {
+            const long long rb = (long long)(r0 + tr + k * RS) * n + c0;
+#pragma unroll
+            for (int j = 0; j < kMwTW; ++j) {
+                const double v = a[k][j], av = fabs(v);
+                lsum = fma(v, v, lsum);
+                const bool gt = av > lmax;
+                lmax = gt ? av : lmax;
+                lidx = gt ? rb + j : lidx;
+            }
+        }
+        if (!active) { lmax = -1.0; lsum = 0.0; }
+        wave_amax_sum(lmax, lidx, lsum);
+        if (lane == 0) { wmax[wv] = lmax; widx[wv] = lidx; wsum[wv] = lsum; }
+        __syncthreads();
+        if (tid == 0) {
+            double bm = wmax[0], bs = 0.0;
+            long long bi = widx[0];
+            for (int k = 0; k < kMwThreads / kWave; ++k) {
+                bs += wsum[k];
+                amax_merge(bm, bi, wmax[k], widx[k]);
+            }
+            w.pmax[cur][blockIdx.x] = bm;
+            w.psum[cur][blockIdx.x] = bs;
+            w.pidx[cur][blockIdx.x] = bi;
+            s_bi = bi;
+        }
+        __syncthreads();
+        if (s_bi != 0x7fffffffffffffffLL && active) {
+            const int local = (int)(s_bi / n) - r0;
+            if (local % RS == tr) {
+                double *dst = w.prow[cur] + (long long)blockIdx.x * n;
+#pragma unroll
+                for (int k = 0; k < kMwK; ++k)
+                    if (k == local / RS)
+#pragma unroll
+                        for (int j = 0; j < kMwTW; ++j)
+                            if (c0 + j < n) dst[c0 + j] = a[k][j];
+            }
+        }
+        __syncthreads();  // this workgroup's stores are done before thread 0 releases them
+        if (tid == 0) s_ok = coop_grid_sync(w.ctl, (unsigned)(t + 1) * (unsigned)G);
+        __syncthreads();
+        if (!s_ok) {
+            if (tid == 0) J.info[0] = -2.0;
+            return;
+        }
+        // decide pivot t from every workgroup's partials, in workgroup order
+        double bm = -1.0, bs = 0.0;
+        long long bi = 0x7fffffffffffffffLL;
+        for (int b = tid; b < G; b += kMwThreads) {
+            amax_merge(bm, bi, w.pmax[cur][b], w.pidx[cur][b]);
+            bs += w.psum[cur][b];
+        }
+        wave_amax_sum(bm, bi, bs);
+        if (lane == 0) { wmax[wv] = bm; widx[wv] = bi; wsum[wv] = bs; }
+        __syncthreads();
+        if (tid == 0) {
+            double gm = wmax[0], gs = 0.0;
+            long long gi = widx[0];
+            for (int k = 0; k < kMwThreads / kWave; ++k) {
+                gs += wsum[k];
+                amax_merge(gm, gi, wmax[k], widx[k]);
+            }
+            if (t == 0) tol2 = J.rel_tol2 * gs;
+            int stop = (t >= rmax) || (gm <= 0.0) || (gs <= tol2);
+            if (t == 0 && gm <= 0.0) stop = 2;  // all-zero block
+            if (t == 0 && stop == 1) stop = 0;  // always take at least one pivot of a nonzero block
+            s_stop = stop;
+            s_gi = gi;
+            s_wk = gm > 0.0 ? (int)((gi / n) / J.rows) : 0;
+            if (blockIdx.x == 0) {
+                if (stop) {
+                    int rank = t;
+                    if (stop == 2) {
+                        rank = 1;
+                        J.rowpiv[0] = 0; J.colpiv[0] = 0;
+                    }
+                    J.info[0] = (double)rank;
+                    J.info[1] = gs;
+                } else {
+                    J.rowpiv[t] = (int)(gi / n);
+                    J.colpiv[t] = (int)(gi % n);
+                }
+            }
+        }
+        __syncthreads();
+        if (s_stop) {
+            if (s_stop == 2)
+                for (int row = r0 + tid; row < min(m, r0 + J.rows); row += kMwThreads)
+                    J.L[(long long)row * rmax] = (row == 0) ? 1.0 : 0.0;
+            return;
+        }
+        const int pi = (int)(s_gi / n), pj = (int)(s_gi % n);
+        {
+            const double *prow = w.prow[cur] + (long long)s_wk * n;
+            for (int j = tid; j < n; j += kMwThreads) u[j] = prow[j];
+        }
+        if (active && pj >= c0 && pj < c0 + kMwTW) {  // the pivot column's owners publish it
+#pragma unroll
+            for (int j = 0; j < kMwTW; ++j)
+                if (c0 + j == pj)
+#pragma unroll
+                    for (int k = 0; k < kMwK; ++k) lc[tr + k * RS] = a[k][j];
+        }
+        __syncthreads();
+        const double inv = 1.0 / u[pj];
+        if (active) {
+            double uu[kMwTW];
+#pragma unroll
+            for (int j = 0; j < kMwTW; ++j) uu[j] = c0 + j < n ? u[c0 + j] : 0.0;
+#pragma unroll
+            for (int k = 0; k < kMwK; ++k) {
+                const int row = r0 + tr + k * RS;
+                if (row >= m) continue;
+                const double l = row == pi ? 1.0 : lc[tr + k * RS] * inv;
+                if (tc == 0) J.L[(long long)row * rmax + t] = l;
+                if (row == pi) {
+#pragma unroll
+                    for (int j = 0; j < kMwTW; ++j) a[k][j] = 0.0;
+                } else {
+#pragma unroll
+                    for (int j = 0; j < kMwTW; ++j) a[k][j] = fma(-l, uu[j], a[k][j]);
+                }
+            }
+            if (pj >= c0 && pj < c0 + kMwTW) {
+#pragma unroll
+                for (int j = 0; j < kMwTW; ++j)
+                    if (c0 + j == pj)
+#pragma unroll
+                        for (int k = 0; k < kMwK; ++k) a[k][j] = 0.0;
+            }
+        }
+        __syncthreads();  // u and lc are rewritten at the next step
+    }
+}
+
+__global__ __launch_bounds__(kMwThreads) void k_prrlu_coop(PrrluJob J) { prrlu_coop_body(J); }
+
+__global__ __launch_bounds__(kMwThreads) void k_prrlu_coop_batch(const PrrluJob *__restrict__ jobs) {
+    const PrrluJob J = jobs[blockIdx.y];
+    if (J.mode != 2 || (int)blockIdx.x >= J.nblk) return;
+    prrlu_coop_body(J);
+}
+
 __global__ void k_prrlu_mw_init(PrrluJob J) { prrlu_mw_init_body(J); }
 
 __global__ __launch_bounds__(kMwThreads) void k_prrlu_mw_step(PrrluJob J, int t) { prrlu_mw_step_body(J, t); }
 
 __global__ void k_prrlu_mw_init_batch(const PrrluJob *__restrict__ jobs, int njobs) {
     const int z = blockIdx.x * blockDim.x + threadIdx.x;
-    if (z < njobs && jobs[z].mode == 1) prrlu_mw_init_body(jobs[z]);
+    if (z < njobs && jobs[z].mode >= 1) prrlu_mw_init_body(jobs[z]);
 }
 
-__global__ __launch_bounds__(kMwThreads) void k_prrlu_mw_step_batch(const PrrluJob *__restrict__ jobs, int t) {
+// Steps the jobs of modes 1 .. max_mode (2 also when the persistent launch is not used).
+__global__ __launch_bounds__(kMwThreads) void k_prrlu_mw_step_batch(const PrrluJob *__restrict__ jobs, int t,
+                                                                     int max_mode) {
     const PrrluJob J = jobs[blockIdx.y];
-    if (J.mode != 1 || (int)blockIdx.x >= J.nblk) return;
+    if (J.mode < 1 || J.mode > max_mode || (int)blockIdx.x >= J.nblk) return;
     prrlu_mw_step_body(J, t);
 }
 
@@ -1493,21 +1701,39 @@ void jacobi_svd(hipStream_t s, int n, int batch, const double *R, double *sigma,
 
 size_t jacobi_scratch_doubles(int n, int batch) { return (size_t)batch * ((size_t)n * n + n); }
 
+// Workgroups of the persistent pivot kernel that the device holds at once (0: unknown, and the
+// persistent form is not used).
+int coop_capacity() {
+    static int cap = -1;
+    if (cap < 0) {
+        int dev = 0, ncu = 0, nb = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_prrlu_coop_batch, kMwThreads, 0) != hipSuccess)
+            cap = 0;
+        else
+            cap = nb * ncu;
+    }
+    return cap;
+}
+
+// mode 0: one workgroup, register tiles; 1: multi-workgroup, one launch per step; 2: as 1, and
+// small enough for the persistent single launch.
 void prrlu_prepare(PrrluJob &j) {
     j.shape = tile_shape_for(j.m, j.n);
-    j.mode = j.shape >= 0 ? 0 : 1;
     const int tpr = (j.n + kMwTW - 1) / kMwTW;
     WTT_REQUIRE(tpr <= kMwThreads && j.n <= kMwCand, WENOTT_EINVAL,
                 "pivot block wider than the multi-workgroup form supports");
     j.rows = (kMwThreads / tpr) * kMwK;
     j.nblk = (j.m + j.rows - 1) / j.rows;
+    j.mode = j.shape >= 0 ? 0 : (j.nblk <= kCoopMaxBlk ? 2 : 1);
 }
 
 size_t prrlu_ws_doubles(int m, int n) {
     PrrluJob j{};
     j.m = m; j.n = n;
     prrlu_prepare(j);
-    return 2 * (3 * (size_t)j.nblk + (size_t)j.nblk * n) + 2;
+    return 2 * (3 * (size_t)j.nblk + (size_t)j.nblk * n) + sizeof(PrrluCtl) / sizeof(double) + 1;
 }
 
 int prrlu(hipStream_t s, int m, int n, double *A, int rmax, double rel_tol2, int *rowpiv, int *colpiv, double *L,
@@ -1523,6 +1749,13 @@ int prrlu(hipStream_t s, int m, int n, double *A, int rmax, double rel_tol2, int
                       colpiv, L, info);
         WTT_HIP(hipGetLastError());
         return rmax + 1;
+    }
+    if (j.mode == 2 && j.nblk <= coop_capacity()) {  // the whole factorisation in one launch
+        if (t_begin > 0) return rmax + 2;
+        k_prrlu_mw_init<<<1, 1, 0, s>>>(j);
+        k_prrlu_coop<<<j.nblk, kMwThreads, 0, s>>>(j);
+        WTT_HIP(hipGetLastError());
+        return rmax + 2;
     }
     // launch t decides pivot t - 1, so the last possible decision (stop at rmax) is launch rmax + 1
     if (t_begin == 0) k_prrlu_mw_init<<<1, 1, 0, s>>>(j);
@@ -1576,7 +1809,7 @@ size_t gemm_tn_splitk_part(int M, int N, int K, int batch) {
 void prrlu_batch(hipStream_t s, int njobs, const PrrluJob *host_jobs, const PrrluJob *dev_jobs, int t_begin,
                  int t_end) {
     if (njobs <= 0) return;
-    int maxblk = 0, nmw = 0;
+    int maxblk = 0, nmw = 0, maxcoop = 0, ncoop = 0;
     int lds_shape[kNumTileShapes] = {};  // LDS bytes per tile shape in use (0: unused)
     for (int i = 0; i < njobs; ++i) {
         const PrrluJob &j = host_jobs[i];
@@ -1585,8 +1818,15 @@ void prrlu_batch(hipStream_t s, int njobs, const PrrluJob *host_jobs, const Prrl
         } else {
             maxblk = std::max(maxblk, j.nblk);
             ++nmw;
+            if (j.mode == 2) {
+                maxcoop = std::max(maxcoop, j.nblk);
+                ++ncoop;
+            }
         }
     }
+    // the persistent launch finishes its jobs (or marks them failed) at the first chunk; jobs
+    // still open at later chunks are stepped one launch per step
+    const bool coop = t_begin == 0 && ncoop > 0 && (long long)maxcoop * njobs <= coop_capacity();
     if (t_begin == 0)
         for (int k = 0; k < kNumTileShapes; ++k)
             if (lds_shape[k] > 0)
@@ -1594,8 +1834,10 @@ void prrlu_batch(hipStream_t s, int njobs, const PrrluJob *host_jobs, const Prrl
                               nullptr, nullptr);
     if (nmw) {
         if (t_begin == 0) k_prrlu_mw_init_batch<<<cdiv(njobs, 64), 64, 0, s>>>(dev_jobs, njobs);
-        for (int t = t_begin; t <= t_end; ++t)
-            k_prrlu_mw_step_batch<<<dim3(maxblk, njobs), kMwThreads, 0, s>>>(dev_jobs, t);
+        if (coop) k_prrlu_coop_batch<<<dim3(maxcoop, njobs), kMwThreads, 0, s>>>(dev_jobs);
+        if (!coop || nmw > ncoop)
+            for (int t = t_begin; t <= t_end; ++t)
+                k_prrlu_mw_step_batch<<<dim3(maxblk, njobs), kMwThreads, 0, s>>>(dev_jobs, t, coop ? 1 : 2);
     }
     WTT_HIP(hipGetLastError());
 }

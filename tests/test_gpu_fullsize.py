@@ -1,0 +1,90 @@
+"""The benchmark workload at its full size and launch configuration (needs a GPU).
+
+The four-quadrant Riemann problem on 512 x 512 cells with eps_TT dynamic from 1e-8 is the
+workload the benchmark times. Its ranks grow from 2 to about 20 within the first twenty steps,
+and from a bond rank of about 17 on the cross blocks (512 x 4 (r + 4)) no longer fit one
+workgroup's registers, so the later steps run the multi-workgroup pivot search (one persistent
+launch per factorisation). The oracle steps the full grid (about 0.1 s per step), so every step
+is checked against it from the same densified state with the alphas the step used: the
+per-step bound of the parity tests, 10 eps_TT in the relative Frobenius norm.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from tests.gpu_util import oracle_problem, rel_err
+
+pytestmark = pytest.mark.gpu
+
+STEPS = 24
+
+
+@pytest.fixture(scope="module")
+def W():
+    from paper_2405_12301_amd import wenott
+    wenott.load()
+    oracle.build(force=False)
+    return wenott
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def test_quadrants_512_every_step_vs_oracle(W):
+    _say("case: quadrants 512^2, dynamic eps from 1e-8,", STEPS, "steps, each against the oracle")
+    f = workloads.config2_quadrants_2d(512, seed=0)
+    s = W.Solver(f, W.default_opts(eps_mode=1, eps0=f.eps0))
+    P = oracle_problem(f)
+    try:
+        worst = 0.0
+        for step in range(STEPS):
+            u = s.dense()
+            dt = f.cfl * min(f.h) / s.max_wavespeed()
+            s.step(dt)
+            info = s.info()
+            P.ssprk3(u, dt, alphas=[info.alpha[j] for j in range(3)])
+            err = rel_err(s.dense(), u)
+            worst = max(worst, err / info.eps)
+            if step % 4 == 3 or step == STEPS - 1:
+                _say(f"  step {step} ranks={list(info.ranks)[:3]} eps={info.eps:.3e} err={err:.3e}")
+            assert err <= 10 * info.eps, (step, err, info.eps)
+        assert max(list(s.info().ranks)[:3]) >= 17  # the later crosses took the multi-workgroup search
+        _say(f"  worst err / eps = {worst:.2f}")
+    finally:
+        s.close()
+
+
+def test_quadrants_512_batch_matches_single_and_oracle(W):
+    _say("case: quadrants 512^2, two states in lock-step against single steps and the oracle")
+    flows = [workloads.config2_quadrants_2d(512, seed=sd) for sd in (0, 3)]
+    opts = W.default_opts(eps_mode=1, eps0=flows[0].eps0)
+    batch = [W.Solver(f, opts) for f in flows]
+    single = [W.Solver(f, opts) for f in flows]
+    P = oracle_problem(flows[0])
+    try:
+        for step in range(STEPS):
+            check = step >= STEPS - 2
+            u0 = batch[0].dense() if check else None
+            dts = [f.cfl * min(f.h) / s.max_wavespeed() for f, s in zip(flows, batch)]
+            W.wenott_batch_rk3_step([s.ctx for s in batch], dts)
+            for s1, dt in zip(single, dts):
+                s1.step(dt)
+            if check:
+                info = batch[0].info()
+                P.ssprk3(u0, dt=dts[0], alphas=[info.alpha[j] for j in range(3)])
+                err = rel_err(batch[0].dense(), u0)
+                _say(f"  step {step} ranks={list(info.ranks)[:3]} err vs oracle={err:.3e}")
+                assert err <= 10 * info.eps, (step, err)
+        for i, (b, s1) in enumerate(zip(batch, single)):
+            d = rel_err(b.dense(), s1.dense())
+            _say(f"  state {i}: batched vs single after {STEPS} steps {d:.3e}")
+            assert d <= 10 * STEPS * b.info().eps, (i, d)
+        assert max(list(batch[0].info().ranks)[:3]) >= 17
+    finally:
+        for s in batch + single:
+            s.close()
