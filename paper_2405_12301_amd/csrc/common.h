@@ -138,7 +138,7 @@ void prrlu_batch(hipStream_t s, int njobs, const PrrluJob *host_jobs, const Prrl
                  int t_end);
 bool jacobi_batch_fits(int nmax);
 void jacobi_svd_batch(hipStream_t s, int njobs, int ncomp, int nmax, const SvdJob *dev_jobs);
-void chol_upper_inv_batch(hipStream_t s, int njobs, int ncomp, const CholJob *dev_jobs);
+void chol_upper_inv_batch(hipStream_t s, int njobs, int ncomp, int rmax, const CholJob *dev_jobs);  // rmax: largest r
 
 // X (m x r, row-major) = L (m x ldl) * inv(L[rowpiv, :r]), the interpolative basis.
 void interp_solve(hipStream_t s, int m, int r, const double *L, int ldl, const int *rowpiv, double *X);

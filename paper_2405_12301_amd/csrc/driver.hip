@@ -1648,7 +1648,7 @@ void batch_round(std::vector<BState> &bs, std::vector<TT> &Xs) {
                 cj[z] = CholJob{Gm, Xi, ws, r, nc};
             }
             CholJob *dc = bs[0].c->ring.put(cj.data(), cj.size());
-            chol_upper_inv_batch(bs[0].c->s, (int)ns, nc, dc);
+            chol_upper_inv_batch(bs[0].c->s, (int)ns, nc, *std::max_element(rr.begin(), rr.end()), dc);
             for (size_t z = 0; z < ns; ++z) {
                 wenott_ctx *c = bs[z].c;
                 const int m = Xs[z].R[k] * Xs[z].N[k], r = rr[z];

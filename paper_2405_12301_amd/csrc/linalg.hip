@@ -1366,6 +1366,61 @@ __device__ __forceinline__ void chol_inv_body(int r, const double *__restrict__ 
     }
 }
 
+// One wave per matrix for r <= 64, everything in LDS (leading dimension r + 1): right-looking
+// Cholesky with lane i owning column i (row j of R, then the trailing update of column i), then
+// R^{-1} by back substitution, lane i forming column i. The same arithmetic as above (a column
+// whose pivot is not above 0.5 is a zero padding column with a unit diagonal); the sums run in
+// another order.
+constexpr int kCholWaveMax = 63;  // 2 r (r + 1) doubles of LDS stay within 64 KB
+
+__device__ __forceinline__ void chol_inv_wave_body(int r, const double *__restrict__ G, double *__restrict__ X) {
+    extern __shared__ double cw[];
+    const int ld = r + 1, lane = threadIdx.x;
+    double *A = cw, *Xs = cw + r * ld;
+    for (int e = lane; e < r * r; e += kWave) A[(e / r) * ld + e % r] = G[e];
+    __syncthreads();
+    for (int j = 0; j < r; ++j) {
+        const double dd = A[j * ld + j];
+        const bool zc = !(dd > 0.5);
+        const double rjj = zc ? 1.0 : sqrt(dd), inv = 1.0 / rjj;
+        double rji = 0.0;
+        if (lane > j && lane < r) {
+            rji = zc ? 0.0 : A[j * ld + lane] * inv;
+            A[j * ld + lane] = rji;
+        }
+        if (lane == j) A[j * ld + j] = rjj;
+        __syncthreads();
+        if (lane > j && lane < r)
+            for (int k = j + 1; k <= lane; ++k) A[k * ld + lane] = fma(-A[j * ld + k], rji, A[k * ld + lane]);
+        __syncthreads();
+    }
+    if (lane < r) {
+        const int i = lane;
+        for (int j = i; j >= 0; --j) {
+            double v = (j == i) ? 1.0 : 0.0;
+            for (int k = j + 1; k <= i; ++k) v = fma(-A[j * ld + k], Xs[k * ld + i], v);
+            Xs[j * ld + i] = v / A[j * ld + j];
+        }
+    }
+    __syncthreads();
+    for (int e = lane; e < r * r; e += kWave) {
+        const int j = e / r, i = e % r;
+        X[e] = j <= i ? Xs[j * ld + i] : 0.0;
+    }
+}
+
+__global__ __launch_bounds__(64) void k_chol_inv_wave(int r, const double *__restrict__ Gin, double *__restrict__ Xout) {
+    const long long off = (long long)blockIdx.x * r * r;
+    chol_inv_wave_body(r, Gin + off, Xout + off);
+}
+
+__global__ __launch_bounds__(64) void k_chol_inv_wave_batch(const CholJob *__restrict__ jobs) {
+    const CholJob j = jobs[blockIdx.x];
+    if ((int)blockIdx.y >= j.batch) return;
+    const long long off = (long long)blockIdx.y * j.r * j.r;
+    chol_inv_wave_body(j.r, j.G + off, j.X + off);
+}
+
 __global__ __launch_bounds__(256) void k_chol_inv(int r, const double *__restrict__ Gin, double *__restrict__ Xout,
                                                   double *__restrict__ Rws) {
     const long long off = (long long)blockIdx.x * r * r;
@@ -1776,7 +1831,10 @@ void interp_solve(hipStream_t s, int m, int r, const double *L, int ldl, const i
 }
 
 void chol_upper_inv(hipStream_t s, int r, int batch, const double *G, double *X, double *ws) {
-    k_chol_inv<<<batch, 256, 0, s>>>(r, G, X, ws);
+    if (r <= kCholWaveMax)
+        k_chol_inv_wave<<<batch, kWave, sizeof(double) * 2 * (size_t)r * (r + 1), s>>>(r, G, X);
+    else
+        k_chol_inv<<<batch, 256, 0, s>>>(r, G, X, ws);
     WTT_HIP(hipGetLastError());
 }
 
@@ -1854,9 +1912,13 @@ void jacobi_svd_batch(hipStream_t s, int njobs, int ncomp, int nmax, const SvdJo
     WTT_HIP(hipGetLastError());
 }
 
-void chol_upper_inv_batch(hipStream_t s, int njobs, int ncomp, const CholJob *dev_jobs) {
+void chol_upper_inv_batch(hipStream_t s, int njobs, int ncomp, int rmax, const CholJob *dev_jobs) {
     if (njobs <= 0) return;
-    k_chol_inv_batch<<<dim3(njobs, ncomp), 256, 0, s>>>(dev_jobs);
+    if (rmax <= kCholWaveMax)
+        k_chol_inv_wave_batch<<<dim3(njobs, ncomp), kWave, sizeof(double) * 2 * (size_t)rmax * (rmax + 1), s>>>(
+            dev_jobs);
+    else
+        k_chol_inv_batch<<<dim3(njobs, ncomp), 256, 0, s>>>(dev_jobs);
     WTT_HIP(hipGetLastError());
 }
 
