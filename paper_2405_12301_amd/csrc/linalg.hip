@@ -599,6 +599,86 @@ __device__ void jacobi_sweeps(int n, double *X, int *nrot, double *nrm, double e
     }
 }
 
+// Sum over each half-wave (lanes 0..31 and 32..63; every lane active); every lane gets the sum
+// of its own half.
+__device__ __forceinline__ double half_wave_sum(double v) {
+    v += dpp_d<0xB1>(v);
+    v += dpp_d<0x4E>(v);
+    v += dpp_d<0x141>(v);
+    v += dpp_d<0x140>(v);
+    const double lo = readlane_d(v, 0) + readlane_d(v, 16), hi = readlane_d(v, 32) + readlane_d(v, 48);
+    return (threadIdx.x & 32) ? hi : lo;
+}
+
+// The same sweeps for n <= 64 with 1024 threads: pair k of a round goes to half-wave k (32
+// half-waves cover the n / 2 pairs), lane l of a half holding rows l % 32 and l % 32 + 32 of both
+// columns in registers from the dot product to the rotation. Every pair of a round is in flight
+// at once and each costs one segmented reduction; the pairs, their order and the rotation
+// formulas are those of jacobi_sweeps.
+__device__ void jacobi_sweeps_small(int n, double *X, int *nrot, double *nrm, double eta) {
+    const int tid = threadIdx.x, lane = tid % kWave, w = tid / kWave;
+    const int hl = lane & 31, slot = 2 * w + (lane >> 5), nslots = 2 * (int)(blockDim.x / kWave);
+    const int i0 = hl, i1 = hl + 32;
+    const int np = n + (n & 1);
+    const double tol2 = 1e-30;  // (1e-15)^2: the relative threshold of jacobi_sweeps, squared
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        for (int j0 = 0; j0 < n; j0 += nslots) {
+            const int j = j0 + slot;
+            double ss = 0.0;
+            if (j < n) {
+                const double *xj = X + (long long)j * n;
+                const double u0 = i0 < n ? xj[i0] : 0.0, u1 = i1 < n ? xj[i1] : 0.0;
+                ss = fma(u0, u0, u1 * u1);
+            }
+            ss = half_wave_sum(ss);
+            if (j < n && hl == 0) nrm[j] = ss;
+        }
+        if (tid == 0) *nrot = 0;
+        __syncthreads();
+        for (int r = 0; r < np - 1; ++r) {
+            int p = 0, q = n;
+            if (slot < np / 2) circle_pair(r, slot, np, &p, &q);
+            const bool valid = q < n;
+            double *xp = X + (long long)p * n, *xq = X + (long long)(valid ? q : p) * n;
+            double x0 = 0.0, x1 = 0.0, y0 = 0.0, y1 = 0.0, a = 0.0, b = 0.0;
+            if (valid) {
+                if (i0 < n) { x0 = xp[i0]; y0 = xq[i0]; }
+                if (i1 < n) { x1 = xp[i1]; y1 = xq[i1]; }
+                a = nrm[p];
+                b = nrm[q];
+            }
+            const double c = half_wave_sum(fma(x0, y0, x1 * y1));
+            if (valid && c != 0.0 && c * c > tol2 * (a * b) && fabs(c) > eta) {
+                const double dd = b - a;
+                const double t = copysign(1.0, dd) * (2.0 * c) / (fabs(dd) + sqrt(dd * dd + 4.0 * c * c));
+                const double cs = rsqrt(1.0 + t * t), sn = cs * t;
+                if (i0 < n) {
+                    xp[i0] = cs * x0 - sn * y0;
+                    xq[i0] = sn * x0 + cs * y0;
+                }
+                if (i1 < n) {
+                    xp[i1] = cs * x1 - sn * y1;
+                    xq[i1] = sn * x1 + cs * y1;
+                }
+                if (hl == 0) {
+                    nrm[p] = fmax(a - t * c, 0.0);
+                    nrm[q] = b + t * c;
+                    *nrot = 1;  // every writer stores the same value
+                }
+            }
+            __syncthreads();
+        }
+        const int done = *nrot == 0;
+        __syncthreads();
+        if (done) break;
+    }
+}
+
+__device__ __forceinline__ void jacobi_run(int n, double *X, int *nrot, double *nrm, double eta) {
+    if (n <= 64 && blockDim.x == 1024) jacobi_sweeps_small(n, X, nrot, nrm, eta);
+    else jacobi_sweeps(n, X, nrot, nrm, eta);
+}
+
 // Singular values = final column norms of X, descending by rank counting (ties to the lower
 // column); the right singular vectors of C are the normalised columns (row-major V, column pos
 // = singular vector pos; a zero column gives a zero vector, whose singular value 0 is never
@@ -637,7 +717,7 @@ __global__ __launch_bounds__(1024) void k_jacobi_lds(int n, const double *__rest
     const double *Rz = Rin + (long long)z * n * n;
     for (int e = tid; e < n * n; e += blockDim.x) X[e] = Rz[e];
     __syncthreads();
-    jacobi_sweeps(n, X, &nrot, sig_tmp, jacobi_eta(delta, z, n));
+    jacobi_run(n, X, &nrot, sig_tmp, jacobi_eta(delta, z, n));
     jacobi_finish(n, X, sig_tmp, sigma + (long long)z * n, Vout + (long long)z * n * n);
 }
 
@@ -652,7 +732,7 @@ __global__ __launch_bounds__(1024) void k_jacobi_global(int n, const double *__r
     const double *Rz = Rin + (long long)z * n * n;
     for (long long e = tid; e < (long long)n * n; e += blockDim.x) X[e] = Rz[e];
     __syncthreads();
-    jacobi_sweeps(n, X, &nrot, sig_tmp, jacobi_eta(delta, z, n));
+    jacobi_run(n, X, &nrot, sig_tmp, jacobi_eta(delta, z, n));
     jacobi_finish(n, X, sig_tmp, sigma + (long long)z * n, Vout + (long long)z * n * n);
 }
 
@@ -1446,7 +1526,7 @@ __global__ __launch_bounds__(1024) void k_jacobi_lds_batch(const SvdJob *__restr
     const double *Rz = j.A + (long long)z * n * n;
     for (int e = tid; e < n * n; e += blockDim.x) X[e] = Rz[e];
     __syncthreads();
-    jacobi_sweeps(n, X, &nrot, sig_tmp, jacobi_eta(j.delta, z, n));
+    jacobi_run(n, X, &nrot, sig_tmp, jacobi_eta(j.delta, z, n));
     jacobi_finish(n, X, sig_tmp, j.sigma + (long long)z * n, j.V + (long long)z * n * n);
 }
 
