@@ -437,10 +437,15 @@ __device__ __forceinline__ void qr_reg_prep(double (&a)[RPT], int j, int lane, d
         for (int q = 0; q < RPT; ++q)
             if (q == qj) a[q] = 0.0;
     }
-    double ss = 0.0;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;  // four chains for latency
 #pragma unroll
-    for (int q = 0; q < RPT; ++q) ss = fma(a[q], a[q], ss);
-    const double xn2 = row_sum16(ss);
+    for (int q = 0; q < RPT; q += 4) {
+        s0 = fma(a[q], a[q], s0);
+        s1 = fma(a[q + 1], a[q + 1], s1);
+        s2 = fma(a[q + 2], a[q + 2], s2);
+        s3 = fma(a[q + 3], a[q + 3], s3);
+    }
+    const double xn2 = row_sum16((s0 + s1) + (s2 + s3));
     double beta, tau, scale;
     if (xn2 == 0.0) {
         beta = alpha; tau = 0.0; scale = 0.0;
@@ -458,9 +463,9 @@ __device__ __forceinline__ void qr_reg_prep(double (&a)[RPT], int j, int lane, d
     }
 }
 
-template <int RPT>
-__global__ __launch_bounds__(1024) void k_qr_reg(int m, int n, int bm, int nblk, const double *__restrict__ A,
-                                                 long long sz, long long rs, long long cs, double *__restrict__ Rout) {
+template <int RPT, int NT>
+__global__ __launch_bounds__(NT) void k_qr_reg(int m, int n, int bm, int nblk, const double *__restrict__ A,
+                                               long long sz, long long rs, long long cs, double *__restrict__ Rout) {
     __shared__ double vb[2][16 * RPT];
     __shared__ double tb[2];
     __shared__ double Rl[64 * 64];
@@ -480,10 +485,15 @@ __global__ __launch_bounds__(1024) void k_qr_reg(int m, int n, int bm, int nblk,
     for (int j = 0; j < n; ++j) {
         if (c > j && c < n) {
             const double *v = vb[j & 1];
-            double dot = 0.0;
+            double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;  // four chains for latency
 #pragma unroll
-            for (int q = 0; q < RPT; ++q) dot = fma(v[rg + 16 * q], a[q], dot);
-            const double f = tb[j & 1] * row_sum16(dot);
+            for (int q = 0; q < RPT; q += 4) {
+                d0 = fma(v[rg + 16 * q], a[q], d0);
+                d1 = fma(v[rg + 16 * (q + 1)], a[q + 1], d1);
+                d2 = fma(v[rg + 16 * (q + 2)], a[q + 2], d2);
+                d3 = fma(v[rg + 16 * (q + 3)], a[q + 3], d3);
+            }
+            const double f = tb[j & 1] * row_sum16((d0 + d1) + (d2 + d3));
 #pragma unroll
             for (int q = 0; q < RPT; ++q) a[q] = fma(-f, v[rg + 16 * q], a[q]);
             const int qj = j >> 4;
@@ -500,7 +510,7 @@ __global__ __launch_bounds__(1024) void k_qr_reg(int m, int n, int bm, int nblk,
         __syncthreads();
     }
     double *R = Rout + ((long long)z * nblk + blk) * (long long)n * n;
-    for (int e = tid; e < n * n; e += 1024) {
+    for (int e = tid; e < n * n; e += NT) {
         const int i = e / n, l = e % n;
         R[e] = i <= l ? Rl[i * 64 + l] : 0.0;
     }
@@ -1765,29 +1775,35 @@ void launch_hhqr(hipStream_t s, int nblk, int batch, bool lds, int m, int n, int
     WTT_HIP(hipGetLastError());
 }
 
-constexpr int kQrRegCols = 64, kQrRegRows = 256;  // 16 rows per lane at most (no spills)
+// 1024 threads (64 columns) hold up to 16 rows per lane without spilling; 512 threads (32
+// columns, twice the registers per lane) hold 32.
+constexpr int kQrRegCols = 64;
+inline int qr_reg_rows(int n) { return n <= 32 ? 512 : 256; }
 
 void launch_qr_reg(hipStream_t s, int nblk, int batch, int m, int n, int bm, const double *A, long long sz,
                    long long rs, long long cs, double *Rout) {
     const int rows = std::max(bm, n);
     const dim3 grid(nblk, batch);
-    WTT_REQUIRE(n <= kQrRegCols && rows <= kQrRegRows, WENOTT_EINVAL, "register QR block too large");
-    if (rows <= 64) k_qr_reg<4><<<grid, 1024, 0, s>>>(m, n, bm, nblk, A, sz, rs, cs, Rout);
-    else if (rows <= 128) k_qr_reg<8><<<grid, 1024, 0, s>>>(m, n, bm, nblk, A, sz, rs, cs, Rout);
-    else k_qr_reg<16><<<grid, 1024, 0, s>>>(m, n, bm, nblk, A, sz, rs, cs, Rout);
+    WTT_REQUIRE(n <= kQrRegCols && rows <= qr_reg_rows(n), WENOTT_EINVAL, "register QR block too large");
+    if (rows <= 64) k_qr_reg<4, 1024><<<grid, 1024, 0, s>>>(m, n, bm, nblk, A, sz, rs, cs, Rout);
+    else if (rows <= 128) k_qr_reg<8, 1024><<<grid, 1024, 0, s>>>(m, n, bm, nblk, A, sz, rs, cs, Rout);
+    else if (rows <= 256) k_qr_reg<16, 1024><<<grid, 1024, 0, s>>>(m, n, bm, nblk, A, sz, rs, cs, Rout);
+    else k_qr_reg<32, 512><<<grid, 512, 0, s>>>(m, n, bm, nblk, A, sz, rs, cs, Rout);
     WTT_HIP(hipGetLastError());
 }
 
 void tsqr_r(hipStream_t s, int m, int n, int batch, const double *A, long long sz, long long rs, long long cs,
             double *R, double *scratch) {
     if (n <= kQrRegCols) {
-        // register-resident leaves of up to 256 rows, then nodes of up to 256 stacked rows; the
-        // two R buffers fit in what tsqr_scratch_doubles reserves for the general plan's R buffers
-        int nblk = (m + kQrRegRows - 1) / kQrRegRows;
-        const int bm = std::min(m, kQrRegRows);
+        // register-resident leaves of up to qr_reg_rows(n) rows, then nodes of as many stacked
+        // rows; the two R buffers fit in what tsqr_scratch_doubles reserves for the general
+        // plan's R buffers (whose leaves are never taller)
+        const int maxrows = qr_reg_rows(n);
+        int nblk = (m + maxrows - 1) / maxrows;
+        const int bm = std::min(m, maxrows);
         double *cur = scratch, *nxt = scratch + (long long)batch * nblk * n * n;
         launch_qr_reg(s, nblk, batch, m, n, bm, A, sz, rs, cs, nblk == 1 ? R : cur);
-        const int group = std::max(2, kQrRegRows / n);
+        const int group = std::max(2, maxrows / n);
         while (nblk > 1) {
             const int nb2 = (nblk + group - 1) / group;
             const int bm2 = std::min(group, nblk) * n;
