@@ -762,17 +762,17 @@ __global__ __launch_bounds__(1024) void k_jacobi_global(int n, const double *__r
 struct PrrluCtl {
     double tol2;
     int stop_launch;
-    unsigned bar;  // grid barrier arrivals of the persistent form
-    int fail;      // set by a workgroup of the persistent form whose barrier wait ran out
-    int pad;
+    int fail;  // set by a workgroup of the persistent form whose polls ran out
 };
 
 struct PrrluWs {
     double *pmax[2], *psum[2], *prow[2];
     long long *pidx[2];
+    unsigned *pseq[2];  // persistent form: step stamp of each workgroup's partials
     PrrluCtl *ctl;
 };
 
+// Per parity: max | sum | index | stamp (nblk each, one double apiece) | rows (nblk x n).
 __host__ __device__ inline PrrluWs prrlu_ws_split(double *ws, int n, int nblk) {
     PrrluWs w;
     double *p = ws;
@@ -780,8 +780,9 @@ __host__ __device__ inline PrrluWs prrlu_ws_split(double *ws, int n, int nblk) {
         w.pmax[b] = p;
         w.psum[b] = p + nblk;
         w.pidx[b] = (long long *)(p + 2 * nblk);
-        w.prow[b] = p + 3 * nblk;
-        p += 3 * nblk + (size_t)nblk * n;
+        w.pseq[b] = (unsigned *)(p + 3 * nblk);
+        w.prow[b] = p + 4 * nblk;
+        p += 4 * nblk + (size_t)nblk * n;
     }
     w.ctl = (PrrluCtl *)p;
     return w;
@@ -793,8 +794,8 @@ __device__ __forceinline__ void prrlu_mw_init_body(const PrrluJob &J) {
     const PrrluWs w = prrlu_ws_split(J.ws, J.n, J.nblk);
     w.ctl->stop_launch = 0;
     w.ctl->tol2 = 0.0;
-    w.ctl->bar = 0u;
     w.ctl->fail = 0;
+    for (int b = 0; b < J.nblk; ++b) w.pseq[0][2 * b] = w.pseq[1][2 * b] = 0u;
     J.info[0] = -1.0;  // not finished: the host launches further steps
 }
 
@@ -987,21 +988,22 @@ __device__ __forceinline__ void prrlu_mw_step_body(const PrrluJob &J, int t) {
 // launched only when the device holds all its workgroups at once (the grid is at most the
 // occupancy times the compute units); a plain launch is used, since the cooperative launch API
 // costs about 0.1 ms of host time per call. Workgroups are dispatched in order, so even a grid
-// that other work keeps partly waiting makes progress as slots free up. Per pivot step every workgroup publishes the
-// partials and candidate row of its residual (double-buffered by step parity), all meet at a
-// grid barrier (a counter with device-scope release / acquire atomics), and each then takes the
-// same decision from the partials, reads the winning row and eliminates it from its stripe. Two
-// buffers and one barrier per step suffice: a buffer is written again two steps later, after
-// the next barrier, which no workgroup passes before every workgroup has read it. The barrier
-// wait is bounded: after kCoopSpin polls a workgroup marks the job failed and leaves (info[0] =
-// -2), and the others leave at their next poll.
-constexpr int kCoopMaxBlk = 64;
+// that other work keeps partly waiting makes progress as slots free up.
+// Per pivot step t every workgroup publishes its partials and candidate row (double-buffered by
+// step parity) and then stamps its slot with t + 1 (a device-scope release store). Every wave
+// of every workgroup gathers all slots itself, lane b polling slot b (device-scope acquire
+// loads) and reading its partials, and reduces them in slot order; so all waves take the same
+// decision with no barrier beyond the stamps. Each thread then reads its columns of the winning
+// row, and only the pivot column of the stripe passes through LDS. A buffer of one parity is
+// written again two steps later, which no workgroup can reach before every workgroup has read
+// it. The polls are bounded: after kCoopSpin polls a workgroup marks the job failed (info[0] =
+// -2) and leaves, and the others leave at their next poll.
+constexpr int kCoopMaxBlk = 64;  // one slot per lane of a wave
 constexpr int kCoopSpin = 1 << 22;
 
-__device__ __forceinline__ bool coop_grid_sync(PrrluCtl *ctl, unsigned target) {
-    __hip_atomic_fetch_add(&ctl->bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ bool coop_poll(const unsigned *stamp, unsigned target, PrrluCtl *ctl) {
     for (int sp = 0; sp < kCoopSpin; ++sp) {
-        if (__hip_atomic_load(&ctl->bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= target) return true;
+        if (__hip_atomic_load(stamp, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= target) return true;
         if (__hip_atomic_load(&ctl->fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
         __builtin_amdgcn_s_sleep(1);
     }
@@ -1011,18 +1013,16 @@ __device__ __forceinline__ bool coop_grid_sync(PrrluCtl *ctl, unsigned target) {
 
 __device__ __forceinline__ void prrlu_coop_body(const PrrluJob &J) {
     __shared__ double lc[kMwThreads * kMwK];
-    __shared__ double u[kMwCand];
     __shared__ double wmax[kMwThreads / kWave], wsum[kMwThreads / kWave];
     __shared__ long long widx[kMwThreads / kWave];
-    __shared__ int s_stop, s_wk, s_ok;
-    __shared__ long long s_gi, s_bi;
+    __shared__ int s_fail;
     const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave;
-    const int m = J.m, n = J.n, rmax = J.rmax, G = J.nblk;
+    const int m = J.m, n = J.n, rmax = J.rmax, G = J.nblk, blk = blockIdx.x;
     const PrrluWs w = prrlu_ws_split(J.ws, n, J.nblk);
     const int tpr = (n + kMwTW - 1) / kMwTW, RS = kMwThreads / tpr;
     const int tr = tid / tpr, tc = tid % tpr, c0 = tc * kMwTW;
     const bool active = tr < RS;
-    const int r0 = blockIdx.x * J.rows;
+    const int r0 = blk * J.rows;
     double a[kMwK][kMwTW];
 #pragma unroll
     for (int k = 0; k < kMwK; ++k) {
@@ -1031,7 +1031,8 @@ __device__ __forceinline__ void prrlu_coop_body(const PrrluJob &J) {
 #pragma unroll
         for (int j = 0; j < kMwTW; ++j) a[k][j] = (rv && c0 + j < n) ? J.A[(long long)row * n + c0 + j] : 0.0;
     }
-    double tol2 = 0.0;  // thread 0: every workgroup forms the same value from the same partials
+    if (tid == 0) s_fail = 0;
+    double tol2 = 0.0;  // every workgroup forms the same value from the same partials
     for (int t = 0;; ++t) {
         const int cur = t & 1;
         // partials of the residual after t pivots, and this stripe's candidate row
@@ -1053,23 +1054,21 @@ __device__ __forceinline__ void prrlu_coop_body(const PrrluJob &J) {
         wave_amax_sum(lmax, lidx, lsum);
         if (lane == 0) { wmax[wv] = lmax; widx[wv] = lidx; wsum[wv] = lsum; }
         __syncthreads();
-        if (tid == 0) {
-            double bm = wmax[0], bs = 0.0;
-            long long bi = widx[0];
-            for (int k = 0; k < kMwThreads / kWave; ++k) {
-                bs += wsum[k];
-                amax_merge(bm, bi, wmax[k], widx[k]);
-            }
-            w.pmax[cur][blockIdx.x] = bm;
-            w.psum[cur][blockIdx.x] = bs;
-            w.pidx[cur][blockIdx.x] = bi;
-            s_bi = bi;
+        double bm = wmax[0], bs = 0.0;
+        long long bi = widx[0];
+        for (int k = 0; k < kMwThreads / kWave; ++k) {
+            bs += wsum[k];
+            amax_merge(bm, bi, wmax[k], widx[k]);
         }
-        __syncthreads();
-        if (s_bi != 0x7fffffffffffffffLL && active) {
-            const int local = (int)(s_bi / n) - r0;
+        if (tid == 0) {
+            w.pmax[cur][blk] = bm;
+            w.psum[cur][blk] = bs;
+            w.pidx[cur][blk] = bi;
+        }
+        if (bi != 0x7fffffffffffffffLL && active) {  // a real row: ties go to the lowest index
+            const int local = (int)(bi / n) - r0;
             if (local % RS == tr) {
-                double *dst = w.prow[cur] + (long long)blockIdx.x * n;
+                double *dst = w.prow[cur] + (long long)blk * n;
 #pragma unroll
                 for (int k = 0; k < kMwK; ++k)
                     if (k == local / RS)
@@ -1078,38 +1077,34 @@ __device__ __forceinline__ void prrlu_coop_body(const PrrluJob &J) {
                             if (c0 + j < n) dst[c0 + j] = a[k][j];
             }
         }
-        __syncthreads();  // this workgroup's stores are done before thread 0 releases them
-        if (tid == 0) s_ok = coop_grid_sync(w.ctl, (unsigned)(t + 1) * (unsigned)G);
-        __syncthreads();
-        if (!s_ok) {
-            if (tid == 0) J.info[0] = -2.0;
-            return;
-        }
-        // decide pivot t from every workgroup's partials, in workgroup order
-        double bm = -1.0, bs = 0.0;
-        long long bi = 0x7fffffffffffffffLL;
-        for (int b = tid; b < G; b += kMwThreads) {
-            amax_merge(bm, bi, w.pmax[cur][b], w.pidx[cur][b]);
-            bs += w.psum[cur][b];
-        }
-        wave_amax_sum(bm, bi, bs);
-        if (lane == 0) { wmax[wv] = bm; widx[wv] = bi; wsum[wv] = bs; }
-        __syncthreads();
-        if (tid == 0) {
-            double gm = wmax[0], gs = 0.0;
-            long long gi = widx[0];
-            for (int k = 0; k < kMwThreads / kWave; ++k) {
-                gs += wsum[k];
-                amax_merge(gm, gi, wmax[k], widx[k]);
+        __syncthreads();  // this workgroup's stores are complete before the stamp releases them
+        if (tid == 0)
+            __hip_atomic_store(&w.pseq[cur][2 * blk], (unsigned)(t + 1), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        // every wave gathers every slot and decides pivot t on its own
+        double gm = -1.0, gs = 0.0;
+        long long gi = 0x7fffffffffffffffLL;
+        bool ok = true;
+        if (lane < G) {
+            ok = coop_poll(&w.pseq[cur][2 * lane], (unsigned)(t + 1), w.ctl);
+            if (ok) {
+                gm = w.pmax[cur][lane];
+                gs = w.psum[cur][lane];
+                gi = w.pidx[cur][lane];
             }
-            if (t == 0) tol2 = J.rel_tol2 * gs;
-            int stop = (t >= rmax) || (gm <= 0.0) || (gs <= tol2);
-            if (t == 0 && gm <= 0.0) stop = 2;  // all-zero block
-            if (t == 0 && stop == 1) stop = 0;  // always take at least one pivot of a nonzero block
-            s_stop = stop;
-            s_gi = gi;
-            s_wk = gm > 0.0 ? (int)((gi / n) / J.rows) : 0;
-            if (blockIdx.x == 0) {
+        }
+        const bool wave_ok = __ballot(!ok) == 0;
+        wave_amax_sum(gm, gi, gs);
+        if (t == 0) tol2 = J.rel_tol2 * gs;
+        int stop = (t >= rmax) || (gm <= 0.0) || (gs <= tol2);
+        if (t == 0 && gm <= 0.0) stop = 2;  // all-zero block
+        if (t == 0 && stop == 1) stop = 0;  // always take at least one pivot of a nonzero block
+        const int pi = stop ? 0 : (int)(gi / n), pj = stop ? 0 : (int)(gi % n);
+        const int wk = stop ? 0 : pi / J.rows;  // the workgroup whose stripe holds the pivot row
+        double uu[kMwTW], upj = 1.0;
+        if (!wave_ok) {
+            if (lane == 0) s_fail = 1;
+        } else {
+            if (blk == 0 && tid == 0) {
                 if (stop) {
                     int rank = t;
                     if (stop == 2) {
@@ -1119,36 +1114,37 @@ __device__ __forceinline__ void prrlu_coop_body(const PrrluJob &J) {
                     J.info[0] = (double)rank;
                     J.info[1] = gs;
                 } else {
-                    J.rowpiv[t] = (int)(gi / n);
-                    J.colpiv[t] = (int)(gi % n);
+                    J.rowpiv[t] = pi;
+                    J.colpiv[t] = pj;
+                }
+            }
+            if (!stop) {
+                const double *urow = w.prow[cur] + (long long)wk * n;
+                upj = urow[pj];
+#pragma unroll
+                for (int j = 0; j < kMwTW; ++j) uu[j] = (active && c0 + j < n) ? urow[c0 + j] : 0.0;
+                if (active && pj >= c0 && pj < c0 + kMwTW) {  // the pivot column's owners publish it
+#pragma unroll
+                    for (int j = 0; j < kMwTW; ++j)
+                        if (c0 + j == pj)
+#pragma unroll
+                            for (int k = 0; k < kMwK; ++k) lc[tr + k * RS] = a[k][j];
                 }
             }
         }
         __syncthreads();
-        if (s_stop) {
-            if (s_stop == 2)
+        if (s_fail) {
+            if (tid == 0) J.info[0] = -2.0;
+            return;
+        }
+        if (stop) {  // every wave took the same decision
+            if (stop == 2)
                 for (int row = r0 + tid; row < min(m, r0 + J.rows); row += kMwThreads)
                     J.L[(long long)row * rmax] = (row == 0) ? 1.0 : 0.0;
             return;
         }
-        const int pi = (int)(s_gi / n), pj = (int)(s_gi % n);
-        {
-            const double *prow = w.prow[cur] + (long long)s_wk * n;
-            for (int j = tid; j < n; j += kMwThreads) u[j] = prow[j];
-        }
-        if (active && pj >= c0 && pj < c0 + kMwTW) {  // the pivot column's owners publish it
-#pragma unroll
-            for (int j = 0; j < kMwTW; ++j)
-                if (c0 + j == pj)
-#pragma unroll
-                    for (int k = 0; k < kMwK; ++k) lc[tr + k * RS] = a[k][j];
-        }
-        __syncthreads();
-        const double inv = 1.0 / u[pj];
+        const double inv = 1.0 / upj;
         if (active) {
-            double uu[kMwTW];
-#pragma unroll
-            for (int j = 0; j < kMwTW; ++j) uu[j] = c0 + j < n ? u[c0 + j] : 0.0;
 #pragma unroll
             for (int k = 0; k < kMwK; ++k) {
                 const int row = r0 + tr + k * RS;
@@ -1171,7 +1167,8 @@ __device__ __forceinline__ void prrlu_coop_body(const PrrluJob &J) {
                         for (int k = 0; k < kMwK; ++k) a[k][j] = 0.0;
             }
         }
-        __syncthreads();  // u and lc are rewritten at the next step
+        // lc and the wave partials are next written after the next step's first barrier, which
+        // every wave reaches only when done with this step's values
     }
 }
 
@@ -1884,7 +1881,7 @@ size_t prrlu_ws_doubles(int m, int n) {
     PrrluJob j{};
     j.m = m; j.n = n;
     prrlu_prepare(j);
-    return 2 * (3 * (size_t)j.nblk + (size_t)j.nblk * n) + sizeof(PrrluCtl) / sizeof(double) + 1;
+    return 2 * (4 * (size_t)j.nblk + (size_t)j.nblk * n) + sizeof(PrrluCtl) / sizeof(double) + 1;
 }
 
 int prrlu(hipStream_t s, int m, int n, double *A, int rmax, double rel_tol2, int *rowpiv, int *colpiv, double *L,
