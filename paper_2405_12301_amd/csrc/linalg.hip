@@ -1404,6 +1404,49 @@ __global__ __launch_bounds__(256) void k_interp_lds(int m, int r, const double *
     }
 }
 
+// The same for r <= RMAX with the row held in registers: v starts as L[i, :r]; for s from r - 1
+// down, v[s] is final and v[t] -= v[s] L_I[s][t] for t < s (the unrolled loops keep v in
+// registers). A pivot row gets its exact unit row (x = e_s for row rowpiv[s]) in the same
+// launch.
+template <int RMAX>
+__global__ __launch_bounds__(128) void k_interp_reg(int m, int r, const double *__restrict__ L, int ldl,
+                                                    const int *__restrict__ rowpiv, double *__restrict__ X) {
+    extern __shared__ double LI[];
+    __shared__ int piv_of[128];  // pivot position of this workgroup's rows, -1 for none
+    const int tid = threadIdx.x, i0 = blockIdx.x * 128;
+    piv_of[tid] = -1;
+    for (int e = tid; e < r * r; e += 128) LI[e] = L[(long long)rowpiv[e / r] * ldl + e % r];
+    __syncthreads();
+    for (int sp = tid; sp < r; sp += 128) {
+        const int pr = rowpiv[sp] - i0;
+        if (pr >= 0 && pr < 128) piv_of[pr] = sp;
+    }
+    __syncthreads();
+    const int i = i0 + tid;
+    if (i >= m) return;
+    double *x = X + (long long)i * r;
+    const int ps = piv_of[tid];
+    if (ps >= 0) {
+        for (int t = 0; t < r; ++t) x[t] = t == ps ? 1.0 : 0.0;
+        return;
+    }
+    const double *l = L + (long long)i * ldl;
+    double v[RMAX];
+#pragma unroll
+    for (int t = 0; t < RMAX; ++t) v[t] = t < r ? l[t] : 0.0;
+#pragma unroll
+    for (int sp = RMAX - 1; sp > 0; --sp) {
+        if (sp < r) {
+            const double *li = LI + sp * r;
+#pragma unroll
+            for (int t = 0; t < sp; ++t) v[t] = fma(-v[sp], li[t], v[t]);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < RMAX; ++t)
+        if (t < r) x[t] = v[t];
+}
+
 __global__ void k_interp_exact_rows(int r, const int *__restrict__ rowpiv, double *__restrict__ X) {
     int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= r * r) return;
@@ -1915,6 +1958,13 @@ int prrlu(hipStream_t s, int m, int n, double *A, int rmax, double rel_tol2, int
 
 void interp_solve(hipStream_t s, int m, int r, const double *L, int ldl, const int *rowpiv, double *X) {
     const size_t lds = sizeof(double) * (size_t)r * r;
+    if (r > 0 && r <= 64) {  // registers; the exact pivot rows in the same launch
+        if (r <= 16) k_interp_reg<16><<<cdiv(m, 128), 128, lds, s>>>(m, r, L, ldl, rowpiv, X);
+        else if (r <= 32) k_interp_reg<32><<<cdiv(m, 128), 128, lds, s>>>(m, r, L, ldl, rowpiv, X);
+        else k_interp_reg<64><<<cdiv(m, 128), 128, lds, s>>>(m, r, L, ldl, rowpiv, X);
+        WTT_HIP(hipGetLastError());
+        return;
+    }
     if (r > 0 && lds <= (size_t)lds_limit_bytes() - 1024)
         k_interp_lds<<<cdiv(m, 256), 256, lds, s>>>(m, r, L, ldl, rowpiv, X);
     else
