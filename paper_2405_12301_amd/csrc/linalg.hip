@@ -991,19 +991,21 @@ __device__ __forceinline__ void prrlu_mw_step_body(const PrrluJob &J, int t) {
 // that other work keeps partly waiting makes progress as slots free up.
 // Per pivot step t every workgroup publishes its partials and candidate row (double-buffered by
 // step parity) and then stamps its slot with t + 1 (a device-scope release store). Every wave
-// of every workgroup gathers all slots itself, lane b polling slot b (device-scope acquire
-// loads) and reading its partials, and reduces them in slot order; so all waves take the same
-// decision with no barrier beyond the stamps. Each thread then reads its columns of the winning
-// row, and only the pivot column of the stripe passes through LDS. A buffer of one parity is
+// of every workgroup gathers all slots itself, lane b polling slot b (device-scope loads, then
+// one acquire fence per wave) and reading its partials, and reduces them in slot order; so all
+// waves take the same decision with no barrier beyond the stamps. Each thread then reads its
+// columns of the winning row, and only the pivot column of the stripe passes through LDS. A buffer of one parity is
 // written again two steps later, which no workgroup can reach before every workgroup has read
 // it. The polls are bounded: after kCoopSpin polls a workgroup marks the job failed (info[0] =
 // -2) and leaves, and the others leave at their next poll.
 constexpr int kCoopMaxBlk = 64;  // one slot per lane of a wave
 constexpr int kCoopSpin = 1 << 22;
 
+// Relaxed device-scope polls; the caller's wave takes one acquire fence after all its lanes'
+// polls have succeeded, rather than one cache invalidation per poll.
 __device__ __forceinline__ bool coop_poll(const unsigned *stamp, unsigned target, PrrluCtl *ctl) {
     for (int sp = 0; sp < kCoopSpin; ++sp) {
-        if (__hip_atomic_load(stamp, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= target) return true;
+        if (__hip_atomic_load(stamp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) return true;
         if (__hip_atomic_load(&ctl->fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
         __builtin_amdgcn_s_sleep(1);
     }
@@ -1084,15 +1086,14 @@ __device__ __forceinline__ void prrlu_coop_body(const PrrluJob &J) {
         double gm = -1.0, gs = 0.0;
         long long gi = 0x7fffffffffffffffLL;
         bool ok = true;
-        if (lane < G) {
-            ok = coop_poll(&w.pseq[cur][2 * lane], (unsigned)(t + 1), w.ctl);
-            if (ok) {
-                gm = w.pmax[cur][lane];
-                gs = w.psum[cur][lane];
-                gi = w.pidx[cur][lane];
-            }
-        }
+        if (lane < G) ok = coop_poll(&w.pseq[cur][2 * lane], (unsigned)(t + 1), w.ctl);
         const bool wave_ok = __ballot(!ok) == 0;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // every slot's partials and row are visible
+        if (lane < G && wave_ok) {
+            gm = w.pmax[cur][lane];
+            gs = w.psum[cur][lane];
+            gi = w.pidx[cur][lane];
+        }
         wave_amax_sum(gm, gi, gs);
         if (t == 0) tol2 = J.rel_tol2 * gs;
         int stop = (t >= rmax) || (gm <= 0.0) || (gs <= tol2);
