@@ -788,7 +788,7 @@ __host__ __device__ inline PrrluWs prrlu_ws_split(double *ws, int n, int nblk) {
     return w;
 }
 
-constexpr int kMwThreads = 256, kMwTW = 8, kMwK = 2;
+constexpr int kMwThreads = 256, kMwTW = 8, kMwK = 2, kMwKBig = 8, kMwBigMinBlk = 128;
 
 __device__ __forceinline__ void prrlu_mw_init_body(const PrrluJob &J) {
     const PrrluWs w = prrlu_ws_split(J.ws, J.n, J.nblk);
@@ -799,14 +799,16 @@ __device__ __forceinline__ void prrlu_mw_init_body(const PrrluJob &J) {
     J.info[0] = -1.0;  // not finished: the host launches further steps
 }
 
-// Workgroup b owns a stripe of J.rows = RS * kMwK rows; thread (tr, tc) holds the kMwTW columns
-// [8 tc, 8 tc + 8) of rows r0 + tr + k RS, k < kMwK, with RS = 256 / ceil(n / 8). The stripe is
+// Workgroup b owns a stripe of J.rows = RS * K rows; thread (tr, tc) holds the kMwTW columns
+// [8 tc, 8 tc + 8) of rows r0 + tr + k RS, k < K, with RS = 256 / ceil(n / 8); K = K, or
+// KBig for tall blocks (more loads in flight per thread, fewer workgroups per step). The stripe is
 // loaded before the decision (it does not depend on it); the candidate row a workgroup leaves
 // for the next launch comes from the registers of the threads that hold it.
 constexpr int kMwCand = 2048;  // doubles: the widest pivot row (n <= 256 * 8)
 
+template <int K>
 __device__ __forceinline__ void prrlu_mw_step_body(const PrrluJob &J, int t) {
-    __shared__ double lc[kMwThreads * kMwK];
+    __shared__ double lc[kMwThreads * K];
     __shared__ double u[kMwCand];
     __shared__ double wmax[kMwThreads / kWave], wsum[kMwThreads / kWave];
     __shared__ long long widx[kMwThreads / kWave];
@@ -823,9 +825,9 @@ __device__ __forceinline__ void prrlu_mw_step_body(const PrrluJob &J, int t) {
     const bool active = tr < RS;
     const int r0 = blockIdx.x * J.rows;
     const int cur = t & 1, prev = cur ^ 1;
-    double a[kMwK][kMwTW];
+    double a[K][kMwTW];
 #pragma unroll
-    for (int k = 0; k < kMwK; ++k) {
+    for (int k = 0; k < K; ++k) {
         const int row = r0 + tr + k * RS;
         const bool rv = active && row < m;
 #pragma unroll
@@ -895,7 +897,7 @@ __device__ __forceinline__ void prrlu_mw_step_body(const PrrluJob &J, int t) {
             for (int j = 0; j < kMwTW; ++j)
                 if (c0 + j == pj)
 #pragma unroll
-                    for (int k = 0; k < kMwK; ++k) lc[tr + k * RS] = a[k][j];
+                    for (int k = 0; k < K; ++k) lc[tr + k * RS] = a[k][j];
         }
         __syncthreads();
         const double inv = 1.0 / urow[pj];
@@ -904,7 +906,7 @@ __device__ __forceinline__ void prrlu_mw_step_body(const PrrluJob &J, int t) {
 #pragma unroll
             for (int j = 0; j < kMwTW; ++j) uu[j] = c0 + j < n ? urow[c0 + j] : 0.0;
 #pragma unroll
-            for (int k = 0; k < kMwK; ++k) {
+            for (int k = 0; k < K; ++k) {
                 const int row = r0 + tr + k * RS;
                 if (row >= m) continue;
                 const double l = row == pi ? 1.0 : lc[tr + k * RS] * inv;
@@ -922,10 +924,10 @@ __device__ __forceinline__ void prrlu_mw_step_body(const PrrluJob &J, int t) {
                 for (int j = 0; j < kMwTW; ++j)
                     if (c0 + j == pj)
 #pragma unroll
-                        for (int k = 0; k < kMwK; ++k) a[k][j] = 0.0;
+                        for (int k = 0; k < K; ++k) a[k][j] = 0.0;
             }
 #pragma unroll
-            for (int k = 0; k < kMwK; ++k) {
+            for (int k = 0; k < K; ++k) {
                 const int row = r0 + tr + k * RS;
                 if (row >= m) continue;
 #pragma unroll
@@ -937,7 +939,7 @@ __device__ __forceinline__ void prrlu_mw_step_body(const PrrluJob &J, int t) {
     double lmax = -1.0, lsum = 0.0;
     long long lidx = 0x7fffffffffffffffLL;
 #pragma unroll
-    for (int k = 0; k < kMwK; ++k) {
+    for (int k = 0; k < K; ++k) {
         const long long rb = (long long)(r0 + tr + k * RS) * n + c0;
 #pragma unroll
         for (int j = 0; j < kMwTW; ++j) {
@@ -974,7 +976,7 @@ __device__ __forceinline__ void prrlu_mw_step_body(const PrrluJob &J, int t) {
         if (local % RS == tr) {
             double *dst = w.prow[cur] + (long long)blockIdx.x * n;
 #pragma unroll
-            for (int k = 0; k < kMwK; ++k)
+            for (int k = 0; k < K; ++k)
                 if (k == local / RS)
 #pragma unroll
                     for (int j = 0; j < kMwTW; ++j)
@@ -1183,19 +1185,21 @@ __global__ __launch_bounds__(kMwThreads) void k_prrlu_coop_batch(const PrrluJob 
 
 __global__ void k_prrlu_mw_init(PrrluJob J) { prrlu_mw_init_body(J); }
 
-__global__ __launch_bounds__(kMwThreads) void k_prrlu_mw_step(PrrluJob J, int t) { prrlu_mw_step_body(J, t); }
+template <int K>
+__global__ __launch_bounds__(kMwThreads) void k_prrlu_mw_step(PrrluJob J, int t) { prrlu_mw_step_body<K>(J, t); }
 
 __global__ void k_prrlu_mw_init_batch(const PrrluJob *__restrict__ jobs, int njobs) {
     const int z = blockIdx.x * blockDim.x + threadIdx.x;
     if (z < njobs && jobs[z].mode >= 1) prrlu_mw_init_body(jobs[z]);
 }
 
-// Steps the jobs of modes 1 .. max_mode (2 also when the persistent launch is not used).
+// Steps the jobs of the modes in mode_mask (bit m: mode m) whose stripes hold K rows per thread.
+template <int K>
 __global__ __launch_bounds__(kMwThreads) void k_prrlu_mw_step_batch(const PrrluJob *__restrict__ jobs, int t,
-                                                                     int max_mode) {
+                                                                     int mode_mask) {
     const PrrluJob J = jobs[blockIdx.y];
-    if (J.mode < 1 || J.mode > max_mode || (int)blockIdx.x >= J.nblk) return;
-    prrlu_mw_step_body(J, t);
+    if (!((mode_mask >> J.mode) & 1) || (int)blockIdx.x >= J.nblk) return;
+    prrlu_mw_step_body<K>(J, t);
 }
 
 // Single-workgroup form: the whole block stays in registers for all pivot steps. Thread tid
@@ -1909,8 +1913,11 @@ int coop_capacity() {
     return cap;
 }
 
-// mode 0: one workgroup, register tiles; 1: multi-workgroup, one launch per step; 2: as 1, and
-// small enough for the persistent single launch.
+// mode 0: one workgroup, register tiles; 1: multi-workgroup stripes of kMwK rows per thread,
+// one launch per step; 2: as 1, small enough for the persistent single launch (stepped as 1
+// when the device cannot hold the grid); 3: stripes of kMwKBig rows per thread, one launch per
+// step, for blocks tall enough to fill the device with them (measured on 20480 x 180: 23 us per
+// step against 25; on 4096 x 180 the longer stripes leave too few workgroups: 17 against 10).
 void prrlu_prepare(PrrluJob &j) {
     j.shape = tile_shape_for(j.m, j.n);
     const int tpr = (j.n + kMwTW - 1) / kMwTW;
@@ -1918,7 +1925,17 @@ void prrlu_prepare(PrrluJob &j) {
                 "pivot block wider than the multi-workgroup form supports");
     j.rows = (kMwThreads / tpr) * kMwK;
     j.nblk = (j.m + j.rows - 1) / j.rows;
-    j.mode = j.shape >= 0 ? 0 : (j.nblk <= kCoopMaxBlk ? 2 : 1);
+    if (j.shape >= 0) {
+        j.mode = 0;
+    } else if (j.nblk <= kCoopMaxBlk) {
+        j.mode = 2;
+    } else if (j.nblk < 4 * kMwBigMinBlk) {
+        j.mode = 1;
+    } else {  // tall enough that the longer stripes still give kMwBigMinBlk workgroups or more
+        j.mode = 3;
+        j.rows = (kMwThreads / tpr) * kMwKBig;
+        j.nblk = (j.m + j.rows - 1) / j.rows;
+    }
 }
 
 size_t prrlu_ws_doubles(int m, int n) {
@@ -1952,7 +1969,10 @@ int prrlu(hipStream_t s, int m, int n, double *A, int rmax, double rel_tol2, int
     // launch t decides pivot t - 1, so the last possible decision (stop at rmax) is launch rmax + 1
     if (t_begin == 0) k_prrlu_mw_init<<<1, 1, 0, s>>>(j);
     const int last = std::min(t_end, rmax + 1);
-    for (int t = t_begin; t <= last; ++t) k_prrlu_mw_step<<<j.nblk, kMwThreads, 0, s>>>(j, t);
+    for (int t = t_begin; t <= last; ++t) {
+        if (j.mode == 3) k_prrlu_mw_step<kMwKBig><<<j.nblk, kMwThreads, 0, s>>>(j, t);
+        else k_prrlu_mw_step<kMwK><<<j.nblk, kMwThreads, 0, s>>>(j, t);
+    }
     WTT_HIP(hipGetLastError());
     return last + 1;
 }
@@ -2011,12 +2031,16 @@ size_t gemm_tn_splitk_part(int M, int N, int K, int batch) {
 void prrlu_batch(hipStream_t s, int njobs, const PrrluJob *host_jobs, const PrrluJob *dev_jobs, int t_begin,
                  int t_end) {
     if (njobs <= 0) return;
-    int maxblk = 0, nmw = 0, maxcoop = 0, ncoop = 0;
+    int maxblk = 0, nmw = 0, maxcoop = 0, ncoop = 0, maxbig = 0, nbig = 0;
     int lds_shape[kNumTileShapes] = {};  // LDS bytes per tile shape in use (0: unused)
     for (int i = 0; i < njobs; ++i) {
         const PrrluJob &j = host_jobs[i];
         if (j.mode == 0) {
             lds_shape[j.shape] = std::max(lds_shape[j.shape], (int)(sizeof(double) * (size_t)(j.m + j.n)));
+        } else if (j.mode == 3) {
+            maxbig = std::max(maxbig, j.nblk);
+            ++nbig;
+            ++nmw;
         } else {
             maxblk = std::max(maxblk, j.nblk);
             ++nmw;
@@ -2037,9 +2061,12 @@ void prrlu_batch(hipStream_t s, int njobs, const PrrluJob *host_jobs, const Prrl
     if (nmw) {
         if (t_begin == 0) k_prrlu_mw_init_batch<<<cdiv(njobs, 64), 64, 0, s>>>(dev_jobs, njobs);
         if (coop) k_prrlu_coop_batch<<<dim3(maxcoop, njobs), kMwThreads, 0, s>>>(dev_jobs);
-        if (!coop || nmw > ncoop)
-            for (int t = t_begin; t <= t_end; ++t)
-                k_prrlu_mw_step_batch<<<dim3(maxblk, njobs), kMwThreads, 0, s>>>(dev_jobs, t, coop ? 1 : 2);
+        const bool small = maxblk > 0 && (!coop || nmw - nbig > ncoop);  // mode 1, or mode 2 stepped
+        for (int t = t_begin; t <= t_end; ++t) {
+            if (small)
+                k_prrlu_mw_step_batch<kMwK><<<dim3(maxblk, njobs), kMwThreads, 0, s>>>(dev_jobs, t, coop ? 2 : 6);
+            if (nbig) k_prrlu_mw_step_batch<kMwKBig><<<dim3(maxbig, njobs), kMwThreads, 0, s>>>(dev_jobs, t, 8);
+        }
     }
     WTT_HIP(hipGetLastError());
 }
