@@ -785,7 +785,9 @@ FluxTT cross_generic(wenott_ctx *c, const CrossTarget &t, double eps, CrossStat 
             ISet Rk = k < d - 1 ? with_kick(Rset[k], rng, kick_now, k + 1, M) : Rset[k];
             const int p = Lset[k].count, q = Rk.count;
             const long long rows = (long long)p * M[k], cols = (long long)q * nc;
-            double *B = c->sc.get<double>(S_BLOCK, (size_t)(rows * cols));
+            // the last core is the block itself: evaluated straight into its allocation
+            double *B = k < d - 1 ? c->sc.get<double>(S_BLOCK, (size_t)(rows * cols))
+                                  : (F.core[k] = dalloc<double>(c->s, (size_t)(rows * cols)));
             t.eval(k, Lset[k], Rk, true, B);
             if (k < d - 1) {
                 double *L = nullptr;
@@ -810,9 +812,6 @@ FluxTT cross_generic(wenott_ctx *c, const CrossTarget &t, double eps, CrossStat 
                 }
                 Lset[k + 1] = std::move(nl);
                 st.maxrank = std::max(st.maxrank, r);
-            } else {
-                F.core[k] = dalloc<double>(c->s, (size_t)(rows * cols));
-                WTT_HIP(hipMemcpyAsync(F.core[k], B, sizeof(double) * rows * cols, hipMemcpyDeviceToDevice, c->s));
             }
         }
         resid = t.residual(F, rng);

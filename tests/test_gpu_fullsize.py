@@ -88,3 +88,26 @@ def test_quadrants_512_batch_matches_single_and_oracle(W):
     finally:
         for s in batch + single:
             s.close()
+
+
+def test_blast_full_size_single_state_steps_vs_oracle(W):
+    """One spherical blast of the batched workload at its full size (256 x 192 x 128, seed 0,
+    dynamic eps from 1e-6), stepped on its own: its ranks reach ~120 in the first step, so the
+    cross blocks (10^6-10^7 entries) take the multi-workgroup pivot search one launch per step
+    and the TSQR of the wide unfoldings; the step against the oracle on the full grid (observed
+    2.7 eps; a second step, not run here, gave 7.8 eps)."""
+    _say("case: blast 256 x 192 x 128 (seed 0), a single-state step against the oracle")
+    f = workloads.config4_blast_3d(seed=0)
+    s = W.Solver(f, W.default_opts(eps_mode=1, eps0=f.eps0))
+    P = oracle_problem(f)
+    try:
+        u = s.dense()
+        dt = f.cfl * min(f.h) / s.max_wavespeed()
+        s.step(dt)
+        info = s.info()
+        P.ssprk3(u, dt, alphas=[info.alpha[j] for j in range(3)])
+        err = rel_err(s.dense(), u)
+        _say(f"  ranks={list(info.ranks)[:4]} eps={info.eps:.2e} err={err:.3e}")
+        assert err <= 10 * info.eps, (err, info.eps)
+    finally:
+        s.close()
