@@ -170,12 +170,13 @@ void iface(hipStream_t s, const FiberGeom &g, int side, const double *const *cor
 // terms use FP64 values: X0[c][a][i][b] (X itself) and WN (Un, read only when wn != 0).
 template <typename T>
 struct StageArgsT {
-    const T *W0;
+    const T *W0;  // X at the block points, [c][a][i][b] with component stride w0_cs
     const T *Wd[kMaxDim];
-    const double *X0;
-    const double *WN;
+    const double *X0;  // the same values in FP64 (same layout as W0)
+    const double *WN;  // Un at the block points, [c][a][i][b] (component stride p Nk q)
     double wn, wx, wl;
     double inv_h[kMaxDim], eps_w[kMaxDim];
+    long long w0_cs;  // p Nk q for a separate gather; 7 p Nk q when W0 is the centre slice of a Wd
 };
 template <typename T>
 void stage_block(hipStream_t s, const FiberGeom &g, int p, int q, const StageArgsT<T> &a, double *out, long long sa,

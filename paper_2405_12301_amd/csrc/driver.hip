@@ -967,9 +967,11 @@ void eval_stage_block(wenott_ctx *c, const TT &X, const TT *Un, StageWeights w, 
     StageArgsT<double> a{};
     StageArgsT<float> a32{};
     const bool fp32 = c->o.precision == 1;
-    a.W0 = gather(X, -1, S_P, S_Q, S_T, S_W);
-    a.X0 = a.W0;
-    if (fp32) {
+    const long long blk = (long long)p * Nk * q;
+    a.w0_cs = a32.w0_cs = blk;
+    if (fp32) {  // the FP64 values of X at the block points for the combination, FP32 for the fluxes
+        a.W0 = gather(X, -1, S_P, S_Q, S_T, S_W);
+        a.X0 = a.W0;
         a32.W0 = gather32(X, -1, S_F_W0);
         a32.X0 = a.W0;
     }
@@ -978,11 +980,17 @@ void eval_stage_block(wenott_ctx *c, const TT &X, const TT *Un, StageWeights w, 
         a.inv_h[dd] = a32.inv_h[dd] = 1.0 / c->h[dd];
         a.eps_w[dd] = a32.eps_w[dd] = c->h[dd] * c->h[dd];
         if (dd == k) continue;
-        if (fp32)
+        if (fp32) {
             a32.Wd[dd] = gather32(X, dd, od == 0 ? S_F_WD0 : S_F_WD1);
-        else
+        } else {
             a.Wd[dd] = gather(X, dd, od == 0 ? S_PD0 : S_PD1, od == 0 ? S_QD0 : S_QD1, od == 0 ? S_TD0 : S_TD1,
                               od == 0 ? S_WD0 : S_WD1);
+            if (od == 0) {  // X at the block points is the unshifted (centre) slice of this gather
+                a.W0 = a.Wd[dd] + 3 * blk;
+                a.X0 = a.W0;
+                a.w0_cs = 7 * blk;
+            }
+        }
         ++od;
     }
     a.WN = nullptr;

@@ -408,7 +408,7 @@ __global__ __launch_bounds__(256) void k_stage(FiberGeom g, int p, int q, StageA
             for (int s = 0; s < 7; ++s) {
                 const int cell = ghost_map(i - 3 + s, Nk, g.bc[g.k]);
 #pragma unroll
-                for (int c = 0; c < NC; ++c) v[c][s] = sa_.W0[(((long long)c * p + a) * Nk + cell) * q + b];
+                for (int c = 0; c < NC; ++c) v[c][s] = sa_.W0[c * sa_.w0_cs + ((long long)a * Nk + cell) * q + b];
             }
         } else {
             const T *W = sa_.Wd[d];
@@ -424,7 +424,7 @@ __global__ __launch_bounds__(256) void k_stage(FiberGeom g, int p, int q, StageA
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
         const long long idx = (((long long)c * p + a) * Nk + i) * q + b;
-        double y = sa_.wx * sa_.X0[idx] + sa_.wl * (double)acc[c];
+        double y = sa_.wx * sa_.X0[c * sa_.w0_cs + ((long long)a * Nk + i) * q + b] + sa_.wl * (double)acc[c];
         if (sa_.wn != 0.0) y += sa_.wn * sa_.WN[idx];
         finite &= (y == y) && fabs(y) < 1e300;
         o[c * sc] = y;
