@@ -188,6 +188,22 @@ __global__ __launch_bounds__(256) void k_weno(FiberGeom g, int p, int M, int q, 
     if (!finite) atomicOr(flags, kFlagNaN);
 }
 
+// sum_t x[t sx] y[t sy], t < n, in four interleaved chains so that the loads of several terms
+// are in flight at once (the operands come from L2)
+__device__ inline double dot4(const double *__restrict__ x, long long sx, const double *__restrict__ y, long long sy,
+                              int n) {
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int t = 0;
+    for (; t + 3 < n; t += 4) {
+        a0 = fma(x[t * sx], y[t * sy], a0);
+        a1 = fma(x[(t + 1) * sx], y[(t + 1) * sy], a1);
+        a2 = fma(x[(t + 2) * sx], y[(t + 2) * sy], a2);
+        a3 = fma(x[(t + 3) * sx], y[(t + 3) * sy], a3);
+    }
+    for (; t < n; ++t) a0 = fma(x[t * sx], y[t * sy], a0);
+    return (a0 + a1) + (a2 + a3);
+}
+
 template <int ND>
 __global__ __launch_bounds__(256) void k_dense_eval(int mode, int ncomp, long long nrows, int R, int nlast,
                                                     const double *__restrict__ Lm, long long lm_stride,
@@ -213,13 +229,7 @@ __global__ __launch_bounds__(256) void k_dense_eval(int mode, int ncomp, long lo
         }
         double qv[NC];
 #pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            const double *l = Lm + c * lm_stride + row * R;
-            const double *gg = G + c * g_stride + j;
-            double acc = 0.0;
-            for (int al = 0; al < R; ++al) acc += l[al] * gg[(long long)al * nlast];
-            qv[c] = acc;
-        }
+        for (int c = 0; c < NC; ++c) qv[c] = dot4(Lm + c * lm_stride + row * R, 1, G + c * g_stride + j, nlast, R);
         if (mode == 0) {
 #pragma unroll
             for (int c = 0; c < NC; ++c) out[c * ncell + e] = qv[c];
@@ -262,17 +272,14 @@ __device__ inline double tt_point(const CoreSet &cs, int c, const int *cell) {
     const double *G0 = cs.c[0] + c * cs.cstride[0];
     const double *G1 = cs.c[1] + c * cs.cstride[1];
     if (ND == 2) {
-        double acc = 0.0;
-        for (int al = 0; al < cs.R[1]; ++al) acc += G0[(long long)cell[0] * cs.R[1] + al] * G1[(long long)al * cs.N[1] + cell[1]];
-        return acc;
+        return dot4(G0 + (long long)cell[0] * cs.R[1], 1, G1 + cell[1], cs.N[1], cs.R[1]);
     } else {
         const double *G2 = cs.c[2] + c * cs.cstride[2];
         double acc = 0.0;
         for (int be = 0; be < cs.R[2]; ++be) {
-            double v = 0.0;
-            for (int al = 0; al < cs.R[1]; ++al)
-                v += G0[(long long)cell[0] * cs.R[1] + al] * G1[((long long)al * cs.N[1] + cell[1]) * cs.R[2] + be];
-            acc += v * G2[(long long)be * cs.N[2] + cell[2]];
+            const double v = dot4(G0 + (long long)cell[0] * cs.R[1], 1, G1 + (long long)cell[1] * cs.R[2] + be,
+                                  (long long)cs.N[1] * cs.R[2], cs.R[1]);
+            acc = fma(v, G2[(long long)be * cs.N[2] + cell[2]], acc);
         }
         return acc;
     }
@@ -318,11 +325,9 @@ __global__ __launch_bounds__(256) void k_sample_flux(FiberGeom g, CoreSet fs, in
         double approx[NC];
         for (int c = 0; c < NC; ++c) approx[c] = 0.0;
         if (ND == 2) {
-            for (int al = 0; al < fs.R[1]; ++al) {
-                double l = fs.c[0][(long long)m[0] * fs.R[1] + al];
-                const double *last = fs.c[1] + ((long long)al * fs.N[1] + m[1]) * NC;
-                for (int c = 0; c < NC; ++c) approx[c] += l * last[c];
-            }
+            for (int c = 0; c < NC; ++c)
+                approx[c] = dot4(fs.c[0] + (long long)m[0] * fs.R[1], 1, fs.c[1] + (long long)m[1] * NC + c,
+                                 (long long)fs.N[1] * NC, fs.R[1]);
         } else {
             for (int be = 0; be < fs.R[2]; ++be) {
                 double v = 0.0;
@@ -585,11 +590,9 @@ __global__ __launch_bounds__(256) void k_sample_stage(FiberGeom g, CoreSet fs, i
         double approx[NC];
         for (int c = 0; c < NC; ++c) approx[c] = 0.0;
         if (ND == 2) {
-            for (int al = 0; al < fs.R[1]; ++al) {
-                double l = fs.c[0][(long long)m[0] * fs.R[1] + al];
-                const double *last = fs.c[1] + ((long long)al * fs.N[1] + m[1]) * NC;
-                for (int c = 0; c < NC; ++c) approx[c] += l * last[c];
-            }
+            for (int c = 0; c < NC; ++c)
+                approx[c] = dot4(fs.c[0] + (long long)m[0] * fs.R[1], 1, fs.c[1] + (long long)m[1] * NC + c,
+                                 (long long)fs.N[1] * NC, fs.R[1]);
         } else {
             for (int be = 0; be < fs.R[2]; ++be) {
                 double v = 0.0;

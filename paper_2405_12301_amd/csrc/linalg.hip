@@ -1503,9 +1503,9 @@ __device__ __forceinline__ void chol_inv_body(int r, const double *__restrict__ 
 
 // One wave per matrix for r <= 64, everything in LDS (leading dimension r + 1): right-looking
 // Cholesky with lane i owning column i (row j of R, then the trailing update of column i), then
-// R^{-1} by back substitution, lane i forming column i. The same arithmetic as above (a column
-// whose pivot is not above 0.5 is a zero padding column with a unit diagonal); the sums run in
-// another order.
+// R^{-1} by back substitution, lane i forming column i; the loops go four rows at a time so
+// that their LDS loads overlap. The same arithmetic as above (a column whose pivot is not above
+// 0.5 is a zero padding column with a unit diagonal); the sums run in another order.
 constexpr int kCholWaveMax = 63;  // 2 r (r + 1) doubles of LDS stay within 64 KB
 
 __device__ __forceinline__ void chol_inv_wave_body(int r, const double *__restrict__ G, double *__restrict__ X) {
@@ -1525,16 +1525,35 @@ __device__ __forceinline__ void chol_inv_wave_body(int r, const double *__restri
         }
         if (lane == j) A[j * ld + j] = rjj;
         __syncthreads();
-        if (lane > j && lane < r)
-            for (int k = j + 1; k <= lane; ++k) A[k * ld + lane] = fma(-A[j * ld + k], rji, A[k * ld + lane]);
+        if (lane > j && lane < r) {  // four rows at a time, so that their loads overlap
+            int k = j + 1;
+            for (; k + 3 <= lane; k += 4) {
+                const double r0 = A[j * ld + k], r1 = A[j * ld + k + 1], r2 = A[j * ld + k + 2],
+                             r3 = A[j * ld + k + 3];
+                const double a0 = A[k * ld + lane], a1 = A[(k + 1) * ld + lane], a2 = A[(k + 2) * ld + lane],
+                             a3 = A[(k + 3) * ld + lane];
+                A[k * ld + lane] = fma(-r0, rji, a0);
+                A[(k + 1) * ld + lane] = fma(-r1, rji, a1);
+                A[(k + 2) * ld + lane] = fma(-r2, rji, a2);
+                A[(k + 3) * ld + lane] = fma(-r3, rji, a3);
+            }
+            for (; k <= lane; ++k) A[k * ld + lane] = fma(-A[j * ld + k], rji, A[k * ld + lane]);
+        }
         __syncthreads();
     }
     if (lane < r) {
         const int i = lane;
         for (int j = i; j >= 0; --j) {
-            double v = (j == i) ? 1.0 : 0.0;
-            for (int k = j + 1; k <= i; ++k) v = fma(-A[j * ld + k], Xs[k * ld + i], v);
-            Xs[j * ld + i] = v / A[j * ld + j];
+            double v0 = (j == i) ? 1.0 : 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;  // four chains
+            int k = j + 1;
+            for (; k + 3 <= i; k += 4) {
+                v0 = fma(-A[j * ld + k], Xs[k * ld + i], v0);
+                v1 = fma(-A[j * ld + k + 1], Xs[(k + 1) * ld + i], v1);
+                v2 = fma(-A[j * ld + k + 2], Xs[(k + 2) * ld + i], v2);
+                v3 = fma(-A[j * ld + k + 3], Xs[(k + 3) * ld + i], v3);
+            }
+            for (; k <= i; ++k) v0 = fma(-A[j * ld + k], Xs[k * ld + i], v0);
+            Xs[j * ld + i] = ((v0 + v1) + (v2 + v3)) / A[j * ld + j];
         }
     }
     __syncthreads();
