@@ -685,7 +685,8 @@ __device__ void jacobi_sweeps_small(int n, double *X, int *nrot, double *nrm, do
 }
 
 __device__ __forceinline__ void jacobi_run(int n, double *X, int *nrot, double *nrm, double eta) {
-    if (n <= 64 && blockDim.x == 1024) jacobi_sweeps_small(n, X, nrot, nrm, eta);
+    // the half-wave form needs a half-wave per pair: (n + 1) / 2 <= 2 blockDim.x / 64
+    if (n <= 64 && (n + 1) / 2 <= (int)(blockDim.x / 32)) jacobi_sweeps_small(n, X, nrot, nrm, eta);
     else jacobi_sweeps(n, X, nrot, nrm, eta);
 }
 
@@ -1903,12 +1904,20 @@ void tsqr_r(hipStream_t s, int m, int n, int batch, const double *A, long long s
     }
 }
 
+// Threads of a Jacobi workgroup: as few waves as give every column pair of a round its own
+// half-wave (fewer waves at each round's barrier), else 1024.
+int jacobi_threads(int n) {
+    if (n > 64) return 1024;
+    const int waves = std::max(1, ((n + 1) / 2 + 1) / 2);
+    return std::min(1024, 64 * waves);
+}
+
 void jacobi_svd(hipStream_t s, int n, int batch, const double *R, double *sigma, double *V, double *scratch,
                 const double *delta) {
     // static LDS of the kernel: the column-norm buffer (512 doubles) and a counter
     const size_t lds = sizeof(double) * (size_t)n * n;
     if (n <= 512 && lds + 512 * sizeof(double) + 64 <= (size_t)lds_limit_bytes())
-        k_jacobi_lds<<<batch, 1024, lds, s>>>(n, R, sigma, V, delta);
+        k_jacobi_lds<<<batch, jacobi_threads(n), lds, s>>>(n, R, sigma, V, delta);
     else
         k_jacobi_global<<<batch, 1024, 0, s>>>(n, R, sigma, V, scratch, delta);
     WTT_HIP(hipGetLastError());
@@ -2098,7 +2107,7 @@ bool jacobi_batch_fits(int nmax) {
 void jacobi_svd_batch(hipStream_t s, int njobs, int ncomp, int nmax, const SvdJob *dev_jobs) {
     if (njobs <= 0) return;
     const size_t lds = sizeof(double) * (size_t)nmax * nmax;
-    k_jacobi_lds_batch<<<dim3(njobs, ncomp), 1024, lds, s>>>(dev_jobs);
+    k_jacobi_lds_batch<<<dim3(njobs, ncomp), jacobi_threads(nmax), lds, s>>>(dev_jobs);
     WTT_HIP(hipGetLastError());
 }
 
