@@ -324,10 +324,24 @@ __global__ __launch_bounds__(256) void k_sample_flux(FiberGeom g, CoreSet fs, in
         const int *m = pts + pt * ND;
         double approx[NC];
         for (int c = 0; c < NC; ++c) approx[c] = 0.0;
-        if (ND == 2) {
-            for (int c = 0; c < NC; ++c)
-                approx[c] = dot4(fs.c[0] + (long long)m[0] * fs.R[1], 1, fs.c[1] + (long long)m[1] * NC + c,
-                                 (long long)fs.N[1] * NC, fs.R[1]);
+        if (ND == 2) {  // two rank terms per pass, each with its own accumulators
+            const double *g0 = fs.c[0] + (long long)m[0] * fs.R[1];
+            const double *g1 = fs.c[1] + (long long)m[1] * NC;
+            const long long st1 = (long long)fs.N[1] * NC;
+            double ap2[NC];
+            for (int c = 0; c < NC; ++c) ap2[c] = 0.0;
+            int al = 0;
+            for (; al + 1 < fs.R[1]; al += 2) {
+                const double l0 = g0[al], l1 = g0[al + 1];
+                const double *a0 = g1 + al * st1, *a1 = a0 + st1;
+                for (int c = 0; c < NC; ++c) {
+                    approx[c] = fma(l0, a0[c], approx[c]);
+                    ap2[c] = fma(l1, a1[c], ap2[c]);
+                }
+            }
+            if (al < fs.R[1])
+                for (int c = 0; c < NC; ++c) approx[c] = fma(g0[al], g1[al * st1 + c], approx[c]);
+            for (int c = 0; c < NC; ++c) approx[c] += ap2[c];
         } else {
             for (int be = 0; be < fs.R[2]; ++be) {
                 double v = 0.0;
@@ -439,6 +453,8 @@ __global__ __launch_bounds__(256) void k_stage(FiberGeom g, int p, int q, StageA
 }
 
 // X at the 7 d star cells (slot d * 7 + s) of every point; cs2 (Un) at slot 7 d when given.
+// Layout ust[(slot * NC + c) * npts + pt]: the point is the fastest index, so that the stage
+// kernel (one point per thread) reads it coalesced.
 template <int ND>
 __global__ void k_sample_star(FiberGeom g, CoreSet cs, CoreSet un, int use_un, int npts, const int *__restrict__ pts,
                               double *__restrict__ ust) {
@@ -446,9 +462,9 @@ __global__ void k_sample_star(FiberGeom g, CoreSet cs, CoreSet un, int use_un, i
     constexpr int SL = 7 * ND + 1;
     long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (e >= (long long)npts * SL * NC) return;
-    const int c = (int)(e % NC);
-    const int slot = (int)((e / NC) % SL);
-    const int pt = (int)(e / ((long long)NC * SL));
+    const int pt = (int)(e % npts);
+    const int c = (int)((e / npts) % NC);
+    const int slot = (int)(e / ((long long)npts * NC));
     int cell[ND];
 #pragma unroll
     for (int d = 0; d < ND; ++d) cell[d] = pts[pt * ND + d];
@@ -561,7 +577,7 @@ __global__ __launch_bounds__(256) void k_sample_star3(FiberGeom g, CoreSet cs, C
         un_part = block_sum256(un_part, red);
         if (tid == 0) vals[21] = use_un ? un_part : 0.0;
         __syncthreads();
-        for (int q = tid; q < SL; q += 256) ust[((long long)pt * SL + q) * NC + c] = vals[q];
+        for (int q = tid; q < SL; q += 256) ust[((long long)q * NC + c) * npts + pt] = vals[q];
         __syncthreads();
     }
 }
@@ -577,22 +593,36 @@ __global__ __launch_bounds__(256) void k_sample_stage(FiberGeom g, CoreSet fs, i
     double d2 = 0.0, n2 = 0.0;
     bool ok = true;
     if (pt < npts) {
-        const double *u = ust + (long long)pt * SL * NC;
+        const double *u = ust + pt;  // slot q, component c at u[(q * NC + c) * npts]
         double L[NC];
         for (int c = 0; c < NC; ++c) L[c] = 0.0;
         for (int d = 0; d < ND; ++d) {
             double v[NC][7];
             for (int s = 0; s < 7; ++s)
-                for (int c = 0; c < NC; ++c) v[c][s] = u[(d * 7 + s) * NC + c];
+                for (int c = 0; c < NC; ++c) v[c][s] = u[((long long)(d * 7 + s) * NC + c) * npts];
             ok &= stage_dir<ND, double>(v, d, g.gamma - 1.0, geom_alpha(g), hs.eps_w[d], hs.inv_h[d], L);
         }
         const int *m = pts + pt * ND;
         double approx[NC];
         for (int c = 0; c < NC; ++c) approx[c] = 0.0;
-        if (ND == 2) {
-            for (int c = 0; c < NC; ++c)
-                approx[c] = dot4(fs.c[0] + (long long)m[0] * fs.R[1], 1, fs.c[1] + (long long)m[1] * NC + c,
-                                 (long long)fs.N[1] * NC, fs.R[1]);
+        if (ND == 2) {  // two rank terms per pass, each with its own accumulators
+            const double *g0 = fs.c[0] + (long long)m[0] * fs.R[1];
+            const double *g1 = fs.c[1] + (long long)m[1] * NC;
+            const long long st1 = (long long)fs.N[1] * NC;
+            double ap2[NC];
+            for (int c = 0; c < NC; ++c) ap2[c] = 0.0;
+            int al = 0;
+            for (; al + 1 < fs.R[1]; al += 2) {
+                const double l0 = g0[al], l1 = g0[al + 1];
+                const double *a0 = g1 + al * st1, *a1 = a0 + st1;
+                for (int c = 0; c < NC; ++c) {
+                    approx[c] = fma(l0, a0[c], approx[c]);
+                    ap2[c] = fma(l1, a1[c], ap2[c]);
+                }
+            }
+            if (al < fs.R[1])
+                for (int c = 0; c < NC; ++c) approx[c] = fma(g0[al], g1[al * st1 + c], approx[c]);
+            for (int c = 0; c < NC; ++c) approx[c] += ap2[c];
         } else {
             for (int be = 0; be < fs.R[2]; ++be) {
                 double v = 0.0;
@@ -603,7 +633,8 @@ __global__ __launch_bounds__(256) void k_sample_stage(FiberGeom g, CoreSet fs, i
             }
         }
         for (int c = 0; c < NC; ++c) {
-            double ex = wx * u[(0 * 7 + 3) * NC + c] + wl * L[c] + (wn != 0.0 ? wn * u[7 * ND * NC + c] : 0.0);
+            double ex = wx * u[((long long)3 * NC + c) * npts] + wl * L[c] +
+                        (wn != 0.0 ? wn * u[((long long)7 * ND * NC + c) * npts] : 0.0);
             d2 += (ex - approx[c]) * (ex - approx[c]);
             n2 += ex * ex;
         }
