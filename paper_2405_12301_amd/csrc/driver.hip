@@ -383,9 +383,11 @@ const double *left_part(wenott_ctx *c, const TT &U, long long *stride) {
 // Pinned host slots read after a later synchronisation: the component norms of the last rounding.
 constexpr int kPinNorms = 4080;
 
-// Enqueue the exact alpha of U into alpha slot `slot` of the status block and a copy of the
-// block head (flag word and alpha slots) to its pinned mirror. Returns the device address.
-double *exact_alpha_launch(wenott_ctx *c, const TT &U, int slot) {
+// Enqueue the exact alpha of U into alpha slot `slot` of the status block and, with readback,
+// a copy of the block head (flag word and alpha slots) to its pinned mirror. Returns the device
+// address. Without readback the head reaches the host with the next status readback (every
+// stage cross makes one: its sampled residual).
+double *exact_alpha_launch(wenott_ctx *c, const TT &U, int slot, bool readback = true) {
     double *dst = c->d_status + kStatusAlpha + slot;
     long long lms = 0;
     const double *Lm = left_part(c, U, &lms);
@@ -398,7 +400,7 @@ double *exact_alpha_launch(wenott_ctx *c, const TT &U, int slot) {
     dense_eval(c->s, 1, U.d, U.nc, nrows, U.R[U.d - 1], nlast, Lm, lms, U.core[U.d - 1], U.cstride(U.d - 1),
                c->gamma, nullptr, part, nblocks, c->d_flags);
     reduce_max_dev(c->s, part, nblocks, dst);
-    status_readback(c, kStatusAlpha + 4);
+    if (readback) status_readback(c, kStatusAlpha + 4);
     return dst;
 }
 
@@ -2023,7 +2025,8 @@ wenott_status wenott_rk3_step(wenott_ctx *c, double dt, double eps_in, const dou
                 else if (c->o.alpha_mode == 2) a = c->o.alpha_given;
                 else if (st == 0 && c->alpha_cache_valid) a = c->alpha_cache;
                 else if (deferred) {
-                    c->alpha_dev = exact_alpha_launch(c, X, st);
+                    // its value reaches the host with the stage cross's residual readback
+                    c->alpha_dev = exact_alpha_launch(c, X, st, false);
                     a = 1.0;  // not used by the kernels while alpha_dev is set
                 } else a = exact_alpha(c, X);
                 if (!deferred) {
