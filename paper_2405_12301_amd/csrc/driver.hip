@@ -1192,7 +1192,9 @@ int svd_ranks(wenott_ctx *c, int m, int n, const double *A, long long sz, long l
 // core becomes (U_r^T G'_k) G_{k+1}. Each truncation keeps the smallest rank whose discarded
 // tail is at most eps ||X_c||_F / sqrt(d-1), so ||X - Y||_F <= eps ||X||_F per component.
 // Returns the Frobenius norms of the components in norms.
-void round_tt(wenott_ctx *c, TT &X, double eps, bool truncate, std::vector<double> &norms) {
+// norms (out): the component norms ||X_c||_F, when want_norms (one transfer; a caller that only
+// needs them at its last rounding skips it for the others).
+void round_tt(wenott_ctx *c, TT &X, double eps, bool truncate, std::vector<double> &norms, bool want_norms = true) {
     const int d = X.d, nc = X.nc;
     hipStream_t s = c->s;
     std::vector<double *> T(d + 1, nullptr);
@@ -1228,7 +1230,8 @@ void round_tt(wenott_ctx *c, TT &X, double eps, bool truncate, std::vector<doubl
         double *dn = c->sc.get<double>(S_NORMS, 2 * (size_t)nc);
         frob_norms(s, nc, (long long)N0 * R1, C0, (long long)N0 * R1, dn, dn + nc,
                    eps / std::sqrt((double)std::max(d - 1, 1)));
-        WTT_HIP(hipMemcpyAsync(c->h_pinned_dbl + kPinNorms, dn, nc * sizeof(double), hipMemcpyDeviceToHost, s));
+        if (want_norms || !truncate || d < 2)
+            WTT_HIP(hipMemcpyAsync(c->h_pinned_dbl + kPinNorms, dn, nc * sizeof(double), hipMemcpyDeviceToHost, s));
         norms.assign(nc, 0.0);
     }
     const double *ddelta = c->sc.get<double>(S_NORMS, 2 * (size_t)nc) + nc;
@@ -1303,7 +1306,7 @@ void round_tt(wenott_ctx *c, TT &X, double eps, bool truncate, std::vector<doubl
     }
     for (int k = 1; k < d; ++k) dfree(s, T[k]);
     // the truncation ranks were read after the norms were copied
-    norms.assign(c->h_pinned_dbl + kPinNorms, c->h_pinned_dbl + kPinNorms + nc);
+    if (want_norms) norms.assign(c->h_pinned_dbl + kPinNorms, c->h_pinned_dbl + kPinNorms + nc);
 }
 
 // ===================================================================== batched stepping
@@ -2053,7 +2056,8 @@ wenott_status wenott_rk3_step(wenott_ctx *c, double dt, double eps_in, const dou
                     for (auto &t : terms) t.release(c->s);
                 }
                 c->info.sum_rank[st] = S.maxrank();
-                round_tt(c, S, eps, true, norms);  // synchronises: the deferred alpha has arrived
+                // synchronises (the deferred alpha has arrived); the norms are needed after the last stage
+                round_tt(c, S, eps, true, norms, st == 2);
                 if (x_owned) X.release(c->s);
                 X = S;
                 x_owned = true;
