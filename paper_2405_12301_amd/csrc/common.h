@@ -107,6 +107,10 @@ size_t prrlu_ws_doubles(int m, int n);
 // X = R^{-1} for the upper Cholesky factor R of each r x r Gram matrix G (batch); ws holds
 // batch * r * r doubles. Zero (padding) columns keep a unit diagonal.
 void chol_upper_inv(hipStream_t s, int r, int batch, const double *G, double *X, double *ws);
+// X = R^{-1} for the upper Cholesky factor of U_z^T U_z, U_z the m x r row-major matrix at
+// U + z sU (X_z at X + z r^2), Gram matrix and factorisation in one launch; false (nothing
+// launched) when r is beyond the fused kernel's limit (32).
+bool gram_chol_inv(hipStream_t s, int m, int r, int batch, const double *U, long long sU, double *X);
 
 // Batched forms: one workgroup per job (and per component for the SVD / Cholesky), the jobs
 // read from a device array; used to step many independent states in lock-step.

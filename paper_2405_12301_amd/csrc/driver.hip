@@ -1274,13 +1274,15 @@ void round_tt(wenott_ctx *c, TT &X, double eps, bool truncate, std::vector<doubl
             double *nk2 = c->sc.get<double>(S_TD1, (size_t)nc * m * r);
             for (int pass = 0; pass < 2; ++pass) {
                 double *src = pass == 0 ? nk : nk2, *dst = pass == 0 ? nk2 : nk;
-                double *Gm = c->sc.get<double>(S_PD0, (size_t)nc * r * r);
                 double *Xi = c->sc.get<double>(S_PD1, (size_t)nc * r * r);
-                double *ws = c->sc.get<double>(S_TD0, (size_t)nc * r * r);
-                size_t pc = gemm_tn_splitk_part(r, r, m, nc);
-                gemm_tn_splitk(s, r, r, m, src, r, src, r, Gm, r, nc, (long long)m * r, (long long)m * r,
-                               (long long)r * r, c->sc.get<double>(S_SPLIT, pc), pc);
-                chol_upper_inv(s, r, nc, Gm, Xi, ws);
+                if (!gram_chol_inv(s, m, r, nc, src, (long long)m * r, Xi)) {
+                    double *Gm = c->sc.get<double>(S_PD0, (size_t)nc * r * r);
+                    double *ws = c->sc.get<double>(S_TD0, (size_t)nc * r * r);
+                    size_t pc = gemm_tn_splitk_part(r, r, m, nc);
+                    gemm_tn_splitk(s, r, r, m, src, r, src, r, Gm, r, nc, (long long)m * r, (long long)m * r,
+                                   (long long)r * r, c->sc.get<double>(S_SPLIT, pc), pc);
+                    chol_upper_inv(s, r, nc, Gm, Xi, ws);
+                }
                 GemmBatch bx;
                 bx.nb1 = nc; bx.sA1 = (long long)m * r; bx.sB1 = (long long)r * r; bx.sC1 = (long long)m * r;
                 gemm_f64(s, false, false, m, r, r, 1.0, src, r, Xi, r, 0.0, dst, r, bx);
@@ -1647,20 +1649,28 @@ void batch_round(std::vector<BState> &bs, std::vector<TT> &Xs) {
         for (size_t z = 0; z < ns; ++z)
             nk2[z] = bs[z].c->sc.get<double>(S_TD1, (size_t)nc * Xs[z].R[k] * Xs[z].N[k] * rr[z]);
         for (int pass = 0; pass < 2; ++pass) {  // ping-pong between nk and nk2, ending in nk
+            int rmax_sep = 0;  // largest rank of the states that take the separate Gram path
             for (size_t z = 0; z < ns; ++z) {
                 wenott_ctx *c = bs[z].c;
                 const int m = Xs[z].R[k] * Xs[z].N[k], r = rr[z];
                 double *src = pass == 0 ? nk[z] : nk2[z];
-                double *Gm = c->sc.get<double>(S_PD0, (size_t)nc * r * r);
                 double *Xi = c->sc.get<double>(S_PD1, (size_t)nc * r * r);
+                if (gram_chol_inv(c->s, m, r, nc, src, (long long)m * r, Xi)) {  // as the single-state path
+                    cj[z] = CholJob{nullptr, Xi, nullptr, r, 0};
+                    continue;
+                }
+                double *Gm = c->sc.get<double>(S_PD0, (size_t)nc * r * r);
                 double *ws = c->sc.get<double>(S_TD0, (size_t)nc * r * r);
                 size_t pc = gemm_tn_splitk_part(r, r, m, nc);
                 gemm_tn_splitk(c->s, r, r, m, src, r, src, r, Gm, r, nc, (long long)m * r, (long long)m * r,
                                (long long)r * r, c->sc.get<double>(S_SPLIT, pc), pc);
                 cj[z] = CholJob{Gm, Xi, ws, r, nc};
+                rmax_sep = std::max(rmax_sep, r);
             }
-            CholJob *dc = bs[0].c->ring.put(cj.data(), cj.size());
-            chol_upper_inv_batch(bs[0].c->s, (int)ns, nc, *std::max_element(rr.begin(), rr.end()), dc);
+            if (rmax_sep > 0) {
+                CholJob *dc = bs[0].c->ring.put(cj.data(), cj.size());
+                chol_upper_inv_batch(bs[0].c->s, (int)ns, nc, rmax_sep, dc);
+            }
             for (size_t z = 0; z < ns; ++z) {
                 wenott_ctx *c = bs[z].c;
                 const int m = Xs[z].R[k] * Xs[z].N[k], r = rr[z];

@@ -1,11 +1,14 @@
 // Dense FP64 linear algebra for the TT hot path on gfx950:
-//  - batched GEMM (LDS-tiled, 64x64 tiles, 256 threads, 4x4 outputs per thread);
+//  - batched GEMM (LDS-tiled vector shapes, or 64x64 tiles on the FP64 matrix cores), tile
+//    shape autotuned per problem bucket;
 //  - Householder TSQR returning the R factor of tall unfoldings (one workgroup per row
-//    block, binary-ish reduction tree of stacked R factors);
-//  - one-sided (Hestenes) Jacobi SVD of the small R factors, one workgroup per matrix;
+//    block, leaves held in registers for up to 64 columns, reduction tree of stacked R factors);
+//  - one-sided (Hestenes) Jacobi SVD of the small R factors (on R^T), one workgroup per matrix;
 //  - full-pivot rank-revealing LU used to choose cross pivots (greedy maximum volume:
-//    each step takes the largest residual entry, found by wavefront reductions);
-//  - the interpolative basis L * inv(L[I, :]) of a cross (Sec. 3.3, CUR / skeleton form).
+//    each step takes the largest residual entry, found by wavefront reductions): one workgroup
+//    with the block in registers, a persistent multi-workgroup form, or one launch per step;
+//  - the interpolative basis L * inv(L[I, :]) of a cross (Sec. 3.3, CUR / skeleton form);
+//  - CholeskyQR factors (Gram matrix, Cholesky, inverse) for re-orthonormalising a basis.
 #include <algorithm>
 #include <array>
 #include <map>
@@ -1509,12 +1512,11 @@ __device__ __forceinline__ void chol_inv_body(int r, const double *__restrict__ 
 // 0.5 is a zero padding column with a unit diagonal); the sums run in another order.
 constexpr int kCholWaveMax = 63;  // 2 r (r + 1) doubles of LDS stay within 64 KB
 
-__device__ __forceinline__ void chol_inv_wave_body(int r, const double *__restrict__ G, double *__restrict__ X) {
-    extern __shared__ double cw[];
+// The factorisation and inverse from A (r x r in LDS, leading dimension r + 1, upper triangle
+// read); Xs: LDS of the same size. Every thread of the workgroup calls it (the barriers); the
+// threads of the first wave do the work.
+__device__ __forceinline__ void chol_inv_lds(int r, double *A, double *Xs, double *__restrict__ X) {
     const int ld = r + 1, lane = threadIdx.x;
-    double *A = cw, *Xs = cw + r * ld;
-    for (int e = lane; e < r * r; e += kWave) A[(e / r) * ld + e % r] = G[e];
-    __syncthreads();
     for (int j = 0; j < r; ++j) {
         const double dd = A[j * ld + j];
         const bool zc = !(dd > 0.5);
@@ -1558,10 +1560,56 @@ __device__ __forceinline__ void chol_inv_wave_body(int r, const double *__restri
         }
     }
     __syncthreads();
-    for (int e = lane; e < r * r; e += kWave) {
-        const int j = e / r, i = e % r;
-        X[e] = j <= i ? Xs[j * ld + i] : 0.0;
+    if (lane < kWave)
+        for (int e = lane; e < r * r; e += kWave) {
+            const int j = e / r, i = e % r;
+            X[e] = j <= i ? Xs[j * ld + i] : 0.0;
+        }
+}
+
+__device__ __forceinline__ void chol_inv_wave_body(int r, const double *__restrict__ G, double *__restrict__ X) {
+    extern __shared__ double cw[];
+    const int ld = r + 1, lane = threadIdx.x;
+    double *A = cw, *Xs = cw + r * ld;
+    for (int e = lane; e < r * r; e += kWave) A[(e / r) * ld + e % r] = G[e];
+    __syncthreads();
+    chol_inv_lds(r, A, Xs, X);
+}
+
+// One CholeskyQR factor per workgroup for r <= kGramMaxR: the Gram matrix U^T U of the tall
+// m x r matrix U (row-major) with the rows staged through LDS 64 at a time and thread (i, j)
+// accumulating entry (i, j) (in two chains; U_ti U_tj = U_tj U_ti, so the result is exactly
+// symmetric), then the factorisation and inverse above on it: the Gram GEMM, its partial-sum
+// reduction and the factorisation of the separate path in one launch.
+constexpr int kGramMaxR = 32;
+
+__global__ __launch_bounds__(1024) void k_gram_chol_inv(int m, int r, const double *__restrict__ Uall, long long sU,
+                                                        double *__restrict__ Xall, long long sX) {
+    __shared__ double uc[64 * kGramMaxR];
+    __shared__ double cw[2 * kGramMaxR * (kGramMaxR + 1)];
+    const int tid = threadIdx.x, z = blockIdx.x;
+    const double *U = Uall + (long long)z * sU;
+    const bool act = tid < r * r;
+    const int i = act ? tid / r : 0, j = act ? tid % r : 0;
+    double g0 = 0.0, g1 = 0.0;
+    for (int r0 = 0; r0 < m; r0 += 64) {
+        const int rows = min(64, m - r0);
+        for (int e = tid; e < rows * r; e += 1024) uc[e] = U[(long long)r0 * r + e];
+        __syncthreads();
+        if (act) {
+            int t = 0;
+            for (; t + 1 < rows; t += 2) {
+                g0 = fma(uc[t * r + i], uc[t * r + j], g0);
+                g1 = fma(uc[(t + 1) * r + i], uc[(t + 1) * r + j], g1);
+            }
+            if (t < rows) g0 = fma(uc[t * r + i], uc[t * r + j], g0);
+        }
+        __syncthreads();
     }
+    const int ld = r + 1;
+    if (act) cw[i * ld + j] = g0 + g1;
+    __syncthreads();
+    chol_inv_lds(r, cw, cw + r * ld, Xall + (long long)z * sX);
 }
 
 __global__ __launch_bounds__(64) void k_chol_inv_wave(int r, const double *__restrict__ Gin, double *__restrict__ Xout) {
@@ -2020,6 +2068,13 @@ void interp_solve(hipStream_t s, int m, int r, const double *L, int ldl, const i
         k_interp<<<cdiv(m, 256), 256, 0, s>>>(m, r, L, ldl, rowpiv, X);
     k_interp_exact_rows<<<cdiv((long long)r * r, 256), 256, 0, s>>>(r, rowpiv, X);
     WTT_HIP(hipGetLastError());
+}
+
+bool gram_chol_inv(hipStream_t s, int m, int r, int batch, const double *U, long long sU, double *X) {
+    if (r < 1 || r > kGramMaxR) return false;
+    k_gram_chol_inv<<<batch, 1024, 0, s>>>(m, r, U, sU, X, (long long)r * r);
+    WTT_HIP(hipGetLastError());
+    return true;
 }
 
 void chol_upper_inv(hipStream_t s, int r, int batch, const double *G, double *X, double *ws) {
