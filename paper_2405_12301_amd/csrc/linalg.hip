@@ -8,7 +8,8 @@
 //    each step takes the largest residual entry, found by wavefront reductions): one workgroup
 //    with the block in registers, a persistent multi-workgroup form, or one launch per step;
 //  - the interpolative basis L * inv(L[I, :]) of a cross (Sec. 3.3, CUR / skeleton form);
-//  - CholeskyQR factors (Gram matrix, Cholesky, inverse) for re-orthonormalising a basis.
+//  - CholeskyQR factors (Gram matrix on the FP64 matrix cores, Cholesky and inverse in one
+//    wave's registers) for re-orthonormalising a basis.
 #include <algorithm>
 #include <array>
 #include <map>
@@ -769,26 +770,28 @@ struct PrrluCtl {
     int fail;  // set by a workgroup of the persistent form whose polls ran out
 };
 
+// Per parity c (0, 1): max | sum | index | stamp (nblk each, one double apiece) | rows (nblk x n).
+// The parity copies are found by arithmetic on c, not by indexing arrays of pointers: a
+// run-time index into such an array keeps it in scratch memory, reloaded at every step.
 struct PrrluWs {
-    double *pmax[2], *psum[2], *prow[2];
-    long long *pidx[2];
-    unsigned *pseq[2];  // persistent form: step stamp of each workgroup's partials
+    double *base;       // parity 0
+    long long pstride;  // doubles from parity 0 to parity 1
+    int nblk;
     PrrluCtl *ctl;
+    __host__ __device__ double *pmax(int c) const { return base + c * pstride; }
+    __host__ __device__ double *psum(int c) const { return base + c * pstride + nblk; }
+    __host__ __device__ long long *pidx(int c) const { return (long long *)(base + c * pstride + 2 * nblk); }
+    // persistent form: step stamp of each workgroup's partials
+    __host__ __device__ unsigned *pseq(int c) const { return (unsigned *)(base + c * pstride + 3 * nblk); }
+    __host__ __device__ double *prow(int c) const { return base + c * pstride + 4 * nblk; }
 };
 
-// Per parity: max | sum | index | stamp (nblk each, one double apiece) | rows (nblk x n).
 __host__ __device__ inline PrrluWs prrlu_ws_split(double *ws, int n, int nblk) {
     PrrluWs w;
-    double *p = ws;
-    for (int b = 0; b < 2; ++b) {
-        w.pmax[b] = p;
-        w.psum[b] = p + nblk;
-        w.pidx[b] = (long long *)(p + 2 * nblk);
-        w.pseq[b] = (unsigned *)(p + 3 * nblk);
-        w.prow[b] = p + 4 * nblk;
-        p += 4 * nblk + (size_t)nblk * n;
-    }
-    w.ctl = (PrrluCtl *)p;
+    w.base = ws;
+    w.pstride = 4LL * nblk + (long long)nblk * n;
+    w.nblk = nblk;
+    w.ctl = (PrrluCtl *)(ws + 2 * w.pstride);
     return w;
 }
 
@@ -799,7 +802,7 @@ __device__ __forceinline__ void prrlu_mw_init_body(const PrrluJob &J) {
     w.ctl->stop_launch = 0;
     w.ctl->tol2 = 0.0;
     w.ctl->fail = 0;
-    for (int b = 0; b < J.nblk; ++b) w.pseq[0][2 * b] = w.pseq[1][2 * b] = 0u;
+    for (int b = 0; b < J.nblk; ++b) w.pseq(0)[2 * b] = w.pseq(1)[2 * b] = 0u;
     J.info[0] = -1.0;  // not finished: the host launches further steps
 }
 
@@ -844,8 +847,8 @@ __device__ __forceinline__ void prrlu_mw_step_body(const PrrluJob &J, int t) {
         double bm = -1.0, bs = 0.0;
         long long bi = 0x7fffffffffffffffLL;
         for (int b = tid; b < J.nblk; b += kMwThreads) {
-            amax_merge(bm, bi, w.pmax[prev][b], w.pidx[prev][b]);
-            bs += w.psum[prev][b];
+            amax_merge(bm, bi, w.pmax(prev)[b], w.pidx(prev)[b]);
+            bs += w.psum(prev)[b];
         }
         // the winning workgroup is the owner of the winning index's row stripe
         wave_amax_sum(bm, bi, bs);
@@ -893,7 +896,7 @@ __device__ __forceinline__ void prrlu_mw_step_body(const PrrluJob &J, int t) {
         pi = (int)(s_gi / n);
         pj = (int)(s_gi % n);
         {
-            const double *prow = w.prow[prev] + (long long)s_wk * n;
+            const double *prow = w.prow(prev) + (long long)s_wk * n;
             for (int j = tid; j < n; j += kMwThreads) u[j] = prow[j];
         }
         if (active && pj >= c0 && pj < c0 + kMwTW) {  // the pivot column's owners publish it
@@ -966,9 +969,9 @@ __device__ __forceinline__ void prrlu_mw_step_body(const PrrluJob &J, int t) {
             bs += wsum[k];
             amax_merge(bm, bi, wmax[k], widx[k]);
         }
-        w.pmax[cur][blockIdx.x] = bm;
-        w.psum[cur][blockIdx.x] = bs;
-        w.pidx[cur][blockIdx.x] = bi;
+        w.pmax(cur)[blockIdx.x] = bm;
+        w.psum(cur)[blockIdx.x] = bs;
+        w.pidx(cur)[blockIdx.x] = bi;
         s_bi = bi;
     }
     __syncthreads();
@@ -978,7 +981,7 @@ __device__ __forceinline__ void prrlu_mw_step_body(const PrrluJob &J, int t) {
     if (s_bi != 0x7fffffffffffffffLL && active) {
         const int local = (int)(s_bi / n) - r0;
         if (local % RS == tr) {
-            double *dst = w.prow[cur] + (long long)blockIdx.x * n;
+            double *dst = w.prow(cur) + (long long)blockIdx.x * n;
 #pragma unroll
             for (int k = 0; k < K; ++k)
                 if (k == local / RS)
@@ -1069,14 +1072,14 @@ __device__ __forceinline__ void prrlu_coop_body(const PrrluJob &J) {
             amax_merge(bm, bi, wmax[k], widx[k]);
         }
         if (tid == 0) {
-            w.pmax[cur][blk] = bm;
-            w.psum[cur][blk] = bs;
-            w.pidx[cur][blk] = bi;
+            w.pmax(cur)[blk] = bm;
+            w.psum(cur)[blk] = bs;
+            w.pidx(cur)[blk] = bi;
         }
         if (bi != 0x7fffffffffffffffLL && active) {  // a real row: ties go to the lowest index
             const int local = (int)(bi / n) - r0;
             if (local % RS == tr) {
-                double *dst = w.prow[cur] + (long long)blk * n;
+                double *dst = w.prow(cur) + (long long)blk * n;
 #pragma unroll
                 for (int k = 0; k < kMwK; ++k)
                     if (k == local / RS)
@@ -1087,18 +1090,18 @@ __device__ __forceinline__ void prrlu_coop_body(const PrrluJob &J) {
         }
         __syncthreads();  // this workgroup's stores are complete before the stamp releases them
         if (tid == 0)
-            __hip_atomic_store(&w.pseq[cur][2 * blk], (unsigned)(t + 1), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&w.pseq(cur)[2 * blk], (unsigned)(t + 1), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         // every wave gathers every slot and decides pivot t on its own
         double gm = -1.0, gs = 0.0;
         long long gi = 0x7fffffffffffffffLL;
         bool ok = true;
-        if (lane < G) ok = coop_poll(&w.pseq[cur][2 * lane], (unsigned)(t + 1), w.ctl);
+        if (lane < G) ok = coop_poll(&w.pseq(cur)[2 * lane], (unsigned)(t + 1), w.ctl);
         const bool wave_ok = __ballot(!ok) == 0;
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // every slot's partials and row are visible
         if (lane < G && wave_ok) {
-            gm = w.pmax[cur][lane];
-            gs = w.psum[cur][lane];
-            gi = w.pidx[cur][lane];
+            gm = w.pmax(cur)[lane];
+            gs = w.psum(cur)[lane];
+            gi = w.pidx(cur)[lane];
         }
         wave_amax_sum(gm, gi, gs);
         if (t == 0) tol2 = J.rel_tol2 * gs;
@@ -1126,7 +1129,7 @@ __device__ __forceinline__ void prrlu_coop_body(const PrrluJob &J) {
                 }
             }
             if (!stop) {
-                const double *urow = w.prow[cur] + (long long)wk * n;
+                const double *urow = w.prow(cur) + (long long)wk * n;
                 upj = urow[pj];
 #pragma unroll
                 for (int j = 0; j < kMwTW; ++j) uu[j] = (active && c0 + j < n) ? urow[c0 + j] : 0.0;
@@ -1576,40 +1579,121 @@ __device__ __forceinline__ void chol_inv_wave_body(int r, const double *__restri
     chol_inv_lds(r, A, Xs, X);
 }
 
-// One CholeskyQR factor per workgroup for r <= kGramMaxR: the Gram matrix U^T U of the tall
-// m x r matrix U (row-major) with the rows staged through LDS 64 at a time and thread (i, j)
-// accumulating entry (i, j) (in two chains; U_ti U_tj = U_tj U_ti, so the result is exactly
-// symmetric), then the factorisation and inverse above on it: the Gram GEMM, its partial-sum
-// reduction and the factorisation of the separate path in one launch.
-constexpr int kGramMaxR = 32;
-
-__global__ __launch_bounds__(1024) void k_gram_chol_inv(int m, int r, const double *__restrict__ Uall, long long sU,
-                                                        double *__restrict__ Xall, long long sX) {
-    __shared__ double uc[64 * kGramMaxR];
-    __shared__ double cw[2 * kGramMaxR * (kGramMaxR + 1)];
-    const int tid = threadIdx.x, z = blockIdx.x;
-    const double *U = Uall + (long long)z * sU;
-    const bool act = tid < r * r;
-    const int i = act ? tid / r : 0, j = act ? tid % r : 0;
-    double g0 = 0.0, g1 = 0.0;
-    for (int r0 = 0; r0 < m; r0 += 64) {
-        const int rows = min(64, m - r0);
-        for (int e = tid; e < rows * r; e += 1024) uc[e] = U[(long long)r0 * r + e];
-        __syncthreads();
-        if (act) {
-            int t = 0;
-            for (; t + 1 < rows; t += 2) {
-                g0 = fma(uc[t * r + i], uc[t * r + j], g0);
-                g1 = fma(uc[(t + 1) * r + i], uc[(t + 1) * r + j], g1);
-            }
-            if (t < rows) g0 = fma(uc[t * r + i], uc[t * r + j], g0);
+// The same factorisation and inverse in one wave's registers, for the fused kernel below (where
+// the LDS form's barriers span all its waves): lane i holds column i of the upper triangle
+// (a[k] = A_ki, k <= i; zero below); at step j lane j's a[j] is the pivot, lanes i > j scale
+// their a[j] into R_ji and update their column with row j of R, R_jk read from lane k
+// (readlane). Then R^{-1} in place by back substitution, rows in descending order, lane i
+// forming column i from row j of R, read from the other lanes before a[j] is overwritten; the
+// sums run in four chains. The loops are unrolled (static register indices); rows at or beyond
+// r are skipped by uniform branches.
+template <int RM>
+__device__ __forceinline__ void chol_inv_reg(int r, double (&a)[RM]) {
+    const int i = threadIdx.x % kWave;
+#pragma unroll
+    for (int j = 0; j < RM; ++j) {
+        if (j < r) {
+            const double dd = readlane_d(a[j], j);
+            const bool zc = !(dd > 0.5);
+            const double rjj = zc ? 1.0 : sqrt(dd), inv = 1.0 / rjj;
+            const double rji = (i > j && !zc) ? a[j] * inv : 0.0;
+            a[j] = i > j ? rji : (i == j ? rjj : a[j]);
+#pragma unroll
+            for (int k = j + 1; k < RM; ++k)
+                if (k < r) a[k] = fma(-readlane_d(a[j], k), rji, a[k]);
         }
-        __syncthreads();
     }
-    const int ld = r + 1;
-    if (act) cw[i * ld + j] = g0 + g1;
+#pragma unroll
+    for (int k = 0; k < RM; ++k)
+        if (k > i) a[k] = 0.0;
+#pragma unroll
+    for (int j = RM - 1; j >= 0; --j) {
+        if (j < r) {
+            double v[4] = {i == j ? 1.0 : 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int k = j + 1; k < RM; ++k)
+                if (k < r) v[(k - j - 1) & 3] = fma(-readlane_d(a[j], k), a[k], v[(k - j - 1) & 3]);
+            a[j] = ((v[0] + v[1]) + (v[2] + v[3])) / readlane_d(a[j], j);
+        }
+    }
+}
+
+// One CholeskyQR factor per workgroup for r <= kGramMaxR: the Gram matrix U^T U of the tall
+// m x r matrix U (row-major) on the matrix cores, then the factorisation and inverse above on
+// it (the Gram GEMM, its partial-sum reduction and the factorisation in one launch). Wave w
+// takes the groups of four rows g = w, w + 8, ...; per group lane l loads U[4g + l / 16][l % 16]
+// and U[4g + l / 16][16 + l % 16], which is at once the A operand (U^T) and the B operand (U) of
+// v_mfma_f64_16x16x4f64, so three products per group give the blocks (0,0), (0,1) and (1,1) of
+// G (one for r <= 16); the eight waves' partial blocks are summed in wave order through LDS,
+// whose space then holds G for the register factorisation of the first wave.
+constexpr int kGramMaxR = 32, kGramWaves = 8, kGramQ = 8;
+
+__global__ __launch_bounds__(kGramWaves * 64) void k_gram_chol_inv(int m, int r, const double *__restrict__ Uall,
+                                                                   long long sU, double *__restrict__ Xall,
+                                                                   long long sX) {
+    __shared__ double red[kGramWaves][3][4][kWave];  // then G (kGramMaxR x kGramMaxR)
+    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave, z = blockIdx.x;
+    const int cl = lane % 16, rl = lane / 16;
+    const double *U = Uall + (long long)z * sU;
+    const bool two = r > 16;
+    f64x4 d00 = {0.0, 0.0, 0.0, 0.0}, d01 = d00, d11 = d00;
+    for (int gb = w; 4 * gb < m; gb += kGramWaves * kGramQ) {
+        double u0[kGramQ], u1[kGramQ];
+#pragma unroll
+        for (int q = 0; q < kGramQ; ++q) {
+            const int t = 4 * (gb + kGramWaves * q) + rl;
+            u0[q] = (t < m && cl < r) ? U[(long long)t * r + cl] : 0.0;
+            u1[q] = (two && t < m && 16 + cl < r) ? U[(long long)t * r + 16 + cl] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < kGramQ; ++q) {
+            d00 = __builtin_amdgcn_mfma_f64_16x16x4f64(u0[q], u0[q], d00, 0, 0, 0);
+            if (two) {
+                d01 = __builtin_amdgcn_mfma_f64_16x16x4f64(u0[q], u1[q], d01, 0, 0, 0);
+                d11 = __builtin_amdgcn_mfma_f64_16x16x4f64(u1[q], u1[q], d11, 0, 0, 0);
+            }
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        red[w][0][v][lane] = d00[v];
+        red[w][1][v][lane] = d01[v];
+        red[w][2][v][lane] = d11[v];
+    }
     __syncthreads();
-    chol_inv_lds(r, cw, cw + r * ld, Xall + (long long)z * sX);
+    double g[2];  // this thread's entries of the summed blocks (e = tid, tid + 512)
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int e = threadIdx.x + q * kGramWaves * kWave;
+        g[q] = 0.0;
+        if (e < 3 * 4 * kWave) {
+            const int T = e / (4 * kWave), v = (e / kWave) % 4, l = e % kWave;
+#pragma unroll
+            for (int ww = 0; ww < kGramWaves; ++ww) g[q] += red[ww][T][v][l];
+        }
+    }
+    __syncthreads();  // the partial blocks are consumed; their LDS takes G
+    double *Gs = &red[0][0][0][0];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int e = threadIdx.x + q * kGramWaves * kWave;
+        if (e < 3 * 4 * kWave) {
+            const int T = e / (4 * kWave), v = (e / kWave) % 4, l = e % kWave;
+            // accumulator v of lane l holds block entry (l / 16 + 4 v, l % 16)
+            const int row = (T == 2 ? 16 : 0) + l / 16 + 4 * v, col = (T == 0 ? 0 : 16) + l % 16;
+            Gs[row * kGramMaxR + col] = g[q];
+        }
+    }
+    __syncthreads();
+    if (w != 0) return;
+    double a[kGramMaxR];
+#pragma unroll
+    for (int k = 0; k < kGramMaxR; ++k) a[k] = (k <= lane && lane < r) ? Gs[k * kGramMaxR + lane] : 0.0;
+    chol_inv_reg<kGramMaxR>(r, a);
+    double *X = Xall + (long long)z * sX;
+#pragma unroll
+    for (int j = 0; j < kGramMaxR; ++j)
+        if (j < r && lane < r) X[j * r + lane] = a[j];
 }
 
 __global__ __launch_bounds__(64) void k_chol_inv_wave(int r, const double *__restrict__ Gin, double *__restrict__ Xout) {
@@ -2072,7 +2156,7 @@ void interp_solve(hipStream_t s, int m, int r, const double *L, int ldl, const i
 
 bool gram_chol_inv(hipStream_t s, int m, int r, int batch, const double *U, long long sU, double *X) {
     if (r < 1 || r > kGramMaxR) return false;
-    k_gram_chol_inv<<<batch, 1024, 0, s>>>(m, r, U, sU, X, (long long)r * r);
+    k_gram_chol_inv<<<batch, kGramWaves * kWave, 0, s>>>(m, r, U, sU, X, (long long)r * r);
     WTT_HIP(hipGetLastError());
     return true;
 }
