@@ -259,6 +259,7 @@ struct wenott_ctx {
     int bc[kMaxDim] = {};
     wenott_opts o{};
     hipStream_t s = nullptr;
+    hipEvent_t ev_wait = nullptr;  // host_wait's marker on s
     TT U;
     TT rhs;
     bool have_rhs = false;
@@ -303,6 +304,18 @@ struct wenott_ctx {
     std::vector<float> log_x, log_hist;
     std::vector<int> log_cls;
 };
+
+// Waits on the host for the work queued on c->s by recording an event and polling it. A
+// blocking stream synchronisation may put the host thread to sleep until an interrupt once
+// its short spin runs out; the wake-up then delays the next launch at each of the
+// data-dependent readbacks of a step (pivot ranks, residuals, truncation ranks).
+void host_wait(wenott_ctx *c) {
+    WTT_HIP(hipEventRecord(c->ev_wait, c->s));
+    hipError_t e;
+    while ((e = hipEventQuery(c->ev_wait)) == hipErrorNotReady) {
+    }
+    WTT_HIP(e);
+}
 
 namespace {
 
@@ -408,7 +421,7 @@ double status_alpha(const wenott_ctx *c, int slot) { return c->h_status[kStatusA
 
 double exact_alpha(wenott_ctx *c, const TT &U) {
     exact_alpha_launch(c, U, 3);
-    WTT_HIP(hipStreamSynchronize(c->s));
+    host_wait(c);
     raise_flags(c, status_flags(c));
     return status_alpha(c, 3);
 }
@@ -545,7 +558,7 @@ PivotResult pivots(wenott_ctx *c, double *B, int m, int n, double rel_tol2, doub
     for (;;) {
         WTT_HIP(hipMemcpyAsync(c->h_pinned_int, piv, pivot_info_offset(rmax) + 2 * sizeof(double),
                                hipMemcpyDeviceToHost, c->s));
-        WTT_HIP(hipStreamSynchronize(c->s));
+        host_wait(c);
         const double state = pinned_pivot_info(c, rmax, 0);
         if (state >= 0.0) break;
         WTT_REQUIRE(state != -2.0, WENOTT_EHIP, "pivot search: grid barrier wait ran out");
@@ -588,7 +601,7 @@ double sampled_residual(wenott_ctx *c, const TT &U, const FluxTT &F, int dir, do
     sample_residual(c->s, g, uc, ranks, npts, dp, fc, franks, ust, acc, c->d_flags);
     WTT_REQUIRE(2 * (size_t)nb <= 3000, WENOTT_EINVAL, "too many probe points");
     status_readback(c, kStatusAcc + 2 * nb);
-    WTT_HIP(hipStreamSynchronize(c->s));
+    host_wait(c);
     raise_flags(c, status_flags(c));
     const double *h = c->h_status + kStatusAcc;
     double d2 = 0.0, n2 = 0.0;
@@ -639,7 +652,7 @@ void apply_proposal(wenott_ctx *c, int d, const int *M, const std::vector<float>
                 "proposal forward failed");
     std::vector<float> hy((size_t)nb * OUT);
     WTT_HIP(hipMemcpyAsync(hy.data(), y, hy.size() * sizeof(float), hipMemcpyDeviceToHost, c->s));
-    WTT_HIP(hipStreamSynchronize(c->s));
+    host_wait(c);
     for (int k = 0; k < nb; ++k) {
         const float *yk = hy.data() + (size_t)k * OUT;
         int cls = 0;
@@ -1056,7 +1069,7 @@ double sampled_residual_finish(wenott_ctx *c, int nb) {
 double sampled_stage_residual(wenott_ctx *c, const TT &X, const TT *Un, StageWeights w, double alpha,
                               const FluxTT &F, Rng &rng) {
     const int nb = sampled_stage_residual_launch(c, X, Un, w, alpha, F, rng);
-    WTT_HIP(hipStreamSynchronize(c->s));
+    host_wait(c);
     return sampled_residual_finish(c, nb);
 }
 
@@ -1168,7 +1181,7 @@ int svd_ranks(wenott_ctx *c, int m, int n, const double *A, long long sz, long l
     WTT_HIP(hipMemcpyAsync(c->h_pinned_int, *rk, nc * sizeof(int), hipMemcpyDeviceToHost, c->s));
     const bool tail = (size_t)nc * n <= 3000 && (c->o.use_proposal || c->logging);
     if (tail) WTT_HIP(hipMemcpyAsync(c->h_pinned_dbl + 1024, *sig, (size_t)nc * n * sizeof(double), hipMemcpyDeviceToHost, c->s));
-    WTT_HIP(hipStreamSynchronize(c->s));
+    host_wait(c);
     int r = 1;
     for (int z = 0; z < nc; ++z) r = std::max(r, c->h_pinned_int[z]);
     // normalised log singular-value tail (largest over components), a feature of the proposal
@@ -1236,7 +1249,7 @@ void round_tt(wenott_ctx *c, TT &X, double eps, bool truncate, std::vector<doubl
     }
     const double *ddelta = c->sc.get<double>(S_NORMS, 2 * (size_t)nc) + nc;
     if (!truncate || d < 2) {
-        WTT_HIP(hipStreamSynchronize(s));
+        host_wait(c);
         norms.assign(c->h_pinned_dbl + kPinNorms, c->h_pinned_dbl + kPinNorms + nc);
         for (int k = 1; k < d; ++k) dfree(s, T[k]);
         return;
@@ -1374,7 +1387,7 @@ void batch_pivots(std::vector<BState *> &act, int dir, int k) {
             WTT_HIP(hipMemcpyAsync(b->c->h_pinned_int, b->piv, pivot_info_offset(b->rmax) + 2 * sizeof(double),
                                    hipMemcpyDeviceToHost, b->c->s));
         }
-        WTT_HIP(hipStreamSynchronize(c0->s));
+        host_wait(c0);
         std::vector<size_t> still;
         int rmax_open = 0;
         for (size_t z : open) {
@@ -1478,7 +1491,7 @@ void batch_cross(std::vector<BState> &bs, const double *aw, const double *bw, in
             const StageWeights w{aw[st], bw[st], bw[st] * b->dt};
             b->nb_acc = sampled_stage_residual_launch(b->c, b->X, &b->c->U, w, b->alpha, b->F, b->rng);
         }
-        WTT_HIP(hipStreamSynchronize(act[0]->c->s));
+        host_wait(act[0]->c);
         std::vector<BState *> refresh;
         for (BState *b : act) {
             b->resid = sampled_residual_finish(b->c, b->nb_acc);
@@ -1567,7 +1580,7 @@ void batch_round(std::vector<BState> &bs, std::vector<TT> &Xs) {
         frob_norms(c->s, nc, (long long)N0 * R1, C0, (long long)N0 * R1, dn);
         WTT_HIP(hipMemcpyAsync(c->h_pinned_dbl + 64, dn, nc * sizeof(double), hipMemcpyDeviceToHost, c->s));
     }
-    WTT_HIP(hipStreamSynchronize(bs[0].c->s));
+    host_wait(bs[0].c);
     std::vector<const double *> ddelta(ns);
     for (size_t z = 0; z < ns; ++z) {
         wenott_ctx *c = bs[z].c;
@@ -1623,7 +1636,7 @@ void batch_round(std::vector<BState> &bs, std::vector<TT> &Xs) {
             trunc_ranks(c->s, n, nc, sig[z], ddelta[z], 0.0, c->o.rank_cap, rk[z]);
             WTT_HIP(hipMemcpyAsync(c->h_pinned_int, rk[z], nc * sizeof(int), hipMemcpyDeviceToHost, c->s));
         }
-        WTT_HIP(hipStreamSynchronize(bs[0].c->s));
+        host_wait(bs[0].c);
         std::vector<CholJob> cj(ns);
         std::vector<double *> nk(ns), nk2(ns);
         std::vector<int> rr(ns);
@@ -1758,7 +1771,7 @@ void reset_call_info(wenott_ctx *c) {
 
 void finish_call_info(wenott_ctx *c, double t0) {
     if (c->profiling && c->ev_used >= 2) {
-        WTT_HIP(hipStreamSynchronize(c->s));
+        host_wait(c);
         for (int i = 0; i + 1 < c->ev_used; i += 2) {
             float e = 0.f;
             WTT_HIP(hipEventElapsedTime(&e, c->ev[i], c->ev[i + 1]));
@@ -1877,6 +1890,7 @@ wenott_status wenott_init(wenott_ctx **out, const wenott_tt *state, const wenott
         }
         c->s = (hipStream_t)hip_stream;
         c->sc.s = c->s;
+        WTT_HIP(hipEventCreateWithFlags(&c->ev_wait, hipEventDisableTiming));
         c->ring.init(c->s, 8u << 20);
         WTT_HIP(hipMalloc((void **)&c->d_status, sizeof(double) * kStatusDoubles));
         WTT_HIP(hipMemsetAsync(c->d_status, 0, sizeof(double) * kStatusDoubles, c->s));
@@ -1915,7 +1929,7 @@ wenott_status wenott_init(wenott_ctx **out, const wenott_tt *state, const wenott
                                          sizeof(double) * rb, sizeof(double) * rb, (size_t)ra * U.N[k], kind, c->s));
             }
         }
-        WTT_HIP(hipStreamSynchronize(c->s));
+        host_wait(c);
         c->U = U;
         // norms for the dynamic eps
         TT tmp = copy_tt(c, c->U);
@@ -1958,6 +1972,7 @@ void wenott_destroy(wenott_ctx *c) {
         if (c->h_pinned_int) (void)hipHostFree(c->h_pinned_int);
         if (c->h_pinned_dbl) (void)hipHostFree(c->h_pinned_dbl);
         for (auto e : c->ev) (void)hipEventDestroy(e);
+        if (c->ev_wait) (void)hipEventDestroy(c->ev_wait);
     }
     delete c;
 }
@@ -2128,7 +2143,7 @@ wenott_status wenott_batch_rk3_step(wenott_ctx **ctxs, int32_t n, const double *
                         exact_alpha_launch(b.c, b.X, 3);
                         any = true;
                     }
-                if (any) WTT_HIP(hipStreamSynchronize(ctxs[0]->s));
+                if (any) host_wait(ctxs[0]);
                 for (auto &b : bs) {
                     if (b.c->o.alpha_mode == 2) {
                         b.alpha = b.c->o.alpha_given;
@@ -2209,7 +2224,7 @@ wenott_status wenott_to_dense(wenott_ctx *c, double *out, int32_t on_device) {
             double *tmp = c->sc.get<double>(S_DENSE, (size_t)n);
             to_dense_dev(c, c->U, tmp);
             WTT_HIP(hipMemcpyAsync(out, tmp, sizeof(double) * n, hipMemcpyDeviceToHost, c->s));
-            WTT_HIP(hipStreamSynchronize(c->s));
+            host_wait(c);
         }
     });
 }
@@ -2222,7 +2237,7 @@ wenott_status wenott_get_state(wenott_ctx *c, wenott_tt *view) {
 wenott_status wenott_get_info(wenott_ctx *c, wenott_info *info) {
     if (!c || !info) return WENOTT_EINVAL;
     return run_guarded(c, [&] {
-        WTT_HIP(hipStreamSynchronize(c->s));
+        host_wait(c);
         for (int k = 0; k < 4; ++k) c->info.ranks[k] = k <= c->d ? c->U.R[k] : 0;
         *info = c->info;
     });
