@@ -99,7 +99,8 @@ size_t jacobi_scratch_doubles(int n, int batch);
 // it: this call launches steps t_begin..min(t_end, rmax + 1) and returns the next step; info[0]
 // stays negative until the factorisation has stopped, and the caller continues from the
 // returned step. The register form and the persistent form finish in one call (t_begin = 0);
-// info[0] = -2 reports a persistent launch whose grid barrier wait ran out. Needs rmax >= 1.
+// info[0] = -2 reports a persistent launch whose waits for the other workgroups' partials ran
+// out. Needs rmax >= 1.
 int prrlu(hipStream_t s, int m, int n, double *A, int rmax, double rel_tol2, int *rowpiv, int *colpiv, double *L,
           double *info, double *ws, int t_begin, int t_end);
 size_t prrlu_ws_doubles(int m, int n);

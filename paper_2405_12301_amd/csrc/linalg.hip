@@ -770,7 +770,7 @@ struct PrrluCtl {
     int fail;  // set by a workgroup of the persistent form whose polls ran out
 };
 
-// Per parity c (0, 1): max | sum | index | stamp (nblk each, one double apiece) | rows (nblk x n).
+// Per parity c (0, 1): max | sum | index (nblk each, one double apiece) | rows (nblk x n).
 // The parity copies are found by arithmetic on c, not by indexing arrays of pointers: a
 // run-time index into such an array keeps it in scratch memory, reloaded at every step.
 struct PrrluWs {
@@ -781,15 +781,13 @@ struct PrrluWs {
     __host__ __device__ double *pmax(int c) const { return base + c * pstride; }
     __host__ __device__ double *psum(int c) const { return base + c * pstride + nblk; }
     __host__ __device__ long long *pidx(int c) const { return (long long *)(base + c * pstride + 2 * nblk); }
-    // persistent form: step stamp of each workgroup's partials
-    __host__ __device__ unsigned *pseq(int c) const { return (unsigned *)(base + c * pstride + 3 * nblk); }
-    __host__ __device__ double *prow(int c) const { return base + c * pstride + 4 * nblk; }
+    __host__ __device__ double *prow(int c) const { return base + c * pstride + 3 * nblk; }
 };
 
 __host__ __device__ inline PrrluWs prrlu_ws_split(double *ws, int n, int nblk) {
     PrrluWs w;
     w.base = ws;
-    w.pstride = 4LL * nblk + (long long)nblk * n;
+    w.pstride = 3LL * nblk + (long long)nblk * n;
     w.nblk = nblk;
     w.ctl = (PrrluCtl *)(ws + 2 * w.pstride);
     return w;
@@ -797,13 +795,20 @@ __host__ __device__ inline PrrluWs prrlu_ws_split(double *ws, int n, int nblk) {
 
 constexpr int kMwThreads = 256, kMwTW = 8, kMwK = 2, kMwKBig = 8, kMwBigMinBlk = 128;
 
+// One workgroup per job. The persistent form's exchanged words (both parities) start with the
+// tag of step -2, which no word of steps 0..5 carries.
 __device__ __forceinline__ void prrlu_mw_init_body(const PrrluJob &J) {
     const PrrluWs w = prrlu_ws_split(J.ws, J.n, J.nblk);
-    w.ctl->stop_launch = 0;
-    w.ctl->tol2 = 0.0;
-    w.ctl->fail = 0;
-    for (int b = 0; b < J.nblk; ++b) w.pseq(0)[2 * b] = w.pseq(1)[2 * b] = 0u;
-    J.info[0] = -1.0;  // not finished: the host launches further steps
+    if (threadIdx.x == 0) {
+        w.ctl->stop_launch = 0;
+        w.ctl->tol2 = 0.0;
+        w.ctl->fail = 0;
+        J.info[0] = -1.0;  // not finished: the host launches further steps
+    }
+    if (J.mode == 2) {
+        long long *p = (long long *)J.ws;
+        for (long long e = threadIdx.x; e < 2 * w.pstride; e += blockDim.x) p[e] = 3;
+    }
 }
 
 // Workgroup b owns a stripe of J.rows = RS * K rows; thread (tr, tc) holds the kMwTW columns
@@ -998,23 +1003,51 @@ __device__ __forceinline__ void prrlu_mw_step_body(const PrrluJob &J, int t) {
 // occupancy times the compute units); a plain launch is used, since the cooperative launch API
 // costs about 0.1 ms of host time per call. Workgroups are dispatched in order, so even a grid
 // that other work keeps partly waiting makes progress as slots free up.
-// Per pivot step t every workgroup publishes its partials and candidate row (double-buffered by
-// step parity) and then stamps its slot with t + 1 (a device-scope release store). Every wave
-// of every workgroup gathers all slots itself, lane b polling slot b (device-scope loads, then
-// one acquire fence per wave) and reading its partials, and reduces them in slot order; so all
-// waves take the same decision with no barrier beyond the stamps. Each thread then reads its
-// columns of the winning row, and only the pivot column of the stripe passes through LDS. A buffer of one parity is
-// written again two steps later, which no workgroup can reach before every workgroup has read
-// it. The polls are bounded: after kCoopSpin polls a workgroup marks the job failed (info[0] =
-// -2) and leaves, and the others leave at their next poll.
+// Per pivot step t every workgroup publishes its partials (max, index, sum) and candidate row,
+// double-buffered by step parity, as 64-bit words that carry the step in their two lowest bits
+// (tag (t >> 1) & 3; a double gives up its last two mantissa bits, which every reader clears
+// alike), written and read with relaxed device-scope atomics, which are coherent across the
+// chip without the L2 write-back and invalidation of release/acquire fences. Every wave of every
+// workgroup gathers all slots itself, lane b polling the three partials of slot b until they
+// carry step t's tag, and reduces them in slot order, so all waves take the same decision with
+// no barrier between workgroups; each thread then polls its columns of the winning row the same
+// way, and only the pivot column of the stripe passes through LDS. A slot of one parity is
+// rewritten every second step, so a word left from an earlier step differs by its tag for the
+// next three rewrites (the slots start with the tag of step -2); the index is range-checked
+// before use all the same. The polls are bounded: after kCoopSpin polls a workgroup marks the
+// job failed (info[0] = -2) and leaves, and the others leave at their next poll.
 constexpr int kCoopMaxBlk = 64;  // one slot per lane of a wave
 constexpr int kCoopSpin = 1 << 22;
+constexpr long long kNoRow = 0x7fffffffffffffffLL;
 
-// Relaxed device-scope polls; the caller's wave takes one acquire fence after all its lanes'
-// polls have succeeded, rather than one cache invalidation per poll.
-__device__ __forceinline__ bool coop_poll(const unsigned *stamp, unsigned target, PrrluCtl *ctl) {
+__device__ __forceinline__ int coop_tag(int t) { return (t >> 1) & 3; }
+__device__ __forceinline__ long long coop_word_d(double v, int tg) { return (__double_as_longlong(v) & ~3LL) | tg; }
+__device__ __forceinline__ double coop_val_d(long long b) { return __longlong_as_double(b & ~3LL); }
+__device__ __forceinline__ long long coop_word_i(long long i, int tg) {
+    return (i == kNoRow ? (kNoRow & ~3LL) : (i << 2)) | tg;
+}
+__device__ __forceinline__ long long coop_val_i(long long b) {
+    return (b & ~3LL) == (kNoRow & ~3LL) ? kNoRow : (b >> 2);
+}
+__device__ __forceinline__ void coop_put(long long *p, long long b) {
+    __hip_atomic_store(p, b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ long long coop_get(const long long *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Polls NW words until each carries tag tg (the loads of one round are issued together); false when the job has failed or the polls
+// ran out (then the job is marked failed).
+template <int NW>
+__device__ __forceinline__ bool coop_poll(const long long *const (&p)[NW], int tg, PrrluCtl *ctl, long long (&out)[NW]) {
     for (int sp = 0; sp < kCoopSpin; ++sp) {
-        if (__hip_atomic_load(stamp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) return true;
+        bool all = true;
+#pragma unroll
+        for (int q = 0; q < NW; ++q) {
+            out[q] = coop_get(p[q]);
+            all = all && (int)(out[q] & 3) == tg;
+        }
+        if (all) return true;
         if (__hip_atomic_load(&ctl->fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
         __builtin_amdgcn_s_sleep(1);
     }
@@ -1071,43 +1104,47 @@ __device__ __forceinline__ void prrlu_coop_body(const PrrluJob &J) {
             bs += wsum[k];
             amax_merge(bm, bi, wmax[k], widx[k]);
         }
+        const int tg = coop_tag(t);
+        long long *const pmx = (long long *)w.pmax(cur), *const psm = (long long *)w.psum(cur);
+        long long *const pix = w.pidx(cur), *const prw = (long long *)w.prow(cur);
         if (tid == 0) {
-            w.pmax(cur)[blk] = bm;
-            w.psum(cur)[blk] = bs;
-            w.pidx(cur)[blk] = bi;
+            coop_put(pmx + blk, coop_word_d(bm, tg));
+            coop_put(psm + blk, coop_word_d(bs, tg));
+            coop_put(pix + blk, coop_word_i(bi, tg));
         }
-        if (bi != 0x7fffffffffffffffLL && active) {  // a real row: ties go to the lowest index
+        if (bi != kNoRow && active) {  // a real row: ties go to the lowest index
             const int local = (int)(bi / n) - r0;
             if (local % RS == tr) {
-                double *dst = w.prow(cur) + (long long)blk * n;
+                long long *dst = prw + (long long)blk * n;
 #pragma unroll
                 for (int k = 0; k < kMwK; ++k)
                     if (k == local / RS)
 #pragma unroll
                         for (int j = 0; j < kMwTW; ++j)
-                            if (c0 + j < n) dst[c0 + j] = a[k][j];
+                            if (c0 + j < n) coop_put(dst + c0 + j, coop_word_d(a[k][j], tg));
             }
         }
-        __syncthreads();  // this workgroup's stores are complete before the stamp releases them
-        if (tid == 0)
-            __hip_atomic_store(&w.pseq(cur)[2 * blk], (unsigned)(t + 1), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         // every wave gathers every slot and decides pivot t on its own
         double gm = -1.0, gs = 0.0;
-        long long gi = 0x7fffffffffffffffLL;
+        long long gi = kNoRow;
         bool ok = true;
-        if (lane < G) ok = coop_poll(&w.pseq(cur)[2 * lane], (unsigned)(t + 1), w.ctl);
-        const bool wave_ok = __ballot(!ok) == 0;
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // every slot's partials and row are visible
+        long long got[3] = {0, 0, 0};
+        if (lane < G) {
+            const long long *const src[3] = {pmx + lane, psm + lane, pix + lane};
+            ok = coop_poll<3>(src, tg, w.ctl, got);
+        }
+        bool wave_ok = __ballot(!ok) == 0;
         if (lane < G && wave_ok) {
-            gm = w.pmax(cur)[lane];
-            gs = w.psum(cur)[lane];
-            gi = w.pidx(cur)[lane];
+            gm = coop_val_d(got[0]);
+            gs = coop_val_d(got[1]);
+            gi = coop_val_i(got[2]);
         }
         wave_amax_sum(gm, gi, gs);
         if (t == 0) tol2 = J.rel_tol2 * gs;
         int stop = (t >= rmax) || (gm <= 0.0) || (gs <= tol2);
         if (t == 0 && gm <= 0.0) stop = 2;  // all-zero block
         if (t == 0 && stop == 1) stop = 0;  // always take at least one pivot of a nonzero block
+        if (!stop && !(gi >= 0 && gi < (long long)m * n)) wave_ok = false;  // not a pivot of this block
         const int pi = stop ? 0 : (int)(gi / n), pj = stop ? 0 : (int)(gi % n);
         const int wk = stop ? 0 : pi / J.rows;  // the workgroup whose stripe holds the pivot row
         double uu[kMwTW], upj = 1.0;
@@ -1129,10 +1166,21 @@ __device__ __forceinline__ void prrlu_coop_body(const PrrluJob &J) {
                 }
             }
             if (!stop) {
-                const double *urow = w.prow(cur) + (long long)wk * n;
-                upj = urow[pj];
+                // the pivot entry and this thread's columns of the winning row, polled together
+                // (a column past the block's end polls the pivot entry again)
+                const long long *urow = prw + (long long)wk * n;
+                const long long *src[kMwTW + 1];
+                src[0] = urow + pj;
 #pragma unroll
-                for (int j = 0; j < kMwTW; ++j) uu[j] = (active && c0 + j < n) ? urow[c0 + j] : 0.0;
+                for (int j = 0; j < kMwTW; ++j) src[1 + j] = (active && c0 + j < n) ? urow + c0 + j : urow + pj;
+                long long v[kMwTW + 1];
+                if (coop_poll<kMwTW + 1>(src, tg, w.ctl, v)) {
+                    upj = coop_val_d(v[0]);
+#pragma unroll
+                    for (int j = 0; j < kMwTW; ++j) uu[j] = (active && c0 + j < n) ? coop_val_d(v[1 + j]) : 0.0;
+                } else {
+                    s_fail = 1;
+                }
                 if (active && pj >= c0 && pj < c0 + kMwTW) {  // the pivot column's owners publish it
 #pragma unroll
                     for (int j = 0; j < kMwTW; ++j)
@@ -1195,9 +1243,9 @@ __global__ void k_prrlu_mw_init(PrrluJob J) { prrlu_mw_init_body(J); }
 template <int K>
 __global__ __launch_bounds__(kMwThreads) void k_prrlu_mw_step(PrrluJob J, int t) { prrlu_mw_step_body<K>(J, t); }
 
-__global__ void k_prrlu_mw_init_batch(const PrrluJob *__restrict__ jobs, int njobs) {
-    const int z = blockIdx.x * blockDim.x + threadIdx.x;
-    if (z < njobs && jobs[z].mode >= 1) prrlu_mw_init_body(jobs[z]);
+__global__ void k_prrlu_mw_init_batch(const PrrluJob *__restrict__ jobs) {
+    const PrrluJob J = jobs[blockIdx.x];
+    if (J.mode >= 1) prrlu_mw_init_body(J);
 }
 
 // Steps the jobs of the modes in mode_mask (bit m: mode m) whose stripes hold K rows per thread.
@@ -2102,7 +2150,7 @@ size_t prrlu_ws_doubles(int m, int n) {
     PrrluJob j{};
     j.m = m; j.n = n;
     prrlu_prepare(j);
-    return 2 * (4 * (size_t)j.nblk + (size_t)j.nblk * n) + sizeof(PrrluCtl) / sizeof(double) + 1;
+    return 2 * (3 * (size_t)j.nblk + (size_t)j.nblk * n) + sizeof(PrrluCtl) / sizeof(double) + 1;
 }
 
 int prrlu(hipStream_t s, int m, int n, double *A, int rmax, double rel_tol2, int *rowpiv, int *colpiv, double *L,
@@ -2121,13 +2169,13 @@ int prrlu(hipStream_t s, int m, int n, double *A, int rmax, double rel_tol2, int
     }
     if (j.mode == 2 && j.nblk <= coop_capacity()) {  // the whole factorisation in one launch
         if (t_begin > 0) return rmax + 2;
-        k_prrlu_mw_init<<<1, 1, 0, s>>>(j);
+        k_prrlu_mw_init<<<1, kMwThreads, 0, s>>>(j);
         k_prrlu_coop<<<j.nblk, kMwThreads, 0, s>>>(j);
         WTT_HIP(hipGetLastError());
         return rmax + 2;
     }
     // launch t decides pivot t - 1, so the last possible decision (stop at rmax) is launch rmax + 1
-    if (t_begin == 0) k_prrlu_mw_init<<<1, 1, 0, s>>>(j);
+    if (t_begin == 0) k_prrlu_mw_init<<<1, kMwThreads, 0, s>>>(j);
     const int last = std::min(t_end, rmax + 1);
     for (int t = t_begin; t <= last; ++t) {
         if (j.mode == 3) k_prrlu_mw_step<kMwKBig><<<j.nblk, kMwThreads, 0, s>>>(j, t);
@@ -2226,7 +2274,7 @@ void prrlu_batch(hipStream_t s, int njobs, const PrrluJob *host_jobs, const Prrl
                 dispatch_tile(s, k, njobs, (size_t)lds_shape[k], dev_jobs, 0, 0, nullptr, 0, 0.0, nullptr, nullptr,
                               nullptr, nullptr);
     if (nmw) {
-        if (t_begin == 0) k_prrlu_mw_init_batch<<<cdiv(njobs, 64), 64, 0, s>>>(dev_jobs, njobs);
+        if (t_begin == 0) k_prrlu_mw_init_batch<<<njobs, kMwThreads, 0, s>>>(dev_jobs);
         if (coop) k_prrlu_coop_batch<<<dim3(maxcoop, njobs), kMwThreads, 0, s>>>(dev_jobs);
         const bool small = maxblk > 0 && (!coop || nmw - nbig > ncoop);  // mode 1, or mode 2 stepped
         for (int t = t_begin; t <= t_end; ++t) {
