@@ -302,10 +302,12 @@ def config5_tilted_sod_3d(n: int = 512, seed: int = 0, eps: float = 1e-6, rank_c
                 t_end=0.1, cfl=0.5, eps_mode=1, eps0=1e-6, note=f"seed {seed}, theta {math.degrees(theta):.3f} deg")
 
 
-def random_positive_tt(n, rank: int, seed: int, amp: float = 0.2, bc=None) -> Flow:
-    """A random smooth positive state with TT rank <= rank per variable:
+def random_positive_tt(n, rank: int, seed: int, amp: float = 0.2, bc=None, rough: bool = False) -> Flow:
+    """A random positive state with TT rank <= rank per variable:
     rho = 1 + amp T_0, rho u_d = amp T_d, rho E = 3 + amp T_E, where every T is a random TT
-    of low-frequency periodic profiles scaled so that |T| <= 1 everywhere."""
+    scaled so that |T| <= 1 everywhere. Its profiles are low-frequency periodic ones (three
+    frequencies, so the ranks stay <= 5 whatever `rank` asks for), or with rough=True
+    independent normal values in every cell, whose TT ranks are `rank` (generically)."""
     n = tuple(int(m) for m in n)
     d = len(n)
     rng = np.random.default_rng(seed)
@@ -316,10 +318,13 @@ def random_positive_tt(n, rank: int, seed: int, amp: float = 0.2, bc=None) -> Fl
         cores = []
         for k in range(d):
             prof = np.zeros((ranks[k], n[k], ranks[k + 1]))
-            for f in range(3):
-                c = rng.normal(size=(ranks[k], 1, ranks[k + 1])) / (1.0 + f)
-                ph = rng.uniform(0, 2 * math.pi, size=(ranks[k], 1, ranks[k + 1]))
-                prof += c * np.cos(2 * math.pi * f * xs[k][None, :, None] + ph)
+            if rough:
+                prof += rng.normal(size=prof.shape)
+            else:
+                for f in range(3):
+                    c = rng.normal(size=(ranks[k], 1, ranks[k + 1])) / (1.0 + f)
+                    ph = rng.uniform(0, 2 * math.pi, size=(ranks[k], 1, ranks[k + 1]))
+                    prof += c * np.cos(2 * math.pi * f * xs[k][None, :, None] + ph)
             # bound: |T| <= prod_k max_i ||core_k(i)||_inf-row-sum  -> normalise every core
             row = np.abs(prof).sum(axis=2).max()
             cores.append(prof / row)
@@ -337,4 +342,4 @@ def random_positive_tt(n, rank: int, seed: int, amp: float = 0.2, bc=None) -> Fl
     if bc is None:
         bc = (PERIODIC,) * d
     return Flow("random_tt_%dd" % d, d, n, (0.0,) * d, (1.0,) * d, tuple(bc), 1.4, comps, t_end=0.0,
-                eps_mode=0, eps0=1e-12, note=f"seed {seed}, rank {rank}")
+                eps_mode=0, eps0=1e-12, note=f"seed {seed}, rank {rank}" + (", rough" if rough else ""))
