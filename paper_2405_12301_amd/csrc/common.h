@@ -210,7 +210,9 @@ void weno_block(hipStream_t s, const FiberGeom &g, int p, int q, const T *W, dou
 
 // Dense evaluation of a TT list from the left part Lm[c] ((prod of N_0..N_{d-2}) x R) and the
 // last cores G[c] (R x N_{d-1}): mode 0 writes out[c][cell]; mode 1 reduces max(|u|+a) into
-// partial[block] and raises flags on non-physical cells.
+// partial[block] and raises flags on non-physical cells. nblocks must be
+// dense_eval_blocks(mode, nrows, R, nlast), the number of partials mode 1 writes.
+int dense_eval_blocks(int mode, long long nrows, int R, int nlast);
 void dense_eval(hipStream_t s, int mode, int d, int ncomp, long long nrows, int R, int nlast, const double *Lm,
                 long long lm_stride, const double *G, long long g_stride, double gamma, double *out, double *partial,
                 int nblocks, int *flags);

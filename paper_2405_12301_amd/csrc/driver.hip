@@ -407,8 +407,7 @@ double *exact_alpha_launch(wenott_ctx *c, const TT &U, int slot, bool readback =
     long long nrows = 1;
     for (int k = 0; k < U.d - 1; ++k) nrows *= U.N[k];
     int nlast = U.N[U.d - 1];
-    long long ncell = nrows * nlast;
-    int nblocks = (int)((ncell + 255) / 256);
+    const int nblocks = dense_eval_blocks(1, nrows, U.R[U.d - 1], nlast);
     double *part = c->sc.get<double>(S_PART, nblocks);
     dense_eval(c->s, 1, U.d, U.nc, nrows, U.R[U.d - 1], nlast, Lm, lms, U.core[U.d - 1], U.cstride(U.d - 1),
                c->gamma, nullptr, part, nblocks, c->d_flags);
@@ -432,8 +431,7 @@ void to_dense_dev(wenott_ctx *c, const TT &U, double *out) {
     long long nrows = 1;
     for (int k = 0; k < U.d - 1; ++k) nrows *= U.N[k];
     int nlast = U.N[U.d - 1];
-    long long ncell = nrows * nlast;
-    int nblocks = (int)((ncell + 255) / 256);
+    const int nblocks = dense_eval_blocks(0, nrows, U.R[U.d - 1], nlast);
     dense_eval(c->s, 0, U.d, U.nc, nrows, U.R[U.d - 1], nlast, Lm, lms, U.core[U.d - 1], U.cstride(U.d - 1),
                c->gamma, out, nullptr, nblocks, c->d_flags);
 }
@@ -561,7 +559,7 @@ PivotResult pivots(wenott_ctx *c, double *B, int m, int n, double rel_tol2, doub
         host_wait(c);
         const double state = pinned_pivot_info(c, rmax, 0);
         if (state >= 0.0) break;
-        WTT_REQUIRE(state != -2.0, WENOTT_EHIP, "pivot search: grid barrier wait ran out");
+        WTT_REQUIRE(state != -2.0, WENOTT_EHIP, "pivot search: the wait for the other workgroups ran out");
         WTT_REQUIRE(next <= rmax + 1, WENOTT_EHIP, "pivot search did not stop");
         ev_record(c, KC_PIVOT);
         next = prrlu(c->s, m, n, B, rmax, rel_tol2, piv, piv + rmax, L, info, ws, next, next + std::max(8, next / 2));
@@ -1392,7 +1390,7 @@ void batch_pivots(std::vector<BState *> &act, int dir, int k) {
         int rmax_open = 0;
         for (size_t z : open) {
             const double state = pinned_pivot_info(act[z]->c, act[z]->rmax, 0);
-            WTT_REQUIRE(state != -2.0, WENOTT_EHIP, "pivot search: grid barrier wait ran out");
+            WTT_REQUIRE(state != -2.0, WENOTT_EHIP, "pivot search: the wait for the other workgroups ran out");
             if (state < 0.0) {
                 still.push_back(z);
                 rmax_open = std::max(rmax_open, act[z]->rmax);

@@ -252,6 +252,61 @@ __global__ __launch_bounds__(256) void k_dense_eval(int mode, int ncomp, long lo
     }
 }
 
+// Mode 1 (the exact alpha) with the last core's column held in registers: thread j of a
+// workgroup keeps G[c][:, j] (NC x R values) and sweeps RB rows of the left part, whose entries
+// are the same for every thread of the workgroup (uniform loads); per cell it forms NC dot
+// products of length R from registers. The form above re-reads the column for every cell, and
+// at N^3 cells that L2 traffic, not the arithmetic, sets its time.
+template <int ND, int RM>
+__global__ __launch_bounds__(256) void k_alpha_eval(long long nrows, int R, int nlast, int RB,
+                                                    const double *__restrict__ Lm, long long lm_stride,
+                                                    const double *__restrict__ G, long long g_stride, double gamma,
+                                                    double *__restrict__ partial, int *__restrict__ flags) {
+    constexpr int NC = ND + 2;
+    __shared__ double red[4];
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    const bool jv = j < nlast;
+    double g[NC][RM];
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int b = 0; b < RM; ++b) g[c][b] = (jv && b < R) ? G[c * g_stride + (long long)b * nlast + j] : 0.0;
+    const long long r0 = (long long)blockIdx.y * RB, r1 = min(nrows, r0 + RB);
+    double speed = 0.0;
+    bool ok = true;
+    for (long long row = r0; row < r1; ++row) {
+        double qv[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const double *l = Lm + c * lm_stride + row * R;
+            double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+            for (int b = 0; b < RM; b += 2) {
+                if (b < R) s0 = fma(l[b], g[c][b], s0);
+                if (b + 1 < R) s1 = fma(l[b + 1], g[c][b + 1], s1);
+            }
+            qv[c] = s0 + s1;
+        }
+        if (jv) {
+            const double inv = 1.0 / qv[0];
+            double u2 = 0.0;
+#pragma unroll
+            for (int d = 0; d < ND; ++d) u2 += qv[1 + d] * qv[1 + d];
+            u2 *= inv * inv;
+            const double pr = (gamma - 1.0) * (qv[NC - 1] - 0.5 * qv[0] * u2);
+            const bool cell_ok = qv[0] > 0.0 && pr > 0.0;
+            ok = ok && cell_ok;
+            speed = fmax(speed, cell_ok ? sqrt(u2) + sqrt(gamma * pr * inv) : 0.0);
+        }
+    }
+    for (int off = kWave / 2; off > 0; off >>= 1) speed = fmax(speed, __shfl_xor(speed, off, kWave));
+    if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = speed;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        partial[(long long)blockIdx.y * gridDim.x + blockIdx.x] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    if (!ok) atomicOr(flags, kFlagNonPhys);
+}
+
 __global__ void k_reduce_max(const double *__restrict__ partial, int n, double *__restrict__ out) {
     __shared__ double red[16];
     double v = 0.0;
@@ -587,7 +642,6 @@ __global__ __launch_bounds__(256) void k_sample_stage(FiberGeom g, CoreSet fs, i
                                                       const double *__restrict__ ust, double wn, double wx, double wl,
                                                       StageArgsT<double> hs, double *__restrict__ acc, int *__restrict__ flags) {
     constexpr int NC = ND + 2;
-    constexpr int SL = 7 * ND + 1;
     __shared__ double red[2][4];
     const int pt = blockIdx.x * blockDim.x + threadIdx.x;
     double d2 = 0.0, n2 = 0.0;
@@ -685,12 +739,49 @@ template void weno_block<double>(hipStream_t, const FiberGeom &, int, int, const
 template void weno_block<float>(hipStream_t, const FiberGeom &, int, int, const float *, double *, long long,
                                 long long, long long, long long, int *);
 
+// Rows per workgroup of k_alpha_eval: enough workgroups (about 2048) to fill the device, at most
+// 64 rows each.
+int alpha_rows_per_block(long long nrows, int nlast) {
+    const long long gx = (long long)cdiv(nlast, 256);
+    return (int)std::max(1LL, std::min(64LL, nrows * gx / 2048));
+}
+
+// k_alpha_eval serves mode 1 when the rank fits its registers and each thread sweeps rows
+// enough (four or more) to repay holding the column.
+bool alpha_reg_path(int mode, long long nrows, int R, int nlast) {
+    return mode == 1 && R <= 32 && alpha_rows_per_block(nrows, nlast) >= 4;
+}
+
+int dense_eval_blocks(int mode, long long nrows, int R, int nlast) {
+    if (alpha_reg_path(mode, nrows, R, nlast))
+        return (int)((long long)cdiv(nlast, 256) * (long long)cdiv(nrows, alpha_rows_per_block(nrows, nlast)));
+    return (int)cdiv(nrows * nlast, 256);
+}
+
+template <int ND>
+void launch_alpha_eval(hipStream_t s, long long nrows, int R, int nlast, const double *Lm, long long lm_stride,
+                       const double *G, long long g_stride, double gamma, double *partial, int *flags) {
+    const int RB = alpha_rows_per_block(nrows, nlast);
+    const dim3 grid((unsigned)cdiv(nlast, 256), (unsigned)cdiv(nrows, RB));
+    if (R <= 8)
+        k_alpha_eval<ND, 8><<<grid, 256, 0, s>>>(nrows, R, nlast, RB, Lm, lm_stride, G, g_stride, gamma, partial, flags);
+    else if (R <= 16)
+        k_alpha_eval<ND, 16><<<grid, 256, 0, s>>>(nrows, R, nlast, RB, Lm, lm_stride, G, g_stride, gamma, partial, flags);
+    else
+        k_alpha_eval<ND, 32><<<grid, 256, 0, s>>>(nrows, R, nlast, RB, Lm, lm_stride, G, g_stride, gamma, partial, flags);
+}
+
 void dense_eval(hipStream_t s, int mode, int d, int ncomp, long long nrows, int R, int nlast, const double *Lm,
                 long long lm_stride, const double *G, long long g_stride, double gamma, double *out, double *partial,
                 int nblocks, int *flags) {
     (void)ncomp;
-    long long ncell = nrows * nlast;
-    WTT_REQUIRE(cdiv(ncell, 256) == (unsigned)nblocks, WENOTT_EINVAL, "dense_eval block count");
+    WTT_REQUIRE(dense_eval_blocks(mode, nrows, R, nlast) == nblocks, WENOTT_EINVAL, "dense_eval block count");
+    if (alpha_reg_path(mode, nrows, R, nlast)) {
+        if (d == 2) launch_alpha_eval<2>(s, nrows, R, nlast, Lm, lm_stride, G, g_stride, gamma, partial, flags);
+        else launch_alpha_eval<3>(s, nrows, R, nlast, Lm, lm_stride, G, g_stride, gamma, partial, flags);
+        WTT_HIP(hipGetLastError());
+        return;
+    }
     if (d == 2)
         k_dense_eval<2><<<nblocks, 256, 0, s>>>(mode, 4, nrows, R, nlast, Lm, lm_stride, G, g_stride, gamma, out,
                                                 partial, flags);

@@ -80,6 +80,24 @@ def test_round_error_bound_and_ranks(W, shape, rank, rough, eps):
 SCHEMES = [0, 1]
 
 
+@pytest.mark.parametrize("n", [96, 128])
+def test_exact_alpha_3d_register_path(W, n):
+    """The exact alpha at 96^3 and 128^3 (9216 and 16384 rows of the left part, so each thread of
+    the alpha kernel sweeps 4 and 8 rows with its column of the last core in registers) against
+    the oracle's alpha of the densified state."""
+    _say("case: exact alpha 3D smooth wave", n)
+    f = workloads.config3_wave_3d(n, seed=0)
+    s = W.Solver(f)
+    try:
+        ref = dense_of_cores(f.cores)
+        a = s.max_wavespeed()
+        want = oracle_problem(f).alpha(ref)
+        _say(f"  alpha {a!r} oracle {want!r}")
+        assert abs(a - want) <= 1e-12 * want
+    finally:
+        s.close()
+
+
 @pytest.mark.parametrize("scheme", SCHEMES)
 def test_rhs_matches_oracle_config1(W, scheme):
     _say("case: rhs, smooth wave 2D 64^2, scheme", scheme)
