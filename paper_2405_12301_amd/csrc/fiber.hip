@@ -253,50 +253,76 @@ __global__ __launch_bounds__(256) void k_dense_eval(int mode, int ncomp, long lo
 }
 
 // Mode 1 (the exact alpha) with the last core's column held in registers: thread j of a
-// workgroup keeps G[c][:, j] (NC x R values) and sweeps RB rows of the left part, whose entries
-// are the same for every thread of the workgroup (uniform loads); per cell it forms NC dot
-// products of length R from registers. The form above re-reads the column for every cell, and
-// at N^3 cells that L2 traffic, not the arithmetic, sets its time.
-template <int ND, int RM>
+// workgroup keeps G[c][:, j] (NC x R values) and sweeps RB rows of the left part, staged in LDS
+// first by one coalesced load of the chunk (NC x RB x R values, read back as broadcasts); per
+// cell it forms NC dot products of length R from registers. The form above re-reads the column
+// for every cell, and at N^3 cells that L2 traffic, not the arithmetic, sets its time; loading
+// the rows one by one inside the sweep would instead wait a memory round trip per row.
+// 1/x and sqrt(x) for x > 0 (sqrt(0) = 0) to about 1 ulp: the hardware estimates (about 23 correct
+// bits) refined by two Newton-Raphson steps each, for r = 1/x (r <- r + r (1 - x r)) and for
+// y = 1/sqrt(x) (y <- y + y (1 - x y^2) / 2), sqrt(x) = x y. The cell speeds only feed a maximum,
+// and these take a third of the instructions of the correctly rounded forms.
+__device__ __forceinline__ double nr_rcp(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return fma(r, fma(-x, r, 1.0), r);
+}
+__device__ __forceinline__ double nr_sqrt(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+    y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+    return x > 0.0 ? x * y : 0.0;
+}
+
+// RM: the register columns' length; EXACT: R == RM, so that no term needs a rank check.
+template <int ND, int RM, bool EXACT>
 __global__ __launch_bounds__(256) void k_alpha_eval(long long nrows, int R, int nlast, int RB,
                                                     const double *__restrict__ Lm, long long lm_stride,
                                                     const double *__restrict__ G, long long g_stride, double gamma,
                                                     double *__restrict__ partial, int *__restrict__ flags) {
     constexpr int NC = ND + 2;
+    if (EXACT) R = RM;
     __shared__ double red[4];
+    extern __shared__ double lrows[];  // [c][row - r0][b], NC x RB x R
     const int j = blockIdx.x * 256 + threadIdx.x;
     const bool jv = j < nlast;
+    const long long r0 = (long long)blockIdx.y * RB, r1 = min(nrows, r0 + RB);
+    const int chunk = RB * R;
+    for (int e = threadIdx.x; e < NC * chunk; e += 256) {
+        const int c = e / chunk, q = e - c * chunk;
+        lrows[e] = r0 * R + q < r1 * R ? Lm[c * lm_stride + r0 * R + q] : 0.0;
+    }
     double g[NC][RM];
 #pragma unroll
     for (int c = 0; c < NC; ++c)
 #pragma unroll
         for (int b = 0; b < RM; ++b) g[c][b] = (jv && b < R) ? G[c * g_stride + (long long)b * nlast + j] : 0.0;
-    const long long r0 = (long long)blockIdx.y * RB, r1 = min(nrows, r0 + RB);
+    __syncthreads();
     double speed = 0.0;
     bool ok = true;
     for (long long row = r0; row < r1; ++row) {
         double qv[NC];
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            const double *l = Lm + c * lm_stride + row * R;
+            const double *l = lrows + c * chunk + (row - r0) * R;
             double s0 = 0.0, s1 = 0.0;
 #pragma unroll
             for (int b = 0; b < RM; b += 2) {
-                if (b < R) s0 = fma(l[b], g[c][b], s0);
-                if (b + 1 < R) s1 = fma(l[b + 1], g[c][b + 1], s1);
+                if (EXACT || b < R) s0 = fma(l[b], g[c][b], s0);
+                if (b + 1 < RM && (EXACT || b + 1 < R)) s1 = fma(l[b + 1], g[c][b + 1], s1);
             }
             qv[c] = s0 + s1;
         }
         if (jv) {
-            const double inv = 1.0 / qv[0];
-            double u2 = 0.0;
+            const double inv = nr_rcp(qv[0]);
+            double m2 = 0.0;
 #pragma unroll
-            for (int d = 0; d < ND; ++d) u2 += qv[1 + d] * qv[1 + d];
-            u2 *= inv * inv;
+            for (int d = 0; d < ND; ++d) m2 = fma(qv[1 + d], qv[1 + d], m2);
+            const double u2 = m2 * inv * inv;
             const double pr = (gamma - 1.0) * (qv[NC - 1] - 0.5 * qv[0] * u2);
             const bool cell_ok = qv[0] > 0.0 && pr > 0.0;
             ok = ok && cell_ok;
-            speed = fmax(speed, cell_ok ? sqrt(u2) + sqrt(gamma * pr * inv) : 0.0);
+            speed = fmax(speed, cell_ok ? nr_sqrt(u2) + nr_sqrt(gamma * pr * inv) : 0.0);
         }
     }
     for (int off = kWave / 2; off > 0; off >>= 1) speed = fmax(speed, __shfl_xor(speed, off, kWave));
@@ -740,35 +766,47 @@ template void weno_block<float>(hipStream_t, const FiberGeom &, int, int, const 
                                 long long, long long, long long, int *);
 
 // Rows per workgroup of k_alpha_eval: enough workgroups (about 2048) to fill the device, at most
-// 64 rows each.
-int alpha_rows_per_block(long long nrows, int nlast) {
+// 64 rows each and at most 48 KB of staged rows (5 components x R doubles a row).
+int alpha_rows_per_block(long long nrows, int R, int nlast) {
     const long long gx = (long long)cdiv(nlast, 256);
-    return (int)std::max(1LL, std::min(64LL, nrows * gx / 2048));
+    const long long cap = std::min(64LL, 6144LL / (5LL * std::max(R, 1)));
+    return (int)std::max(1LL, std::min(cap, nrows * gx / 2048));
 }
 
 // k_alpha_eval serves mode 1 when the rank fits its registers and each thread sweeps rows
 // enough (four or more) to repay holding the column.
 bool alpha_reg_path(int mode, long long nrows, int R, int nlast) {
-    return mode == 1 && R <= 32 && alpha_rows_per_block(nrows, nlast) >= 4;
+    return mode == 1 && R <= 32 && alpha_rows_per_block(nrows, R, nlast) >= 4;
 }
 
 int dense_eval_blocks(int mode, long long nrows, int R, int nlast) {
     if (alpha_reg_path(mode, nrows, R, nlast))
-        return (int)((long long)cdiv(nlast, 256) * (long long)cdiv(nrows, alpha_rows_per_block(nrows, nlast)));
+        return (int)((long long)cdiv(nlast, 256) * (long long)cdiv(nrows, alpha_rows_per_block(nrows, R, nlast)));
     return (int)cdiv(nrows * nlast, 256);
 }
 
 template <int ND>
 void launch_alpha_eval(hipStream_t s, long long nrows, int R, int nlast, const double *Lm, long long lm_stride,
                        const double *G, long long g_stride, double gamma, double *partial, int *flags) {
-    const int RB = alpha_rows_per_block(nrows, nlast);
+    const int RB = alpha_rows_per_block(nrows, R, nlast);
     const dim3 grid((unsigned)cdiv(nlast, 256), (unsigned)cdiv(nrows, RB));
-    if (R <= 8)
-        k_alpha_eval<ND, 8><<<grid, 256, 0, s>>>(nrows, R, nlast, RB, Lm, lm_stride, G, g_stride, gamma, partial, flags);
-    else if (R <= 16)
-        k_alpha_eval<ND, 16><<<grid, 256, 0, s>>>(nrows, R, nlast, RB, Lm, lm_stride, G, g_stride, gamma, partial, flags);
-    else
-        k_alpha_eval<ND, 32><<<grid, 256, 0, s>>>(nrows, R, nlast, RB, Lm, lm_stride, G, g_stride, gamma, partial, flags);
+    const size_t lds = sizeof(double) * (size_t)(ND + 2) * RB * R;  // <= 48 KB
+#define WTT_ALPHA(RM_, EX_) \
+    k_alpha_eval<ND, RM_, EX_><<<grid, 256, lds, s>>>(nrows, R, nlast, RB, Lm, lm_stride, G, g_stride, gamma, partial, flags)
+    switch (R) {
+    case 1: WTT_ALPHA(1, true); break;
+    case 2: WTT_ALPHA(2, true); break;
+    case 3: WTT_ALPHA(3, true); break;
+    case 4: WTT_ALPHA(4, true); break;
+    case 5: WTT_ALPHA(5, true); break;
+    case 6: WTT_ALPHA(6, true); break;
+    case 7: WTT_ALPHA(7, true); break;
+    case 8: WTT_ALPHA(8, true); break;
+    default:
+        if (R <= 16) WTT_ALPHA(16, false);
+        else WTT_ALPHA(32, false);
+    }
+#undef WTT_ALPHA
 }
 
 void dense_eval(hipStream_t s, int mode, int d, int ncomp, long long nrows, int R, int nlast, const double *Lm,
