@@ -355,12 +355,26 @@ __device__ inline double tt_point(const CoreSet &cs, int c, const int *cell) {
     if (ND == 2) {
         return dot4(G0 + (long long)cell[0] * cs.R[1], 1, G1 + cell[1], cs.N[1], cs.R[1]);
     } else {
+        // four right indices at a time: per left index one contiguous run of G1(a, i1, be..be+3),
+        // so the loads of a run are issued together rather than one dependent dot product per be
         const double *G2 = cs.c[2] + c * cs.cstride[2];
+        const int R1 = cs.R[1], R2 = cs.R[2];
+        const long long s1 = (long long)cs.N[1] * R2;
+        const double *g0 = G0 + (long long)cell[0] * R1, *g1 = G1 + (long long)cell[1] * R2;
         double acc = 0.0;
-        for (int be = 0; be < cs.R[2]; ++be) {
-            const double v = dot4(G0 + (long long)cell[0] * cs.R[1], 1, G1 + (long long)cell[1] * cs.R[2] + be,
-                                  (long long)cs.N[1] * cs.R[2], cs.R[1]);
-            acc = fma(v, G2[(long long)be * cs.N[2] + cell[2]], acc);
+        for (int b0 = 0; b0 < R2; b0 += 4) {
+            const int nb = min(4, R2 - b0);
+            double v[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int a = 0; a < R1; ++a) {
+                const double x = g0[a];
+                const double *r = g1 + a * s1 + b0;
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    if (t < nb) v[t] = fma(x, r[t], v[t]);
+            }
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                if (t < nb) acc = fma(v[t], G2[(long long)(b0 + t) * cs.N[2] + cell[2]], acc);
         }
         return acc;
     }
