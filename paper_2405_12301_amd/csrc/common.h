@@ -166,6 +166,16 @@ __device__ inline double geom_alpha(const FiberGeom &g) { return g.alpha_dev ? *
 // (ghost-mapped): S = 6 for a face index (cells m-3..m+2), S = 7 for a cell (i-3..i+3).
 void iface(hipStream_t s, const FiberGeom &g, int side, const double *const *cores, const int *ranks, int count,
            const int *idx, int S, int shift_mode, double *out);
+// The same for up to 8 interface matrices of one block (same geometry, free core g.k) in one
+// launch; each request as the arguments of iface.
+struct IfaceReq {
+    const double *const *cores;
+    const int *ranks;
+    int side, count, S, shift_mode;
+    const int *idx;
+    double *out;
+};
+void iface_batch(hipStream_t s, const FiberGeom &g, int n, const IfaceReq *req);
 
 // Fused stage kernel: Y = wn Un + wx X + wl L(X) at the block points (a, i, b) of core k,
 // L(X) = -sum_d (Fhat_d(+1/2) - Fhat_d(-1/2)) / h_d from the seven cells around each point in

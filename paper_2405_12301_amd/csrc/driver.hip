@@ -895,48 +895,72 @@ void eval_stage_block(wenott_ctx *c, const TT &X, const TT *Un, StageWeights w, 
     const int *didxL = k > 0 ? c->ring.put(L.v.data(), L.v.size()) : nullptr;
     const int *didxR = k < d - 1 ? c->ring.put(Rs.v.data(), Rs.v.size()) : nullptr;
 
-    // W = P G_k Q for a TT (X or Un); S shifts on P (left) or Q (right) of mode `shift`.
-    auto gather = [&](const TT &Y, int shift, int slotP, int slotQ, int slotT, int slotW) -> double * {
-        const int Rk = Y.R[k], Rk1 = Y.R[k + 1];
-        int ranks[kMaxDim + 1];
-        for (int j = 0; j <= d; ++j) ranks[j] = Y.R[j];
-        const double *cores[kMaxDim];
-        for (int j = 0; j < d; ++j) cores[j] = Y.core[j];
-        const int SL = (shift >= 0 && shift < k) ? 7 : 1, SR = (shift > k) ? 7 : 1, S = std::max(SL, SR);
+    // W = P G_k Q for a TT (X or Un); S shifts on P (left) or Q (right) of mode `shift`. In two
+    // parts, so that the interface matrices of all the gathers of a block go in one launch: gplan
+    // takes P and Q from their slots and queues their requests, gfinish forms T = P G_k and
+    // W = T Q. A GatherJob stays in place until its requests have been launched.
+    struct GatherJob {
+        const TT *Y = nullptr;
+        int shift = -1, slotP = 0, slotQ = 0, slotT = 0, slotW = 0, SL = 1, SR = 1;
+        int ranks[kMaxDim + 1] = {};
+        const double *cores[kMaxDim] = {};
+        double *P = nullptr, *Q = nullptr;
+    };
+    auto gplan = [&](GatherJob &G, std::vector<IfaceReq> &rq) {
+        const TT &Y = *G.Y;
+        for (int j = 0; j <= d; ++j) G.ranks[j] = Y.R[j];
+        for (int j = 0; j < d; ++j) G.cores[j] = Y.core[j];
+        G.SL = (G.shift >= 0 && G.shift < k) ? 7 : 1;
+        G.SR = (G.shift > k) ? 7 : 1;
+        if (k > 0) {  // at the first core the left part is the scalar 1 (p = 1, R_0 = 1)
+            G.P = c->sc.get<double>(G.slotP, (size_t)nc * G.SL * p * Y.R[k]);
+            rq.push_back(IfaceReq{G.cores, G.ranks, 0, p, G.SL, G.SL == 7 ? G.shift : -1, didxL, G.P});
+        }
+        if (k < d - 1) {  // at the last core the right part is the scalar 1 (q = 1, R_d = 1)
+            G.Q = c->sc.get<double>(G.slotQ, (size_t)nc * G.SR * Y.R[k + 1] * q);
+            rq.push_back(IfaceReq{G.cores, G.ranks, 1, q, G.SR, G.SR == 7 ? G.shift : -1, didxR, G.Q});
+        }
+    };
+    auto gfinish = [&](GatherJob &G) -> double * {
+        const TT &Y = *G.Y;
+        const int Rk = Y.R[k], Rk1 = Y.R[k + 1], SL = G.SL, SR = G.SR, S = std::max(SL, SR);
         const long long tsz = (long long)p * Nk * Rk1;
-        // T = P G_k; at the first core the left part is the scalar 1 (p = 1, R_0 = 1) and T is
-        // the core itself
+        // T = P G_k; at the first core T is the core itself
         const double *T;
         long long tA1;
         if (k == 0) {
             T = Y.core[k];
             tA1 = Y.cstride(k);
         } else {
-            double *P = c->sc.get<double>(slotP, (size_t)nc * SL * p * Rk);
-            iface(s, g, 0, cores, ranks, p, didxL, SL, SL == 7 ? shift : -1, P);
-            double *Tm = c->sc.get<double>(slotT, (size_t)nc * SL * tsz);
+            double *Tm = c->sc.get<double>(G.slotT, (size_t)nc * SL * tsz);
             GemmBatch b1;
             b1.nb1 = nc; b1.nb2 = SL;
             b1.sA1 = (long long)SL * p * Rk; b1.sA2 = (long long)p * Rk;
             b1.sB1 = Y.cstride(k); b1.sB2 = 0;
             b1.sC1 = SL * tsz; b1.sC2 = tsz;
-            gemm_f64(s, false, false, p, Nk * Rk1, Rk, 1.0, P, Rk, Y.core[k], Nk * Rk1, 0.0, Tm, Nk * Rk1, b1);
+            gemm_f64(s, false, false, p, Nk * Rk1, Rk, 1.0, G.P, Rk, Y.core[k], Nk * Rk1, 0.0, Tm, Nk * Rk1, b1);
             T = Tm;
             tA1 = SL * tsz;
         }
-        // W = T Q; at the last core the right part is the scalar 1 (q = 1, R_d = 1) and W = T
+        // W = T Q; at the last core W = T
         if (k == d - 1) return const_cast<double *>(T);
-        double *Q = c->sc.get<double>(slotQ, (size_t)nc * SR * Rk1 * q);
-        iface(s, g, 1, cores, ranks, q, didxR, SR, SR == 7 ? shift : -1, Q);
         const long long wsz = (long long)p * Nk * q;
-        double *W = c->sc.get<double>(slotW, (size_t)nc * S * wsz);
+        double *W = c->sc.get<double>(G.slotW, (size_t)nc * S * wsz);
         GemmBatch b2;
         b2.nb1 = nc; b2.nb2 = S;
         b2.sA1 = tA1; b2.sA2 = SL == 7 ? tsz : 0;
         b2.sB1 = (long long)SR * Rk1 * q; b2.sB2 = SR == 7 ? (long long)Rk1 * q : 0;
         b2.sC1 = S * wsz; b2.sC2 = wsz;
-        gemm_f64(s, false, false, p * Nk, q, Rk1, 1.0, T, Rk1, Q, q, 0.0, W, q, b2);
+        gemm_f64(s, false, false, p * Nk, q, Rk1, 1.0, T, Rk1, G.Q, q, 0.0, W, q, b2);
         return W;
+    };
+    auto gather = [&](const TT &Y, int shift, int slotP, int slotQ, int slotT, int slotW) -> double * {
+        GatherJob G;
+        G.Y = &Y; G.shift = shift; G.slotP = slotP; G.slotQ = slotQ; G.slotT = slotT; G.slotW = slotW;
+        std::vector<IfaceReq> rq;
+        gplan(G, rq);
+        iface_batch(s, g, (int)rq.size(), rq.data());
+        return gfinish(G);
     };
     // FP32 gather: interface matrices formed in FP64 and rounded, the block contractions
     // P G_k Q in FP32 on the matrix cores.
@@ -988,6 +1012,10 @@ void eval_stage_block(wenott_ctx *c, const TT &X, const TT *Un, StageWeights w, 
         a32.W0 = gather32(X, -1, S_F_W0);
         a32.X0 = a.W0;
     }
+    // FP64: the gathers of X along the other directions and of Un, their interface matrices in
+    // one launch
+    GatherJob gj[kMaxDim + 1];
+    int gdir[kMaxDim + 1], ng = 0;
     int od = 0;
     for (int dd = 0; dd < d; ++dd) {
         a.inv_h[dd] = a32.inv_h[dd] = 1.0 / c->h[dd];
@@ -996,18 +1024,43 @@ void eval_stage_block(wenott_ctx *c, const TT &X, const TT *Un, StageWeights w, 
         if (fp32) {
             a32.Wd[dd] = gather32(X, dd, od == 0 ? S_F_WD0 : S_F_WD1);
         } else {
-            a.Wd[dd] = gather(X, dd, od == 0 ? S_PD0 : S_PD1, od == 0 ? S_QD0 : S_QD1, od == 0 ? S_TD0 : S_TD1,
-                              od == 0 ? S_WD0 : S_WD1);
-            if (od == 0) {  // X at the block points is the unshifted (centre) slice of this gather
-                a.W0 = a.Wd[dd] + 3 * blk;
-                a.X0 = a.W0;
-                a.w0_cs = 7 * blk;
-            }
+            GatherJob &G = gj[ng];
+            G.Y = &X; G.shift = dd;
+            G.slotP = od == 0 ? S_PD0 : S_PD1; G.slotQ = od == 0 ? S_QD0 : S_QD1;
+            G.slotT = od == 0 ? S_TD0 : S_TD1; G.slotW = od == 0 ? S_WD0 : S_WD1;
+            gdir[ng++] = dd;
         }
         ++od;
     }
     a.WN = nullptr;
-    if (Un && w.wn != 0.0) a.WN = gather(*Un, -1, S_PN, S_QN, S_TN, S_WN);
+    const bool want_un = Un && w.wn != 0.0;
+    if (fp32) {
+        if (want_un) a.WN = gather(*Un, -1, S_PN, S_QN, S_TN, S_WN);
+    } else {
+        if (want_un) {
+            GatherJob &G = gj[ng];
+            G.Y = Un; G.shift = -1; G.slotP = S_PN; G.slotQ = S_QN; G.slotT = S_TN; G.slotW = S_WN;
+            gdir[ng++] = -1;
+        }
+        std::vector<IfaceReq> rq;
+        for (int i = 0; i < ng; ++i) gplan(gj[i], rq);
+        iface_batch(s, g, (int)rq.size(), rq.data());
+        bool first = true;
+        for (int i = 0; i < ng; ++i) {
+            double *W = gfinish(gj[i]);
+            if (gdir[i] < 0) {
+                a.WN = W;
+            } else {
+                a.Wd[gdir[i]] = W;
+                if (first) {  // X at the block points is the unshifted (centre) slice of this gather
+                    a.W0 = W + 3 * blk;
+                    a.X0 = a.W0;
+                    a.w0_cs = 7 * blk;
+                    first = false;
+                }
+            }
+        }
+    }
     a.wn = a32.wn = w.wn; a.wx = a32.wx = w.wx; a.wl = a32.wl = w.wl;
     a32.WN = a.WN;
     long long sa, si, sb, sc;

@@ -42,12 +42,12 @@ __device__ inline int mode_index(const FiberGeom &g, int mode, int v, int s, int
     return v;
 }
 
-__global__ void k_iface(FiberGeom g, CoreSet cs, int side, int count, const int *__restrict__ idx, int S,
-                        int shift_mode, double *__restrict__ out) {
+__device__ inline void iface_entry(const FiberGeom &g, const CoreSet &cs, int side, int count,
+                                   const int *__restrict__ idx, int S, int shift_mode, double *__restrict__ out,
+                                   long long e) {
     const int k = g.k;
     const int Rout = side == 0 ? cs.R[k] : cs.R[k + 1];
     const long long tot = (long long)g.ncomp * S * count * Rout;
-    long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (e >= tot) return;
     const int beta = (int)(e % Rout);
     long long r = e / Rout;
@@ -90,6 +90,34 @@ __global__ void k_iface(FiberGeom g, CoreSet cs, int side, int count, const int 
         }
         out[(((long long)c * S + s) * Rout + beta) * count + a] = val;
     }
+}
+
+__global__ void k_iface(FiberGeom g, CoreSet cs, int side, int count, const int *__restrict__ idx, int S,
+                        int shift_mode, double *__restrict__ out) {
+    iface_entry(g, cs, side, count, idx, S, shift_mode, out, blockIdx.x * (long long)blockDim.x + threadIdx.x);
+}
+
+// Several interface matrices of one block (the left and right ones of every gather) in one
+// launch: job q owns workgroups [first[q], first[q + 1]).
+constexpr int kMaxIfaceJobs = 8;
+struct IfaceJob {
+    CoreSet cs;
+    const int *idx;
+    double *out;
+    int side, count, S, shift_mode;
+};
+struct IfaceBatch {
+    IfaceJob job[kMaxIfaceJobs];
+    int first[kMaxIfaceJobs + 1];
+    int n;
+};
+
+__global__ void k_iface_batch(FiberGeom g, IfaceBatch b) {
+    int q = 0;
+    while (q + 1 < b.n && (int)blockIdx.x >= b.first[q + 1]) ++q;
+    const IfaceJob &J = b.job[q];
+    iface_entry(g, J.cs, J.side, J.count, J.idx, J.S, J.shift_mode, J.out,
+                (long long)((int)blockIdx.x - b.first[q]) * blockDim.x + threadIdx.x);
 }
 
 // Left-biased WENO5-JS value at x_{i+1/2} from v_{i-2..i+2} (Sec. 2.2): candidate values,
@@ -759,6 +787,31 @@ void iface(hipStream_t s, const FiberGeom &g, int side, const double *const *cor
     long long tot = (long long)g.ncomp * S * count * Rout;
     if (tot == 0) return;
     k_iface<<<cdiv(tot, 256), 256, 0, s>>>(g, cs, side, count, idx, S, shift_mode, out);
+    WTT_HIP(hipGetLastError());
+}
+
+void iface_batch(hipStream_t s, const FiberGeom &g, int n, const IfaceReq *req) {
+    WTT_REQUIRE(n >= 0 && n <= kMaxIfaceJobs, WENOTT_EINVAL, "too many interface matrices in one launch");
+    int modes[kMaxDim];
+    for (int k = 0; k < g.d; ++k) modes[k] = g.n[k];
+    IfaceBatch b{};
+    long long blocks = 0;
+    for (int q = 0; q < n; ++q) {
+        const IfaceReq &r = req[q];
+        IfaceJob &J = b.job[b.n];
+        J.cs = make_coreset(g, r.cores, r.ranks, modes);
+        J.idx = r.idx; J.out = r.out; J.side = r.side; J.count = r.count; J.S = r.S; J.shift_mode = r.shift_mode;
+        const int Rout = r.side == 0 ? r.ranks[g.k] : r.ranks[g.k + 1];
+        const long long tot = (long long)g.ncomp * r.S * r.count * Rout;
+        if (tot == 0) continue;
+        b.first[b.n] = (int)blocks;
+        blocks += cdiv(tot, 256);
+        ++b.n;
+    }
+    if (b.n == 0) return;
+    WTT_REQUIRE(blocks < (1LL << 31), WENOTT_EINVAL, "interface matrices too large");
+    b.first[b.n] = (int)blocks;
+    k_iface_batch<<<(unsigned)blocks, 256, 0, s>>>(g, b);
     WTT_HIP(hipGetLastError());
 }
 
