@@ -1676,6 +1676,20 @@ __device__ __forceinline__ void chol_inv_reg(int r, double (&a)[RM]) {
 // whose space then holds G for the register factorisation of the first wave.
 constexpr int kGramMaxR = 32, kGramWaves = 8, kGramQ = 8;
 
+// The first wave's factorisation and inverse of G (Gs: kGramMaxR x kGramMaxR, upper triangle),
+// X = R^{-1} row-major r x r.
+template <int RM>
+__device__ __forceinline__ void gram_chol_finish(int r, const double *Gs, double *__restrict__ X) {
+    const int lane = threadIdx.x % kWave;
+    double a[RM];
+#pragma unroll
+    for (int k = 0; k < RM; ++k) a[k] = (k <= lane && lane < r) ? Gs[k * kGramMaxR + lane] : 0.0;
+    chol_inv_reg<RM>(r, a);
+#pragma unroll
+    for (int j = 0; j < RM; ++j)
+        if (j < r && lane < r) X[j * r + lane] = a[j];
+}
+
 __global__ __launch_bounds__(kGramWaves * 64) void k_gram_chol_inv(int m, int r, const double *__restrict__ Uall,
                                                                    long long sU, double *__restrict__ Xall,
                                                                    long long sX) {
@@ -1734,14 +1748,11 @@ __global__ __launch_bounds__(kGramWaves * 64) void k_gram_chol_inv(int m, int r,
     }
     __syncthreads();
     if (w != 0) return;
-    double a[kGramMaxR];
-#pragma unroll
-    for (int k = 0; k < kGramMaxR; ++k) a[k] = (k <= lane && lane < r) ? Gs[k * kGramMaxR + lane] : 0.0;
-    chol_inv_reg<kGramMaxR>(r, a);
     double *X = Xall + (long long)z * sX;
-#pragma unroll
-    for (int j = 0; j < kGramMaxR; ++j)
-        if (j < r && lane < r) X[j * r + lane] = a[j];
+    if (r <= 8) gram_chol_finish<8>(r, Gs, X);  // the unrolled code sized to r
+    else if (r <= 16) gram_chol_finish<16>(r, Gs, X);
+    else if (r <= 24) gram_chol_finish<24>(r, Gs, X);
+    else gram_chol_finish<kGramMaxR>(r, Gs, X);
 }
 
 __global__ __launch_bounds__(64) void k_chol_inv_wave(int r, const double *__restrict__ Gin, double *__restrict__ Xout) {
