@@ -285,23 +285,8 @@ __global__ __launch_bounds__(256) void k_dense_eval(int mode, int ncomp, long lo
 // first by one coalesced load of the chunk (NC x RB x R values, read back as broadcasts); per
 // cell it forms NC dot products of length R from registers. The form above re-reads the column
 // for every cell, and at N^3 cells that L2 traffic, not the arithmetic, sets its time; loading
-// the rows one by one inside the sweep would instead wait a memory round trip per row.
-// 1/x and sqrt(x) for x > 0 (sqrt(0) = 0) to about 1 ulp: the hardware estimates (about 23 correct
-// bits) refined by two Newton-Raphson steps each, for r = 1/x (r <- r + r (1 - x r)) and for
-// y = 1/sqrt(x) (y <- y + y (1 - x y^2) / 2), sqrt(x) = x y. The cell speeds only feed a maximum,
-// and these take a third of the instructions of the correctly rounded forms.
-__device__ __forceinline__ double nr_rcp(double x) {
-    double r = __builtin_amdgcn_rcp(x);
-    r = fma(r, fma(-x, r, 1.0), r);
-    return fma(r, fma(-x, r, 1.0), r);
-}
-__device__ __forceinline__ double nr_sqrt(double x) {
-    double y = __builtin_amdgcn_rsq(x);
-    y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
-    y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
-    return x > 0.0 ? x * y : 0.0;
-}
-
+// the rows one by one inside the sweep would instead wait a memory round trip per row. The cell
+// speeds only feed a maximum; their reciprocal and square roots are the Newton-refined ones.
 // RM: the register columns' length; EXACT: R == RM, so that no term needs a rank check.
 template <int ND, int RM, bool EXACT>
 __global__ __launch_bounds__(256) void k_alpha_eval(long long nrows, int R, int nlast, int RB,
