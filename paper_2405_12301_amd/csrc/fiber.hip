@@ -509,14 +509,23 @@ __device__ inline bool stage_dir(const T (&v)[ND + 2][7], int dir, T gm1, T alph
     return ok;
 }
 
+// Points are split over the directions: DG lanes per point (2 in 2D; 4 in 3D, one idle), lane d
+// forming the flux difference along direction d from its own gathered cells, the group's sum
+// taken by shuffles (lanes of a group are consecutive and all alive or all gone), and the
+// group's first lane forming the stage combination. A 3D block has ~10^4 points, a few dozen
+// workgroups at one point per thread; more and shorter threads shorten the dependent chain each
+// one runs. The direction-dependent operands are chosen by comparisons (a per-lane index into
+// the argument arrays would send them to scratch memory).
 template <int ND, typename T>
 __global__ __launch_bounds__(256) void k_stage(FiberGeom g, int p, int q, StageArgsT<T> sa_, double *__restrict__ out,
                                                long long sa, long long si, long long sb, long long sc,
                                                int *__restrict__ flags) {
-    constexpr int NC = ND + 2;
+    constexpr int NC = ND + 2, DG = ND == 2 ? 2 : 4;
     const int Nk = g.n[g.k];
     const long long tot = (long long)p * Nk * q;
-    long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    const long long et = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    const long long e = et / DG;
+    const int d = (int)(et % DG);
     if (e >= tot) return;
     const int b = (int)(e % q);
     const long long r = e / q;
@@ -527,8 +536,7 @@ __global__ __launch_bounds__(256) void k_stage(FiberGeom g, int p, int q, StageA
 #pragma unroll
     for (int c = 0; c < NC; ++c) acc[c] = T(0);
     bool ok = true;
-#pragma unroll
-    for (int d = 0; d < ND; ++d) {
+    if (d < ND) {
         T v[NC][7];
         if (d == g.k) {
 #pragma unroll
@@ -538,14 +546,22 @@ __global__ __launch_bounds__(256) void k_stage(FiberGeom g, int p, int q, StageA
                 for (int c = 0; c < NC; ++c) v[c][s] = sa_.W0[c * sa_.w0_cs + ((long long)a * Nk + cell) * q + b];
             }
         } else {
-            const T *W = sa_.Wd[d];
+            const T *W = d == 0 ? sa_.Wd[0] : (d == 1 ? sa_.Wd[1] : sa_.Wd[ND - 1]);
 #pragma unroll
             for (int s = 0; s < 7; ++s)
 #pragma unroll
                 for (int c = 0; c < NC; ++c) v[c][s] = W[((((long long)c * 7 + s) * p + a) * Nk + i) * q + b];
         }
-        ok &= stage_dir<ND, T>(v, d, gm1, alpha, T(sa_.eps_w[d]), T(sa_.inv_h[d]), acc);
+        const T eps = T(d == 0 ? sa_.eps_w[0] : (d == 1 ? sa_.eps_w[1] : sa_.eps_w[ND - 1]));
+        const T ih = T(d == 0 ? sa_.inv_h[0] : (d == 1 ? sa_.inv_h[1] : sa_.inv_h[ND - 1]));
+        ok = stage_dir<ND, T>(v, d, gm1, alpha, eps, ih, acc);
     }
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int off = 1; off < DG; off <<= 1) acc[c] += __shfl_xor(acc[c], off, kWave);
+    if (!ok) atomicOr(flags, kFlagNonPhys);
+    if (d != 0) return;
     bool finite = true;
     double *o = out + a * sa + i * si + b * sb;
 #pragma unroll
@@ -556,7 +572,6 @@ __global__ __launch_bounds__(256) void k_stage(FiberGeom g, int p, int q, StageA
         finite &= (y == y) && fabs(y) < 1e300;
         o[c * sc] = y;
     }
-    if (!ok) atomicOr(flags, kFlagNonPhys);
     if (!finite) atomicOr(flags, kFlagNaN);
 }
 
@@ -919,10 +934,10 @@ void stage_block(hipStream_t s, const FiberGeom &g, int p, int q, const StageArg
                  long long si, long long sb, long long sc, int *flags) {
     long long tot = (long long)p * g.n[g.k] * q;
     if (tot == 0) return;
-    if (g.d == 2)
-        k_stage<2, T><<<cdiv(tot, 256), 256, 0, s>>>(g, p, q, a, out, sa, si, sb, sc, flags);
-    else
-        k_stage<3, T><<<cdiv(tot, 256), 256, 0, s>>>(g, p, q, a, out, sa, si, sb, sc, flags);
+    if (g.d == 2)  // two lanes per point
+        k_stage<2, T><<<cdiv(2 * tot, 256), 256, 0, s>>>(g, p, q, a, out, sa, si, sb, sc, flags);
+    else  // four lanes per point
+        k_stage<3, T><<<cdiv(4 * tot, 256), 256, 0, s>>>(g, p, q, a, out, sa, si, sb, sc, flags);
     WTT_HIP(hipGetLastError());
 }
 template void stage_block<double>(hipStream_t, const FiberGeom &, int, int, const StageArgsT<double> &, double *,
