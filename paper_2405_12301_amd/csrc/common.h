@@ -218,6 +218,8 @@ void gemm_f32(hipStream_t s, int M, int N, int K, const float *A, int lda, const
               const GemmBatch &bt = GemmBatch());
 void to_f32(hipStream_t s, long long n, const double *x, float *y);
 
+// Workgroups (partial sum pairs written to acc) of sample_stage for d dimensions.
+int sample_stage_blocks(int d, int npts);
 // Exact stage value at random cells and the sampled residual of a TT of it: X at the 7 d
 // star cells (slot d*7 + s), Un at the point, TT approximation (shared cores + last core with
 // one slice per component).

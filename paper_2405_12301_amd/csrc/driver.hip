@@ -333,7 +333,7 @@ void raise_flags(wenott_ctx *c, int f) {
     }
 }
 
-constexpr int kStatusAlpha = 1, kStatusAcc = 8, kMaxResidualBlocks = 64;
+constexpr int kStatusAlpha = 1, kStatusAcc = 8, kMaxResidualBlocks = 256;
 constexpr int kStatusDoubles = kStatusAcc + 2 * kMaxResidualBlocks;
 
 int status_flags(const wenott_ctx *c) { return *(const int *)c->h_status; }
@@ -1092,7 +1092,7 @@ int sampled_stage_residual_launch(wenott_ctx *c, const TT &X, const TT *Un, Stag
     sample_points(c->s, npts, d, X.N, rng.next(), dp);
     const int SL = 7 * d + 1;
     double *ust = c->sc.get<double>(S_UST, (size_t)npts * SL * X.nc);
-    int nb = (npts + 255) / 256;
+    const int nb = sample_stage_blocks(d, npts);
     WTT_REQUIRE(nb <= kMaxResidualBlocks, WENOTT_EINVAL, "too many probe points");
     double *acc = c->d_status + kStatusAcc;
     int xr[kMaxDim + 1], nr[kMaxDim + 1], fr[kMaxDim + 1];

@@ -705,48 +705,44 @@ __global__ __launch_bounds__(256) void k_sample_star3(FiberGeom g, CoreSet cs, C
     }
 }
 
+// One point per DG lanes (2 in 2D; 4 in 3D, one idle), 256 / DG points per workgroup: lane d
+// forms the flux difference along direction d and a share of the flux TT's rank sum at the
+// point; the group adds both by shuffles and its first lane forms the residual terms. One
+// partial pair per workgroup (sample_stage_blocks of them).
 template <int ND>
 __global__ __launch_bounds__(256) void k_sample_stage(FiberGeom g, CoreSet fs, int npts, const int *__restrict__ pts,
-                                                      const double *__restrict__ ust, double wn, double wx, double wl,
-                                                      StageArgsT<double> hs, double *__restrict__ acc, int *__restrict__ flags) {
-    constexpr int NC = ND + 2;
+                                                       const double *__restrict__ ust, double wn, double wx, double wl,
+                                                       StageArgsT<double> hs, double *__restrict__ acc,
+                                                       int *__restrict__ flags) {
+    constexpr int NC = ND + 2, DG = ND == 2 ? 2 : 4;
     __shared__ double red[2][4];
-    const int pt = blockIdx.x * blockDim.x + threadIdx.x;
+    const int pt = blockIdx.x * (256 / DG) + threadIdx.x / DG, d = threadIdx.x % DG;
     double d2 = 0.0, n2 = 0.0;
     bool ok = true;
-    if (pt < npts) {
+    if (pt < npts) {  // the lanes of a point are alive together
         const double *u = ust + pt;  // slot q, component c at u[(q * NC + c) * npts]
-        double L[NC];
-        for (int c = 0; c < NC; ++c) L[c] = 0.0;
-        for (int d = 0; d < ND; ++d) {
+        double L[NC], approx[NC];
+        for (int c = 0; c < NC; ++c) L[c] = approx[c] = 0.0;
+        if (d < ND) {
             double v[NC][7];
             for (int s = 0; s < 7; ++s)
                 for (int c = 0; c < NC; ++c) v[c][s] = u[((long long)(d * 7 + s) * NC + c) * npts];
-            ok &= stage_dir<ND, double>(v, d, g.gamma - 1.0, geom_alpha(g), hs.eps_w[d], hs.inv_h[d], L);
+            const double eps = d == 0 ? hs.eps_w[0] : (d == 1 ? hs.eps_w[1] : hs.eps_w[ND - 1]);
+            const double ih = d == 0 ? hs.inv_h[0] : (d == 1 ? hs.inv_h[1] : hs.inv_h[ND - 1]);
+            ok = stage_dir<ND, double>(v, d, g.gamma - 1.0, geom_alpha(g), eps, ih, L);
         }
         const int *m = pts + pt * ND;
-        double approx[NC];
-        for (int c = 0; c < NC; ++c) approx[c] = 0.0;
-        if (ND == 2) {  // two rank terms per pass, each with its own accumulators
+        if (ND == 2) {  // rank terms al = d, d + DG, ...
             const double *g0 = fs.c[0] + (long long)m[0] * fs.R[1];
             const double *g1 = fs.c[1] + (long long)m[1] * NC;
             const long long st1 = (long long)fs.N[1] * NC;
-            double ap2[NC];
-            for (int c = 0; c < NC; ++c) ap2[c] = 0.0;
-            int al = 0;
-            for (; al + 1 < fs.R[1]; al += 2) {
-                const double l0 = g0[al], l1 = g0[al + 1];
-                const double *a0 = g1 + al * st1, *a1 = a0 + st1;
-                for (int c = 0; c < NC; ++c) {
-                    approx[c] = fma(l0, a0[c], approx[c]);
-                    ap2[c] = fma(l1, a1[c], ap2[c]);
-                }
+            for (int al = d; al < fs.R[1]; al += DG) {
+                const double l0 = g0[al];
+                const double *a0 = g1 + al * st1;
+                for (int c = 0; c < NC; ++c) approx[c] = fma(l0, a0[c], approx[c]);
             }
-            if (al < fs.R[1])
-                for (int c = 0; c < NC; ++c) approx[c] = fma(g0[al], g1[al * st1 + c], approx[c]);
-            for (int c = 0; c < NC; ++c) approx[c] += ap2[c];
-        } else {
-            for (int be = 0; be < fs.R[2]; ++be) {
+        } else {  // right rank terms be = d, d + DG, ...
+            for (int be = d; be < fs.R[2]; be += DG) {
                 double v = 0.0;
                 for (int al = 0; al < fs.R[1]; ++al)
                     v += fs.c[0][(long long)m[0] * fs.R[1] + al] * fs.c[1][((long long)al * fs.N[1] + m[1]) * fs.R[2] + be];
@@ -754,12 +750,20 @@ __global__ __launch_bounds__(256) void k_sample_stage(FiberGeom g, CoreSet fs, i
                 for (int c = 0; c < NC; ++c) approx[c] += v * last[c];
             }
         }
-        for (int c = 0; c < NC; ++c) {
-            double ex = wx * u[((long long)3 * NC + c) * npts] + wl * L[c] +
-                        (wn != 0.0 ? wn * u[((long long)7 * ND * NC + c) * npts] : 0.0);
-            d2 += (ex - approx[c]) * (ex - approx[c]);
-            n2 += ex * ex;
-        }
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+            for (int off = 1; off < DG; off <<= 1) {
+                L[c] += __shfl_xor(L[c], off, kWave);
+                approx[c] += __shfl_xor(approx[c], off, kWave);
+            }
+        if (d == 0)
+            for (int c = 0; c < NC; ++c) {
+                double ex = wx * u[((long long)3 * NC + c) * npts] + wl * L[c] +
+                            (wn != 0.0 ? wn * u[((long long)7 * ND * NC + c) * npts] : 0.0);
+                d2 += (ex - approx[c]) * (ex - approx[c]);
+                n2 += ex * ex;
+            }
     }
     for (int off = kWave / 2; off > 0; off >>= 1) {
         d2 += __shfl_xor(d2, off, kWave);
@@ -945,6 +949,8 @@ template void stage_block<double>(hipStream_t, const FiberGeom &, int, int, cons
 template void stage_block<float>(hipStream_t, const FiberGeom &, int, int, const StageArgsT<float> &, double *,
                                  long long, long long, long long, long long, int *);
 
+int sample_stage_blocks(int d, int npts) { return (int)cdiv((long long)npts * (d == 2 ? 2 : 4), 256); }
+
 void sample_stage(hipStream_t s, const FiberGeom &g, const double *const *xcores, const int *xranks,
                   const double *const *ncores, const int *nranks, int npts, const int *pts,
                   const double *const *fcores, const int *franks, double wn, double wx, double wl,
@@ -966,7 +972,8 @@ void sample_stage(hipStream_t s, const FiberGeom &g, const double *const *xcores
     long long n1 = (long long)npts * SL * g.ncomp;
     if (g.d == 2) {
         k_sample_star<2><<<cdiv(n1, 256), 256, 0, s>>>(g, xs, us, ncores != nullptr, npts, pts, ust);
-        k_sample_stage<2><<<cdiv(npts, 256), 256, 0, s>>>(g, fs, npts, pts, ust, wn, wx, wl, hs, acc, flags);
+        k_sample_stage<2><<<sample_stage_blocks(2, npts), 256, 0, s>>>(g, fs, npts, pts, ust, wn, wx, wl, hs, acc,
+                                                                     flags);
     } else {
         // the point-per-workgroup form pays off once a cell costs more than a few hundred
         // multiply-adds (R1 R2); below that one thread per sample is faster
@@ -975,7 +982,8 @@ void sample_stage(hipStream_t s, const FiberGeom &g, const double *const *xcores
             k_sample_star3<<<npts, 256, lds, s>>>(g, xs, us, ncores != nullptr, npts, pts, ust);
         else
             k_sample_star<3><<<cdiv(n1, 256), 256, 0, s>>>(g, xs, us, ncores != nullptr, npts, pts, ust);
-        k_sample_stage<3><<<cdiv(npts, 256), 256, 0, s>>>(g, fs, npts, pts, ust, wn, wx, wl, hs, acc, flags);
+        k_sample_stage<3><<<sample_stage_blocks(3, npts), 256, 0, s>>>(g, fs, npts, pts, ust, wn, wx, wl, hs, acc,
+                                                                     flags);
     }
     WTT_HIP(hipGetLastError());
 }
