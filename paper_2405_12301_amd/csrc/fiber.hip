@@ -509,18 +509,19 @@ __device__ inline bool stage_dir(const T (&v)[ND + 2][7], int dir, T gm1, T alph
     return ok;
 }
 
-// Points are split over the directions: DG lanes per point (2 in 2D; 4 in 3D, one idle), lane d
-// forming the flux difference along direction d from its own gathered cells, the group's sum
-// taken by shuffles (lanes of a group are consecutive and all alive or all gone), and the
-// group's first lane forming the stage combination. A 3D block has ~10^4 points, a few dozen
-// workgroups at one point per thread; more and shorter threads shorten the dependent chain each
-// one runs. The direction-dependent operands are chosen by comparisons (a per-lane index into
-// the argument arrays would send them to scratch memory).
-template <int ND, typename T>
+// DG lanes per point. With DG > 1 the points of a small block (a 3D block has ~10^4, a few dozen
+// workgroups at one point per thread) are split over the directions (DG = 2 in 2D; 4 in 3D, one
+// idle): lane d forms the flux difference along direction d from its own gathered cells, the
+// group's sum is taken by shuffles (the lanes of a group are consecutive and all alive or all
+// gone) and the group's first lane forms the stage combination; more and shorter threads
+// shorten the dependent chain each one runs. A large block fills the device at one point per
+// thread (DG = 1, every direction in one lane). The direction-dependent operands are chosen by
+// comparisons (a per-lane index into the argument arrays would send them to scratch memory).
+template <int ND, int DG, typename T>
 __global__ __launch_bounds__(256) void k_stage(FiberGeom g, int p, int q, StageArgsT<T> sa_, double *__restrict__ out,
                                                long long sa, long long si, long long sb, long long sc,
                                                int *__restrict__ flags) {
-    constexpr int NC = ND + 2, DG = ND == 2 ? 2 : 4;
+    constexpr int NC = ND + 2;
     const int Nk = g.n[g.k];
     const long long tot = (long long)p * Nk * q;
     const long long et = blockIdx.x * (long long)blockDim.x + threadIdx.x;
@@ -536,9 +537,10 @@ __global__ __launch_bounds__(256) void k_stage(FiberGeom g, int p, int q, StageA
 #pragma unroll
     for (int c = 0; c < NC; ++c) acc[c] = T(0);
     bool ok = true;
-    if (d < ND) {
+#pragma unroll
+    for (int dd = d; dd < ND; dd += DG) {
         T v[NC][7];
-        if (d == g.k) {
+        if (dd == g.k) {
 #pragma unroll
             for (int s = 0; s < 7; ++s) {
                 const int cell = ghost_map(i - 3 + s, Nk, g.bc[g.k]);
@@ -546,15 +548,15 @@ __global__ __launch_bounds__(256) void k_stage(FiberGeom g, int p, int q, StageA
                 for (int c = 0; c < NC; ++c) v[c][s] = sa_.W0[c * sa_.w0_cs + ((long long)a * Nk + cell) * q + b];
             }
         } else {
-            const T *W = d == 0 ? sa_.Wd[0] : (d == 1 ? sa_.Wd[1] : sa_.Wd[ND - 1]);
+            const T *W = dd == 0 ? sa_.Wd[0] : (dd == 1 ? sa_.Wd[1] : sa_.Wd[ND - 1]);
 #pragma unroll
             for (int s = 0; s < 7; ++s)
 #pragma unroll
                 for (int c = 0; c < NC; ++c) v[c][s] = W[((((long long)c * 7 + s) * p + a) * Nk + i) * q + b];
         }
-        const T eps = T(d == 0 ? sa_.eps_w[0] : (d == 1 ? sa_.eps_w[1] : sa_.eps_w[ND - 1]));
-        const T ih = T(d == 0 ? sa_.inv_h[0] : (d == 1 ? sa_.inv_h[1] : sa_.inv_h[ND - 1]));
-        ok = stage_dir<ND, T>(v, d, gm1, alpha, eps, ih, acc);
+        const T eps = T(dd == 0 ? sa_.eps_w[0] : (dd == 1 ? sa_.eps_w[1] : sa_.eps_w[ND - 1]));
+        const T ih = T(dd == 0 ? sa_.inv_h[0] : (dd == 1 ? sa_.inv_h[1] : sa_.inv_h[ND - 1]));
+        ok &= stage_dir<ND, T>(v, dd, gm1, alpha, eps, ih, acc);
     }
 #pragma unroll
     for (int c = 0; c < NC; ++c)
@@ -938,10 +940,14 @@ void stage_block(hipStream_t s, const FiberGeom &g, int p, int q, const StageArg
                  long long si, long long sb, long long sc, int *flags) {
     long long tot = (long long)p * g.n[g.k] * q;
     if (tot == 0) return;
-    if (g.d == 2)  // two lanes per point
-        k_stage<2, T><<<cdiv(2 * tot, 256), 256, 0, s>>>(g, p, q, a, out, sa, si, sb, sc, flags);
-    else  // four lanes per point
-        k_stage<3, T><<<cdiv(4 * tot, 256), 256, 0, s>>>(g, p, q, a, out, sa, si, sb, sc, flags);
+    const bool split = tot < (1LL << 17);  // fewer points than ~512 workgroups of one point per thread
+    if (g.d == 2) {
+        if (split) k_stage<2, 2, T><<<cdiv(2 * tot, 256), 256, 0, s>>>(g, p, q, a, out, sa, si, sb, sc, flags);
+        else k_stage<2, 1, T><<<cdiv(tot, 256), 256, 0, s>>>(g, p, q, a, out, sa, si, sb, sc, flags);
+    } else {
+        if (split) k_stage<3, 4, T><<<cdiv(4 * tot, 256), 256, 0, s>>>(g, p, q, a, out, sa, si, sb, sc, flags);
+        else k_stage<3, 1, T><<<cdiv(tot, 256), 256, 0, s>>>(g, p, q, a, out, sa, si, sb, sc, flags);
+    }
     WTT_HIP(hipGetLastError());
 }
 template void stage_block<double>(hipStream_t, const FiberGeom &, int, int, const StageArgsT<double> &, double *,
