@@ -85,8 +85,16 @@ void tsqr_r(hipStream_t s, int m, int n, int batch, const double *A, long long s
 // fit; otherwise scratch must hold jacobi_scratch_doubles(n, batch) doubles.
 // delta (device, one per matrix, may be null): truncation threshold of the singular values;
 // rotations whose effect stays far below it are skipped.
-void jacobi_svd(hipStream_t s, int n, int batch, const double *R, double *sigma, double *V, double *scratch,
-                const double *delta = nullptr);
+// tr (may be null): also form the truncation ranks as trunc_ranks would, in the same launch;
+// returns whether it did (false: the caller runs trunc_ranks).
+struct TruncArgs {
+    const double *delta_abs = nullptr;
+    double rel = 0.0;
+    int rcap = 0;
+    int *ranks = nullptr;
+};
+bool jacobi_svd(hipStream_t s, int n, int batch, const double *R, double *sigma, double *V, double *scratch,
+                const double *delta = nullptr, const TruncArgs *tr = nullptr);
 size_t jacobi_scratch_doubles(int n, int batch);
 
 // Full-pivot rank-revealing LU of one m x n row-major matrix (overwritten by its residual).

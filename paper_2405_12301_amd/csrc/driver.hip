@@ -1223,12 +1223,14 @@ int svd_ranks(wenott_ctx *c, int m, int n, const double *A, long long sz, long l
     *sig = c->sc.get<double>(S_SIG, (size_t)nc * n);
     *V = c->sc.get<double>(S_V, (size_t)nc * n * n);
     double *jac = c->sc.get<double>(S_JAC, jacobi_scratch_doubles(n, nc));
+    *rk = c->sc.get<int>(S_RANKS, nc);
+    TruncArgs ta;
+    ta.delta_abs = delta_abs; ta.rel = rel; ta.rcap = rcap; ta.ranks = *rk;
     ev_record(c, KC_SVD);
-    jacobi_svd(c->s, n, nc, R, *sig, *V, jac, rel == 0.0 ? delta_abs : nullptr);
+    const bool fused = jacobi_svd(c->s, n, nc, R, *sig, *V, jac, rel == 0.0 ? delta_abs : nullptr, &ta);
     ev_record(c, KC_SVD);
     add_work(c, KC_SVD, 0.0, 8.0 * nc * 3.0 * (double)n * n);
-    *rk = c->sc.get<int>(S_RANKS, nc);
-    trunc_ranks(c->s, n, nc, *sig, delta_abs, rel, rcap, *rk);
+    if (!fused) trunc_ranks(c->s, n, nc, *sig, delta_abs, rel, rcap, *rk);
     WTT_HIP(hipMemcpyAsync(c->h_pinned_int, *rk, nc * sizeof(int), hipMemcpyDeviceToHost, c->s));
     const bool tail = (size_t)nc * n <= 3000 && (c->o.use_proposal || c->logging);
     if (tail) WTT_HIP(hipMemcpyAsync(c->h_pinned_dbl + 1024, *sig, (size_t)nc * n * sizeof(double), hipMemcpyDeviceToHost, c->s));

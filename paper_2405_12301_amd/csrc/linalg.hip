@@ -698,7 +698,9 @@ __device__ __forceinline__ void jacobi_run(int n, double *X, int *nrot, double *
 // column); the right singular vectors of C are the normalised columns (row-major V, column pos
 // = singular vector pos; a zero column gives a zero vector, whose singular value 0 is never
 // kept by the truncation).
-__device__ void jacobi_finish(int n, const double *X, double *sig_tmp, double *sigma, double *Vout) {
+// sorted (LDS, may be null): also receives the singular values in descending order.
+__device__ void jacobi_finish(int n, const double *X, double *sig_tmp, double *sigma, double *Vout,
+                              double *sorted = nullptr) {
     const int tid = threadIdx.x, lane = tid % kWave, w = tid / kWave, nw = blockDim.x / kWave;
     for (int j = w; j < n; j += nw) {
         double s = 0.0;
@@ -713,7 +715,10 @@ __device__ void jacobi_finish(int n, const double *X, double *sig_tmp, double *s
         for (int i = lane; i < n; i += kWave) pos += (sig_tmp[i] > sj) || (sig_tmp[i] == sj && i < j);
         pos = (int)wave_sum((double)pos);
         const double inv = sj > 0.0 ? 1.0 / sj : 0.0;
-        if (lane == 0) sigma[pos] = sj;
+        if (lane == 0) {
+            sigma[pos] = sj;
+            if (sorted) sorted[pos] = sj;
+        }
         for (int i = lane; i < n; i += kWave) Vout[(long long)i * n + pos] = X[(long long)j * n + i] * inv;
     }
 }
@@ -723,17 +728,38 @@ __device__ __forceinline__ double jacobi_eta(const double *delta, int z, int n) 
 }
 
 // One workgroup per matrix; X = R^T is a plain copy of the row-major R (column j = row j).
+// With tr.ranks set, the truncation rank of each matrix is formed in the same launch from its
+// sorted singular values, by the arithmetic of trunc_ranks (the tail sum of the smallest
+// sigma^2 at most delta^2, at least 1, at most rcap).
 __global__ __launch_bounds__(1024) void k_jacobi_lds(int n, const double *__restrict__ Rin, double *__restrict__ sigma,
-                                                     double *__restrict__ Vout, const double *__restrict__ delta) {
+                                                     double *__restrict__ Vout, const double *__restrict__ delta,
+                                                     TruncArgs tr) {
     extern __shared__ double X[];
     __shared__ int nrot;
-    __shared__ double sig_tmp[512];
+    __shared__ double sig_tmp[512], sorted[512];
     const int z = blockIdx.x, tid = threadIdx.x;
     const double *Rz = Rin + (long long)z * n * n;
     for (int e = tid; e < n * n; e += blockDim.x) X[e] = Rz[e];
     __syncthreads();
     jacobi_run(n, X, &nrot, sig_tmp, jacobi_eta(delta, z, n));
-    jacobi_finish(n, X, sig_tmp, sigma + (long long)z * n, Vout + (long long)z * n * n);
+    jacobi_finish(n, X, sig_tmp, sigma + (long long)z * n, Vout + (long long)z * n * n, tr.ranks ? sorted : nullptr);
+    if (!tr.ranks) return;
+    __syncthreads();
+    if (tid == 0) {
+        double tot = 0.0;
+        for (int j = 0; j < n; ++j) tot += sorted[j] * sorted[j];
+        const double dl = tr.delta_abs ? tr.delta_abs[z] : tr.rel * sqrt(tot);
+        const double d2 = dl * dl;
+        double tail = 0.0;
+        int r = n;
+        while (r > 0 && tail + sorted[r - 1] * sorted[r - 1] <= d2) {
+            tail += sorted[r - 1] * sorted[r - 1];
+            --r;
+        }
+        if (r < 1) r = 1;
+        if (r > tr.rcap) r = tr.rcap;
+        tr.ranks[z] = r;
+    }
 }
 
 __global__ __launch_bounds__(1024) void k_jacobi_global(int n, const double *__restrict__ Rin,
@@ -2103,15 +2129,18 @@ int jacobi_threads(int n) {
     return std::min(1024, 64 * waves);
 }
 
-void jacobi_svd(hipStream_t s, int n, int batch, const double *R, double *sigma, double *V, double *scratch,
-                const double *delta) {
-    // static LDS of the kernel: the column-norm buffer (512 doubles) and a counter
+bool jacobi_svd(hipStream_t s, int n, int batch, const double *R, double *sigma, double *V, double *scratch,
+                const double *delta, const TruncArgs *tr) {
+    // static LDS of the kernel: the column-norm and sorted buffers (2 x 512 doubles), a counter
     const size_t lds = sizeof(double) * (size_t)n * n;
-    if (n <= 512 && lds + 512 * sizeof(double) + 64 <= (size_t)lds_limit_bytes())
-        k_jacobi_lds<<<batch, jacobi_threads(n), lds, s>>>(n, R, sigma, V, delta);
-    else
-        k_jacobi_global<<<batch, 1024, 0, s>>>(n, R, sigma, V, scratch, delta);
+    if (n <= 512 && lds + 2 * 512 * sizeof(double) + 64 <= (size_t)lds_limit_bytes()) {
+        k_jacobi_lds<<<batch, jacobi_threads(n), lds, s>>>(n, R, sigma, V, delta, tr ? *tr : TruncArgs{});
+        WTT_HIP(hipGetLastError());
+        return tr != nullptr;
+    }
+    k_jacobi_global<<<batch, 1024, 0, s>>>(n, R, sigma, V, scratch, delta);
     WTT_HIP(hipGetLastError());
+    return false;
 }
 
 size_t jacobi_scratch_doubles(int n, int batch) { return (size_t)batch * ((size_t)n * n + n); }
