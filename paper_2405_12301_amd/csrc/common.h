@@ -40,6 +40,16 @@ constexpr int kFlagNonPhys = 1;
 constexpr int kFlagNaN = 2;
 
 // Ghost-cell map: periodic wraps, transmissive clamps (both sides alike).
+// Random probe cells: coordinate j of point i is splitmix64(seed + golden (e + 1)) mod N_j with
+// e = i d + j, so any kernel can form a point's cell from (seed, i) alone.
+__host__ __device__ inline int probe_coord(unsigned long long seed, long long e, int nj) {
+    unsigned long long z = seed + 0x9E3779B97F4A7C15ULL * (unsigned long long)(e + 1);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    z ^= z >> 31;
+    return (int)(z % (unsigned long long)nj);
+}
+
 __host__ __device__ inline int ghost_map(int i, int n, int bc) {
     if (bc == WENOTT_BC_PERIODIC) {
         int r = i % n;
@@ -232,7 +242,7 @@ int sample_stage_blocks(int d, int npts);
 // star cells (slot d*7 + s), Un at the point, TT approximation (shared cores + last core with
 // one slice per component).
 void sample_stage(hipStream_t s, const FiberGeom &g, const double *const *xcores, const int *xranks,
-                  const double *const *ncores, const int *nranks, int npts, const int *pts,
+                  const double *const *ncores, const int *nranks, int npts, unsigned long long seed,
                   const double *const *fcores, const int *franks, double wn, double wx, double wl,
                   const double *inv_h, const double *eps_w, double *ust, double *acc, int *flags);
 

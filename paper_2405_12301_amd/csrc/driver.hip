@@ -1088,8 +1088,7 @@ int sampled_stage_residual_launch(wenott_ctx *c, const TT &X, const TT *Un, Stag
     g.d = d; g.ncomp = X.nc; g.dir = 0; g.k = 0;
     for (int j = 0; j < d; ++j) { g.n[j] = X.N[j]; g.bc[j] = c->bc[j]; }
     g.gamma = c->gamma; g.alpha = alpha; g.alpha_dev = c->alpha_dev;
-    int *dp = c->sc.get<int>(S_PTS, (size_t)npts * d);
-    sample_points(c->s, npts, d, X.N, rng.next(), dp);
+    const unsigned long long seed = rng.next();
     const int SL = 7 * d + 1;
     double *ust = c->sc.get<double>(S_UST, (size_t)npts * SL * X.nc);
     const int nb = sample_stage_blocks(d, npts);
@@ -1102,7 +1101,7 @@ int sampled_stage_residual_launch(wenott_ctx *c, const TT &X, const TT *Un, Stag
     double inv_h[kMaxDim], eps_w[kMaxDim];
     for (int j = 0; j < d; ++j) { inv_h[j] = 1.0 / c->h[j]; eps_w[j] = c->h[j] * c->h[j]; }
     const bool use_un = Un && w.wn != 0.0;
-    sample_stage(c->s, g, xc, xr, use_un ? ncs : nullptr, nr, npts, dp, fc, fr, use_un ? w.wn : 0.0, w.wx, w.wl,
+    sample_stage(c->s, g, xc, xr, use_un ? ncs : nullptr, nr, npts, seed, fc, fr, use_un ? w.wn : 0.0, w.wx, w.wl,
                  inv_h, eps_w, ust, acc, c->d_flags);
     status_readback(c, kStatusAcc + 2 * nb);
     return nb;

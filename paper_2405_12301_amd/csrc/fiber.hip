@@ -581,7 +581,7 @@ __global__ __launch_bounds__(256) void k_stage(FiberGeom g, int p, int q, StageA
 // Layout ust[(slot * NC + c) * npts + pt]: the point is the fastest index, so that the stage
 // kernel (one point per thread) reads it coalesced.
 template <int ND>
-__global__ void k_sample_star(FiberGeom g, CoreSet cs, CoreSet un, int use_un, int npts, const int *__restrict__ pts,
+__global__ void k_sample_star(FiberGeom g, CoreSet cs, CoreSet un, int use_un, int npts, unsigned long long seed,
                               double *__restrict__ ust) {
     constexpr int NC = ND + 2;
     constexpr int SL = 7 * ND + 1;
@@ -592,7 +592,7 @@ __global__ void k_sample_star(FiberGeom g, CoreSet cs, CoreSet un, int use_un, i
     const int slot = (int)(e / ((long long)npts * NC));
     int cell[ND];
 #pragma unroll
-    for (int d = 0; d < ND; ++d) cell[d] = pts[pt * ND + d];
+    for (int d = 0; d < ND; ++d) cell[d] = probe_coord(seed, (long long)pt * ND + d, g.n[d]);
     if (slot == 7 * ND) {
         ust[e] = use_un ? tt_point<ND>(un, c, cell) : 0.0;
         return;
@@ -622,14 +622,15 @@ __device__ inline double wave_sum_f(double v) {
 }
 
 __global__ __launch_bounds__(256) void k_sample_star3(FiberGeom g, CoreSet cs, CoreSet un, int use_un, int npts,
-                                                      const int *__restrict__ pts, double *__restrict__ ust) {
+                                                      unsigned long long seed, double *__restrict__ ust) {
     constexpr int NC = 5, SL = 22;
     extern __shared__ double sm[];
     __shared__ double red[4];
     __shared__ double vals[SL];
     const int pt = blockIdx.x, tid = threadIdx.x, lane = tid % kWave, w = tid / kWave;
     if (pt >= npts) return;
-    const int i0 = pts[pt * 3], i1 = pts[pt * 3 + 1], i2 = pts[pt * 3 + 2];
+    const int i0 = probe_coord(seed, (long long)pt * 3, g.n[0]), i1 = probe_coord(seed, (long long)pt * 3 + 1, g.n[1]),
+              i2 = probe_coord(seed, (long long)pt * 3 + 2, g.n[2]);
     const int N0 = g.n[0], N1 = g.n[1], N2 = g.n[2];
     for (int c = 0; c < NC; ++c) {
         const int R1 = cs.R[1], R2 = cs.R[2];
@@ -712,7 +713,7 @@ __global__ __launch_bounds__(256) void k_sample_star3(FiberGeom g, CoreSet cs, C
 // point; the group adds both by shuffles and its first lane forms the residual terms. One
 // partial pair per workgroup (sample_stage_blocks of them).
 template <int ND>
-__global__ __launch_bounds__(256) void k_sample_stage(FiberGeom g, CoreSet fs, int npts, const int *__restrict__ pts,
+__global__ __launch_bounds__(256) void k_sample_stage(FiberGeom g, CoreSet fs, int npts, unsigned long long seed,
                                                        const double *__restrict__ ust, double wn, double wx, double wl,
                                                        StageArgsT<double> hs, double *__restrict__ acc,
                                                        int *__restrict__ flags) {
@@ -733,7 +734,8 @@ __global__ __launch_bounds__(256) void k_sample_stage(FiberGeom g, CoreSet fs, i
             const double ih = d == 0 ? hs.inv_h[0] : (d == 1 ? hs.inv_h[1] : hs.inv_h[ND - 1]);
             ok = stage_dir<ND, double>(v, d, g.gamma - 1.0, geom_alpha(g), eps, ih, L);
         }
-        const int *m = pts + pt * ND;
+        int m[ND];
+        for (int dd = 0; dd < ND; ++dd) m[dd] = probe_coord(seed, (long long)pt * ND + dd, g.n[dd]);
         if (ND == 2) {  // rank terms al = d, d + DG, ...
             const double *g0 = fs.c[0] + (long long)m[0] * fs.R[1];
             const double *g1 = fs.c[1] + (long long)m[1] * NC;
@@ -958,7 +960,7 @@ template void stage_block<float>(hipStream_t, const FiberGeom &, int, int, const
 int sample_stage_blocks(int d, int npts) { return (int)cdiv((long long)npts * (d == 2 ? 2 : 4), 256); }
 
 void sample_stage(hipStream_t s, const FiberGeom &g, const double *const *xcores, const int *xranks,
-                  const double *const *ncores, const int *nranks, int npts, const int *pts,
+                  const double *const *ncores, const int *nranks, int npts, unsigned long long seed,
                   const double *const *fcores, const int *franks, double wn, double wx, double wl,
                   const double *inv_h, const double *eps_w, double *ust, double *acc, int *flags) {
     int modes[kMaxDim];
@@ -977,18 +979,18 @@ void sample_stage(hipStream_t s, const FiberGeom &g, const double *const *xcores
     const int SL = 7 * g.d + 1;
     long long n1 = (long long)npts * SL * g.ncomp;
     if (g.d == 2) {
-        k_sample_star<2><<<cdiv(n1, 256), 256, 0, s>>>(g, xs, us, ncores != nullptr, npts, pts, ust);
-        k_sample_stage<2><<<sample_stage_blocks(2, npts), 256, 0, s>>>(g, fs, npts, pts, ust, wn, wx, wl, hs, acc,
+        k_sample_star<2><<<cdiv(n1, 256), 256, 0, s>>>(g, xs, us, ncores != nullptr, npts, seed, ust);
+        k_sample_stage<2><<<sample_stage_blocks(2, npts), 256, 0, s>>>(g, fs, npts, seed, ust, wn, wx, wl, hs, acc,
                                                                      flags);
     } else {
         // the point-per-workgroup form pays off once a cell costs more than a few hundred
         // multiply-adds (R1 R2); below that one thread per sample is faster
         const size_t lds = sizeof(double) * 2 * ((size_t)xs.R[1] + xs.R[2]);
         if (lds <= 48 * 1024 && (long long)xs.R[1] * xs.R[2] > 512)
-            k_sample_star3<<<npts, 256, lds, s>>>(g, xs, us, ncores != nullptr, npts, pts, ust);
+            k_sample_star3<<<npts, 256, lds, s>>>(g, xs, us, ncores != nullptr, npts, seed, ust);
         else
-            k_sample_star<3><<<cdiv(n1, 256), 256, 0, s>>>(g, xs, us, ncores != nullptr, npts, pts, ust);
-        k_sample_stage<3><<<sample_stage_blocks(3, npts), 256, 0, s>>>(g, fs, npts, pts, ust, wn, wx, wl, hs, acc,
+            k_sample_star<3><<<cdiv(n1, 256), 256, 0, s>>>(g, xs, us, ncores != nullptr, npts, seed, ust);
+        k_sample_stage<3><<<sample_stage_blocks(3, npts), 256, 0, s>>>(g, fs, npts, seed, ust, wn, wx, wl, hs, acc,
                                                                      flags);
     }
     WTT_HIP(hipGetLastError());

@@ -187,17 +187,11 @@ void build_projectors(hipStream_t s, int n, int batch, int R, const double *sigm
     WTT_HIP(hipGetLastError());
 }
 
-// Random probe cells: coordinate j of point i is splitmix64(seed + golden (i d + j + 1)) mod N_j.
 __global__ void k_sample_points(int npts, int d, int n0, int n1, int n2, unsigned long long seed, int *__restrict__ out) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= npts * d) return;
     const int j = e % d;
-    unsigned long long z = seed + 0x9E3779B97F4A7C15ULL * (unsigned long long)(e + 1);
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
-    z ^= z >> 31;
-    const int nj = j == 0 ? n0 : (j == 1 ? n1 : n2);
-    out[e] = (int)(z % (unsigned long long)nj);
+    out[e] = probe_coord(seed, e, j == 0 ? n0 : (j == 1 ? n1 : n2));
 }
 
 void sample_points(hipStream_t s, int npts, int d, const int *n, unsigned long long seed, int *out) {
