@@ -260,6 +260,7 @@ struct wenott_ctx {
     wenott_opts o{};
     hipStream_t s = nullptr;
     hipEvent_t ev_wait = nullptr;  // host_wait's marker on s
+    unsigned long long waits = 0;  // host_wait calls so far
     TT U;
     TT rhs;
     bool have_rhs = false;
@@ -310,6 +311,7 @@ struct wenott_ctx {
 // its short spin runs out; the wake-up then delays the next launch at each of the
 // data-dependent readbacks of a step (pivot ranks, residuals, truncation ranks).
 void host_wait(wenott_ctx *c) {
+    ++c->waits;
     WTT_HIP(hipEventRecord(c->ev_wait, c->s));
     hipError_t e;
     while ((e = hipEventQuery(c->ev_wait)) == hipErrorNotReady) {
@@ -737,6 +739,14 @@ struct CrossTarget {
     int M[kMaxDim] = {};
     std::function<void(int k, const ISet &L, const ISet &R, bool lr, double *out)> eval;
     std::function<double(const FluxTT &F, Rng &rng)> residual;
+    // Optional speculation: residual_launch queues the residual check without waiting,
+    // speculate queues the consumer of an accepted F (and synchronises at its own readbacks),
+    // residual_finish then reads the residual, and discard drops the speculative result when
+    // the sweep is not accepted.
+    std::function<int(const FluxTT &F, Rng &rng)> residual_launch;
+    std::function<double(int nb)> residual_finish;
+    std::function<void(const FluxTT &F)> speculate;
+    std::function<void()> discard;
     int warm_slot = 0;
     bool learn = false;  // stage cross: keep bond histories, log samples, use the proposal
     double lambda = 0.0;
@@ -827,8 +837,26 @@ FluxTT cross_generic(wenott_ctx *c, const CrossTarget &t, double eps, CrossStat 
                 st.maxrank = std::max(st.maxrank, r);
             }
         }
-        resid = t.residual(F, rng);
-        if ((resid <= eps && !(cold && sweep == 0)) || sweep + 1 == c->o.max_sweeps) { ++sweep; break; }
+        if (t.speculate && !(cold && sweep == 0)) {
+            // the sweep is usually accepted: its consumer runs behind the residual check, and one
+            // synchronisation (the consumer's first readback) serves both
+            const int nb = t.residual_launch(F, rng);
+            const unsigned long long w0 = c->waits;
+            try {
+                t.speculate(F);
+            } catch (...) {
+                host_wait(c);
+                raise_flags(c, status_flags(c));  // a flux failure outranks its consequences
+                throw;
+            }
+            if (c->waits == w0) host_wait(c);
+            resid = t.residual_finish(nb);
+            if (resid <= eps || sweep + 1 == c->o.max_sweeps) { ++sweep; break; }
+            t.discard();
+        } else {
+            resid = t.residual(F, rng);
+            if ((resid <= eps && !(cold && sweep == 0)) || sweep + 1 == c->o.max_sweeps) { ++sweep; break; }
+        }
         // right-to-left sweep: refresh the right index sets from the new left ones
         for (int k = d - 1; k >= 1; --k) {
             ISet Lk = with_kick(Lset[k], rng, kick, 0, M);
@@ -1124,7 +1152,8 @@ double sampled_stage_residual(wenott_ctx *c, const TT &X, const TT *Un, StageWei
 }
 
 FluxTT cross_stage(wenott_ctx *c, const TT &X, const TT *Un, StageWeights w, double alpha, double eps,
-                   CrossStat &st) {
+                   CrossStat &st, const std::function<void(const FluxTT &)> *speculate = nullptr,
+                   const std::function<void()> *discard = nullptr) {
     // FP32 flux evaluation: the face-flux differences (Fhat(+1/2) - Fhat(-1/2)) / h cancel, so
     // the dt L part of the stage value carries relative noise up to ~1e-6 of the stage value;
     // the cross tolerance is floored there (pivots chasing FP32 noise would run to the cap).
@@ -1138,6 +1167,14 @@ FluxTT cross_stage(wenott_ctx *c, const TT &X, const TT *Un, StageWeights w, dou
         eval_stage_block(c, X, Un, w, alpha, k, L, R, lr, out);
     };
     t.residual = [&](const FluxTT &F, Rng &rng) { return sampled_stage_residual(c, X, Un, w, alpha, F, rng); };
+    if (speculate && discard) {
+        t.residual_launch = [&](const FluxTT &F, Rng &rng) {
+            return sampled_stage_residual_launch(c, X, Un, w, alpha, F, rng);
+        };
+        t.residual_finish = [&](int nb) { return sampled_residual_finish(c, nb); };
+        t.speculate = *speculate;
+        t.discard = *discard;
+    }
     t.warm_slot = kMaxDim;
     t.learn = w.wx != 0.0;  // stage crosses of rk3_step
     double hmin = c->h[0];
@@ -2114,14 +2151,34 @@ wenott_status wenott_rk3_step(wenott_ctx *c, double dt, double eps_in, const dou
                     c->info.alpha[st] = a;
                 }
                 TT S;
+                bool rounded = false;
                 if (c->o.scheme == 0) {
-                    // stage-cross: one cross of a_s U^n + b_s (X + dt L(X)) itself
+                    // stage-cross: one cross of a_s U^n + b_s (X + dt L(X)) itself; the rounding of
+                    // a sweep's result is queued behind that sweep's residual check and dropped
+                    // if the sweep is not accepted
                     CrossStat cs;
-                    FluxTT F = cross_stage(c, X, &c->U, StageWeights{aw[st], bw[st], bw[st] * dt}, a, eps, cs);
+                    const std::function<void(const FluxTT &)> spec = [&](const FluxTT &F) {
+                        S = cross_to_tt(c, F, -1);
+                        c->info.sum_rank[st] = S.maxrank();
+                        rounded = true;
+                        round_tt(c, S, eps, true, norms, st == 2);
+                    };
+                    const std::function<void()> drop = [&]() {
+                        S.release(c->s);
+                        rounded = false;
+                    };
+                    FluxTT F;
+                    try {
+                        F = cross_stage(c, X, &c->U, StageWeights{aw[st], bw[st], bw[st] * dt}, a, eps, cs, &spec,
+                                        &drop);
+                    } catch (...) {
+                        if (rounded) S.release(c->s);
+                        throw;
+                    }
                     c->info.sweeps[st][0] = cs.sweeps;
                     c->info.residual[st][0] = cs.residual;
                     c->info.flux_rank[st][0] = cs.maxrank;
-                    S = cross_to_tt(c, F, -1);
+                    if (!rounded) S = cross_to_tt(c, F, -1);
                     F.release(c->s);
                 } else {
                     std::vector<TT> terms = rhs_terms(c, X, a, eps, st);
@@ -2132,9 +2189,11 @@ wenott_status wenott_rk3_step(wenott_ctx *c, double dt, double eps_in, const dou
                     S = tt_sum(c, w);
                     for (auto &t : terms) t.release(c->s);
                 }
-                c->info.sum_rank[st] = S.maxrank();
-                // synchronises (the deferred alpha has arrived); the norms are needed after the last stage
-                round_tt(c, S, eps, true, norms, st == 2);
+                if (!rounded) {
+                    c->info.sum_rank[st] = S.maxrank();
+                    // synchronises (the deferred alpha has arrived); the norms are needed after the last stage
+                    round_tt(c, S, eps, true, norms, st == 2);
+                }
                 if (x_owned) X.release(c->s);
                 X = S;
                 x_owned = true;

@@ -165,9 +165,10 @@ def test_dense_comparator_matches_oracle(W, which):
         W.wenott_dense_destroy(ctx)
 
 
-def _step_parity(W, f, eps, nsteps=1, opts=None, tol_factor=10.0, scheme=0):
+def _step_parity(W, f, eps, nsteps=1, opts=None, tol_factor=10.0, scheme=0, sweeps_out=None):
     """Advance the TT path and the oracle from the same densified state with the same dt and
-    the alphas the TT path used; per-step error in the max_c ||.||_F / max_c ||.||_F norm."""
+    the alphas the TT path used; per-step error in the max_c ||.||_F / max_c ||.||_F norm.
+    sweeps_out, if given, receives each step's per-stage sweep counts."""
     o = opts if opts is not None else W.default_opts(eps0=eps, scheme=scheme)
     s = W.Solver(f, o)
     try:
@@ -182,12 +183,26 @@ def _step_parity(W, f, eps, nsteps=1, opts=None, tol_factor=10.0, scheme=0):
             P.ssprk3(u, dt, alphas=al)
             e = rel_err(s.dense(), u)
             errs.append(e)
+            if sweeps_out is not None:
+                sweeps_out.append([info.sweeps[j][0] for j in range(3)])
             _say("  step err", e, "eps", info.eps, "ranks", list(info.ranks), "sweeps",
                  [list(r) for r in info.sweeps], "sum ranks", list(info.sum_rank))
             assert e <= tol_factor * info.eps, (e, info.eps)
         return errs
     finally:
         s.close()
+
+
+def test_stage_cross_rejected_warm_sweep(W):
+    """A stage cross whose first (warm-started) sweep misses eps: the TT-rounding queued behind
+    that sweep's residual check is dropped, the refresh and second sweep run, and the step still
+    matches the oracle. Without the random kick the warm index sets cannot grow in the first
+    sweep, so the rank growth of the four-quadrant problem at eps 1e-10 forces such a stage."""
+    _say("case: rejected warm sweep, four-quadrant 2D 48^2, eps 1e-10, no kick")
+    f = workloads.config2_quadrants_2d(48, seed=1)
+    sw = []
+    _step_parity(W, f, 1e-10, nsteps=4, opts=W.default_opts(eps0=1e-10, eps_mode=0, kick_rank=0), sweeps_out=sw)
+    assert any(n >= 2 for st in sw[1:] for n in st), sw
 
 
 @pytest.mark.parametrize("scheme", SCHEMES)
