@@ -2,15 +2,18 @@
 
 A step is one SSP-RK3 step of WENO-TT (per stage: exact alpha, one rank-adaptive cross of the
 stage value whose fiber kernel gathers the star stencil from the TT cores and applies
-Lax-Friedrichs splitting and WENO5-JS, one TT-rounding; dynamic eps_TT) on the 2D
-four-quadrant Riemann problem, 512 x 512, transmissive, FP64, eps_TT(0) = 1e-8.
-dt = 0.5 h / alpha is taken from the state at the start of every step (inside the timed
-region). The state evolves through warmup and timed steps from t = 0.
+Lax-Friedrichs splitting and WENO5-JS, one TT-rounding; dynamic eps_TT). The default workload is
+the 3D tilted Sod problem, 512^3 on [0,1]^3, transmissive, FP64, eps_TT(0) = 1e-6: Sod states
+across a plane whose normal is e_x turned by a seeded angle (Sec. 5.5 shapes, eq. cfl-other
+time step). dt = 0.5 h / alpha is taken from the state at the start of every step (inside the
+timed region). The state evolves through warmup and timed steps from t = 0.
 
 Printed: one JSON line with the dense-equivalent throughput (cells x steps / s), the
 roofline of the dominant kernel class measured with HIP events on the library's stream
-(with the other classes as a breakdown), the dense GPU WENO5 comparator on the same
-workload, and the oracle timed on the host cores.
+(with the other classes as a breakdown), the dense GPU WENO5 comparator run with the same
+time steps, the L1 error of the density of both against the exact solution at the same time
+(on the central box [0.25, 0.75]^3 for the tilted Sod problem) with the equal-L1 check, and the
+oracle timed on the host cores.
 """
 from __future__ import annotations
 
@@ -34,13 +37,14 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--n", type=int, default=0, help="cells per dimension (0: the workload's own size)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-dense", action="store_true")
-    ap.add_argument("--workload", default="quadrants2d", choices=["quadrants2d", "wave3d", "sod3d", "blast_batch"],
-                    help="quadrants2d is the contract workload; the others are side measurements")
+    ap.add_argument("--workload", default="sod3d_tilted",
+                    choices=["sod3d_tilted", "quadrants2d", "wave3d", "sod3d", "blast_batch"],
+                    help="sod3d_tilted (512^3) is the contract workload; the others are side measurements")
     ap.add_argument("--batch", type=int, default=32, help="states of the blast_batch workload")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy three times (the reference for "
@@ -73,8 +77,8 @@ def cpu_baseline(flow, seconds):
         cells *= m
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": cells * steps / el, "unit": "cell-updates/s", "cores": cores, "kind": "oracle",
-            "sample": f"{steps} SSP-RK3 steps of the dense FP64 oracle from t=0 on the same {flow.n[0]}x{flow.n[1]} "
-                      f"initial state ({el:.1f} s)"}
+            "sample": f"{steps} SSP-RK3 step(s) of the dense FP64 oracle from t=0 on the same "
+                      f"{'x'.join(str(m) for m in flow.n)} initial state ({el:.1f} s)"}
 
 
 CLASS_NAMES = ["k_stage (fused star-stencil LF + WENO5-JS stage-value fiber kernel)",
@@ -215,6 +219,22 @@ def main():
     if args.workload == "blast_batch":
         blast_batch(args)
         return
+    single_state(args)
+
+
+def central_box_l1(rho_dev, flow, t, box):
+    """mean |rho - rho_exact| over the cells whose centres lie in box (lo, hi) per dimension."""
+    import numpy as np
+    n = flow.n[0]
+    xs = (np.arange(n) + 0.5) / n
+    idx = np.nonzero((xs >= box[0]) & (xs <= box[1]))[0]
+    a, b = int(idx[0]), int(idx[-1]) + 1
+    got = rho_dev[a:b, a:b, a:b].cpu().numpy()
+    return float(np.mean(np.abs(got - flow.exact_rho(t, box=box))))
+
+
+def single_state(args):
+    import numpy as np
     import torch
 
     import workloads
@@ -223,21 +243,33 @@ def main():
     W.load()
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    if args.workload == "quadrants2d":
-        flow = workloads.config2_quadrants_2d(args.n, seed=args.seed)
+    box = None
+    if args.workload == "sod3d_tilted":
+        n = args.n or 512
+        flow = workloads.config5_tilted_sod_3d(n, seed=args.seed)
         opts = W.default_opts(eps_mode=1, eps0=flow.eps0, precision=args.precision)
-        wl = (f"four-quadrant Riemann problem 2D {args.n}x{args.n}, transmissive, seed {args.seed}, "
+        box = (0.25, 0.75)
+        wl = (f"3D tilted Sod {n}^3 on [0,1]^3 ({flow.note}), transmissive, dynamic eps_TT from 1e-6, CFL 0.5; "
+              f"L1 of rho against the exact 1D Sod solution along the normal on [0.25,0.75]^3")
+    elif args.workload == "quadrants2d":
+        n = args.n or 512
+        flow = workloads.config2_quadrants_2d(n, seed=args.seed)
+        opts = W.default_opts(eps_mode=1, eps0=flow.eps0, precision=args.precision)
+        wl = (f"four-quadrant Riemann problem 2D {n}x{n}, transmissive, seed {args.seed}, "
               f"dynamic eps_TT from 1e-8, CFL 0.5")
     elif args.workload == "wave3d":
-        flow = workloads.config3_wave_3d(args.n, seed=args.seed)
+        n = args.n or 256
+        flow = workloads.config3_wave_3d(n, seed=args.seed)
         eps_w = 1e-10 if args.precision == 0 else 1e-6
         opts = W.default_opts(eps_mode=0, eps0=eps_w, precision=args.precision)
-        wl = (f"3D smooth density wave {args.n}^3 with 8 Fourier modes, periodic, eps_TT {eps_w:g} fixed, CFL 0.5; "
+        wl = (f"3D smooth density wave {n}^3 with 8 Fourier modes, periodic, eps_TT {eps_w:g} fixed, CFL 0.5; "
               f"L1 error of rho against the exact (translated) solution reported for TT and dense")
     else:
-        flow = workloads.sod_1d_like(3, args.n)
+        n = args.n or 256
+        flow = workloads.sod_1d_like(3, n)
         opts = W.default_opts(eps_mode=0, eps0=1e-6, precision=args.precision)
-        wl = f"3D Sod shock tube {args.n}^3 (axis-aligned, rank 1), transmissive, eps_TT 1e-6, CFL 0.5"
+        wl = f"3D Sod shock tube {n}^3 (axis-aligned, rank 1), transmissive, eps_TT 1e-6, CFL 0.5"
+    print(f"# workload: {wl}", file=sys.stderr, flush=True)
     cells = 1
     for m in flow.n:
         cells *= m
@@ -245,12 +277,13 @@ def main():
     solver = W.Solver(flow, opts)
     W.wenott_set_profiling(solver.ctx, True)
 
-    t_sim = 0.0
+    dts = []
     for _ in range(args.warmup):
         a = solver.max_wavespeed()
-        solver.step(flow.cfl * h / a)
-        t_sim += flow.cfl * h / a
+        dts.append(flow.cfl * h / a)
+        solver.step(dts[-1])
     torch.cuda.synchronize()
+    print(f"# warmup done, ranks {list(solver.info().ranks)[:flow.ndim + 1]}", file=sys.stderr, flush=True)
     ncls = 4
     cls_ms = [0.0] * ncls
     cls_fl = [0.0] * ncls
@@ -260,9 +293,8 @@ def main():
     t0 = time.perf_counter()
     for _ in range(args.steps):
         a = solver.max_wavespeed()
-        dt = flow.cfl * h / a
-        solver.step(dt)
-        t_sim += dt
+        dts.append(flow.cfl * h / a)
+        solver.step(dts[-1])
         inf = solver.info()
         for i in range(ncls):
             cls_ms[i] += inf.class_ms[i]
@@ -272,48 +304,52 @@ def main():
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     trace_mark(torch, dev)
+    t_sim = float(sum(dts))
     info = solver.info()
     ranks = list(info.ranks)[:flow.ndim + 1]
     eps_now = info.eps
+    print(f"# timed {args.steps} steps: {el * 1e3 / args.steps:.2f} ms/step, ranks {ranks}", file=sys.stderr,
+          flush=True)
     l1 = None
     if flow.exact_rho is not None:
-        import numpy as np
-        rho_tt = solver.dense(device=True)[0].cpu().numpy()
-        l1 = {"tt": float(np.mean(np.abs(rho_tt - flow.exact_rho(t_sim)))), "t_tt": t_sim}
+        rho_tt = solver.dense(device=True)[0]
+        if box is not None:
+            l1 = {"tt": central_box_l1(rho_tt, flow, t_sim, box), "t": t_sim, "box": list(box)}
+        else:
+            l1 = {"tt": float(np.mean(np.abs(rho_tt.cpu().numpy() - flow.exact_rho(t_sim)))), "t": t_sim}
         del rho_tt
     solver.close()
 
     roofline = roofline_of(cls_ms, cls_fl, cls_by, cls_n, args.steps,
-                           f"{args.workload}_{args.n}" if args.precision == 0 else None)
+                           f"{args.workload}_{n}" if args.precision == 0 else None)
 
     dense = None
     if not args.no_dense:
-        import numpy as np
-        # dense GPU WENO5 comparator on the same initial state and the same number of steps
-        u0 = None
-        s2 = W.Solver(flow, opts)
+        # dense GPU WENO5 comparator on the same initial state with the same time steps
+        s2 = W.Solver(flow, W.default_opts())
         u0 = s2.dense(device=True)
         s2.close()
         ctx = W.wenott_dense_init(flow.n, flow.lo, flow.hi, flow.gamma, flow.bc)
-        t_dense = 0.0
-        for _ in range(args.warmup):
-            a = W.wenott_dense_max_wavespeed(ctx, u0)
-            W.wenott_dense_rk3_step(ctx, u0, flow.cfl * h / a)
-            t_dense += flow.cfl * h / a
+        for dt in dts[:args.warmup]:
+            W.wenott_dense_rk3_step(ctx, u0, dt)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        for _ in range(args.steps):
-            a = W.wenott_dense_max_wavespeed(ctx, u0)
-            W.wenott_dense_rk3_step(ctx, u0, flow.cfl * h / a)
-            t_dense += flow.cfl * h / a
+        for dt in dts[args.warmup:]:
+            W.wenott_dense_max_wavespeed(ctx, u0)  # the TT step's dt rule reads alpha too
+            W.wenott_dense_rk3_step(ctx, u0, dt)
         torch.cuda.synchronize()
         el2 = time.perf_counter() - t1
         W.wenott_dense_destroy(ctx)
         if l1 is not None:
-            l1["dense"] = float(np.mean(np.abs(u0[0].cpu().numpy() - flow.exact_rho(t_dense))))
-            l1["t_dense"] = t_dense
+            if box is not None:
+                l1["dense"] = central_box_l1(u0[0], flow, t_sim, box)
+            else:
+                l1["dense"] = float(np.mean(np.abs(u0[0].cpu().numpy() - flow.exact_rho(t_sim))))
+            l1["equal_l1"] = bool(l1["tt"] <= 1.05 * l1["dense"])
+        del u0
         dense = {"value": cells * args.steps / el2, "unit": "cell-updates/s", "ms_per_step": el2 * 1e3 / args.steps,
-                 "note": "hand-written dense FP64 WENO5-JS + LF + SSP-RK3 on the same GPU, same steps"}
+                 "note": "hand-written dense FP64 WENO5-JS + LF + SSP-RK3 on the same GPU, the same time steps"}
+        print(f"# dense comparator {el2 * 1e3 / args.steps:.2f} ms/step", file=sys.stderr, flush=True)
 
     out = {
         "metric": METRIC,
@@ -333,12 +369,13 @@ def main():
         "roofline": roofline,
         "dense_gpu_weno5": dense,
     }
+    if dense is not None:
+        out["tt_over_dense"] = out["value"] / dense["value"]
     if l1 is not None:
         out["l1_error_vs_exact"] = l1
-    if not args.no_cpu_baseline and args.workload == "quadrants2d":
+    if not args.no_cpu_baseline and args.workload in ("sod3d_tilted", "quadrants2d"):
         out["cpu_baseline"] = cpu_baseline(flow, args.cpu_seconds)
     print(json.dumps(out))
-
 
 if __name__ == "__main__":
     main()

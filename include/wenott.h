@@ -86,12 +86,19 @@ typedef struct {
     int32_t alpha_mode; /* 0 exact max(|u|+a) over the grid, 2 use alpha_given [0] */
     int32_t use_proposal; /* 1: seed stage crosses from the learned proposal (wenott_set_proposal) [0] */
     double alpha_given; /* the Lax-Friedrichs alpha when alpha_mode = 2 */
-    int32_t rounds_per_stage; /* 1 = one rounding per SSP-RK3 stage [1] */
+    int32_t rounds_per_stage; /* 1: one rounding per SSP-RK3 stage, after the whole combination
+                                 a U^n + b (X + dt L(X)) [1]. 2: eq. tt-ssprk3 literally (Sec. 4.4):
+                                 X + dt L(X) is rounded (the forward Euler step of eq.
+                                 tt-forward-euler), and in stages 2 and 3 the combination with U^n
+                                 is rounded again. Not available in batched stepping. */
     int32_t graph_mode; /* reserved, must be 0 [0] */
     int32_t scheme;     /* 0: one cross per stage of the stage value a U^n + b (X + dt L(X)) itself;
                            1: one cross of the flux Fhat_d per direction (Algorithms lf-cross and
                               weno-cross fused), shift difference on core d, TT sum of the stage
-                              terms. Both round once per stage. [0] */
+                              terms. [0] */
+    double conv_slack;  /* a cross is accepted when its sampled relative residual is <= eps; one whose
+                           residual is still above conv_slack * eps after max_sweeps sweeps fails the
+                           call with ENOCONV (and the state is left unchanged). >= 1 [1] */
 } wenott_opts;
 
 /* Per-call diagnostics, filled by wenott_get_info. */
@@ -121,6 +128,12 @@ typedef struct {
     /* learned proposal: stage crosses seeded by it and those whose first sweep was accepted */
     int64_t proposals_tried, proposals_accepted;
     int64_t pivots_total;    /* rank-revealing LU pivots taken in the last call */
+    /* pivot searches of the last call that stopped at their rank limit (min(rank_cap, 128) or the
+     * block's size) while their residual was still above the pivot tolerance */
+    int64_t rank_capped;
+    /* pivot searches of the last call whose single-launch (persistent) form gave up waiting for
+     * workgroups that were not resident, and that were redone with one launch per pivot */
+    int64_t pivot_fallbacks;
 } wenott_info;
 
 /* Fill *o with the defaults. */
@@ -190,14 +203,25 @@ wenott_status wenott_gemm_autotune_table(int32_t *out, int32_t max, int32_t *cou
  * truncated SVDs, so that ||X - Y||_F <= eps ||X||_F per component. eps > 0. */
 wenott_status wenott_round(wenott_ctx *ctx, double eps);
 
-/* Dense values of the state into a caller buffer out[ncomp][N_1][N_2][N_3] (C order, FP64).
- * on_device = 1: out is device memory (written on the stream); 0: host memory (synchronises). */
+/* Dense values of the state: every cell's value is the product of its core slices,
+ * U(i_1..i_d) = G_1(i_1) ... G_d(i_d) (Sec. 3.1, eqs. TT_def and TT_def_2), for every conserved
+ * variable of the list U_TT (Sec. 4.1, after eq. euler-system-TT), written to a caller buffer
+ * out[ncomp][N_1][N_2][N_3] (C order, FP64, interior cells only; the caller owns it).
+ * on_device = 1: out is device memory (written on the stream, no synchronisation); 0: host
+ * memory (synchronises). Errors: EINVAL on NULL arguments, EHIP. */
 wenott_status wenott_to_dense(wenott_ctx *ctx, double *out, int32_t on_device);
 
-/* Library-owned view of the current state (device cores, padded common ranks). */
+/* Library-owned view of the current state U_TT (Sec. 4.1: one TT per conserved variable, cores
+ * as in eq. TT_def): device core pointers and padded common ranks (the zero-padded rows and
+ * columns leave every value of eq. TT_def_2 unchanged). Valid until the next call that changes
+ * the state; the caller must not free or write it. Errors: EINVAL on NULL arguments. */
 wenott_status wenott_get_state(wenott_ctx *ctx, wenott_tt *view);
 
-/* Diagnostics of the last rhs / rk3_step call and the current ranks. Synchronises. */
+/* Diagnostics of the last rhs / rk3_step call and the current ranks: the alpha of each stage
+ * (eq. lax-friedrichs with the alpha of Sec. 4.2), the eps_TT and C_eps of eq. eps-tt-formula
+ * (Sec. 4.6), the sweeps and sampled residuals of each cross (Sec. 3.3 and the eps_cross =
+ * eps_TT rule of Sec. 5), the ranks before and after each rounding (Sec. 3.2), and the kernel
+ * class timings. Copied into the caller's struct. Synchronises. Errors: EINVAL on NULL. */
 wenott_status wenott_get_info(wenott_ctx *ctx, wenott_info *info);
 
 /* max over the grid of |u| + a for the current state (the alpha of eq. lax-friedrichs as
@@ -207,6 +231,12 @@ wenott_status wenott_max_wavespeed(wenott_ctx *ctx, double *alpha);
 
 /* Current eps_TT of the dynamic rule (eq. eps-tt-formula) or the fixed one. */
 wenott_status wenott_current_eps(wenott_ctx *ctx, double *eps);
+
+/* Testing hook (process-wide): the bound on the polls with which the single-launch pivot search
+ * waits for its other workgroups. < 0 restores the default bound; 0 makes every such wait give
+ * up at once, so that the fallback (the block evaluated again and searched one launch per pivot
+ * step, counted in wenott_info.pivot_fallbacks) runs. Every kernel still ends normally. */
+wenott_status wenott_set_pivot_wait_limit(int32_t polls);
 
 /* Record device time of the fiber kernels (reported as fiber_ms by wenott_get_info). */
 wenott_status wenott_set_profiling(wenott_ctx *ctx, int32_t on);

@@ -110,7 +110,7 @@ size_t jacobi_scratch_doubles(int n, int batch);
 // Full-pivot rank-revealing LU of one m x n row-major matrix (overwritten by its residual).
 // Stops when the residual's squared Frobenius norm <= rel_tol2 * (initial squared norm), after
 // rmax pivots, or at a zero residual. Writes rank (>= 1), row/col pivots, L columns (m x rmax, row-major) and the final
-// residual norm^2 into info[0..1] = {rank, resid2} (as doubles).
+// residual norm^2 and the stopping threshold into info[0..2] = {rank, resid2, tol2} (as doubles).
 // ws: prrlu_ws_doubles(m, n) doubles (double-buffered per-workgroup partials and candidate rows,
 // and control, of the multi-workgroup form used when the block does not fit one workgroup's
 // registers). That form runs one launch per step, launch t deciding pivot t - 1 and eliminating
@@ -118,9 +118,13 @@ size_t jacobi_scratch_doubles(int n, int batch);
 // stays negative until the factorisation has stopped, and the caller continues from the
 // returned step. The register form and the persistent form finish in one call (t_begin = 0);
 // info[0] = -2 reports a persistent launch whose waits for the other workgroups' partials ran
-// out. Needs rmax >= 1.
+// out (A is then partly eliminated: the caller evaluates it again and calls with
+// allow_persistent = false, which takes the one-launch-per-step form). Needs rmax >= 1.
 int prrlu(hipStream_t s, int m, int n, double *A, int rmax, double rel_tol2, int *rowpiv, int *colpiv, double *L,
-          double *info, double *ws, int t_begin, int t_end);
+          double *info, double *ws, int t_begin, int t_end, bool allow_persistent = true);
+// Bound on the polls of the persistent pivot search's waits for other workgroups (< 0: the
+// default bound; 0: the waits give up at once, to exercise the fallback). Process-wide.
+void set_coop_spin(int polls);
 size_t prrlu_ws_doubles(int m, int n);
 
 // X = R^{-1} for the upper Cholesky factor R of each r x r Gram matrix G (batch); ws holds
@@ -143,6 +147,7 @@ struct PrrluJob {
     // multi-workgroup (rows per workgroup, workgroups) stepped one launch per pivot, 2 the same
     // layout in one persistent launch (when the workgroups can all be resident)
     int mode, shape, rows, nblk;
+    int spin;  // poll bound of the persistent form's waits (set by prrlu_prepare)
 };
 void prrlu_prepare(PrrluJob &j);
 struct SvdJob {

@@ -517,6 +517,7 @@ ISet with_kick(const ISet &base, Rng &rng, int kick, int first_mode, const int *
 
 struct PivotResult {
     int rank;
+    bool capped = false;  // stopped at the rank limit with the residual above the tolerance
     std::vector<int> rows, cols;
 };
 
@@ -530,13 +531,13 @@ int pivot_guess(const wenott_ctx *c, int hist_slot, int n, int rmax) {
     return std::max(1, std::min(g, rmax));
 }
 
-// Pivot indices (2 rmax + 2 ints) and the {rank, residual} pair share one device buffer, so
-// that one transfer brings both back: byte offset of the pair.
+// Pivot indices (2 rmax + 2 ints) and the {rank, residual, threshold} triple share one device
+// buffer, so that one transfer brings both back: byte offset of the triple.
 size_t pivot_info_offset(int rmax) { return ((2 * (size_t)rmax + 2) * sizeof(int) + 7) / 8 * 8; }
 
 int *pivot_buffer(wenott_ctx *c, int rmax, double **info) {
     const size_t off = pivot_info_offset(rmax);
-    int *piv = c->sc.get<int>(S_PIV, off / sizeof(int) + 4);
+    int *piv = c->sc.get<int>(S_PIV, off / sizeof(int) + 6);
     *info = (double *)((char *)piv + off);
     return piv;
 }
@@ -545,30 +546,49 @@ double pinned_pivot_info(const wenott_ctx *c, int rmax, int which) {
     return ((const double *)((const char *)c->h_pinned_int + pivot_info_offset(rmax)))[which];
 }
 
-PivotResult pivots(wenott_ctx *c, double *B, int m, int n, double rel_tol2, double **Lout, int hist_slot) {
+// Full-pivot rank-revealing LU of the block B (m x n). When the single-launch persistent form
+// gives up waiting for workgroups that are not all resident (info -2), the block is partly
+// eliminated: reeval() writes it again and the search is redone one launch per step.
+PivotResult pivots(wenott_ctx *c, double *B, int m, int n, double rel_tol2, double **Lout, int hist_slot,
+                   const std::function<void()> &reeval) {
     int rmax = std::min(std::min(c->o.rank_cap, kMaxRankLds), std::min(m, n));
     double *info = nullptr;
     int *piv = pivot_buffer(c, rmax, &info);
     double *L = c->sc.get<double>(S_L, (size_t)m * rmax);
     double *ws = c->sc.get<double>(S_ROWBUF, prrlu_ws_doubles(m, n));
+    bool persistent = true;
     ev_record(c, KC_PIVOT);
     int next = prrlu(c->s, m, n, B, rmax, rel_tol2, piv, piv + rmax, L, info, ws, 0,
                      pivot_guess(c, hist_slot, n, rmax) + 1);
     ev_record(c, KC_PIVOT);
     for (;;) {
-        WTT_HIP(hipMemcpyAsync(c->h_pinned_int, piv, pivot_info_offset(rmax) + 2 * sizeof(double),
+        WTT_HIP(hipMemcpyAsync(c->h_pinned_int, piv, pivot_info_offset(rmax) + 3 * sizeof(double),
                                hipMemcpyDeviceToHost, c->s));
         host_wait(c);
         const double state = pinned_pivot_info(c, rmax, 0);
         if (state >= 0.0) break;
-        WTT_REQUIRE(state != -2.0, WENOTT_EHIP, "pivot search: the wait for the other workgroups ran out");
+        if (state == -2.0) {
+            WTT_REQUIRE(persistent, WENOTT_EHIP, "pivot search: the stepped form reported a persistent failure");
+            persistent = false;
+            c->info.pivot_fallbacks += 1;
+            reeval();
+            ev_record(c, KC_PIVOT);
+            next = prrlu(c->s, m, n, B, rmax, rel_tol2, piv, piv + rmax, L, info, ws, 0,
+                         pivot_guess(c, hist_slot, n, rmax) + 1, false);
+            ev_record(c, KC_PIVOT);
+            continue;
+        }
         WTT_REQUIRE(next <= rmax + 1, WENOTT_EHIP, "pivot search did not stop");
         ev_record(c, KC_PIVOT);
-        next = prrlu(c->s, m, n, B, rmax, rel_tol2, piv, piv + rmax, L, info, ws, next, next + std::max(8, next / 2));
+        next = prrlu(c->s, m, n, B, rmax, rel_tol2, piv, piv + rmax, L, info, ws, next, next + std::max(8, next / 2),
+                     persistent);
         ev_record(c, KC_PIVOT);
     }
     PivotResult r;
     r.rank = (int)pinned_pivot_info(c, rmax, 0);
+    // stopped at the rank limit with the residual above the tolerance
+    r.capped = r.rank >= rmax && rmax < std::min(m, n) && pinned_pivot_info(c, rmax, 1) > pinned_pivot_info(c, rmax, 2);
+    if (r.capped) c->info.rank_capped += 1;
     if (hist_slot >= 0) c->piv_hist[hist_slot] = r.rank;
     r.cols.assign(c->h_pinned_int + rmax, c->h_pinned_int + rmax + r.rank);
     c->info.pivots_total += r.rank;
@@ -796,7 +816,9 @@ FluxTT cross_generic(wenott_ctx *c, const CrossTarget &t, double eps, CrossStat 
     }
     std::vector<ISet> usedR(d);
     std::vector<std::vector<int>> usedC(d);
+    bool capped = false;  // a pivot search of the last left-to-right sweep stopped at its rank limit
     for (; sweep < c->o.max_sweeps; ++sweep) {
+        capped = false;
         F.release(c->s);
         Lset[0].len = 0;
         Lset[0].count = 1;
@@ -814,7 +836,9 @@ FluxTT cross_generic(wenott_ctx *c, const CrossTarget &t, double eps, CrossStat 
             t.eval(k, Lset[k], Rk, true, B);
             if (k < d - 1) {
                 double *L = nullptr;
-                PivotResult pr = pivots(c, B, (int)rows, (int)cols, rel2, &L, hist_index(t.warm_slot, 0, k));
+                PivotResult pr = pivots(c, B, (int)rows, (int)cols, rel2, &L, hist_index(t.warm_slot, 0, k),
+                                        [&] { t.eval(k, Lset[k], Rk, true, B); });
+                capped = capped || pr.capped;
                 if (t.learn) {
                     usedR[k] = Rk;
                     usedC[k] = pr.cols;
@@ -866,7 +890,8 @@ FluxTT cross_generic(wenott_ctx *c, const CrossTarget &t, double eps, CrossStat 
             double *B = c->sc.get<double>(S_BLOCK, (size_t)(rows * cols));
             t.eval(k, Lk, Rk, false, B);
             double *L = nullptr;
-            PivotResult pr = pivots(c, B, (int)rows, (int)cols, rel2, &L, hist_index(t.warm_slot, 1, k));
+            PivotResult pr = pivots(c, B, (int)rows, (int)cols, rel2, &L, hist_index(t.warm_slot, 1, k),
+                                    [&] { t.eval(k, Lk, Rk, false, B); });
             ISet nr;
             nr.len = d - k;
             nr.count = pr.rank;
@@ -886,8 +911,11 @@ FluxTT cross_generic(wenott_ctx *c, const CrossTarget &t, double eps, CrossStat 
     st.residual = resid;
     if (proposed && sweep == 1 && resid <= eps) c->info.proposals_accepted += 1;
     if (t.learn) learn_update(c, d, nc, M, F, usedR, usedC, feats, have_feats, sweep, resid);
-    if (!(resid <= 1e3 * eps) && !(resid <= 1e-12))
-        throw StatusError(WENOTT_ENOCONV, "cross did not converge");
+    if (!(resid <= c->o.conv_slack * eps) && !(resid <= 1e-12)) {
+        F.release(c->s);
+        throw StatusError(WENOTT_ENOCONV, capped ? "cross did not converge: a pivot search stopped at the rank limit"
+                                                 : "cross did not converge within max_sweeps sweeps");
+    }
     return F;
 }
 
@@ -1443,7 +1471,10 @@ struct BState {
 // One batched pivot phase over the given states: prrLU of each state's block. The register
 // jobs finish in the first launch; the multi-workgroup jobs run in chunks of pivot steps, each
 // chunk followed by one synchronisation, until every job has stopped.
-void batch_pivots(std::vector<BState *> &act, int dir, int k) {
+// A job whose single-launch (persistent) form gave up waiting for workgroups that were not all
+// resident left its block partly eliminated: reeval(b) writes the block again and the job is redone
+// in the one-launch-per-step layout.
+void batch_pivots(std::vector<BState *> &act, int dir, int k, const std::function<void(BState *)> &reeval) {
     if (act.empty()) return;
     wenott_ctx *c0 = act[0]->c;
     std::vector<PrrluJob> jobs;
@@ -1462,7 +1493,7 @@ void batch_pivots(std::vector<BState *> &act, int dir, int k) {
         jobs.push_back(j);
     }
     int t_begin = 0;
-    std::vector<size_t> open(act.size());
+    std::vector<size_t> open(act.size()), redo;
     for (size_t z = 0; z < act.size(); ++z) open[z] = z;
     for (;;) {
         std::vector<PrrluJob> hj;
@@ -1473,7 +1504,7 @@ void batch_pivots(std::vector<BState *> &act, int dir, int k) {
         ev_record(c0, KC_PIVOT);
         for (size_t z : open) {
             BState *b = act[z];
-            WTT_HIP(hipMemcpyAsync(b->c->h_pinned_int, b->piv, pivot_info_offset(b->rmax) + 2 * sizeof(double),
+            WTT_HIP(hipMemcpyAsync(b->c->h_pinned_int, b->piv, pivot_info_offset(b->rmax) + 3 * sizeof(double),
                                    hipMemcpyDeviceToHost, b->c->s));
         }
         host_wait(c0);
@@ -1481,11 +1512,28 @@ void batch_pivots(std::vector<BState *> &act, int dir, int k) {
         int rmax_open = 0;
         for (size_t z : open) {
             const double state = pinned_pivot_info(act[z]->c, act[z]->rmax, 0);
-            WTT_REQUIRE(state != -2.0, WENOTT_EHIP, "pivot search: the wait for the other workgroups ran out");
-            if (state < 0.0) {
+            if (state == -2.0) {
+                WTT_REQUIRE(jobs[z].mode == 2, WENOTT_EHIP, "pivot search: the stepped form reported a persistent failure");
+                redo.push_back(z);
+            } else if (state < 0.0) {
                 still.push_back(z);
                 rmax_open = std::max(rmax_open, act[z]->rmax);
             }
+        }
+        if (still.empty() && !redo.empty()) {
+            // the jobs whose persistent launch gave up: one launch per step, from a freshly evaluated block
+            for (size_t z : redo) {
+                reeval(act[z]);
+                jobs[z].mode = 1;
+                act[z]->c->info.pivot_fallbacks += 1;
+            }
+            open = std::move(redo);
+            redo.clear();
+            t_begin = 0;
+            t_end = 0;
+            for (size_t z : open)
+                t_end = std::max(t_end, pivot_guess(act[z]->c, hist_index(kMaxDim, dir, k), act[z]->n, act[z]->rmax) + 1);
+            continue;
         }
         if (still.empty()) break;
         t_begin = t_end + 1;
@@ -1556,7 +1604,11 @@ void batch_cross(std::vector<BState> &bs, const double *aw, const double *bw, in
                 }
             }
             if (k == d - 1) break;
-            batch_pivots(act, 0, k);
+            batch_pivots(act, 0, k, [&](BState *b) {
+                const size_t z = b - bs.data();
+                const StageWeights w{aw[st], bw[st], bw[st] * b->dt};
+                eval_stage_block(b->c, b->X, &b->c->U, w, b->alpha, k, b->Lset[k], Rk[z], true, b->B);
+            });
             for (BState *b : act) {
                 const int r = (int)pinned_pivot_info(b->c, b->rmax, 0);
                 std::vector<int> rows(b->c->h_pinned_int, b->c->h_pinned_int + r);
@@ -1601,7 +1653,11 @@ void batch_cross(std::vector<BState> &bs, const double *aw, const double *bw, in
                 const StageWeights w{aw[st], bw[st], bw[st] * b->dt};
                 eval_stage_block(b->c, b->X, &b->c->U, w, b->alpha, k, Lk[z], R, false, b->B);
             }
-            batch_pivots(refresh, 1, k);
+            batch_pivots(refresh, 1, k, [&](BState *b) {
+                const size_t z = b - bs.data();
+                const StageWeights w{aw[st], bw[st], bw[st] * b->dt};
+                eval_stage_block(b->c, b->X, &b->c->U, w, b->alpha, k, Lk[z], b->Rset[k], false, b->B);
+            });
             for (BState *b : refresh) {
                 const ISet &R = b->Rset[k];
                 const int r = (int)pinned_pivot_info(b->c, b->rmax, 0), q = R.count;
@@ -1627,8 +1683,8 @@ void batch_cross(std::vector<BState> &bs, const double *aw, const double *bw, in
         int fr = 1;
         for (int k = 1; k < d; ++k) fr = std::max(fr, b.F.R[k]);
         b.c->info.flux_rank[st][0] = fr;
-        if (!(b.resid <= 1e3 * b.ceps) && !(b.resid <= 1e-12))
-            throw StatusError(WENOTT_ENOCONV, "cross did not converge");
+        if (!(b.resid <= b.c->o.conv_slack * b.ceps) && !(b.resid <= 1e-12))
+            throw StatusError(WENOTT_ENOCONV, "cross did not converge within max_sweeps sweeps");
     }
 }
 
@@ -1846,6 +1902,8 @@ void reset_call_info(wenott_ctx *c) {
     c->info.proposals_tried = 0;
     c->info.proposals_accepted = 0;
     c->info.pivots_total = 0;
+    c->info.rank_capped = 0;
+    c->info.pivot_fallbacks = 0;
     c->info.fiber_points = 0;
     c->info.fiber_launches = 0;
     c->info.fiber_ms = 0.0;
@@ -1924,6 +1982,7 @@ void wenott_default_opts(wenott_opts *o) {
     o->rounds_per_stage = 1;
     o->graph_mode = 0;
     o->scheme = 0;
+    o->conv_slack = 1.0;
 }
 
 const char *wenott_strerror(wenott_status s) {
@@ -1965,6 +2024,11 @@ wenott_status wenott_init(wenott_ctx **out, const wenott_tt *state, const wenott
         WTT_REQUIRE(c->o.eps_mode == 0 || c->o.eps_mode == 1, WENOTT_EINVAL, "eps_mode must be 0 or 1");
         WTT_REQUIRE(c->o.scheme == 0 || c->o.scheme == 1, WENOTT_EINVAL, "scheme must be 0 or 1");
         WTT_REQUIRE(c->o.precision == 0 || c->o.scheme == 0, WENOTT_EINVAL, "the FP32 path runs in scheme 0");
+        WTT_REQUIRE(c->o.rounds_per_stage == 1 || c->o.rounds_per_stage == 2, WENOTT_EINVAL,
+                    "rounds_per_stage must be 1 or 2");
+        WTT_REQUIRE(c->o.conv_slack >= 1.0, WENOTT_EINVAL, "conv_slack must be >= 1");
+        WTT_REQUIRE(c->o.probe_points >= 16 && c->o.probe_points <= 65536, WENOTT_EINVAL,
+                    "probe_points must be in [16, 65536]");
         for (int k = 0; k < d; ++k) {
             WTT_REQUIRE(grid->n[k] >= 3 && grid->n[k] <= (1 << 20), WENOTT_EINVAL, "grid size out of range");
             WTT_REQUIRE(grid->hi[k] > grid->lo[k], WENOTT_EINVAL, "empty box");
@@ -2150,6 +2214,10 @@ wenott_status wenott_rk3_step(wenott_ctx *c, double dt, double eps_in, const dou
                     WTT_REQUIRE(a > 0.0, WENOTT_EINVAL, "alpha must be positive");
                     c->info.alpha[st] = a;
                 }
+                // rounds_per_stage = 2 (eq. tt-ssprk3 literally): the forward Euler value
+                // Z = X + dt L(X) is rounded, then a_s U^n + b_s Z is formed and rounded again
+                const bool two = c->o.rounds_per_stage == 2 && aw[st] != 0.0;
+                const double wa = two ? 0.0 : aw[st], wb = two ? 1.0 : bw[st];
                 TT S;
                 bool rounded = false;
                 if (c->o.scheme == 0) {
@@ -2161,7 +2229,7 @@ wenott_status wenott_rk3_step(wenott_ctx *c, double dt, double eps_in, const dou
                         S = cross_to_tt(c, F, -1);
                         c->info.sum_rank[st] = S.maxrank();
                         rounded = true;
-                        round_tt(c, S, eps, true, norms, st == 2);
+                        round_tt(c, S, eps, true, norms, st == 2 && !two);
                     };
                     const std::function<void()> drop = [&]() {
                         S.release(c->s);
@@ -2169,8 +2237,7 @@ wenott_status wenott_rk3_step(wenott_ctx *c, double dt, double eps_in, const dou
                     };
                     FluxTT F;
                     try {
-                        F = cross_stage(c, X, &c->U, StageWeights{aw[st], bw[st], bw[st] * dt}, a, eps, cs, &spec,
-                                        &drop);
+                        F = cross_stage(c, X, &c->U, StageWeights{wa, wb, wb * dt}, a, eps, cs, &spec, &drop);
                     } catch (...) {
                         if (rounded) S.release(c->s);
                         throw;
@@ -2183,15 +2250,21 @@ wenott_status wenott_rk3_step(wenott_ctx *c, double dt, double eps_in, const dou
                 } else {
                     std::vector<TT> terms = rhs_terms(c, X, a, eps, st);
                     std::vector<std::pair<double, const TT *>> w;
-                    if (aw[st] != 0.0) w.push_back({aw[st], &c->U});
-                    w.push_back({bw[st], &X});
-                    for (auto &t : terms) w.push_back({bw[st] * dt, &t});
+                    if (wa != 0.0) w.push_back({wa, &c->U});
+                    w.push_back({wb, &X});
+                    for (auto &t : terms) w.push_back({wb * dt, &t});
                     S = tt_sum(c, w);
                     for (auto &t : terms) t.release(c->s);
                 }
                 if (!rounded) {
                     c->info.sum_rank[st] = S.maxrank();
                     // synchronises (the deferred alpha has arrived); the norms are needed after the last stage
+                    round_tt(c, S, eps, true, norms, st == 2 && !two);
+                }
+                if (two) {  // round(a_s U^n + b_s round(X + dt L(X)))
+                    TT Y = tt_sum(c, {{aw[st], &c->U}, {bw[st], &S}});
+                    S.release(c->s);
+                    S = Y;
                     round_tt(c, S, eps, true, norms, st == 2);
                 }
                 if (x_owned) X.release(c->s);
@@ -2231,8 +2304,10 @@ wenott_status wenott_batch_rk3_step(wenott_ctx **ctxs, int32_t n, const double *
             wenott_ctx *c = ctxs[i];
             WTT_REQUIRE(c->d == d && c->s == ctxs[0]->s, WENOTT_EINVAL,
                         "batched states need the same dimension and the same stream");
-            WTT_REQUIRE(c->o.scheme == 0 && c->o.use_proposal == 0 && !c->logging, WENOTT_EINVAL,
-                        "batched stepping runs the stage-cross scheme without the proposal or cross logging");
+            WTT_REQUIRE(c->o.scheme == 0 && c->o.use_proposal == 0 && !c->logging && c->o.rounds_per_stage == 1,
+                        WENOTT_EINVAL,
+                        "batched stepping runs the stage-cross scheme with one rounding per stage, without the "
+                        "proposal or cross logging");
             for (int j = 0; j < i; ++j) WTT_REQUIRE(ctxs[j] != c, WENOTT_EINVAL, "a context appears twice");
         }
         double t0 = seconds_now();
@@ -2366,6 +2441,11 @@ wenott_status wenott_max_wavespeed(wenott_ctx *c, double *alpha) {
 wenott_status wenott_current_eps(wenott_ctx *c, double *eps) {
     if (!c || !eps) return WENOTT_EINVAL;
     return run_guarded(c, [&] { *eps = current_eps(c); });
+}
+
+wenott_status wenott_set_pivot_wait_limit(int32_t polls) {
+    set_coop_spin(polls);
+    return WENOTT_OK;
 }
 
 wenott_status wenott_set_profiling(wenott_ctx *c, int32_t on) {

@@ -910,6 +910,7 @@ __device__ __forceinline__ void prrlu_mw_step_body(const PrrluJob &J, int t) {
                     }
                     J.info[0] = (double)rank;
                     J.info[1] = gs;
+                    J.info[2] = tol2;
                     w.ctl->stop_launch = t;
                 } else {
                     J.rowpiv[tp] = (int)(gi / n);
@@ -1040,8 +1041,9 @@ __device__ __forceinline__ void prrlu_mw_step_body(const PrrluJob &J, int t) {
 // way, and only the pivot column of the stripe passes through LDS. A slot of one parity is
 // rewritten every second step, so a word left from an earlier step differs by its tag for the
 // next three rewrites (the slots start with the tag of step -2); the index is range-checked
-// before use all the same. The polls are bounded: after kCoopSpin polls a workgroup marks the
-// job failed (info[0] = -2) and leaves, and the others leave at their next poll.
+// before use all the same. The polls are bounded: after J.spin polls (kCoopSpin unless the host
+// set another bound) a workgroup marks the job failed (info[0] = -2) and leaves, and the others
+// leave at their next poll.
 constexpr int kCoopMaxBlk = 64;  // one slot per lane of a wave
 constexpr int kCoopSpin = 1 << 22;
 constexpr long long kNoRow = 0x7fffffffffffffffLL;
@@ -1065,8 +1067,9 @@ __device__ __forceinline__ long long coop_get(const long long *p) {
 // Polls NW words until each carries tag tg (the loads of one round are issued together); false when the job has failed or the polls
 // ran out (then the job is marked failed).
 template <int NW>
-__device__ __forceinline__ bool coop_poll(const long long *const (&p)[NW], int tg, PrrluCtl *ctl, long long (&out)[NW]) {
-    for (int sp = 0; sp < kCoopSpin; ++sp) {
+__device__ __forceinline__ bool coop_poll(const long long *const (&p)[NW], int tg, PrrluCtl *ctl, int spin,
+                                          long long (&out)[NW]) {
+    for (int sp = 0; sp < spin; ++sp) {
         bool all = true;
 #pragma unroll
         for (int q = 0; q < NW; ++q) {
@@ -1157,7 +1160,7 @@ __device__ __forceinline__ void prrlu_coop_body(const PrrluJob &J) {
         long long got[3] = {0, 0, 0};
         if (lane < G) {
             const long long *const src[3] = {pmx + lane, psm + lane, pix + lane};
-            ok = coop_poll<3>(src, tg, w.ctl, got);
+            ok = coop_poll<3>(src, tg, w.ctl, J.spin, got);
         }
         bool wave_ok = __ballot(!ok) == 0;
         if (lane < G && wave_ok) {
@@ -1186,6 +1189,7 @@ __device__ __forceinline__ void prrlu_coop_body(const PrrluJob &J) {
                     }
                     J.info[0] = (double)rank;
                     J.info[1] = gs;
+                    J.info[2] = tol2;
                 } else {
                     J.rowpiv[t] = pi;
                     J.colpiv[t] = pj;
@@ -1200,7 +1204,7 @@ __device__ __forceinline__ void prrlu_coop_body(const PrrluJob &J) {
 #pragma unroll
                 for (int j = 0; j < kMwTW; ++j) src[1 + j] = (active && c0 + j < n) ? urow + c0 + j : urow + pj;
                 long long v[kMwTW + 1];
-                if (coop_poll<kMwTW + 1>(src, tg, w.ctl, v)) {
+                if (coop_poll<kMwTW + 1>(src, tg, w.ctl, J.spin, v)) {
                     upj = coop_val_d(v[0]);
 #pragma unroll
                     for (int j = 0; j < kMwTW; ++j) uu[j] = (active && c0 + j < n) ? coop_val_d(v[1 + j]) : 0.0;
@@ -1393,6 +1397,7 @@ __device__ __forceinline__ void prrlu_tile_body(int m, int n, const double *__re
         }
         info[0] = (double)rank;
         info[1] = bs;
+        info[2] = tol2;
     }
     if (stop == 2)
         for (int i = tid; i < m; i += NT) L[(long long)i * rmax] = (i == 0) ? 1.0 : 0.0;
@@ -2166,7 +2171,14 @@ int coop_capacity() {
 // when the device cannot hold the grid); 3: stripes of kMwKBig rows per thread, one launch per
 // step, for blocks tall enough to fill the device with them (measured on 20480 x 180: 23 us per
 // step against 25; on 4096 x 180 the longer stripes leave too few workgroups: 17 against 10).
+namespace {
+int g_coop_spin = kCoopSpin;
+}
+
+void set_coop_spin(int polls) { g_coop_spin = polls > 0 ? polls : (polls == 0 ? 0 : kCoopSpin); }
+
 void prrlu_prepare(PrrluJob &j) {
+    j.spin = g_coop_spin;
     j.shape = tile_shape_for(j.m, j.n);
     const int tpr = (j.n + kMwTW - 1) / kMwTW;
     WTT_REQUIRE(tpr <= kMwThreads && j.n <= kMwCand, WENOTT_EINVAL,
@@ -2194,7 +2206,7 @@ size_t prrlu_ws_doubles(int m, int n) {
 }
 
 int prrlu(hipStream_t s, int m, int n, double *A, int rmax, double rel_tol2, int *rowpiv, int *colpiv, double *L,
-          double *info, double *ws, int t_begin, int t_end) {
+          double *info, double *ws, int t_begin, int t_end, bool allow_persistent) {
     PrrluJob j{};
     j.A = A; j.m = m; j.n = n; j.rmax = rmax; j.rel_tol2 = rel_tol2;
     j.rowpiv = rowpiv; j.colpiv = colpiv; j.L = L; j.info = info; j.ws = ws;
@@ -2207,7 +2219,7 @@ int prrlu(hipStream_t s, int m, int n, double *A, int rmax, double rel_tol2, int
         WTT_HIP(hipGetLastError());
         return rmax + 1;
     }
-    if (j.mode == 2 && j.nblk <= coop_capacity()) {  // the whole factorisation in one launch
+    if (j.mode == 2 && allow_persistent && j.nblk <= coop_capacity()) {  // the whole factorisation in one launch
         if (t_begin > 0) return rmax + 2;
         k_prrlu_mw_init<<<1, kMwThreads, 0, s>>>(j);
         k_prrlu_coop<<<j.nblk, kMwThreads, 0, s>>>(j);

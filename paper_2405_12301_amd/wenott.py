@@ -24,7 +24,7 @@ EXPORTED = ["wenott_default_opts", "wenott_init", "wenott_rhs", "wenott_rk3_step
             "wenott_dense_rk3_step", "wenott_dense_destroy", "wenott_mlp_nparams", "wenott_mlp_workspace",
             "wenott_mlp_init_params", "wenott_mlp_forward", "wenott_mlp_loss_grad", "wenott_mlp_adam_step",
             "wenott_set_proposal", "wenott_set_cross_logging", "wenott_get_cross_log", "wenott_batch_rk3_step",
-            "wenott_gemm_autotune", "wenott_gemm_autotune_table"]
+            "wenott_gemm_autotune", "wenott_gemm_autotune_table", "wenott_set_pivot_wait_limit"]
 
 MLP_IN, MLP_HID, MLP_OUT, MLP_RANK_CLASSES, MLP_BINS = 96, 128, 81, 17, 64
 
@@ -44,7 +44,8 @@ class wenott_opts(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("max_sweeps", ctypes.c_int32), ("kick_rank", ctypes.c_int32),
                 ("rank_cap", ctypes.c_int32), ("probe_points", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("alpha_mode", ctypes.c_int32), ("use_proposal", ctypes.c_int32), ("alpha_given", ctypes.c_double),
-                ("rounds_per_stage", ctypes.c_int32), ("graph_mode", ctypes.c_int32), ("scheme", ctypes.c_int32)]
+                ("rounds_per_stage", ctypes.c_int32), ("graph_mode", ctypes.c_int32), ("scheme", ctypes.c_int32),
+                ("conv_slack", ctypes.c_double)]
 
 
 class wenott_info(ctypes.Structure):
@@ -57,7 +58,8 @@ class wenott_info(ctypes.Structure):
                 ("class_ms", ctypes.c_double * 4), ("class_launches", ctypes.c_int64 * 4),
                 ("class_flops", ctypes.c_double * 4), ("class_bytes", ctypes.c_double * 4),
                 ("proposals_tried", ctypes.c_int64), ("proposals_accepted", ctypes.c_int64),
-                ("pivots_total", ctypes.c_int64)]
+                ("pivots_total", ctypes.c_int64), ("rank_capped", ctypes.c_int64),
+                ("pivot_fallbacks", ctypes.c_int64)]
 
 
 _lib = None
@@ -92,6 +94,7 @@ def load(path: str = LIB_PATH):
     lib.wenott_max_wavespeed.argtypes = [vp, P(ctypes.c_double)]
     lib.wenott_current_eps.argtypes = [vp, P(ctypes.c_double)]
     lib.wenott_set_profiling.argtypes = [vp, ctypes.c_int32]
+    lib.wenott_set_pivot_wait_limit.argtypes = [ctypes.c_int32]
     lib.wenott_last_error.argtypes = [vp]
     lib.wenott_last_error.restype = ctypes.c_char_p
     lib.wenott_destroy.argtypes = [vp]
@@ -118,7 +121,7 @@ def load(path: str = LIB_PATH):
     for name in ("wenott_init", "wenott_rhs", "wenott_rk3_step", "wenott_batch_rk3_step", "wenott_round",
                  "wenott_gemm_autotune", "wenott_gemm_autotune_table", "wenott_to_dense",
                  "wenott_get_state", "wenott_get_info", "wenott_max_wavespeed", "wenott_current_eps",
-                 "wenott_set_profiling", "wenott_dense_init", "wenott_dense_max_wavespeed", "wenott_dense_rhs",
+                 "wenott_set_profiling", "wenott_set_pivot_wait_limit", "wenott_dense_init", "wenott_dense_max_wavespeed", "wenott_dense_rhs",
                  "wenott_dense_rk3_step", "wenott_mlp_init_params", "wenott_mlp_forward", "wenott_mlp_loss_grad",
                  "wenott_mlp_adam_step", "wenott_set_proposal", "wenott_set_cross_logging", "wenott_get_cross_log"):
         getattr(lib, name).restype = ctypes.c_int
@@ -266,6 +269,10 @@ def wenott_current_eps(ctx) -> float:
 
 def wenott_set_profiling(ctx, on: bool):
     _check(load().wenott_set_profiling(ctx, 1 if on else 0), ctx)
+
+
+def wenott_set_pivot_wait_limit(polls: int):
+    _check(load().wenott_set_pivot_wait_limit(int(polls)), None)
 
 
 def _grid(n, lo, hi):

@@ -278,28 +278,134 @@ def sod_1d_like(ndim: int, n: int, axis: int = 0) -> Flow:
                 cores, t_end=0.2, cfl=0.5, eps_mode=1, eps0=1e-6)
 
 
-def config5_tilted_sod_3d(n: int = 512, seed: int = 0, eps: float = 1e-6, rank_cap: int = 64) -> Flow:
-    """Sod states across the plane n.(x - 1/2) = 0 on [0,1]^3, n = e_x tilted by theta ~ U[0,5] deg
-    about a random axis perpendicular to e_x; the TT is a TT-SVD of the sampled field."""
+SOD_LEFT = (1.0, 0.0, 1.0)     # (rho, u, p) on the side n.(x - 1/2) < 0
+SOD_RIGHT = (0.125, 0.0, 0.1)  # (rho, u, p) on the other side
+
+
+def sod_exact_rho(s, t, gamma=1.4, left=SOD_LEFT, right=SOD_RIGHT):
+    """Density of the exact solution of a 1D Riemann problem at signed distance s from the
+    initial discontinuity and time t > 0 (left state at s < 0). Written from the wave curves of
+    the gamma-law gas: the star pressure solves phi_L(p) + phi_R(p) + u_R - u_L = 0, where
+    phi_K(p) is the velocity jump across a shock (p > p_K, Rankine-Hugoniot) or a rarefaction
+    (p <= p_K, isentrope and Riemann invariant) into state K; Newton iteration from the
+    arithmetic mean of the two pressures. Used for the L1 error of the tilted Sod workload."""
+    g = gamma
+    s = np.asarray(s, dtype=np.float64)
+
+    def phi(p, rho_k, p_k):
+        c_k = math.sqrt(g * p_k / rho_k)
+        if p > p_k:
+            a = 2.0 / ((g + 1.0) * rho_k)
+            b = p_k * (g - 1.0) / (g + 1.0)
+            q = math.sqrt(a / (b + p))
+            return (p - p_k) * q, q * (1.0 - (p - p_k) / (2.0 * (b + p)))
+        ratio = p / p_k
+        z = (g - 1.0) / (2.0 * g)
+        return 2.0 * c_k / (g - 1.0) * (ratio ** z - 1.0), ratio ** (-(g + 1.0) / (2.0 * g)) / (rho_k * c_k)
+
+    (rl, ul, pl), (rr, ur, pr) = left, right
+    p = 0.5 * (pl + pr)
+    for _ in range(100):
+        fl, dl = phi(p, rl, pl)
+        fr, dr = phi(p, rr, pr)
+        step = (fl + fr + ur - ul) / (dl + dr)
+        p_new = max(p - step, 1e-14 * p)
+        done = abs(p_new - p) < 1e-15 * p
+        p = p_new
+        if done:
+            break
+    fl, _ = phi(p, rl, pl)
+    fr, _ = phi(p, rr, pr)
+    u_star = 0.5 * (ul + ur + fr - fl)
+    xi = s / t
+    out = np.empty_like(xi)
+    cl, cr = math.sqrt(g * pl / rl), math.sqrt(g * pr / rr)
+    gm = (g - 1.0) / (g + 1.0)
+    # left of the contact
+    lmask = xi <= u_star
+    if p > pl:  # left-facing shock
+        rho_sl = rl * (p / pl + gm) / (gm * p / pl + 1.0)
+        sh = ul - cl * math.sqrt((g + 1.0) / (2.0 * g) * p / pl + (g - 1.0) / (2.0 * g))
+        out[lmask] = np.where(xi[lmask] < sh, rl, rho_sl)
+    else:  # left rarefaction fan between its head and tail speeds
+        rho_sl = rl * (p / pl) ** (1.0 / g)
+        c_sl = cl * (p / pl) ** ((g - 1.0) / (2.0 * g))
+        head, tail = ul - cl, u_star - c_sl
+        x = xi[lmask]
+        fan = rl * (2.0 / (g + 1.0) + (g - 1.0) / ((g + 1.0) * cl) * (ul - x)) ** (2.0 / (g - 1.0))
+        out[lmask] = np.where(x < head, rl, np.where(x > tail, rho_sl, fan))
+    rmask = ~lmask
+    if p > pr:  # right-facing shock
+        rho_sr = rr * (p / pr + gm) / (gm * p / pr + 1.0)
+        sh = ur + cr * math.sqrt((g + 1.0) / (2.0 * g) * p / pr + (g - 1.0) / (2.0 * g))
+        out[rmask] = np.where(xi[rmask] > sh, rr, rho_sr)
+    else:  # right rarefaction fan
+        rho_sr = rr * (p / pr) ** (1.0 / g)
+        c_sr = cr * (p / pr) ** ((g - 1.0) / (2.0 * g))
+        head, tail = ur + cr, u_star + c_sr
+        x = xi[rmask]
+        fan = rr * (2.0 / (g + 1.0) - (g - 1.0) / ((g + 1.0) * cr) * (ur - x)) ** (2.0 / (g - 1.0))
+        out[rmask] = np.where(x > head, rr, np.where(x < tail, rho_sr, fan))
+    return out
+
+
+def _exact_svd_tt2(field2d, rel=1e-13):
+    """Exact low-rank factors of a sampled 2D field: U S V^T with the singular values above
+    rel * sigma_max kept (the field of a tilted step has exact rank = its number of distinct
+    rows, the rest is rounding)."""
+    u, s, vt = np.linalg.svd(field2d, full_matrices=False)
+    r = max(1, int(np.sum(s > rel * s[0])))
+    return u[:, :r], s[:r], vt[:r]
+
+
+def config5_tilted_sod_3d(n: int = 512, seed: int = 0) -> Flow:
+    """Sod states (1, 0, 0, 0, 1) | (0.125, 0, 0, 0, 0.1) across the plane n.(x - 1/2) = 0 on
+    [0,1]^3, transmissive. n is e_x turned by theta ~ U[0, 5] degrees about e_z or e_y (seeded,
+    either sign), so the data depend on two coordinates and the TT is exact: for a turn about e_z
+    the state is f(x, y) (cores U | S V^T | ones), about e_y it is f(x, z) (cores U | identity |
+    S V^T), with ranks = the number of distinct step rows, about N tan(theta) + 1.
+    exact_rho(t) gives the exact density (the 1D Riemann solution along n)."""
     g = 1.4
     rng = np.random.default_rng(seed)
     theta = math.radians(rng.uniform(0.0, 5.0))
-    phi = rng.uniform(0.0, 2.0 * math.pi)
-    axis = np.array([0.0, math.cos(phi), math.sin(phi)])
-    ex = np.array([1.0, 0.0, 0.0])
-    nvec = ex * math.cos(theta) + np.cross(axis, ex) * math.sin(theta)
-    xs = [(np.arange(n) + 0.5) / n - 0.5 for _ in range(3)]
-    s = nvec[0] * xs[0][:, None, None] + nvec[1] * xs[1][None, :, None] + nvec[2] * xs[2][None, None, :]
-    left = s < 0.0
-    rho = np.where(left, 1.0, 0.125)
-    ene = np.where(left, 1.0, 0.1) / (g - 1.0)
-    del s
-    cores = [tt_svd_input(rho, eps, rank_cap)]
+    about_z = bool(rng.integers(0, 2) == 0)
+    sign = 1.0 if rng.integers(0, 2) == 0 else -1.0
+    nvec = np.array([math.cos(theta), 0.0, 0.0])
+    nvec[1 if about_z else 2] = sign * math.sin(theta)
+    x = (np.arange(n) + 0.5) / n - 0.5
+    other = 1 if about_z else 2
+    s2 = nvec[0] * x[:, None] + nvec[other] * x[None, :]  # signed distance on the (x, other) plane
+    left = s2 < 0.0
+    rho2 = np.where(left, SOD_LEFT[0], SOD_RIGHT[0])
+    ene2 = np.where(left, SOD_LEFT[2], SOD_RIGHT[2]) / (g - 1.0)
+
+    def tt_of(field2d):
+        u, s, vt = _exact_svd_tt2(field2d)
+        r = u.shape[1]
+        g0 = u[None, :, :]
+        right = (s[:, None] * vt)
+        if about_z:
+            return [g0, right[:, :, None], np.ones((1, n, 1))]
+        mid = np.zeros((r, n, r))
+        mid[np.arange(r), :, np.arange(r)] = 1.0
+        return [g0, mid, right[:, :, None]]
+
     zeros = [np.zeros((1, n, 1)) for _ in range(3)]
-    cores += [[z.copy() for z in zeros] for _ in range(3)]
-    cores.append(tt_svd_input(ene, eps, rank_cap))
+    cores = [tt_of(rho2)] + [[z.copy() for z in zeros] for _ in range(3)] + [tt_of(ene2)]
+    xs = (np.arange(n) + 0.5) / n - 0.5
+
+    def exact_rho(t, box=None):
+        """Exact density on the grid (or on the cells whose centres lie in box = (lo, hi))."""
+        idx = np.arange(n) if box is None else np.nonzero((xs + 0.5 >= box[0]) & (xs + 0.5 <= box[1]))[0]
+        xx = xs[idx]
+        s3 = (nvec[0] * xx[:, None, None] + nvec[1] * xx[None, :, None] + nvec[2] * xx[None, None, :])
+        return sod_exact_rho(s3, t, g)
+
+    axis = "z" if about_z else "y"
     return Flow("tilted_sod_3d", 3, (n,) * 3, (0.0,) * 3, (1.0,) * 3, (TRANSMISSIVE,) * 3, g, cores,
-                t_end=0.1, cfl=0.5, eps_mode=1, eps0=1e-6, note=f"seed {seed}, theta {math.degrees(theta):.3f} deg")
+                t_end=0.1, cfl=0.5, eps_mode=1, eps0=1e-6,
+                note=f"seed {seed}, theta {math.degrees(theta):.3f} deg about {'+' if sign > 0 else '-'}e_{axis}",
+                exact_rho=exact_rho)
 
 
 def random_positive_tt(n, rank: int, seed: int, amp: float = 0.2, bc=None, rough: bool = False) -> Flow:
