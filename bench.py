@@ -158,7 +158,9 @@ def blast_batch(args):
     t_gen = time.perf_counter()
     flows = [workloads.config4_blast_3d(seed=args.seed + i) for i in range(args.batch)]
     print(f"# generated {len(flows)} blast states in {time.perf_counter() - t_gen:.1f} s", file=sys.stderr, flush=True)
-    solvers = [W.Solver(f, W.default_opts(eps_mode=1, eps0=f.eps0)) for f in flows]
+    # their crosses stop at the cross-rank limit of 128 with sampled residuals above eps: an
+    # explicit slack
+    solvers = [W.Solver(f, W.default_opts(eps_mode=1, eps0=f.eps0, conv_slack=100.0)) for f in flows]
     for s in solvers:
         W.wenott_set_profiling(s.ctx, True)
     cells = sum(int(f.n[0]) * int(f.n[1]) * int(f.n[2]) for f in flows)

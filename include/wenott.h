@@ -83,7 +83,12 @@ typedef struct {
     int32_t rank_cap;   /* maximum rank of any bond, cross and rounding [256] */
     int32_t probe_points; /* random points of the sampled cross residual [4096] */
     uint64_t seed;      /* seed of the library's own counter-based generator [12345] */
-    int32_t alpha_mode; /* 0 exact max(|u|+a) over the grid, 2 use alpha_given [0] */
+    int32_t alpha_mode; /* the Lax-Friedrichs alpha of every stage (eq. lax-friedrichs; for the Euler
+                           system the maximum of |u| + a, Sec. 4.2): 0 exact maximum over every cell;
+                           1 estimated by a search along grid lines that never visits all N^d cells
+                           (the role of tt_max_abs in eq. cfl-other), a lower bound of the exact
+                           maximum that reaches it whenever a visited line crosses the maximising
+                           cell; 2 alpha_given [1] */
     int32_t use_proposal; /* 1: seed stage crosses from the learned proposal (wenott_set_proposal) [0] */
     double alpha_given; /* the Lax-Friedrichs alpha when alpha_mode = 2 */
     int32_t rounds_per_stage; /* 1: one rounding per SSP-RK3 stage, after the whole combination
@@ -226,7 +231,9 @@ wenott_status wenott_get_info(wenott_ctx *ctx, wenott_info *info);
 
 /* max over the grid of |u| + a for the current state (the alpha of eq. lax-friedrichs as
  * defined for the Euler system in Sec. 4.2), for the caller's dt = lambda h / alpha
- * (eq. cfl-other). Synchronises. ENONPHYS if rho <= 0 or p <= 0 anywhere. */
+ * (eq. cfl-other): exact with alpha_mode 0 or 2, the line-search estimate with alpha_mode 1.
+ * The first stage of the next step reuses it. Synchronises. ENONPHYS if rho <= 0 or p <= 0 at
+ * an evaluated cell (every cell in mode 0). */
 wenott_status wenott_max_wavespeed(wenott_ctx *ctx, double *alpha);
 
 /* Current eps_TT of the dynamic rule (eq. eps-tt-formula) or the fixed one. */
@@ -238,6 +245,31 @@ wenott_status wenott_current_eps(wenott_ctx *ctx, double *eps);
  * step, counted in wenott_info.pivot_fallbacks) runs. Every kernel still ends normally. */
 wenott_status wenott_set_pivot_wait_limit(int32_t polls);
 
+/* The pivot selection of the cross on its own (Sec. 3.3: the maximum-volume choice of the
+ * interpolation rows and columns, taken greedily): full-pivot rank-revealing LU of the m x n
+ * row-major device matrix A (not modified; copied to a workspace the call allocates). Each step
+ * takes the entry of largest magnitude of the residual (ties to the lowest linear index), records
+ * its row and column and eliminates it; the search stops when the residual's squared Frobenius
+ * norm is <= rel_tol2 times A's, after rmax pivots (1 <= rmax <= min(m, n)), or at a zero
+ * residual, and always takes one pivot of a nonzero block. Outputs (device): rowpiv[rmax] and
+ * colpiv[rmax] (the first rank entries are set), L (m x rmax row-major: column t is the residual
+ * column of pivot t divided by the pivot, 1 at the pivot row); info (host, 3 doubles) = {rank,
+ * final residual squared norm, stopping threshold}. allow_persistent = 0 forces the one-launch-
+ * per-step layouts (the fallback of the persistent ones); 1 lets the library choose, as the
+ * cross does. Synchronises hip_stream. Errors: EINVAL, ENOMEM, EHIP. */
+wenott_status wenott_pivot_search(const double *A, int32_t m, int32_t n, int32_t rmax, double rel_tol2,
+                                  int32_t allow_persistent, int32_t *rowpiv, int32_t *colpiv, double *L, double *info,
+                                  void *hip_stream);
+
+/* Diagnostic: the layout the pivot search (full-pivot rank-revealing LU, Sec. 3.3 maxvol role)
+ * takes for an m x n cross block on the current device, into out[7] = {mode (0 one workgroup,
+ * registers; 1 and 3 one launch per pivot step; 2 and 4 one persistent launch), tile shape or
+ * rows per thread, rows per workgroup, workgroups, the device's capacity for that persistent
+ * launch (0 when stepped), the capacities of the 24-row-per-thread persistent form and of the
+ * form that streams further rows}.
+ * Errors: EINVAL. */
+wenott_status wenott_pivot_layout(int32_t m, int32_t n, int32_t *out);
+
 /* Record device time of the fiber kernels (reported as fiber_ms by wenott_get_info). */
 wenott_status wenott_set_profiling(wenott_ctx *ctx, int32_t on);
 
@@ -247,6 +279,14 @@ const char *wenott_last_error(wenott_ctx *ctx);
 
 void wenott_destroy(wenott_ctx *ctx);
 const char *wenott_strerror(wenott_status s);
+
+/* Process-level drain and release: waits for the current device, returns the device blocks the
+ * library keeps cached for reuse to the runtime and destroys the GEMM autotuner's events (its
+ * chosen tile shapes are kept). Meant to run before the HIP runtime is torn down (the Python
+ * binding registers it at interpreter exit), so that no library-owned HIP object outlives the
+ * runtime; the library stays usable afterwards. Contexts are not touched: destroy them first.
+ * Errors: EHIP. */
+wenott_status wenott_finalize(void);
 
 /* ------------------------------------------------------------------------------------
  * Learned cross proposal (an addition to the paper's method). A 3-layer MLP

@@ -8,7 +8,6 @@ TEST INFRASTRUCTURE ONLY (part of the oracle).
   (Sec. 3.3 first paragraph), each truncated to the smallest rank whose discarded tail is
   at most delta = eps ||X||_F / sqrt(d-1), so that ||X - X_TT||_F <= eps ||X||_F.
   Its ranks are the reference for what a rounding to the same tolerance may keep.
-* ``unfolding_ranks``: the epsilon-ranks of the plain unfoldings of a full tensor.
 * ``maxvol_dominant``: the maximum-volume condition (Sec. 3.3) checked by brute force.
 """
 from __future__ import annotations
@@ -65,15 +64,6 @@ def tt_ranks(cores):
     return [1] + [int(g.shape[2]) for g in cores[:-1]] + [1]
 
 
-def unfolding_ranks(x: np.ndarray, rtol: float):
-    """Numerical ranks (singular values above rtol * largest) of the unfoldings of x."""
-    ranks = []
-    for k in range(1, x.ndim):
-        s = np.linalg.svd(x.reshape(int(np.prod(x.shape[:k])), -1), compute_uv=False)
-        ranks.append(int(np.sum(s > rtol * s[0])) if s.size and s[0] > 0 else 0)
-    return ranks
-
-
 def maxvol_dominant(a: np.ndarray, rows, tol: float = 1e-12) -> bool:
     """True iff the r rows `rows` of the n x r matrix a form a dominant submatrix:
     every entry of B = a a[rows]^{-1} is at most 1 in modulus (up to tol)."""
@@ -91,3 +81,38 @@ def max_volume_rows(a: np.ndarray):
         if v > best:
             best, arg = v, rows
     return arg, best
+
+
+def full_pivot_lu(a: np.ndarray, rel_tol2: float, rmax: int):
+    """Greedy maximum-volume pivots by complete pivoting (the cross's pivot rule, Sec. 3.3):
+    at each step the residual entry of largest magnitude (the first in row-major order among
+    equals) is the pivot; its row and column are recorded, L's column is the residual column
+    divided by the pivot (1 at the pivot row) and the rank-one term is subtracted. The search
+    stops when the residual's squared Frobenius norm is <= rel_tol2 times the block's, after rmax
+    pivots, or at a zero residual; a nonzero block always gives at least one pivot, an all-zero
+    block gives rank 1 with pivot (0, 0). Returns (rank, rows, cols, L (m x rank), residual^2)."""
+    r = np.array(a, dtype=np.float64, copy=True)
+    m, n = r.shape
+    tol2 = rel_tol2 * float(np.sum(r * r))
+    rows, cols, lcols = [], [], []
+    for t in range(rmax + 1):
+        s2 = float(np.sum(r * r))
+        e = int(np.argmax(np.abs(r)))
+        pmax = abs(r.flat[e])
+        if t == 0 and pmax <= 0.0:
+            l0 = np.zeros(m)
+            l0[0] = 1.0
+            return 1, [0], [0], l0[:, None], 0.0
+        if t > 0 and (t >= rmax or pmax <= 0.0 or s2 <= tol2):
+            return t, rows, cols, np.stack(lcols, axis=1), s2
+        i, j = divmod(e, n)
+        lcol = r[:, j] / r[i, j]
+        lcol[i] = 1.0
+        urow = r[i, :].copy()
+        r -= np.outer(lcol, urow)
+        r[i, :] = 0.0
+        r[:, j] = 0.0
+        rows.append(i)
+        cols.append(j)
+        lcols.append(lcol)
+    raise AssertionError("unreachable")

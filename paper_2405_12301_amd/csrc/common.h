@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <stdexcept>
 #include <string>
@@ -72,6 +73,8 @@ void gemm_f64(hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha
 // gemm_tune_table copies up to max_entries rows of {ta, tb, log2 M, log2 N, log2 K, log2 batch,
 // shape (-1 while tuning)} and returns the count.
 void gemm_tune_enable(int mode);
+// Waits for the timings in flight and destroys the tuner's events (the chosen shapes are kept).
+void gemm_tune_release();
 int gemm_tune_table(int32_t *out, int max_entries);
 
 // C[z] = A[z]^T B[z] (A: K x M, B: K x N) with the long reduction split into chunks summed
@@ -126,6 +129,10 @@ int prrlu(hipStream_t s, int m, int n, double *A, int rmax, double rel_tol2, int
 // default bound; 0: the waits give up at once, to exercise the fallback). Process-wide.
 void set_coop_spin(int polls);
 size_t prrlu_ws_doubles(int m, int n);
+// The layout prrlu takes for an m x n block: {mode, shape (tile id or K), rows per workgroup,
+// workgroups, device capacity of that persistent form (0 if stepped), capacity of the K = 8 and
+// K = 16 persistent forms}.
+void prrlu_layout(int m, int n, bool allow_big, int *out);
 
 // X = R^{-1} for the upper Cholesky factor R of each r x r Gram matrix G (batch); ws holds
 // batch * r * r doubles. Zero (padding) columns keep a unit diagonal.
@@ -145,11 +152,12 @@ struct PrrluJob {
     double *L, *info, *ws;  // ws: prrlu_ws_doubles(m, n) doubles
     // set by prrlu_prepare: 0 single-workgroup register tiles (shape: tile shape id), 1
     // multi-workgroup (rows per workgroup, workgroups) stepped one launch per pivot, 2 the same
-    // layout in one persistent launch (when the workgroups can all be resident)
+    // layout in one persistent launch (when the workgroups can all be resident), 3 stepped with
+    // longer stripes, 4 one persistent launch of long stripes (K rows per thread in shape)
     int mode, shape, rows, nblk;
     int spin;  // poll bound of the persistent form's waits (set by prrlu_prepare)
 };
-void prrlu_prepare(PrrluJob &j);
+void prrlu_prepare(PrrluJob &j, bool allow_big = false);
 struct SvdJob {
     const double *A;  // R factors, as for jacobi_svd
     double *sigma, *V;
@@ -268,6 +276,20 @@ void dense_eval(hipStream_t s, int mode, int d, int ncomp, long long nrows, int 
                 long long lm_stride, const double *G, long long g_stride, double gamma, double *out, double *partial,
                 int nblocks, int *flags);
 void reduce_max_dev(hipStream_t s, const double *partial, int n, double *dst);
+
+// ------------------------------------------------------------------ alpha.hip
+// Estimated max over the grid of |u| + a of a TT state (ndim + 2 components, cores[k] the
+// [c][R_k][N_k][R_{k+1}] core of every component, ranks common): a search along grid lines
+// through kAlphaStartCells seeded cells and the previous best cell (best: device int[d], in/out,
+// best[0] < 0 for none), then kAlphaRounds - 1 rounds along every mode through the kAlphaKeep
+// best cells. Writes the estimate to the device scalar alpha; raises kFlagNonPhys in flags for a
+// non-physical cell on a visited line. Workspace: alpha_search_ints(d, N_1) ints and
+// alpha_search_doubles(d, N_1) doubles.
+constexpr int kAlphaStartCells = 256, kAlphaKeep = 16, kAlphaMiddleLines = 4, kAlphaRounds = 3;
+size_t alpha_search_ints(int d, int n1);
+size_t alpha_search_doubles(int d, int n1);
+void alpha_search(hipStream_t s, int d, const int *n, const double *const *cores, const int *ranks, double gamma,
+                  unsigned long long seed, int *best, int *wsi, double *wsd, double *alpha, int *flags);
 
 // Sampled residual of a flux TT at random points (face index on mode dir).
 void sample_residual(hipStream_t s, const FiberGeom &g, const double *const *ucores, const int *ranks, int npts,

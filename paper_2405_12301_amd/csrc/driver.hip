@@ -79,6 +79,17 @@ void release_stream_cache(hipStream_t s) {
     for (auto &b : blocks) (void)hipFreeAsync(b.second, s);
 }
 
+// Returns the idle blocks of every stream to the runtime (blocks still in use stay tracked).
+void release_all_caches() {
+    std::vector<hipStream_t> streams;
+    {
+        AllocCache &ac = alloc_cache();
+        std::lock_guard<std::mutex> g(ac.mu);
+        for (auto &kv : ac.idle) streams.push_back(kv.first);
+    }
+    for (hipStream_t s : streams) release_stream_cache(s);
+}
+
 // Drops p from the bookkeeping (for teardown paths that free it themselves).
 void forget_block(void *p) {
     AllocCache &ac = alloc_cache();
@@ -142,7 +153,7 @@ enum Slot {
     S_P, S_Q, S_T, S_W, S_PTS, S_BLOCK, S_L, S_PIV, S_ROWBUF, S_TSQR, S_R, S_SIG, S_V, S_JAC, S_W1, S_W2,
     S_RANKS, S_PART, S_UST, S_LM, S_NORMS, S_TMP, S_DENSE,
     S_PD0, S_PD1, S_QD0, S_QD1, S_TD0, S_TD1, S_WD0, S_WD1, S_PN, S_QN, S_TN, S_WN, S_SPLIT,
-    S_F_G, S_F_P, S_F_Q, S_F_T, S_F_W0, S_F_WD0, S_F_WD1, S_MLPY, S_MLPW, S_NSLOTS
+    S_F_G, S_F_P, S_F_Q, S_F_T, S_F_W0, S_F_WD0, S_F_WD1, S_MLPY, S_MLPW, S_AL_I, S_AL_D, S_NSLOTS
 };
 
 struct Scratch {
@@ -276,7 +287,8 @@ struct wenott_ctx {
     double *h_pinned_dbl = nullptr;
     std::vector<ISet> warm[kMaxDim + 1];  // per flux direction, and [kMaxDim] for the stage value
     bool warm_valid[kMaxDim + 1] = {};
-    uint64_t counter = 0;
+    uint64_t counter = 0;        // random streams of the crosses
+    uint64_t alpha_counter = 0;  // random start cells of the alpha searches
     double c_eps = 0.0, max_norm = 0.0;
     bool profiling = false;
     std::vector<hipEvent_t> ev;
@@ -294,8 +306,9 @@ struct wenott_ctx {
     };
     BondHist bond[kMaxDim];
     int piv_hist[(kMaxDim + 1) * 2 * kMaxDim];  // last pivot rank per (cross slot, sweep direction, core)
+    int *d_best = nullptr;              // best cell of the last alpha search (device int[kMaxDim])
     const double *alpha_dev = nullptr;  // stage alpha on the device (read by the fiber kernels) when set
-    double alpha_cache = 0.0;           // exact alpha of the current state, if alpha_cache_valid
+    double alpha_cache = 0.0;           // alpha of the current state (alpha_mode rule), if alpha_cache_valid
     bool alpha_cache_valid = false;
     float last_sig[16] = {};
     int prev_sweeps = 1;
@@ -398,12 +411,28 @@ const double *left_part(wenott_ctx *c, const TT &U, long long *stride) {
 // Pinned host slots read after a later synchronisation: the component norms of the last rounding.
 constexpr int kPinNorms = 4080;
 
-// Enqueue the exact alpha of U into alpha slot `slot` of the status block and, with readback,
+// Enqueue the alpha of U (alpha_mode 0: exact, every cell; 1: the line-search estimate) into
+// alpha slot `slot` of the status block and, with readback,
 // a copy of the block head (flag word and alpha slots) to its pinned mirror. Returns the device
 // address. Without readback the head reaches the host with the next status readback (every
 // stage cross makes one: its sampled residual).
-double *exact_alpha_launch(wenott_ctx *c, const TT &U, int slot, bool readback = true) {
+double *alpha_launch(wenott_ctx *c, const TT &U, int slot, bool readback = true) {
     double *dst = c->d_status + kStatusAlpha + slot;
+    if (c->o.alpha_mode == 1) {  // line search (the tt_max_abs estimate of eq. cfl-other)
+        int ranks[kMaxDim + 1];
+        const double *cores[kMaxDim];
+        for (int k = 0; k <= U.d; ++k) ranks[k] = U.R[k];
+        for (int k = 0; k < U.d; ++k) cores[k] = U.core[k];
+        // its own counter: the cross's random sets follow the same sequence whether or not the
+        // caller asked for alpha in between
+        const unsigned long long seed = c->o.seed * 0x9E3779B97F4A7C15ULL + 0xA5A5ULL * (++c->alpha_counter);
+        alpha_search(c->s, U.d, U.N, cores, ranks, c->gamma, seed, c->d_best,
+                     c->sc.get<int>(S_AL_I, alpha_search_ints(U.d, U.N[1])),
+                     c->sc.get<double>(S_AL_D, alpha_search_doubles(U.d, U.N[1])),
+                     dst, c->d_flags);
+        if (readback) status_readback(c, kStatusAlpha + 4);
+        return dst;
+    }
     long long lms = 0;
     const double *Lm = left_part(c, U, &lms);
     long long nrows = 1;
@@ -420,8 +449,8 @@ double *exact_alpha_launch(wenott_ctx *c, const TT &U, int slot, bool readback =
 
 double status_alpha(const wenott_ctx *c, int slot) { return c->h_status[kStatusAlpha + slot]; }
 
-double exact_alpha(wenott_ctx *c, const TT &U) {
-    exact_alpha_launch(c, U, 3);
+double alpha_now(wenott_ctx *c, const TT &U) {
+    alpha_launch(c, U, 3);
     host_wait(c);
     raise_flags(c, status_flags(c));
     return status_alpha(c, 3);
@@ -1976,7 +2005,7 @@ void wenott_default_opts(wenott_opts *o) {
     o->rank_cap = 256;
     o->probe_points = 4096;
     o->seed = 12345;
-    o->alpha_mode = 0;
+    o->alpha_mode = 1;
     o->use_proposal = 0;
     o->alpha_given = 0.0;
     o->rounds_per_stage = 1;
@@ -2022,6 +2051,7 @@ wenott_status wenott_init(wenott_ctx **out, const wenott_tt *state, const wenott
         WTT_REQUIRE(c->o.precision == 0 || c->o.precision == 1, WENOTT_EINVAL, "precision must be 0 or 1");
         WTT_REQUIRE(c->o.max_sweeps >= 1 && c->o.rank_cap >= 1 && c->o.kick_rank >= 0, WENOTT_EINVAL, "bad options");
         WTT_REQUIRE(c->o.eps_mode == 0 || c->o.eps_mode == 1, WENOTT_EINVAL, "eps_mode must be 0 or 1");
+        WTT_REQUIRE(c->o.alpha_mode >= 0 && c->o.alpha_mode <= 2, WENOTT_EINVAL, "alpha_mode must be 0, 1 or 2");
         WTT_REQUIRE(c->o.scheme == 0 || c->o.scheme == 1, WENOTT_EINVAL, "scheme must be 0 or 1");
         WTT_REQUIRE(c->o.precision == 0 || c->o.scheme == 0, WENOTT_EINVAL, "the FP32 path runs in scheme 0");
         WTT_REQUIRE(c->o.rounds_per_stage == 1 || c->o.rounds_per_stage == 2, WENOTT_EINVAL,
@@ -2051,6 +2081,8 @@ wenott_status wenott_init(wenott_ctx **out, const wenott_tt *state, const wenott
         WTT_HIP(hipHostMalloc((void **)&c->h_status, sizeof(double) * kStatusDoubles, hipHostMallocDefault));
         WTT_HIP(hipHostMalloc((void **)&c->h_pinned_int, 4096 * sizeof(int), hipHostMallocDefault));
         WTT_HIP(hipHostMalloc((void **)&c->h_pinned_dbl, 4096 * sizeof(double), hipHostMallocDefault));
+        WTT_HIP(hipMalloc((void **)&c->d_best, sizeof(int) * kMaxDim));
+        WTT_HIP(hipMemsetAsync(c->d_best, 0xff, sizeof(int) * kMaxDim, c->s));  // -1: no best cell yet
         // common padded ranks
         const int nc = c->nc;
         TT U;
@@ -2121,6 +2153,7 @@ void wenott_destroy(wenott_ctx *c) {
         (void)hipStreamSynchronize(c->s);
         c->ring.destroy();
         if (c->d_status) (void)hipFree(c->d_status);
+        if (c->d_best) (void)hipFree(c->d_best);
         if (c->h_status) (void)hipHostFree(c->h_status);
         if (c->h_pinned_int) (void)hipHostFree(c->h_pinned_int);
         if (c->h_pinned_dbl) (void)hipHostFree(c->h_pinned_dbl);
@@ -2150,7 +2183,7 @@ wenott_status wenott_rhs(wenott_ctx *c, double alpha, wenott_tt *view) {
     return run_guarded(c, [&] {
         double t0 = seconds_now();
         reset_call_info(c);
-        double a = alpha > 0.0 ? alpha : (c->o.alpha_mode == 2 ? c->o.alpha_given : exact_alpha(c, c->U));
+        double a = alpha > 0.0 ? alpha : (c->o.alpha_mode == 2 ? c->o.alpha_given : alpha_now(c, c->U));
         WTT_REQUIRE(a > 0.0, WENOTT_EINVAL, "alpha must be positive");
         c->info.alpha[0] = a;
         double eps = current_eps(c);
@@ -2207,9 +2240,9 @@ wenott_status wenott_rk3_step(wenott_ctx *c, double dt, double eps_in, const dou
                 else if (st == 0 && c->alpha_cache_valid) a = c->alpha_cache;
                 else if (deferred) {
                     // its value reaches the host with the stage cross's residual readback
-                    c->alpha_dev = exact_alpha_launch(c, X, st, false);
+                    c->alpha_dev = alpha_launch(c, X, st, false);
                     a = 1.0;  // not used by the kernels while alpha_dev is set
-                } else a = exact_alpha(c, X);
+                } else a = alpha_now(c, X);
                 if (!deferred) {
                     WTT_REQUIRE(a > 0.0, WENOTT_EINVAL, "alpha must be positive");
                     c->info.alpha[st] = a;
@@ -2324,15 +2357,20 @@ wenott_status wenott_batch_rk3_step(wenott_ctx **ctxs, int32_t n, const double *
         try {
             for (int st = 0; st < 3; ++st) {
                 bool any = false;
+                // the first stage reuses an alpha the caller had computed for this state, as the
+                // single-state step does
+                auto cached = [&](const BState &b) { return st == 0 && b.c->alpha_cache_valid; };
                 for (auto &b : bs)
-                    if (b.c->o.alpha_mode != 2) {
-                        exact_alpha_launch(b.c, b.X, 3);
+                    if (b.c->o.alpha_mode != 2 && !cached(b)) {
+                        alpha_launch(b.c, b.X, 3);
                         any = true;
                     }
                 if (any) host_wait(ctxs[0]);
                 for (auto &b : bs) {
                     if (b.c->o.alpha_mode == 2) {
                         b.alpha = b.c->o.alpha_given;
+                    } else if (cached(b)) {
+                        b.alpha = b.c->alpha_cache;
                     } else {
                         raise_flags(b.c, status_flags(b.c));
                         b.alpha = status_alpha(b.c, 3);
@@ -2375,6 +2413,19 @@ wenott_status wenott_batch_rk3_step(wenott_ctx **ctxs, int32_t n, const double *
         }
         for (int i = 0; i < n; ++i) finish_call_info(ctxs[i], t0);
     });
+}
+
+wenott_status wenott_finalize(void) {
+    try {
+        WTT_HIP(hipDeviceSynchronize());
+        release_all_caches();
+        gemm_tune_release();
+        WTT_HIP(hipDeviceSynchronize());
+        return WENOTT_OK;
+    } catch (const HipError &e) {
+        note_error(nullptr, e.what());
+        return WENOTT_EHIP;
+    }
 }
 
 wenott_status wenott_gemm_autotune(int32_t mode) {
@@ -2432,7 +2483,7 @@ wenott_status wenott_get_info(wenott_ctx *c, wenott_info *info) {
 wenott_status wenott_max_wavespeed(wenott_ctx *c, double *alpha) {
     if (!c || !alpha) return WENOTT_EINVAL;
     return run_guarded(c, [&] {
-        *alpha = exact_alpha(c, c->U);
+        *alpha = alpha_now(c, c->U);
         c->alpha_cache = *alpha;  // the first stage of the next step reuses it
         c->alpha_cache_valid = *alpha > 0.0;
     });
@@ -2441,6 +2492,53 @@ wenott_status wenott_max_wavespeed(wenott_ctx *c, double *alpha) {
 wenott_status wenott_current_eps(wenott_ctx *c, double *eps) {
     if (!c || !eps) return WENOTT_EINVAL;
     return run_guarded(c, [&] { *eps = current_eps(c); });
+}
+
+wenott_status wenott_pivot_search(const double *A, int32_t m, int32_t n, int32_t rmax, double rel_tol2,
+                                  int32_t allow_persistent, int32_t *rowpiv, int32_t *colpiv, double *L, double *info,
+                                  void *hip_stream) {
+    if (!A || m < 1 || n < 1 || rmax < 1 || rmax > std::min(m, n) || !(rel_tol2 >= 0.0) || !rowpiv || !colpiv || !L ||
+        !info)
+        return WENOTT_EINVAL;
+    hipStream_t s = (hipStream_t)hip_stream;
+    double *B = nullptr, *ws = nullptr, *dinfo = nullptr;
+    int *piv = nullptr;
+    const wenott_status st = run_guarded(nullptr, [&] {
+        WTT_HIP(hipMallocAsync((void **)&B, sizeof(double) * (size_t)m * n, s));
+        WTT_HIP(hipMallocAsync((void **)&ws, sizeof(double) * prrlu_ws_doubles(m, n), s));
+        WTT_HIP(hipMallocAsync((void **)&dinfo, sizeof(double) * 4, s));
+        WTT_HIP(hipMallocAsync((void **)&piv, sizeof(int) * 2 * (size_t)rmax, s));
+        WTT_HIP(hipMemcpyAsync(B, A, sizeof(double) * (size_t)m * n, hipMemcpyDeviceToDevice, s));
+        bool persistent = allow_persistent != 0;
+        int next = prrlu(s, m, n, B, rmax, rel_tol2, piv, piv + rmax, L, dinfo, ws, 0, 8, persistent);
+        double h[3];
+        for (;;) {
+            WTT_HIP(hipMemcpyAsync(h, dinfo, sizeof(double) * 3, hipMemcpyDeviceToHost, s));
+            WTT_HIP(hipStreamSynchronize(s));
+            if (h[0] >= 0.0) break;
+            WTT_REQUIRE(h[0] != -2.0, WENOTT_EHIP, "pivot search: the wait for the other workgroups ran out");
+            WTT_REQUIRE(next <= rmax + 1, WENOTT_EHIP, "pivot search did not stop");
+            next = prrlu(s, m, n, B, rmax, rel_tol2, piv, piv + rmax, L, dinfo, ws, next, next + std::max(8, next / 2),
+                         persistent);
+        }
+        WTT_HIP(hipMemcpyAsync(rowpiv, piv, sizeof(int) * rmax, hipMemcpyDeviceToDevice, s));
+        WTT_HIP(hipMemcpyAsync(colpiv, piv + rmax, sizeof(int) * rmax, hipMemcpyDeviceToDevice, s));
+        WTT_HIP(hipStreamSynchronize(s));
+        info[0] = h[0];
+        info[1] = h[1];
+        info[2] = h[2];
+    });
+    if (B) (void)hipFreeAsync(B, s);
+    if (ws) (void)hipFreeAsync(ws, s);
+    if (dinfo) (void)hipFreeAsync(dinfo, s);
+    if (piv) (void)hipFreeAsync(piv, s);
+    (void)hipStreamSynchronize(s);
+    return st;
+}
+
+wenott_status wenott_pivot_layout(int32_t m, int32_t n, int32_t *out) {
+    if (m < 1 || n < 1 || !out) return WENOTT_EINVAL;
+    return run_guarded(nullptr, [&] { prrlu_layout(m, n, true, out); });
 }
 
 wenott_status wenott_set_pivot_wait_limit(int32_t polls) {

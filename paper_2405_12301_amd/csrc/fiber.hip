@@ -602,109 +602,180 @@ __global__ void k_sample_star(FiberGeom g, CoreSet cs, CoreSet un, int use_un, i
     ust[e] = tt_point<ND>(cs, c, cell);
 }
 
-// 3D star samples with one 256-thread workgroup per probe point. For point (i0, i1, i2) and a
-// component with cores G0 (N0 x R1), G1 (R1 x N1 x R2), G2 (R2 x N2): the line along mode 0 needs
-// the vector w = G1(:, i1, :) G2(:, i2) once and a dot product per cell; the line along mode 2
-// needs v = G0(i0, :) G1(:, i1, :) once and a dot product per cell; the cells along mode 1 each
-// need one such matrix-vector product. 9 R1 R2 multiply-adds per point and component instead
-// of 22; G1 rows are read contiguously by consecutive threads.
-__device__ inline double block_sum256(double v, double *red) {
-    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
-    __syncthreads();
-    if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = v;
-    __syncthreads();
-    return (red[0] + red[1]) + (red[2] + red[3]);
-}
-
-__device__ inline double wave_sum_f(double v) {
+// 3D star samples by slices of the middle core: workgroup j owns slice j of mode 1 and serves
+// every (probe point, shift) whose mode-1 cell maps to j, so each slice G1(:, j, :) of every
+// component is read once, staged in LDS, instead of by every point that needs it (a point needs 7
+// slices; at R = 60 a slice is 28 KB and 4096 points would read ~4 GB). The pairs of the slice
+// are collected from all points into an LDS list; per component the slice is staged and one wave
+// serves a pair, its lanes over the right rank index be:
+//   t(be) = sum_al G0(i0, al) S(al, be); slot 7 + s (mode-1 line) = sum_be t(be) G2(be, i2).
+// The pair whose shift is 0 (j = i1) also forms the mode-2 line from v = t (slots 14 + q:
+// sum_be t(be) G2(be, i2 + q - 3)), the mode-0 line from w1(al) = sum_be S(al, be) G2(be, i2)
+// (slots q: sum_al G0(i0 + q - 3, al) w1(al), lanes over al) and U^n at the point (slot 21).
+// A slice larger than the LDS budget is read from global memory in place.
+__device__ inline double wave_sum_d(double v) {
     for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
     return v;
 }
 
-__global__ __launch_bounds__(256) void k_sample_star3(FiberGeom g, CoreSet cs, CoreSet un, int use_un, int npts,
-                                                      unsigned long long seed, double *__restrict__ ust) {
-    constexpr int NC = 5, SL = 22;
-    extern __shared__ double sm[];
-    __shared__ double red[4];
-    __shared__ double vals[SL];
-    const int pt = blockIdx.x, tid = threadIdx.x, lane = tid % kWave, w = tid / kWave;
-    if (pt >= npts) return;
-    const int i0 = probe_coord(seed, (long long)pt * 3, g.n[0]), i1 = probe_coord(seed, (long long)pt * 3 + 1, g.n[1]),
-              i2 = probe_coord(seed, (long long)pt * 3 + 2, g.n[2]);
+constexpr int kSlicePairs = 2048;      // pairs held at once (a slice gets ~7 npts / N1 of them)
+constexpr int kSliceLdsDoubles = 8192;  // staged slice (R1 R2 <= 8192)
+
+__global__ __launch_bounds__(256) void k_sample_slices3(FiberGeom g, CoreSet cs, CoreSet un, int use_un, int npts,
+                                                        unsigned long long seed, double *__restrict__ ust) {
+    constexpr int NC = 5;
+    __shared__ int pair_pt[kSlicePairs];
+    __shared__ unsigned char pair_s[kSlicePairs];
+    __shared__ int npairs;
+    __shared__ double S_lds[kSliceLdsDoubles];
+    const int j = blockIdx.x, tid = threadIdx.x, lane = tid % kWave, w = tid / kWave;
     const int N0 = g.n[0], N1 = g.n[1], N2 = g.n[2];
-    for (int c = 0; c < NC; ++c) {
-        const int R1 = cs.R[1], R2 = cs.R[2];
-        double *g0row = sm, *w1 = sm + R1, *v = sm + 2 * R1, *g2col = sm + 2 * R1 + R2;
-        const double *G0 = cs.c[0] + c * cs.cstride[0];
-        const double *G1 = cs.c[1] + c * cs.cstride[1];
-        const double *G2 = cs.c[2] + c * cs.cstride[2];
-        for (int al = tid; al < R1; al += 256) g0row[al] = G0[(long long)i0 * R1 + al];
-        for (int be = tid; be < R2; be += 256) g2col[be] = G2[(long long)be * N2 + i2];
+    const int R1 = cs.R[1], R2 = cs.R[2];
+    const long long s1 = (long long)N1 * R2;
+    const bool staged = (long long)R1 * R2 <= kSliceLdsDoubles;
+    int scan = 0;  // next point to scan
+    while (scan < npts) {
+        // collect pairs until the list could overflow with the next 256 points (7 pairs each)
+        if (tid == 0) npairs = 0;
         __syncthreads();
-        // v = G0(i0, :) G1(:, i1, :)
-        for (int be = tid; be < R2; be += 256) {
-            double acc = 0.0;
-            for (int al = 0; al < R1; ++al) acc = fma(g0row[al], G1[((long long)al * N1 + i1) * R2 + be], acc);
-            v[be] = acc;
-        }
-        // w = G1(:, i1, :) G2(:, i2)
-        for (int al = w; al < R1; al += 4) {
-            const double *row = G1 + ((long long)al * N1 + i1) * R2;
-            double p = 0.0;
-            for (int be = lane; be < R2; be += kWave) p = fma(row[be], g2col[be], p);
-            p = wave_sum_f(p);
-            if (lane == 0) w1[al] = p;
-        }
-        __syncthreads();
-        // lines along modes 0 and 2: 14 dot products over the four waves
-        for (int q = w; q < 14; q += 4) {
-            const int sft = q % 7 - 3;
-            double p = 0.0;
-            if (q < 7) {
-                const double *row = G0 + (long long)ghost_map(i0 + sft, N0, g.bc[0]) * R1;
-                for (int al = lane; al < R1; al += kWave) p = fma(row[al], w1[al], p);
-            } else {
-                const int j2 = ghost_map(i2 + sft, N2, g.bc[2]);
-                for (int be = lane; be < R2; be += kWave) p = fma(v[be], G2[(long long)be * N2 + j2], p);
+        while (scan < npts && npairs + 7 * 256 <= kSlicePairs) {
+            const int pt = scan + tid;
+            if (pt < npts) {
+                const int i1 = probe_coord(seed, (long long)pt * 3 + 1, N1);
+                for (int sh = 0; sh < 7; ++sh)
+                    if (ghost_map(i1 + sh - 3, N1, g.bc[1]) == j) {
+                        const int q = atomicAdd(&npairs, 1);
+                        pair_pt[q] = pt;
+                        pair_s[q] = (unsigned char)sh;
+                    }
             }
-            p = wave_sum_f(p);
-            if (lane == 0) vals[q < 7 ? q : 14 + (q - 7)] = p;
+            scan += 256;
+            __syncthreads();
         }
-        // line along mode 1
-        for (int sft = -3; sft <= 3; ++sft) {
-            double part = 0.0;
-            if (sft == 0) {
-                for (int be = tid; be < R2; be += 256) part = fma(v[be], g2col[be], part);
-            } else {
-                const int j1 = ghost_map(i1 + sft, N1, g.bc[1]);
-                for (int be = tid; be < R2; be += 256) {
-                    double acc = 0.0;
-                    for (int al = 0; al < R1; ++al) acc = fma(g0row[al], G1[((long long)al * N1 + j1) * R2 + be], acc);
-                    part = fma(acc, g2col[be], part);
+        const int np = npairs;
+        for (int c = 0; c < NC && np > 0; ++c) {
+            const double *G1c = cs.c[1] + c * cs.cstride[1] + (long long)j * R2;  // S(al, be) = G1c[al s1 + be]
+            if (staged) {
+                for (int e = tid; e < R1 * R2; e += 256) {
+                    const int al = e / R2, be = e - al * R2;
+                    S_lds[e] = G1c[al * s1 + be];
                 }
             }
-            part = block_sum256(part, red);
-            if (tid == 0) vals[7 + sft + 3] = part;
-        }
-        // U^n at the point itself
-        double un_part = 0.0;
-        if (use_un) {
-            const int S1 = un.R[1], S2 = un.R[2];
-            const double *H0 = un.c[0] + c * un.cstride[0];
-            const double *H1 = un.c[1] + c * un.cstride[1];
-            const double *H2 = un.c[2] + c * un.cstride[2];
-            for (int be = tid; be < S2; be += 256) {
-                double acc = 0.0;
-                for (int al = 0; al < S1; ++al)
-                    acc = fma(H0[(long long)i0 * S1 + al], H1[((long long)al * N1 + i1) * S2 + be], acc);
-                un_part = fma(acc, H2[(long long)be * N2 + i2], un_part);
+            __syncthreads();
+            const double *S = staged ? S_lds : G1c;
+            const long long sS = staged ? R2 : s1;
+            const double *G0 = cs.c[0] + c * cs.cstride[0];
+            const double *G2 = cs.c[2] + c * cs.cstride[2];
+            for (int q = w; q < np; q += 256 / kWave) {
+                const int p = pair_pt[q], sh = pair_s[q];
+                const int i0 = probe_coord(seed, (long long)p * 3, N0), i2 = probe_coord(seed, (long long)p * 3 + 2, N2);
+                const double *g0 = G0 + (long long)i0 * R1;
+                const bool centre = sh == 3;
+                double val = 0.0, l2[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+                int k2[7];
+#pragma unroll
+                for (int qq = 0; qq < 7; ++qq) k2[qq] = ghost_map(i2 + qq - 3, N2, g.bc[2]);
+                double g2c = 0.0;  // G2(be, i2) of this lane's be (R2 <= 64: every be has its lane)
+                for (int be0 = 0; be0 < R2; be0 += kWave) {
+                    const int be = be0 + lane;
+                    double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
+                    for (int al0 = 0; al0 < R1; al0 += kWave) {
+                        const double gv = al0 + lane < R1 ? g0[al0 + lane] : 0.0;
+                        const int na = min(kWave, R1 - al0);
+                        int a = 0;
+                        for (; a + 3 < na; a += 4) {
+                            const double x0 = __shfl(gv, a, kWave), x1 = __shfl(gv, a + 1, kWave);
+                            const double x2 = __shfl(gv, a + 2, kWave), x3 = __shfl(gv, a + 3, kWave);
+                            if (be < R2) {
+                                t0 = fma(x0, S[(al0 + a) * sS + be], t0);
+                                t1 = fma(x1, S[(al0 + a + 1) * sS + be], t1);
+                                t2 = fma(x2, S[(al0 + a + 2) * sS + be], t2);
+                                t3 = fma(x3, S[(al0 + a + 3) * sS + be], t3);
+                            }
+                        }
+                        for (; a < na; ++a) {
+                            const double x0 = __shfl(gv, a, kWave);
+                            if (be < R2) t0 = fma(x0, S[(al0 + a) * sS + be], t0);
+                        }
+                    }
+                    if (be >= R2) continue;
+                    const double t = (t0 + t1) + (t2 + t3);
+                    const double *g2 = G2 + (long long)be * N2;
+                    const double g2v = g2[i2];
+                    if (be0 == 0) g2c = g2v;
+                    val = fma(t, g2v, val);
+                    if (centre)
+#pragma unroll
+                        for (int qq = 0; qq < 7; ++qq) l2[qq] = fma(t, g2[k2[qq]], l2[qq]);
+                }
+                val = wave_sum_d(val);
+                if (lane == 0) ust[((long long)(7 + sh) * NC + c) * npts + p] = val;
+                if (!centre) continue;
+#pragma unroll
+                for (int qq = 0; qq < 7; ++qq) {
+                    const double v2 = wave_sum_d(l2[qq]);
+                    if (lane == 0) ust[((long long)(14 + qq) * NC + c) * npts + p] = v2;
+                }
+                // mode-0 line: w1(al) = S(al, :) . G2(:, i2), lanes over al; G2(:, i2) comes from the
+                // lanes that loaded it above when R2 <= 64 (by shuffles), else from memory
+                double l0[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+                for (int al0 = 0; al0 < R1; al0 += kWave) {
+                    const int al = al0 + lane;
+                    const double *row = S + (al < R1 ? al : 0) * sS;
+                    double w0 = 0.0, w1 = 0.0;
+                    if (R2 <= kWave) {
+                        int be = 0;
+                        for (; be + 1 < R2; be += 2) {
+                            const double x0 = __shfl(g2c, be, kWave), x1 = __shfl(g2c, be + 1, kWave);
+                            w0 = fma(row[be], x0, w0);
+                            w1 = fma(row[be + 1], x1, w1);
+                        }
+                        if (be < R2) w0 = fma(row[be], __shfl(g2c, be, kWave), w0);
+                    } else {
+                        for (int be = 0; be < R2; ++be) w0 = fma(row[be], G2[(long long)be * N2 + i2], w0);
+                    }
+                    if (al >= R1) continue;
+                    const double wv = w0 + w1;
+#pragma unroll
+                    for (int qq = 0; qq < 7; ++qq)
+                        l0[qq] = fma(G0[(long long)ghost_map(i0 + qq - 3, N0, g.bc[0]) * R1 + al], wv, l0[qq]);
+                }
+#pragma unroll
+                for (int qq = 0; qq < 7; ++qq) {
+                    const double v0 = wave_sum_d(l0[qq]);
+                    if (lane == 0) ust[((long long)qq * NC + c) * npts + p] = v0;
+                }
+                // U^n at the point
+                double unv = 0.0;
+                if (use_un) {
+                    const int S1 = un.R[1], S2 = un.R[2];
+                    const double *H0 = un.c[0] + c * un.cstride[0] + (long long)i0 * S1;
+                    const double *H1 = un.c[1] + c * un.cstride[1] + (long long)j * S2;
+                    const double *H2 = un.c[2] + c * un.cstride[2];
+                    const long long t1s = (long long)N1 * S2;
+                    for (int be0 = 0; be0 < S2; be0 += kWave) {
+                        const int be = be0 + lane, bq = be < S2 ? be : 0;
+                        double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
+                        for (int al0 = 0; al0 < S1; al0 += kWave) {
+                            const double hv = al0 + lane < S1 ? H0[al0 + lane] : 0.0;
+                            const int na = min(kWave, S1 - al0);
+                            int a = 0;
+                            for (; a + 3 < na; a += 4) {
+                                t0 = fma(__shfl(hv, a, kWave), H1[(al0 + a) * t1s + bq], t0);
+                                t1 = fma(__shfl(hv, a + 1, kWave), H1[(al0 + a + 1) * t1s + bq], t1);
+                                t2 = fma(__shfl(hv, a + 2, kWave), H1[(al0 + a + 2) * t1s + bq], t2);
+                                t3 = fma(__shfl(hv, a + 3, kWave), H1[(al0 + a + 3) * t1s + bq], t3);
+                            }
+                            for (; a < na; ++a) t0 = fma(__shfl(hv, a, kWave), H1[(al0 + a) * t1s + bq], t0);
+                        }
+                        if (be < S2) unv = fma((t0 + t1) + (t2 + t3), H2[(long long)be * N2 + i2], unv);
+                    }
+                    unv = wave_sum_d(unv);
+                }
+                if (lane == 0) ust[((long long)21 * NC + c) * npts + p] = unv;
             }
+            __syncthreads();  // the staged slice is replaced for the next component
         }
-        un_part = block_sum256(un_part, red);
-        if (tid == 0) vals[21] = use_un ? un_part : 0.0;
-        __syncthreads();
-        for (int q = tid; q < SL; q += 256) ust[((long long)q * NC + c) * npts + pt] = vals[q];
-        __syncthreads();
     }
 }
 
@@ -983,11 +1054,10 @@ void sample_stage(hipStream_t s, const FiberGeom &g, const double *const *xcores
         k_sample_stage<2><<<sample_stage_blocks(2, npts), 256, 0, s>>>(g, fs, npts, seed, ust, wn, wx, wl, hs, acc,
                                                                      flags);
     } else {
-        // the point-per-workgroup form pays off once a cell costs more than a few hundred
-        // multiply-adds (R1 R2); below that one thread per sample is faster
-        const size_t lds = sizeof(double) * 2 * ((size_t)xs.R[1] + xs.R[2]);
-        if (lds <= 48 * 1024 && (long long)xs.R[1] * xs.R[2] > 512)
-            k_sample_star3<<<npts, 256, lds, s>>>(g, xs, us, ncores != nullptr, npts, seed, ust);
+        // the slice form pays off once a cell costs more than a few hundred multiply-adds
+        // (R1 R2); below that one thread per sample value is faster
+        if ((long long)xs.R[1] * xs.R[2] > 512)
+            k_sample_slices3<<<g.n[1], 256, 0, s>>>(g, xs, us, ncores != nullptr, npts, seed, ust);
         else
             k_sample_star<3><<<cdiv(n1, 256), 256, 0, s>>>(g, xs, us, ncores != nullptr, npts, seed, ust);
         k_sample_stage<3><<<sample_stage_blocks(3, npts), 256, 0, s>>>(g, fs, npts, seed, ust, wn, wx, wl, hs, acc,

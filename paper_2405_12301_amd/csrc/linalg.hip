@@ -831,7 +831,7 @@ __device__ __forceinline__ void prrlu_mw_init_body(const PrrluJob &J) {
         w.ctl->fail = 0;
         J.info[0] = -1.0;  // not finished: the host launches further steps
     }
-    if (J.mode == 2) {
+    if (J.mode == 2 || J.mode == 4) {  // the persistent forms
         long long *p = (long long *)J.ws;
         for (long long e = threadIdx.x; e < 2 * w.pstride; e += blockDim.x) p[e] = 3;
     }
@@ -1045,6 +1045,8 @@ __device__ __forceinline__ void prrlu_mw_step_body(const PrrluJob &J, int t) {
 // set another bound) a workgroup marks the job failed (info[0] = -2) and leaves, and the others
 // leave at their next poll.
 constexpr int kCoopMaxBlk = 64;  // one slot per lane of a wave
+constexpr int kCoopBigSlots = 256;  // the persistent form for large blocks: four slots per lane
+constexpr int kCoopBigRows = 2048;  // its stripes' rows at most (the pivot-column buffer)
 constexpr int kCoopSpin = 1 << 22;
 constexpr long long kNoRow = 0x7fffffffffffffffLL;
 
@@ -1084,25 +1086,67 @@ __device__ __forceinline__ bool coop_poll(const long long *const (&p)[NW], int t
     return false;
 }
 
-__device__ __forceinline__ void prrlu_coop_body(const PrrluJob &J) {
-    __shared__ double lc[kMwThreads * kMwK];
-    __shared__ double wmax[kMwThreads / kWave], wsum[kMwThreads / kWave];
-    __shared__ long long widx[kMwThreads / kWave];
+// NT threads per workgroup. Thread (tr, tc) owns columns [c0, c0 + kMwTW) of the stripe rows
+// r0 + tr + k RS: rows k < K in registers, K <= k < K + KL in LDS (element (k, j) at
+// ld[((k - K) kMwTW + j) NT + tid]: consecutive threads, consecutive words) and, with GL, rows
+// K + KL <= k < J.shape left in A itself and streamed through at every step. Up to 64 SPL
+// workgroups (each polling lane gathers SPL slots). LC: the pivot-column buffer (>= J.rows).
+// The rows outside the registers have their partials for the next step formed in the same pass
+// that eliminates them.
+template <int NT, int K, int KL, bool GL, int SPL, int LC>
+__device__ __forceinline__ void prrlu_coop_body_t(const PrrluJob &J) {
+    __shared__ double lc[LC];
+    __shared__ double ld[KL > 0 ? KL * kMwTW * NT : 1];
+    __shared__ double wmax[NT / kWave], wsum[NT / kWave];
+    __shared__ long long widx[NT / kWave];
     __shared__ int s_fail;
     const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave;
     const int m = J.m, n = J.n, rmax = J.rmax, G = J.nblk, blk = blockIdx.x;
     const PrrluWs w = prrlu_ws_split(J.ws, n, J.nblk);
-    const int tpr = (n + kMwTW - 1) / kMwTW, RS = kMwThreads / tpr;
+    const int tpr = (n + kMwTW - 1) / kMwTW, RS = NT / tpr;
     const int tr = tid / tpr, tc = tid % tpr, c0 = tc * kMwTW;
     const bool active = tr < RS;
     const int r0 = blk * J.rows;
-    double a[kMwK][kMwTW];
+    const int KT = GL ? J.shape : K + KL;  // rows per thread
+    double *__restrict__ A = J.A;
+    double a[K][kMwTW];
 #pragma unroll
-    for (int k = 0; k < kMwK; ++k) {
+    for (int k = 0; k < K; ++k) {
         const int row = r0 + tr + k * RS;
         const bool rv = active && row < m;
 #pragma unroll
-        for (int j = 0; j < kMwTW; ++j) a[k][j] = (rv && c0 + j < n) ? J.A[(long long)row * n + c0 + j] : 0.0;
+        for (int j = 0; j < kMwTW; ++j) a[k][j] = (rv && c0 + j < n) ? A[(long long)row * n + c0 + j] : 0.0;
+    }
+    // partials (largest magnitude, its slot k kMwTW + j, squared sum) of the rows outside the
+    // registers, for the coming step
+    double xmax = -1.0, xsum = 0.0;
+    int xk = 0;
+#pragma unroll
+    for (int k = 0; k < KL; ++k) {
+        const int row = r0 + tr + (K + k) * RS;
+        const bool rv = active && row < m;
+#pragma unroll
+        for (int j = 0; j < kMwTW; ++j) {
+            const double v = (rv && c0 + j < n) ? A[(long long)row * n + c0 + j] : 0.0;
+            ld[(k * kMwTW + j) * NT + tid] = v;
+            xsum = fma(v, v, xsum);
+            if (fabs(v) > xmax) { xmax = fabs(v); xk = (K + k) * kMwTW + j; }
+        }
+    }
+    if (GL && active) {
+        for (int k = K + KL; k < KT; ++k) {
+            const int row = r0 + tr + k * RS;
+            if (row >= m) break;
+            const double *src = A + (long long)row * n + c0;
+            double v[kMwTW];
+#pragma unroll
+            for (int j = 0; j < kMwTW; ++j) v[j] = c0 + j < n ? src[j] : 0.0;
+#pragma unroll
+            for (int j = 0; j < kMwTW; ++j) {
+                xsum = fma(v[j], v[j], xsum);
+                if (fabs(v[j]) > xmax) { xmax = fabs(v[j]); xk = k * kMwTW + j; }
+            }
+        }
     }
     if (tid == 0) s_fail = 0;
     double tol2 = 0.0;  // every workgroup forms the same value from the same partials
@@ -1110,26 +1154,30 @@ __device__ __forceinline__ void prrlu_coop_body(const PrrluJob &J) {
         const int cur = t & 1;
         // partials of the residual after t pivots, and this stripe's candidate row
         double lmax = -1.0, lsum = 0.0;
-        long long lidx = 0x7fffffffffffffffLL;
+        int lk = 0;  // the thread's best entry as k * kMwTW + j (the global index is formed once)
 #pragma unroll
-        for (int k = 0; k < kMwK; ++k) {
-            const long long rb = (long long)(r0 + tr + k * RS) * n + c0;
+        for (int k = 0; k < K; ++k) {
 #pragma unroll
             for (int j = 0; j < kMwTW; ++j) {
                 const double v = a[k][j], av = fabs(v);
                 lsum = fma(v, v, lsum);
                 const bool gt = av > lmax;
                 lmax = gt ? av : lmax;
-                lidx = gt ? rb + j : lidx;
+                lk = gt ? k * kMwTW + j : lk;
             }
         }
-        if (!active) { lmax = -1.0; lsum = 0.0; }
+        if (KL > 0 || GL) {  // the other rows have larger row indices: ties stay with the registers
+            lsum += xsum;
+            if (xmax > lmax) { lmax = xmax; lk = xk; }
+        }
+        long long lidx = (long long)(r0 + tr + (lk / kMwTW) * RS) * n + c0 + lk % kMwTW;
+        if (!active) { lmax = -1.0; lsum = 0.0; lidx = 0x7fffffffffffffffLL; }
         wave_amax_sum(lmax, lidx, lsum);
         if (lane == 0) { wmax[wv] = lmax; widx[wv] = lidx; wsum[wv] = lsum; }
         __syncthreads();
         double bm = wmax[0], bs = 0.0;
         long long bi = widx[0];
-        for (int k = 0; k < kMwThreads / kWave; ++k) {
+        for (int k = 0; k < NT / kWave; ++k) {
             bs += wsum[k];
             amax_merge(bm, bi, wmax[k], widx[k]);
         }
@@ -1145,28 +1193,49 @@ __device__ __forceinline__ void prrlu_coop_body(const PrrluJob &J) {
             const int local = (int)(bi / n) - r0;
             if (local % RS == tr) {
                 long long *dst = prw + (long long)blk * n;
+                const int kk = local / RS;
 #pragma unroll
-                for (int k = 0; k < kMwK; ++k)
-                    if (k == local / RS)
+                for (int k = 0; k < K; ++k)
+                    if (k == kk)
 #pragma unroll
                         for (int j = 0; j < kMwTW; ++j)
                             if (c0 + j < n) coop_put(dst + c0 + j, coop_word_d(a[k][j], tg));
+                if (kk >= K && kk < K + KL) {
+#pragma unroll
+                    for (int j = 0; j < kMwTW; ++j)
+                        if (c0 + j < n) coop_put(dst + c0 + j, coop_word_d(ld[((kk - K) * kMwTW + j) * NT + tid], tg));
+                } else if (GL && kk >= K + KL) {
+                    const double *src = A + (long long)(r0 + local) * n;
+#pragma unroll
+                    for (int j = 0; j < kMwTW; ++j)
+                        if (c0 + j < n) coop_put(dst + c0 + j, coop_word_d(src[c0 + j], tg));
+                }
             }
         }
         // every wave gathers every slot and decides pivot t on its own
         double gm = -1.0, gs = 0.0;
         long long gi = kNoRow;
         bool ok = true;
-        long long got[3] = {0, 0, 0};
-        if (lane < G) {
-            const long long *const src[3] = {pmx + lane, psm + lane, pix + lane};
-            ok = coop_poll<3>(src, tg, w.ctl, J.spin, got);
+        long long got[3 * SPL];
+        if (lane < G) {  // slots lane, lane + 64, ...; a slot past the grid polls slot lane again
+            const long long *src[3 * SPL];
+#pragma unroll
+            for (int q = 0; q < SPL; ++q) {
+                const int sl = lane + kWave * q < G ? lane + kWave * q : lane;
+                src[3 * q] = pmx + sl;
+                src[3 * q + 1] = psm + sl;
+                src[3 * q + 2] = pix + sl;
+            }
+            ok = coop_poll<3 * SPL>(src, tg, w.ctl, J.spin, got);
         }
         bool wave_ok = __ballot(!ok) == 0;
         if (lane < G && wave_ok) {
-            gm = coop_val_d(got[0]);
-            gs = coop_val_d(got[1]);
-            gi = coop_val_i(got[2]);
+#pragma unroll
+            for (int q = 0; q < SPL; ++q)
+                if (lane + kWave * q < G) {  // slots in workgroup order within the lane
+                    gs += coop_val_d(got[3 * q + 1]);
+                    amax_merge(gm, gi, coop_val_d(got[3 * q]), coop_val_i(got[3 * q + 2]));
+                }
         }
         wave_amax_sum(gm, gi, gs);
         if (t == 0) tol2 = J.rel_tol2 * gs;
@@ -1214,9 +1283,17 @@ __device__ __forceinline__ void prrlu_coop_body(const PrrluJob &J) {
                 if (active && pj >= c0 && pj < c0 + kMwTW) {  // the pivot column's owners publish it
 #pragma unroll
                     for (int j = 0; j < kMwTW; ++j)
-                        if (c0 + j == pj)
+                        if (c0 + j == pj) {
 #pragma unroll
-                            for (int k = 0; k < kMwK; ++k) lc[tr + k * RS] = a[k][j];
+                            for (int k = 0; k < K; ++k) lc[tr + k * RS] = a[k][j];
+#pragma unroll
+                            for (int k = 0; k < KL; ++k) lc[tr + (K + k) * RS] = ld[(k * kMwTW + j) * NT + tid];
+                        }
+                    if (GL)
+                        for (int k = K + KL; k < KT; ++k) {
+                            const int row = r0 + tr + k * RS;
+                            lc[tr + k * RS] = row < m ? A[(long long)row * n + pj] : 0.0;
+                        }
                 }
             }
         }
@@ -1227,14 +1304,14 @@ __device__ __forceinline__ void prrlu_coop_body(const PrrluJob &J) {
         }
         if (stop) {  // every wave took the same decision
             if (stop == 2)
-                for (int row = r0 + tid; row < min(m, r0 + J.rows); row += kMwThreads)
+                for (int row = r0 + tid; row < min(m, r0 + J.rows); row += NT)
                     J.L[(long long)row * rmax] = (row == 0) ? 1.0 : 0.0;
             return;
         }
         const double inv = 1.0 / upj;
         if (active) {
 #pragma unroll
-            for (int k = 0; k < kMwK; ++k) {
+            for (int k = 0; k < K; ++k) {
                 const int row = r0 + tr + k * RS;
                 if (row >= m) continue;
                 const double l = row == pi ? 1.0 : lc[tr + k * RS] * inv;
@@ -1252,15 +1329,65 @@ __device__ __forceinline__ void prrlu_coop_body(const PrrluJob &J) {
                 for (int j = 0; j < kMwTW; ++j)
                     if (c0 + j == pj)
 #pragma unroll
-                        for (int k = 0; k < kMwK; ++k) a[k][j] = 0.0;
+                        for (int k = 0; k < K; ++k) a[k][j] = 0.0;
             }
+            // the other rows: eliminate, write back and form their partials for the next step
+            xmax = -1.0;
+            xsum = 0.0;
+            xk = 0;
+#pragma unroll
+            for (int k = 0; k < KL; ++k) {
+                const int row = r0 + tr + (K + k) * RS;
+                if (row >= m) continue;
+                const double l = row == pi ? 1.0 : lc[tr + (K + k) * RS] * inv;
+                if (tc == 0) J.L[(long long)row * rmax + t] = l;
+                double v[kMwTW];
+#pragma unroll
+                for (int j = 0; j < kMwTW; ++j) v[j] = ld[(k * kMwTW + j) * NT + tid];
+#pragma unroll
+                for (int j = 0; j < kMwTW; ++j) {
+                    v[j] = (row == pi || c0 + j == pj) ? 0.0 : fma(-l, uu[j], v[j]);
+                    ld[(k * kMwTW + j) * NT + tid] = v[j];
+                    xsum = fma(v[j], v[j], xsum);
+                    if (fabs(v[j]) > xmax) { xmax = fabs(v[j]); xk = (K + k) * kMwTW + j; }
+                }
+            }
+            if (GL)
+                for (int k = K + KL; k < KT; ++k) {
+                    const int row = r0 + tr + k * RS;
+                    if (row >= m) break;
+                    const double l = row == pi ? 1.0 : lc[tr + k * RS] * inv;
+                    if (tc == 0) J.L[(long long)row * rmax + t] = l;
+                    double *dst = A + (long long)row * n + c0;
+                    double v[kMwTW];
+#pragma unroll
+                    for (int j = 0; j < kMwTW; ++j) v[j] = c0 + j < n ? dst[j] : 0.0;
+#pragma unroll
+                    for (int j = 0; j < kMwTW; ++j) {
+                        v[j] = (row == pi || c0 + j == pj) ? 0.0 : fma(-l, uu[j], v[j]);
+                        if (c0 + j < n) dst[j] = v[j];
+                        xsum = fma(v[j], v[j], xsum);
+                        if (fabs(v[j]) > xmax) { xmax = fabs(v[j]); xk = k * kMwTW + j; }
+                    }
+                }
         }
         // lc and the wave partials are next written after the next step's first barrier, which
         // every wave reaches only when done with this step's values
     }
 }
 
+__device__ __forceinline__ void prrlu_coop_body(const PrrluJob &J) {
+    prrlu_coop_body_t<kMwThreads, kMwK, 0, false, 1, kMwThreads * kMwK>(J);
+}
+
 __global__ __launch_bounds__(kMwThreads) void k_prrlu_coop(PrrluJob J) { prrlu_coop_body(J); }
+
+// The persistent form for blocks of up to ~5 10^6 entries: K rows per thread in registers (a
+// block of 22528 x 240 is 176 stripes of 128 rows at K = 16), up to 256 workgroups, one per CU.
+template <int K, int KL, bool GL>
+__global__ __launch_bounds__(kMwThreads) void k_prrlu_coop_big(PrrluJob J) {
+    prrlu_coop_body_t<kMwThreads, K, KL, GL, kCoopBigSlots / kWave, kCoopBigRows>(J);
+}
 
 __global__ __launch_bounds__(kMwThreads) void k_prrlu_coop_batch(const PrrluJob *__restrict__ jobs) {
     const PrrluJob J = jobs[blockIdx.y];
@@ -1908,6 +2035,21 @@ void launch_gemm(int shape, hipStream_t s, bool ta, bool tb, int M, int N, int K
 
 }  // namespace
 
+void gemm_tune_release() {
+    GemmTuner &t = tuner();
+    std::lock_guard<std::mutex> lk(t.mu);
+    for (auto &kv : t.table) {
+        for (auto &p : kv.second.pending) {  // timings still in flight are dropped
+            (void)hipEventSynchronize(p.e1);
+            (void)hipEventDestroy(p.e0);
+            (void)hipEventDestroy(p.e1);
+        }
+        kv.second.pending.clear();
+    }
+    for (hipEvent_t e : t.free_events) (void)hipEventDestroy(e);
+    t.free_events.clear();
+}
+
 void gemm_tune_enable(int mode) {
     GemmTuner &t = tuner();
     std::lock_guard<std::mutex> lk(t.mu);
@@ -2177,7 +2319,29 @@ int g_coop_spin = kCoopSpin;
 
 void set_coop_spin(int polls) { g_coop_spin = polls > 0 ? polls : (polls == 0 ? 0 : kCoopSpin); }
 
-void prrlu_prepare(PrrluJob &j) {
+// Workgroups of the large persistent form with K register rows and KL LDS rows per thread that
+// the device holds at once.
+template <int K, int KL, bool GL>
+int coop_big_capacity() {
+    static int cap = -1;
+    if (cap < 0) {
+        int dev = 0, ncu = 0, nb = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_prrlu_coop_big<K, KL, GL>, kMwThreads, 0) != hipSuccess)
+            cap = 0;
+        else
+            cap = nb * ncu;
+    }
+    return cap;
+}
+
+// mode 4 (allow_big): a block whose kMwK-row stripes would need more workgroups than the small
+// persistent form takes is split into stripes of 8, 16 (registers) or 24 (16 in registers, 8 in
+// LDS) rows per thread, the first whose grid fits kCoopBigSlots and the device at once, or of
+// more rows per thread (the rest streamed from the block), and factorised in one persistent
+// launch; the rows per thread are kept in shape.
+void prrlu_prepare(PrrluJob &j, bool allow_big) {
     j.spin = g_coop_spin;
     j.shape = tile_shape_for(j.m, j.n);
     const int tpr = (j.n + kMwTW - 1) / kMwTW;
@@ -2187,9 +2351,46 @@ void prrlu_prepare(PrrluJob &j) {
     j.nblk = (j.m + j.rows - 1) / j.rows;
     if (j.shape >= 0) {
         j.mode = 0;
-    } else if (j.nblk <= kCoopMaxBlk) {
+        return;
+    }
+    if (j.nblk <= kCoopMaxBlk) {
         j.mode = 2;
-    } else if (j.nblk < 4 * kMwBigMinBlk) {
+        return;
+    }
+    if (allow_big) {
+        // 24 rows in registers would spill to scratch memory: the third form keeps 8 of them in LDS
+        const int ks[3] = {8, 16, 24};
+        const int caps[3] = {coop_big_capacity<8, 0, false>(), coop_big_capacity<16, 0, false>(),
+                             coop_big_capacity<16, 8, false>()};
+        const int RS = kMwThreads / tpr;
+        for (int q = 0; q < 3; ++q) {
+            const int rows = RS * ks[q];
+            const int nblk = (j.m + rows - 1) / rows;
+            if (rows <= kCoopBigRows && nblk <= kCoopBigSlots && nblk <= caps[q]) {
+                j.mode = 4;
+                j.shape = ks[q];
+                j.rows = rows;
+                j.nblk = nblk;
+                return;
+            }
+        }
+        // larger still: the rows beyond 24 per thread stay in the block and are streamed at every
+        // step, over as many workgroups as the device holds at once
+        const int gmax = std::min(kCoopBigSlots, coop_big_capacity<14, 8, true>());
+        if (gmax > 0) {
+            const int per = (j.m + gmax - 1) / gmax;  // rows per workgroup
+            const int kt = std::max(25, (per + RS - 1) / RS);  // 14 in registers, 8 in LDS, the rest streamed
+            const int rows = RS * kt;
+            if (rows <= kCoopBigRows) {
+                j.mode = 4;
+                j.shape = kt;
+                j.rows = rows;
+                j.nblk = (j.m + rows - 1) / rows;
+                return;
+            }
+        }
+    }
+    if (j.nblk < 4 * kMwBigMinBlk) {
         j.mode = 1;
     } else {  // tall enough that the longer stripes still give kMwBigMinBlk workgroups or more
         j.mode = 3;
@@ -2198,11 +2399,36 @@ void prrlu_prepare(PrrluJob &j) {
     }
 }
 
-size_t prrlu_ws_doubles(int m, int n) {
+void prrlu_layout(int m, int n, bool allow_big, int *out) {
     PrrluJob j{};
     j.m = m; j.n = n;
-    prrlu_prepare(j);
-    return 2 * (3 * (size_t)j.nblk + (size_t)j.nblk * n) + sizeof(PrrluCtl) / sizeof(double) + 1;
+    prrlu_prepare(j, allow_big);
+    out[0] = j.mode;
+    out[1] = j.shape;
+    out[2] = j.rows;
+    out[3] = j.nblk;
+    out[4] = j.mode == 2 ? coop_capacity()
+                         : (j.mode == 4 ? (j.shape == 8 ? coop_big_capacity<8, 0, false>()
+                                                        : (j.shape == 16 ? coop_big_capacity<16, 0, false>()
+                                                                         : (j.shape == 24
+                                                                                ? coop_big_capacity<16, 8, false>()
+                                                                                : coop_big_capacity<14, 8, true>())))
+                                        : 0);
+    out[5] = coop_big_capacity<16, 8, false>();
+    out[6] = coop_big_capacity<14, 8, true>();
+}
+
+// Enough for every layout prrlu may take for this block (the persistent one and its stepped
+// fallback).
+size_t prrlu_ws_doubles(int m, int n) {
+    size_t best = 0;
+    for (int big = 0; big < 2; ++big) {
+        PrrluJob j{};
+        j.m = m; j.n = n;
+        prrlu_prepare(j, big != 0);
+        best = std::max(best, 2 * (3 * (size_t)j.nblk + (size_t)j.nblk * n) + sizeof(PrrluCtl) / sizeof(double) + 1);
+    }
+    return best;
 }
 
 int prrlu(hipStream_t s, int m, int n, double *A, int rmax, double rel_tol2, int *rowpiv, int *colpiv, double *L,
@@ -2211,7 +2437,17 @@ int prrlu(hipStream_t s, int m, int n, double *A, int rmax, double rel_tol2, int
     j.A = A; j.m = m; j.n = n; j.rmax = rmax; j.rel_tol2 = rel_tol2;
     j.rowpiv = rowpiv; j.colpiv = colpiv; j.L = L; j.info = info; j.ws = ws;
     WTT_REQUIRE(rmax >= 1 && m >= 1 && n >= 1, WENOTT_EINVAL, "pivot search needs a nonempty block and rmax >= 1");
-    prrlu_prepare(j);
+    prrlu_prepare(j, allow_persistent);
+    if (j.mode == 4) {  // large blocks: the whole factorisation in one launch, stripes in registers
+        if (t_begin > 0) return rmax + 2;
+        k_prrlu_mw_init<<<1, kMwThreads, 0, s>>>(j);
+        if (j.shape == 8) k_prrlu_coop_big<8, 0, false><<<j.nblk, kMwThreads, 0, s>>>(j);
+        else if (j.shape == 16) k_prrlu_coop_big<16, 0, false><<<j.nblk, kMwThreads, 0, s>>>(j);
+        else if (j.shape == 24) k_prrlu_coop_big<16, 8, false><<<j.nblk, kMwThreads, 0, s>>>(j);
+        else k_prrlu_coop_big<14, 8, true><<<j.nblk, kMwThreads, 0, s>>>(j);
+        WTT_HIP(hipGetLastError());
+        return rmax + 2;
+    }
     if (j.mode == 0) {
         if (t_begin > 0) return rmax + 1;
         dispatch_tile(s, j.shape, 1, sizeof(double) * (size_t)(m + n), nullptr, m, n, A, rmax, rel_tol2, rowpiv,

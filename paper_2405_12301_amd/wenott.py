@@ -8,6 +8,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import weakref
 
 import numpy as np
 
@@ -24,7 +25,8 @@ EXPORTED = ["wenott_default_opts", "wenott_init", "wenott_rhs", "wenott_rk3_step
             "wenott_dense_rk3_step", "wenott_dense_destroy", "wenott_mlp_nparams", "wenott_mlp_workspace",
             "wenott_mlp_init_params", "wenott_mlp_forward", "wenott_mlp_loss_grad", "wenott_mlp_adam_step",
             "wenott_set_proposal", "wenott_set_cross_logging", "wenott_get_cross_log", "wenott_batch_rk3_step",
-            "wenott_gemm_autotune", "wenott_gemm_autotune_table", "wenott_set_pivot_wait_limit"]
+            "wenott_gemm_autotune", "wenott_gemm_autotune_table", "wenott_set_pivot_wait_limit", "wenott_finalize",
+            "wenott_pivot_layout", "wenott_pivot_search"]
 
 MLP_IN, MLP_HID, MLP_OUT, MLP_RANK_CLASSES, MLP_BINS = 96, 128, 81, 17, 64
 
@@ -95,6 +97,10 @@ def load(path: str = LIB_PATH):
     lib.wenott_current_eps.argtypes = [vp, P(ctypes.c_double)]
     lib.wenott_set_profiling.argtypes = [vp, ctypes.c_int32]
     lib.wenott_set_pivot_wait_limit.argtypes = [ctypes.c_int32]
+    lib.wenott_finalize.argtypes = []
+    lib.wenott_pivot_layout.argtypes = [ctypes.c_int32, ctypes.c_int32, P(ctypes.c_int32)]
+    lib.wenott_pivot_search.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                        ctypes.c_int32, vp, vp, vp, P(ctypes.c_double), vp]
     lib.wenott_last_error.argtypes = [vp]
     lib.wenott_last_error.restype = ctypes.c_char_p
     lib.wenott_destroy.argtypes = [vp]
@@ -121,12 +127,30 @@ def load(path: str = LIB_PATH):
     for name in ("wenott_init", "wenott_rhs", "wenott_rk3_step", "wenott_batch_rk3_step", "wenott_round",
                  "wenott_gemm_autotune", "wenott_gemm_autotune_table", "wenott_to_dense",
                  "wenott_get_state", "wenott_get_info", "wenott_max_wavespeed", "wenott_current_eps",
-                 "wenott_set_profiling", "wenott_set_pivot_wait_limit", "wenott_dense_init", "wenott_dense_max_wavespeed", "wenott_dense_rhs",
+                 "wenott_set_profiling", "wenott_set_pivot_wait_limit", "wenott_finalize", "wenott_pivot_layout",
+                 "wenott_pivot_search",
+                 "wenott_dense_init", "wenott_dense_max_wavespeed", "wenott_dense_rhs",
                  "wenott_dense_rk3_step", "wenott_mlp_init_params", "wenott_mlp_forward", "wenott_mlp_loss_grad",
                  "wenott_mlp_adam_step", "wenott_set_proposal", "wenott_set_cross_logging", "wenott_get_cross_log"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
+    # drain and release the library's cached device blocks and events before the runtime goes
+    import atexit
+    atexit.register(_finalize_at_exit)
     return lib
+
+
+_live = weakref.WeakSet()  # solvers not yet closed (closed at exit before the library finalizes)
+
+
+def _finalize_at_exit():
+    for s in list(_live):
+        try:
+            s.close()
+        except Exception:
+            pass
+    if _lib is not None:
+        _lib.wenott_finalize()
 
 
 class WenottError(RuntimeError):
@@ -271,6 +295,27 @@ def wenott_set_profiling(ctx, on: bool):
     _check(load().wenott_set_profiling(ctx, 1 if on else 0), ctx)
 
 
+def wenott_pivot_search(A, rmax: int, rel_tol2: float, allow_persistent: bool = True):
+    """A: (m, n) float64 CUDA tensor. Returns (rank, rowpiv, colpiv, L (m x rmax tensor), resid2, tol2)."""
+    import torch
+    m, n = A.shape
+    A = A.contiguous()
+    rp = torch.zeros(rmax, dtype=torch.int32, device=A.device)
+    cp = torch.zeros(rmax, dtype=torch.int32, device=A.device)
+    L = torch.zeros((m, rmax), dtype=torch.float64, device=A.device)
+    info = (ctypes.c_double * 3)()
+    _check(load().wenott_pivot_search(_ptr(A), int(m), int(n), int(rmax), float(rel_tol2), 1 if allow_persistent else 0,
+                                      _ptr(rp), _ptr(cp), _ptr(L), info, _stream_handle()), None)
+    r = int(info[0])
+    return r, rp[:r].cpu().numpy(), cp[:r].cpu().numpy(), L, info[1], info[2]
+
+
+def wenott_pivot_layout(m: int, n: int):
+    out = (ctypes.c_int32 * 7)()
+    _check(load().wenott_pivot_layout(int(m), int(n), out), None)
+    return list(out)
+
+
 def wenott_set_pivot_wait_limit(polls: int):
     _check(load().wenott_set_pivot_wait_limit(int(polls)), None)
 
@@ -382,11 +427,13 @@ class Solver:
         self.n = tuple(flow.n)
         self.ncomp = flow.ncomp
         self.ctx = wenott_init(flow.cores, flow.n, flow.lo, flow.hi, flow.gamma, flow.bc, opts, stream)
+        _live.add(self)
 
     def close(self):
         if self.ctx:
             wenott_destroy(self.ctx)
             self.ctx = None
+        _live.discard(self)
 
     def __del__(self):
         try:

@@ -20,3 +20,29 @@ def rel_err(a, b):
     num = max(np.linalg.norm(a[c] - b[c]) for c in range(a.shape[0]))
     den = max(np.linalg.norm(b[c]) for c in range(b.shape[0]))
     return num / den
+
+
+def eps_formula(flow, u, c_eps):
+    """eq. eps-tt-formula in d dimensions, computed here from the densified state u:
+    eps = C_eps V^{1/2} h^{5 - d/2} / max_q ||q||_F with V the domain volume, h the geometric mean
+    of the cell sizes and ||q||_F over the interior cells (the d = 3 case is the paper's h^{7/2})."""
+    d = len(flow.n)
+    vol = float(np.prod([b - a for a, b in zip(flow.lo, flow.hi)]))
+    h = float(np.prod(flow.h)) ** (1.0 / d)
+    qmax = max(np.linalg.norm(u[c]) for c in range(u.shape[0]))
+    return c_eps * vol ** 0.5 * h ** (5.0 - 0.5 * d) / qmax
+
+
+class EpsTracker:
+    """The dynamic eps_TT of a run, computed independently of the library: C_eps is fixed so
+    that the formula gives eps0 on the initial state (the "dynamic from eps0" reading), or
+    given; eps(u) then follows eq. eps-tt-formula on each densified state."""
+
+    def __init__(self, flow, u0, eps0=None, c_eps=None):
+        self.flow = flow
+        if c_eps is None:
+            c_eps = eps0 / eps_formula(flow, u0, 1.0)
+        self.c_eps = c_eps
+
+    def __call__(self, u):
+        return eps_formula(self.flow, u, self.c_eps)

@@ -12,7 +12,7 @@ import pytest
 
 import oracle
 import workloads
-from tests.gpu_util import oracle_problem, rel_err
+from tests.gpu_util import EpsTracker, oracle_problem, rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -180,11 +180,14 @@ def test_blast_batch_full_size_two_states_vs_oracle(W):
     used, and the per-step error is within 10 eps_TT."""
     _say("case: blast batch, 32 states at full size, one batched step")
     flows = [workloads.config4_blast_3d(seed=i) for i in range(32)]
-    solvers = [W.Solver(f, W.default_opts(eps_mode=1, eps0=f.eps0)) for f in flows]
+    # crosses of these states stop at the cross-rank limit of 128 (the joint rank of the five
+    # stacked components is larger) with sampled residuals above eps: an explicit slack
+    solvers = [W.Solver(f, W.default_opts(eps_mode=1, eps0=f.eps0, conv_slack=100.0)) for f in flows]
     try:
         cells = [int(np.prod(f.n)) for f in flows]
         pick = [int(np.argmin(cells)), int(np.argmax(cells))]
         u0 = {i: solvers[i].dense() for i in pick}
+        e_step = {i: EpsTracker(flows[i], u0[i], eps0=flows[i].eps0)(u0[i]) for i in pick}
         dts = [f.cfl * min(f.h) / s.max_wavespeed() for f, s in zip(flows, solvers)]
         W.wenott_batch_rk3_step([s.ctx for s in solvers], dts)
         for i in pick:
@@ -193,8 +196,9 @@ def test_blast_batch_full_size_two_states_vs_oracle(W):
             u = u0[i]
             P.ssprk3(u, dts[i], alphas=[info.alpha[j] for j in range(3)])
             err = rel_err(solvers[i].dense(), u)
-            _say(f"  state {i} n={flows[i].n} ranks={list(info.ranks)[:4]} eps={info.eps:.2e} err={err:.3e}")
-            assert err <= 10 * info.eps, (i, err, info.eps)
+            _say(f"  state {i} n={flows[i].n} ranks={list(info.ranks)[:4]} eps={e_step[i]:.2e} err={err:.3e}")
+            assert abs(info.eps - e_step[i]) <= 1e-10 * e_step[i], (i, info.eps, e_step[i])
+            assert err <= 10 * e_step[i], (i, err, e_step[i])
         for s in solvers:
             assert all(np.isfinite(list(s.info().ranks)[:4]))
     finally:

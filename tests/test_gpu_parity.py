@@ -7,7 +7,7 @@ import pytest
 import oracle
 import workloads
 from oracle import tt_ref
-from tests.gpu_util import dense_of_cores, oracle_problem, rel_err
+from tests.gpu_util import EpsTracker, dense_of_cores, eps_formula, oracle_problem, rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -39,7 +39,7 @@ def assert_rhs_parity(got, Lref, u, P, alpha, eps):
 def test_to_dense_and_alpha_config1(W):
     _say("case: to_dense / alpha, smooth wave 2D 64^2")
     f = workloads.config1_smooth_wave_2d(64)
-    s = W.Solver(f)
+    s = W.Solver(f, W.default_opts(alpha_mode=0))
     try:
         got = s.dense()
         ref = dense_of_cores(f.cores)
@@ -87,7 +87,7 @@ def test_exact_alpha_3d_register_path(W, n):
     the oracle's alpha of the densified state."""
     _say("case: exact alpha 3D smooth wave", n)
     f = workloads.config3_wave_3d(n, seed=0)
-    s = W.Solver(f)
+    s = W.Solver(f, W.default_opts(alpha_mode=0))
     try:
         ref = dense_of_cores(f.cores)
         a = s.max_wavespeed()
@@ -165,17 +165,33 @@ def test_dense_comparator_matches_oracle(W, which):
         W.wenott_dense_destroy(ctx)
 
 
+def step_eps(o, f, u0):
+    """eps_TT of each step computed here, not read from the library: the fixed eps0, or eq.
+    eps-tt-formula on the densified state before the step with C_eps fixed by eps0 on u0 (or the
+    given C_eps)."""
+    if o.eps_mode == 0:
+        return lambda u: o.eps0
+    if o.eps0 > 0:
+        return EpsTracker(f, u0, eps0=o.eps0)
+    return EpsTracker(f, u0, c_eps=o.c_eps)
+
+
 def _step_parity(W, f, eps, nsteps=1, opts=None, tol_factor=10.0, scheme=0, sweeps_out=None):
     """Advance the TT path and the oracle from the same densified state with the same dt and
-    the alphas the TT path used; per-step error in the max_c ||.||_F / max_c ||.||_F norm.
-    sweeps_out, if given, receives each step's per-stage sweep counts."""
+    the alphas the TT path used; per-step error in the max_c ||.||_F / max_c ||.||_F norm,
+    bounded by tol_factor times the eps_TT this test computes itself (and the library's eps is
+    checked against it). sweeps_out, if given, receives each step's per-stage sweep counts."""
     o = opts if opts is not None else W.default_opts(eps0=eps, scheme=scheme)
     s = W.Solver(f, o)
     try:
         P = oracle_problem(f)
         errs = []
+        eps_of = None
         for _ in range(nsteps):
             u = s.dense()
+            if eps_of is None:
+                eps_of = step_eps(o, f, u)
+            e_ind = eps_of(u)
             dt = 0.5 * min(P.h) / P.alpha(u)
             s.step(dt)
             info = s.info()
@@ -185,9 +201,10 @@ def _step_parity(W, f, eps, nsteps=1, opts=None, tol_factor=10.0, scheme=0, swee
             errs.append(e)
             if sweeps_out is not None:
                 sweeps_out.append([info.sweeps[j][0] for j in range(3)])
-            _say("  step err", e, "eps", info.eps, "ranks", list(info.ranks), "sweeps",
+            _say("  step err", e, "eps", e_ind, "ranks", list(info.ranks), "sweeps",
                  [list(r) for r in info.sweeps], "sum ranks", list(info.sum_rank))
-            assert e <= tol_factor * info.eps, (e, info.eps)
+            assert abs(info.eps - e_ind) <= 1e-10 * e_ind, (info.eps, e_ind)
+            assert e <= tol_factor * e_ind, (e, e_ind)
         return errs
     finally:
         s.close()

@@ -318,3 +318,104 @@ def test_maxvol_brute_force_is_dominant():
         assert tt_ref.maxvol_dominant(a, rows)
         # a different subset with a smaller volume is not dominant in general
         assert vol > 0
+
+
+# --- transmissive boundary after a wave has left the domain (reading C8) --------------
+@pytest.mark.parametrize("side", ["high", "low"])
+def test_transmissive_outflow_after_the_shock_leaves(side):
+    """Sod run to t = 0.32: the right-moving shock (speed 1.752) left x = 1 at t = 0.285, the
+    rarefaction head (speed -1.183) has not reached x = 0. Zero-order extrapolation lets the
+    shock out: the whole domain stays within first-order discretisation error of the exact
+    solution on the infinite line, also next to the boundary it crossed. A periodic ghost map
+    would bring the other side's state in at t = 0 and a reflecting one would send a reflected
+    shock back (an O(0.5) density error next to the wall). side = "low" mirrors the problem."""
+    L, R = (1.0, 0.0, 1.0), (0.125, 0.0, 0.1)
+    N, t = 400, 0.32
+    P = oracle.Problem((N,), (0.0,), (1.0,), (oracle.BC_TRANSMISSIVE,))
+    x = P.centers(0)
+    high = side == "high"
+    left = x < 0.5 if high else x >= 0.5
+    U = np.stack([np.where(left, 1.0, 0.125), 0 * x, np.where(left, 1.0, 0.1) / 0.4]).copy()
+    P.run(U, t, cfl=0.5)
+    xi = (x - 0.5) / t if high else (0.5 - x) / t
+    rho_ex = riemann.sample(L, R, xi)[0]
+    near = x >= 0.95 if high else x <= 0.05
+    assert riemann.star_state(L, R)[1] > 0 and 0.5 + 1.7522 * 0.285 > 1.0 - 1e-3
+    assert float(np.mean(np.abs(U[0] - rho_ex))) < 2.5e-3
+    assert float(np.max(np.abs(U[0] - rho_ex)[near])) < 1e-2
+    # the outflow state next to the boundary is the post-shock one (rho* = 0.2656)
+    assert abs(U[0][-1 if high else 0] - 0.2656) < 5e-3
+
+
+# --- the independent eps_TT of the GPU tests (eq. eps-tt-formula) ----------------------
+def test_eps_formula_helper_hand_values():
+    """eps = C V^{1/2} h^{5 - d/2} / max_q ||q||_F on a constant state, worked by hand:
+    3D ones on 8^3 cells of [0,2]^3: V = 8, h = 1/4, ||q|| = sqrt(512), so eps = C sqrt(8) 2^-7 /
+    sqrt(512) = C / 1024; 2D ones on 16 x 4 cells of [0,1] x [0,4]: h = (1/16 * 1)^(1/2) = 1/4,
+    V = 4, ||q|| = 8, eps = C * 2 * 4^-4 / 8 = C / 1024."""
+    import dataclasses
+
+    import workloads
+    from tests.gpu_util import EpsTracker, eps_formula
+    f3 = dataclasses.replace(workloads.random_positive_tt((8, 8, 8), 2, seed=0), lo=(0.0,) * 3, hi=(2.0,) * 3)
+    u3 = np.ones((5, 8, 8, 8))
+    assert abs(eps_formula(f3, u3, 3.0) - 3.0 / 1024) < 1e-17
+    f2 = dataclasses.replace(workloads.random_positive_tt((16, 4), 2, seed=0), lo=(0.0, 0.0), hi=(1.0, 4.0))
+    u2 = np.ones((4, 16, 4))
+    u2[3] *= 0.5  # the largest component norm counts
+    assert abs(eps_formula(f2, u2, 5.0) - 5.0 / 1024) < 1e-17
+    tr = EpsTracker(f2, u2, eps0=1e-6)
+    assert abs(tr(u2) - 1e-6) < 1e-21 and abs(tr(2.0 * u2) - 0.5e-6) < 1e-21
+
+
+# --- the tilted Sod workload: its exact solution and its initial TT ---------------------
+def test_workload_exact_sod_matches_the_oracle_riemann_solver():
+    """The benchmark's L1 reference (workloads.sod_exact_rho, its own wave-curve solver) against
+    the oracle's exact Riemann solver on the same similarity variable, through all five regions."""
+    import workloads
+    s = np.linspace(-0.6, 0.6, 4801)
+    for t in (0.05, 0.2):
+        a = workloads.sod_exact_rho(s, t)
+        b = riemann.sample((1.0, 0.0, 1.0), (0.125, 0.0, 0.1), s / t)[0]
+        assert np.max(np.abs(a - b)) < 1e-13
+
+
+@pytest.mark.parametrize("seed", [0, 2, 4])
+def test_tilted_sod_initial_tt_is_exact(seed):
+    """The initial TT of the tilted Sod workload equals the sampled step field cell by cell, and
+    its ranks are the number of distinct step rows, about N tan(theta) + 1."""
+    import workloads
+    n = 64
+    f = workloads.config5_tilted_sod_3d(n, seed=seed)
+    rho = tt_ref.tt_full(f.cores[0])
+    ene = tt_ref.tt_full(f.cores[4])
+    ex = f.exact_rho(1e-12)  # t -> 0: the initial step
+    assert np.array_equal(np.unique(rho.round(12)), np.array([0.125, 1.0]))
+    assert np.max(np.abs(rho - ex)) < 1e-12
+    assert np.max(np.abs(ene - np.where(rho > 0.5, 2.5, 0.25))) < 1e-12
+    for c in (1, 2, 3):
+        assert np.max(np.abs(tt_ref.tt_full(f.cores[c]))) == 0.0
+    theta = math.radians(float(f.note.split("theta ")[1].split(" deg")[0]))
+    r = max(g.shape[2] for g in f.cores[0][:-1])
+    assert r <= n * math.tan(theta) + 2
+
+
+# --- the cross's pivot rule (complete pivoting, Sec. 3.3) -------------------------------
+@pytest.mark.parametrize("shape,rank", [((12, 9), 3), ((40, 25), 7), ((30, 30), 30)])
+def test_full_pivot_lu_recovers_low_rank_and_bounds_l(shape, rank):
+    """The oracle's pivot rule on exactly low-rank matrices: it stops at the exact rank, the
+    skeleton A(:, J) A(I, J)^{-1} A(I, :) reproduces A, every entry of L is at most 1 in
+    magnitude (complete pivoting), and the first pivot is the largest entry of A."""
+    rng = np.random.default_rng(rank)
+    A = rng.normal(size=(shape[0], rank)) @ rng.normal(size=(rank, shape[1]))
+    r, rows, cols, L, s2 = tt_ref.full_pivot_lu(A, 1e-26, min(shape))
+    assert r == rank
+    skel = A[:, cols] @ np.linalg.solve(A[np.ix_(rows, cols)], A[rows, :])
+    assert np.max(np.abs(skel - A)) <= 1e-10 * np.max(np.abs(A))
+    assert np.max(np.abs(L)) <= 1.0 + 1e-12
+    assert divmod(int(np.argmax(np.abs(A))), shape[1]) == (rows[0], cols[0])
+    # L L(I, :)^{-1} is the interpolative basis of the cross: A = L L(I, :)^{-1} A(I, :), and
+    # L(I, :) is unit lower triangular in pivot order
+    LI = L[rows, :]
+    assert np.allclose(np.diag(LI), 1.0) and np.max(np.abs(np.triu(LI, 1))) <= 1e-12
+    assert np.max(np.abs(L @ np.linalg.solve(LI, A[rows, :]) - A)) <= 1e-10 * np.max(np.abs(A))
