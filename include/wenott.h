@@ -236,6 +236,18 @@ wenott_status wenott_get_info(wenott_ctx *ctx, wenott_info *info);
  * an evaluated cell (every cell in mode 0). */
 wenott_status wenott_max_wavespeed(wenott_ctx *ctx, double *alpha);
 
+/* wenott_max_wavespeed without any allocation, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * kernels and the same result as wenott_max_wavespeed, with their workspace in a static device
+ * array of 1 MiB per GPU (held until the process ends) instead of the context's cache. It calls
+ * no hipMalloc, hipFree or allocating library routine. Supported: alpha_mode 1 (any grid; about
+ * 16 KB of workspace) and the exact alpha (alpha_mode 0 or 2) of 2D states whose per-workgroup
+ * partial maxima fit the array; anything larger is rejected with EINVAL. Every call on one GPU
+ * shares that GPU's array, which keeps the last call's contents (every entry a call reads it has
+ * written first, so nothing needs clearing): calls that overlap on one GPU, on any contexts or
+ * streams, race. Synchronises; the first stage of the next step reuses the value. */
+wenott_status wenott_max_wavespeed_noalloc(wenott_ctx *ctx, double *alpha);
+
 /* Current eps_TT of the dynamic rule (eq. eps-tt-formula) or the fixed one. */
 wenott_status wenott_current_eps(wenott_ctx *ctx, double *eps);
 

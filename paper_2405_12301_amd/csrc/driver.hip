@@ -262,8 +262,30 @@ struct ISet {  // a set of multi-indices of a fixed length
 
 }  // namespace
 
+// Device workspace of wenott_max_wavespeed_noalloc: a file-scope array, one copy per GPU, held
+// until the process ends. Its device address is taken once per device (at the first wenott_init
+// on that device) with hipGetSymbolAddress; host code only ever uses that address.
+constexpr size_t kNoAllocBytes = size_t(1) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+void *g_noalloc_ptr[kMaxDevices] = {};
+
+// The address of this device's copy of scratch (obtained on the first call per device).
+void *noalloc_scratch_of(int dev) {
+    WTT_REQUIRE(dev >= 0 && dev < kMaxDevices, WENOTT_EINVAL, "device index out of range");
+    std::lock_guard<std::mutex> g(g_noalloc_mu);
+    if (!g_noalloc_ptr[dev]) {
+        void *p = nullptr;
+        WTT_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        g_noalloc_ptr[dev] = p;
+    }
+    return g_noalloc_ptr[dev];
+}
+
 struct wenott_ctx {
     int d = 0, nc = 0;
+    void *noalloc_ws = nullptr;  // this device's copy of scratch
     int N[kMaxDim] = {};
     double lo[kMaxDim] = {}, hi[kMaxDim] = {}, h[kMaxDim] = {};
     double gamma = 1.4;
@@ -2072,6 +2094,11 @@ wenott_status wenott_init(wenott_ctx **out, const wenott_tt *state, const wenott
             c->bc[k] = bc[2 * k];
         }
         c->s = (hipStream_t)hip_stream;
+        {
+            int dev = 0;
+            WTT_HIP(hipGetDevice(&dev));
+            c->noalloc_ws = noalloc_scratch_of(dev);
+        }
         c->sc.s = c->s;
         WTT_HIP(hipEventCreateWithFlags(&c->ev_wait, hipEventDisableTiming));
         c->ring.init(c->s, 8u << 20);
@@ -2485,6 +2512,47 @@ wenott_status wenott_max_wavespeed(wenott_ctx *c, double *alpha) {
     return run_guarded(c, [&] {
         *alpha = alpha_now(c, c->U);
         c->alpha_cache = *alpha;  // the first stage of the next step reuses it
+        c->alpha_cache_valid = *alpha > 0.0;
+    });
+}
+
+wenott_status wenott_max_wavespeed_noalloc(wenott_ctx *c, double *alpha) {
+    if (!c || !alpha) return WENOTT_EINVAL;
+    return run_guarded(c, [&] {
+        const TT &U = c->U;
+        char *ws = (char *)c->noalloc_ws;
+        WTT_REQUIRE(ws != nullptr, WENOTT_EHIP, "no device workspace");
+        double *dst = c->d_status + kStatusAlpha + 3;
+        if (c->o.alpha_mode == 1) {
+            const size_t ni = alpha_search_ints(U.d, U.N[1]), nd = alpha_search_doubles(U.d, U.N[1]);
+            const size_t off = (ni * sizeof(int) + 255) / 256 * 256;
+            WTT_REQUIRE(off + nd * sizeof(double) <= kNoAllocBytes, WENOTT_EINVAL, "alpha search workspace too large");
+            int ranks[kMaxDim + 1];
+            const double *cores[kMaxDim];
+            for (int k = 0; k <= U.d; ++k) ranks[k] = U.R[k];
+            for (int k = 0; k < U.d; ++k) cores[k] = U.core[k];
+            const unsigned long long seed = c->o.seed * 0x9E3779B97F4A7C15ULL + 0xA5A5ULL * (++c->alpha_counter);
+            alpha_search(c->s, U.d, U.N, cores, ranks, c->gamma, seed, c->d_best, (int *)ws, (double *)(ws + off), dst,
+                         c->d_flags);
+        } else {
+            // the exact maximum over every cell: in 2D the left part of a cell is its first core, so
+            // the only workspace is one partial maximum per workgroup
+            WTT_REQUIRE(U.d == 2, WENOTT_EINVAL,
+                        "the exact alpha of a 3D state needs a left-part workspace beyond the static limit; use "
+                        "alpha_mode 1 or wenott_max_wavespeed");
+            const long long nrows = U.N[0];
+            const int nblocks = dense_eval_blocks(1, nrows, U.R[1], U.N[1]);
+            WTT_REQUIRE((size_t)nblocks * sizeof(double) <= kNoAllocBytes, WENOTT_EINVAL,
+                        "grid too large for the static workspace of the exact alpha");
+            dense_eval(c->s, 1, U.d, U.nc, nrows, U.R[1], U.N[1], U.core[0], U.cstride(0), U.core[1], U.cstride(1),
+                       c->gamma, nullptr, (double *)ws, nblocks, c->d_flags);
+            reduce_max_dev(c->s, (double *)ws, nblocks, dst);
+        }
+        status_readback(c, kStatusAlpha + 4);
+        host_wait(c);
+        raise_flags(c, status_flags(c));
+        *alpha = status_alpha(c, 3);
+        c->alpha_cache = *alpha;
         c->alpha_cache_valid = *alpha > 0.0;
     });
 }

@@ -26,7 +26,7 @@ EXPORTED = ["wenott_default_opts", "wenott_init", "wenott_rhs", "wenott_rk3_step
             "wenott_mlp_init_params", "wenott_mlp_forward", "wenott_mlp_loss_grad", "wenott_mlp_adam_step",
             "wenott_set_proposal", "wenott_set_cross_logging", "wenott_get_cross_log", "wenott_batch_rk3_step",
             "wenott_gemm_autotune", "wenott_gemm_autotune_table", "wenott_set_pivot_wait_limit", "wenott_finalize",
-            "wenott_pivot_layout", "wenott_pivot_search"]
+            "wenott_pivot_layout", "wenott_pivot_search", "wenott_max_wavespeed_noalloc"]
 
 MLP_IN, MLP_HID, MLP_OUT, MLP_RANK_CLASSES, MLP_BINS = 96, 128, 81, 17, 64
 
@@ -94,6 +94,7 @@ def load(path: str = LIB_PATH):
     lib.wenott_get_state.argtypes = [vp, P(wenott_tt)]
     lib.wenott_get_info.argtypes = [vp, P(wenott_info)]
     lib.wenott_max_wavespeed.argtypes = [vp, P(ctypes.c_double)]
+    lib.wenott_max_wavespeed_noalloc.argtypes = [vp, P(ctypes.c_double)]
     lib.wenott_current_eps.argtypes = [vp, P(ctypes.c_double)]
     lib.wenott_set_profiling.argtypes = [vp, ctypes.c_int32]
     lib.wenott_set_pivot_wait_limit.argtypes = [ctypes.c_int32]
@@ -126,7 +127,8 @@ def load(path: str = LIB_PATH):
     lib.wenott_get_cross_log.argtypes = [vp, vp, vp, vp, ctypes.c_int32, P(ctypes.c_int32)]
     for name in ("wenott_init", "wenott_rhs", "wenott_rk3_step", "wenott_batch_rk3_step", "wenott_round",
                  "wenott_gemm_autotune", "wenott_gemm_autotune_table", "wenott_to_dense",
-                 "wenott_get_state", "wenott_get_info", "wenott_max_wavespeed", "wenott_current_eps",
+                 "wenott_get_state", "wenott_get_info", "wenott_max_wavespeed", "wenott_max_wavespeed_noalloc",
+                 "wenott_current_eps",
                  "wenott_set_profiling", "wenott_set_pivot_wait_limit", "wenott_finalize", "wenott_pivot_layout",
                  "wenott_pivot_search",
                  "wenott_dense_init", "wenott_dense_max_wavespeed", "wenott_dense_rhs",
@@ -282,6 +284,12 @@ def wenott_get_info(ctx) -> wenott_info:
 def wenott_max_wavespeed(ctx) -> float:
     a = ctypes.c_double()
     _check(load().wenott_max_wavespeed(ctx, ctypes.byref(a)), ctx)
+    return a.value
+
+
+def wenott_max_wavespeed_noalloc(ctx) -> float:
+    a = ctypes.c_double()
+    _check(load().wenott_max_wavespeed_noalloc(ctx, ctypes.byref(a)), ctx)
     return a.value
 
 
