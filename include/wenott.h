@@ -46,6 +46,13 @@ typedef enum {
  * realised as index maps of the ghost cells, never as stored ghost slices. */
 typedef enum { WENOTT_BC_PERIODIC = 0, WENOTT_BC_TRANSMISSIVE = 1 } wenott_bc;
 
+/* The conservation law the state obeys. EULER: the compressible Euler system with the ideal-gas
+ * law (Sec. 2.1), ncomp = ndim + 2 (rho, momenta, total energy). The two scalar laws of Sec. 5.1
+ * and 5.2, one component, unit velocity along every axis: LINADV u_t + sum_d u_{x_d} = 0
+ * (f_d(u) = u, alpha = 1), BURGERS u_t + sum_d (u^2/2)_{x_d} = 0 (f_d(u) = u^2/2, alpha =
+ * max |u|). The scalar laws run in scheme 0 without the learned proposal; gamma is not used. */
+typedef enum { WENOTT_LAW_EULER = 0, WENOTT_LAW_LINADV = 1, WENOTT_LAW_BURGERS = 2 } wenott_law;
+
 /* Uniform cell-centred grid: ndim in {2, 3}; n[d] interior cells; box [lo, hi]. */
 typedef struct {
     int32_t ndim;
@@ -55,7 +62,8 @@ typedef struct {
     double hi[3];
 } wenott_grid;
 
-/* A list of ncomp tensor trains (one per conserved variable, ncomp = ndim + 2).
+/* A list of ncomp tensor trains (one per conserved variable: ncomp = ndim + 2 for the Euler
+ * law, 1 for a scalar law).
  * ranks:  host array [ncomp][ndim + 1]; ranks[c][0] = ranks[c][ndim] = 1.
  * cores:  host array of ncomp * ndim pointers; cores[c * ndim + k] points to the
  *         (ranks[c][k], N_k, ranks[c][k+1]) FP64 core, on the host (on_device = 0) or
@@ -104,6 +112,13 @@ typedef struct {
     double conv_slack;  /* a cross is accepted when its sampled relative residual is <= eps; one whose
                            residual is still above conv_slack * eps after max_sweeps sweeps fails the
                            call with ENOCONV (and the state is left unchanged). >= 1 [1] */
+    int32_t law;        /* the conservation law (wenott_law) [WENOTT_LAW_EULER] */
+    int32_t pad_;
+    double cross_ratio; /* eps_cross / eps_TT, in (0, 1]: the crosses stop their pivot searches and
+                           accept their sampled residuals at cross_ratio * eps_TT while the roundings
+                           keep eps_TT. 1 is the paper's eps_cross = eps_TT (Sec. 5); below 1 the
+                           crosses keep the singular directions just under eps_TT and the rounding
+                           truncates them optimally (SVD) instead of the cross's interpolation [1] */
 } wenott_opts;
 
 /* Per-call diagnostics, filled by wenott_get_info. */
@@ -149,7 +164,8 @@ void wenott_default_opts(wenott_opts *o);
  *   out:    receives the context.
  *   state:  the initial TT list (Sec. 4.1: U_TT = {rho_TT, (rho u)_TT, ..., (rho E)_TT}).
  *   grid:   the cell-centred grid; state mode sizes must equal grid.n.
- *   gamma:  ratio of specific heats (Sec. 2.1), > 1.
+ *   gamma:  ratio of specific heats (Sec. 2.1), > 1 (Euler law; not used by the scalar laws).
+ *   The law comes from opts->law; state->ncomp must be its component count.
  *   bc:     6 entries, bc[2*d + side] (side 0 = low, 1 = high); both sides of a dimension
  *           must agree in this build.
  *   opts:   NULL for defaults.
@@ -230,8 +246,9 @@ wenott_status wenott_get_state(wenott_ctx *ctx, wenott_tt *view);
 wenott_status wenott_get_info(wenott_ctx *ctx, wenott_info *info);
 
 /* max over the grid of |u| + a for the current state (the alpha of eq. lax-friedrichs as
- * defined for the Euler system in Sec. 4.2), for the caller's dt = lambda h / alpha
- * (eq. cfl-other): exact with alpha_mode 0 or 2, the line-search estimate with alpha_mode 1.
+ * defined for the Euler system in Sec. 4.2; max |u| for Burgers, 1 for linear advection), for
+ * the caller's dt = lambda h / alpha (eq. cfl-other): exact with alpha_mode 0 or 2, the
+ * line-search estimate with alpha_mode 1.
  * The first stage of the next step reuses it. Synchronises. ENONPHYS if rho <= 0 or p <= 0 at
  * an evaluated cell (every cell in mode 0). */
 wenott_status wenott_max_wavespeed(wenott_ctx *ctx, double *alpha);

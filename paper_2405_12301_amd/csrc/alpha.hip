@@ -36,9 +36,11 @@ __device__ inline void amax_pair(double &v, int &i, double ov, int oi) {
     if (ov > v || (ov == v && oi < i)) { v = ov; i = oi; }
 }
 
-// |u| + a of a cell from its conserved values; 0 (and ok = false) for a non-physical cell.
-template <int ND>
-__device__ inline double cell_speed(const double (&q)[ND + 2], double gamma, bool &ok) {
+// Wave speed of a cell from its conserved values: |u| + a for the Euler law, 0 (and ok = false)
+// for a non-physical cell; |u| for Burgers (|f'(u)| of f = u^2 / 2).
+template <int ND, int LW>
+__device__ inline double cell_speed(const double *q, double gamma, bool &ok) {
+    if (LW == kLawBurgers) return fabs(q[0]);
     constexpr int NC = ND + 2;
     const double rho = q[0];
     double u2 = 0.0;
@@ -56,12 +58,12 @@ __device__ inline double cell_speed(const double (&q)[ND + 2], double gamma, boo
 // mode 0, R_{d-1} for the last mode), so each cell of the line is one dot product with a row
 // (mode 0) or a column (last mode) of its core. Candidate pt * ND + dd receives the line's largest
 // value and its cell; a mode outside mode_mask (or the middle mode) writes -1.
-template <int ND>
+template <int ND, int LW>
 __global__ __launch_bounds__(kLineThreads) void k_alpha_outer(LineCores T, double gamma, int npts,
                                                               const int *__restrict__ pts, int mode_mask,
                                                               double *__restrict__ cval, int *__restrict__ ccell,
                                                               int *__restrict__ flags) {
-    constexpr int NC = ND + 2;
+    constexpr int NC = LawNC<ND, LW>::v;
     extern __shared__ double vec[];  // [NC][R] partial products of the other cores
     __shared__ double wv[kLineThreads / kWave];
     __shared__ int wi[kLineThreads / kWave];
@@ -135,7 +137,7 @@ __global__ __launch_bounds__(kLineThreads) void k_alpha_outer(LineCores T, doubl
             }
             q[c] = acc0 + acc1;
         }
-        const double sp = cell_speed<ND>(q, gamma, ok);
+        const double sp = cell_speed<ND, LW>(q, gamma, ok);
         if (sp > best) { best = sp; bi = i; }
     }
     for (int off = kWave / 2; off > 0; off >>= 1) {
@@ -160,11 +162,12 @@ __global__ __launch_bounds__(kLineThreads) void k_alpha_outer(LineCores T, doubl
 // (cell, component), its lanes over the right rank index so that the row reads of the slice are
 // contiguous; the chunk's maximum and its cell are candidate pt * nchunk + chunk.
 constexpr int kMidCells = 16;
+template <int LW>
 __global__ __launch_bounds__(kLineThreads) void k_alpha_mid(LineCores T, double gamma, int npts,
                                                             const int *__restrict__ pts, int nchunk,
                                                             double *__restrict__ cval, int *__restrict__ ccell,
                                                             int *__restrict__ flags) {
-    constexpr int NC = 5;
+    constexpr int NC = LawNC<3, LW>::v;
     extern __shared__ double sm[];  // l [NC][R1], r [NC][R2]
     __shared__ double qv[kMidCells][NC];
     const int pt = blockIdx.x, chunk = blockIdx.y, tid = threadIdx.x, lane = tid % kWave, w = tid / kWave;
@@ -215,7 +218,7 @@ __global__ __launch_bounds__(kLineThreads) void k_alpha_mid(LineCores T, double 
             double q[NC];
 #pragma unroll
             for (int c = 0; c < NC; ++c) q[c] = qv[tid][c];
-            best = cell_speed<3>(q, gamma, ok);
+            best = cell_speed<3, LW>(q, gamma, ok);
             bi = j0 + tid;
         }
         for (int off = kWave / 2; off > 0; off >>= 1) {
@@ -307,9 +310,11 @@ size_t alpha_search_ints(int d, int n1) {
 }
 size_t alpha_search_doubles(int d, int n1) { return alpha_cands(d, kAlphaStartCells, n1) + 64; }
 
-void alpha_search(hipStream_t s, int d, const int *n, const double *const *cores, const int *ranks, double gamma,
-                  unsigned long long seed, int *best, int *wsi, double *wsd, double *alpha, int *flags) {
-    WTT_REQUIRE(d == 2 || d == 3, WENOTT_EINVAL, "alpha search needs 2 or 3 dimensions");
+namespace {
+
+template <int LW>
+void alpha_search_t(hipStream_t s, int d, const int *n, const double *const *cores, const int *ranks, double gamma,
+                    unsigned long long seed, int *best, int *wsi, double *wsd, double *alpha, int *flags) {
     LineCores T{};
     for (int k = 0; k <= d; ++k) T.R[k] = ranks[k];
     for (int k = 0; k < d; ++k) {
@@ -317,8 +322,9 @@ void alpha_search(hipStream_t s, int d, const int *n, const double *const *cores
         T.N[k] = n[k];
         T.cs[k] = (long long)ranks[k] * n[k] * ranks[k + 1];
     }
-    const size_t lds_outer = sizeof(double) * (size_t)(d + 2) * std::max(ranks[1], ranks[d - 1]);
-    const size_t lds_mid = d == 3 ? sizeof(double) * 5 * (size_t)(ranks[1] + ranks[2]) : 0;
+    const size_t nc = d == 2 ? LawNC<2, LW>::v : LawNC<3, LW>::v;
+    const size_t lds_outer = sizeof(double) * nc * std::max(ranks[1], ranks[d - 1]);
+    const size_t lds_mid = d == 3 ? sizeof(double) * nc * (size_t)(ranks[1] + ranks[2]) : 0;
     WTT_REQUIRE(lds_outer <= 60 * 1024 && lds_mid <= 60 * 1024, WENOTT_EINVAL, "ranks too large for the alpha search");
     const int M = kAlphaStartCells, K = kAlphaKeep, KM = kAlphaMiddleLines;
     const int nchunk = d == 3 ? alpha_mid_chunks(n[1]) : 0;
@@ -334,15 +340,15 @@ void alpha_search(hipStream_t s, int d, const int *n, const double *const *cores
         const int nmid = std::min(npts, KM);
         const int ncand = npts * d + (d == 3 ? nmid * nchunk : 0);
         if (d == 2) {
-            k_alpha_outer<2><<<dim3(npts, 2), kLineThreads, lds_outer, s>>>(T, gamma, npts, cur, outer, cval, ccell,
-                                                                          flags);
+            k_alpha_outer<2, LW><<<dim3(npts, 2), kLineThreads, lds_outer, s>>>(T, gamma, npts, cur, outer, cval,
+                                                                              ccell, flags);
             k_alpha_select<2><<<1, kSelectThreads, sizeof(double) * (size_t)ncand, s>>>(ncand, cval, ccell, K, nxt,
                                                                                      best, alpha, round > 0);
         } else {
-            k_alpha_outer<3><<<dim3(npts, 3), kLineThreads, lds_outer, s>>>(T, gamma, npts, cur, outer, cval, ccell,
-                                                                          flags);
-            k_alpha_mid<<<dim3(nmid, nchunk), kLineThreads, lds_mid, s>>>(T, gamma, nmid, cur, nchunk,
-                                                                         cval + npts * 3, ccell + npts * 9, flags);
+            k_alpha_outer<3, LW><<<dim3(npts, 3), kLineThreads, lds_outer, s>>>(T, gamma, npts, cur, outer, cval,
+                                                                              ccell, flags);
+            k_alpha_mid<LW><<<dim3(nmid, nchunk), kLineThreads, lds_mid, s>>>(T, gamma, nmid, cur, nchunk,
+                                                                             cval + npts * 3, ccell + npts * 9, flags);
             k_alpha_select<3><<<1, kSelectThreads, sizeof(double) * (size_t)ncand, s>>>(ncand, cval, ccell, K, nxt,
                                                                                      best, alpha, round > 0);
         }
@@ -350,6 +356,16 @@ void alpha_search(hipStream_t s, int d, const int *n, const double *const *cores
         cur = nxt;
     }
     WTT_HIP(hipGetLastError());
+}
+
+}  // namespace
+
+void alpha_search(hipStream_t s, int d, int law, const int *n, const double *const *cores, const int *ranks,
+                  double gamma, unsigned long long seed, int *best, int *wsi, double *wsd, double *alpha, int *flags) {
+    WTT_REQUIRE(d == 2 || d == 3, WENOTT_EINVAL, "alpha search needs 2 or 3 dimensions");
+    WTT_REQUIRE(law == kLawEuler || law == kLawBurgers, WENOTT_EINVAL, "alpha search: no search for this law");
+    if (law == kLawEuler) alpha_search_t<kLawEuler>(s, d, n, cores, ranks, gamma, seed, best, wsi, wsd, alpha, flags);
+    else alpha_search_t<kLawBurgers>(s, d, n, cores, ranks, gamma, seed, best, wsi, wsd, alpha, flags);
 }
 
 }  // namespace wtt

@@ -180,8 +180,18 @@ void chol_upper_inv_batch(hipStream_t s, int njobs, int ncomp, int rmax, const C
 void interp_solve(hipStream_t s, int m, int r, const double *L, int ldl, const int *rowpiv, double *X);
 
 // ------------------------------------------------------------------ fiber.hip
+// Conservation laws the fiber kernels evaluate: the Euler system (Sec. 2.1, d + 2 components)
+// and the two scalar laws of Sec. 5.1-5.2 with unit velocity along every axis, linear advection
+// f_dir(u) = u and Burgers f_dir(u) = u^2 / 2 (one component).
+enum { kLawEuler = 0, kLawLinAdv = 1, kLawBurgers = 2 };
+template <int ND, int LW>
+struct LawNC {
+    static constexpr int v = LW == kLawEuler ? ND + 2 : 1;
+};
+
 struct FiberGeom {
     int d, ncomp, dir, k;       // dimension, components, flux direction, free core
+    int law;                    // kLawEuler / kLawLinAdv / kLawBurgers
     int n[kMaxDim];             // cells per dimension
     int bc[kMaxDim];            // boundary code per dimension
     double gamma, alpha, eps_w; // EOS, LF alpha, WENO epsilon (h_dir^2)
@@ -268,18 +278,20 @@ void weno_block(hipStream_t s, const FiberGeom &g, int p, int q, const T *W, dou
                 long long sb, long long sc, int *flags);
 
 // Dense evaluation of a TT list from the left part Lm[c] ((prod of N_0..N_{d-2}) x R) and the
-// last cores G[c] (R x N_{d-1}): mode 0 writes out[c][cell]; mode 1 reduces max(|u|+a) into
-// partial[block] and raises flags on non-physical cells. nblocks must be
-// dense_eval_blocks(mode, nrows, R, nlast), the number of partials mode 1 writes.
+// last cores G[c] (R x N_{d-1}): mode 0 writes out[c][cell]; mode 1 reduces the cell wave speed
+// (|u| + a for the Euler law, |u| for Burgers) into partial[block] and raises flags on
+// non-physical cells. nblocks must be dense_eval_blocks(mode, nrows, R, nlast), the number of
+// partials mode 1 writes. law: kLawEuler or kLawBurgers for mode 1, any law for mode 0.
 int dense_eval_blocks(int mode, long long nrows, int R, int nlast);
-void dense_eval(hipStream_t s, int mode, int d, int ncomp, long long nrows, int R, int nlast, const double *Lm,
+void dense_eval(hipStream_t s, int mode, int d, int law, long long nrows, int R, int nlast, const double *Lm,
                 long long lm_stride, const double *G, long long g_stride, double gamma, double *out, double *partial,
                 int nblocks, int *flags);
 void reduce_max_dev(hipStream_t s, const double *partial, int n, double *dst);
 
 // ------------------------------------------------------------------ alpha.hip
-// Estimated max over the grid of |u| + a of a TT state (ndim + 2 components, cores[k] the
-// [c][R_k][N_k][R_{k+1}] core of every component, ranks common): a search along grid lines
+// Estimated max over the grid of the cell wave speed of a TT state (|u| + a for the Euler law,
+// ndim + 2 components; |u| for Burgers, one component; cores[k] the [c][R_k][N_k][R_{k+1}] core
+// of every component, ranks common): a search along grid lines
 // through kAlphaStartCells seeded cells and the previous best cell (best: device int[d], in/out,
 // best[0] < 0 for none), then kAlphaRounds - 1 rounds along every mode through the kAlphaKeep
 // best cells. Writes the estimate to the device scalar alpha; raises kFlagNonPhys in flags for a
@@ -288,8 +300,8 @@ void reduce_max_dev(hipStream_t s, const double *partial, int n, double *dst);
 constexpr int kAlphaStartCells = 256, kAlphaKeep = 16, kAlphaMiddleLines = 4, kAlphaRounds = 3;
 size_t alpha_search_ints(int d, int n1);
 size_t alpha_search_doubles(int d, int n1);
-void alpha_search(hipStream_t s, int d, const int *n, const double *const *cores, const int *ranks, double gamma,
-                  unsigned long long seed, int *best, int *wsi, double *wsd, double *alpha, int *flags);
+void alpha_search(hipStream_t s, int d, int law, const int *n, const double *const *cores, const int *ranks,
+                  double gamma, unsigned long long seed, int *best, int *wsi, double *wsd, double *alpha, int *flags);
 
 // Sampled residual of a flux TT at random points (face index on mode dir).
 void sample_residual(hipStream_t s, const FiberGeom &g, const double *const *ucores, const int *ranks, int npts,

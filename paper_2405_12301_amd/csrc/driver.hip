@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <functional>
 #include <map>
@@ -285,6 +286,7 @@ void *noalloc_scratch_of(int dev) {
 
 struct wenott_ctx {
     int d = 0, nc = 0;
+    int law = 0;                 // wenott_law
     void *noalloc_ws = nullptr;  // this device's copy of scratch
     int N[kMaxDim] = {};
     double lo[kMaxDim] = {}, hi[kMaxDim] = {}, h[kMaxDim] = {};
@@ -440,6 +442,11 @@ constexpr int kPinNorms = 4080;
 // stage cross makes one: its sampled residual).
 double *alpha_launch(wenott_ctx *c, const TT &U, int slot, bool readback = true) {
     double *dst = c->d_status + kStatusAlpha + slot;
+    if (c->law == WENOTT_LAW_LINADV) {  // f'(u) = 1 along every axis
+        fill(c->s, dst, 1, 1.0);
+        if (readback) status_readback(c, kStatusAlpha + 4);
+        return dst;
+    }
     if (c->o.alpha_mode == 1) {  // line search (the tt_max_abs estimate of eq. cfl-other)
         int ranks[kMaxDim + 1];
         const double *cores[kMaxDim];
@@ -448,7 +455,7 @@ double *alpha_launch(wenott_ctx *c, const TT &U, int slot, bool readback = true)
         // its own counter: the cross's random sets follow the same sequence whether or not the
         // caller asked for alpha in between
         const unsigned long long seed = c->o.seed * 0x9E3779B97F4A7C15ULL + 0xA5A5ULL * (++c->alpha_counter);
-        alpha_search(c->s, U.d, U.N, cores, ranks, c->gamma, seed, c->d_best,
+        alpha_search(c->s, U.d, c->law, U.N, cores, ranks, c->gamma, seed, c->d_best,
                      c->sc.get<int>(S_AL_I, alpha_search_ints(U.d, U.N[1])),
                      c->sc.get<double>(S_AL_D, alpha_search_doubles(U.d, U.N[1])),
                      dst, c->d_flags);
@@ -462,7 +469,7 @@ double *alpha_launch(wenott_ctx *c, const TT &U, int slot, bool readback = true)
     int nlast = U.N[U.d - 1];
     const int nblocks = dense_eval_blocks(1, nrows, U.R[U.d - 1], nlast);
     double *part = c->sc.get<double>(S_PART, nblocks);
-    dense_eval(c->s, 1, U.d, U.nc, nrows, U.R[U.d - 1], nlast, Lm, lms, U.core[U.d - 1], U.cstride(U.d - 1),
+    dense_eval(c->s, 1, U.d, c->law, nrows, U.R[U.d - 1], nlast, Lm, lms, U.core[U.d - 1], U.cstride(U.d - 1),
                c->gamma, nullptr, part, nblocks, c->d_flags);
     reduce_max_dev(c->s, part, nblocks, dst);
     if (readback) status_readback(c, kStatusAlpha + 4);
@@ -485,7 +492,7 @@ void to_dense_dev(wenott_ctx *c, const TT &U, double *out) {
     for (int k = 0; k < U.d - 1; ++k) nrows *= U.N[k];
     int nlast = U.N[U.d - 1];
     const int nblocks = dense_eval_blocks(0, nrows, U.R[U.d - 1], nlast);
-    dense_eval(c->s, 0, U.d, U.nc, nrows, U.R[U.d - 1], nlast, Lm, lms, U.core[U.d - 1], U.cstride(U.d - 1),
+    dense_eval(c->s, 0, U.d, c->law, nrows, U.R[U.d - 1], nlast, Lm, lms, U.core[U.d - 1], U.cstride(U.d - 1),
                c->gamma, out, nullptr, nblocks, c->d_flags);
 }
 
@@ -497,7 +504,7 @@ void eval_block(wenott_ctx *c, const TT &U, int dir, int k, const ISet &L, const
     FiberGeom g{};
     g.d = d; g.ncomp = nc; g.dir = dir; g.k = k;
     for (int j = 0; j < d; ++j) { g.n[j] = U.N[j]; g.bc[j] = c->bc[j]; }
-    g.gamma = c->gamma; g.alpha = alpha; g.eps_w = c->h[dir] * c->h[dir];
+    g.law = c->law; g.gamma = c->gamma; g.alpha = alpha; g.eps_w = c->h[dir] * c->h[dir];
     const int p = L.count, q = Rs.count;
     const int SL = dir < k ? 6 : 1, SR = dir > k ? 6 : 1, S = std::max(SL, SR);
     const int Rk = U.R[k], Rk1 = U.R[k + 1], Nk = U.N[k];
@@ -658,7 +665,7 @@ double sampled_residual(wenott_ctx *c, const TT &U, const FluxTT &F, int dir, do
     FiberGeom g{};
     g.d = d; g.ncomp = U.nc; g.dir = dir; g.k = 0;
     for (int j = 0; j < d; ++j) { g.n[j] = U.N[j]; g.bc[j] = c->bc[j]; }
-    g.gamma = c->gamma; g.alpha = alpha; g.eps_w = c->h[dir] * c->h[dir];
+    g.law = c->law; g.gamma = c->gamma; g.alpha = alpha; g.eps_w = c->h[dir] * c->h[dir];
     int *dp = c->sc.get<int>(S_PTS, (size_t)npts * d);
     sample_points(c->s, npts, d, F.M, rng.next(), dp);
     double *ust = c->sc.get<double>(S_UST, (size_t)npts * 6 * U.nc);
@@ -831,6 +838,7 @@ struct CrossTarget {
 // right index sets and the next sweep starts with a tighter pivot tolerance. Every sampled
 // index set is enriched by kick_rank random indices.
 FluxTT cross_generic(wenott_ctx *c, const CrossTarget &t, double eps, CrossStat &st) {
+    eps *= c->o.cross_ratio;  // eps_cross
     const int d = t.d, nc = t.nc;
     const int *M = t.M;
     Rng rng(c->o.seed ^ (0x5851F42D4C957F2DULL * (++c->counter)));
@@ -852,7 +860,7 @@ FluxTT cross_generic(wenott_ctx *c, const CrossTarget &t, double eps, CrossStat 
     F.d = d; F.nc = nc;
     for (int j = 0; j < d; ++j) F.M[j] = M[j];
     double rel2 = eps * eps / (4.0 * d);
-    const int kick = c->o.kick_rank;
+    int kick = c->o.kick_rank;
     double resid = 1e300;
     int sweep = 0;
     bool have_feats = t.learn;
@@ -870,6 +878,7 @@ FluxTT cross_generic(wenott_ctx *c, const CrossTarget &t, double eps, CrossStat 
     bool capped = false;  // a pivot search of the last left-to-right sweep stopped at its rank limit
     for (; sweep < c->o.max_sweeps; ++sweep) {
         capped = false;
+        bool saturated = false;  // a pivot search used every column of its block
         F.release(c->s);
         Lset[0].len = 0;
         Lset[0].count = 1;
@@ -890,6 +899,7 @@ FluxTT cross_generic(wenott_ctx *c, const CrossTarget &t, double eps, CrossStat 
                 PivotResult pr = pivots(c, B, (int)rows, (int)cols, rel2, &L, hist_index(t.warm_slot, 0, k),
                                         [&] { t.eval(k, Lset[k], Rk, true, B); });
                 capped = capped || pr.capped;
+                saturated = saturated || (pr.rank >= cols && cols < rows);
                 if (t.learn) {
                     usedR[k] = Rk;
                     usedC[k] = pr.cols;
@@ -943,6 +953,7 @@ FluxTT cross_generic(wenott_ctx *c, const CrossTarget &t, double eps, CrossStat 
             double *L = nullptr;
             PivotResult pr = pivots(c, B, (int)rows, (int)cols, rel2, &L, hist_index(t.warm_slot, 1, k),
                                     [&] { t.eval(k, Lk, Rk, false, B); });
+            saturated = saturated || (pr.rank >= cols && cols < rows);
             ISet nr;
             nr.len = d - k;
             nr.count = pr.rank;
@@ -955,6 +966,11 @@ FluxTT cross_generic(wenott_ctx *c, const CrossTarget &t, double eps, CrossStat 
             Rset[k - 1] = std::move(nr);
         }
         rel2 *= 0.25;
+        // A search that used every column found as many pivots as the index sets allowed: the rank
+        // is limited by the sets (one column per index tuple and component, so a single-component
+        // law adds at most kick pivots per sweep), not by the tolerance. Such a cross doubles its
+        // enrichment for the next sweep.
+        if (saturated) kick = std::min(2 * std::max(kick, 2), 128);
     }
     c->warm[t.warm_slot] = Rset;
     c->warm_valid[t.warm_slot] = true;
@@ -964,8 +980,12 @@ FluxTT cross_generic(wenott_ctx *c, const CrossTarget &t, double eps, CrossStat 
     if (t.learn) learn_update(c, d, nc, M, F, usedR, usedC, feats, have_feats, sweep, resid);
     if (!(resid <= c->o.conv_slack * eps) && !(resid <= 1e-12)) {
         F.release(c->s);
-        throw StatusError(WENOTT_ENOCONV, capped ? "cross did not converge: a pivot search stopped at the rank limit"
-                                                 : "cross did not converge within max_sweeps sweeps");
+        char msg[192];
+        std::snprintf(msg, sizeof(msg), "%s (sampled residual %.3e, eps_cross %.3e, %d sweeps, rank %d)",
+                      capped ? "cross did not converge: a pivot search stopped at the rank limit"
+                             : "cross did not converge within max_sweeps sweeps",
+                      resid, eps, sweep, st.maxrank);
+        throw StatusError(WENOTT_ENOCONV, msg);
     }
     return F;
 }
@@ -997,7 +1017,7 @@ void eval_stage_block(wenott_ctx *c, const TT &X, const TT *Un, StageWeights w, 
     FiberGeom g{};
     g.d = d; g.ncomp = nc; g.dir = 0; g.k = k;
     for (int j = 0; j < d; ++j) { g.n[j] = X.N[j]; g.bc[j] = c->bc[j]; }
-    g.gamma = c->gamma; g.alpha = alpha; g.eps_w = 0.0; g.alpha_dev = c->alpha_dev;
+    g.law = c->law; g.gamma = c->gamma; g.alpha = alpha; g.eps_w = 0.0; g.alpha_dev = c->alpha_dev;
     const int p = L.count, q = Rs.count, Nk = X.N[k];
     const int *didxL = k > 0 ? c->ring.put(L.v.data(), L.v.size()) : nullptr;
     const int *didxR = k < d - 1 ? c->ring.put(Rs.v.data(), Rs.v.size()) : nullptr;
@@ -1194,7 +1214,7 @@ int sampled_stage_residual_launch(wenott_ctx *c, const TT &X, const TT *Un, Stag
     FiberGeom g{};
     g.d = d; g.ncomp = X.nc; g.dir = 0; g.k = 0;
     for (int j = 0; j < d; ++j) { g.n[j] = X.N[j]; g.bc[j] = c->bc[j]; }
-    g.gamma = c->gamma; g.alpha = alpha; g.alpha_dev = c->alpha_dev;
+    g.law = c->law; g.gamma = c->gamma; g.alpha = alpha; g.alpha_dev = c->alpha_dev;
     const unsigned long long seed = rng.next();
     const int SL = 7 * d + 1;
     double *ust = c->sc.get<double>(S_UST, (size_t)npts * SL * X.nc);
@@ -1510,6 +1530,8 @@ struct BState {
     double rel2 = 0.0, resid = 1e300;
     int sweep = 0;
     bool active = true, cold = false;
+    int kick = 0;            // enrichment of this sweep's index sets
+    bool saturated = false;  // a pivot search of this sweep used every column of its block
     // per-core pivots of the batched pivot phase
     double *B = nullptr, *L = nullptr;
     int *piv = nullptr;
@@ -1620,11 +1642,13 @@ void batch_cross(std::vector<BState> &bs, const double *aw, const double *bw, in
         b.F.d = d; b.F.nc = nc;
         for (int j = 0; j < d; ++j) b.F.M[j] = b.M[j];
         // the FP32 fiber path floors the cross tolerance as in the single-state cross
-        b.ceps = c->o.precision == 1 ? std::max(b.eps, 1e-6) : b.eps;
+        b.ceps = (c->o.precision == 1 ? std::max(b.eps, 1e-6) : b.eps) * c->o.cross_ratio;
         b.rel2 = b.ceps * b.ceps / (4.0 * d);
         b.resid = 1e300;
         b.sweep = 0;
         b.active = true;
+        b.kick = c->o.kick_rank;
+        b.saturated = false;
     }
     const int max_sweeps = bs[0].c->o.max_sweeps;
     for (int sweep = 0; sweep < max_sweeps; ++sweep) {
@@ -1633,6 +1657,7 @@ void batch_cross(std::vector<BState> &bs, const double *aw, const double *bw, in
             if (b.active) act.push_back(&b);
         if (act.empty()) break;
         for (BState *b : act) {
+            b->saturated = false;
             b->F.release(b->c->s);
             b->Lset[0].len = 0; b->Lset[0].count = 1; b->Lset[0].v.clear();
             b->F.R[0] = 1; b->F.R[d] = 1;
@@ -1641,7 +1666,7 @@ void batch_cross(std::vector<BState> &bs, const double *aw, const double *bw, in
         for (int k = 0; k < d; ++k) {
             for (BState *b : act) {
                 const size_t z = b - bs.data();
-                Rk[z] = k < d - 1 ? with_kick(b->Rset[k], b->rng, b->c->o.kick_rank, k + 1, b->M) : b->Rset[k];
+                Rk[z] = k < d - 1 ? with_kick(b->Rset[k], b->rng, b->kick, k + 1, b->M) : b->Rset[k];
                 const int p = b->Lset[k].count, q = Rk[z].count;
                 b->m = p * b->M[k];
                 b->n = q * nc;
@@ -1662,6 +1687,7 @@ void batch_cross(std::vector<BState> &bs, const double *aw, const double *bw, in
             });
             for (BState *b : act) {
                 const int r = (int)pinned_pivot_info(b->c, b->rmax, 0);
+                b->saturated = b->saturated || (r >= b->n && b->n < b->m);
                 std::vector<int> rows(b->c->h_pinned_int, b->c->h_pinned_int + r);
                 b->F.core[k] = dalloc<double>(b->c->s, (size_t)b->m * r);
                 interp_solve(b->c->s, b->m, r, b->L, b->rmax, b->piv, b->F.core[k]);
@@ -1696,7 +1722,7 @@ void batch_cross(std::vector<BState> &bs, const double *aw, const double *bw, in
             std::vector<ISet> Lk(bs.size());
             for (BState *b : refresh) {
                 const size_t z = b - bs.data();
-                Lk[z] = with_kick(b->Lset[k], b->rng, b->c->o.kick_rank, 0, b->M);
+                Lk[z] = with_kick(b->Lset[k], b->rng, b->kick, 0, b->M);
                 const ISet &R = b->Rset[k];
                 b->m = b->M[k] * R.count;
                 b->n = Lk[z].count * nc;
@@ -1712,6 +1738,7 @@ void batch_cross(std::vector<BState> &bs, const double *aw, const double *bw, in
             for (BState *b : refresh) {
                 const ISet &R = b->Rset[k];
                 const int r = (int)pinned_pivot_info(b->c, b->rmax, 0), q = R.count;
+                b->saturated = b->saturated || (r >= b->n && b->n < b->m);
                 ISet nr;
                 nr.len = d - k;
                 nr.count = r;
@@ -1724,7 +1751,10 @@ void batch_cross(std::vector<BState> &bs, const double *aw, const double *bw, in
                 b->Rset[k - 1] = std::move(nr);
             }
         }
-        for (BState *b : refresh) b->rel2 *= 0.25;
+        for (BState *b : refresh) {
+            b->rel2 *= 0.25;
+            if (b->saturated) b->kick = std::min(2 * std::max(b->kick, 2), 128);  // as in the single-state cross
+        }
     }
     for (auto &b : bs) {
         b.c->warm[kMaxDim] = b.Rset;
@@ -2034,6 +2064,8 @@ void wenott_default_opts(wenott_opts *o) {
     o->graph_mode = 0;
     o->scheme = 0;
     o->conv_slack = 1.0;
+    o->law = WENOTT_LAW_EULER;
+    o->cross_ratio = 1.0;
 }
 
 const char *wenott_strerror(wenott_status s) {
@@ -2059,15 +2091,23 @@ wenott_status wenott_init(wenott_ctx **out, const wenott_tt *state, const wenott
     wenott_status st = run_guarded(c, [&] {
         const int d = grid->ndim;
         WTT_REQUIRE(d == 2 || d == 3, WENOTT_EINVAL, "ndim must be 2 or 3");
-        WTT_REQUIRE(state->ndim == d && state->ncomp == d + 2, WENOTT_EINVAL, "state must hold ndim + 2 TTs");
+        if (opts) c->o = *opts; else wenott_default_opts(&c->o);
+        const int law = c->o.law;
+        WTT_REQUIRE(law == WENOTT_LAW_EULER || law == WENOTT_LAW_LINADV || law == WENOTT_LAW_BURGERS, WENOTT_EINVAL,
+                    "unknown conservation law");
+        const int nc = law == WENOTT_LAW_EULER ? d + 2 : 1;
+        WTT_REQUIRE(state->ndim == d && state->ncomp == nc, WENOTT_EINVAL,
+                    "state must hold ndim + 2 TTs (Euler) or one TT (scalar law)");
         WTT_REQUIRE(state->dtype == 0, WENOTT_EINVAL, "only FP64 cores are accepted");
         WTT_REQUIRE(state->ranks && state->cores, WENOTT_EINVAL, "null ranks or cores");
-        WTT_REQUIRE(gamma > 1.0, WENOTT_EINVAL, "gamma must exceed 1");
+        WTT_REQUIRE(law != WENOTT_LAW_EULER || gamma > 1.0, WENOTT_EINVAL, "gamma must exceed 1");
+        WTT_REQUIRE(law == WENOTT_LAW_EULER || c->o.use_proposal == 0, WENOTT_EINVAL,
+                    "the scalar laws run without the proposal");
         c->d = d;
-        c->nc = d + 2;
+        c->law = law;
+        c->nc = nc;
         c->gamma = gamma;
         std::fill(std::begin(c->piv_hist), std::end(c->piv_hist), -1);
-        if (opts) c->o = *opts; else wenott_default_opts(&c->o);
         WTT_REQUIRE(c->o.graph_mode == 0, WENOTT_ENOTBUILT, "option not available");
         WTT_REQUIRE(c->o.use_proposal == 0 || c->o.use_proposal == 1, WENOTT_EINVAL, "use_proposal must be 0 or 1");
         WTT_REQUIRE(c->o.precision == 0 || c->o.precision == 1, WENOTT_EINVAL, "precision must be 0 or 1");
@@ -2079,6 +2119,7 @@ wenott_status wenott_init(wenott_ctx **out, const wenott_tt *state, const wenott
         WTT_REQUIRE(c->o.rounds_per_stage == 1 || c->o.rounds_per_stage == 2, WENOTT_EINVAL,
                     "rounds_per_stage must be 1 or 2");
         WTT_REQUIRE(c->o.conv_slack >= 1.0, WENOTT_EINVAL, "conv_slack must be >= 1");
+        WTT_REQUIRE(c->o.cross_ratio > 0.0 && c->o.cross_ratio <= 1.0, WENOTT_EINVAL, "cross_ratio must be in (0, 1]");
         WTT_REQUIRE(c->o.probe_points >= 16 && c->o.probe_points <= 65536, WENOTT_EINVAL,
                     "probe_points must be in [16, 65536]");
         for (int k = 0; k < d; ++k) {
@@ -2111,7 +2152,6 @@ wenott_status wenott_init(wenott_ctx **out, const wenott_tt *state, const wenott
         WTT_HIP(hipMalloc((void **)&c->d_best, sizeof(int) * kMaxDim));
         WTT_HIP(hipMemsetAsync(c->d_best, 0xff, sizeof(int) * kMaxDim, c->s));  // -1: no best cell yet
         // common padded ranks
-        const int nc = c->nc;
         TT U;
         U.d = d; U.nc = nc;
         for (int k = 0; k < d; ++k) U.N[k] = c->N[k];
@@ -2523,7 +2563,9 @@ wenott_status wenott_max_wavespeed_noalloc(wenott_ctx *c, double *alpha) {
         char *ws = (char *)c->noalloc_ws;
         WTT_REQUIRE(ws != nullptr, WENOTT_EHIP, "no device workspace");
         double *dst = c->d_status + kStatusAlpha + 3;
-        if (c->o.alpha_mode == 1) {
+        if (c->law == WENOTT_LAW_LINADV) {
+            fill(c->s, dst, 1, 1.0);
+        } else if (c->o.alpha_mode == 1) {
             const size_t ni = alpha_search_ints(U.d, U.N[1]), nd = alpha_search_doubles(U.d, U.N[1]);
             const size_t off = (ni * sizeof(int) + 255) / 256 * 256;
             WTT_REQUIRE(off + nd * sizeof(double) <= kNoAllocBytes, WENOTT_EINVAL, "alpha search workspace too large");
@@ -2532,8 +2574,8 @@ wenott_status wenott_max_wavespeed_noalloc(wenott_ctx *c, double *alpha) {
             for (int k = 0; k <= U.d; ++k) ranks[k] = U.R[k];
             for (int k = 0; k < U.d; ++k) cores[k] = U.core[k];
             const unsigned long long seed = c->o.seed * 0x9E3779B97F4A7C15ULL + 0xA5A5ULL * (++c->alpha_counter);
-            alpha_search(c->s, U.d, U.N, cores, ranks, c->gamma, seed, c->d_best, (int *)ws, (double *)(ws + off), dst,
-                         c->d_flags);
+            alpha_search(c->s, U.d, c->law, U.N, cores, ranks, c->gamma, seed, c->d_best, (int *)ws,
+                         (double *)(ws + off), dst, c->d_flags);
         } else {
             // the exact maximum over every cell: in 2D the left part of a cell is its first core, so
             // the only workspace is one partial maximum per workgroup
@@ -2544,8 +2586,8 @@ wenott_status wenott_max_wavespeed_noalloc(wenott_ctx *c, double *alpha) {
             const int nblocks = dense_eval_blocks(1, nrows, U.R[1], U.N[1]);
             WTT_REQUIRE((size_t)nblocks * sizeof(double) <= kNoAllocBytes, WENOTT_EINVAL,
                         "grid too large for the static workspace of the exact alpha");
-            dense_eval(c->s, 1, U.d, U.nc, nrows, U.R[1], U.N[1], U.core[0], U.cstride(0), U.core[1], U.cstride(1),
-                       c->gamma, nullptr, (double *)ws, nblocks, c->d_flags);
+            dense_eval(c->s, 1, U.d, c->law, nrows, U.R[1], U.N[1], U.core[0], U.cstride(0), U.core[1],
+                       U.cstride(1), c->gamma, nullptr, (double *)ws, nblocks, c->d_flags);
             reduce_max_dev(c->s, (double *)ws, nblocks, dst);
         }
         status_readback(c, kStatusAlpha + 4);

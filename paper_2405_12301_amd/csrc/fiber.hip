@@ -142,9 +142,16 @@ __device__ inline T weno5(T vm2, T vm1, T v0, T vp1, T vp2, T eps) {
     return (a0 * q0 + a1 * q1 + a2 * q2) / (a0 + a1 + a2);
 }
 
-// f^{+-} = (f_dir(q) +- alpha q) / 2 for one stencil cell (Sec. 2.1 fluxes, eq. lax-friedrichs).
-template <int ND, typename T>
+// f^{+-} = (f_dir(q) +- alpha q) / 2 for one stencil cell (eq. lax-friedrichs) with the Euler
+// fluxes of Sec. 2.1, or the scalar fluxes of Sec. 5.1 (f = u) and Sec. 5.2 (f = u^2 / 2).
+template <int ND, int LW, typename T>
 __device__ inline bool split_flux(const T *q, int dir, T gm1, T alpha, T *fp, T *fm) {
+    if (LW != kLawEuler) {
+        const T f = LW == kLawLinAdv ? q[0] : T(0.5) * q[0] * q[0];
+        fp[0] = T(0.5) * (f + alpha * q[0]);
+        fm[0] = T(0.5) * (f - alpha * q[0]);
+        return true;
+    }
     constexpr int NC = ND + 2;
     T rho = q[0];
     T inv = T(1) / rho;
@@ -167,11 +174,11 @@ __device__ inline bool split_flux(const T *q, int dir, T gm1, T alpha, T *fp, T 
     return rho > T(0) && p > T(0);
 }
 
-template <int ND, typename T>
+template <int ND, int LW, typename T>
 __global__ __launch_bounds__(256) void k_weno(FiberGeom g, int p, int M, int q, const T *__restrict__ W,
                                               double *__restrict__ out, long long sa, long long si, long long sb,
                                               long long sc, int *__restrict__ flags) {
-    constexpr int NC = ND + 2;
+    constexpr int NC = LawNC<ND, LW>::v;
     const long long tot = (long long)p * M * q;
     long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (e >= tot) return;
@@ -195,7 +202,7 @@ __global__ __launch_bounds__(256) void k_weno(FiberGeom g, int p, int M, int q, 
             for (int c = 0; c < NC; ++c) qv[c] = W[((((long long)c * 6 + s) * p + a) * Nk + i) * q + b];
         }
         T fpt[NC], fmt[NC];
-        ok &= split_flux<ND, T>(qv, g.dir, T(g.gamma - 1.0), T(geom_alpha(g)), fpt, fmt);
+        ok &= split_flux<ND, LW, T>(qv, g.dir, T(g.gamma - 1.0), T(geom_alpha(g)), fpt, fmt);
 #pragma unroll
         for (int c = 0; c < NC; ++c) { fp[c][s] = fpt[c]; fm[c][s] = fmt[c]; }
     }
@@ -232,13 +239,13 @@ __device__ inline double dot4(const double *__restrict__ x, long long sx, const 
     return (a0 + a1) + (a2 + a3);
 }
 
-template <int ND>
-__global__ __launch_bounds__(256) void k_dense_eval(int mode, int ncomp, long long nrows, int R, int nlast,
+template <int ND, int LW>
+__global__ __launch_bounds__(256) void k_dense_eval(int mode, long long nrows, int R, int nlast,
                                                     const double *__restrict__ Lm, long long lm_stride,
                                                     const double *__restrict__ G, long long g_stride, double gamma,
                                                     double *__restrict__ out, double *__restrict__ partial,
                                                     int *__restrict__ flags) {
-    constexpr int NC = ND + 2;
+    constexpr int NC = LawNC<ND, LW>::v;
     __shared__ double red[4];
     const long long ncell = nrows * nlast;
     long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
@@ -261,6 +268,8 @@ __global__ __launch_bounds__(256) void k_dense_eval(int mode, int ncomp, long lo
         if (mode == 0) {
 #pragma unroll
             for (int c = 0; c < NC; ++c) out[c * ncell + e] = qv[c];
+        } else if (LW == kLawBurgers) {
+            speed = fabs(qv[0]);
         } else {
             double inv = 1.0 / qv[0], u2 = 0.0;
 #pragma unroll
@@ -288,12 +297,12 @@ __global__ __launch_bounds__(256) void k_dense_eval(int mode, int ncomp, long lo
 // the rows one by one inside the sweep would instead wait a memory round trip per row. The cell
 // speeds only feed a maximum; their reciprocal and square roots are the Newton-refined ones.
 // RM: the register columns' length; EXACT: R == RM, so that no term needs a rank check.
-template <int ND, int RM, bool EXACT>
+template <int ND, int LW, int RM, bool EXACT>
 __global__ __launch_bounds__(256) void k_alpha_eval(long long nrows, int R, int nlast, int RB,
                                                     const double *__restrict__ Lm, long long lm_stride,
                                                     const double *__restrict__ G, long long g_stride, double gamma,
                                                     double *__restrict__ partial, int *__restrict__ flags) {
-    constexpr int NC = ND + 2;
+    constexpr int NC = LawNC<ND, LW>::v;
     if (EXACT) R = RM;
     __shared__ double red[4];
     extern __shared__ double lrows[];  // [c][row - r0][b], NC x RB x R
@@ -326,7 +335,9 @@ __global__ __launch_bounds__(256) void k_alpha_eval(long long nrows, int R, int 
             }
             qv[c] = s0 + s1;
         }
-        if (jv) {
+        if (jv && LW == kLawBurgers) {
+            speed = fmax(speed, fabs(qv[0]));
+        } else if (jv) {
             const double inv = nr_rcp(qv[0]);
             double m2 = 0.0;
 #pragma unroll
@@ -396,7 +407,7 @@ __device__ inline double tt_point(const CoreSet &cs, int c, const int *cell) {
 template <int ND>
 __global__ void k_sample_state(FiberGeom g, CoreSet cs, int npts, const int *__restrict__ pts,
                                double *__restrict__ ust) {
-    constexpr int NC = ND + 2;
+    const int NC = g.ncomp;
     long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (e >= (long long)npts * 6 * NC) return;
     const int c = (int)(e % NC);
@@ -411,11 +422,11 @@ __global__ void k_sample_state(FiberGeom g, CoreSet cs, int npts, const int *__r
     ust[e] = tt_point<ND>(cs, c, cell);
 }
 
-template <int ND>
+template <int ND, int LW>
 __global__ __launch_bounds__(256) void k_sample_flux(FiberGeom g, CoreSet fs, int npts, const int *__restrict__ pts,
                                                      const double *__restrict__ ust, double *__restrict__ acc,
                                                      int *__restrict__ flags) {
-    constexpr int NC = ND + 2;
+    constexpr int NC = LawNC<ND, LW>::v;
     __shared__ double red[2][4];
     const int pt = blockIdx.x * blockDim.x + threadIdx.x;
     double d2 = 0.0, n2 = 0.0;
@@ -425,7 +436,7 @@ __global__ __launch_bounds__(256) void k_sample_flux(FiberGeom g, CoreSet fs, in
         for (int s = 0; s < 6; ++s) {
             double qv[NC], a[NC], b[NC];
             for (int c = 0; c < NC; ++c) qv[c] = ust[((long long)pt * 6 + s) * NC + c];
-            ok &= split_flux<ND, double>(qv, g.dir, g.gamma - 1.0, geom_alpha(g), a, b);
+            ok &= split_flux<ND, LW, double>(qv, g.dir, g.gamma - 1.0, geom_alpha(g), a, b);
             for (int c = 0; c < NC; ++c) { fp[c][s] = a[c]; fm[c][s] = b[c]; }
         }
         // approximation: shared cores 0..d-2, last core (R, M, NC)
@@ -484,9 +495,10 @@ __global__ __launch_bounds__(256) void k_sample_flux(FiberGeom g, CoreSet fs, in
 // -(Fhat(+1/2) - Fhat(-1/2)) / h along one direction from the state at cells -3..+3
 // (slots 0..6) of every component. Face +1/2: f^+ from slots 1..5, f^- mirrored from 6..2;
 // face -1/2: f^+ from slots 0..4, f^- mirrored from 5..1.
-template <int ND, typename T>
-__device__ inline bool stage_dir(const T (&v)[ND + 2][7], int dir, T gm1, T alpha, T eps, T inv_h, T *acc) {
-    constexpr int NC = ND + 2;
+template <int ND, int LW, typename T>
+__device__ inline bool stage_dir(const T (&v)[LawNC<ND, LW>::v][7], int dir, T gm1, T alpha, T eps, T inv_h,
+                                 T *acc) {
+    constexpr int NC = LawNC<ND, LW>::v;
     T fp[NC][7], fm[NC][7];
     bool ok = true;
 #pragma unroll
@@ -494,7 +506,7 @@ __device__ inline bool stage_dir(const T (&v)[ND + 2][7], int dir, T gm1, T alph
         T qv[NC], a[NC], b[NC];
 #pragma unroll
         for (int c = 0; c < NC; ++c) qv[c] = v[c][s];
-        ok &= split_flux<ND, T>(qv, dir, gm1, alpha, a, b);
+        ok &= split_flux<ND, LW, T>(qv, dir, gm1, alpha, a, b);
 #pragma unroll
         for (int c = 0; c < NC; ++c) { fp[c][s] = a[c]; fm[c][s] = b[c]; }
     }
@@ -517,11 +529,11 @@ __device__ inline bool stage_dir(const T (&v)[ND + 2][7], int dir, T gm1, T alph
 // shorten the dependent chain each one runs. A large block fills the device at one point per
 // thread (DG = 1, every direction in one lane). The direction-dependent operands are chosen by
 // comparisons (a per-lane index into the argument arrays would send them to scratch memory).
-template <int ND, int DG, typename T>
+template <int ND, int LW, int DG, typename T>
 __global__ __launch_bounds__(256) void k_stage(FiberGeom g, int p, int q, StageArgsT<T> sa_, double *__restrict__ out,
                                                long long sa, long long si, long long sb, long long sc,
                                                int *__restrict__ flags) {
-    constexpr int NC = ND + 2;
+    constexpr int NC = LawNC<ND, LW>::v;
     const int Nk = g.n[g.k];
     const long long tot = (long long)p * Nk * q;
     const long long et = blockIdx.x * (long long)blockDim.x + threadIdx.x;
@@ -556,7 +568,7 @@ __global__ __launch_bounds__(256) void k_stage(FiberGeom g, int p, int q, StageA
         }
         const T eps = T(dd == 0 ? sa_.eps_w[0] : (dd == 1 ? sa_.eps_w[1] : sa_.eps_w[ND - 1]));
         const T ih = T(dd == 0 ? sa_.inv_h[0] : (dd == 1 ? sa_.inv_h[1] : sa_.inv_h[ND - 1]));
-        ok &= stage_dir<ND, T>(v, dd, gm1, alpha, eps, ih, acc);
+        ok &= stage_dir<ND, LW, T>(v, dd, gm1, alpha, eps, ih, acc);
     }
 #pragma unroll
     for (int c = 0; c < NC; ++c)
@@ -583,7 +595,7 @@ __global__ __launch_bounds__(256) void k_stage(FiberGeom g, int p, int q, StageA
 template <int ND>
 __global__ void k_sample_star(FiberGeom g, CoreSet cs, CoreSet un, int use_un, int npts, unsigned long long seed,
                               double *__restrict__ ust) {
-    constexpr int NC = ND + 2;
+    const int NC = g.ncomp;
     constexpr int SL = 7 * ND + 1;
     long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (e >= (long long)npts * SL * NC) return;
@@ -623,7 +635,7 @@ constexpr int kSliceLdsDoubles = 8192;  // staged slice (R1 R2 <= 8192)
 
 __global__ __launch_bounds__(256) void k_sample_slices3(FiberGeom g, CoreSet cs, CoreSet un, int use_un, int npts,
                                                         unsigned long long seed, double *__restrict__ ust) {
-    constexpr int NC = 5;
+    const int NC = g.ncomp;
     __shared__ int pair_pt[kSlicePairs];
     __shared__ unsigned char pair_s[kSlicePairs];
     __shared__ int npairs;
@@ -783,12 +795,12 @@ __global__ __launch_bounds__(256) void k_sample_slices3(FiberGeom g, CoreSet cs,
 // forms the flux difference along direction d and a share of the flux TT's rank sum at the
 // point; the group adds both by shuffles and its first lane forms the residual terms. One
 // partial pair per workgroup (sample_stage_blocks of them).
-template <int ND>
+template <int ND, int LW>
 __global__ __launch_bounds__(256) void k_sample_stage(FiberGeom g, CoreSet fs, int npts, unsigned long long seed,
                                                        const double *__restrict__ ust, double wn, double wx, double wl,
                                                        StageArgsT<double> hs, double *__restrict__ acc,
                                                        int *__restrict__ flags) {
-    constexpr int NC = ND + 2, DG = ND == 2 ? 2 : 4;
+    constexpr int NC = LawNC<ND, LW>::v, DG = ND == 2 ? 2 : 4;
     __shared__ double red[2][4];
     const int pt = blockIdx.x * (256 / DG) + threadIdx.x / DG, d = threadIdx.x % DG;
     double d2 = 0.0, n2 = 0.0;
@@ -803,7 +815,7 @@ __global__ __launch_bounds__(256) void k_sample_stage(FiberGeom g, CoreSet fs, i
                 for (int c = 0; c < NC; ++c) v[c][s] = u[((long long)(d * 7 + s) * NC + c) * npts];
             const double eps = d == 0 ? hs.eps_w[0] : (d == 1 ? hs.eps_w[1] : hs.eps_w[ND - 1]);
             const double ih = d == 0 ? hs.inv_h[0] : (d == 1 ? hs.inv_h[1] : hs.inv_h[ND - 1]);
-            ok = stage_dir<ND, double>(v, d, g.gamma - 1.0, geom_alpha(g), eps, ih, L);
+            ok = stage_dir<ND, LW, double>(v, d, g.gamma - 1.0, geom_alpha(g), eps, ih, L);
         }
         int m[ND];
         for (int dd = 0; dd < ND; ++dd) m[dd] = probe_coord(seed, (long long)pt * ND + dd, g.n[dd]);
@@ -900,10 +912,15 @@ void weno_block(hipStream_t s, const FiberGeom &g, int p, int q, const T *W, dou
     const int M = g.k == g.dir ? g.n[g.k] + 1 : g.n[g.k];
     long long tot = (long long)p * M * q;
     if (tot == 0) return;
-    if (g.d == 2)
-        k_weno<2, T><<<cdiv(tot, 256), 256, 0, s>>>(g, p, M, q, W, out, sa, si, sb, sc, flags);
-    else
-        k_weno<3, T><<<cdiv(tot, 256), 256, 0, s>>>(g, p, M, q, W, out, sa, si, sb, sc, flags);
+#define WTT_WENO(ND_, LW_) k_weno<ND_, LW_, T><<<cdiv(tot, 256), 256, 0, s>>>(g, p, M, q, W, out, sa, si, sb, sc, flags)
+    if (g.law == kLawEuler) {
+        if (g.d == 2) WTT_WENO(2, kLawEuler); else WTT_WENO(3, kLawEuler);
+    } else if (g.law == kLawLinAdv) {
+        if (g.d == 2) WTT_WENO(2, kLawLinAdv); else WTT_WENO(3, kLawLinAdv);
+    } else {
+        if (g.d == 2) WTT_WENO(2, kLawBurgers); else WTT_WENO(3, kLawBurgers);
+    }
+#undef WTT_WENO
     WTT_HIP(hipGetLastError());
 }
 template void weno_block<double>(hipStream_t, const FiberGeom &, int, int, const double *, double *, long long,
@@ -931,14 +948,14 @@ int dense_eval_blocks(int mode, long long nrows, int R, int nlast) {
     return (int)cdiv(nrows * nlast, 256);
 }
 
-template <int ND>
+template <int ND, int LW>
 void launch_alpha_eval(hipStream_t s, long long nrows, int R, int nlast, const double *Lm, long long lm_stride,
                        const double *G, long long g_stride, double gamma, double *partial, int *flags) {
     const int RB = alpha_rows_per_block(nrows, R, nlast);
     const dim3 grid((unsigned)cdiv(nlast, 256), (unsigned)cdiv(nrows, RB));
-    const size_t lds = sizeof(double) * (size_t)(ND + 2) * RB * R;  // <= 48 KB
+    const size_t lds = sizeof(double) * (size_t)LawNC<ND, LW>::v * RB * R;  // <= 48 KB
 #define WTT_ALPHA(RM_, EX_) \
-    k_alpha_eval<ND, RM_, EX_><<<grid, 256, lds, s>>>(nrows, R, nlast, RB, Lm, lm_stride, G, g_stride, gamma, partial, flags)
+    k_alpha_eval<ND, LW, RM_, EX_><<<grid, 256, lds, s>>>(nrows, R, nlast, RB, Lm, lm_stride, G, g_stride, gamma, partial, flags)
     switch (R) {
     case 1: WTT_ALPHA(1, true); break;
     case 2: WTT_ALPHA(2, true); break;
@@ -955,24 +972,37 @@ void launch_alpha_eval(hipStream_t s, long long nrows, int R, int nlast, const d
 #undef WTT_ALPHA
 }
 
-void dense_eval(hipStream_t s, int mode, int d, int ncomp, long long nrows, int R, int nlast, const double *Lm,
-                long long lm_stride, const double *G, long long g_stride, double gamma, double *out, double *partial,
-                int nblocks, int *flags) {
-    (void)ncomp;
-    WTT_REQUIRE(dense_eval_blocks(mode, nrows, R, nlast) == nblocks, WENOTT_EINVAL, "dense_eval block count");
+template <int LW>
+void dense_eval_t(hipStream_t s, int mode, int d, long long nrows, int R, int nlast, const double *Lm,
+                  long long lm_stride, const double *G, long long g_stride, double gamma, double *out, double *partial,
+                  int nblocks, int *flags) {
     if (alpha_reg_path(mode, nrows, R, nlast)) {
-        if (d == 2) launch_alpha_eval<2>(s, nrows, R, nlast, Lm, lm_stride, G, g_stride, gamma, partial, flags);
-        else launch_alpha_eval<3>(s, nrows, R, nlast, Lm, lm_stride, G, g_stride, gamma, partial, flags);
+        if (d == 2) launch_alpha_eval<2, LW>(s, nrows, R, nlast, Lm, lm_stride, G, g_stride, gamma, partial, flags);
+        else launch_alpha_eval<3, LW>(s, nrows, R, nlast, Lm, lm_stride, G, g_stride, gamma, partial, flags);
         WTT_HIP(hipGetLastError());
         return;
     }
     if (d == 2)
-        k_dense_eval<2><<<nblocks, 256, 0, s>>>(mode, 4, nrows, R, nlast, Lm, lm_stride, G, g_stride, gamma, out,
-                                                partial, flags);
+        k_dense_eval<2, LW><<<nblocks, 256, 0, s>>>(mode, nrows, R, nlast, Lm, lm_stride, G, g_stride, gamma, out,
+                                                    partial, flags);
     else
-        k_dense_eval<3><<<nblocks, 256, 0, s>>>(mode, 5, nrows, R, nlast, Lm, lm_stride, G, g_stride, gamma, out,
-                                                partial, flags);
+        k_dense_eval<3, LW><<<nblocks, 256, 0, s>>>(mode, nrows, R, nlast, Lm, lm_stride, G, g_stride, gamma, out,
+                                                    partial, flags);
     WTT_HIP(hipGetLastError());
+}
+
+void dense_eval(hipStream_t s, int mode, int d, int law, long long nrows, int R, int nlast, const double *Lm,
+                long long lm_stride, const double *G, long long g_stride, double gamma, double *out, double *partial,
+                int nblocks, int *flags) {
+    WTT_REQUIRE(dense_eval_blocks(mode, nrows, R, nlast) == nblocks, WENOTT_EINVAL, "dense_eval block count");
+    WTT_REQUIRE(mode == 0 || law != kLawLinAdv, WENOTT_EINVAL, "linear advection has no wave-speed evaluation");
+    // the scalar laws share the one-component evaluation (the speed of mode 1 is Burgers')
+    if (law == kLawEuler)
+        dense_eval_t<kLawEuler>(s, mode, d, nrows, R, nlast, Lm, lm_stride, G, g_stride, gamma, out, partial, nblocks,
+                                flags);
+    else
+        dense_eval_t<kLawBurgers>(s, mode, d, nrows, R, nlast, Lm, lm_stride, G, g_stride, gamma, out, partial,
+                                  nblocks, flags);
 }
 
 void reduce_max_dev(hipStream_t s, const double *partial, int n, double *dst) {
@@ -997,13 +1027,18 @@ void sample_residual(hipStream_t s, const FiberGeom &g, const double *const *uco
         fs.cstride[k] = 0;
     }
     long long n1 = (long long)npts * 6 * g.ncomp;
-    if (g.d == 2) {
-        k_sample_state<2><<<cdiv(n1, 256), 256, 0, s>>>(g, us, npts, pts, ustencil);
-        k_sample_flux<2><<<cdiv(npts, 256), 256, 0, s>>>(g, fs, npts, pts, ustencil, acc, flags);
+    if (g.d == 2) k_sample_state<2><<<cdiv(n1, 256), 256, 0, s>>>(g, us, npts, pts, ustencil);
+    else k_sample_state<3><<<cdiv(n1, 256), 256, 0, s>>>(g, us, npts, pts, ustencil);
+#define WTT_SFLUX(ND_, LW_) \
+    k_sample_flux<ND_, LW_><<<cdiv(npts, 256), 256, 0, s>>>(g, fs, npts, pts, ustencil, acc, flags)
+    if (g.law == kLawEuler) {
+        if (g.d == 2) WTT_SFLUX(2, kLawEuler); else WTT_SFLUX(3, kLawEuler);
+    } else if (g.law == kLawLinAdv) {
+        if (g.d == 2) WTT_SFLUX(2, kLawLinAdv); else WTT_SFLUX(3, kLawLinAdv);
     } else {
-        k_sample_state<3><<<cdiv(n1, 256), 256, 0, s>>>(g, us, npts, pts, ustencil);
-        k_sample_flux<3><<<cdiv(npts, 256), 256, 0, s>>>(g, fs, npts, pts, ustencil, acc, flags);
+        if (g.d == 2) WTT_SFLUX(2, kLawBurgers); else WTT_SFLUX(3, kLawBurgers);
     }
+#undef WTT_SFLUX
     WTT_HIP(hipGetLastError());
 }
 
@@ -1014,13 +1049,18 @@ void stage_block(hipStream_t s, const FiberGeom &g, int p, int q, const StageArg
     long long tot = (long long)p * g.n[g.k] * q;
     if (tot == 0) return;
     const bool split = tot < (1LL << 17);  // fewer points than ~512 workgroups of one point per thread
-    if (g.d == 2) {
-        if (split) k_stage<2, 2, T><<<cdiv(2 * tot, 256), 256, 0, s>>>(g, p, q, a, out, sa, si, sb, sc, flags);
-        else k_stage<2, 1, T><<<cdiv(tot, 256), 256, 0, s>>>(g, p, q, a, out, sa, si, sb, sc, flags);
+#define WTT_STAGE(ND_, LW_)                                                                                    \
+    if (split) k_stage<ND_, LW_, ND_ == 2 ? 2 : 4, T><<<cdiv((ND_ == 2 ? 2 : 4) * tot, 256), 256, 0, s>>>(      \
+                   g, p, q, a, out, sa, si, sb, sc, flags);                                                    \
+    else k_stage<ND_, LW_, 1, T><<<cdiv(tot, 256), 256, 0, s>>>(g, p, q, a, out, sa, si, sb, sc, flags)
+    if (g.law == kLawEuler) {
+        if (g.d == 2) { WTT_STAGE(2, kLawEuler); } else { WTT_STAGE(3, kLawEuler); }
+    } else if (g.law == kLawLinAdv) {
+        if (g.d == 2) { WTT_STAGE(2, kLawLinAdv); } else { WTT_STAGE(3, kLawLinAdv); }
     } else {
-        if (split) k_stage<3, 4, T><<<cdiv(4 * tot, 256), 256, 0, s>>>(g, p, q, a, out, sa, si, sb, sc, flags);
-        else k_stage<3, 1, T><<<cdiv(tot, 256), 256, 0, s>>>(g, p, q, a, out, sa, si, sb, sc, flags);
+        if (g.d == 2) { WTT_STAGE(2, kLawBurgers); } else { WTT_STAGE(3, kLawBurgers); }
     }
+#undef WTT_STAGE
     WTT_HIP(hipGetLastError());
 }
 template void stage_block<double>(hipStream_t, const FiberGeom &, int, int, const StageArgsT<double> &, double *,
@@ -1051,8 +1091,6 @@ void sample_stage(hipStream_t s, const FiberGeom &g, const double *const *xcores
     long long n1 = (long long)npts * SL * g.ncomp;
     if (g.d == 2) {
         k_sample_star<2><<<cdiv(n1, 256), 256, 0, s>>>(g, xs, us, ncores != nullptr, npts, seed, ust);
-        k_sample_stage<2><<<sample_stage_blocks(2, npts), 256, 0, s>>>(g, fs, npts, seed, ust, wn, wx, wl, hs, acc,
-                                                                     flags);
     } else {
         // the slice form pays off once a cell costs more than a few hundred multiply-adds
         // (R1 R2); below that one thread per sample value is faster
@@ -1060,9 +1098,18 @@ void sample_stage(hipStream_t s, const FiberGeom &g, const double *const *xcores
             k_sample_slices3<<<g.n[1], 256, 0, s>>>(g, xs, us, ncores != nullptr, npts, seed, ust);
         else
             k_sample_star<3><<<cdiv(n1, 256), 256, 0, s>>>(g, xs, us, ncores != nullptr, npts, seed, ust);
-        k_sample_stage<3><<<sample_stage_blocks(3, npts), 256, 0, s>>>(g, fs, npts, seed, ust, wn, wx, wl, hs, acc,
-                                                                     flags);
     }
+    const unsigned nb = sample_stage_blocks(g.d, npts);
+#define WTT_SSTAGE(ND_, LW_) \
+    k_sample_stage<ND_, LW_><<<nb, 256, 0, s>>>(g, fs, npts, seed, ust, wn, wx, wl, hs, acc, flags)
+    if (g.law == kLawEuler) {
+        if (g.d == 2) WTT_SSTAGE(2, kLawEuler); else WTT_SSTAGE(3, kLawEuler);
+    } else if (g.law == kLawLinAdv) {
+        if (g.d == 2) WTT_SSTAGE(2, kLawLinAdv); else WTT_SSTAGE(3, kLawLinAdv);
+    } else {
+        if (g.d == 2) WTT_SSTAGE(2, kLawBurgers); else WTT_SSTAGE(3, kLawBurgers);
+    }
+#undef WTT_SSTAGE
     WTT_HIP(hipGetLastError());
 }
 

@@ -47,7 +47,11 @@ class wenott_opts(ctypes.Structure):
                 ("rank_cap", ctypes.c_int32), ("probe_points", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("alpha_mode", ctypes.c_int32), ("use_proposal", ctypes.c_int32), ("alpha_given", ctypes.c_double),
                 ("rounds_per_stage", ctypes.c_int32), ("graph_mode", ctypes.c_int32), ("scheme", ctypes.c_int32),
-                ("conv_slack", ctypes.c_double)]
+                ("conv_slack", ctypes.c_double), ("law", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("cross_ratio", ctypes.c_double)]
+
+
+LAW_EULER, LAW_LINADV, LAW_BURGERS = 0, 1, 2
 
 
 class wenott_info(ctypes.Structure):
@@ -434,6 +438,12 @@ class Solver:
         self.flow = flow
         self.n = tuple(flow.n)
         self.ncomp = flow.ncomp
+        law = getattr(flow, "law", LAW_EULER)
+        if opts is None:
+            opts = default_opts(law=law)
+        elif opts.law != law:
+            opts = wenott_opts.from_buffer_copy(opts)
+            opts.law = law
         self.ctx = wenott_init(flow.cores, flow.n, flow.lo, flow.hi, flow.gamma, flow.bc, opts, stream)
         _live.add(self)
 

@@ -12,7 +12,8 @@ def dense_of_cores(cores):
 
 def oracle_problem(flow):
     bcs = tuple(oracle.BC_PERIODIC if b == 0 else oracle.BC_TRANSMISSIVE for b in flow.bc)
-    return oracle.Problem(flow.n, flow.lo, flow.hi, bcs, gamma=flow.gamma)
+    model = {0: oracle.EULER, 1: oracle.LINADV, 2: oracle.BURGERS}[getattr(flow, "law", 0)]
+    return oracle.Problem(flow.n, flow.lo, flow.hi, bcs, gamma=flow.gamma, model=model)
 
 
 def rel_err(a, b):

@@ -35,10 +35,18 @@ class Flow:
     note: str = ""
     # density of the exact solution on the grid at time t, where one is known in closed form
     exact_rho: object = None
+    # conservation law: 0 Euler (ndim + 2 components), 1 linear advection, 2 Burgers (one)
+    law: int = 0
+    # C_eps of the dynamic eps_TT when it is given rather than fixed by eps(0) = eps0 (0: not given)
+    c_eps: float = 0.0
+    # fixed time step, when the workload prescribes one rather than a CFL number (0: none)
+    fixed_dt: float = 0.0
+    # the whole exact solution on the grid at time t, [ncomp][cells], where known (scalar laws)
+    exact: object = None
 
     @property
     def ncomp(self):
-        return self.ndim + 2
+        return self.ndim + 2 if self.law == 0 else 1
 
     @property
     def h(self):
@@ -406,6 +414,55 @@ def config5_tilted_sod_3d(n: int = 512, seed: int = 0) -> Flow:
                 t_end=0.1, cfl=0.5, eps_mode=1, eps0=1e-6,
                 note=f"seed {seed}, theta {math.degrees(theta):.3f} deg about {'+' if sign > 0 else '-'}e_{axis}",
                 exact_rho=exact_rho)
+
+
+def scalar_linadv_3d(n: int = 40) -> Flow:
+    """3D linear advection u_t + u_x + u_y + u_z = 0 of u0 = sin(2 pi (x+y+z)) on the periodic
+    unit cube (Sec. 5.1): one component, TT rank 2, dt = h^{5/3}, T = 0.1, dynamic eps_TT with
+    C_eps = 500. Exact solution: u0 translated by t (1, 1, 1)."""
+    lo, hi = (0.0,) * 3, (1.0,) * 3
+    h = 1.0 / n
+    xs = [(np.arange(n) + 0.5) * h for _ in range(3)]
+    k = 2.0 * math.pi
+    u = _sin_plane_term(xs, (k, k, k), 0.0, 1.0)
+
+    def exact(t):
+        s = xs[0][:, None, None] + xs[1][None, :, None] + xs[2][None, None, :]
+        return np.sin(k * (s - 3.0 * t))[None]
+
+    return Flow("linadv_3d", 3, (n, n, n), lo, hi, (PERIODIC,) * 3, 1.4, [u], t_end=0.1, cfl=0.0,
+                eps_mode=1, eps0=0.0, note="u0=sin(2pi(x+y+z)), C_eps=500, dt=h^(5/3)", law=1,
+                c_eps=500.0, fixed_dt=h ** (5.0 / 3.0), exact=exact)
+
+
+def burgers_exact(xi, t):
+    """Solution of u_t + sum_d (u^2/2)_{x_d} = 0 with u0 = 0.5 + 0.5 sin(2 pi xi), xi = x+y+z,
+    before the characteristics cross (t < 1/(3 pi)): u = u0(xi - 3 u t), solved by Newton."""
+    u = 0.5 + 0.5 * np.sin(2.0 * math.pi * xi)
+    for _ in range(100):
+        a = 2.0 * math.pi * (xi - 3.0 * u * t)
+        g = u - (0.5 + 0.5 * np.sin(a))
+        u = u - g / (1.0 + 3.0 * math.pi * t * np.cos(a))
+    return u
+
+
+def scalar_burgers_3d(n: int = 40) -> Flow:
+    """3D Burgers u_t + u u_x + u u_y + u u_z = 0 of u0 = 0.5 + 0.5 sin(2 pi (x+y+z)) on the
+    periodic unit cube (Sec. 5.2): one component, initial TT rank 3, dt = h^{5/3},
+    T = 1/(12 pi), dynamic eps_TT with C_eps = 10."""
+    lo, hi = (0.0,) * 3, (1.0,) * 3
+    h = 1.0 / n
+    xs = [(np.arange(n) + 0.5) * h for _ in range(3)]
+    k = 2.0 * math.pi
+    u = _concat_terms([_const_term(xs, 0.5), _sin_plane_term(xs, (k, k, k), 0.0, 0.5)])
+
+    def exact(t):
+        s = xs[0][:, None, None] + xs[1][None, :, None] + xs[2][None, None, :]
+        return burgers_exact(s, t)[None]
+
+    return Flow("burgers_3d", 3, (n, n, n), lo, hi, (PERIODIC,) * 3, 1.4, [u], t_end=1.0 / (12.0 * math.pi),
+                cfl=0.0, eps_mode=1, eps0=0.0, note="u0=0.5+0.5sin(2pi(x+y+z)), C_eps=10, dt=h^(5/3)", law=2,
+                c_eps=10.0, fixed_dt=h ** (5.0 / 3.0), exact=exact)
 
 
 def random_positive_tt(n, rank: int, seed: int, amp: float = 0.2, bc=None, rough: bool = False) -> Flow:
