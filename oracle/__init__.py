@@ -25,7 +25,7 @@ _LIB = os.path.join(_BUILD, "liboracle.so")
 _SRC = os.path.join(_HERE, "weno_oracle.c")
 
 OK, EINVAL, ENOMEM, ENONPHYS = 0, -1, -2, -5
-BC_PERIODIC, BC_TRANSMISSIVE = 0, 1
+BC_PERIODIC, BC_TRANSMISSIVE, BC_SYMMETRY, BC_INFLOW = 0, 1, 2, 3
 EULER, LINADV, BURGERS = 0, 1, 2
 
 
@@ -43,7 +43,8 @@ def build(force: bool = True) -> str:
 
 class _Problem(ctypes.Structure):
     _fields_ = [("model", ctypes.c_int), ("ndim", ctypes.c_int), ("n", ctypes.c_int64 * 3),
-                ("h", ctypes.c_double * 3), ("gamma", ctypes.c_double), ("bc", ctypes.c_int * 3)]
+                ("h", ctypes.c_double * 3), ("gamma", ctypes.c_double), ("bc", (ctypes.c_int * 2) * 3),
+                ("inflow", ((ctypes.c_double * 5) * 2) * 3)]
 
 
 _lib = None
@@ -64,6 +65,8 @@ def _load():
         lib.or_ssprk3.argtypes = [P, ctypes.c_double, ctypes.c_int, dp, dp]
         lib.or_run.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_double, dp,
                                ctypes.POINTER(ctypes.c_int64)]
+        lib.or_inflow_conserved.argtypes = [P, dp, dp]
+        lib.or_inflow_conserved.restype = None
         for f in (lib.or_alpha, lib.or_interface_flux, lib.or_rhs, lib.or_rhs_naive, lib.or_ssprk3, lib.or_run):
             f.restype = ctypes.c_int
         _lib = lib
@@ -85,26 +88,48 @@ class Problem:
     """A dense problem on a uniform cell-centred grid.
 
     ``n`` are the interior cells per dimension, ``lo``/``hi`` the domain box, ``bc`` one
-    boundary type per dimension (both sides alike).
+    boundary type per dimension, or a (low, high) pair of them (periodic only in pairs).
+    ``inflow`` maps (dimension, side) of each BC_INFLOW side to its primitive state
+    (rho, u_1..u_ndim, p) for the Euler law or (u,) for a scalar law (Sec. 4.5.2).
     """
 
-    def __init__(self, n, lo, hi, bc, gamma: float = 1.4, model: int = EULER):
+    def __init__(self, n, lo, hi, bc, gamma: float = 1.4, model: int = EULER, inflow=None):
         self.ndim = len(n)
         self.n = tuple(int(v) for v in n)
         self.lo = tuple(float(v) for v in lo)
         self.hi = tuple(float(v) for v in hi)
         self.h = tuple((b - a) / m for a, b, m in zip(self.lo, self.hi, self.n))
-        self.bc = tuple(int(b) for b in bc)
+        self.bc = tuple((int(b), int(b)) if np.ndim(b) == 0 else (int(b[0]), int(b[1])) for b in bc)
         self.gamma = float(gamma)
         self.model = int(model)
         self.ncomp = self.ndim + 2 if model == EULER else 1
+        inflow = dict(inflow or {})
         p = _Problem()
         p.model, p.ndim, p.gamma = self.model, self.ndim, self.gamma
         for d in range(3):
             p.n[d] = self.n[d] if d < self.ndim else 1
             p.h[d] = self.h[d] if d < self.ndim else 1.0
-            p.bc[d] = self.bc[d] if d < self.ndim else 0
+            for side in range(2):
+                p.bc[d][side] = self.bc[d][side] if d < self.ndim else 0
+        for d, (b0, b1) in enumerate(self.bc):
+            if (b0 == BC_PERIODIC) != (b1 == BC_PERIODIC) or not all(0 <= b <= 3 for b in (b0, b1)):
+                raise ValueError(f"bad boundary pair {self.bc[d]} in dimension {d}")
+            for side, b in enumerate((b0, b1)):
+                if b == BC_INFLOW:
+                    prim = np.ascontiguousarray(inflow.pop((d, side)), dtype=np.float64)
+                    if prim.shape != (self.ncomp,):
+                        raise ValueError("inflow state needs ncomp primitive values")
+                    q = np.zeros(5)
+                    _load().or_inflow_conserved(ctypes.byref(p), _dp(prim), _dp(q))
+                    for c in range(self.ncomp):
+                        p.inflow[d][side][c] = q[c]
+        if inflow:
+            raise ValueError(f"inflow states given for sides that are not BC_INFLOW: {sorted(inflow)}")
         self._p = p
+
+    def inflow_conserved(self, d: int, side: int) -> np.ndarray:
+        """The conserved ghost state of an inflow side."""
+        return np.array([self._p.inflow[d][side][c] for c in range(self.ncomp)])
 
     @property
     def shape(self):

@@ -16,8 +16,11 @@
  *     d = (3/10, 3/5, 1/10) and eps = dx^2 (Sec. 2.2); the f^- side is the mirror image
  *     of the f^+ side (the paper defers it to Shu 1998);
  *   - SSP-RK3 in Shu-Osher form (Sec. 2.2 and Sec. 4.4, eq. tt-ssprk3 without rounding);
- *   - ghost layers of three cells per side with periodic copies (Sec. 4.5.1) or, for the
- *     transmissive boundaries the paper does not describe, zero-order extrapolation.
+ *   - ghost layers of three cells per side (Sec. 4.5): periodic copies (Sec. 4.5.1); a
+ *     symmetry plane mirrors the interior cells with the momentum normal to it negated
+ *     (Sec. 4.5.3); an inflow side holds a constant state in its ghost cells, the full-tensor
+ *     value of the paper's zeroed ghost slices plus the rank-1 boundary TT (Sec. 4.5.2); for
+ *     the transmissive boundaries the paper does not describe, zero-order extrapolation.
  *
  * Two scalar laws are included for the paper's Tables 1 and 2: 3D linear advection
  * u_t + u_x + u_y + u_z = 0 and 3D Burgers u_t + u u_x + u u_y + u u_z = 0 (Sec. 5.1, 5.2).
@@ -33,7 +36,7 @@
 #include <string.h>
 
 enum { OR_OK = 0, OR_EINVAL = -1, OR_ENOMEM = -2, OR_ENONPHYS = -5 };
-enum { OR_BC_PERIODIC = 0, OR_BC_TRANSMISSIVE = 1 };
+enum { OR_BC_PERIODIC = 0, OR_BC_TRANSMISSIVE = 1, OR_BC_SYMMETRY = 2, OR_BC_INFLOW = 3 };
 enum { OR_EULER = 0, OR_LINADV = 1, OR_BURGERS = 2 };
 
 /* Problem description passed from Python (ctypes) as flat arrays. */
@@ -43,7 +46,8 @@ typedef struct {
     int64_t n[3];   /* interior cells per dimension */
     double h[3];    /* grid spacing per dimension */
     double gamma;   /* ratio of specific heats (Euler only) */
-    int bc[3];      /* boundary type per dimension (both sides equal) */
+    int bc[3][2];   /* boundary type per dimension and side (0 low, 1 high) */
+    double inflow[3][2][5]; /* conserved state of the ghost cells of an inflow side */
 } or_problem;
 
 static int ncomp_of(const or_problem *p) { return p->model == OR_EULER ? p->ndim + 2 : 1; }
@@ -54,15 +58,52 @@ static int64_t ncell_of(const or_problem *p) {
     return c;
 }
 
-/* Ghost-cell index map (Sec. 4.5): periodic wraps, transmissive clamps. */
-static int64_t ghost_map(int64_t i, int64_t n, int bc) {
-    if (bc == OR_BC_PERIODIC) {
+/* Interior cell whose values a cell i (-3 <= i < n + 3) of a grid line takes (Sec. 4.5):
+ * itself inside; periodic wraps; a symmetry plane mirrors (ghost -1-l <-> interior l at the
+ * low side, n+l <-> n-1-l at the high side); transmissive clamps. An inflow ghost takes no
+ * interior cell (its state is the side's inflow state); the clamp is returned for it. */
+static int64_t ghost_map(int64_t i, int64_t n, const int bc[2]) {
+    if (i >= 0 && i < n) return i;
+    int b = bc[i >= n];
+    if (b == OR_BC_PERIODIC) {
         int64_t r = i % n;
         return r < 0 ? r + n : r;
     }
-    if (i < 0) return 0;
-    if (i >= n) return n - 1;
-    return i;
+    if (b == OR_BC_SYMMETRY) return i < 0 ? -1 - i : 2 * n - 1 - i;
+    return i < 0 ? 0 : n - 1;
+}
+
+/* Conserved state q of cell i along direction dir of the line starting at interior offset
+ * base (stride st): the interior values of ghost_map's cell, with the momentum normal to a
+ * symmetry plane negated, or the inflow state of an inflow side. */
+static void line_state(const or_problem *p, const double *U, int64_t base, int64_t st, int dir, int64_t i,
+                       double *q) {
+    int ncomp = ncomp_of(p);
+    int64_t nc = ncell_of(p), n = p->n[dir];
+    int ghost = i < 0 || i >= n, side = i >= n;
+    int b = p->bc[dir][side];
+    if (ghost && b == OR_BC_INFLOW) {
+        for (int c = 0; c < ncomp; ++c) q[c] = p->inflow[dir][side][c];
+        return;
+    }
+    int64_t j = ghost_map(i, n, p->bc[dir]);
+    for (int c = 0; c < ncomp; ++c) q[c] = U[(int64_t)c * nc + base + j * st];
+    if (ghost && b == OR_BC_SYMMETRY && p->model == OR_EULER) q[1 + dir] = -q[1 + dir];
+}
+
+/* Conserved inflow state from the primitive one (rho, u_1..u_ndim, p) by the boundary
+ * relations of Sec. 4.5.2: rho u_d = rho_in u_d,in and rho E = p_in / (gamma - 1) +
+ * rho_in |u_in|^2 / 2; the scalar laws take u itself. */
+void or_inflow_conserved(const or_problem *p, const double *prim, double *q) {
+    if (p->model != OR_EULER) { q[0] = prim[0]; return; }
+    int nd = p->ndim;
+    double rho = prim[0], ke = 0.0;
+    q[0] = rho;
+    for (int d = 0; d < nd; ++d) {
+        q[1 + d] = rho * prim[1 + d];
+        ke += rho * prim[1 + d] * prim[1 + d];
+    }
+    q[nd + 1] = prim[nd + 1] / (p->gamma - 1.0) + 0.5 * ke;
 }
 
 /* Pressure from the ideal-gas law p = (gamma-1)(rhoE - |m|^2/(2 rho)) (Sec. 2.1). */
@@ -177,9 +218,8 @@ int or_interface_flux(const or_problem *p, double alpha, const double *U, int di
         double *fm = (double *)malloc(sizeof(double) * (size_t)(N + 6) * ncomp);
         if (!fp || !fm) { free(fp); free(fm); bad |= 2; continue; }
         for (int64_t g = -3; g < N + 3; ++g) {
-            int64_t i = ghost_map(g, N, p->bc[dir]);
             double q[5], f[5];
-            for (int c = 0; c < ncomp; ++c) q[c] = U[(int64_t)c * nc + base + i * st[dir]];
+            line_state(p, U, base, st[dir], dir, g, q);
             if (p->model == OR_EULER) {
                 if (!(q[0] > 0.0) || !(pressure(q, nd, p->gamma) > 0.0)) bad |= 1;
             }
@@ -309,13 +349,11 @@ int or_run(const or_problem *p, double t_end, double cfl, double fixed_dt, doubl
  * --------------------------------------------------------------------------------- */
 static void cell_state(const or_problem *p, const double *U, const int64_t idx[3], int dir, int64_t off,
                        double *q) {
-    int64_t nc = ncell_of(p), st[3], lin = 0;
+    int64_t st[3], base = 0;
     strides_of(p, st);
-    for (int d = 0; d < p->ndim; ++d) {
-        int64_t i = idx[d] + (d == dir ? off : 0);
-        lin += ghost_map(i, p->n[d], p->bc[d]) * st[d];
-    }
-    for (int c = 0; c < ncomp_of(p); ++c) q[c] = U[(int64_t)c * nc + lin];
+    for (int d = 0; d < p->ndim; ++d)
+        if (d != dir) base += idx[d] * st[d];
+    line_state(p, U, base, st[dir], dir, idx[dir] + off, q);
 }
 
 static double face_flux_naive(const or_problem *p, double alpha, const double *U, const int64_t idx[3], int dir,

@@ -419,3 +419,110 @@ def test_full_pivot_lu_recovers_low_rank_and_bounds_l(shape, rank):
     LI = L[rows, :]
     assert np.allclose(np.diag(LI), 1.0) and np.max(np.abs(np.triu(LI, 1))) <= 1e-12
     assert np.max(np.abs(L @ np.linalg.solve(LI, A[rows, :]) - A)) <= 1e-10 * np.max(np.abs(A))
+
+
+# --- Sec. 4.5.2-4.5.3: symmetry planes and inflow sides --------------------------------
+def _mirror_full(U, axis, momentum_sign):
+    """The half state U on the high half of a box, continued across its low face along `axis`:
+    cell -1-l of the full box holds cell l, the momentum component normal to the face negated."""
+    M = np.flip(U, axis=1 + axis).copy()
+    if momentum_sign:
+        M[1 + axis] = -M[1 + axis]
+    return np.concatenate([M, U], axis=1 + axis)
+
+
+@pytest.mark.parametrize("ndim,axis", [(1, 0), (2, 0), (2, 1), (3, 2)])
+def test_symmetry_plane_is_the_mirrored_full_box(ndim, axis):
+    """A symmetry plane at x_axis = 0 on [0, 1] equals the upper half of the problem on [-1, 1]
+    whose lower half is the mirror image (the momentum normal to the plane odd, everything else
+    even): one right-hand side bit for bit (the faces of the upper half see the same cell values),
+    and SSP-RK3 steps to rounding (the mirror is a symmetry of the Euler equations)."""
+    rng = np.random.default_rng(40 + 3 * ndim + axis)
+    n = tuple(14 if d == axis else 9 - d for d in range(ndim))
+    U = _random_state(n, rng)
+    bc_half = tuple((oracle.BC_SYMMETRY, oracle.BC_TRANSMISSIVE) if d == axis else oracle.BC_PERIODIC
+                    for d in range(ndim))
+    bc_full = tuple(oracle.BC_TRANSMISSIVE if d == axis else oracle.BC_PERIODIC for d in range(ndim))
+    half = oracle.Problem(n, (0.0,) * ndim, (1.0,) * ndim, bc_half)
+    nf = tuple(2 * m if d == axis else m for d, m in enumerate(n))
+    full = oracle.Problem(nf, tuple(-1.0 if d == axis else 0.0 for d in range(ndim)), (1.0,) * ndim, bc_full)
+    V = _mirror_full(U, axis, True)
+    upper = (slice(None),) + tuple(slice(n[axis], None) if d == axis else slice(None) for d in range(ndim))
+    a = full.alpha(V)
+    assert half.alpha(U) == a
+    assert np.array_equal(half.rhs(U, a), full.rhs(V, a)[upper])
+    assert np.array_equal(half.rhs(U, a, naive=True), full.rhs(V, a, naive=True)[upper])
+    for _ in range(3):
+        dt = 0.4 * min(half.h) / a
+        al = half.ssprk3(U, dt)
+        full.ssprk3(V, dt, alphas=al)
+        a = half.alpha(U)
+    assert np.max(np.abs(U - V[upper])) <= 1e-13 * np.max(np.abs(U))
+
+
+def test_symmetry_plane_high_side_and_scalar_mirror():
+    """The same at the high face of [-1, 0], and for a scalar law (mirrored without a sign)."""
+    rng = np.random.default_rng(44)
+    U = _random_state((16,), rng)
+    half = oracle.Problem((16,), (-1.0,), (0.0,), ((oracle.BC_TRANSMISSIVE, oracle.BC_SYMMETRY),))
+    full = oracle.Problem((32,), (-1.0,), (1.0,), (oracle.BC_TRANSMISSIVE,))
+    V = np.flip(_mirror_full(np.flip(U, axis=1).copy(), 0, True), axis=1).copy()
+    a = full.alpha(V)
+    assert np.array_equal(half.rhs(U, a), full.rhs(V, a)[:, :16])
+    u = U[:1].copy()
+    shalf = oracle.Problem((16,), (0.0,), (1.0,), ((oracle.BC_SYMMETRY, oracle.BC_TRANSMISSIVE),),
+                           model=oracle.BURGERS)
+    sfull = oracle.Problem((32,), (-1.0,), (1.0,), (oracle.BC_TRANSMISSIVE,), model=oracle.BURGERS)
+    v = _mirror_full(u, 0, False)
+    assert np.array_equal(shalf.rhs(u, 1.7), sfull.rhs(v, 1.7)[:, 16:])
+
+
+def test_inflow_state_from_primitives_hand_values():
+    P = oracle.Problem((4, 4), (0, 0), (1, 1), ((oracle.BC_INFLOW, oracle.BC_TRANSMISSIVE), oracle.BC_PERIODIC),
+                       gamma=1.4, inflow={(0, 0): (1.2, 0.5, -0.3, 2.0)})
+    # rho, rho u, rho v, p / (gamma - 1) + rho |u|^2 / 2 = 5 + 0.6 * 0.34
+    assert np.allclose(P.inflow_conserved(0, 0), [1.2, 0.6, -0.36, 5.204], rtol=0, atol=1e-15)
+    S = oracle.Problem((4,), (0,), (1,), ((oracle.BC_TRANSMISSIVE, oracle.BC_INFLOW),), model=oracle.LINADV,
+                       inflow={(0, 1): (0.25,)})
+    assert S.inflow_conserved(0, 1).tolist() == [0.25]
+    with pytest.raises(ValueError):
+        oracle.Problem((4,), (0,), (1,), ((oracle.BC_PERIODIC, oracle.BC_INFLOW),), inflow={(0, 1): (1, 0, 1)})
+    with pytest.raises(ValueError):
+        oracle.Problem((4,), (0,), (1,), (oracle.BC_TRANSMISSIVE,), inflow={(0, 0): (1, 0, 1)})
+
+
+@pytest.mark.parametrize("side", [0, 1])
+def test_inflow_side_is_three_explicit_cells(side):
+    """An inflow side holds the inflow state in its three ghost cells (the zeroed ghost slices
+    plus the rank-1 boundary TT of Sec. 4.5.2): the right-hand side of the interior equals, bit for
+    bit, the one of a box extended by three cells that hold that state (their own ghosts never
+    reach an interior face)."""
+    rng = np.random.default_rng(50 + side)
+    n = (13, 7)
+    prim = (0.8, 1.3, 0.2, 0.6)
+    U = _random_state(n, rng)
+    bcs = (oracle.BC_INFLOW, oracle.BC_TRANSMISSIVE) if side == 0 else (oracle.BC_TRANSMISSIVE, oracle.BC_INFLOW)
+    P = oracle.Problem(n, (0, 0), (1.3, 1.0), (bcs, oracle.BC_PERIODIC), inflow={(0, side): prim})
+    h = P.h[0]
+    lo, hi = (0.0 - 3 * h, 0.0) if side == 0 else (0.0, 1.3 + 3 * h)
+    ext = oracle.Problem((16, 7), (lo, 0), (hi if side else 1.3, 1.0), (oracle.BC_TRANSMISSIVE, oracle.BC_PERIODIC))
+    q = P.inflow_conserved(0, side)
+    block = np.broadcast_to(q[:, None, None], (4, 3, 7))
+    V = np.concatenate([block, U], axis=1) if side == 0 else np.concatenate([U, block], axis=1)
+    V = np.ascontiguousarray(V)
+    a = P.alpha(U)
+    inner = slice(3, None) if side == 0 else slice(0, 13)
+    assert np.array_equal(P.rhs(U, a), ext.rhs(V, a)[:, inner])
+    assert np.array_equal(P.rhs(U, a, naive=True), ext.rhs(V, a, naive=True)[:, inner])
+
+
+def test_uniform_flow_through_an_inflow_side_stays_exact():
+    prim = (1.1, 0.7, -0.2, 0.9)
+    P = oracle.Problem((10, 6), (0, 0), (1, 1), ((oracle.BC_INFLOW, oracle.BC_TRANSMISSIVE), oracle.BC_PERIODIC),
+                       inflow={(0, 0): prim})
+    q = P.inflow_conserved(0, 0)
+    U = np.ascontiguousarray(np.broadcast_to(q[:, None, None], (4, 10, 6)))
+    U0 = U.copy()
+    for _ in range(3):
+        P.ssprk3(U, 0.01)
+    assert np.array_equal(U, U0)
