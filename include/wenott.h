@@ -41,10 +41,21 @@ typedef enum {
     WENOTT_ENOTBUILT = -7 /* feature not available in this build */
 } wenott_status;
 
-/* Boundary treatment per grid side (Sec. 4.5). PERIODIC copies core slices (Sec. 4.5.1);
- * TRANSMISSIVE is zero-order extrapolation (the paper does not describe it). Both are
- * realised as index maps of the ghost cells, never as stored ghost slices. */
-typedef enum { WENOTT_BC_PERIODIC = 0, WENOTT_BC_TRANSMISSIVE = 1 } wenott_bc;
+/* Boundary treatment per grid side (Sec. 4.5), each with three ghost cells. PERIODIC copies
+ * core slices (Sec. 4.5.1), on both sides of a dimension or neither. TRANSMISSIVE is zero-order
+ * extrapolation (the paper does not describe it). SYMMETRY is a symmetry plane (Sec. 4.5.3): the
+ * ghosts mirror the cells next to the face, ghost -1-l taking cell l, with the momentum normal
+ * to the face negated (Euler law). INFLOW (Sec. 4.5.2) holds the side's constant inflow state
+ * in its ghosts, the full-tensor value of the paper's zeroed ghost slices plus its rank-1
+ * boundary TT; the state is given by wenott_set_inflow. All of them are realised in the
+ * gathers as index maps and values of the ghost cells, never as stored ghost slices, so no
+ * boundary TT is added and no rounding is spent on it. */
+typedef enum {
+    WENOTT_BC_PERIODIC = 0,
+    WENOTT_BC_TRANSMISSIVE = 1,
+    WENOTT_BC_SYMMETRY = 2,
+    WENOTT_BC_INFLOW = 3
+} wenott_bc;
 
 /* The conservation law the state obeys. EULER: the compressible Euler system with the ideal-gas
  * law (Sec. 2.1), ncomp = ndim + 2 (rho, momenta, total energy). The two scalar laws of Sec. 5.1
@@ -166,8 +177,9 @@ void wenott_default_opts(wenott_opts *o);
  *   grid:   the cell-centred grid; state mode sizes must equal grid.n.
  *   gamma:  ratio of specific heats (Sec. 2.1), > 1 (Euler law; not used by the scalar laws).
  *   The law comes from opts->law; state->ncomp must be its component count.
- *   bc:     6 entries, bc[2*d + side] (side 0 = low, 1 = high); both sides of a dimension
- *           must agree in this build.
+ *   bc:     6 entries, bc[2*d + side] (side 0 = low, 1 = high), wenott_bc values; a periodic
+ *           side needs a periodic opposite side. An INFLOW side needs its state from
+ *           wenott_set_inflow before the first step.
  *   opts:   NULL for defaults.
  *   hip_stream: a hipStream_t (NULL = null stream).
  * Errors: EINVAL on inconsistent shapes/ranks/options, ENOMEM, EHIP.
@@ -264,6 +276,13 @@ wenott_status wenott_max_wavespeed(wenott_ctx *ctx, double *alpha);
  * written first, so nothing needs clearing): calls that overlap on one GPU, on any contexts or
  * streams, race. Synchronises; the first stage of the next step reuses the value. */
 wenott_status wenott_max_wavespeed_noalloc(wenott_ctx *ctx, double *alpha);
+
+/* The inflow state of side `side` (0 low, 1 high) of dimension `dim`, a WENOTT_BC_INFLOW side
+ * (Sec. 4.5.2): prim holds the primitive values rho, u_1..u_ndim, p (Euler law; ndim + 2 host
+ * doubles, rho > 0, p > 0) or u (scalar law; one double). The ghost cells of the side take the
+ * conserved state rho, rho u_d, p / (gamma - 1) + rho |u|^2 / 2 from the next step on; it may be
+ * changed between steps. Errors: EINVAL for a side that is not INFLOW or a non-physical state. */
+wenott_status wenott_set_inflow(wenott_ctx *ctx, int32_t dim, int32_t side, const double *prim);
 
 /* Current eps_TT of the dynamic rule (eq. eps-tt-formula) or the fixed one. */
 wenott_status wenott_current_eps(wenott_ctx *ctx, double *eps);
@@ -367,6 +386,7 @@ wenott_status wenott_get_cross_log(wenott_ctx *ctx, float *x, int32_t *rank_clas
  * ---------------------------------------------------------------------------------- */
 typedef struct wenott_dense wenott_dense;
 
+/* Euler law only; bc as for wenott_init, with periodic, transmissive and symmetry sides. */
 wenott_status wenott_dense_init(wenott_dense **out, const wenott_grid *grid, double gamma, const int32_t *bc,
                                 void *hip_stream);
 /* exact max over the grid of |u| + a; ENONPHYS if rho <= 0 or p <= 0 anywhere. Synchronises. */

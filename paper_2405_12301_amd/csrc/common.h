@@ -51,12 +51,34 @@ __host__ __device__ inline int probe_coord(unsigned long long seed, long long e,
     return (int)(z % (unsigned long long)nj);
 }
 
+// Boundary code of one grid dimension: the low side's wenott_bc in bits 0-3, the high side's in
+// bits 4-7 (periodic only in pairs).
+__host__ __device__ inline int bc_code(int lo, int hi) { return lo | (hi << 4); }
+__host__ __device__ inline int bc_side(int bc, int hi) { return hi ? (bc >> 4) & 15 : bc & 15; }
+
+// Interior cell whose values cell i (-3 <= i < n + 3) of a grid line takes (Sec. 4.5): itself
+// inside; periodic wraps (Sec. 4.5.1); a symmetry plane mirrors, ghost -1-l <-> cell l at the low
+// side and n+l <-> n-1-l at the high side (Sec. 4.5.3); transmissive clamps. An inflow ghost takes
+// the side's constant state (Sec. 4.5.2); the clamp returned for it only keeps reads in bounds.
 __host__ __device__ inline int ghost_map(int i, int n, int bc) {
-    if (bc == WENOTT_BC_PERIODIC) {
+    if (i >= 0 && i < n) return i;
+    const int b = bc_side(bc, i >= n);
+    if (b == WENOTT_BC_PERIODIC) {
         int r = i % n;
         return r < 0 ? r + n : r;
     }
-    return i < 0 ? 0 : (i >= n ? n - 1 : i);
+    if (b == WENOTT_BC_SYMMETRY) return i < 0 ? -1 - i : 2 * n - 1 - i;
+    return i < 0 ? 0 : n - 1;
+}
+
+// What the value of cell i is beyond ghost_map's cell: kGhostPlain (that cell's values),
+// kGhostMirror (a symmetry ghost: the momentum normal to the plane negated), kGhostInflow (the
+// side's inflow state).
+enum { kGhostPlain = 0, kGhostMirror = 1, kGhostInflow = 2 };
+__host__ __device__ inline int ghost_kind(int i, int n, int bc) {
+    if (i >= 0 && i < n) return kGhostPlain;
+    const int b = bc_side(bc, i >= n);
+    return b == WENOTT_BC_SYMMETRY ? kGhostMirror : (b == WENOTT_BC_INFLOW ? kGhostInflow : kGhostPlain);
 }
 
 // ------------------------------------------------------------------ linalg.hip
@@ -196,9 +218,21 @@ struct FiberGeom {
     int bc[kMaxDim];            // boundary code per dimension
     double gamma, alpha, eps_w; // EOS, LF alpha, WENO epsilon (h_dir^2)
     const double *alpha_dev;    // if set, alpha is read from this device scalar instead
+    double qin[kMaxDim][2][5];  // conserved ghost state of each inflow side [dim][low/high][c]
 };
 
 __device__ inline double geom_alpha(const FiberGeom &g) { return g.alpha_dev ? *g.alpha_dev : g.alpha; }
+
+// Value of component c at cell `raw` along mode m (maybe a ghost) from the value v read at
+// ghost_map's cell: negated for the normal momentum of a symmetry plane (Euler law), the inflow
+// state on an inflow side.
+template <typename T>
+__device__ inline T ghost_fix(const FiberGeom &g, int m, int raw, int c, T v) {
+    const int kind = ghost_kind(raw, g.n[m], g.bc[m]);
+    if (kind == kGhostMirror && g.law == kLawEuler && c == 1 + m) return -v;
+    if (kind == kGhostInflow) return T(g.qin[m][raw >= g.n[m]][c]);
+    return v;
+}
 
 // 1/x, 1/sqrt(x) and sqrt(x) for x > 0 (nr_sqrt(0) = 0) to about 1 ulp: the hardware estimates
 // (about 23 correct bits) refined by two Newton-Raphson steps each, for r = 1/x
@@ -253,6 +287,15 @@ struct StageArgsT {
 template <typename T>
 void stage_block(hipStream_t s, const FiberGeom &g, int p, int q, const StageArgsT<T> &a, double *out, long long sa,
                  long long si, long long sb, long long sc, int *flags);
+
+// Writes the conserved inflow state of g.qin into the gathered block W ([c][s][a][i][b], component
+// stride cs, shift stride ss, block p x Nk x q) at the cells on an inflow side of mode `mode`:
+// `pairs` (device, 3 ints each: shift s, pivot index, side 0 low / 1 high) list the (shift, pivot)
+// combinations of the left interface (right = false, pivot a) or the right one (right = true,
+// pivot b) whose shifted cell is an inflow ghost; their interface rows are zero (iface).
+template <typename T>
+void inflow_fill(hipStream_t s, const FiberGeom &g, int mode, int npairs, const int *pairs, bool right, int p, int Nk,
+                 int q, long long cs, long long ss, T *W);
 
 // FP32 batched GEMM C = A B (row-major) on the matrix cores (v_mfma_f32_16x16x4f32).
 void gemm_f32(hipStream_t s, int M, int N, int K, const float *A, int lda, const float *B, int ldb, float *C, int ldc,

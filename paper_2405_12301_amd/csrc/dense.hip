@@ -74,6 +74,7 @@ __global__ __launch_bounds__(256) void k_face_flux(DenseGeom g, int dir, double 
         double q[NC];
 #pragma unroll
         for (int c = 0; c < NC; ++c) q[c] = U[c * g.ncell + idx];
+        if (ghost_kind(m - 3 + s, g.n[dir], g.bc[dir]) == kGhostMirror) q[1 + dir] = -q[1 + dir];
         const double inv = 1.0 / q[0];
         double ke = 0.0;
 #pragma unroll
@@ -271,9 +272,13 @@ wenott_status wenott_dense_init(wenott_dense **out, const wenott_grid *grid, dou
         long long ncell = 1;
         for (int k = 0; k < d; ++k) {
             WTT_REQUIRE(grid->n[k] >= 3 && grid->hi[k] > grid->lo[k], WENOTT_EINVAL, "bad grid");
-            WTT_REQUIRE(bc[2 * k] == bc[2 * k + 1] && (bc[2 * k] == 0 || bc[2 * k] == 1), WENOTT_EINVAL, "bad bc");
+            for (int side = 0; side < 2; ++side)
+                WTT_REQUIRE(bc[2 * k + side] >= WENOTT_BC_PERIODIC && bc[2 * k + side] <= WENOTT_BC_SYMMETRY,
+                            WENOTT_EINVAL, "the dense comparator takes periodic, transmissive and symmetry sides");
+            WTT_REQUIRE((bc[2 * k] == WENOTT_BC_PERIODIC) == (bc[2 * k + 1] == WENOTT_BC_PERIODIC), WENOTT_EINVAL,
+                        "a periodic side needs a periodic opposite side");
             c->g.n[k] = (int)grid->n[k];
-            c->g.bc[k] = bc[2 * k];
+            c->g.bc[k] = bc_code(bc[2 * k], bc[2 * k + 1]);
             c->h[k] = (grid->hi[k] - grid->lo[k]) / grid->n[k];
             ncell *= grid->n[k];
         }

@@ -291,7 +291,9 @@ struct wenott_ctx {
     int N[kMaxDim] = {};
     double lo[kMaxDim] = {}, hi[kMaxDim] = {}, h[kMaxDim] = {};
     double gamma = 1.4;
-    int bc[kMaxDim] = {};
+    int bc[kMaxDim] = {};         // bc_code(low, high) per dimension
+    double qin[kMaxDim][2][5] = {};  // conserved inflow state per inflow side
+    bool qin_set[kMaxDim][2] = {};
     wenott_opts o{};
     hipStream_t s = nullptr;
     hipEvent_t ev_wait = nullptr;  // host_wait's marker on s
@@ -496,6 +498,51 @@ void to_dense_dev(wenott_ctx *c, const TT &U, double *out) {
                c->gamma, out, nullptr, nblocks, c->d_flags);
 }
 
+// ---------------------------------------------------------------- boundary sides
+void require_inflow_states(const wenott_ctx *c) {
+    for (int k = 0; k < c->d; ++k)
+        for (int side = 0; side < 2; ++side)
+            WTT_REQUIRE(bc_side(c->bc[k], side) != WENOTT_BC_INFLOW || c->qin_set[k][side], WENOTT_EINVAL,
+                        "an inflow side has no state (wenott_set_inflow)");
+}
+
+bool has_inflow(const wenott_ctx *c, int m) {
+    return bc_side(c->bc[m], 0) == WENOTT_BC_INFLOW || bc_side(c->bc[m], 1) == WENOTT_BC_INFLOW;
+}
+
+// (shift, pivot, side) triples of the index tuples of `set` (mode m at tuple position pos) whose
+// shifted cell v - 3 + s (s < S) along m lies on an inflow side of m.
+std::vector<int> inflow_pairs(const wenott_ctx *c, const std::vector<int> &v, int len, int count, int pos, int m,
+                              int S) {
+    std::vector<int> out;
+    const int n = c->N[m];
+    for (int t = 0; t < count; ++t)
+        for (int sh = 0; sh < S; ++sh) {
+            const int raw = v[(size_t)t * len + pos] - 3 + sh;
+            if (ghost_kind(raw, n, c->bc[m]) != kGhostInflow) continue;
+            out.push_back(sh);
+            out.push_back(t);
+            out.push_back(raw >= n ? 1 : 0);
+        }
+    return out;
+}
+
+// The inflow state into a gathered block W ([c][S][p][Nk][q]) shifted along mode m != k, after
+// its interface rows of the inflow cells were zeroed.
+template <typename T>
+void fill_inflow_block(wenott_ctx *c, const FiberGeom &g, int m, int k, const ISet &L, const ISet &Rs, int S, int Nk,
+                       T *W) {
+    if (m < 0 || m == k || !has_inflow(c, m)) return;
+    const bool right = m > k;
+    const ISet &set = right ? Rs : L;
+    const std::vector<int> pr = inflow_pairs(c, set.v, set.len, set.count, right ? m - k - 1 : m, m, S);
+    if (pr.empty()) return;
+    const int p = L.count, q = Rs.count;
+    const long long blk = (long long)p * Nk * q;
+    inflow_fill<T>(c->s, g, m, (int)pr.size() / 3, c->ring.put(pr.data(), pr.size()), right, p, Nk, q, S * blk, blk,
+                   W);
+}
+
 // ---------------------------------------------------------------- block evaluation
 // Flux block Fhat_dir(I_<k[a], i, J_>k[b], c) written with strides (L->R or R->L unfolding).
 void eval_block(wenott_ctx *c, const TT &U, int dir, int k, const ISet &L, const ISet &Rs, double alpha, bool lr,
@@ -504,7 +551,7 @@ void eval_block(wenott_ctx *c, const TT &U, int dir, int k, const ISet &L, const
     FiberGeom g{};
     g.d = d; g.ncomp = nc; g.dir = dir; g.k = k;
     for (int j = 0; j < d; ++j) { g.n[j] = U.N[j]; g.bc[j] = c->bc[j]; }
-    g.law = c->law; g.gamma = c->gamma; g.alpha = alpha; g.eps_w = c->h[dir] * c->h[dir];
+    g.law = c->law; std::memcpy(g.qin, c->qin, sizeof g.qin); g.gamma = c->gamma; g.alpha = alpha; g.eps_w = c->h[dir] * c->h[dir];
     const int p = L.count, q = Rs.count;
     const int SL = dir < k ? 6 : 1, SR = dir > k ? 6 : 1, S = std::max(SL, SR);
     const int Rk = U.R[k], Rk1 = U.R[k + 1], Nk = U.N[k];
@@ -536,6 +583,7 @@ void eval_block(wenott_ctx *c, const TT &U, int dir, int k, const ISet &L, const
     b2.sB1 = (long long)SR * Rk1 * q; b2.sB2 = SR == 6 ? (long long)Rk1 * q : 0;
     b2.sC1 = S * wsz; b2.sC2 = wsz;
     gemm_f64(c->s, false, false, p * Nk, q, Rk1, 1.0, T, Rk1, Q, q, 0.0, W, q, b2);
+    if (dir != k) fill_inflow_block<double>(c, g, dir, k, L, Rs, 6, Nk, W);
 
     const int M = k == dir ? Nk + 1 : Nk;
     long long sa, si, sb, sc;
@@ -665,7 +713,7 @@ double sampled_residual(wenott_ctx *c, const TT &U, const FluxTT &F, int dir, do
     FiberGeom g{};
     g.d = d; g.ncomp = U.nc; g.dir = dir; g.k = 0;
     for (int j = 0; j < d; ++j) { g.n[j] = U.N[j]; g.bc[j] = c->bc[j]; }
-    g.law = c->law; g.gamma = c->gamma; g.alpha = alpha; g.eps_w = c->h[dir] * c->h[dir];
+    g.law = c->law; std::memcpy(g.qin, c->qin, sizeof g.qin); g.gamma = c->gamma; g.alpha = alpha; g.eps_w = c->h[dir] * c->h[dir];
     int *dp = c->sc.get<int>(S_PTS, (size_t)npts * d);
     sample_points(c->s, npts, d, F.M, rng.next(), dp);
     double *ust = c->sc.get<double>(S_UST, (size_t)npts * 6 * U.nc);
@@ -1017,7 +1065,7 @@ void eval_stage_block(wenott_ctx *c, const TT &X, const TT *Un, StageWeights w, 
     FiberGeom g{};
     g.d = d; g.ncomp = nc; g.dir = 0; g.k = k;
     for (int j = 0; j < d; ++j) { g.n[j] = X.N[j]; g.bc[j] = c->bc[j]; }
-    g.law = c->law; g.gamma = c->gamma; g.alpha = alpha; g.eps_w = 0.0; g.alpha_dev = c->alpha_dev;
+    g.law = c->law; std::memcpy(g.qin, c->qin, sizeof g.qin); g.gamma = c->gamma; g.alpha = alpha; g.eps_w = 0.0; g.alpha_dev = c->alpha_dev;
     const int p = L.count, q = Rs.count, Nk = X.N[k];
     const int *didxL = k > 0 ? c->ring.put(L.v.data(), L.v.size()) : nullptr;
     const int *didxR = k < d - 1 ? c->ring.put(Rs.v.data(), Rs.v.size()) : nullptr;
@@ -1149,7 +1197,9 @@ void eval_stage_block(wenott_ctx *c, const TT &X, const TT *Un, StageWeights w, 
         a.eps_w[dd] = a32.eps_w[dd] = c->h[dd] * c->h[dd];
         if (dd == k) continue;
         if (fp32) {
-            a32.Wd[dd] = gather32(X, dd, od == 0 ? S_F_WD0 : S_F_WD1);
+            float *W32 = gather32(X, dd, od == 0 ? S_F_WD0 : S_F_WD1);
+            fill_inflow_block<float>(c, g, dd, k, L, Rs, 7, Nk, W32);
+            a32.Wd[dd] = W32;
         } else {
             GatherJob &G = gj[ng];
             G.Y = &X; G.shift = dd;
@@ -1178,6 +1228,7 @@ void eval_stage_block(wenott_ctx *c, const TT &X, const TT *Un, StageWeights w, 
             if (gdir[i] < 0) {
                 a.WN = W;
             } else {
+                fill_inflow_block<double>(c, g, gdir[i], k, L, Rs, 7, Nk, W);
                 a.Wd[gdir[i]] = W;
                 if (first) {  // X at the block points is the unshifted (centre) slice of this gather
                     a.W0 = W + 3 * blk;
@@ -1214,7 +1265,7 @@ int sampled_stage_residual_launch(wenott_ctx *c, const TT &X, const TT *Un, Stag
     FiberGeom g{};
     g.d = d; g.ncomp = X.nc; g.dir = 0; g.k = 0;
     for (int j = 0; j < d; ++j) { g.n[j] = X.N[j]; g.bc[j] = c->bc[j]; }
-    g.law = c->law; g.gamma = c->gamma; g.alpha = alpha; g.alpha_dev = c->alpha_dev;
+    g.law = c->law; std::memcpy(g.qin, c->qin, sizeof g.qin); g.gamma = c->gamma; g.alpha = alpha; g.alpha_dev = c->alpha_dev;
     const unsigned long long seed = rng.next();
     const int SL = 7 * d + 1;
     double *ust = c->sc.get<double>(S_UST, (size_t)npts * SL * X.nc);
@@ -2125,14 +2176,16 @@ wenott_status wenott_init(wenott_ctx **out, const wenott_tt *state, const wenott
         for (int k = 0; k < d; ++k) {
             WTT_REQUIRE(grid->n[k] >= 3 && grid->n[k] <= (1 << 20), WENOTT_EINVAL, "grid size out of range");
             WTT_REQUIRE(grid->hi[k] > grid->lo[k], WENOTT_EINVAL, "empty box");
-            WTT_REQUIRE(bc[2 * k] == bc[2 * k + 1], WENOTT_EINVAL, "both sides of a dimension must agree");
-            WTT_REQUIRE(bc[2 * k] == WENOTT_BC_PERIODIC || bc[2 * k] == WENOTT_BC_TRANSMISSIVE, WENOTT_EINVAL,
-                        "unknown boundary type");
+            for (int side = 0; side < 2; ++side)
+                WTT_REQUIRE(bc[2 * k + side] >= WENOTT_BC_PERIODIC && bc[2 * k + side] <= WENOTT_BC_INFLOW,
+                            WENOTT_EINVAL, "unknown boundary type");
+            WTT_REQUIRE((bc[2 * k] == WENOTT_BC_PERIODIC) == (bc[2 * k + 1] == WENOTT_BC_PERIODIC), WENOTT_EINVAL,
+                        "a periodic side needs a periodic opposite side");
             c->N[k] = (int)grid->n[k];
             c->lo[k] = grid->lo[k];
             c->hi[k] = grid->hi[k];
             c->h[k] = (grid->hi[k] - grid->lo[k]) / grid->n[k];
-            c->bc[k] = bc[2 * k];
+            c->bc[k] = bc_code(bc[2 * k], bc[2 * k + 1]);
         }
         c->s = (hipStream_t)hip_stream;
         {
@@ -2248,6 +2301,7 @@ static void fill_view(wenott_ctx *c, const TT &X, wenott_tt *view) {
 wenott_status wenott_rhs(wenott_ctx *c, double alpha, wenott_tt *view) {
     if (!c || !view) return WENOTT_EINVAL;
     return run_guarded(c, [&] {
+        require_inflow_states(c);
         double t0 = seconds_now();
         reset_call_info(c);
         double a = alpha > 0.0 ? alpha : (c->o.alpha_mode == 2 ? c->o.alpha_given : alpha_now(c, c->U));
@@ -2285,6 +2339,7 @@ wenott_status wenott_rhs(wenott_ctx *c, double alpha, wenott_tt *view) {
 wenott_status wenott_rk3_step(wenott_ctx *c, double dt, double eps_in, const double *alphas) {
     if (!c || !(dt > 0.0)) return WENOTT_EINVAL;
     return run_guarded(c, [&] {
+        require_inflow_states(c);
         double t0 = seconds_now();
         reset_call_info(c);
         const double eps = eps_in > 0.0 ? eps_in : current_eps(c);
@@ -2409,6 +2464,7 @@ wenott_status wenott_batch_rk3_step(wenott_ctx **ctxs, int32_t n, const double *
                         "batched stepping runs the stage-cross scheme with one rounding per stage, without the "
                         "proposal or cross logging");
             for (int j = 0; j < i; ++j) WTT_REQUIRE(ctxs[j] != c, WENOTT_EINVAL, "a context appears twice");
+            require_inflow_states(c);
         }
         double t0 = seconds_now();
         std::vector<BState> bs(n);
@@ -2596,6 +2652,34 @@ wenott_status wenott_max_wavespeed_noalloc(wenott_ctx *c, double *alpha) {
         *alpha = status_alpha(c, 3);
         c->alpha_cache = *alpha;
         c->alpha_cache_valid = *alpha > 0.0;
+    });
+}
+
+wenott_status wenott_set_inflow(wenott_ctx *c, int32_t dim, int32_t side, const double *prim) {
+    if (!c || !prim) return WENOTT_EINVAL;
+    return run_guarded(c, [&] {
+        WTT_REQUIRE(dim >= 0 && dim < c->d && (side == 0 || side == 1), WENOTT_EINVAL, "no such side");
+        WTT_REQUIRE(bc_side(c->bc[dim], side) == WENOTT_BC_INFLOW, WENOTT_EINVAL, "the side is not an inflow side");
+        double q[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        if (c->law == WENOTT_LAW_EULER) {
+            // Sec. 4.5.2: rho, rho u_d = rho_in u_d,in, rho E = p_in / (gamma - 1) + rho_in |u_in|^2 / 2
+            const double rho = prim[0], p = prim[c->d + 1];
+            WTT_REQUIRE(rho > 0.0 && p > 0.0 && std::isfinite(rho) && std::isfinite(p), WENOTT_EINVAL,
+                        "non-physical inflow state");
+            double ke = 0.0;
+            q[0] = rho;
+            for (int j = 0; j < c->d; ++j) {
+                WTT_REQUIRE(std::isfinite(prim[1 + j]), WENOTT_EINVAL, "non-finite inflow velocity");
+                q[1 + j] = rho * prim[1 + j];
+                ke += rho * prim[1 + j] * prim[1 + j];
+            }
+            q[c->d + 1] = p / (c->gamma - 1.0) + 0.5 * ke;
+        } else {
+            WTT_REQUIRE(std::isfinite(prim[0]), WENOTT_EINVAL, "non-finite inflow value");
+            q[0] = prim[0];
+        }
+        for (int j = 0; j < 5; ++j) c->qin[dim][side][j] = q[j];
+        c->qin_set[dim][side] = true;
     });
 }
 

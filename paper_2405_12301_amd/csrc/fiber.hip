@@ -42,6 +42,15 @@ __device__ inline int mode_index(const FiberGeom &g, int mode, int v, int s, int
     return v;
 }
 
+// Factor of an interface entry whose shifted mode m sits at cell `raw` (maybe a ghost): -1 for
+// the normal momentum at a symmetry plane, 0 on an inflow side (whose constant state is written
+// into the gathered block afterwards, inflow_fill), else 1.
+__device__ inline double ghost_factor(const FiberGeom &g, int m, int raw, int c) {
+    const int kind = ghost_kind(raw, g.n[m], g.bc[m]);
+    if (kind == kGhostInflow) return 0.0;
+    return kind == kGhostMirror && g.law == kLawEuler && c == 1 + m ? -1.0 : 1.0;
+}
+
 __device__ inline void iface_entry(const FiberGeom &g, const CoreSet &cs, int side, int count,
                                    const int *__restrict__ idx, int S, int shift_mode, double *__restrict__ out,
                                    long long e) {
@@ -70,6 +79,7 @@ __device__ inline void iface_entry(const FiberGeom &g, const CoreSet &cs, int si
                 acc += G0[(long long)i0 * cs.R[1] + al] * G1[((long long)al * cs.N[1] + i1) * cs.R[2] + beta];
             val = acc;
         }
+        if (shift_mode >= 0) val *= ghost_factor(g, shift_mode, mi[shift_mode] - 3 + s, c);
         out[(((long long)c * S + s) * count + a) * Rout + beta] = val;
     } else {
         const int len = g.d - 1 - k;
@@ -88,6 +98,7 @@ __device__ inline void iface_entry(const FiberGeom &g, const CoreSet &cs, int si
                 acc += G1[((long long)beta * cs.N[1] + j1) * cs.R[2] + b2] * G2[(long long)b2 * cs.N[2] + j2];
             val = acc;
         }
+        if (shift_mode >= 0) val *= ghost_factor(g, shift_mode, mi[shift_mode - k - 1] - 3 + s, c);
         out[(((long long)c * S + s) * Rout + beta) * count + a] = val;
     }
 }
@@ -196,7 +207,8 @@ __global__ __launch_bounds__(256) void k_weno(FiberGeom g, int p, int M, int q, 
         if (same) {
             const int cell = ghost_map(i - 3 + s, Nk, g.bc[g.k]);
 #pragma unroll
-            for (int c = 0; c < NC; ++c) qv[c] = W[(((long long)c * p + a) * Nk + cell) * q + b];
+            for (int c = 0; c < NC; ++c)
+                qv[c] = ghost_fix<T>(g, g.k, i - 3 + s, c, W[(((long long)c * p + a) * Nk + cell) * q + b]);
         } else {
 #pragma unroll
             for (int c = 0; c < NC; ++c) qv[c] = W[((((long long)c * 6 + s) * p + a) * Nk + i) * q + b];
@@ -419,7 +431,7 @@ __global__ void k_sample_state(FiberGeom g, CoreSet cs, int npts, const int *__r
         int v = pts[pt * ND + d];
         cell[d] = d == g.dir ? ghost_map(v - 3 + s, g.n[d], g.bc[d]) : v;
     }
-    ust[e] = tt_point<ND>(cs, c, cell);
+    ust[e] = ghost_fix<double>(g, g.dir, pts[pt * ND + g.dir] - 3 + s, c, tt_point<ND>(cs, c, cell));
 }
 
 template <int ND, int LW>
@@ -557,7 +569,9 @@ __global__ __launch_bounds__(256) void k_stage(FiberGeom g, int p, int q, StageA
             for (int s = 0; s < 7; ++s) {
                 const int cell = ghost_map(i - 3 + s, Nk, g.bc[g.k]);
 #pragma unroll
-                for (int c = 0; c < NC; ++c) v[c][s] = sa_.W0[c * sa_.w0_cs + ((long long)a * Nk + cell) * q + b];
+                for (int c = 0; c < NC; ++c)
+                    v[c][s] = ghost_fix<T>(g, g.k, i - 3 + s, c,
+                                           sa_.W0[c * sa_.w0_cs + ((long long)a * Nk + cell) * q + b]);
             }
         } else {
             const T *W = dd == 0 ? sa_.Wd[0] : (dd == 1 ? sa_.Wd[1] : sa_.Wd[ND - 1]);
@@ -610,8 +624,9 @@ __global__ void k_sample_star(FiberGeom g, CoreSet cs, CoreSet un, int use_un, i
         return;
     }
     const int d = slot / 7, s = slot % 7;
-    cell[d] = ghost_map(cell[d] - 3 + s, g.n[d], g.bc[d]);
-    ust[e] = tt_point<ND>(cs, c, cell);
+    const int raw = cell[d] - 3 + s;
+    cell[d] = ghost_map(raw, g.n[d], g.bc[d]);
+    ust[e] = ghost_fix<double>(g, d, raw, c, tt_point<ND>(cs, c, cell));
 }
 
 // 3D star samples by slices of the middle core: workgroup j owns slice j of mode 1 and serves
@@ -681,6 +696,7 @@ __global__ __launch_bounds__(256) void k_sample_slices3(FiberGeom g, CoreSet cs,
             for (int q = w; q < np; q += 256 / kWave) {
                 const int p = pair_pt[q], sh = pair_s[q];
                 const int i0 = probe_coord(seed, (long long)p * 3, N0), i2 = probe_coord(seed, (long long)p * 3 + 2, N2);
+                const int i1 = probe_coord(seed, (long long)p * 3 + 1, N1);
                 const double *g0 = G0 + (long long)i0 * R1;
                 const bool centre = sh == 3;
                 double val = 0.0, l2[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
@@ -721,12 +737,12 @@ __global__ __launch_bounds__(256) void k_sample_slices3(FiberGeom g, CoreSet cs,
                         for (int qq = 0; qq < 7; ++qq) l2[qq] = fma(t, g2[k2[qq]], l2[qq]);
                 }
                 val = wave_sum_d(val);
-                if (lane == 0) ust[((long long)(7 + sh) * NC + c) * npts + p] = val;
+                if (lane == 0) ust[((long long)(7 + sh) * NC + c) * npts + p] = ghost_fix<double>(g, 1, i1 + sh - 3, c, val);
                 if (!centre) continue;
 #pragma unroll
                 for (int qq = 0; qq < 7; ++qq) {
                     const double v2 = wave_sum_d(l2[qq]);
-                    if (lane == 0) ust[((long long)(14 + qq) * NC + c) * npts + p] = v2;
+                    if (lane == 0) ust[((long long)(14 + qq) * NC + c) * npts + p] = ghost_fix<double>(g, 2, i2 + qq - 3, c, v2);
                 }
                 // mode-0 line: w1(al) = S(al, :) . G2(:, i2), lanes over al; G2(:, i2) comes from the
                 // lanes that loaded it above when R2 <= 64 (by shuffles), else from memory
@@ -755,7 +771,7 @@ __global__ __launch_bounds__(256) void k_sample_slices3(FiberGeom g, CoreSet cs,
 #pragma unroll
                 for (int qq = 0; qq < 7; ++qq) {
                     const double v0 = wave_sum_d(l0[qq]);
-                    if (lane == 0) ust[((long long)qq * NC + c) * npts + p] = v0;
+                    if (lane == 0) ust[((long long)qq * NC + c) * npts + p] = ghost_fix<double>(g, 0, i0 + qq - 3, c, v0);
                 }
                 // U^n at the point
                 double unv = 0.0;
@@ -867,7 +883,41 @@ __global__ __launch_bounds__(256) void k_sample_stage(FiberGeom g, CoreSet fs, i
 
 inline unsigned cdiv(long long a, long long b) { return (unsigned)((a + b - 1) / b); }
 
+// Gathered block values of the cells on an inflow side (Sec. 4.5.2): for every listed pair
+// (shift s, pivot t, side) of the left (right = 0: t indexes a) or right (right = 1: t indexes b)
+// interface, W[c][s][a][i][b] = the side's conserved inflow state for all i and the other pivot.
+// Component stride cs, shift stride ss, block p x Nk x q.
+template <typename T>
+__global__ void k_inflow_fill(FiberGeom g, int mode, int npairs, const int *__restrict__ pairs, int right, int p,
+                              int Nk, int q, long long cs, long long ss, T *__restrict__ W) {
+    const long long per = right ? (long long)p * Nk : (long long)Nk * q;
+    const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (e >= (long long)npairs * g.ncomp * per) return;
+    const long long r = e % per;
+    const int c = (int)((e / per) % g.ncomp);
+    const int pr = (int)(e / (per * g.ncomp));
+    const int s = pairs[3 * pr], t = pairs[3 * pr + 1], side = pairs[3 * pr + 2];
+    long long off;
+    if (right) off = r * q + t;                          // r = a Nk + i
+    else off = ((long long)t * Nk + r / q) * q + r % q;  // r = i q + b
+    W[c * cs + s * ss + off] = T(g.qin[mode][side][c]);
+}
+
 }  // namespace
+
+template <typename T>
+void inflow_fill(hipStream_t s, const FiberGeom &g, int mode, int npairs, const int *pairs, bool right, int p, int Nk,
+                 int q, long long cs, long long ss, T *W) {
+    const long long per = right ? (long long)p * Nk : (long long)Nk * q;
+    const long long tot = (long long)npairs * g.ncomp * per;
+    if (tot == 0) return;
+    k_inflow_fill<T><<<cdiv(tot, 256), 256, 0, s>>>(g, mode, npairs, pairs, right ? 1 : 0, p, Nk, q, cs, ss, W);
+    WTT_HIP(hipGetLastError());
+}
+template void inflow_fill<double>(hipStream_t, const FiberGeom &, int, int, const int *, bool, int, int, int,
+                                  long long, long long, double *);
+template void inflow_fill<float>(hipStream_t, const FiberGeom &, int, int, const int *, bool, int, int, int,
+                                 long long, long long, float *);
 
 void iface(hipStream_t s, const FiberGeom &g, int side, const double *const *cores, const int *ranks, int count,
            const int *idx, int S, int shift_mode, double *out) {

@@ -26,7 +26,7 @@ EXPORTED = ["wenott_default_opts", "wenott_init", "wenott_rhs", "wenott_rk3_step
             "wenott_mlp_init_params", "wenott_mlp_forward", "wenott_mlp_loss_grad", "wenott_mlp_adam_step",
             "wenott_set_proposal", "wenott_set_cross_logging", "wenott_get_cross_log", "wenott_batch_rk3_step",
             "wenott_gemm_autotune", "wenott_gemm_autotune_table", "wenott_set_pivot_wait_limit", "wenott_finalize",
-            "wenott_pivot_layout", "wenott_pivot_search", "wenott_max_wavespeed_noalloc"]
+            "wenott_pivot_layout", "wenott_pivot_search", "wenott_max_wavespeed_noalloc", "wenott_set_inflow"]
 
 MLP_IN, MLP_HID, MLP_OUT, MLP_RANK_CLASSES, MLP_BINS = 96, 128, 81, 17, 64
 
@@ -100,6 +100,7 @@ def load(path: str = LIB_PATH):
     lib.wenott_max_wavespeed.argtypes = [vp, P(ctypes.c_double)]
     lib.wenott_max_wavespeed_noalloc.argtypes = [vp, P(ctypes.c_double)]
     lib.wenott_current_eps.argtypes = [vp, P(ctypes.c_double)]
+    lib.wenott_set_inflow.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, P(ctypes.c_double)]
     lib.wenott_set_profiling.argtypes = [vp, ctypes.c_int32]
     lib.wenott_set_pivot_wait_limit.argtypes = [ctypes.c_int32]
     lib.wenott_finalize.argtypes = []
@@ -189,7 +190,8 @@ def _stream_handle():
 # ---- thin wrappers with the C names ---------------------------------------------------
 def wenott_init(cores, n, lo, hi, gamma, bc, opts=None, stream=None):
     """cores: [ncomp][ndim] arrays (numpy host arrays or torch CUDA tensors), FP64,
-    each of shape (R_{k-1}, N_k, R_k). bc: one code per dimension. Returns a ctypes handle."""
+    each of shape (R_{k-1}, N_k, R_k). bc: per dimension one wenott_bc code or a (low, high)
+    pair. Returns a ctypes handle."""
     lib = load()
     ndim = len(n)
     ncomp = len(cores)
@@ -217,9 +219,7 @@ def wenott_init(cores, n, lo, hi, gamma, bc, opts=None, stream=None):
             if k == ndim - 1:
                 ranks[c * (ndim + 1) + ndim] = a.shape[2]
     t = wenott_tt(ndim, ncomp, ranks, ptrs, 0, on_device)
-    bcs = (ctypes.c_int32 * 6)()
-    for d in range(ndim):
-        bcs[2 * d] = bcs[2 * d + 1] = int(bc[d])
+    bcs = _bcs(bc)
     o = opts if opts is not None else default_opts()
     h = ctypes.c_void_p()
     st = _stream_handle() if stream is None else stream
@@ -297,6 +297,11 @@ def wenott_max_wavespeed_noalloc(ctx) -> float:
     return a.value
 
 
+def wenott_set_inflow(ctx, dim, side, prim):
+    a = (ctypes.c_double * len(prim))(*[float(v) for v in prim])
+    _check(load().wenott_set_inflow(ctx, int(dim), int(side), a), ctx)
+
+
 def wenott_current_eps(ctx) -> float:
     a = ctypes.c_double()
     _check(load().wenott_current_eps(ctx, ctypes.byref(a)), ctx)
@@ -341,9 +346,11 @@ def _grid(n, lo, hi):
 
 
 def _bcs(bc):
+    """bc per dimension: one wenott_bc value for both sides, or a (low, high) pair."""
     b = (ctypes.c_int32 * 6)()
     for d in range(len(bc)):
-        b[2 * d] = b[2 * d + 1] = int(bc[d])
+        lo, hi = (bc[d], bc[d]) if isinstance(bc[d], (int, np.integer)) else bc[d]
+        b[2 * d], b[2 * d + 1] = int(lo), int(hi)
     return b
 
 
@@ -446,6 +453,8 @@ class Solver:
             opts.law = law
         self.ctx = wenott_init(flow.cores, flow.n, flow.lo, flow.hi, flow.gamma, flow.bc, opts, stream)
         _live.add(self)
+        for (dim, side), prim in sorted((getattr(flow, "inflow", None) or {}).items()):
+            wenott_set_inflow(self.ctx, dim, side, prim)
 
     def close(self):
         if self.ctx:

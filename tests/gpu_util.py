@@ -11,9 +11,12 @@ def dense_of_cores(cores):
 
 
 def oracle_problem(flow):
-    bcs = tuple(oracle.BC_PERIODIC if b == 0 else oracle.BC_TRANSMISSIVE for b in flow.bc)
+    # the library's wenott_bc values and the oracle's boundary codes are both written out here
+    code = {0: oracle.BC_PERIODIC, 1: oracle.BC_TRANSMISSIVE, 2: oracle.BC_SYMMETRY, 3: oracle.BC_INFLOW}
+    bcs = tuple((code[b], code[b]) if np.ndim(b) == 0 else (code[b[0]], code[b[1]]) for b in flow.bc)
     model = {0: oracle.EULER, 1: oracle.LINADV, 2: oracle.BURGERS}[getattr(flow, "law", 0)]
-    return oracle.Problem(flow.n, flow.lo, flow.hi, bcs, gamma=flow.gamma, model=model)
+    return oracle.Problem(flow.n, flow.lo, flow.hi, bcs, gamma=flow.gamma, model=model,
+                          inflow=getattr(flow, "inflow", None))
 
 
 def rel_err(a, b):

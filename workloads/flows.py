@@ -43,6 +43,8 @@ class Flow:
     fixed_dt: float = 0.0
     # the whole exact solution on the grid at time t, [ncomp][cells], where known (scalar laws)
     exact: object = None
+    # primitive state of each inflow side: {(dimension, side): (rho, u_1..u_ndim, p) or (u,)}
+    inflow: object = None
 
     @property
     def ncomp(self):
