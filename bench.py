@@ -50,6 +50,9 @@ def parse():
                     help="only run a plain 256 MiB device-to-device copy three times (the reference for "
                          "the FETCH_SIZE / WRITE_SIZE counters)")
     ap.add_argument("--precision", type=int, default=0, help="0 FP64 fiber path, 1 FP32 fiber path")
+    ap.add_argument("--scheme", type=int, default=0,
+                    help="0 stage cross (the contract line), 1 flux cross per direction, 2 LF-cross + WENO-crosses "
+                         "as written in the paper (side measurements)")
     return ap.parse_args()
 
 
@@ -249,27 +252,27 @@ def single_state(args):
     if args.workload == "sod3d_tilted":
         n = args.n or 512
         flow = workloads.config5_tilted_sod_3d(n, seed=args.seed)
-        opts = W.default_opts(eps_mode=1, eps0=flow.eps0, precision=args.precision)
+        opts = W.default_opts(eps_mode=1, eps0=flow.eps0, precision=args.precision, scheme=args.scheme)
         box = (0.25, 0.75)
         wl = (f"3D tilted Sod {n}^3 on [0,1]^3 ({flow.note}), transmissive, dynamic eps_TT from 1e-6, CFL 0.5; "
               f"L1 of rho against the exact 1D Sod solution along the normal on [0.25,0.75]^3")
     elif args.workload == "quadrants2d":
         n = args.n or 512
         flow = workloads.config2_quadrants_2d(n, seed=args.seed)
-        opts = W.default_opts(eps_mode=1, eps0=flow.eps0, precision=args.precision)
+        opts = W.default_opts(eps_mode=1, eps0=flow.eps0, precision=args.precision, scheme=args.scheme)
         wl = (f"four-quadrant Riemann problem 2D {n}x{n}, transmissive, seed {args.seed}, "
               f"dynamic eps_TT from 1e-8, CFL 0.5")
     elif args.workload == "wave3d":
         n = args.n or 256
         flow = workloads.config3_wave_3d(n, seed=args.seed)
         eps_w = 1e-10 if args.precision == 0 else 1e-6
-        opts = W.default_opts(eps_mode=0, eps0=eps_w, precision=args.precision)
+        opts = W.default_opts(eps_mode=0, eps0=eps_w, precision=args.precision, scheme=args.scheme)
         wl = (f"3D smooth density wave {n}^3 with 8 Fourier modes, periodic, eps_TT {eps_w:g} fixed, CFL 0.5; "
               f"L1 error of rho against the exact (translated) solution reported for TT and dense")
     else:
         n = args.n or 256
         flow = workloads.sod_1d_like(3, n)
-        opts = W.default_opts(eps_mode=0, eps0=1e-6, precision=args.precision)
+        opts = W.default_opts(eps_mode=0, eps0=1e-6, precision=args.precision, scheme=args.scheme)
         wl = f"3D Sod shock tube {n}^3 (axis-aligned, rank 1), transmissive, eps_TT 1e-6, CFL 0.5"
     print(f"# workload: {wl}", file=sys.stderr, flush=True)
     cells = 1

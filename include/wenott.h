@@ -119,7 +119,13 @@ typedef struct {
     int32_t scheme;     /* 0: one cross per stage of the stage value a U^n + b (X + dt L(X)) itself;
                            1: one cross of the flux Fhat_d per direction (Algorithms lf-cross and
                               weno-cross fused), shift difference on core d, TT sum of the stage
-                              terms. [0] */
+                              terms;
+                           2: the two-stage pipeline of Sec. 4.2-4.3 as written: per direction
+                              one LF-cross of the 2 ncomp split fluxes at the cells (Algorithm
+                              lf-cross, a last core of 2 ncomp slices), then one WENO-cross per
+                              slice on the faces (Algorithm weno-cross: f^+ slices left-biased,
+                              f^- slices mirrored), shift differences, TT sum, rounding; FP64,
+                              periodic and transmissive sides. [0] */
     double conv_slack;  /* a cross is accepted when its sampled relative residual is <= eps; one whose
                            residual is still above conv_slack * eps after max_sweeps sweeps fails the
                            call with ENOCONV (and the state is left unchanged). >= 1 [1] */

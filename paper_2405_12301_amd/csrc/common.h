@@ -288,6 +288,17 @@ template <typename T>
 void stage_block(hipStream_t s, const FiberGeom &g, int p, int q, const StageArgsT<T> &a, double *out, long long sa,
                  long long si, long long sb, long long sc, int *flags);
 
+// LF-cross (Sec. 4.2): f^+ and f^- of every component at the block's cells from the state there
+// (W0[c * cs + (a Nk + i) q + b]); output (a, i, b, c) with c < 2 ncomp, f^+ first, at
+// out[a * sa + i * si + b * sb + c * sc]. The sampled residual of such a cross: the state at the
+// probe cells pts (ustencil: npts * 6 * ncomp doubles of workspace) against the candidate
+// (fcores, franks; last core [R][N][2 ncomp]); acc receives one partial pair per 256 points.
+void lf_block(hipStream_t s, const FiberGeom &g, int p, int q, const double *W0, long long cs, double *out,
+              long long sa, long long si, long long sb, long long sc, int *flags);
+void sample_lf_residual(hipStream_t s, const FiberGeom &g, const double *const *ucores, const int *ranks, int npts,
+                        const int *pts, const double *const *fcores, const int *franks, double *ustencil, double *acc,
+                        int *flags);
+
 // Writes the conserved inflow state of g.qin into the gathered block W ([c][s][a][i][b], component
 // stride cs, shift stride ss, block p x Nk x q) at the cells on an inflow side of mode `mode`:
 // `pairs` (device, 3 ints each: shift s, pivot index, side 0 low / 1 high) list the (shift, pivot)

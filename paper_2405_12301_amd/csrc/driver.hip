@@ -256,6 +256,15 @@ struct FluxTT {
     }
 };
 
+// Warm-start slots of the crosses (their last right index sets and pivot ranks): the flux cross
+// of each direction (scheme 1), the stage cross (scheme 0), and per direction the LF-cross and the
+// WENO-crosses of its 2 ncomp split-flux slices (scheme 2).
+constexpr int kSlotStage = kMaxDim;
+constexpr int kSlotLf = kMaxDim + 1;
+constexpr int kSlotWeno = 2 * kMaxDim + 1;
+constexpr int kMaxSlices = 10;
+constexpr int kWarmSlots = kSlotWeno + kMaxDim * kMaxSlices;
+
 struct ISet {  // a set of multi-indices of a fixed length
     int len = 0, count = 0;
     std::vector<int> v;
@@ -311,8 +320,8 @@ struct wenott_ctx {
     double *d_status = nullptr, *h_status = nullptr;
     int *h_pinned_int = nullptr;
     double *h_pinned_dbl = nullptr;
-    std::vector<ISet> warm[kMaxDim + 1];  // per flux direction, and [kMaxDim] for the stage value
-    bool warm_valid[kMaxDim + 1] = {};
+    std::vector<ISet> warm[kWarmSlots];  // right index sets of the last cross of each slot
+    bool warm_valid[kWarmSlots] = {};
     uint64_t counter = 0;        // random streams of the crosses
     uint64_t alpha_counter = 0;  // random start cells of the alpha searches
     double c_eps = 0.0, max_norm = 0.0;
@@ -331,7 +340,7 @@ struct wenott_ctx {
         std::vector<int> useful;  // right multi-indices whose columns were pivots (len d-1-k each)
     };
     BondHist bond[kMaxDim];
-    int piv_hist[(kMaxDim + 1) * 2 * kMaxDim];  // last pivot rank per (cross slot, sweep direction, core)
+    int piv_hist[kWarmSlots * 2 * kMaxDim];  // last pivot rank per (cross slot, sweep direction, core)
     int *d_best = nullptr;              // best cell of the last alpha search (device int[kMaxDim])
     const double *alpha_dev = nullptr;  // stage alpha on the device (read by the fiber kernels) when set
     double alpha_cache = 0.0;           // alpha of the current state (alpha_mode rule), if alpha_cache_valid
@@ -545,13 +554,16 @@ void fill_inflow_block(wenott_ctx *c, const FiberGeom &g, int m, int k, const IS
 
 // ---------------------------------------------------------------- block evaluation
 // Flux block Fhat_dir(I_<k[a], i, J_>k[b], c) written with strides (L->R or R->L unfolding).
+// law: the conservation law whose split fluxes are reconstructed (the context's; the WENO-crosses
+// of scheme 2 pass linear advection with alpha = +1 or -1, whose split fluxes are the input slice
+// and zero, so that the kernel forms the one-sided WENO5 reconstruction of the slice).
 void eval_block(wenott_ctx *c, const TT &U, int dir, int k, const ISet &L, const ISet &Rs, double alpha, bool lr,
-                double *out) {
+                double *out, int law) {
     const int d = U.d, nc = U.nc;
     FiberGeom g{};
     g.d = d; g.ncomp = nc; g.dir = dir; g.k = k;
     for (int j = 0; j < d; ++j) { g.n[j] = U.N[j]; g.bc[j] = c->bc[j]; }
-    g.law = c->law; std::memcpy(g.qin, c->qin, sizeof g.qin); g.gamma = c->gamma; g.alpha = alpha; g.eps_w = c->h[dir] * c->h[dir];
+    g.law = law; std::memcpy(g.qin, c->qin, sizeof g.qin); g.gamma = c->gamma; g.alpha = alpha; g.eps_w = c->h[dir] * c->h[dir];
     const int p = L.count, q = Rs.count;
     const int SL = dir < k ? 6 : 1, SR = dir > k ? 6 : 1, S = std::max(SL, SR);
     const int Rk = U.R[k], Rk1 = U.R[k + 1], Nk = U.N[k];
@@ -708,12 +720,13 @@ PivotResult pivots(wenott_ctx *c, double *B, int m, int n, double rel_tol2, doub
     return r;
 }
 
-double sampled_residual(wenott_ctx *c, const TT &U, const FluxTT &F, int dir, double alpha, Rng &rng) {
+double sampled_residual(wenott_ctx *c, const TT &U, const FluxTT &F, int dir, double alpha, Rng &rng, int law,
+                        bool lf = false) {
     const int d = U.d, npts = std::max(c->o.probe_points, 16);
     FiberGeom g{};
     g.d = d; g.ncomp = U.nc; g.dir = dir; g.k = 0;
     for (int j = 0; j < d; ++j) { g.n[j] = U.N[j]; g.bc[j] = c->bc[j]; }
-    g.law = c->law; std::memcpy(g.qin, c->qin, sizeof g.qin); g.gamma = c->gamma; g.alpha = alpha; g.eps_w = c->h[dir] * c->h[dir];
+    g.law = law; std::memcpy(g.qin, c->qin, sizeof g.qin); g.gamma = c->gamma; g.alpha = alpha; g.eps_w = c->h[dir] * c->h[dir];
     int *dp = c->sc.get<int>(S_PTS, (size_t)npts * d);
     sample_points(c->s, npts, d, F.M, rng.next(), dp);
     double *ust = c->sc.get<double>(S_UST, (size_t)npts * 6 * U.nc);
@@ -724,7 +737,8 @@ double sampled_residual(wenott_ctx *c, const TT &U, const FluxTT &F, int dir, do
     for (int j = 0; j <= d; ++j) { ranks[j] = U.R[j]; franks[j] = F.R[j]; }
     const double *uc[kMaxDim], *fc[kMaxDim];
     for (int j = 0; j < d; ++j) { uc[j] = U.core[j]; fc[j] = F.core[j]; }
-    sample_residual(c->s, g, uc, ranks, npts, dp, fc, franks, ust, acc, c->d_flags);
+    if (lf) sample_lf_residual(c->s, g, uc, ranks, npts, dp, fc, franks, ust, acc, c->d_flags);
+    else sample_residual(c->s, g, uc, ranks, npts, dp, fc, franks, ust, acc, c->d_flags);
     WTT_REQUIRE(2 * (size_t)nb <= 3000, WENOTT_EINVAL, "too many probe points");
     status_readback(c, kStatusAcc + 2 * nb);
     host_wait(c);
@@ -1038,17 +1052,79 @@ FluxTT cross_generic(wenott_ctx *c, const CrossTarget &t, double eps, CrossStat 
     return F;
 }
 
-FluxTT cross_flux(wenott_ctx *c, const TT &U, int dir, double alpha, double eps, CrossStat &st) {
+// Cross of the numerical flux Fhat_dir on the faces (scheme 1; with law and slot given, a
+// WENO-cross of scheme 2).
+FluxTT cross_flux(wenott_ctx *c, const TT &U, int dir, double alpha, double eps, CrossStat &st, int slot = -1,
+                  int law = -1) {
+    if (law < 0) law = c->law;
     CrossTarget t;
     t.d = U.d;
     t.nc = U.nc;
     t.q0 = std::max(2, U.maxrank());
     for (int j = 0; j < U.d; ++j) t.M[j] = U.N[j] + (j == dir ? 1 : 0);
     t.eval = [&](int k, const ISet &L, const ISet &R, bool lr, double *out) {
-        eval_block(c, U, dir, k, L, R, alpha, lr, out);
+        eval_block(c, U, dir, k, L, R, alpha, lr, out, law);
     };
-    t.residual = [&](const FluxTT &F, Rng &rng) { return sampled_residual(c, U, F, dir, alpha, rng); };
-    t.warm_slot = dir;
+    t.residual = [&](const FluxTT &F, Rng &rng) { return sampled_residual(c, U, F, dir, alpha, rng, law); };
+    t.warm_slot = slot >= 0 ? slot : dir;
+    return cross_generic(c, t, eps, st);
+}
+
+// LF-cross block (Sec. 4.2): the state at the block's cells, gathered as P G_k Q, then the split
+// fluxes f^+ and f^- of every component (2 ncomp outputs per point).
+void eval_lf_block(wenott_ctx *c, const TT &U, int dir, int k, const ISet &L, const ISet &Rs, double alpha, bool lr,
+                   double *out) {
+    const int d = U.d, nc = U.nc;
+    FiberGeom g{};
+    g.d = d; g.ncomp = nc; g.dir = dir; g.k = k;
+    for (int j = 0; j < d; ++j) { g.n[j] = U.N[j]; g.bc[j] = c->bc[j]; }
+    g.law = c->law; g.gamma = c->gamma; g.alpha = alpha;
+    const int p = L.count, q = Rs.count, Rk = U.R[k], Rk1 = U.R[k + 1], Nk = U.N[k];
+    int ranks[kMaxDim + 1];
+    for (int j = 0; j <= d; ++j) ranks[j] = U.R[j];
+    const double *cores[kMaxDim];
+    for (int j = 0; j < d; ++j) cores[j] = U.core[j];
+    double *P = c->sc.get<double>(S_P, (size_t)nc * p * Rk);
+    if (k == 0) fill(c->s, P, (long long)nc * p * Rk, 1.0);
+    else iface(c->s, g, 0, cores, ranks, p, c->ring.put(L.v.data(), L.v.size()), 1, -1, P);
+    double *Q = c->sc.get<double>(S_Q, (size_t)nc * Rk1 * q);
+    if (k == d - 1) fill(c->s, Q, (long long)nc * Rk1 * q, 1.0);
+    else iface(c->s, g, 1, cores, ranks, q, c->ring.put(Rs.v.data(), Rs.v.size()), 1, -1, Q);
+    const long long tsz = (long long)p * Nk * Rk1, wsz = (long long)p * Nk * q;
+    double *T = c->sc.get<double>(S_T, (size_t)nc * tsz);
+    GemmBatch b1;
+    b1.nb1 = nc;
+    b1.sA1 = (long long)p * Rk; b1.sB1 = U.cstride(k); b1.sC1 = tsz;
+    gemm_f64(c->s, false, false, p, Nk * Rk1, Rk, 1.0, P, Rk, U.core[k], Nk * Rk1, 0.0, T, Nk * Rk1, b1);
+    double *W = c->sc.get<double>(S_W, (size_t)nc * wsz);
+    GemmBatch b2;
+    b2.nb1 = nc;
+    b2.sA1 = tsz; b2.sB1 = (long long)Rk1 * q; b2.sC1 = wsz;
+    gemm_f64(c->s, false, false, p * Nk, q, Rk1, 1.0, T, Rk1, Q, q, 0.0, W, q, b2);
+    const int no = 2 * nc;
+    long long sa, si, sb, sc;
+    if (lr) { sa = (long long)Nk * q * no; si = (long long)q * no; sb = no; sc = 1; }
+    else { sa = no; si = (long long)q * p * no; sb = (long long)p * no; sc = 1; }
+    ev_record(c, KC_FIBER);
+    lf_block(c->s, g, p, q, W, wsz, out, sa, si, sb, sc, c->d_flags);
+    ev_record(c, KC_FIBER);
+    c->info.fiber_points += (long long)p * Nk * q;
+    c->info.fiber_launches += 1;
+}
+
+// LF-cross (Sec. 4.2, Algorithm lf-cross): one cross of the 2 ncomp split fluxes at the cells,
+// a TT whose last core carries the 2 ncomp slices.
+FluxTT cross_lf(wenott_ctx *c, const TT &U, int dir, double alpha, double eps, CrossStat &st) {
+    CrossTarget t;
+    t.d = U.d;
+    t.nc = 2 * U.nc;
+    t.q0 = std::max(2, U.maxrank());
+    for (int j = 0; j < U.d; ++j) t.M[j] = U.N[j];
+    t.eval = [&](int k, const ISet &L, const ISet &R, bool lr, double *out) {
+        eval_lf_block(c, U, dir, k, L, R, alpha, lr, out);
+    };
+    t.residual = [&](const FluxTT &F, Rng &rng) { return sampled_residual(c, U, F, dir, alpha, rng, c->law, true); };
+    t.warm_slot = kSlotLf + dir;
     return cross_generic(c, t, eps, st);
 }
 
@@ -2014,8 +2090,93 @@ double current_eps(const wenott_ctx *c) {
 }
 
 // L(U) as a TT: cross per direction, shift difference, sum over directions.
+// One TT of nc components from nc single-component TTs of the same grid: ranks padded to the
+// largest, each component's cores in the leading block of its slot.
+TT pack_components(wenott_ctx *c, const std::vector<TT> &parts) {
+    const TT &a = parts[0];
+    TT S;
+    S.d = a.d; S.nc = (int)parts.size();
+    for (int j = 0; j < a.d; ++j) S.N[j] = a.N[j];
+    for (int k = 0; k <= a.d; ++k) {
+        S.R[k] = 1;
+        for (const TT &X : parts) S.R[k] = std::max(S.R[k], X.R[k]);
+    }
+    S.alloc(c->s);
+    for (int k = 0; k < S.d; ++k) {
+        fill(c->s, S.core[k], S.cstride(k) * S.nc, 0.0);
+        for (int i = 0; i < S.nc; ++i) {
+            const TT &X = parts[i];
+            place_block(c->s, 1, X.R[k], S.N[k], X.R[k + 1], X.core[k], X.cstride(k), 1.0,
+                        S.core[k] + i * S.cstride(k), S.R[k], S.R[k + 1], S.cstride(k), 0, 0);
+        }
+    }
+    return S;
+}
+
+// Scheme 2, per direction (Sec. 4.2-4.3): the LF-cross of the 2 ncomp split fluxes at the cells,
+// its slices as single-component TTs (the shared cores and one slice of the last core), then per
+// slice one WENO-cross of the one-sided reconstruction on the faces (f^+ slices left-biased, f^-
+// slices mirrored), each warm-started from its own previous cross. Returns the two terms
+// -(T^d - 1)/h_d F^+ and -(T^d - 1)/h_d F^- (their sum is L_d), each packed over components.
+void lf_weno_terms(wenott_ctx *c, const TT &U, int dir, double alpha, double eps, int stage, std::vector<TT> &terms) {
+    const int d = U.d, nc = U.nc;
+    CrossStat lst;
+    FluxTT F = cross_lf(c, U, dir, alpha, eps, lst);
+    int sweeps = lst.sweeps, rmax = lst.maxrank;
+    double resid = lst.residual;
+    const int k = d - 1;
+    const long long per = (long long)F.R[k] * F.M[k];
+    double *slices = dalloc<double>(c->s, (size_t)per * 2 * nc);
+    std::vector<TT> plus, minus;
+    auto release_all = [&]() {
+        for (auto &t : plus) t.release(c->s);
+        for (auto &t : minus) t.release(c->s);
+        dfree(c->s, slices);
+        F.release(c->s);
+    };
+    try {
+        split_last(c->s, F.R[k], F.M[k], 2 * nc, F.core[k], slices, per);
+        for (int j = 0; j < 2 * nc; ++j) {
+            TT V;  // a view: the LF-cross's shared cores and slice j of its last core
+            V.d = d; V.nc = 1;
+            for (int m = 0; m < d; ++m) V.N[m] = F.M[m];
+            for (int m = 0; m <= d; ++m) V.R[m] = F.R[m];
+            for (int m = 0; m < d - 1; ++m) V.core[m] = F.core[m];
+            V.core[k] = slices + j * per;
+            CrossStat wst;
+            FluxTT Wf = cross_flux(c, V, dir, j < nc ? 1.0 : -1.0, eps, wst, kSlotWeno + dir * kMaxSlices + j,
+                                   kLawLinAdv);
+            sweeps = std::max(sweeps, wst.sweeps);
+            rmax = std::max(rmax, wst.maxrank);
+            resid = std::max(resid, wst.residual);
+            (j < nc ? plus : minus).push_back(cross_to_tt(c, Wf, dir));
+            Wf.release(c->s);
+        }
+        terms.push_back(pack_components(c, plus));
+        terms.push_back(pack_components(c, minus));
+    } catch (...) {
+        release_all();
+        throw;
+    }
+    release_all();
+    if (stage >= 0 && stage < 3) {
+        c->info.sweeps[stage][dir] = sweeps;
+        c->info.residual[stage][dir] = resid;
+        c->info.flux_rank[stage][dir] = rmax;
+    }
+}
+
 std::vector<TT> rhs_terms(wenott_ctx *c, const TT &U, double alpha, double eps, int stage) {
     std::vector<TT> terms;
+    if (c->o.scheme == 2) {
+        try {
+            for (int dir = 0; dir < U.d; ++dir) lf_weno_terms(c, U, dir, alpha, eps, stage, terms);
+        } catch (...) {
+            for (auto &t : terms) t.release(c->s);
+            throw;
+        }
+        return terms;
+    }
     for (int dir = 0; dir < U.d; ++dir) {
         CrossStat st;
         FluxTT F = cross_flux(c, U, dir, alpha, eps, st);
@@ -2165,7 +2326,8 @@ wenott_status wenott_init(wenott_ctx **out, const wenott_tt *state, const wenott
         WTT_REQUIRE(c->o.max_sweeps >= 1 && c->o.rank_cap >= 1 && c->o.kick_rank >= 0, WENOTT_EINVAL, "bad options");
         WTT_REQUIRE(c->o.eps_mode == 0 || c->o.eps_mode == 1, WENOTT_EINVAL, "eps_mode must be 0 or 1");
         WTT_REQUIRE(c->o.alpha_mode >= 0 && c->o.alpha_mode <= 2, WENOTT_EINVAL, "alpha_mode must be 0, 1 or 2");
-        WTT_REQUIRE(c->o.scheme == 0 || c->o.scheme == 1, WENOTT_EINVAL, "scheme must be 0 or 1");
+        WTT_REQUIRE(c->o.scheme >= 0 && c->o.scheme <= 2, WENOTT_EINVAL, "scheme must be 0, 1 or 2");
+        WTT_REQUIRE(c->o.scheme != 2 || c->o.use_proposal == 0, WENOTT_EINVAL, "the proposal serves the stage cross");
         WTT_REQUIRE(c->o.precision == 0 || c->o.scheme == 0, WENOTT_EINVAL, "the FP32 path runs in scheme 0");
         WTT_REQUIRE(c->o.rounds_per_stage == 1 || c->o.rounds_per_stage == 2, WENOTT_EINVAL,
                     "rounds_per_stage must be 1 or 2");
@@ -2181,6 +2343,11 @@ wenott_status wenott_init(wenott_ctx **out, const wenott_tt *state, const wenott
                             WENOTT_EINVAL, "unknown boundary type");
             WTT_REQUIRE((bc[2 * k] == WENOTT_BC_PERIODIC) == (bc[2 * k + 1] == WENOTT_BC_PERIODIC), WENOTT_EINVAL,
                         "a periodic side needs a periodic opposite side");
+            // scheme 2 reconstructs the split fluxes' slices, whose ghost values are index maps of
+            // their own only for periodic and transmissive sides
+            for (int side = 0; side < 2; ++side)
+                WTT_REQUIRE(c->o.scheme != 2 || bc[2 * k + side] <= WENOTT_BC_TRANSMISSIVE, WENOTT_EINVAL,
+                            "scheme 2 takes periodic and transmissive sides");
             c->N[k] = (int)grid->n[k];
             c->lo[k] = grid->lo[k];
             c->hi[k] = grid->hi[k];

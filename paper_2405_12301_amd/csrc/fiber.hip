@@ -235,6 +235,94 @@ __global__ __launch_bounds__(256) void k_weno(FiberGeom g, int p, int M, int q, 
     if (!finite) atomicOr(flags, kFlagNaN);
 }
 
+// LF-cross evaluation (Sec. 4.2, Algorithm lf-cross): the split fluxes f^+ and f^- of every
+// component at the block's cells, 2 ncomp values per point (f^+ in slots 0..ncomp-1, f^- after
+// them). W0 holds the state at the block points, W0[c * cs + (a Nk + i) q + b].
+template <int ND, int LW>
+__global__ __launch_bounds__(256) void k_lf(FiberGeom g, int p, int q, const double *__restrict__ W0, long long cs,
+                                            double *__restrict__ out, long long sa, long long si, long long sb,
+                                            long long sc, int *__restrict__ flags) {
+    constexpr int NC = LawNC<ND, LW>::v;
+    const int Nk = g.n[g.k];
+    const long long tot = (long long)p * Nk * q;
+    const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (e >= tot) return;
+    const int b = (int)(e % q);
+    const long long r = e / q;
+    const int i = (int)(r % Nk);
+    const int a = (int)(r / Nk);
+    double qv[NC], fp[NC], fm[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) qv[c] = W0[c * cs + e];
+    const bool ok = split_flux<ND, LW, double>(qv, g.dir, g.gamma - 1.0, geom_alpha(g), fp, fm);
+    bool finite = true;
+    double *o = out + a * sa + i * si + b * sb;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        finite &= (fp[c] == fp[c]) && (fm[c] == fm[c]) && fabs(fp[c]) < 1e300 && fabs(fm[c]) < 1e300;
+        o[c * sc] = fp[c];
+        o[(NC + c) * sc] = fm[c];
+    }
+    if (!ok) atomicOr(flags, kFlagNonPhys);
+    if (!finite) atomicOr(flags, kFlagNaN);
+}
+
+// Sampled residual of an LF-cross: the split fluxes at each probe cell (from the state value in
+// slot 3 of the k_sample_state layout) against the candidate TT with 2 ncomp slices on its last
+// core; one partial pair (|diff|^2, |exact|^2) per workgroup.
+template <int ND, int LW>
+__global__ __launch_bounds__(256) void k_sample_lf(FiberGeom g, CoreSet fs, int npts, const int *__restrict__ pts,
+                                                   const double *__restrict__ ust, double *__restrict__ acc,
+                                                   int *__restrict__ flags) {
+    constexpr int NC = LawNC<ND, LW>::v, NO = 2 * NC;
+    __shared__ double red[2][4];
+    const int pt = blockIdx.x * blockDim.x + threadIdx.x;
+    double d2 = 0.0, n2 = 0.0;
+    bool ok = true;
+    if (pt < npts) {
+        double qv[NC], ex[NO];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) qv[c] = ust[((long long)pt * 6 + 3) * NC + c];
+        ok = split_flux<ND, LW, double>(qv, g.dir, g.gamma - 1.0, geom_alpha(g), ex, ex + NC);
+        const int *m = pts + pt * ND;
+        double approx[NO];
+#pragma unroll
+        for (int c = 0; c < NO; ++c) approx[c] = 0.0;
+        if (ND == 2) {
+            const double *g0 = fs.c[0] + (long long)m[0] * fs.R[1];
+            const double *g1 = fs.c[1] + (long long)m[1] * NO;
+            for (int al = 0; al < fs.R[1]; ++al)
+#pragma unroll
+                for (int c = 0; c < NO; ++c) approx[c] = fma(g0[al], g1[al * (long long)fs.N[1] * NO + c], approx[c]);
+        } else {
+            for (int be = 0; be < fs.R[2]; ++be) {
+                double v = 0.0;
+                for (int al = 0; al < fs.R[1]; ++al)
+                    v += fs.c[0][(long long)m[0] * fs.R[1] + al] * fs.c[1][((long long)al * fs.N[1] + m[1]) * fs.R[2] + be];
+                const double *last = fs.c[2] + ((long long)be * fs.N[2] + m[2]) * NO;
+#pragma unroll
+                for (int c = 0; c < NO; ++c) approx[c] = fma(v, last[c], approx[c]);
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < NO; ++c) {
+            d2 += (ex[c] - approx[c]) * (ex[c] - approx[c]);
+            n2 += ex[c] * ex[c];
+        }
+    }
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        d2 += __shfl_xor(d2, off, kWave);
+        n2 += __shfl_xor(n2, off, kWave);
+    }
+    if (threadIdx.x % kWave == 0) { red[0][threadIdx.x / kWave] = d2; red[1][threadIdx.x / kWave] = n2; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        acc[2 * blockIdx.x] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+        acc[2 * blockIdx.x + 1] = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+    }
+    if (!ok) atomicOr(flags, kFlagNonPhys);
+}
+
 // sum_t x[t sx] y[t sy], t < n, in four interleaved chains so that the loads of several terms
 // are in flight at once (the operands come from L2)
 __device__ inline double dot4(const double *__restrict__ x, long long sx, const double *__restrict__ y, long long sy,
@@ -1092,6 +1180,50 @@ void sample_residual(hipStream_t s, const FiberGeom &g, const double *const *uco
     WTT_HIP(hipGetLastError());
 }
 
+
+void lf_block(hipStream_t s, const FiberGeom &g, int p, int q, const double *W0, long long cs, double *out,
+              long long sa, long long si, long long sb, long long sc, int *flags) {
+    const long long tot = (long long)p * g.n[g.k] * q;
+    if (tot == 0) return;
+#define WTT_LF(ND_, LW_) k_lf<ND_, LW_><<<cdiv(tot, 256), 256, 0, s>>>(g, p, q, W0, cs, out, sa, si, sb, sc, flags)
+    if (g.law == kLawEuler) {
+        if (g.d == 2) WTT_LF(2, kLawEuler); else WTT_LF(3, kLawEuler);
+    } else if (g.law == kLawLinAdv) {
+        if (g.d == 2) WTT_LF(2, kLawLinAdv); else WTT_LF(3, kLawLinAdv);
+    } else {
+        if (g.d == 2) WTT_LF(2, kLawBurgers); else WTT_LF(3, kLawBurgers);
+    }
+#undef WTT_LF
+    WTT_HIP(hipGetLastError());
+}
+
+void sample_lf_residual(hipStream_t s, const FiberGeom &g, const double *const *ucores, const int *ranks, int npts,
+                        const int *pts, const double *const *fcores, const int *franks, double *ustencil, double *acc,
+                        int *flags) {
+    int modes[kMaxDim];
+    for (int k = 0; k < g.d; ++k) modes[k] = g.n[k];
+    CoreSet us = make_coreset(g, ucores, ranks, modes);
+    CoreSet fs{};
+    for (int k = 0; k <= g.d; ++k) fs.R[k] = franks[k];
+    for (int k = 0; k < g.d; ++k) {
+        fs.c[k] = fcores[k];
+        fs.N[k] = modes[k];
+        fs.cstride[k] = 0;
+    }
+    const long long n1 = (long long)npts * 6 * g.ncomp;
+    if (g.d == 2) k_sample_state<2><<<cdiv(n1, 256), 256, 0, s>>>(g, us, npts, pts, ustencil);
+    else k_sample_state<3><<<cdiv(n1, 256), 256, 0, s>>>(g, us, npts, pts, ustencil);
+#define WTT_SLF(ND_, LW_) k_sample_lf<ND_, LW_><<<cdiv(npts, 256), 256, 0, s>>>(g, fs, npts, pts, ustencil, acc, flags)
+    if (g.law == kLawEuler) {
+        if (g.d == 2) WTT_SLF(2, kLawEuler); else WTT_SLF(3, kLawEuler);
+    } else if (g.law == kLawLinAdv) {
+        if (g.d == 2) WTT_SLF(2, kLawLinAdv); else WTT_SLF(3, kLawLinAdv);
+    } else {
+        if (g.d == 2) WTT_SLF(2, kLawBurgers); else WTT_SLF(3, kLawBurgers);
+    }
+#undef WTT_SLF
+    WTT_HIP(hipGetLastError());
+}
 
 template <typename T>
 void stage_block(hipStream_t s, const FiberGeom &g, int p, int q, const StageArgsT<T> &a, double *out, long long sa,
