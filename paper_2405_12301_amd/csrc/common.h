@@ -75,6 +75,10 @@ __host__ __device__ inline int ghost_map(int i, int n, int bc) {
 // kGhostMirror (a symmetry ghost: the momentum normal to the plane negated), kGhostInflow (the
 // side's inflow state).
 enum { kGhostPlain = 0, kGhostMirror = 1, kGhostInflow = 2 };
+// A dimension with a symmetry or inflow side (its ghost values are more than an index map).
+__host__ __device__ inline bool bc_special(int bc) {
+    return (bc & 15) >= WENOTT_BC_SYMMETRY || ((bc >> 4) & 15) >= WENOTT_BC_SYMMETRY;
+}
 __host__ __device__ inline int ghost_kind(int i, int n, int bc) {
     if (i >= 0 && i < n) return kGhostPlain;
     const int b = bc_side(bc, i >= n);
@@ -161,7 +165,7 @@ void prrlu_layout(int m, int n, bool allow_big, int *out);
 void chol_upper_inv(hipStream_t s, int r, int batch, const double *G, double *X, double *ws);
 // X = R^{-1} for the upper Cholesky factor of U_z^T U_z, U_z the m x r row-major matrix at
 // U + z sU (X_z at X + z r^2), Gram matrix and factorisation in one launch; false (nothing
-// launched) when r is beyond the fused kernel's limit (32).
+// launched) when r exceeds 32 or the Gram matrix is too tall for one workgroup (m r^2 > 4e6).
 bool gram_chol_inv(hipStream_t s, int m, int r, int batch, const double *U, long long sU, double *X);
 
 // Batched forms: one workgroup per job (and per component for the SVD / Cholesky), the jobs
@@ -228,6 +232,7 @@ __device__ inline double geom_alpha(const FiberGeom &g) { return g.alpha_dev ? *
 // state on an inflow side.
 template <typename T>
 __device__ inline T ghost_fix(const FiberGeom &g, int m, int raw, int c, T v) {
+    if (!bc_special(g.bc[m])) return v;  // uniform: periodic and transmissive sides are index maps
     const int kind = ghost_kind(raw, g.n[m], g.bc[m]);
     if (kind == kGhostMirror && g.law == kLawEuler && c == 1 + m) return -v;
     if (kind == kGhostInflow) return T(g.qin[m][raw >= g.n[m]][c]);

@@ -74,7 +74,7 @@ __global__ __launch_bounds__(256) void k_face_flux(DenseGeom g, int dir, double 
         double q[NC];
 #pragma unroll
         for (int c = 0; c < NC; ++c) q[c] = U[c * g.ncell + idx];
-        if (ghost_kind(m - 3 + s, g.n[dir], g.bc[dir]) == kGhostMirror) q[1 + dir] = -q[1 + dir];
+        if (bc_special(g.bc[dir]) && ghost_kind(m - 3 + s, g.n[dir], g.bc[dir]) == kGhostMirror) q[1 + dir] = -q[1 + dir];
         const double inv = 1.0 / q[0];
         double ke = 0.0;
 #pragma unroll

@@ -1176,6 +1176,26 @@ void eval_stage_block(wenott_ctx *c, const TT &X, const TT *Un, StageWeights w, 
         const TT &Y = *G.Y;
         const int Rk = Y.R[k], Rk1 = Y.R[k + 1], SL = G.SL, SR = G.SR, S = std::max(SL, SR);
         const long long tsz = (long long)p * Nk * Rk1;
+        // Shifts on the left with a right part: W_s = P_s (G_k Q) forms G_k Q once instead of
+        // P_s G_k for every shift, when that is fewer multiply-adds
+        // (Rk Nk Rk1 q + SL p Rk Nk q against SL p Nk Rk1 (Rk + q)).
+        if (SL > 1 && k < d - 1 &&
+            (double)Rk * Rk1 * q + (double)SL * p * Rk * q < (double)SL * p * Rk1 * (Rk + q)) {
+            const long long zsz = (long long)Rk * Nk * q, wsz = (long long)p * Nk * q;
+            double *Z = c->sc.get<double>(G.slotT, (size_t)nc * zsz);
+            GemmBatch bz;
+            bz.nb1 = nc;
+            bz.sA1 = Y.cstride(k); bz.sB1 = (long long)Rk1 * q; bz.sC1 = zsz;
+            gemm_f64(s, false, false, Rk * Nk, q, Rk1, 1.0, Y.core[k], Rk1, G.Q, q, 0.0, Z, q, bz);
+            double *W = c->sc.get<double>(G.slotW, (size_t)nc * SL * wsz);
+            GemmBatch bw;
+            bw.nb1 = nc; bw.nb2 = SL;
+            bw.sA1 = (long long)SL * p * Rk; bw.sA2 = (long long)p * Rk;
+            bw.sB1 = zsz; bw.sB2 = 0;
+            bw.sC1 = SL * wsz; bw.sC2 = wsz;
+            gemm_f64(s, false, false, p, Nk * q, Rk, 1.0, G.P, Rk, Z, Nk * q, 0.0, W, Nk * q, bw);
+            return W;
+        }
         // T = P G_k; at the first core T is the core itself
         const double *T;
         long long tA1;

@@ -46,6 +46,7 @@ __device__ inline int mode_index(const FiberGeom &g, int mode, int v, int s, int
 // the normal momentum at a symmetry plane, 0 on an inflow side (whose constant state is written
 // into the gathered block afterwards, inflow_fill), else 1.
 __device__ inline double ghost_factor(const FiberGeom &g, int m, int raw, int c) {
+    if (!bc_special(g.bc[m])) return 1.0;
     const int kind = ghost_kind(raw, g.n[m], g.bc[m]);
     if (kind == kGhostInflow) return 0.0;
     return kind == kGhostMirror && g.law == kLawEuler && c == 1 + m ? -1.0 : 1.0;

@@ -1913,6 +1913,21 @@ __global__ __launch_bounds__(kGramWaves * 64) void k_gram_chol_inv(int m, int r,
     else gram_chol_finish<kGramMaxR>(r, Gs, X);
 }
 
+// X = R^{-1} of the upper Cholesky factor of one r x r matrix G (row-major, upper triangle read)
+// per workgroup of one wave, r <= RM <= 64, in registers (chol_inv_reg).
+template <int RM>
+__global__ __launch_bounds__(64) void k_chol_inv_reg(int r, const double *__restrict__ Gin, double *__restrict__ Xout) {
+    const int lane = threadIdx.x;
+    const long long off = (long long)blockIdx.x * r * r;
+    double a[RM];
+#pragma unroll
+    for (int k = 0; k < RM; ++k) a[k] = (k <= lane && lane < r) ? Gin[off + (long long)k * r + lane] : 0.0;
+    chol_inv_reg<RM>(r, a);
+#pragma unroll
+    for (int j = 0; j < RM; ++j)
+        if (j < r && lane < r) Xout[off + (long long)j * r + lane] = a[j];
+}
+
 __global__ __launch_bounds__(64) void k_chol_inv_wave(int r, const double *__restrict__ Gin, double *__restrict__ Xout) {
     const long long off = (long long)blockIdx.x * r * r;
     chol_inv_wave_body(r, Gin + off, Xout + off);
@@ -2491,23 +2506,38 @@ void interp_solve(hipStream_t s, int m, int r, const double *L, int ldl, const i
 }
 
 bool gram_chol_inv(hipStream_t s, int m, int r, int batch, const double *U, long long sU, double *X) {
-    if (r < 1 || r > kGramMaxR) return false;
+    // one workgroup forms each Gram matrix: only while that is a few tens of microseconds of one
+    // CU's matrix-core rate (m r^2 <= 4e6); taller bases take the split-K GEMM over the device
+    if (r < 1 || r > kGramMaxR || (double)m * r * r > 4e6) return false;
     k_gram_chol_inv<<<batch, kGramWaves * kWave, 0, s>>>(m, r, U, sU, X, (long long)r * r);
     WTT_HIP(hipGetLastError());
     return true;
 }
 
 void chol_upper_inv(hipStream_t s, int r, int batch, const double *G, double *X, double *ws) {
-    if (r <= kCholWaveMax)
+    // one wave with column i of the factor in lane i's registers up to 32 columns (the unrolled
+    // code of wider forms outgrows the instruction cache: 147 us at r = 57 against 106 us in LDS)
+    if (r <= 32) {
+        if (r <= 16) k_chol_inv_reg<16><<<batch, kWave, 0, s>>>(r, G, X);
+        else k_chol_inv_reg<32><<<batch, kWave, 0, s>>>(r, G, X);
+    } else if (r <= kCholWaveMax)
         k_chol_inv_wave<<<batch, kWave, sizeof(double) * 2 * (size_t)r * (r + 1), s>>>(r, G, X);
     else
         k_chol_inv<<<batch, 256, 0, s>>>(r, G, X, ws);
     WTT_HIP(hipGetLastError());
 }
 
+// Rows of K per split-K chunk: a multiple of 64 such that the chunks of the batch number about
+// 512 (a few per CU) rather than K / 64 each, whose partial sums would cost more to add than
+// the products.
+int splitk_chunk(int K, int batch) {
+    const long long want = ((long long)K * batch + 511) / 512;
+    return (int)std::max(64LL, (want + 63) / 64 * 64);
+}
+
 void gemm_tn_splitk(hipStream_t s, int M, int N, int K, const double *A, int lda, const double *B, int ldb, double *C,
                     int ldc, int batch, long long sA, long long sB, long long sC, double *part, size_t part_cap) {
-    const int chunk = 64;
+    const int chunk = splitk_chunk(K, batch);
     const int nchunk = (K + chunk - 1) / chunk;
     const long long per = (long long)M * N;
     if (nchunk <= 1 || (size_t)per * nchunk * batch > part_cap) {
@@ -2528,7 +2558,8 @@ void gemm_tn_splitk(hipStream_t s, int M, int N, int K, const double *A, int lda
 }
 
 size_t gemm_tn_splitk_part(int M, int N, int K, int batch) {
-    return (size_t)M * N * ((K + 63) / 64) * batch;
+    const int chunk = splitk_chunk(K, batch);
+    return (size_t)M * N * ((K + chunk - 1) / chunk) * batch;
 }
 
 void prrlu_batch(hipStream_t s, int njobs, const PrrluJob *host_jobs, const PrrluJob *dev_jobs, int t_begin,
