@@ -255,7 +255,7 @@ def test_step_parity_quadrants_shocks(W, n, scheme):
 def test_full_rank_exactness_8d(W, ndim, scheme):
     _say("case: full-rank exactness on 8^d, random smooth state, d =", ndim, "scheme", scheme)
     f = workloads.random_positive_tt((8,) * ndim, rank=8, seed=7, amp=0.3)
-    _step_parity(W, f, 1e-13, nsteps=1, tol_factor=1e2, scheme=scheme)
+    _step_parity(W, f, 1e-13, nsteps=1, tol_factor=10, scheme=scheme)
 
 
 @pytest.mark.parametrize("scheme", SCHEMES)
