@@ -182,6 +182,7 @@ struct PrrluJob {
     // longer stripes, 4 one persistent launch of long stripes (K rows per thread in shape)
     int mode, shape, rows, nblk;
     int spin;  // poll bound of the persistent form's waits (set by prrlu_prepare)
+    int kl;    // mode 4: rows per thread held in LDS (set by prrlu_prepare)
 };
 void prrlu_prepare(PrrluJob &j, bool allow_big = false);
 struct SvdJob {

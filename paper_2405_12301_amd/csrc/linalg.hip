@@ -1047,7 +1047,10 @@ __device__ __forceinline__ void prrlu_mw_step_body(const PrrluJob &J, int t) {
 constexpr int kCoopMaxBlk = 64;  // one slot per lane of a wave
 constexpr int kCoopBigSlots = 256;  // the persistent form for large blocks: four slots per lane
 constexpr int kCoopBigRows = 2048;  // its stripes' rows at most (the pivot-column buffer)
+// the LDS buffer of the form that also holds rows in LDS: all of the 160 KB but the wave partials
+constexpr int kCoopLdsDoubles = 20464;
 constexpr int kCoopSpin = 1 << 22;
+constexpr int kCoopGLChunk = 3;  // streamed rows loaded together
 constexpr long long kNoRow = 0x7fffffffffffffffLL;
 
 __device__ __forceinline__ int coop_tag(int t) { return (t >> 1) & 3; }
@@ -1066,16 +1069,16 @@ __device__ __forceinline__ long long coop_get(const long long *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Polls NW words until each carries tag tg (the loads of one round are issued together); false when the job has failed or the polls
-// ran out (then the job is marked failed).
+// Polls the NW words p[off[q]] until each carries tag tg (the loads of one round are issued
+// together); false when the job has failed or the polls ran out (then the job is marked failed).
 template <int NW>
-__device__ __forceinline__ bool coop_poll(const long long *const (&p)[NW], int tg, PrrluCtl *ctl, int spin,
+__device__ __forceinline__ bool coop_poll(const long long *p, const int (&off)[NW], int tg, PrrluCtl *ctl, int spin,
                                           long long (&out)[NW]) {
     for (int sp = 0; sp < spin; ++sp) {
         bool all = true;
 #pragma unroll
         for (int q = 0; q < NW; ++q) {
-            out[q] = coop_get(p[q]);
+            out[q] = coop_get(p + off[q]);
             all = all && (int)(out[q] & 3) == tg;
         }
         if (all) return true;
@@ -1086,92 +1089,116 @@ __device__ __forceinline__ bool coop_poll(const long long *const (&p)[NW], int t
     return false;
 }
 
-// NT threads per workgroup. Thread (tr, tc) owns columns [c0, c0 + kMwTW) of the stripe rows
-// r0 + tr + k RS: rows k < K in registers, K <= k < K + KL in LDS (element (k, j) at
-// ld[((k - K) kMwTW + j) NT + tid]: consecutive threads, consecutive words) and, with GL, rows
-// K + KL <= k < J.shape left in A itself and streamed through at every step. Up to 64 SPL
-// workgroups (each polling lane gathers SPL slots). LC: the pivot-column buffer (>= J.rows).
-// The rows outside the registers have their partials for the next step formed in the same pass
-// that eliminates them.
-template <int NT, int K, int KL, bool GL, int SPL, int LC>
+// Partials (largest magnitude, its position, squared sum) of the entries one thread holds, in NC
+// independent chains (column j goes to chain j mod NC); entries are added in increasing position
+// k kMwTW + j, and strict comparisons keep the first (lowest-index) entry of a tie.
+template <int NC>
+struct CoopAcc {
+    double pm[NC], ps[NC];
+    int pq[NC];
+    __device__ __forceinline__ void reset() {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) { pm[c] = -1.0; ps[c] = 0.0; pq[c] = 0; }
+    }
+    __device__ __forceinline__ void add(int j, int k, double v) {
+        const int c = j % NC;
+        ps[c] = fma(v, v, ps[c]);
+        const double av = fabs(v);
+        const bool gt = av > pm[c];
+        pm[c] = gt ? av : pm[c];
+        pq[c] = gt ? k * kMwTW + j : pq[c];
+    }
+    // position as k kMwTW + j, in the order of the global index
+    __device__ __forceinline__ void merge(double &mx, double &sm, int &pos) const {
+        mx = pm[0]; sm = ps[0]; pos = pq[0];
+#pragma unroll
+        for (int c = 1; c < NC; ++c) {
+            sm += ps[c];
+            const bool take = pm[c] > mx || (pm[c] == mx && pq[c] < pos);
+            mx = take ? pm[c] : mx;
+            pos = take ? pq[c] : pos;
+        }
+    }
+};
+
+// NT threads per workgroup; NA = RS tpr of them are active (tpr = ceil(n / kMwTW)). Active thread
+// (tr, tc) owns the columns tc + j tpr, j < kMwTW (so that the lanes of a wave touch consecutive
+// words) of the stripe rows r0 + tr + k RS: rows k < K in registers,
+// K <= k < K + kl (kl = J.kl) in LDS and, with GL, rows K + kl <= k < J.shape left in A itself and
+// streamed through at every step. Up to 64 SPL workgroups (each polling lane gathers SPL slots).
+// One LDS buffer of LB doubles holds the LDS rows (element (k, j) of thread tid at
+// ld[((k - K) kMwTW + j) NA + tid]: consecutive threads, consecutive words) and after them the
+// pivot column (J.rows doubles, element (tr, k) at lc[tr KT + k]).
+// Each step's elimination forms the partials of the next step in the same pass, with no branch
+// per row: the holders of the pivot column clear it when they publish it, those of the pivot row
+// clear the row before the pass, and both stay zero in it (the pivot row's multiplier is
+// published as 0, the pivot row's entry in the pivot column is taken as 0).
+template <int NT, int K, bool GL, int SPL, int LB>
 __device__ __forceinline__ void prrlu_coop_body_t(const PrrluJob &J) {
-    __shared__ double lc[LC];
-    __shared__ double ld[KL > 0 ? KL * kMwTW * NT : 1];
+    __shared__ double lbuf[LB];
     __shared__ double wmax[NT / kWave], wsum[NT / kWave];
     __shared__ long long widx[NT / kWave];
     __shared__ int s_fail;
     const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave;
     const int m = J.m, n = J.n, rmax = J.rmax, G = J.nblk, blk = blockIdx.x;
     const PrrluWs w = prrlu_ws_split(J.ws, n, J.nblk);
-    const int tpr = (n + kMwTW - 1) / kMwTW, RS = NT / tpr;
-    const int tr = tid / tpr, tc = tid % tpr, c0 = tc * kMwTW;
+    const int tpr = (n + kMwTW - 1) / kMwTW, RS = NT / tpr, NA = RS * tpr;
+    const int tr = tid / tpr, tc = tid % tpr;  // column j of the thread: tc + j tpr
     const bool active = tr < RS;
     const int r0 = blk * J.rows;
-    const int KT = GL ? J.shape : K + KL;  // rows per thread
+    const int kl = J.kl;  // rows per thread in LDS
+    const int KT = GL ? J.shape : K + kl;  // rows per thread
     double *__restrict__ A = J.A;
+    double *const ldt = lbuf + tid;  // this thread's LDS rows: element (k, j) at ldt[(k kMwTW + j) NA]
+    double *const lc = lbuf + kl * kMwTW * NA;
+    CoopAcc<(K >= 14) ? 1 : 4> acc;  // as many chains as the registers allow
+    acc.reset();
     double a[K][kMwTW];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const int row = r0 + tr + k * RS;
         const bool rv = active && row < m;
 #pragma unroll
-        for (int j = 0; j < kMwTW; ++j) a[k][j] = (rv && c0 + j < n) ? A[(long long)row * n + c0 + j] : 0.0;
-    }
-    // partials (largest magnitude, its slot k kMwTW + j, squared sum) of the rows outside the
-    // registers, for the coming step
-    double xmax = -1.0, xsum = 0.0;
-    int xk = 0;
-#pragma unroll
-    for (int k = 0; k < KL; ++k) {
-        const int row = r0 + tr + (K + k) * RS;
-        const bool rv = active && row < m;
-#pragma unroll
         for (int j = 0; j < kMwTW; ++j) {
-            const double v = (rv && c0 + j < n) ? A[(long long)row * n + c0 + j] : 0.0;
-            ld[(k * kMwTW + j) * NT + tid] = v;
-            xsum = fma(v, v, xsum);
-            if (fabs(v) > xmax) { xmax = fabs(v); xk = (K + k) * kMwTW + j; }
+            a[k][j] = (rv && tc + j * tpr < n) ? A[(long long)row * n + tc + j * tpr] : 0.0;
+            acc.add(j, k, a[k][j]);
         }
     }
-    if (GL && active) {
-        for (int k = K + KL; k < KT; ++k) {
-            const int row = r0 + tr + k * RS;
-            if (row >= m) break;
-            const double *src = A + (long long)row * n + c0;
+    if (active) {
+        for (int k = 0; k < kl; ++k) {
+            const int row = r0 + tr + (K + k) * RS;
+            const double *src = A + (long long)row * n + tc;
             double v[kMwTW];
 #pragma unroll
-            for (int j = 0; j < kMwTW; ++j) v[j] = c0 + j < n ? src[j] : 0.0;
+            for (int j = 0; j < kMwTW; ++j) v[j] = (row < m && tc + j * tpr < n) ? src[j * tpr] : 0.0;
 #pragma unroll
             for (int j = 0; j < kMwTW; ++j) {
-                xsum = fma(v[j], v[j], xsum);
-                if (fabs(v[j]) > xmax) { xmax = fabs(v[j]); xk = k * kMwTW + j; }
+                ldt[(k * kMwTW + j) * NA] = v[j];
+                acc.add(j, K + k, v[j]);
             }
         }
+        if (GL)
+            for (int k = K + kl; k < KT; ++k) {
+                const int row = r0 + tr + k * RS;
+                if (row >= m) break;
+                const double *src = A + (long long)row * n + tc;
+                double v[kMwTW];
+#pragma unroll
+                for (int j = 0; j < kMwTW; ++j) v[j] = tc + j * tpr < n ? src[j * tpr] : 0.0;
+#pragma unroll
+                for (int j = 0; j < kMwTW; ++j) acc.add(j, k, v[j]);
+            }
     }
     if (tid == 0) s_fail = 0;
     double tol2 = 0.0;  // every workgroup forms the same value from the same partials
     for (int t = 0;; ++t) {
         const int cur = t & 1;
         // partials of the residual after t pivots, and this stripe's candidate row
-        double lmax = -1.0, lsum = 0.0;
-        int lk = 0;  // the thread's best entry as k * kMwTW + j (the global index is formed once)
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-#pragma unroll
-            for (int j = 0; j < kMwTW; ++j) {
-                const double v = a[k][j], av = fabs(v);
-                lsum = fma(v, v, lsum);
-                const bool gt = av > lmax;
-                lmax = gt ? av : lmax;
-                lk = gt ? k * kMwTW + j : lk;
-            }
-        }
-        if (KL > 0 || GL) {  // the other rows have larger row indices: ties stay with the registers
-            lsum += xsum;
-            if (xmax > lmax) { lmax = xmax; lk = xk; }
-        }
-        long long lidx = (long long)(r0 + tr + (lk / kMwTW) * RS) * n + c0 + lk % kMwTW;
-        if (!active) { lmax = -1.0; lsum = 0.0; lidx = 0x7fffffffffffffffLL; }
+        double lmax, lsum;
+        int lk;  // the thread's best entry as k * kMwTW + j (the global index is formed once)
+        acc.merge(lmax, lsum, lk);
+        long long lidx = (long long)(r0 + tr + (lk / kMwTW) * RS) * n + tc + (lk % kMwTW) * tpr;
+        if (!active) { lmax = -1.0; lsum = 0.0; lidx = kNoRow; }
         wave_amax_sum(lmax, lidx, lsum);
         if (lane == 0) { wmax[wv] = lmax; widx[wv] = lidx; wsum[wv] = lsum; }
         __syncthreads();
@@ -1199,16 +1226,16 @@ __device__ __forceinline__ void prrlu_coop_body_t(const PrrluJob &J) {
                     if (k == kk)
 #pragma unroll
                         for (int j = 0; j < kMwTW; ++j)
-                            if (c0 + j < n) coop_put(dst + c0 + j, coop_word_d(a[k][j], tg));
-                if (kk >= K && kk < K + KL) {
+                            if (tc + j * tpr < n) coop_put(dst + tc + j * tpr, coop_word_d(a[k][j], tg));
+                if (kk >= K && kk < K + kl) {
 #pragma unroll
                     for (int j = 0; j < kMwTW; ++j)
-                        if (c0 + j < n) coop_put(dst + c0 + j, coop_word_d(ld[((kk - K) * kMwTW + j) * NT + tid], tg));
-                } else if (GL && kk >= K + KL) {
+                        if (tc + j * tpr < n) coop_put(dst + tc + j * tpr, coop_word_d(ldt[((kk - K) * kMwTW + j) * NA], tg));
+                } else if (GL && kk >= K + kl) {
                     const double *src = A + (long long)(r0 + local) * n;
 #pragma unroll
                     for (int j = 0; j < kMwTW; ++j)
-                        if (c0 + j < n) coop_put(dst + c0 + j, coop_word_d(src[c0 + j], tg));
+                        if (tc + j * tpr < n) coop_put(dst + tc + j * tpr, coop_word_d(src[tc + j * tpr], tg));
                 }
             }
         }
@@ -1218,15 +1245,16 @@ __device__ __forceinline__ void prrlu_coop_body_t(const PrrluJob &J) {
         bool ok = true;
         long long got[3 * SPL];
         if (lane < G) {  // slots lane, lane + 64, ...; a slot past the grid polls slot lane again
-            const long long *src[3 * SPL];
+            // (max, sum and index of a slot at offsets 0, G, 2G from pmx)
+            int off[3 * SPL];
 #pragma unroll
             for (int q = 0; q < SPL; ++q) {
                 const int sl = lane + kWave * q < G ? lane + kWave * q : lane;
-                src[3 * q] = pmx + sl;
-                src[3 * q + 1] = psm + sl;
-                src[3 * q + 2] = pix + sl;
+                off[3 * q] = sl;
+                off[3 * q + 1] = G + sl;
+                off[3 * q + 2] = 2 * G + sl;
             }
-            ok = coop_poll<3 * SPL>(src, tg, w.ctl, J.spin, got);
+            ok = coop_poll<3 * SPL>(pmx, off, tg, w.ctl, J.spin, got);
         }
         bool wave_ok = __ballot(!ok) == 0;
         if (lane < G && wave_ok) {
@@ -1268,31 +1296,42 @@ __device__ __forceinline__ void prrlu_coop_body_t(const PrrluJob &J) {
                 // the pivot entry and this thread's columns of the winning row, polled together
                 // (a column past the block's end polls the pivot entry again)
                 const long long *urow = prw + (long long)wk * n;
-                const long long *src[kMwTW + 1];
-                src[0] = urow + pj;
+                int off[kMwTW + 1];
+                off[0] = pj;
 #pragma unroll
-                for (int j = 0; j < kMwTW; ++j) src[1 + j] = (active && c0 + j < n) ? urow + c0 + j : urow + pj;
+                for (int j = 0; j < kMwTW; ++j) off[1 + j] = (active && tc + j * tpr < n) ? tc + j * tpr : pj;
                 long long v[kMwTW + 1];
-                if (coop_poll<kMwTW + 1>(src, tg, w.ctl, J.spin, v)) {
+                if (coop_poll<kMwTW + 1>(urow, off, tg, w.ctl, J.spin, v)) {
                     upj = coop_val_d(v[0]);
 #pragma unroll
-                    for (int j = 0; j < kMwTW; ++j) uu[j] = (active && c0 + j < n) ? coop_val_d(v[1 + j]) : 0.0;
+                    for (int j = 0; j < kMwTW; ++j)  // the pivot column is left out of the update
+                        uu[j] = (active && tc + j * tpr < n && tc + j * tpr != pj) ? coop_val_d(v[1 + j]) : 0.0;
                 } else {
                     s_fail = 1;
                 }
-                if (active && pj >= c0 && pj < c0 + kMwTW) {  // the pivot column's owners publish it
+                if (active && pj % tpr == tc) {
+                    // the pivot column's owners publish it, with 0 in the pivot row (whose
+                    // holders clear it and leave it out of the update), and clear it
+                    const int jp = pj / tpr;
 #pragma unroll
                     for (int j = 0; j < kMwTW; ++j)
-                        if (c0 + j == pj) {
+                        if (j == jp) {
 #pragma unroll
-                            for (int k = 0; k < K; ++k) lc[tr + k * RS] = a[k][j];
-#pragma unroll
-                            for (int k = 0; k < KL; ++k) lc[tr + (K + k) * RS] = ld[(k * kMwTW + j) * NT + tid];
+                            for (int k = 0; k < K; ++k) {
+                                lc[tr * KT + k] = r0 + tr + k * RS == pi ? 0.0 : a[k][j];
+                                a[k][j] = 0.0;
+                            }
                         }
+                    for (int k = 0; k < kl; ++k) {
+                        const int e = (k * kMwTW + jp) * NA;
+                        lc[tr * KT + K + k] = r0 + tr + (K + k) * RS == pi ? 0.0 : ldt[e];
+                        ldt[e] = 0.0;
+                    }
                     if (GL)
-                        for (int k = K + KL; k < KT; ++k) {
+                        for (int k = K + kl; k < KT; ++k) {
                             const int row = r0 + tr + k * RS;
-                            lc[tr + k * RS] = row < m ? A[(long long)row * n + pj] : 0.0;
+                            lc[tr * KT + k] = row < m && row != pi ? A[(long long)row * n + pj] : 0.0;
+                            if (row < m) A[(long long)row * n + pj] = 0.0;
                         }
                 }
             }
@@ -1309,67 +1348,71 @@ __device__ __forceinline__ void prrlu_coop_body_t(const PrrluJob &J) {
             return;
         }
         const double inv = 1.0 / upj;
+        acc.reset();
         if (active) {
+            // where the pivot row sits for this workgroup (pk uniform)
+            const int pl = pi - r0;
+            const int pk = (pl >= 0 && pl < J.rows) ? pl / RS : -1;
+            const bool rown = pk >= 0 && pl % RS == tr;
+            const double *lcr = lc + tr * KT;  // this thread's rows of the pivot column
+            // the pivot row's holders clear it (its multiplier in lc is 0, so it stays 0)
+            if (pk >= 0 && pk < K) {
+#pragma unroll
+                for (int k = 0; k < K; ++k)
+                    if (k == pk) {
+                        if (rown)
+#pragma unroll
+                            for (int j = 0; j < kMwTW; ++j) a[k][j] = 0.0;
+                    }
+            } else if (pk >= K && pk < K + kl) {
+                if (rown)
+#pragma unroll
+                    for (int j = 0; j < kMwTW; ++j) ldt[((pk - K) * kMwTW + j) * NA] = 0.0;
+            } else if (GL && pk >= K + kl) {
+                if (rown)
+#pragma unroll
+                    for (int j = 0; j < kMwTW; ++j)
+                        if (tc + j * tpr < n) A[(long long)pi * n + tc + j * tpr] = 0.0;
+            }
 #pragma unroll
             for (int k = 0; k < K; ++k) {
-                const int row = r0 + tr + k * RS;
-                if (row >= m) continue;
-                const double l = row == pi ? 1.0 : lc[tr + k * RS] * inv;
-                if (tc == 0) J.L[(long long)row * rmax + t] = l;
-                if (row == pi) {
-#pragma unroll
-                    for (int j = 0; j < kMwTW; ++j) a[k][j] = 0.0;
-                } else {
-#pragma unroll
-                    for (int j = 0; j < kMwTW; ++j) a[k][j] = fma(-l, uu[j], a[k][j]);
-                }
-            }
-            if (pj >= c0 && pj < c0 + kMwTW) {
-#pragma unroll
-                for (int j = 0; j < kMwTW; ++j)
-                    if (c0 + j == pj)
-#pragma unroll
-                        for (int k = 0; k < K; ++k) a[k][j] = 0.0;
-            }
-            // the other rows: eliminate, write back and form their partials for the next step
-            xmax = -1.0;
-            xsum = 0.0;
-            xk = 0;
-#pragma unroll
-            for (int k = 0; k < KL; ++k) {
-                const int row = r0 + tr + (K + k) * RS;
-                if (row >= m) continue;
-                const double l = row == pi ? 1.0 : lc[tr + (K + k) * RS] * inv;
-                if (tc == 0) J.L[(long long)row * rmax + t] = l;
-                double v[kMwTW];
-#pragma unroll
-                for (int j = 0; j < kMwTW; ++j) v[j] = ld[(k * kMwTW + j) * NT + tid];
+                const double l = lcr[k] * inv;
 #pragma unroll
                 for (int j = 0; j < kMwTW; ++j) {
-                    v[j] = (row == pi || c0 + j == pj) ? 0.0 : fma(-l, uu[j], v[j]);
-                    ld[(k * kMwTW + j) * NT + tid] = v[j];
-                    xsum = fma(v[j], v[j], xsum);
-                    if (fabs(v[j]) > xmax) { xmax = fabs(v[j]); xk = (K + k) * kMwTW + j; }
+                    a[k][j] = fma(-l, uu[j], a[k][j]);
+                    acc.add(j, k, a[k][j]);
+                }
+            }
+            for (int k = 0; k < kl; ++k) {
+                const double l = lcr[K + k] * inv;
+#pragma unroll
+                for (int j = 0; j < kMwTW; ++j) {
+                    const double v = fma(-l, uu[j], ldt[(k * kMwTW + j) * NA]);
+                    ldt[(k * kMwTW + j) * NA] = v;
+                    acc.add(j, K + k, v);
                 }
             }
             if (GL)
-                for (int k = K + KL; k < KT; ++k) {
+                for (int k = K + kl; k < KT; ++k) {
                     const int row = r0 + tr + k * RS;
                     if (row >= m) break;
-                    const double l = row == pi ? 1.0 : lc[tr + k * RS] * inv;
-                    if (tc == 0) J.L[(long long)row * rmax + t] = l;
-                    double *dst = A + (long long)row * n + c0;
+                    const double l = lcr[k] * inv;
+                    double *dst = A + (long long)row * n + tc;
                     double v[kMwTW];
 #pragma unroll
-                    for (int j = 0; j < kMwTW; ++j) v[j] = c0 + j < n ? dst[j] : 0.0;
+                    for (int j = 0; j < kMwTW; ++j) v[j] = tc + j * tpr < n ? dst[j * tpr] : 0.0;
 #pragma unroll
                     for (int j = 0; j < kMwTW; ++j) {
-                        v[j] = (row == pi || c0 + j == pj) ? 0.0 : fma(-l, uu[j], v[j]);
-                        if (c0 + j < n) dst[j] = v[j];
-                        xsum = fma(v[j], v[j], xsum);
-                        if (fabs(v[j]) > xmax) { xmax = fabs(v[j]); xk = k * kMwTW + j; }
+                        v[j] = fma(-l, uu[j], v[j]);
+                        if (tc + j * tpr < n) dst[j * tpr] = v[j];
+                        acc.add(j, k, v[j]);
                     }
                 }
+        }
+        // the multipliers (the pivot row's is 1), stripe row q = tr + k RS from lc[tr KT + k]
+        for (int q = tid; q < J.rows; q += NT) {
+            const int row = r0 + q;
+            if (row < m) J.L[(long long)row * rmax + t] = row == pi ? 1.0 : lc[(q % RS) * KT + q / RS] * inv;
         }
         // lc and the wave partials are next written after the next step's first barrier, which
         // every wave reaches only when done with this step's values
@@ -1377,16 +1420,17 @@ __device__ __forceinline__ void prrlu_coop_body_t(const PrrluJob &J) {
 }
 
 __device__ __forceinline__ void prrlu_coop_body(const PrrluJob &J) {
-    prrlu_coop_body_t<kMwThreads, kMwK, 0, false, 1, kMwThreads * kMwK>(J);
+    prrlu_coop_body_t<kMwThreads, kMwK, false, 1, kMwThreads * kMwK>(J);
 }
 
 __global__ __launch_bounds__(kMwThreads) void k_prrlu_coop(PrrluJob J) { prrlu_coop_body(J); }
 
-// The persistent form for blocks of up to ~5 10^6 entries: K rows per thread in registers (a
-// block of 22528 x 240 is 176 stripes of 128 rows at K = 16), up to 256 workgroups, one per CU.
-template <int K, int KL, bool GL>
+// The persistent form for large blocks: K rows per thread in registers (a block of 22528 x 240
+// is 176 stripes of 128 rows at K = 16), with LB > kCoopBigRows J.kl more in LDS and with GL the
+// rest streamed, up to 256 workgroups, one per CU.
+template <int K, bool GL, int LB>
 __global__ __launch_bounds__(kMwThreads) void k_prrlu_coop_big(PrrluJob J) {
-    prrlu_coop_body_t<kMwThreads, K, KL, GL, kCoopBigSlots / kWave, kCoopBigRows>(J);
+    prrlu_coop_body_t<kMwThreads, K, GL, kCoopBigSlots / kWave, LB>(J);
 }
 
 __global__ __launch_bounds__(kMwThreads) void k_prrlu_coop_batch(const PrrluJob *__restrict__ jobs) {
@@ -2336,14 +2380,14 @@ void set_coop_spin(int polls) { g_coop_spin = polls > 0 ? polls : (polls == 0 ? 
 
 // Workgroups of the large persistent form with K register rows and KL LDS rows per thread that
 // the device holds at once.
-template <int K, int KL, bool GL>
+template <int K, bool GL, int LB>
 int coop_big_capacity() {
     static int cap = -1;
     if (cap < 0) {
         int dev = 0, ncu = 0, nb = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_prrlu_coop_big<K, KL, GL>, kMwThreads, 0) != hipSuccess)
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_prrlu_coop_big<K, GL, LB>, kMwThreads, 0) != hipSuccess)
             cap = 0;
         else
             cap = nb * ncu;
@@ -2352,12 +2396,14 @@ int coop_big_capacity() {
 }
 
 // mode 4 (allow_big): a block whose kMwK-row stripes would need more workgroups than the small
-// persistent form takes is split into stripes of 8, 16 (registers) or 24 (16 in registers, 8 in
-// LDS) rows per thread, the first whose grid fits kCoopBigSlots and the device at once, or of
-// more rows per thread (the rest streamed from the block), and factorised in one persistent
-// launch; the rows per thread are kept in shape.
+// persistent form takes is split into stripes of 8 or 16 rows per thread held in registers, the
+// first whose grid fits kCoopBigSlots and the device at once, or else over as many workgroups as
+// the device holds at once into stripes of more rows per thread: 16 in registers, as many more as
+// fit in LDS, the rest streamed from the block; all factorised in one persistent launch (shape:
+// rows per thread, kl: rows per thread in LDS).
 void prrlu_prepare(PrrluJob &j, bool allow_big) {
     j.spin = g_coop_spin;
+    j.kl = 0;
     j.shape = tile_shape_for(j.m, j.n);
     const int tpr = (j.n + kMwTW - 1) / kMwTW;
     WTT_REQUIRE(tpr <= kMwThreads && j.n <= kMwCand, WENOTT_EINVAL,
@@ -2373,12 +2419,11 @@ void prrlu_prepare(PrrluJob &j, bool allow_big) {
         return;
     }
     if (allow_big) {
-        // 24 rows in registers would spill to scratch memory: the third form keeps 8 of them in LDS
-        const int ks[3] = {8, 16, 24};
-        const int caps[3] = {coop_big_capacity<8, 0, false>(), coop_big_capacity<16, 0, false>(),
-                             coop_big_capacity<16, 8, false>()};
-        const int RS = kMwThreads / tpr;
-        for (int q = 0; q < 3; ++q) {
+        // more than 16 rows per thread in registers would spill to scratch memory
+        const int ks[2] = {8, 16};
+        const int caps[2] = {coop_big_capacity<8, false, kCoopBigRows>(), coop_big_capacity<16, false, kCoopBigRows>()};
+        const int RS = kMwThreads / tpr, NA = RS * tpr;
+        for (int q = 0; q < 2; ++q) {
             const int rows = RS * ks[q];
             const int nblk = (j.m + rows - 1) / rows;
             if (rows <= kCoopBigRows && nblk <= kCoopBigSlots && nblk <= caps[q]) {
@@ -2389,16 +2434,17 @@ void prrlu_prepare(PrrluJob &j, bool allow_big) {
                 return;
             }
         }
-        // larger still: the rows beyond 24 per thread stay in the block and are streamed at every
-        // step, over as many workgroups as the device holds at once
-        const int gmax = std::min(kCoopBigSlots, coop_big_capacity<14, 8, true>());
+        const int gmax = std::min(kCoopBigSlots, std::min(coop_big_capacity<16, false, kCoopLdsDoubles>(),
+                                                          coop_big_capacity<16, true, kCoopLdsDoubles>()));
         if (gmax > 0) {
-            const int per = (j.m + gmax - 1) / gmax;  // rows per workgroup
-            const int kt = std::max(25, (per + RS - 1) / RS);  // 14 in registers, 8 in LDS, the rest streamed
+            const int per = (j.m + gmax - 1) / gmax;           // rows per workgroup
+            const int kt = std::max(17, (per + RS - 1) / RS);  // rows per thread
             const int rows = RS * kt;
-            if (rows <= kCoopBigRows) {
+            const int kl = std::min(kt - 16, (kCoopLdsDoubles - rows) / (kMwTW * NA));
+            if (rows <= kCoopBigRows && kl >= 0) {
                 j.mode = 4;
                 j.shape = kt;
+                j.kl = kl;
                 j.rows = rows;
                 j.nblk = (j.m + rows - 1) / rows;
                 return;
@@ -2423,14 +2469,13 @@ void prrlu_layout(int m, int n, bool allow_big, int *out) {
     out[2] = j.rows;
     out[3] = j.nblk;
     out[4] = j.mode == 2 ? coop_capacity()
-                         : (j.mode == 4 ? (j.shape == 8 ? coop_big_capacity<8, 0, false>()
-                                                        : (j.shape == 16 ? coop_big_capacity<16, 0, false>()
-                                                                         : (j.shape == 24
-                                                                                ? coop_big_capacity<16, 8, false>()
-                                                                                : coop_big_capacity<14, 8, true>())))
+                         : (j.mode == 4 ? (j.shape == 8    ? coop_big_capacity<8, false, kCoopBigRows>()
+                                           : j.shape == 16 ? coop_big_capacity<16, false, kCoopBigRows>()
+                                           : j.shape == 16 + j.kl ? coop_big_capacity<16, false, kCoopLdsDoubles>()
+                                                                  : coop_big_capacity<16, true, kCoopLdsDoubles>())
                                         : 0);
-    out[5] = coop_big_capacity<16, 8, false>();
-    out[6] = coop_big_capacity<14, 8, true>();
+    out[5] = j.kl;
+    out[6] = j.mode == 4 && j.shape > 16 ? j.shape - 16 - j.kl : 0;
 }
 
 // Enough for every layout prrlu may take for this block (the persistent one and its stepped
@@ -2456,10 +2501,10 @@ int prrlu(hipStream_t s, int m, int n, double *A, int rmax, double rel_tol2, int
     if (j.mode == 4) {  // large blocks: the whole factorisation in one launch, stripes in registers
         if (t_begin > 0) return rmax + 2;
         k_prrlu_mw_init<<<1, kMwThreads, 0, s>>>(j);
-        if (j.shape == 8) k_prrlu_coop_big<8, 0, false><<<j.nblk, kMwThreads, 0, s>>>(j);
-        else if (j.shape == 16) k_prrlu_coop_big<16, 0, false><<<j.nblk, kMwThreads, 0, s>>>(j);
-        else if (j.shape == 24) k_prrlu_coop_big<16, 8, false><<<j.nblk, kMwThreads, 0, s>>>(j);
-        else k_prrlu_coop_big<14, 8, true><<<j.nblk, kMwThreads, 0, s>>>(j);
+        if (j.shape == 8) k_prrlu_coop_big<8, false, kCoopBigRows><<<j.nblk, kMwThreads, 0, s>>>(j);
+        else if (j.shape == 16) k_prrlu_coop_big<16, false, kCoopBigRows><<<j.nblk, kMwThreads, 0, s>>>(j);
+        else if (j.shape == 16 + j.kl) k_prrlu_coop_big<16, false, kCoopLdsDoubles><<<j.nblk, kMwThreads, 0, s>>>(j);
+        else k_prrlu_coop_big<16, true, kCoopLdsDoubles><<<j.nblk, kMwThreads, 0, s>>>(j);
         WTT_HIP(hipGetLastError());
         return rmax + 2;
     }

@@ -40,9 +40,10 @@ def _block(m, n, rank, seed):
     (900, 120, 20, False),       # the same stepped
     (6000, 200, 30, True),       # long stripes in registers
     (22528, 240, 44, True),      # 16 rows per thread
-    (30208, 315, 48, True),      # 24 rows per thread (8 in LDS)
+    (30208, 315, 48, True),      # 20 rows per thread (4 in LDS)
     (30208, 315, 48, False),     # stepped, long stripes
     (61440, 300, 40, True),      # rows streamed through the block
+    (22528, 660, 100, True),     # the widest cross blocks of the 512^3 workload
 ])
 def test_pivot_search_matches_the_definition(W, m, n, rank, persistent):
     import torch
