@@ -1385,11 +1385,18 @@ __device__ __forceinline__ void prrlu_coop_body_t(const PrrluJob &J) {
             }
             for (int k = 0; k < kl; ++k) {
                 const double l = lcr[K + k] * inv;
+                double v[kMwTW];
+#pragma unroll
+                for (int j = 0; j < kMwTW; ++j) v[j] = ldt[(k * kMwTW + j) * NA];
+                // all the row's reads are issued before the first is used
+                static_assert(kMwTW == 8, "one asm operand per column");
+                asm volatile("" : "+v"(v[0]), "+v"(v[1]), "+v"(v[2]), "+v"(v[3]), "+v"(v[4]), "+v"(v[5]), "+v"(v[6]),
+                             "+v"(v[7]));
 #pragma unroll
                 for (int j = 0; j < kMwTW; ++j) {
-                    const double v = fma(-l, uu[j], ldt[(k * kMwTW + j) * NA]);
-                    ldt[(k * kMwTW + j) * NA] = v;
-                    acc.add(j, K + k, v);
+                    v[j] = fma(-l, uu[j], v[j]);
+                    ldt[(k * kMwTW + j) * NA] = v[j];
+                    acc.add(j, K + k, v[j]);
                 }
             }
             if (GL)
@@ -1401,6 +1408,8 @@ __device__ __forceinline__ void prrlu_coop_body_t(const PrrluJob &J) {
                     double v[kMwTW];
 #pragma unroll
                     for (int j = 0; j < kMwTW; ++j) v[j] = tc + j * tpr < n ? dst[j * tpr] : 0.0;
+                    asm volatile("" : "+v"(v[0]), "+v"(v[1]), "+v"(v[2]), "+v"(v[3]), "+v"(v[4]), "+v"(v[5]), "+v"(v[6]),
+                                 "+v"(v[7]));
 #pragma unroll
                     for (int j = 0; j < kMwTW; ++j) {
                         v[j] = fma(-l, uu[j], v[j]);
