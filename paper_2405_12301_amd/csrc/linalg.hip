@@ -1327,11 +1327,23 @@ __device__ __forceinline__ void prrlu_coop_body_t(const PrrluJob &J) {
                         lc[tr * KT + K + k] = r0 + tr + (K + k) * RS == pi ? 0.0 : ldt[e];
                         ldt[e] = 0.0;
                     }
-                    if (GL)
-                        for (int k = K + kl; k < KT; ++k) {
-                            const int row = r0 + tr + k * RS;
-                            lc[tr * KT + k] = row < m && row != pi ? A[(long long)row * n + pj] : 0.0;
-                            if (row < m) A[(long long)row * n + pj] = 0.0;
+                    if (GL)  // the streamed rows' entries, four reads issued together
+                        for (int k0 = K + kl; k0 < KT; k0 += 4) {
+                            double v[4];
+#pragma unroll
+                            for (int h = 0; h < 4; ++h) {
+                                const int row = r0 + tr + (k0 + h) * RS;
+                                v[h] = k0 + h < KT && row < m ? A[(long long)row * n + pj] : 0.0;
+                            }
+                            asm volatile("" : "+v"(v[0]), "+v"(v[1]), "+v"(v[2]), "+v"(v[3]));
+#pragma unroll
+                            for (int h = 0; h < 4; ++h) {
+                                const int k = k0 + h, row = r0 + tr + k * RS;
+                                if (k < KT) {
+                                    lc[tr * KT + k] = row != pi ? v[h] : 0.0;
+                                    if (row < m) A[(long long)row * n + pj] = 0.0;
+                                }
+                            }
                         }
                 }
             }
