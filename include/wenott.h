@@ -366,7 +366,8 @@ int64_t wenott_mlp_nparams(void);
 int64_t wenott_mlp_workspace(int32_t batch);
 /* He-normal weights, zero biases, from a counter-based generator. params: device. */
 wenott_status wenott_mlp_init_params(float *params, uint64_t seed, void *hip_stream);
-/* y[batch][OUT] = MLP(x[batch][IN]); all device; bf16 != 0 rounds operands to BF16. */
+/* y[batch][OUT] = MLP(x[batch][IN]); all device; bf16 != 0: operands rounded to BF16, FP32 sums on
+ * the matrix cores (v_mfma_f32_16x16x16bf16_1k). */
 wenott_status wenott_mlp_forward(const float *params, const float *x, int32_t batch, float *y, int32_t bf16,
                                  float *work, void *hip_stream);
 /* grad[nparams] and loss (device scalar) of a batch; rank_class[batch] in 0..16, hist[batch][BINS]. */

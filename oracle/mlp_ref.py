@@ -31,6 +31,23 @@ def forward(p, x):
     return h1, h2, h2 @ W3 + b3
 
 
+def bf16(a):
+    """Round to the nearest BF16 value (ties to even), returned as float64: the upper 16 bits of
+    the FP32 encoding after adding half an ulp of the bits dropped."""
+    u = np.asarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000).astype(np.uint32)
+    return r.view(np.float32).astype(np.float64)
+
+
+def forward_bf16(p, x):
+    """BF16 inference: every layer's operands (input or previous activation as FP32, weights,
+    biases) rounded to BF16, products and sums exact (FP64)."""
+    W1, b1, W2, b2, W3, b3 = unpack(p)
+    h1 = np.maximum(bf16(x) @ bf16(W1) + bf16(b1), 0.0).astype(np.float32)
+    h2 = np.maximum(bf16(h1) @ bf16(W2) + bf16(b2), 0.0).astype(np.float32)
+    return h1, h2, bf16(h2) @ bf16(W3) + bf16(b3)
+
+
 def _logsumexp(z):
     m = z.max(axis=1, keepdims=True)
     return m[:, 0] + np.log(np.exp(z - m).sum(axis=1))

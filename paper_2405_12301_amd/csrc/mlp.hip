@@ -5,7 +5,7 @@
 // the next right index set should sample. Loss: cross-entropy of the rank class plus
 // cross-entropy of the bin distribution against the target histogram, averaged over the batch.
 // Training kernels run in FP32; inference can use BF16 weights and activations with FP32
-// accumulation.
+// accumulation on the matrix cores.
 #include <cmath>
 #include <cstdint>
 #include <functional>
@@ -43,6 +43,44 @@ __global__ void k_dense(int B, int nin, int nout, const float *__restrict__ in, 
     }
     acc += bf16 ? bf16_round(bias[o]) : bias[o];
     out[e] = relu ? fmaxf(acc, 0.f) : acc;
+}
+
+// The BF16 encoding of x rounded to nearest even (the upper 16 bits of bf16_round(x)).
+__device__ inline short bf16_bits(float x) { return (short)(__float_as_uint(bf16_round(x)) >> 16); }
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// The BF16 form of k_dense on the matrix cores: one wave per 16 x 16 tile of out (16 samples x
+// 16 outputs), v_mfma_f32_16x16x16bf16_1k over K in steps of 16. Operand layout of the
+// instruction: lane l supplies A[l % 16][4 (l / 16) + j] and B[4 (l / 16) + j][l % 16], j < 4,
+// and holds D[4 (l / 16) + v][l % 16], v < 4. The products of BF16 operands are exact in FP32,
+// so the result differs from k_dense's BF16 form only by the order of the FP32 sums.
+__global__ __launch_bounds__(64) void k_dense_bf16_mfma(int B, int nin, int nout, const float *__restrict__ in,
+                                                        const float *__restrict__ W, const float *__restrict__ bias,
+                                                        float *__restrict__ out, int relu) {
+    const int l = threadIdx.x, o0 = blockIdx.x * 16, b0 = blockIdx.y * 16;
+    const int r = l % 16, kg = 4 * (l / 16);
+    const int b = b0 + r, o = o0 + r;  // this lane's row of A and column of B
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < nin; k0 += 16) {
+        bf16x4 av, bv;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int k = k0 + kg + j;
+            av[j] = (b < B && k < nin) ? bf16_bits(in[(long long)b * nin + k]) : (short)0;
+            bv[j] = (o < nout && k < nin) ? bf16_bits(W[(long long)k * nout + o]) : (short)0;
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int bo = b0 + kg + v;
+        if (bo < B && o < nout) {
+            const float y = acc[v] + bf16_round(bias[o]);
+            out[(long long)bo * nout + o] = relu ? fmaxf(y, 0.f) : y;
+        }
+    }
 }
 
 // dy = (softmax - target) / B for both heads; per-sample loss into lossb[b]
@@ -157,10 +195,18 @@ struct Acts {  // activations of one batch (device, FP32)
     float *h1, *h2, *y;
 };
 
+// bf16: BF16 operands with FP32 sums on the matrix cores; else FP32 on the vector units
 void forward(hipStream_t s, const float *P, const float *x, int B, Acts a, int bf16) {
-    k_dense<<<cdiv((long long)B * HID, 256), 256, 0, s>>>(B, IN, HID, x, P + OFF_W1, P + OFF_B1, a.h1, 1, bf16);
-    k_dense<<<cdiv((long long)B * HID, 256), 256, 0, s>>>(B, HID, HID, a.h1, P + OFF_W2, P + OFF_B2, a.h2, 1, bf16);
-    k_dense<<<cdiv((long long)B * OUT, 256), 256, 0, s>>>(B, HID, OUT, a.h2, P + OFF_W3, P + OFF_B3, a.y, 0, bf16);
+    if (bf16) {
+        const int bt = (B + 15) / 16;
+        k_dense_bf16_mfma<<<dim3((HID + 15) / 16, bt), 64, 0, s>>>(B, IN, HID, x, P + OFF_W1, P + OFF_B1, a.h1, 1);
+        k_dense_bf16_mfma<<<dim3((HID + 15) / 16, bt), 64, 0, s>>>(B, HID, HID, a.h1, P + OFF_W2, P + OFF_B2, a.h2, 1);
+        k_dense_bf16_mfma<<<dim3((OUT + 15) / 16, bt), 64, 0, s>>>(B, HID, OUT, a.h2, P + OFF_W3, P + OFF_B3, a.y, 0);
+    } else {
+        k_dense<<<cdiv((long long)B * HID, 256), 256, 0, s>>>(B, IN, HID, x, P + OFF_W1, P + OFF_B1, a.h1, 1, 0);
+        k_dense<<<cdiv((long long)B * HID, 256), 256, 0, s>>>(B, HID, HID, a.h1, P + OFF_W2, P + OFF_B2, a.h2, 1, 0);
+        k_dense<<<cdiv((long long)B * OUT, 256), 256, 0, s>>>(B, HID, OUT, a.h2, P + OFF_W3, P + OFF_B3, a.y, 0, 0);
+    }
     WTT_HIP(hipGetLastError());
 }
 

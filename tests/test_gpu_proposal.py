@@ -60,10 +60,14 @@ def test_mlp_gradients_match_fp64_reference(W):
     W.wenott_mlp_forward(P, xt, y, work, False)
     y_ref = mlp_ref.forward(p64, x.astype(np.float64))[2]
     e32 = np.abs(y.cpu().numpy() - y_ref).max() / np.abs(y_ref).max()
-    W.wenott_mlp_forward(P, xt, y, work, True)
+    W.wenott_mlp_forward(P, xt, y, work, True)  # BF16 operands on the matrix cores
     e16 = np.abs(y.cpu().numpy() - y_ref).max() / np.abs(y_ref).max()
-    _say(f"  forward max rel err FP32 {e32:.2e}, BF16 {e16:.2e}")
-    assert e32 <= 1e-5 and e16 <= 3e-2
+    y16 = mlp_ref.forward_bf16(p64, x.astype(np.float64))[2]
+    e16b = np.abs(y.cpu().numpy() - y16).max() / np.abs(y16).max()
+    _say(f"  forward max rel err FP32 {e32:.2e}, BF16 {e16:.2e} (against BF16 inference in FP64: {e16b:.2e})")
+    # FP32 sums against exact ones; an activation whose FP32 and FP64 values round to
+    # neighbouring BF16 values moves the next layer by one BF16 step of that operand
+    assert e32 <= 1e-5 and e16 <= 3e-2 and e16b <= 1e-3
 
 
 def _quadrant_flows(seeds, n):
