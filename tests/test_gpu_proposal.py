@@ -121,3 +121,84 @@ def test_proposal_trained_on_pivot_logs(W):
              f"{wall * 1e3 / 10:.2f} ms/step, worst step err / eps {worst:.2f}")
     assert stats[1][2] > 0
     assert stats[0][5] <= 10 and stats[1][5] <= 10
+
+
+def _tilted_sod_runs(W, P, n, steps, warm, check_last_only):
+    """Plain cross and proposal-seeded cross on the tilted Sod at n^3 (eps dynamic from 1e-6):
+    pivots, sweeps and ms per step over `steps` steps after `warm` untimed ones; every timed step
+    (or only the last one) checked against the oracle within 10 eps_TT."""
+    import torch
+    f = workloads.config5_tilted_sod_3d(n, seed=0)
+    # an untimed plain run first, so that the contraction tile tuner (process-wide, tuned on live
+    # calls) has settled before either timed run
+    s = W.Solver(f, W.default_opts(eps_mode=1, eps0=f.eps0))
+    try:
+        for _ in range(warm + steps):
+            s.step(f.cfl * min(f.h) / s.max_wavespeed())
+    finally:
+        s.close()
+    stats = {}
+    for use in (0, 1):
+        s = W.Solver(f, W.default_opts(eps_mode=1, eps0=f.eps0, use_proposal=use))
+        try:
+            if use:
+                W.wenott_set_proposal(s.ctx, P)
+            Pb = oracle_problem(f)
+            for _ in range(warm):
+                s.step(f.cfl * min(f.h) / s.max_wavespeed())
+            piv = sweeps = tried = acc = 0
+            wall = 0.0
+            worst = 0.0
+            for k in range(steps):
+                check = (k == steps - 1) or not check_last_only
+                u = s.dense() if check else None
+                dt = f.cfl * min(f.h) / s.max_wavespeed()
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                s.step(dt)
+                torch.cuda.synchronize()
+                wall += time.perf_counter() - t1
+                info = s.info()
+                piv += info.pivots_total
+                tried += info.proposals_tried
+                acc += info.proposals_accepted
+                sweeps += sum(info.sweeps[i][j] for i in range(3) for j in range(1))
+                if check:
+                    Pb.ssprk3(u, dt, alphas=[info.alpha[i] for i in range(3)])
+                    worst = max(worst, rel_err(s.dense(), u) / info.eps)
+                    del u
+            stats[use] = (piv, sweeps, tried, acc, wall * 1e3 / steps, worst)
+        finally:
+            s.close()
+    for use in (0, 1):
+        piv, sw, tr, ac, ms, worst = stats[use]
+        _say(f"  {n}^3 {'proposal' if use else 'plain   '}: pivots {piv}, sweeps {sw}, proposals {ac}/{tr} "
+             f"accepted, {ms:.2f} ms/step, worst checked step err / eps {worst:.2f}")
+    return stats
+
+
+def test_proposal_trained_on_blasts_evaluated_on_tilted_sod(W):
+    """Logs of 200 spherical blasts (seeds 1000-1199 at 64^3, edge width 0.04, 3 logged steps each) train the
+    network; on the tilted Sod (the benchmark workload) the plain and proposal-seeded crosses are
+    compared at 128^3 (6 steps, each checked against the oracle) and at 512^3 (10 timed steps after
+    3, the last checked against the oracle): pivots, sweeps and ms per step are printed; whether
+    the proposal gains is reported, not asserted."""
+    from paper_2405_12301_amd import proposal
+    _say("case: proposal trained on 200 blasts, evaluated on the tilted Sod")
+    t0 = time.time()
+    # at 64^3 the ball's edge is spread over 2.5 cells (width 0.04)
+    flows = [workloads.config4_blast_3d(seed, n=(64, 64, 64), width=0.04) for seed in range(1000, 1200)]
+    # a blast's stacked components can need more than the rank limit of a cross: its sampled
+    # residual may stay above eps after the sweeps, which the explicit slack accepts for logging
+    x, cls, hist = proposal.collect_logs(flows, steps=3,
+                                         opts=W.default_opts(eps_mode=1, eps0=flows[0].eps0, conv_slack=1e3))
+    _say(f"  logged {x.shape[0]} samples from {len(flows)} blasts in {time.time() - t0:.1f} s; "
+         f"rank classes {np.bincount(cls, minlength=17)}")
+    P, losses = proposal.train(x, cls, hist, iters=400)
+    _say(f"  training loss {losses[0]:.3f} -> {losses[-1]:.3f}")
+    assert losses[-1] < losses[0]
+    s128 = _tilted_sod_runs(W, P, 128, steps=6, warm=0, check_last_only=False)
+    s512 = _tilted_sod_runs(W, P, 512, steps=10, warm=3, check_last_only=True)
+    for st in (s128, s512):
+        assert st[1][2] > 0  # the proposal was tried
+        assert st[0][5] <= 10 and st[1][5] <= 10
