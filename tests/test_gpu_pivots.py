@@ -44,6 +44,10 @@ def _block(m, n, rank, seed):
     (30208, 315, 48, False),     # stepped, long stripes
     (61440, 300, 40, True),      # rows streamed through the block
     (22528, 660, 100, True),     # the widest cross blocks of the 512^3 workload
+    (40000, 9, 5, True),         # narrow: two threads per row
+    (38000, 255, 60, True),      # 16 rows per thread in registers, 3 in LDS
+    (90000, 200, 20, True),      # 16 in registers, 10 in LDS, 10 streamed
+    (5000, 2048, 30, True),      # the widest block the layout takes: one row per 256 threads
 ])
 def test_pivot_search_matches_the_definition(W, m, n, rank, persistent):
     import torch
