@@ -227,13 +227,15 @@ wenott_status wenott_batch_rk3_step(wenott_ctx **ctxs, int32_t n, const double *
 /*
  * Tile autotuner of the FP64 contractions (process-wide). Each problem bucket (transposes and
  * the binary orders of magnitude of M, N, K and the batch) is tuned on its first live calls:
- * the candidate shapes (64x64, 32x64, 64x32, 32x32 on the vector units, and 64x64 on the FP64
- * matrix cores) are timed with events collected without synchronising, and the fastest is kept.
- * The vector shapes sum every output in the same order; the matrix-core shape agrees with them
- * to rounding. mode 1: tuned (default); 0: the 64x64 vector shape everywhere; 2 + k: shape k
- * everywhere (k = 0..4). The table call copies up to max rows of {ta, tb, log2 M, log2 N,
- * log2 K, log2 batch, shape (-1 while tuning)} into out (may be NULL) and stores the number of
- * rows in *count.
+ * the candidate shapes (0-3: 64x64, 32x64, 64x32, 32x32 on the vector units; 4: 64x64 on the
+ * FP64 matrix cores; 5-7: matrix-core forms with one operand staged once per workgroup, A
+ * (M <= 64) or B in groups of 64 or 32 columns, for untransposed products with K <= 64) are
+ * timed with events collected without synchronising, and the fastest is kept. The vector
+ * shapes sum every output in the same order; the matrix-core shapes agree with them to
+ * rounding. mode 1: tuned (default); 0: the 64x64 vector shape everywhere; 2 + k: shape k
+ * everywhere (k = 0..7; a resident-operand shape runs as shape 4 on a product it does not
+ * fit). The table call copies up to max rows of {ta, tb, log2 M, log2 N, log2 K, log2 batch,
+ * shape (-1 while tuning)} into out (may be NULL) and stores the number of rows in *count.
  */
 wenott_status wenott_gemm_autotune(int32_t mode);
 wenott_status wenott_gemm_autotune_table(int32_t *out, int32_t max, int32_t *count);

@@ -2739,7 +2739,7 @@ wenott_status wenott_finalize(void) {
 }
 
 wenott_status wenott_gemm_autotune(int32_t mode) {
-    if (mode < 0 || mode > 6) return WENOTT_EINVAL;
+    if (mode < 0 || mode > 9) return WENOTT_EINVAL;  // 2 + k forces shape k = 0..7
     gemm_tune_enable(mode);
     return WENOTT_OK;
 }

@@ -290,6 +290,177 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(int M, int N, int K, double a
             }
 }
 
+// Resident-operand forms for products with a short reduction (K <= 4 KSM, no split-K, neither
+// operand transposed), the interface contractions of the gathers: one operand is staged once per
+// workgroup in LDS, in the lane order of the v_mfma_f64_16x16x4f64 fragments (one conflict-free
+// 64-lane read per fragment), and the other streams from memory in 16-wide strips, each wave
+// loading its next strip while the matrix cores work on the current one; registers hold only the
+// streamed strips and the accumulators, so that several waves share a SIMD. Lane group
+// g = l / 16 takes the reduction indices [g KS, (g + 1) KS), KS = ceil(K / 4), one per MFMA step,
+// so that a lane reads KS consecutive entries of a row of A and every 16 lanes read 128
+// contiguous bytes of a row of B; indices at or beyond K contribute zeros. Accumulator v of lane
+// l holds D[l / 16 + 4 v][l % 16].
+
+// s_waitcnt vmcnt(0) with expcnt and lgkmcnt left open (gfx9 encoding: vmcnt in bits 3:0 and
+// 15:14, expcnt 6:4, lgkmcnt 11:8). Issued after a strip's products and before its stores, while
+// only the next strip's loads are in flight, it lets the copies of those loads at the end of the
+// iteration go without waiting on the stores.
+constexpr int kWaitLoadsOnly = 0x0F70;
+
+// A resident (M <= 16 MI; LDS [i][s][lane] = A[16 i + l % 16][g KS + s]): wave w of the grid takes
+// the 16-column strips w, w + W, ... of B and C.
+template <int MI, int KSM>
+__global__ __launch_bounds__(256) void k_gemm_mfma_ra(int M, int N, int K, double alpha, const double *__restrict__ A,
+                                                      int lda, const double *__restrict__ B, int ldb, double beta,
+                                                      double *__restrict__ C, int ldc, GemmBatch bt) {
+    __shared__ double As[MI * KSM * kWave];
+    const int z = blockIdx.z, z1 = z / bt.nb2, z2 = z % bt.nb2;
+    A += z1 * bt.sA1 + z2 * bt.sA2;
+    B += z1 * bt.sB1 + z2 * bt.sB2;
+    C += z1 * bt.sC1 + z2 * bt.sC2;
+    const int lane = threadIdx.x % kWave, g = lane / 16, c = lane % 16;
+    const int KS = (K + 3) / 4, k0 = g * KS;
+    for (int e = threadIdx.x; e < MI * KSM * kWave; e += blockDim.x) {
+        const int l = e % kWave, s = (e / kWave) % KSM, i = e / (kWave * KSM);
+        const int row = 16 * i + l % 16, k = (l / 16) * KS + s;
+        As[e] = (s < KS && k < K && row < M) ? A[(long long)row * lda + k] : 0.0;
+    }
+    __syncthreads();
+    const int nstrip = (N + 15) / 16, nw = gridDim.x * (blockDim.x / kWave);
+    int st = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    // the streamed loads are unconditional (an index outside the strip reads element 0 and the
+    // value is replaced by 0), so that the next strip's loads stay in flight across the products
+    double bn[KSM];
+#pragma unroll
+    for (int s = 0; s < KSM; ++s) {
+        const int col = 16 * st + c, k = k0 + s;
+        const bool in = st < nstrip && s < KS && k < K && col < N;
+        const double v = B[in ? (long long)k * ldb + col : 0];
+        bn[s] = in ? v : 0.0;
+    }
+    while (st < nstrip) {
+        double b[KSM];
+#pragma unroll
+        for (int s = 0; s < KSM; ++s) b[s] = bn[s];
+        const int nx = st + nw;
+#pragma unroll
+        for (int s = 0; s < KSM; ++s) {
+            const int col = 16 * nx + c, k = k0 + s;
+            const bool in = nx < nstrip && s < KS && k < K && col < N;
+            const double v = B[in ? (long long)k * ldb + col : 0];
+            bn[s] = in ? v : 0.0;
+        }
+        f64x4 acc[MI];
+#pragma unroll
+        for (int i = 0; i < MI; ++i) acc[i] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < KSM; ++s)
+            if (s < KS)
+#pragma unroll
+                for (int i = 0; i < MI; ++i)
+                    acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(As[(i * KSM + s) * kWave + lane], b[s], acc[i], 0, 0, 0);
+        __builtin_amdgcn_s_waitcnt(kWaitLoadsOnly);
+        const int col = 16 * st + c;
+        if (beta == 0.0) {
+#pragma unroll
+            for (int i = 0; i < MI; ++i)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = 16 * i + g + 4 * v;
+                    if (row < M && col < N) C[(long long)row * ldc + col] = alpha * acc[i][v];
+                }
+        } else {
+#pragma unroll
+            for (int i = 0; i < MI; ++i)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = 16 * i + g + 4 * v;
+                    if (row < M && col < N) {
+                        double *o = C + (long long)row * ldc + col;
+                        *o = alpha * acc[i][v] + beta * *o;
+                    }
+                }
+        }
+        st = nx;
+    }
+}
+
+// B resident (LDS [j][s][lane] = B[g KS + s][cb + 16 j + l % 16]): blockIdx.y picks the group of NJ
+// 16-column blocks starting at column cb; wave w of the x-grid takes the 16-row strips
+// w, w + W, ... of A and C.
+template <int NJ, int KSM>
+__global__ __launch_bounds__(256) void k_gemm_mfma_rb(int M, int N, int K, double alpha, const double *__restrict__ A,
+                                                      int lda, const double *__restrict__ B, int ldb, double beta,
+                                                      double *__restrict__ C, int ldc, GemmBatch bt) {
+    __shared__ double Bs[NJ * KSM * kWave];
+    const int z = blockIdx.z, z1 = z / bt.nb2, z2 = z % bt.nb2;
+    A += z1 * bt.sA1 + z2 * bt.sA2;
+    B += z1 * bt.sB1 + z2 * bt.sB2;
+    C += z1 * bt.sC1 + z2 * bt.sC2;
+    const int lane = threadIdx.x % kWave, g = lane / 16, c = lane % 16;
+    const int KS = (K + 3) / 4, k0 = g * KS, cb = 16 * NJ * blockIdx.y;
+    for (int e = threadIdx.x; e < NJ * KSM * kWave; e += blockDim.x) {
+        const int l = e % kWave, s = (e / kWave) % KSM, j = e / (kWave * KSM);
+        const int col = cb + 16 * j + l % 16, k = (l / 16) * KS + s;
+        Bs[e] = (s < KS && k < K && col < N) ? B[(long long)k * ldb + col] : 0.0;
+    }
+    __syncthreads();
+    const int nstrip = (M + 15) / 16, nw = gridDim.x * (blockDim.x / kWave);
+    int st = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    double an[KSM];  // unconditional loads, as in k_gemm_mfma_ra
+#pragma unroll
+    for (int s = 0; s < KSM; ++s) {
+        const int row = 16 * st + c, k = k0 + s;
+        const bool in = st < nstrip && s < KS && k < K && row < M;
+        const double v = A[in ? (long long)row * lda + k : 0];
+        an[s] = in ? v : 0.0;
+    }
+    while (st < nstrip) {
+        double a[KSM];
+#pragma unroll
+        for (int s = 0; s < KSM; ++s) a[s] = an[s];
+        const int nx = st + nw;
+#pragma unroll
+        for (int s = 0; s < KSM; ++s) {
+            const int row = 16 * nx + c, k = k0 + s;
+            const bool in = nx < nstrip && s < KS && k < K && row < M;
+            const double v = A[in ? (long long)row * lda + k : 0];
+            an[s] = in ? v : 0.0;
+        }
+        f64x4 acc[NJ];
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) acc[j] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < KSM; ++s)
+            if (s < KS)
+#pragma unroll
+                for (int j = 0; j < NJ; ++j)
+                    acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], Bs[(j * KSM + s) * kWave + lane], acc[j], 0, 0, 0);
+        __builtin_amdgcn_s_waitcnt(kWaitLoadsOnly);
+        if (beta == 0.0) {
+#pragma unroll
+            for (int j = 0; j < NJ; ++j)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = 16 * st + g + 4 * v, col = cb + 16 * j + c;
+                    if (row < M && col < N) C[(long long)row * ldc + col] = alpha * acc[j][v];
+                }
+        } else {
+#pragma unroll
+            for (int j = 0; j < NJ; ++j)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = 16 * st + g + 4 * v, col = cb + 16 * j + c;
+                    if (row < M && col < N) {
+                        double *o = C + (long long)row * ldc + col;
+                        *o = alpha * acc[j][v] + beta * *o;
+                    }
+                }
+        }
+        st = nx;
+    }
+}
+
 // --------------------------------------------------------------------------- TSQR
 // Householder QR of one row block [r0, r0 + nr) of matrix z, in a column-major scratch copy;
 // only R is kept. Step j reflects column j onto its diagonal: every thread derives the
@@ -544,9 +715,15 @@ int leaf_rows(int n) {
 // with r and (r + k) mod (np-1) with (r - k) mod (np-1) for k = 1 .. np/2 - 1; np - 1 rounds
 // meet every pair once. A padded column (odd n) is never rotated.
 __device__ inline void circle_pair(int r, int k, int np, int *p, int *q) {
+    // 0 <= r < np - 1 and 0 <= k < np / 2: one conditional wrap reduces r + k and r - k mod np - 1
     int a, b;
     if (k == 0) { a = np - 1; b = r; }
-    else { a = (r + k) % (np - 1); b = (r - k + (np - 1)) % (np - 1); }
+    else {
+        a = r + k;
+        a = a >= np - 1 ? a - (np - 1) : a;
+        b = r - k;
+        b = b < 0 ? b + (np - 1) : b;
+    }
     *p = a < b ? a : b;
     *q = a < b ? b : a;
 }
@@ -613,26 +790,24 @@ __device__ void jacobi_sweeps(int n, double *X, int *nrot, double *nrm, double e
     }
 }
 
-// Sum over each half-wave (lanes 0..31 and 32..63; every lane active); every lane gets the sum
-// of its own half.
-__device__ __forceinline__ double half_wave_sum(double v) {
-    v += dpp_d<0xB1>(v);
-    v += dpp_d<0x4E>(v);
-    v += dpp_d<0x141>(v);
-    v += dpp_d<0x140>(v);
-    const double lo = readlane_d(v, 0) + readlane_d(v, 16), hi = readlane_d(v, 32) + readlane_d(v, 48);
-    return (threadIdx.x & 32) ? hi : lo;
+// Sum over each 8-lane segment (every lane active): every lane of a segment gets the same sum,
+// so decisions taken on it agree across the segment.
+__device__ __forceinline__ double seg8_sum(double v) {
+    v += dpp_d<0xB1>(v);   // quad_perm [1,0,3,2]
+    v += dpp_d<0x4E>(v);   // quad_perm [2,3,0,1]
+    return v + dpp_d<0x141>(v);  // row_half_mirror: the other quad of the segment
 }
 
-// The same sweeps for n <= 64 with 1024 threads: pair k of a round goes to half-wave k (32
-// half-waves cover the n / 2 pairs), lane l of a half holding rows l % 32 and l % 32 + 32 of both
-// columns in registers from the dot product to the rotation. Every pair of a round is in flight
-// at once and each costs one segmented reduction; the pairs, their order and the rotation
-// formulas are those of jacobi_sweeps.
-__device__ void jacobi_sweeps_small(int n, double *X, int *nrot, double *nrm, double eta) {
-    const int tid = threadIdx.x, lane = tid % kWave, w = tid / kWave;
-    const int hl = lane & 31, slot = 2 * w + (lane >> 5), nslots = 2 * (int)(blockDim.x / kWave);
-    const int i0 = hl, i1 = hl + 32;
+// The same sweeps for n <= 8 RPL with eight column pairs per wave: pair k of a round goes to the
+// 8-lane segment k (the workgroup has at least n / 2 segments), lane l of a segment holding rows
+// l, l + 8, ..., l + 8 (RPL - 1) of both columns in registers from the dot product to the
+// rotation. Every pair of a round is in flight at once, the rotation angle is formed once per
+// eight pairs, and a pair's dot product is one three-step segment sum; the pairs, their order and
+// the rotation formulas are those of jacobi_sweeps, with the roots and the reciprocal taken by
+// nr_sqrt, nr_rcp and nr_rsqrt.
+template <int RPL>
+__device__ void jacobi_sweeps_seg(int n, double *X, int *nrot, double *nrm, double eta) {
+    const int tid = threadIdx.x, sl = tid & 7, slot = tid >> 3, nslots = (int)(blockDim.x >> 3);
     const int np = n + (n & 1);
     const double tol2 = 1e-30;  // (1e-15)^2: the relative threshold of jacobi_sweeps, squared
     for (int sweep = 0; sweep < 60; ++sweep) {
@@ -641,11 +816,15 @@ __device__ void jacobi_sweeps_small(int n, double *X, int *nrot, double *nrm, do
             double ss = 0.0;
             if (j < n) {
                 const double *xj = X + (long long)j * n;
-                const double u0 = i0 < n ? xj[i0] : 0.0, u1 = i1 < n ? xj[i1] : 0.0;
-                ss = fma(u0, u0, u1 * u1);
+#pragma unroll
+                for (int k = 0; k < RPL; ++k) {
+                    const int i = sl + 8 * k;
+                    const double u = i < n ? xj[i] : 0.0;
+                    ss = fma(u, u, ss);
+                }
             }
-            ss = half_wave_sum(ss);
-            if (j < n && hl == 0) nrm[j] = ss;
+            ss = seg8_sum(ss);
+            if (j < n && sl == 0) nrm[j] = ss;
         }
         if (tid == 0) *nrot = 0;
         __syncthreads();
@@ -654,27 +833,33 @@ __device__ void jacobi_sweeps_small(int n, double *X, int *nrot, double *nrm, do
             if (slot < np / 2) circle_pair(r, slot, np, &p, &q);
             const bool valid = q < n;
             double *xp = X + (long long)p * n, *xq = X + (long long)(valid ? q : p) * n;
-            double x0 = 0.0, x1 = 0.0, y0 = 0.0, y1 = 0.0, a = 0.0, b = 0.0;
+            double x[RPL], y[RPL], a = 0.0, b = 0.0, c = 0.0;
+#pragma unroll
+            for (int k = 0; k < RPL; ++k) {
+                const int i = sl + 8 * k;
+                const bool in = valid && i < n;
+                x[k] = in ? xp[i] : 0.0;
+                y[k] = in ? xq[i] : 0.0;
+                c = fma(x[k], y[k], c);
+            }
             if (valid) {
-                if (i0 < n) { x0 = xp[i0]; y0 = xq[i0]; }
-                if (i1 < n) { x1 = xp[i1]; y1 = xq[i1]; }
                 a = nrm[p];
                 b = nrm[q];
             }
-            const double c = half_wave_sum(fma(x0, y0, x1 * y1));
+            c = seg8_sum(c);
             if (valid && c != 0.0 && c * c > tol2 * (a * b) && fabs(c) > eta) {
                 const double dd = b - a;
-                const double t = copysign(1.0, dd) * (2.0 * c) / (fabs(dd) + sqrt(dd * dd + 4.0 * c * c));
-                const double cs = rsqrt(1.0 + t * t), sn = cs * t;
-                if (i0 < n) {
-                    xp[i0] = cs * x0 - sn * y0;
-                    xq[i0] = sn * x0 + cs * y0;
+                const double t = copysign(1.0, dd) * (2.0 * c) * nr_rcp(fabs(dd) + nr_sqrt(fma(dd, dd, 4.0 * c * c)));
+                const double cs = nr_rsqrt(fma(t, t, 1.0)), sn = cs * t;
+#pragma unroll
+                for (int k = 0; k < RPL; ++k) {
+                    const int i = sl + 8 * k;
+                    if (i < n) {
+                        xp[i] = cs * x[k] - sn * y[k];
+                        xq[i] = sn * x[k] + cs * y[k];
+                    }
                 }
-                if (i1 < n) {
-                    xp[i1] = cs * x1 - sn * y1;
-                    xq[i1] = sn * x1 + cs * y1;
-                }
-                if (hl == 0) {
+                if (sl == 0) {
                     nrm[p] = fmax(a - t * c, 0.0);
                     nrm[q] = b + t * c;
                     *nrot = 1;  // every writer stores the same value
@@ -689,8 +874,11 @@ __device__ void jacobi_sweeps_small(int n, double *X, int *nrot, double *nrm, do
 }
 
 __device__ __forceinline__ void jacobi_run(int n, double *X, int *nrot, double *nrm, double eta) {
-    // the half-wave form needs a half-wave per pair: (n + 1) / 2 <= 2 blockDim.x / 64
-    if (n <= 64 && (n + 1) / 2 <= (int)(blockDim.x / 32)) jacobi_sweeps_small(n, X, nrot, nrm, eta);
+    // the segment forms need a segment per pair of a round: (n + 1) / 2 <= blockDim.x / 8
+    const bool fits = (n + 1) / 2 <= (int)(blockDim.x >> 3);
+    if (fits && n <= 32) jacobi_sweeps_seg<4>(n, X, nrot, nrm, eta);
+    else if (fits && n <= 64) jacobi_sweeps_seg<8>(n, X, nrot, nrm, eta);
+    else if (fits && n <= 128) jacobi_sweeps_seg<16>(n, X, nrot, nrm, eta);
     else jacobi_sweeps(n, X, nrot, nrm, eta);
 }
 
@@ -2047,9 +2235,19 @@ namespace {
 // two events; the timings are collected when the events have completed (no synchronisation),
 // and after kTuneSamples timings of every candidate the fastest shape is kept.
 // Shapes 0-3 run on the vector units and sum every output in the same order; shape 4 is the
-// FP64 matrix-core form (64 x 64), whose results agree with them to rounding.
-constexpr int kGemmShapes[][2] = {{64, 64}, {32, 64}, {64, 32}, {32, 32}, {64, 64}};
-constexpr int kNumGemmShapes = 5, kTuneSamples = 3;
+// FP64 matrix-core form (64 x 64), whose results agree with them to rounding. Shapes 5-7 are the
+// resident-operand matrix-core forms (A resident; B resident in groups of 64 or 32 columns),
+// open to products without transposes or split-K whose K is at most 64 (and M at most 64 for
+// shape 5); elsewhere they are not tuned, and a forced one runs as shape 4.
+constexpr int kGemmShapes[][2] = {{64, 64}, {32, 64}, {64, 32}, {32, 32}, {64, 64}, {64, 64}, {64, 64}, {64, 64}};
+constexpr int kNumGemmShapes = 8, kTuneSamples = 3;
+constexpr int kResidentMaxK = 64, kStripsPerWave = 8;
+
+bool gemm_shape_fits(int shape, bool ta, bool tb, int M, int K, const GemmBatch &bt) {
+    if (shape < 5) return true;
+    if (ta || tb || bt.ktot > 0 || K > kResidentMaxK) return false;
+    return shape != 5 || M <= 64;
+}
 
 struct TuneEntry {
     int choice = -1;  // chosen shape, -1 while tuning
@@ -2091,9 +2289,39 @@ int log2_bucket(long long x) {
     return b;
 }
 
+template <int MI>
+void launch_gemm_ra(hipStream_t s, int M, int N, int K, double alpha, const double *A, int lda, const double *B,
+                    int ldb, double beta, double *C, int ldc, const GemmBatch &bt) {
+    const int nstrip = (N + 15) / 16;
+    dim3 grid(cdiv(nstrip, 4 * kStripsPerWave), 1, bt.nb1 * bt.nb2), block(256);
+    if (K <= 32) k_gemm_mfma_ra<MI, 8><<<grid, block, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, bt);
+    else k_gemm_mfma_ra<MI, 16><<<grid, block, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, bt);
+}
+
+template <int NJ>
+void launch_gemm_rb(hipStream_t s, int M, int N, int K, double alpha, const double *A, int lda, const double *B,
+                    int ldb, double beta, double *C, int ldc, const GemmBatch &bt) {
+    const int nstrip = (M + 15) / 16;
+    dim3 grid(cdiv(nstrip, 4 * kStripsPerWave), cdiv(N, 16 * NJ), bt.nb1 * bt.nb2), block(256);
+    if (K <= 32) k_gemm_mfma_rb<NJ, 8><<<grid, block, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, bt);
+    else k_gemm_mfma_rb<NJ, 16><<<grid, block, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, bt);
+}
+
 template <bool TA, bool TB>
 void launch_gemm_shape(int shape, hipStream_t s, int M, int N, int K, double alpha, const double *A, int lda,
                        const double *B, int ldb, double beta, double *C, int ldc, const GemmBatch &bt) {
+    if (shape >= 5 && !gemm_shape_fits(shape, TA, TB, M, K, bt)) shape = 4;
+    if constexpr (!TA && !TB) {
+        if (shape == 5) {
+            if (M <= 16) launch_gemm_ra<1>(s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, bt);
+            else if (M <= 32) launch_gemm_ra<2>(s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, bt);
+            else if (M <= 48) launch_gemm_ra<3>(s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, bt);
+            else launch_gemm_ra<4>(s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, bt);
+            return;
+        }
+        if (shape == 6) return launch_gemm_rb<4>(s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, bt);
+        if (shape == 7) return launch_gemm_rb<2>(s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, bt);
+    }
     const int tbm = kGemmShapes[shape][0], tbn = kGemmShapes[shape][1];
     dim3 grid(cdiv(N, tbn), cdiv(M, tbm), bt.nb1 * bt.nb2), block(256);
     switch (shape) {
@@ -2184,15 +2412,19 @@ void gemm_f64_tuned(hipStream_t s, bool ta, bool tb, int M, int N, int K, double
                         ++q;
                     }
                 }
-                bool done = true;
-                for (int c = 0; c < kNumGemmShapes; ++c) done = done && e.count[c] >= kTuneSamples;
+                bool fits[kNumGemmShapes], done = true;
+                for (int c = 0; c < kNumGemmShapes; ++c) {
+                    fits[c] = gemm_shape_fits(c, ta, tb, M, K, bt);
+                    done = done && (!fits[c] || e.count[c] >= kTuneSamples);
+                }
                 if (done) {
                     int best = 0;
                     for (int c = 1; c < kNumGemmShapes; ++c)
-                        if (e.total[c] / e.count[c] < e.total[best] / e.count[best]) best = c;
+                        if (fits[c] && e.total[c] / e.count[c] < e.total[best] / e.count[best]) best = c;
                     e.choice = best;
                     shape = best;
                 } else {
+                    while (!fits[e.next]) e.next = (e.next + 1) % kNumGemmShapes;  // shape 0 always fits
                     shape = e.next;
                     e.next = (e.next + 1) % kNumGemmShapes;
                     timed.cand = shape;
@@ -2348,12 +2580,12 @@ void tsqr_r(hipStream_t s, int m, int n, int batch, const double *A, long long s
     }
 }
 
-// Threads of a Jacobi workgroup: as few waves as give every column pair of a round its own
-// half-wave (fewer waves at each round's barrier), else 1024.
+// Threads of a Jacobi workgroup: for n <= 128 as few waves as give every column pair of a round
+// its own 8-lane segment (fewer waves at each round's barrier), else 1024.
 int jacobi_threads(int n) {
-    if (n > 64) return 1024;
-    const int waves = std::max(1, ((n + 1) / 2 + 1) / 2);
-    return std::min(1024, 64 * waves);
+    if (n > 128) return 1024;
+    const int waves = std::max(1, ((n + 1) / 2 + 7) / 8);
+    return 64 * waves;
 }
 
 bool jacobi_svd(hipStream_t s, int n, int batch, const double *R, double *sigma, double *V, double *scratch,
