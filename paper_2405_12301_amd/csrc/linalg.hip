@@ -306,11 +306,20 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(int M, int N, int K, double a
 // only the next strip's loads are in flight, it lets the copies of those loads at the end of the
 // iteration go without waiting on the stores.
 constexpr int kWaitLoadsOnly = 0x0F70;
+// Load from base + a 32-bit byte offset (the streamed operand of one batch entry spans less
+// than 2^31 bytes), so that a load takes one 32-bit offset register beside the scalar base.
+__device__ __forceinline__ double ld_at(const double *__restrict__ base, unsigned byte_off) {
+    return *reinterpret_cast<const double *>(reinterpret_cast<const char *>(base) + byte_off);
+}
+
+// waves per SIMD the resident-operand kernels are compiled for (at most 512 / 3 registers each):
+// several waves hide the latency of the streamed loads
+constexpr int kResidentWaves = 3;
 
 // A resident (M <= 16 MI; LDS [i][s][lane] = A[16 i + l % 16][g KS + s]): wave w of the grid takes
 // the 16-column strips w, w + W, ... of B and C.
 template <int MI, int KSM>
-__global__ __launch_bounds__(256) void k_gemm_mfma_ra(int M, int N, int K, double alpha, const double *__restrict__ A,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kResidentWaves))) void k_gemm_mfma_ra(int M, int N, int K, double alpha, const double *__restrict__ A,
                                                       int lda, const double *__restrict__ B, int ldb, double beta,
                                                       double *__restrict__ C, int ldc, GemmBatch bt) {
     __shared__ double As[MI * KSM * kWave];
@@ -328,37 +337,31 @@ __global__ __launch_bounds__(256) void k_gemm_mfma_ra(int M, int N, int K, doubl
     __syncthreads();
     const int nstrip = (N + 15) / 16, nw = gridDim.x * (blockDim.x / kWave);
     int st = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-    // the streamed loads are unconditional (an index outside the strip reads element 0 and the
-    // value is replaced by 0), so that the next strip's loads stay in flight across the products
+    // The streamed loads are unconditional, from clamped indices: a row k >= K of B meets a zero
+    // of A in LDS, and a column at or beyond N only feeds outputs that are not stored; so no load
+    // needs a predicate, and the next strip's loads stay in flight across the products.
     double bn[KSM];
 #pragma unroll
-    for (int s = 0; s < KSM; ++s) {
-        const int col = 16 * st + c, k = k0 + s;
-        const bool in = st < nstrip && s < KS && k < K && col < N;
-        const double v = B[in ? (long long)k * ldb + col : 0];
-        bn[s] = in ? v : 0.0;
-    }
+    for (int s = 0; s < KSM; ++s) bn[s] = ld_at(B, 8u * (unsigned)(min(k0 + s, K - 1) * ldb + min(16 * st + c, N - 1)));
     while (st < nstrip) {
         double b[KSM];
 #pragma unroll
         for (int s = 0; s < KSM; ++s) b[s] = bn[s];
         const int nx = st + nw;
 #pragma unroll
-        for (int s = 0; s < KSM; ++s) {
-            const int col = 16 * nx + c, k = k0 + s;
-            const bool in = nx < nstrip && s < KS && k < K && col < N;
-            const double v = B[in ? (long long)k * ldb + col : 0];
-            bn[s] = in ? v : 0.0;
-        }
+        for (int s = 0; s < KSM; ++s)
+            bn[s] = ld_at(B, 8u * (unsigned)(min(k0 + s, K - 1) * ldb + min(16 * nx + c, N - 1)));
         f64x4 acc[MI];
 #pragma unroll
         for (int i = 0; i < MI; ++i) acc[i] = f64x4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int s = 0; s < KSM; ++s)
+        for (int s = 0; s < KSM; ++s) {
             if (s < KS)
 #pragma unroll
                 for (int i = 0; i < MI; ++i)
                     acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(As[(i * KSM + s) * kWave + lane], b[s], acc[i], 0, 0, 0);
+            if (s % 4 == 3) __builtin_amdgcn_sched_barrier(0);  // fragments read four steps at a time
+        }
         __builtin_amdgcn_s_waitcnt(kWaitLoadsOnly);
         const int col = 16 * st + c;
         if (beta == 0.0) {
@@ -389,7 +392,7 @@ __global__ __launch_bounds__(256) void k_gemm_mfma_ra(int M, int N, int K, doubl
 // 16-column blocks starting at column cb; wave w of the x-grid takes the 16-row strips
 // w, w + W, ... of A and C.
 template <int NJ, int KSM>
-__global__ __launch_bounds__(256) void k_gemm_mfma_rb(int M, int N, int K, double alpha, const double *__restrict__ A,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kResidentWaves))) void k_gemm_mfma_rb(int M, int N, int K, double alpha, const double *__restrict__ A,
                                                       int lda, const double *__restrict__ B, int ldb, double beta,
                                                       double *__restrict__ C, int ldc, GemmBatch bt) {
     __shared__ double Bs[NJ * KSM * kWave];
@@ -407,35 +410,30 @@ __global__ __launch_bounds__(256) void k_gemm_mfma_rb(int M, int N, int K, doubl
     __syncthreads();
     const int nstrip = (M + 15) / 16, nw = gridDim.x * (blockDim.x / kWave);
     int st = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-    double an[KSM];  // unconditional loads, as in k_gemm_mfma_ra
+    // unconditional loads from clamped indices, as in k_gemm_mfma_ra: a column k >= K of A meets a
+    // zero of B in LDS, and a row at or beyond M only feeds outputs that are not stored
+    double an[KSM];
 #pragma unroll
-    for (int s = 0; s < KSM; ++s) {
-        const int row = 16 * st + c, k = k0 + s;
-        const bool in = st < nstrip && s < KS && k < K && row < M;
-        const double v = A[in ? (long long)row * lda + k : 0];
-        an[s] = in ? v : 0.0;
-    }
+    for (int s = 0; s < KSM; ++s) an[s] = ld_at(A, 8u * (unsigned)(min(16 * st + c, M - 1) * lda + min(k0 + s, K - 1)));
     while (st < nstrip) {
         double a[KSM];
 #pragma unroll
         for (int s = 0; s < KSM; ++s) a[s] = an[s];
         const int nx = st + nw;
 #pragma unroll
-        for (int s = 0; s < KSM; ++s) {
-            const int row = 16 * nx + c, k = k0 + s;
-            const bool in = nx < nstrip && s < KS && k < K && row < M;
-            const double v = A[in ? (long long)row * lda + k : 0];
-            an[s] = in ? v : 0.0;
-        }
+        for (int s = 0; s < KSM; ++s)
+            an[s] = ld_at(A, 8u * (unsigned)(min(16 * nx + c, M - 1) * lda + min(k0 + s, K - 1)));
         f64x4 acc[NJ];
 #pragma unroll
         for (int j = 0; j < NJ; ++j) acc[j] = f64x4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int s = 0; s < KSM; ++s)
+        for (int s = 0; s < KSM; ++s) {
             if (s < KS)
 #pragma unroll
                 for (int j = 0; j < NJ; ++j)
                     acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], Bs[(j * KSM + s) * kWave + lane], acc[j], 0, 0, 0);
+            if (s % 4 == 3) __builtin_amdgcn_sched_barrier(0);  // fragments read four steps at a time
+        }
         __builtin_amdgcn_s_waitcnt(kWaitLoadsOnly);
         if (beta == 0.0) {
 #pragma unroll
@@ -2243,10 +2241,13 @@ constexpr int kGemmShapes[][2] = {{64, 64}, {32, 64}, {64, 32}, {32, 32}, {64, 6
 constexpr int kNumGemmShapes = 8, kTuneSamples = 3;
 constexpr int kResidentMaxK = 64, kStripsPerWave = 8;
 
-bool gemm_shape_fits(int shape, bool ta, bool tb, int M, int K, const GemmBatch &bt) {
+// The streamed operand of one batch entry is addressed by 32-bit byte offsets (B: K rows of ldb;
+// A: M rows of lda), so it must span less than 2^31 bytes.
+bool gemm_shape_fits(int shape, bool ta, bool tb, int M, int N, int K, int lda, int ldb, const GemmBatch &bt) {
     if (shape < 5) return true;
     if (ta || tb || bt.ktot > 0 || K > kResidentMaxK) return false;
-    return shape != 5 || M <= 64;
+    if (shape == 5) return M <= 64 && 8LL * K * ldb + 8LL * N < (1LL << 31);
+    return 8LL * M * lda + 8LL * K < (1LL << 31);
 }
 
 struct TuneEntry {
@@ -2310,7 +2311,7 @@ void launch_gemm_rb(hipStream_t s, int M, int N, int K, double alpha, const doub
 template <bool TA, bool TB>
 void launch_gemm_shape(int shape, hipStream_t s, int M, int N, int K, double alpha, const double *A, int lda,
                        const double *B, int ldb, double beta, double *C, int ldc, const GemmBatch &bt) {
-    if (shape >= 5 && !gemm_shape_fits(shape, TA, TB, M, K, bt)) shape = 4;
+    if (shape >= 5 && !gemm_shape_fits(shape, TA, TB, M, N, K, lda, ldb, bt)) shape = 4;
     if constexpr (!TA && !TB) {
         if (shape == 5) {
             if (M <= 16) launch_gemm_ra<1>(s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, bt);
@@ -2414,7 +2415,7 @@ void gemm_f64_tuned(hipStream_t s, bool ta, bool tb, int M, int N, int K, double
                 }
                 bool fits[kNumGemmShapes], done = true;
                 for (int c = 0; c < kNumGemmShapes; ++c) {
-                    fits[c] = gemm_shape_fits(c, ta, tb, M, K, bt);
+                    fits[c] = gemm_shape_fits(c, ta, tb, M, N, K, lda, ldb, bt);
                     done = done && (!fits[c] || e.count[c] >= kTuneSamples);
                 }
                 if (done) {
