@@ -230,7 +230,8 @@ wenott_status wenott_batch_rk3_step(wenott_ctx **ctxs, int32_t n, const double *
  * the candidate shapes (0-3: 64x64, 32x64, 64x32, 32x32 on the vector units; 4: 64x64 on the
  * FP64 matrix cores; 5-7: matrix-core forms with one operand staged once per workgroup, A
  * (M <= 64) or B in groups of 64 or 32 columns, for untransposed products with K <= 64) are
- * timed with events collected without synchronising, and the fastest is kept. The vector
+ * timed with events collected without synchronising (three timings each; one in buckets of at
+ * least 2^24 outputs), and the fastest is kept. The vector
  * shapes sum every output in the same order; the matrix-core shapes agree with them to
  * rounding. mode 1: tuned (default); 0: the 64x64 vector shape everywhere; 2 + k: shape k
  * everywhere (k = 0..7; a resident-operand shape runs as shape 4 on a product it does not

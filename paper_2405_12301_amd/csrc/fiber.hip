@@ -726,24 +726,45 @@ __global__ void k_sample_star(FiberGeom g, CoreSet cs, CoreSet un, int use_un, i
 // serves a pair, its lanes over the right rank index be:
 //   t(be) = sum_al G0(i0, al) S(al, be); slot 7 + s (mode-1 line) = sum_be t(be) G2(be, i2).
 // The pair whose shift is 0 (j = i1) also forms the mode-2 line from v = t (slots 14 + q:
-// sum_be t(be) G2(be, i2 + q - 3)), the mode-0 line from w1(al) = sum_be S(al, be) G2(be, i2)
-// (slots q: sum_al G0(i0 + q - 3, al) w1(al), lanes over al) and U^n at the point (slot 21).
+// sum_be t(be) G2(be, i2 + q - 3)) and the mode-0 line from w1(al) = sum_be S(al, be) G2(be, i2)
+// (slots q: sum_al G0(i0 + q - 3, al) w1(al), lanes over al); then U^n's slice H1(:, j, :) takes
+// the LDS and those pairs form U^n at the point (slot 21) by the same contraction as t.
 // A slice larger than the LDS budget is read from global memory in place.
 __device__ inline double wave_sum_d(double v) {
     for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
     return v;
 }
 
+// The value of a wave-uniform lane in every lane, through scalar registers (v_readlane) instead
+// of an LDS permute.
+__device__ __forceinline__ double bcast_d(double v, int lane) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
 constexpr int kSlicePairs = 2048;      // pairs held at once (a slice gets ~7 npts / N1 of them)
 constexpr int kSliceLdsDoubles = 8192;  // staged slice (R1 R2 <= 8192)
+// threads of k_sample_slices3 (one workgroup per slice): eight waves share a slice's pairs, two
+// workgroups per CU
+constexpr int kSliceThreads = 512;
 
-__global__ __launch_bounds__(256) void k_sample_slices3(FiberGeom g, CoreSet cs, CoreSet un, int use_un, int npts,
+// Dynamic LDS of k_sample_slices3: room for each of the two slices it stages (state and U^n),
+// which it does for a slice of at most kSliceLdsDoubles (a larger one is read in place); sized
+// to the ranks, so that several workgroups share a CU.
+size_t slice_lds_bytes(long long r1r2, long long s1s2) {
+    const long long a = r1r2 <= kSliceLdsDoubles ? r1r2 : 0, b = s1s2 <= kSliceLdsDoubles ? s1s2 : 0;
+    return (size_t)std::max(a, b) * sizeof(double);
+}
+
+__global__ __launch_bounds__(kSliceThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_sample_slices3(FiberGeom g, CoreSet cs, CoreSet un, int use_un, int npts,
                                                         unsigned long long seed, double *__restrict__ ust) {
     const int NC = g.ncomp;
     __shared__ int pair_pt[kSlicePairs];
     __shared__ unsigned char pair_s[kSlicePairs];
     __shared__ int npairs;
-    __shared__ double S_lds[kSliceLdsDoubles];
+    extern __shared__ double S_lds[];  // slice_lds_bytes
     const int j = blockIdx.x, tid = threadIdx.x, lane = tid % kWave, w = tid / kWave;
     const int N0 = g.n[0], N1 = g.n[1], N2 = g.n[2];
     const int R1 = cs.R[1], R2 = cs.R[2];
@@ -751,12 +772,13 @@ __global__ __launch_bounds__(256) void k_sample_slices3(FiberGeom g, CoreSet cs,
     const bool staged = (long long)R1 * R2 <= kSliceLdsDoubles;
     int scan = 0;  // next point to scan
     while (scan < npts) {
-        // collect pairs until the list could overflow with the next 256 points (7 pairs each)
+        // collect pairs until the list could overflow with the next 256 points (7 pairs each),
+        // 256 points a round
         if (tid == 0) npairs = 0;
         __syncthreads();
         while (scan < npts && npairs + 7 * 256 <= kSlicePairs) {
             const int pt = scan + tid;
-            if (pt < npts) {
+            if (tid < 256 && pt < npts) {
                 const int i1 = probe_coord(seed, (long long)pt * 3 + 1, N1);
                 for (int sh = 0; sh < 7; ++sh)
                     if (ghost_map(i1 + sh - 3, N1, g.bc[1]) == j) {
@@ -772,7 +794,7 @@ __global__ __launch_bounds__(256) void k_sample_slices3(FiberGeom g, CoreSet cs,
         for (int c = 0; c < NC && np > 0; ++c) {
             const double *G1c = cs.c[1] + c * cs.cstride[1] + (long long)j * R2;  // S(al, be) = G1c[al s1 + be]
             if (staged) {
-                for (int e = tid; e < R1 * R2; e += 256) {
+                for (int e = tid; e < R1 * R2; e += kSliceThreads) {
                     const int al = e / R2, be = e - al * R2;
                     S_lds[e] = G1c[al * s1 + be];
                 }
@@ -782,7 +804,7 @@ __global__ __launch_bounds__(256) void k_sample_slices3(FiberGeom g, CoreSet cs,
             const long long sS = staged ? R2 : s1;
             const double *G0 = cs.c[0] + c * cs.cstride[0];
             const double *G2 = cs.c[2] + c * cs.cstride[2];
-            for (int q = w; q < np; q += 256 / kWave) {
+            for (int q = w; q < np; q += kSliceThreads / kWave) {
                 const int p = pair_pt[q], sh = pair_s[q];
                 const int i0 = probe_coord(seed, (long long)p * 3, N0), i2 = probe_coord(seed, (long long)p * 3 + 2, N2);
                 const int i1 = probe_coord(seed, (long long)p * 3 + 1, N1);
@@ -801,8 +823,8 @@ __global__ __launch_bounds__(256) void k_sample_slices3(FiberGeom g, CoreSet cs,
                         const int na = min(kWave, R1 - al0);
                         int a = 0;
                         for (; a + 3 < na; a += 4) {
-                            const double x0 = __shfl(gv, a, kWave), x1 = __shfl(gv, a + 1, kWave);
-                            const double x2 = __shfl(gv, a + 2, kWave), x3 = __shfl(gv, a + 3, kWave);
+                            const double x0 = bcast_d(gv, a), x1 = bcast_d(gv, a + 1);
+                            const double x2 = bcast_d(gv, a + 2), x3 = bcast_d(gv, a + 3);
                             if (be < R2) {
                                 t0 = fma(x0, S[(al0 + a) * sS + be], t0);
                                 t1 = fma(x1, S[(al0 + a + 1) * sS + be], t1);
@@ -811,7 +833,7 @@ __global__ __launch_bounds__(256) void k_sample_slices3(FiberGeom g, CoreSet cs,
                             }
                         }
                         for (; a < na; ++a) {
-                            const double x0 = __shfl(gv, a, kWave);
+                            const double x0 = bcast_d(gv, a);
                             if (be < R2) t0 = fma(x0, S[(al0 + a) * sS + be], t0);
                         }
                     }
@@ -843,11 +865,11 @@ __global__ __launch_bounds__(256) void k_sample_slices3(FiberGeom g, CoreSet cs,
                     if (R2 <= kWave) {
                         int be = 0;
                         for (; be + 1 < R2; be += 2) {
-                            const double x0 = __shfl(g2c, be, kWave), x1 = __shfl(g2c, be + 1, kWave);
+                            const double x0 = bcast_d(g2c, be), x1 = bcast_d(g2c, be + 1);
                             w0 = fma(row[be], x0, w0);
                             w1 = fma(row[be + 1], x1, w1);
                         }
-                        if (be < R2) w0 = fma(row[be], __shfl(g2c, be, kWave), w0);
+                        if (be < R2) w0 = fma(row[be], bcast_d(g2c, be), w0);
                     } else {
                         for (int be = 0; be < R2; ++be) w0 = fma(row[be], G2[(long long)be * N2 + i2], w0);
                     }
@@ -862,14 +884,30 @@ __global__ __launch_bounds__(256) void k_sample_slices3(FiberGeom g, CoreSet cs,
                     const double v0 = wave_sum_d(l0[qq]);
                     if (lane == 0) ust[((long long)qq * NC + c) * npts + p] = ghost_fix<double>(g, 0, i0 + qq - 3, c, v0);
                 }
-                // U^n at the point
+            }
+            __syncthreads();  // the staged slice is replaced by U^n's, then by the next component's
+            // U^n at the centre points (slot 21), its slice H1(:, j, :) staged in the same LDS
+            const int S1 = un.R[1], S2 = un.R[2];
+            const bool staged_un = use_un && (long long)S1 * S2 <= kSliceLdsDoubles;
+            const long long t1g = (long long)N1 * S2;
+            const double *H1g = use_un ? un.c[1] + c * un.cstride[1] + (long long)j * S2 : nullptr;
+            if (staged_un) {
+                for (int e = tid; e < S1 * S2; e += kSliceThreads) {
+                    const int al = e / S2, be = e - al * S2;
+                    S_lds[e] = H1g[al * t1g + be];
+                }
+            }
+            __syncthreads();
+            const double *H1 = staged_un ? S_lds : H1g;
+            const long long t1s = staged_un ? S2 : t1g;
+            for (int q = w; q < np; q += kSliceThreads / kWave) {
+                if (pair_s[q] != 3) continue;
+                const int p = pair_pt[q];
                 double unv = 0.0;
                 if (use_un) {
-                    const int S1 = un.R[1], S2 = un.R[2];
+                    const int i0 = probe_coord(seed, (long long)p * 3, N0), i2 = probe_coord(seed, (long long)p * 3 + 2, N2);
                     const double *H0 = un.c[0] + c * un.cstride[0] + (long long)i0 * S1;
-                    const double *H1 = un.c[1] + c * un.cstride[1] + (long long)j * S2;
                     const double *H2 = un.c[2] + c * un.cstride[2];
-                    const long long t1s = (long long)N1 * S2;
                     for (int be0 = 0; be0 < S2; be0 += kWave) {
                         const int be = be0 + lane, bq = be < S2 ? be : 0;
                         double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
@@ -878,12 +916,12 @@ __global__ __launch_bounds__(256) void k_sample_slices3(FiberGeom g, CoreSet cs,
                             const int na = min(kWave, S1 - al0);
                             int a = 0;
                             for (; a + 3 < na; a += 4) {
-                                t0 = fma(__shfl(hv, a, kWave), H1[(al0 + a) * t1s + bq], t0);
-                                t1 = fma(__shfl(hv, a + 1, kWave), H1[(al0 + a + 1) * t1s + bq], t1);
-                                t2 = fma(__shfl(hv, a + 2, kWave), H1[(al0 + a + 2) * t1s + bq], t2);
-                                t3 = fma(__shfl(hv, a + 3, kWave), H1[(al0 + a + 3) * t1s + bq], t3);
+                                t0 = fma(bcast_d(hv, a), H1[(al0 + a) * t1s + bq], t0);
+                                t1 = fma(bcast_d(hv, a + 1), H1[(al0 + a + 1) * t1s + bq], t1);
+                                t2 = fma(bcast_d(hv, a + 2), H1[(al0 + a + 2) * t1s + bq], t2);
+                                t3 = fma(bcast_d(hv, a + 3), H1[(al0 + a + 3) * t1s + bq], t3);
                             }
-                            for (; a < na; ++a) t0 = fma(__shfl(hv, a, kWave), H1[(al0 + a) * t1s + bq], t0);
+                            for (; a < na; ++a) t0 = fma(bcast_d(hv, a), H1[(al0 + a) * t1s + bq], t0);
                         }
                         if (be < S2) unv = fma((t0 + t1) + (t2 + t3), H2[(long long)be * N2 + i2], unv);
                     }
@@ -891,7 +929,7 @@ __global__ __launch_bounds__(256) void k_sample_slices3(FiberGeom g, CoreSet cs,
                 }
                 if (lane == 0) ust[((long long)21 * NC + c) * npts + p] = unv;
             }
-            __syncthreads();  // the staged slice is replaced for the next component
+            __syncthreads();
         }
     }
 }
@@ -1278,7 +1316,10 @@ void sample_stage(hipStream_t s, const FiberGeom &g, const double *const *xcores
         // the slice form pays off once a cell costs more than a few hundred multiply-adds
         // (R1 R2); below that one thread per sample value is faster
         if ((long long)xs.R[1] * xs.R[2] > 512)
-            k_sample_slices3<<<g.n[1], 256, 0, s>>>(g, xs, us, ncores != nullptr, npts, seed, ust);
+            k_sample_slices3<<<g.n[1], kSliceThreads,
+                               slice_lds_bytes((long long)xs.R[1] * xs.R[2],
+                                               ncores ? (long long)us.R[1] * us.R[2] : 0),
+                               s>>>(g, xs, us, ncores != nullptr, npts, seed, ust);
         else
             k_sample_star<3><<<cdiv(n1, 256), 256, 0, s>>>(g, xs, us, ncores != nullptr, npts, seed, ust);
     }

@@ -2231,14 +2231,15 @@ namespace {
 // binary orders of magnitude of M, N, K and the batch) to the shape chosen for it. A bucket seen
 // for the first time is tuned on the live calls: each call launches the next candidate between
 // two events; the timings are collected when the events have completed (no synchronisation),
-// and after kTuneSamples timings of every candidate the fastest shape is kept.
+// and after kTuneSamples timings of every candidate (one for buckets of at least 2^24 outputs,
+// whose launches are long enough to time once) the fastest shape is kept.
 // Shapes 0-3 run on the vector units and sum every output in the same order; shape 4 is the
 // FP64 matrix-core form (64 x 64), whose results agree with them to rounding. Shapes 5-7 are the
 // resident-operand matrix-core forms (A resident; B resident in groups of 64 or 32 columns),
 // open to products without transposes or split-K whose K is at most 64 (and M at most 64 for
 // shape 5); elsewhere they are not tuned, and a forced one runs as shape 4.
 constexpr int kGemmShapes[][2] = {{64, 64}, {32, 64}, {64, 32}, {32, 32}, {64, 64}, {64, 64}, {64, 64}, {64, 64}};
-constexpr int kNumGemmShapes = 8, kTuneSamples = 3;
+constexpr int kNumGemmShapes = 8, kTuneSamples = 3, kTuneOnceLog2 = 24;
 constexpr int kResidentMaxK = 64, kStripsPerWave = 8;
 
 // The streamed operand of one batch entry is addressed by 32-bit byte offsets (B: K rows of ldb;
@@ -2413,10 +2414,11 @@ void gemm_f64_tuned(hipStream_t s, bool ta, bool tb, int M, int N, int K, double
                         ++q;
                     }
                 }
+                const int need = key[2] + key[3] + key[5] >= kTuneOnceLog2 ? 1 : kTuneSamples;
                 bool fits[kNumGemmShapes], done = true;
                 for (int c = 0; c < kNumGemmShapes; ++c) {
                     fits[c] = gemm_shape_fits(c, ta, tb, M, N, K, lda, ldb, bt);
-                    done = done && (!fits[c] || e.count[c] >= kTuneSamples);
+                    done = done && (!fits[c] || e.count[c] >= need);
                 }
                 if (done) {
                     int best = 0;
