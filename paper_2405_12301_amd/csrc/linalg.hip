@@ -1965,18 +1965,22 @@ __device__ __forceinline__ void chol_inv_body(int r, const double *__restrict__ 
     }
 }
 
-// One wave per matrix for r <= 64, everything in LDS (leading dimension r + 1): right-looking
-// Cholesky with lane i owning column i (row j of R, then the trailing update of column i), then
-// R^{-1} by back substitution, lane i forming column i; the loops go four rows at a time so
-// that their LDS loads overlap. The same arithmetic as above (a column whose pivot is not above
-// 0.5 is a zero padding column with a unit diagonal); the sums run in another order.
+// One workgroup of kCholWaves waves per matrix for r <= 63, everything in LDS (leading
+// dimension r + 1): right-looking Cholesky with lane i of every wave owning column i, wave w
+// updating the trailing rows k with k % kCholWaves == w; then R^{-1} by back substitution in the
+// first wave, lane i forming column i; the loops go four rows at a time so that their LDS loads
+// overlap. The same arithmetic as above (a column whose pivot is not above 0.5 is a zero padding
+// column with a unit diagonal); the sums run in another order.
 constexpr int kCholWaveMax = 63;  // 2 r (r + 1) doubles of LDS stay within 64 KB
+constexpr int kCholWaves = 4;
 
 // The factorisation and inverse from A (r x r in LDS, leading dimension r + 1, upper triangle
-// read); Xs: LDS of the same size. Every thread of the workgroup calls it (the barriers); the
-// threads of the first wave do the work.
+// read); Xs: LDS of the same size. Every thread of the workgroup calls it (the barriers). At step
+// j every thread forms the entries R_jk = A_jk / R_jj it needs from the unscaled row j (the
+// products a stored scaled row would hold), so one barrier per step suffices; the first wave
+// then stores the scaled row j, which no later step of the factorisation reads.
 __device__ __forceinline__ void chol_inv_lds(int r, double *A, double *Xs, double *__restrict__ X) {
-    const int ld = r + 1, lane = threadIdx.x;
+    const int ld = r + 1, lane = threadIdx.x % kWave, w = threadIdx.x / kWave, W = blockDim.x / kWave;
     for (int j = 0; j < r; ++j) {
         const double dd = A[j * ld + j];
         const bool zc = !(dd > 0.5);
@@ -1984,27 +1988,27 @@ __device__ __forceinline__ void chol_inv_lds(int r, double *A, double *Xs, doubl
         double rji = 0.0;
         if (lane > j && lane < r) {
             rji = zc ? 0.0 : A[j * ld + lane] * inv;
-            A[j * ld + lane] = rji;
-        }
-        if (lane == j) A[j * ld + j] = rjj;
-        __syncthreads();
-        if (lane > j && lane < r) {  // four rows at a time, so that their loads overlap
-            int k = j + 1;
-            for (; k + 3 <= lane; k += 4) {
-                const double r0 = A[j * ld + k], r1 = A[j * ld + k + 1], r2 = A[j * ld + k + 2],
-                             r3 = A[j * ld + k + 3];
-                const double a0 = A[k * ld + lane], a1 = A[(k + 1) * ld + lane], a2 = A[(k + 2) * ld + lane],
-                             a3 = A[(k + 3) * ld + lane];
+            int k = j + 1 + (w - (j + 1) % W + W) % W;  // the first row after j that is this wave's
+            for (; k + 3 * W <= lane; k += 4 * W) {
+                const double r0 = zc ? 0.0 : A[j * ld + k] * inv, r1 = zc ? 0.0 : A[j * ld + k + W] * inv,
+                             r2 = zc ? 0.0 : A[j * ld + k + 2 * W] * inv, r3 = zc ? 0.0 : A[j * ld + k + 3 * W] * inv;
+                const double a0 = A[k * ld + lane], a1 = A[(k + W) * ld + lane], a2 = A[(k + 2 * W) * ld + lane],
+                             a3 = A[(k + 3 * W) * ld + lane];
                 A[k * ld + lane] = fma(-r0, rji, a0);
-                A[(k + 1) * ld + lane] = fma(-r1, rji, a1);
-                A[(k + 2) * ld + lane] = fma(-r2, rji, a2);
-                A[(k + 3) * ld + lane] = fma(-r3, rji, a3);
+                A[(k + W) * ld + lane] = fma(-r1, rji, a1);
+                A[(k + 2 * W) * ld + lane] = fma(-r2, rji, a2);
+                A[(k + 3 * W) * ld + lane] = fma(-r3, rji, a3);
             }
-            for (; k <= lane; ++k) A[k * ld + lane] = fma(-A[j * ld + k], rji, A[k * ld + lane]);
+            for (; k <= lane; k += W) A[k * ld + lane] = fma(-(zc ? 0.0 : A[j * ld + k] * inv), rji, A[k * ld + lane]);
         }
         __syncthreads();
+        if (w == 0) {
+            if (lane > j && lane < r) A[j * ld + lane] = rji;
+            if (lane == j) A[j * ld + j] = rjj;
+        }
     }
-    if (lane < r) {
+    __syncthreads();
+    if (w == 0 && lane < r) {
         const int i = lane;
         for (int j = i; j >= 0; --j) {
             double v0 = (j == i) ? 1.0 : 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;  // four chains
@@ -2020,18 +2024,17 @@ __device__ __forceinline__ void chol_inv_lds(int r, double *A, double *Xs, doubl
         }
     }
     __syncthreads();
-    if (lane < kWave)
-        for (int e = lane; e < r * r; e += kWave) {
-            const int j = e / r, i = e % r;
-            X[e] = j <= i ? Xs[j * ld + i] : 0.0;
-        }
+    for (int e = threadIdx.x; e < r * r; e += blockDim.x) {
+        const int j = e / r, i = e % r;
+        X[e] = j <= i ? Xs[j * ld + i] : 0.0;
+    }
 }
 
 __device__ __forceinline__ void chol_inv_wave_body(int r, const double *__restrict__ G, double *__restrict__ X) {
     extern __shared__ double cw[];
-    const int ld = r + 1, lane = threadIdx.x;
+    const int ld = r + 1;
     double *A = cw, *Xs = cw + r * ld;
-    for (int e = lane; e < r * r; e += kWave) A[(e / r) * ld + e % r] = G[e];
+    for (int e = threadIdx.x; e < r * r; e += blockDim.x) A[(e / r) * ld + e % r] = G[e];
     __syncthreads();
     chol_inv_lds(r, A, Xs, X);
 }
@@ -2179,12 +2182,12 @@ __global__ __launch_bounds__(64) void k_chol_inv_reg(int r, const double *__rest
         if (j < r && lane < r) Xout[off + (long long)j * r + lane] = a[j];
 }
 
-__global__ __launch_bounds__(64) void k_chol_inv_wave(int r, const double *__restrict__ Gin, double *__restrict__ Xout) {
+__global__ __launch_bounds__(kCholWaves * kWave) void k_chol_inv_wave(int r, const double *__restrict__ Gin, double *__restrict__ Xout) {
     const long long off = (long long)blockIdx.x * r * r;
     chol_inv_wave_body(r, Gin + off, Xout + off);
 }
 
-__global__ __launch_bounds__(64) void k_chol_inv_wave_batch(const CholJob *__restrict__ jobs) {
+__global__ __launch_bounds__(kCholWaves * kWave) void k_chol_inv_wave_batch(const CholJob *__restrict__ jobs) {
     const CholJob j = jobs[blockIdx.x];
     if ((int)blockIdx.y >= j.batch) return;
     const long long off = (long long)blockIdx.y * j.r * j.r;
@@ -2822,7 +2825,7 @@ void chol_upper_inv(hipStream_t s, int r, int batch, const double *G, double *X,
         if (r <= 16) k_chol_inv_reg<16><<<batch, kWave, 0, s>>>(r, G, X);
         else k_chol_inv_reg<32><<<batch, kWave, 0, s>>>(r, G, X);
     } else if (r <= kCholWaveMax)
-        k_chol_inv_wave<<<batch, kWave, sizeof(double) * 2 * (size_t)r * (r + 1), s>>>(r, G, X);
+        k_chol_inv_wave<<<batch, kCholWaves * kWave, sizeof(double) * 2 * (size_t)r * (r + 1), s>>>(r, G, X);
     else
         k_chol_inv<<<batch, 256, 0, s>>>(r, G, X, ws);
     WTT_HIP(hipGetLastError());
@@ -2921,7 +2924,7 @@ void jacobi_svd_batch(hipStream_t s, int njobs, int ncomp, int nmax, const SvdJo
 void chol_upper_inv_batch(hipStream_t s, int njobs, int ncomp, int rmax, const CholJob *dev_jobs) {
     if (njobs <= 0) return;
     if (rmax <= kCholWaveMax)
-        k_chol_inv_wave_batch<<<dim3(njobs, ncomp), kWave, sizeof(double) * 2 * (size_t)rmax * (rmax + 1), s>>>(
+        k_chol_inv_wave_batch<<<dim3(njobs, ncomp), kCholWaves * kWave, sizeof(double) * 2 * (size_t)rmax * (rmax + 1), s>>>(
             dev_jobs);
     else
         k_chol_inv_batch<<<dim3(njobs, ncomp), 256, 0, s>>>(dev_jobs);
