@@ -22,7 +22,6 @@ namespace {
 
 constexpr int kWave = 64;
 constexpr int kLineThreads = 256;
-constexpr int kSelectThreads = 1024;
 
 struct LineCores {
     const double *c[kMaxDim];
@@ -249,34 +248,45 @@ __global__ void k_alpha_seed(int npts, int n0, int n1, int n2, unsigned long lon
     pts[e] = (i == 0 && best[0] >= 0) ? best[d] : probe_coord(seed, e, nd);
 }
 
-// One workgroup: alpha (out[0]) = the largest candidate value (combined with the value already
-// there when accumulate), its cell into best[], and the cells of the K largest candidates into
-// next[K][ND].
+// Wave argmax under amax_pair's order (the largest value, the smallest index among equal ones),
+// a total order, so the result does not depend on the order of the comparisons: DPP steps within
+// each row of 16 lanes, then the four rows' results through scalar registers; every lane gets
+// the result.
+__device__ inline void wave_amax(double &v, int &i) {
+    amax_pair(v, i, dpp_d<0xB1>(v), dpp_i<0xB1>(i));    // quad_perm [1,0,3,2]
+    amax_pair(v, i, dpp_d<0x4E>(v), dpp_i<0x4E>(i));    // quad_perm [2,3,0,1]
+    amax_pair(v, i, dpp_d<0x141>(v), dpp_i<0x141>(i));  // row_half_mirror
+    amax_pair(v, i, dpp_d<0x140>(v), dpp_i<0x140>(i));  // row_mirror
+    double bv = readlane_d(v, 0);
+    int bi = __builtin_amdgcn_readlane(i, 0);
+#pragma unroll
+    for (int r = 16; r < kWave; r += 16) amax_pair(bv, bi, readlane_d(v, r), __builtin_amdgcn_readlane(i, r));
+    v = bv;
+    i = bi;
+}
+
+// One wave: alpha (out[0]) = the largest candidate value (combined with the value already there
+// when accumulate), its cell into best[], and the cells of the K largest candidates into
+// next[K][ND]. Lane l keeps the largest of its candidates l, l + 64, ... (amax_pair's order); a
+// round takes the wave's largest, marks it taken (-3) and lets its owner lane rescan.
 template <int ND>
-__global__ __launch_bounds__(kSelectThreads) void k_alpha_select(int ncand, const double *__restrict__ cval,
-                                                                 const int *__restrict__ ccell, int K,
-                                                                 int *__restrict__ next, int *__restrict__ best,
-                                                                 double *__restrict__ alpha, int accumulate) {
+__global__ __launch_bounds__(kWave) void k_alpha_select(int ncand, const double *__restrict__ cval,
+                                                        const int *__restrict__ ccell, int K,
+                                                        int *__restrict__ next, int *__restrict__ best,
+                                                        double *__restrict__ alpha, int accumulate) {
     extern __shared__ double vs[];  // ncand values
-    __shared__ double wv[kSelectThreads / kWave];
-    __shared__ int wi[kSelectThreads / kWave];
-    const int tid = threadIdx.x;
-    for (int e = tid; e < ncand; e += kSelectThreads) vs[e] = cval[e];
+    const int lane = threadIdx.x;
+    for (int e = lane; e < ncand; e += kWave) vs[e] = cval[e];
     __syncthreads();
+    double lv = -2.0;
+    int li = 0x7fffffff;
+    for (int e = lane; e < ncand; e += kWave) amax_pair(lv, li, vs[e], e);
     for (int k = 0; k < K; ++k) {
-        double v = -2.0;
-        int i = 0x7fffffff;
-        for (int e = tid; e < ncand; e += kSelectThreads) amax_pair(v, i, vs[e], e);
-        for (int off = kWave / 2; off > 0; off >>= 1) {
-            const double ov = __shfl_xor(v, off, kWave);
-            const int oi = __shfl_xor(i, off, kWave);
-            amax_pair(v, i, ov, oi);
-        }
-        if (tid % kWave == 0) { wv[tid / kWave] = v; wi[tid / kWave] = i; }
-        __syncthreads();
-        if (tid == 0) {
-            for (int w = 1; w < kSelectThreads / kWave; ++w) amax_pair(v, i, wv[w], wi[w]);
-            if (i < 0 || i >= ncand) i = 0;
+        double v = lv;
+        int i = li;
+        wave_amax(v, i);
+        if (i < 0 || i >= ncand) i = 0;
+        if (lane == 0) {
 #pragma unroll
             for (int d = 0; d < ND; ++d) next[k * ND + d] = ccell[i * ND + d];
             if (k == 0) {
@@ -287,9 +297,13 @@ __global__ __launch_bounds__(kSelectThreads) void k_alpha_select(int ncand, cons
 #pragma unroll
                     for (int d = 0; d < ND; ++d) best[d] = ccell[i * ND + d];
             }
-            vs[i] = -3.0;  // taken
         }
-        __syncthreads();
+        if (lane == i % kWave) {  // the owner of candidate i marks it taken and rescans
+            vs[i] = -3.0;
+            lv = -2.0;
+            li = 0x7fffffff;
+            for (int e = lane; e < ncand; e += kWave) amax_pair(lv, li, vs[e], e);
+        }
     }
 }
 
@@ -342,15 +356,15 @@ void alpha_search_t(hipStream_t s, int d, const int *n, const double *const *cor
         if (d == 2) {
             k_alpha_outer<2, LW><<<dim3(npts, 2), kLineThreads, lds_outer, s>>>(T, gamma, npts, cur, outer, cval,
                                                                               ccell, flags);
-            k_alpha_select<2><<<1, kSelectThreads, sizeof(double) * (size_t)ncand, s>>>(ncand, cval, ccell, K, nxt,
-                                                                                     best, alpha, round > 0);
+            k_alpha_select<2><<<1, kWave, sizeof(double) * (size_t)ncand, s>>>(ncand, cval, ccell, K, nxt, best,
+                                                                            alpha, round > 0);
         } else {
             k_alpha_outer<3, LW><<<dim3(npts, 3), kLineThreads, lds_outer, s>>>(T, gamma, npts, cur, outer, cval,
                                                                               ccell, flags);
             k_alpha_mid<LW><<<dim3(nmid, nchunk), kLineThreads, lds_mid, s>>>(T, gamma, nmid, cur, nchunk,
                                                                              cval + npts * 3, ccell + npts * 9, flags);
-            k_alpha_select<3><<<1, kSelectThreads, sizeof(double) * (size_t)ncand, s>>>(ncand, cval, ccell, K, nxt,
-                                                                                     best, alpha, round > 0);
+            k_alpha_select<3><<<1, kWave, sizeof(double) * (size_t)ncand, s>>>(ncand, cval, ccell, K, nxt, best,
+                                                                            alpha, round > 0);
         }
         npts = K;
         cur = nxt;

@@ -240,6 +240,29 @@ __device__ inline T ghost_fix(const FiberGeom &g, int m, int raw, int c, T v) {
     return v;
 }
 
+// Lane moves within a wave: a double permuted with a DPP control word (both 32-bit halves moved
+// alike).
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// The value of lane `lane` (wave-uniform) in every lane, through scalar registers.
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+
 // 1/x, 1/sqrt(x) and sqrt(x) for x > 0 (nr_sqrt(0) = 0) to about 1 ulp: the hardware estimates
 // (about 23 correct bits) refined by two Newton-Raphson steps each, for r = 1/x
 // (r <- r + r (1 - x r)) and for y = 1/sqrt(x) (y <- y + y (1 - x y^2) / 2), sqrt(x) = x y. They

@@ -735,14 +735,6 @@ __device__ inline double wave_sum_d(double v) {
     return v;
 }
 
-// The value of a wave-uniform lane in every lane, through scalar registers (v_readlane) instead
-// of an LDS permute.
-__device__ __forceinline__ double bcast_d(double v, int lane) {
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_readlane((int)b, lane);
-    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
-}
 
 constexpr int kSlicePairs = 2048;      // pairs held at once (a slice gets ~7 npts / N1 of them)
 constexpr int kSliceLdsDoubles = 8192;  // staged slice (R1 R2 <= 8192)
@@ -823,8 +815,8 @@ __global__ __launch_bounds__(kSliceThreads) __attribute__((amdgpu_waves_per_eu(4
                         const int na = min(kWave, R1 - al0);
                         int a = 0;
                         for (; a + 3 < na; a += 4) {
-                            const double x0 = bcast_d(gv, a), x1 = bcast_d(gv, a + 1);
-                            const double x2 = bcast_d(gv, a + 2), x3 = bcast_d(gv, a + 3);
+                            const double x0 = readlane_d(gv, a), x1 = readlane_d(gv, a + 1);
+                            const double x2 = readlane_d(gv, a + 2), x3 = readlane_d(gv, a + 3);
                             if (be < R2) {
                                 t0 = fma(x0, S[(al0 + a) * sS + be], t0);
                                 t1 = fma(x1, S[(al0 + a + 1) * sS + be], t1);
@@ -833,7 +825,7 @@ __global__ __launch_bounds__(kSliceThreads) __attribute__((amdgpu_waves_per_eu(4
                             }
                         }
                         for (; a < na; ++a) {
-                            const double x0 = bcast_d(gv, a);
+                            const double x0 = readlane_d(gv, a);
                             if (be < R2) t0 = fma(x0, S[(al0 + a) * sS + be], t0);
                         }
                     }
@@ -865,11 +857,11 @@ __global__ __launch_bounds__(kSliceThreads) __attribute__((amdgpu_waves_per_eu(4
                     if (R2 <= kWave) {
                         int be = 0;
                         for (; be + 1 < R2; be += 2) {
-                            const double x0 = bcast_d(g2c, be), x1 = bcast_d(g2c, be + 1);
+                            const double x0 = readlane_d(g2c, be), x1 = readlane_d(g2c, be + 1);
                             w0 = fma(row[be], x0, w0);
                             w1 = fma(row[be + 1], x1, w1);
                         }
-                        if (be < R2) w0 = fma(row[be], bcast_d(g2c, be), w0);
+                        if (be < R2) w0 = fma(row[be], readlane_d(g2c, be), w0);
                     } else {
                         for (int be = 0; be < R2; ++be) w0 = fma(row[be], G2[(long long)be * N2 + i2], w0);
                     }
@@ -916,12 +908,12 @@ __global__ __launch_bounds__(kSliceThreads) __attribute__((amdgpu_waves_per_eu(4
                             const int na = min(kWave, S1 - al0);
                             int a = 0;
                             for (; a + 3 < na; a += 4) {
-                                t0 = fma(bcast_d(hv, a), H1[(al0 + a) * t1s + bq], t0);
-                                t1 = fma(bcast_d(hv, a + 1), H1[(al0 + a + 1) * t1s + bq], t1);
-                                t2 = fma(bcast_d(hv, a + 2), H1[(al0 + a + 2) * t1s + bq], t2);
-                                t3 = fma(bcast_d(hv, a + 3), H1[(al0 + a + 3) * t1s + bq], t3);
+                                t0 = fma(readlane_d(hv, a), H1[(al0 + a) * t1s + bq], t0);
+                                t1 = fma(readlane_d(hv, a + 1), H1[(al0 + a + 1) * t1s + bq], t1);
+                                t2 = fma(readlane_d(hv, a + 2), H1[(al0 + a + 2) * t1s + bq], t2);
+                                t3 = fma(readlane_d(hv, a + 3), H1[(al0 + a + 3) * t1s + bq], t3);
                             }
-                            for (; a < na; ++a) t0 = fma(bcast_d(hv, a), H1[(al0 + a) * t1s + bq], t0);
+                            for (; a < na; ++a) t0 = fma(readlane_d(hv, a), H1[(al0 + a) * t1s + bq], t0);
                         }
                         if (be < S2) unv = fma((t0 + t1) + (t2 + t3), H2[(long long)be * N2 + i2], unv);
                     }
