@@ -814,6 +814,7 @@ __global__ __launch_bounds__(kSliceThreads) __attribute__((amdgpu_waves_per_eu(4
                         const double gv = al0 + lane < R1 ? g0[al0 + lane] : 0.0;
                         const int na = min(kWave, R1 - al0);
                         int a = 0;
+#pragma unroll 4
                         for (; a + 3 < na; a += 4) {
                             const double x0 = readlane_d(gv, a), x1 = readlane_d(gv, a + 1);
                             const double x2 = readlane_d(gv, a + 2), x3 = readlane_d(gv, a + 3);
