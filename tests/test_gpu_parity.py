@@ -222,6 +222,21 @@ def test_stage_cross_rejected_warm_sweep(W):
     assert any(n >= 2 for st in sw[1:] for n in st), sw
 
 
+@pytest.mark.parametrize("mode", [7, 8, 9])
+def test_resident_operand_contractions_3d(W, mode):
+    """The resident-operand matrix-core contraction shapes (5: A resident; 6, 7: B resident in
+    64- and 32-column groups) forced on every product they fit, through 3D steps whose gathers
+    have other row, column and reduction counts than the 2D ones (ranks of a wave with 8 modes,
+    K on both sides of 32): each step within 10 eps of the oracle."""
+    _say("case: forced contraction shape", mode - 2, "on a 3D wave 24^3 with 8 modes")
+    f = workloads.config3_wave_3d(24, seed=0, modes=8)
+    W.wenott_gemm_autotune(mode)
+    try:
+        _step_parity(W, f, 1e-9, nsteps=2)
+    finally:
+        W.wenott_gemm_autotune(1)
+
+
 @pytest.mark.parametrize("scheme", SCHEMES)
 def test_step_parity_3d_smooth(W, scheme):
     _say("case: rk3 step, 3D smooth wave 24^3 with 2 Fourier modes, scheme", scheme)
