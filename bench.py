@@ -225,7 +225,7 @@ def blast_batch(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "bench.py runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
     if args.calibrate_copy:
         import torch

@@ -38,7 +38,7 @@ typedef enum {
     WENOTT_ENOCONV = -4,  /* a cross did not reach its tolerance within max_sweeps / rank_cap */
     WENOTT_ENONPHYS = -5, /* rho <= 0 or p <= 0 met at an evaluated point */
     WENOTT_ENAN = -6,     /* NaN or Inf met */
-    WENOTT_ENOTBUILT = -7 /* feature not available in this build */
+    WENOTT_ENOTBUILT = -7 /* feature not available in this library */
 } wenott_status;
 
 /* Boundary treatment per grid side (Sec. 4.5), each with three ghost cells. PERIODIC copies

@@ -2309,7 +2309,7 @@ const char *wenott_strerror(wenott_status s) {
     case WENOTT_ENOCONV: return "cross did not converge";
     case WENOTT_ENONPHYS: return "non-physical state (rho <= 0 or p <= 0)";
     case WENOTT_ENAN: return "NaN or Inf";
-    case WENOTT_ENOTBUILT: return "not available in this build";
+    case WENOTT_ENOTBUILT: return "not available in this library";
     }
     return "unknown status";
 }
