@@ -930,7 +930,8 @@ __global__ __launch_bounds__(kSliceThreads) __attribute__((amdgpu_waves_per_eu(4
 // One point per DG lanes (2 in 2D; 4 in 3D, one idle), 256 / DG points per workgroup: lane d
 // forms the flux difference along direction d and a share of the flux TT's rank sum at the
 // point; the group adds both by shuffles and its first lane forms the residual terms. One
-// partial pair per workgroup (sample_stage_blocks of them).
+// partial pair per workgroup (sample_stage_blocks of them). Launched for 2D states; 3D states
+// take k_sample_stage3 below, one wave per point.
 template <int ND, int LW>
 __global__ __launch_bounds__(256) void k_sample_stage(FiberGeom g, CoreSet fs, int npts, unsigned long long seed,
                                                        const double *__restrict__ ust, double wn, double wx, double wl,
@@ -993,6 +994,71 @@ __global__ __launch_bounds__(256) void k_sample_stage(FiberGeom g, CoreSet fs, i
         n2 += __shfl_xor(n2, off, kWave);
     }
     if (threadIdx.x % kWave == 0) { red[0][threadIdx.x / kWave] = d2; red[1][threadIdx.x / kWave] = n2; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        acc[2 * blockIdx.x] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+        acc[2 * blockIdx.x + 1] = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+    }
+    if (!ok) atomicOr(flags, kFlagNonPhys);
+}
+
+// The same residual partials in 3D with one wave per point (the waves of at most
+// kStageSampleBlocks workgroups take the points in grid-stride order): its lanes run over the
+// right rank index be of the candidate's value sum_be (sum_al G0(m0, al) G1(al, m1, be))
+// G2(be, m2, :), so that the rows of G1 are read coalesced and 4096 points keep the device busy;
+// lanes 0-2 form the flux differences along the three directions from the point's star samples
+// and sum them in the order of the four-lane form. Each be-sum is formed as there; the sums over
+// be and over the points are grouped differently.
+template <int LW>
+__global__ __launch_bounds__(256) void k_sample_stage3(FiberGeom g, CoreSet fs, int npts, unsigned long long seed,
+                                                       const double *__restrict__ ust, double wn, double wx, double wl,
+                                                       StageArgsT<double> hs, double *__restrict__ acc,
+                                                       int *__restrict__ flags) {
+    constexpr int NC = LawNC<3, LW>::v;
+    __shared__ double red[2][4];
+    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave, nw = gridDim.x * (256 / kWave);
+    const int R1 = fs.R[1], R2 = fs.R[2], N1 = fs.N[1], N2 = fs.N[2];
+    double d2 = 0.0, n2 = 0.0;  // lane 0 of each wave
+    bool ok = true;
+    for (int pt = blockIdx.x * (256 / kWave) + w; pt < npts; pt += nw) {
+        const double *u = ust + pt;  // slot q, component c at u[(q * NC + c) * npts]
+        double L[NC], approx[NC];
+        for (int c = 0; c < NC; ++c) L[c] = approx[c] = 0.0;
+        if (lane < 3) {
+            double v[NC][7];
+            for (int s = 0; s < 7; ++s)
+                for (int c = 0; c < NC; ++c) v[c][s] = u[((long long)(lane * 7 + s) * NC + c) * npts];
+            // the direction's operands by comparisons (a per-lane index would go through scratch)
+            const double eps = lane == 0 ? hs.eps_w[0] : (lane == 1 ? hs.eps_w[1] : hs.eps_w[2]);
+            const double ih = lane == 0 ? hs.inv_h[0] : (lane == 1 ? hs.inv_h[1] : hs.inv_h[2]);
+            const bool okd = stage_dir<3, LW, double>(v, lane, g.gamma - 1.0, geom_alpha(g), eps, ih, L);
+            ok = ok && okd;
+        }
+        const int m0 = probe_coord(seed, (long long)pt * 3, g.n[0]), m1 = probe_coord(seed, (long long)pt * 3 + 1, g.n[1]),
+                  m2 = probe_coord(seed, (long long)pt * 3 + 2, g.n[2]);
+        const double *g0 = fs.c[0] + (long long)m0 * R1;
+        for (int be0 = 0; be0 < R2; be0 += kWave) {
+            const int be = be0 + lane;
+            if (be >= R2) continue;
+            double v = 0.0;
+            for (int al = 0; al < R1; ++al) v += g0[al] * fs.c[1][((long long)al * N1 + m1) * R2 + be];
+            const double *last = fs.c[2] + ((long long)be * N2 + m2) * NC;
+            for (int c = 0; c < NC; ++c) approx[c] += v * last[c];
+        }
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            for (int off = 1; off < 4; off <<= 1) L[c] += __shfl_xor(L[c], off, kWave);
+            approx[c] = wave_sum_d(approx[c]);
+        }
+        if (lane == 0)
+            for (int c = 0; c < NC; ++c) {
+                double ex = wx * u[((long long)3 * NC + c) * npts] + wl * L[c] +
+                            (wn != 0.0 ? wn * u[((long long)7 * 3 * NC + c) * npts] : 0.0);
+                d2 += (ex - approx[c]) * (ex - approx[c]);
+                n2 += ex * ex;
+            }
+    }
+    if (lane == 0) { red[0][w] = d2; red[1][w] = n2; }
     __syncthreads();
     if (threadIdx.x == 0) {
         acc[2 * blockIdx.x] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
@@ -1282,7 +1348,13 @@ template void stage_block<double>(hipStream_t, const FiberGeom &, int, int, cons
 template void stage_block<float>(hipStream_t, const FiberGeom &, int, int, const StageArgsT<float> &, double *,
                                  long long, long long, long long, long long, int *);
 
-int sample_stage_blocks(int d, int npts) { return (int)cdiv((long long)npts * (d == 2 ? 2 : 4), 256); }
+// partials of the sampled stage residual: 2D, one workgroup per 128 points (two lanes each);
+// 3D, one wave per point over at most kStageSampleBlocks workgroups of four waves
+constexpr int kStageSampleBlocks = 256;
+int sample_stage_blocks(int d, int npts) {
+    if (d == 2) return (int)cdiv((long long)npts * 2, 256);
+    return (int)std::min<long long>(kStageSampleBlocks, cdiv(npts, 256 / kWave));
+}
 
 void sample_stage(hipStream_t s, const FiberGeom &g, const double *const *xcores, const int *xranks,
                   const double *const *ncores, const int *nranks, int npts, unsigned long long seed,
@@ -1317,16 +1389,17 @@ void sample_stage(hipStream_t s, const FiberGeom &g, const double *const *xcores
             k_sample_star<3><<<cdiv(n1, 256), 256, 0, s>>>(g, xs, us, ncores != nullptr, npts, seed, ust);
     }
     const unsigned nb = sample_stage_blocks(g.d, npts);
-#define WTT_SSTAGE(ND_, LW_) \
-    k_sample_stage<ND_, LW_><<<nb, 256, 0, s>>>(g, fs, npts, seed, ust, wn, wx, wl, hs, acc, flags)
+#define WTT_SSTAGE2(LW_) k_sample_stage<2, LW_><<<nb, 256, 0, s>>>(g, fs, npts, seed, ust, wn, wx, wl, hs, acc, flags)
+#define WTT_SSTAGE3(LW_) k_sample_stage3<LW_><<<nb, 256, 0, s>>>(g, fs, npts, seed, ust, wn, wx, wl, hs, acc, flags)
     if (g.law == kLawEuler) {
-        if (g.d == 2) WTT_SSTAGE(2, kLawEuler); else WTT_SSTAGE(3, kLawEuler);
+        if (g.d == 2) WTT_SSTAGE2(kLawEuler); else WTT_SSTAGE3(kLawEuler);
     } else if (g.law == kLawLinAdv) {
-        if (g.d == 2) WTT_SSTAGE(2, kLawLinAdv); else WTT_SSTAGE(3, kLawLinAdv);
+        if (g.d == 2) WTT_SSTAGE2(kLawLinAdv); else WTT_SSTAGE3(kLawLinAdv);
     } else {
-        if (g.d == 2) WTT_SSTAGE(2, kLawBurgers); else WTT_SSTAGE(3, kLawBurgers);
+        if (g.d == 2) WTT_SSTAGE2(kLawBurgers); else WTT_SSTAGE3(kLawBurgers);
     }
-#undef WTT_SSTAGE
+#undef WTT_SSTAGE2
+#undef WTT_SSTAGE3
     WTT_HIP(hipGetLastError());
 }
 
