@@ -2229,7 +2229,7 @@ constexpr int kResidentMaxK = 64, kStripsPerWave = 8;
 // A: M rows of lda), so it must span less than 2^31 bytes.
 bool gemm_shape_fits(int shape, bool ta, bool tb, int M, int N, int K, int lda, int ldb, const GemmBatch &bt) {
     if (shape < 5) return true;
-    if (ta || tb || bt.ktot > 0 || K > kResidentMaxK) return false;
+    if (ta || tb || bt.ktot > 0 || K < 1 || K > kResidentMaxK) return false;  // clamped indices need K >= 1
     if (shape == 5) return M <= 64 && 8LL * K * ldb + 8LL * N < (1LL << 31);
     return 8LL * M * lda + 8LL * K < (1LL << 31);
 }
