@@ -21,7 +21,9 @@ namespace wtt {
 namespace {
 
 constexpr int kWave = 64;
-constexpr int kLineThreads = 256;
+// threads of the line kernels: one cell of a 512-cell outer line per thread; sixteen waves share a
+// middle-line chunk's (cell, component) tasks
+constexpr int kOuterThreads = 512, kMidThreads = 1024;
 
 struct LineCores {
     const double *c[kMaxDim];
@@ -58,14 +60,14 @@ __device__ inline double cell_speed(const double *q, double gamma, bool &ok) {
 // (mode 0) or a column (last mode) of its core. Candidate pt * ND + dd receives the line's largest
 // value and its cell; a mode outside mode_mask (or the middle mode) writes -1.
 template <int ND, int LW>
-__global__ __launch_bounds__(kLineThreads) void k_alpha_outer(LineCores T, double gamma, int npts,
+__global__ __launch_bounds__(kOuterThreads) void k_alpha_outer(LineCores T, double gamma, int npts,
                                                               const int *__restrict__ pts, int mode_mask,
                                                               double *__restrict__ cval, int *__restrict__ ccell,
                                                               int *__restrict__ flags) {
     constexpr int NC = LawNC<ND, LW>::v;
     extern __shared__ double vec[];  // [NC][R] partial products of the other cores
-    __shared__ double wv[kLineThreads / kWave];
-    __shared__ int wi[kLineThreads / kWave];
+    __shared__ double wv[kOuterThreads / kWave];
+    __shared__ int wi[kOuterThreads / kWave];
     const int pt = blockIdx.x, dd = blockIdx.y, tid = threadIdx.x;
     if (pt >= npts) return;
     const int out = pt * ND + dd;
@@ -82,7 +84,7 @@ __global__ __launch_bounds__(kLineThreads) void k_alpha_outer(LineCores T, doubl
     }
     const bool first = dd == 0;
     const int R = first ? T.R[1] : T.R[ND - 1], Nd = T.N[dd];
-    for (int e = tid; e < NC * R; e += kLineThreads) {
+    for (int e = tid; e < NC * R; e += kOuterThreads) {
         const int c = e / R, a = e - c * R;
         double v;
         if (first) {  // right part at (m_1, ..., m_{d-1}): G_1(a, m_1, :) [G_2(:, m_2)], R_1 values
@@ -111,7 +113,7 @@ __global__ __launch_bounds__(kLineThreads) void k_alpha_outer(LineCores T, doubl
     double best = -1.0;
     int bi = 0;
     bool ok = true;
-    for (int i = tid; i < Nd; i += kLineThreads) {
+    for (int i = tid; i < Nd; i += kOuterThreads) {
         double q[NC];
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
@@ -147,7 +149,7 @@ __global__ __launch_bounds__(kLineThreads) void k_alpha_outer(LineCores T, doubl
     if (tid % kWave == 0) { wv[tid / kWave] = best; wi[tid / kWave] = bi; }
     __syncthreads();
     if (tid == 0) {
-        for (int w = 1; w < kLineThreads / kWave; ++w) amax_pair(best, bi, wv[w], wi[w]);
+        for (int w = 1; w < kOuterThreads / kWave; ++w) amax_pair(best, bi, wv[w], wi[w]);
         cval[out] = best;
         m[dd] = bi;
 #pragma unroll
@@ -162,7 +164,7 @@ __global__ __launch_bounds__(kLineThreads) void k_alpha_outer(LineCores T, doubl
 // contiguous; the chunk's maximum and its cell are candidate pt * nchunk + chunk.
 constexpr int kMidCells = 16;
 template <int LW>
-__global__ __launch_bounds__(kLineThreads) void k_alpha_mid(LineCores T, double gamma, int npts,
+__global__ __launch_bounds__(kMidThreads) void k_alpha_mid(LineCores T, double gamma, int npts,
                                                             const int *__restrict__ pts, int nchunk,
                                                             double *__restrict__ cval, int *__restrict__ ccell,
                                                             int *__restrict__ flags) {
@@ -173,18 +175,18 @@ __global__ __launch_bounds__(kLineThreads) void k_alpha_mid(LineCores T, double 
     const int R1 = T.R[1], R2 = T.R[2], N1 = T.N[1];
     const int m0 = pts[pt * 3], m2 = pts[pt * 3 + 2];
     double *lv = sm, *rv = sm + NC * R1;
-    for (int e = tid; e < NC * R1; e += kLineThreads) {
+    for (int e = tid; e < NC * R1; e += kMidThreads) {
         const int c = e / R1, a = e - c * R1;
         lv[e] = T.c[0][c * T.cs[0] + (long long)m0 * R1 + a];
     }
-    for (int e = tid; e < NC * R2; e += kLineThreads) {
+    for (int e = tid; e < NC * R2; e += kMidThreads) {
         const int c = e / R2, b = e - c * R2;
         rv[e] = T.c[2][c * T.cs[2] + (long long)b * T.N[2] + m2];
     }
     __syncthreads();
     const int j0 = chunk * kMidCells;
     const long long s1 = (long long)N1 * R2;
-    for (int task = w; task < kMidCells * NC; task += kLineThreads / kWave) {
+    for (int task = w; task < kMidCells * NC; task += kMidThreads / kWave) {
         const int jj = task / NC, c = task - jj * NC, j = j0 + jj;
         double acc = 0.0;
         if (j < N1) {
@@ -354,14 +356,14 @@ void alpha_search_t(hipStream_t s, int d, const int *n, const double *const *cor
         const int nmid = std::min(npts, KM);
         const int ncand = npts * d + (d == 3 ? nmid * nchunk : 0);
         if (d == 2) {
-            k_alpha_outer<2, LW><<<dim3(npts, 2), kLineThreads, lds_outer, s>>>(T, gamma, npts, cur, outer, cval,
+            k_alpha_outer<2, LW><<<dim3(npts, 2), kOuterThreads, lds_outer, s>>>(T, gamma, npts, cur, outer, cval,
                                                                               ccell, flags);
             k_alpha_select<2><<<1, kWave, sizeof(double) * (size_t)ncand, s>>>(ncand, cval, ccell, K, nxt, best,
                                                                             alpha, round > 0);
         } else {
-            k_alpha_outer<3, LW><<<dim3(npts, 3), kLineThreads, lds_outer, s>>>(T, gamma, npts, cur, outer, cval,
+            k_alpha_outer<3, LW><<<dim3(npts, 3), kOuterThreads, lds_outer, s>>>(T, gamma, npts, cur, outer, cval,
                                                                               ccell, flags);
-            k_alpha_mid<LW><<<dim3(nmid, nchunk), kLineThreads, lds_mid, s>>>(T, gamma, nmid, cur, nchunk,
+            k_alpha_mid<LW><<<dim3(nmid, nchunk), kMidThreads, lds_mid, s>>>(T, gamma, nmid, cur, nchunk,
                                                                              cval + npts * 3, ccell + npts * 9, flags);
             k_alpha_select<3><<<1, kWave, sizeof(double) * (size_t)ncand, s>>>(ncand, cval, ccell, K, nxt, best,
                                                                             alpha, round > 0);
